@@ -1,0 +1,143 @@
+"""The system matrix A applied matrix-free, its transpose, and the basis D.
+
+Eq. (13) gives trace (i, j) as a sum over voxels of the windowed response,
+delayed by the voxel's travel time and weighted by its apodization:
+
+    y_ij(t) = sum_v h~(t - T_ij(v)) * phi_ij(v) * x(v).
+
+Sampling t at t_m = m / fs (reading: sample 0 at firing), using the tabulated
+template b of Eq. (10) with linear interpolation, and carrying tau of Eq. (7)
+in the voxel weight:
+
+    y[i, j, m] = sum_v W_ij(v) x(v) I_b((m - D_ij(v)) Q),   D = fs T,  W = tau phi,
+
+with I_b the interpolant of b (zero outside the open window).  Reading: the
+scan positions of the array are separate firings, so their traces are stacked
+as rows [P][K][M] of one measurement vector rather than summed (the paper's
+"summing over all transmitters" applies to transmitters firing together, which
+no workload here has).  Echoes that start at or after the last sample are
+dropped.  The transpose is written out from the same sum.
+
+D (Eq. (1)) has one column per trace: the template placed at the direct-arrival
+delay of that trace, in that trace's rows only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import geometry, pulse
+
+_CHUNK = 8192
+
+
+def _taps(delay, acq, b):
+    """Sample indices and values of every voxel's interpolated template."""
+    lh = pulse.window_samples(acq)
+    m0 = np.floor(delay).astype(np.int64)
+    k = np.arange(lh + 2)
+    m = m0[:, None] + k[None, :]
+    val = pulse.interp(b, (m - delay[:, None]) * acq.oversample)
+    return m, val
+
+
+def forward_trace(card, i, j, x_flat, b=None, weight_abs=False):
+    """Trace (i, j) of A x, shape (M,).  x_flat: image in raster order (nz * nx)."""
+    acq = card.acq
+    if b is None:
+        b = pulse.template(acq)
+    n_vox = card.grid.nx * card.grid.nz
+    y = np.zeros(acq.n_samples)
+    for s in range(0, n_vox, _CHUNK):
+        vox = np.arange(s, min(s + _CHUNK, n_vox))
+        delay, w, _ = geometry.trace_geometry(card, i, j, vox)
+        if weight_abs:
+            w = np.abs(w)
+        m, val = _taps(delay, acq, b)
+        contrib = val * (w * x_flat[vox])[:, None]
+        keep = (m >= 0) & (m < acq.n_samples)
+        y += np.bincount(m[keep], weights=contrib[keep], minlength=acq.n_samples)
+    return y
+
+
+def forward(card, x, traces=None, b=None, weight_abs=False):
+    """A x as an array (P, K, M); `traces` restricts to a list of (i, j)."""
+    a = card.array
+    y = np.zeros((a.n_scans, a.n_rx, card.acq.n_samples))
+    x_flat = np.asarray(x, float).reshape(-1)
+    if traces is None:
+        traces = [(i, j) for i in range(a.n_scans) for j in range(a.n_rx)]
+    for i, j in traces:
+        y[i, j] = forward_trace(card, i, j, x_flat, b, weight_abs)
+    return y
+
+
+def adjoint_voxels(card, r, vox, b=None, weight_abs=False):
+    """(A^T r) at the flat voxel indices `vox`; r has shape (P, K, M)."""
+    acq = card.acq
+    if b is None:
+        b = pulse.template(acq)
+    vox = np.asarray(vox, np.int64)
+    out = np.zeros(len(vox))
+    a = card.array
+    for i in range(a.n_scans):
+        for j in range(a.n_rx):
+            rij = r[i, j]
+            for s in range(0, len(vox), _CHUNK):
+                sl = slice(s, s + _CHUNK)
+                delay, w, _ = geometry.trace_geometry(card, i, j, vox[sl])
+                if weight_abs:
+                    w = np.abs(w)
+                m, val = _taps(delay, acq, b)
+                keep = (m >= 0) & (m < acq.n_samples)
+                rv = np.where(keep, rij[np.clip(m, 0, acq.n_samples - 1)], 0.0)
+                out[sl] += w * np.sum(rv * val, axis=1)
+    return out
+
+
+def adjoint(card, r, b=None, weight_abs=False):
+    """A^T r as an image (nz, nx)."""
+    g = card.grid
+    vox = np.arange(g.nx * g.nz)
+    return adjoint_voxels(card, r, vox, b, weight_abs).reshape(g.nz, g.nx)
+
+
+def dense(card, b=None) -> np.ndarray:
+    """A as a dense (P K M, N) matrix, column v = trace response of voxel v."""
+    g, a, acq = card.grid, card.array, card.acq
+    if b is None:
+        b = pulse.template(acq)
+    n_vox = g.nx * g.nz
+    mat = np.zeros((a.n_scans * a.n_rx * acq.n_samples, n_vox))
+    vox = np.arange(n_vox)
+    for i in range(a.n_scans):
+        for j in range(a.n_rx):
+            row0 = (i * a.n_rx + j) * acq.n_samples
+            delay, w, _ = geometry.trace_geometry(card, i, j, vox)
+            m, val = _taps(delay, acq, b)
+            keep = (m >= 0) & (m < acq.n_samples)
+            cols = np.broadcast_to(vox[:, None], m.shape)
+            np.add.at(mat, (row0 + m[keep], cols[keep]), (val * w[:, None])[keep])
+    return mat
+
+
+def direct_basis(card, b=None) -> np.ndarray:
+    """Columns of D as traces d[i, j, :] (P, K, M)."""
+    a, acq = card.array, card.acq
+    if b is None:
+        b = pulse.template(acq)
+    m = np.arange(acq.n_samples)
+    d = np.zeros((a.n_scans, a.n_rx, acq.n_samples))
+    for i in range(a.n_scans):
+        for j in range(a.n_rx):
+            d[i, j] = pulse.interp(b, (m - geometry.direct_delay(card, i, j)) * acq.oversample)
+    return d
+
+
+def apply_direct(card, g, b=None) -> np.ndarray:
+    """D g as traces (P, K, M)."""
+    return direct_basis(card, b) * np.asarray(g, float)[:, :, None]
+
+
+def abs_template(acq) -> np.ndarray:
+    """|b|: its interpolant bounds |I_b| from above, since |(1-f)u + f v| <= (1-f)|u| + f|v|."""
+    return np.abs(pulse.template(acq))
