@@ -1,0 +1,216 @@
+/*
+ * umbir.h -- C ABI of the MI355X (gfx950) library for multi-layer,
+ * collimated-beam ultrasound model-based reconstruction (Alanazi,
+ * Venkatakrishnan, Santos-Villalobos, Buzzard, Bouman, "Model-Based
+ * Reconstruction for Collimated Beam Ultrasound Systems", ICASSP 2022,
+ * arXiv:2202.09703).
+ *
+ * The library applies the system matrix A of the measurement model
+ * y = A x + D g + w (Sec. 2, Eq. (1)) without storing it, applies its exact
+ * transpose, and runs MAP reconstruction of Eq. (18) with a QGGMRF prior
+ * (Eqs. (14)-(17)).
+ *
+ * Conventions for every entry point:
+ *  - Return value: UMBIR_OK (0) or a negative status below.  No C++
+ *    exception crosses this boundary.  umbir_last_error() gives detail text
+ *    for the calling thread's last failure.
+ *  - Device pointers ("_dev") are HIP device memory on the device that was
+ *    current when the geometry was built; the caller owns them.  All device
+ *    arrays are dense, row-major float32 unless stated.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *    Every call except umbir_build_geometry is asynchronous in stream order.
+ *  - Argument checks (null pointers, sizes, parameter ranges) run before any
+ *    HIP call, so they also work on a machine without a GPU.
+ *  - Layouts: image x is [nz][nx] (row = depth, column = lateral position,
+ *    index v = row * nx + col); traces y, r are [P][K][M] (scan position i,
+ *    receiver j, time sample m; sample m is at t = m / fs after firing);
+ *    direct-arrival weights g are [P][K].
+ *  - Workspace: compute calls take a caller-owned device buffer `work` of at
+ *    least umbir_workspace_bytes() bytes.  If `work` is NULL the library
+ *    allocates one on `stream` (hipMallocAsync) and releases it in stream
+ *    order after the call.  One workspace must not be used by two calls that
+ *    may overlap.
+ */
+#ifndef UMBIR_H
+#define UMBIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    UMBIR_OK = 0,
+    UMBIR_EINVAL = -1,    /* invalid argument, problem or prior */
+    UMBIR_ENOMEM = -2,    /* device allocation failed */
+    UMBIR_EDEVICE = -3,   /* HIP runtime or kernel launch error, or no device */
+    UMBIR_ENOTSUP = -4,   /* valid input outside what this build implements */
+    UMBIR_EDIVERGED = -5  /* the MAP cost became non-finite */
+};
+
+#define UMBIR_MAX_LAYERS 8
+
+/* Planar layers below the array face (Sec. 2, "Multi-layered structures",
+ * Fig. 1).  Layer 0 starts at z = 0; the last layer is unbounded.
+ * speed c_l [m/s] > 0, thickness [m] > 0 of layers 0..n_layers-2,
+ * atten alpha_l [s/m] (Eq. (3)) >= 0, density [kg/m^3] > 0.
+ * This build implements alpha = 0 only (ENOTSUP otherwise). */
+typedef struct {
+    int n_layers;              /* 1..UMBIR_MAX_LAYERS */
+    const double* speed;       /* [n_layers] */
+    const double* thickness;   /* [n_layers - 1] (may be NULL if n_layers == 1) */
+    const double* atten;       /* [n_layers] (may be NULL: all zero) */
+    const double* density;     /* [n_layers] */
+} umbir_medium;
+
+/* Voxel grid: centre of (row, col) is (x0 + (col + 1/2) dx, z0 + (row + 1/2) dz). */
+typedef struct {
+    int nx, nz;
+    double dx, dz;             /* > 0 [m] */
+    double x0, z0;             /* left edge of column 0, top edge of row 0 [m]; z0 >= 0 */
+} umbir_grid;
+
+/* Transducers on the face z = 0.  Scan position i fires from tx_x[i];
+ * receiver j of that scan sits at tx_x[i] + rx_offset[j].  beta is the
+ * integer apodization power of Eq. (12).  Every transducer must lie on the
+ * half-voxel lattice of the grid, i.e. 2 (x0 - x) / dx must be an integer
+ * (ENOTSUP otherwise): then the lateral distance of any voxel from any
+ * transducer is a multiple of dx / 2 and travel-time legs are shared. */
+typedef struct {
+    int n_scans;               /* P >= 1 */
+    const double* tx_x;        /* [P] [m] */
+    int n_rx;                  /* K >= 1 */
+    const double* rx_offset;   /* [K] [m] */
+    int beta;                  /* 0..64 */
+} umbir_array;
+
+/* Sampling and pulse.  The transmitted pulse is a Gaussian-windowed sine of
+ * centre f_c and width sigma_t centred at t_win / 2; Eq. (10) keeps it on the
+ * open window (0, t_win).  L_h = t_win * fs must be an integer >= 2.  The
+ * windowed response is tabulated once on a grid `oversample` (Q) times finer
+ * than the sampling grid and interpolated linearly between grid points;
+ * Q must be a power of two in 1..64. */
+typedef struct {
+    int n_samples;             /* M >= 1 */
+    double fs;                 /* sampling rate [Hz] */
+    double f_c;                /* pulse centre frequency [Hz] */
+    double sigma_t;            /* Gaussian width [s] */
+    double t_win;              /* window t_0 of Eq. (10) [s] */
+    int oversample;            /* Q */
+} umbir_acq;
+
+typedef struct {
+    umbir_medium medium;
+    umbir_grid grid;
+    umbir_array array;
+    umbir_acq acq;
+} umbir_problem;
+
+/* MAP prior and noise (Eqs. (2), (15)-(18)).  sigma: noise standard deviation
+ * (> 0); p, q: QGGMRF shapes with 1 < p <= q and q == 2 (Sec. 2 requires
+ * 1 < p < q = 2; p == q == 2 is accepted as the quadratic limit); T: threshold
+ * (> 0); sigma0 (> 0), m (> 0), a (>= 0): scale and depth modulation of
+ * Eqs. (16)-(17).  estimate_direct != 0 also estimates g of Eq. (1). */
+typedef struct {
+    double sigma, p, q, T, sigma0, m, a;
+    int estimate_direct;
+} umbir_prior;
+
+typedef struct umbir_geometry umbir_geometry;
+
+/* Builds the geometry of a problem on the current HIP device: for every
+ * distinct one-way leg (voxel row, lateral distance on the half-voxel
+ * lattice) the Snell ray parameter by an FP64 binary search (Sec. 2,
+ * Eqs. (4)-(6) and the binary search that follows them), its travel time as
+ * Q32.32 fixed-point samples and cos^beta of its angle sum (Eq. (12)); the
+ * per-row transmittance product (Eqs. (3), (7)); the tabulated windowed pulse
+ * (Eqs. (9)-(10)); and the direct-arrival columns of D (Eq. (1)).
+ * The tables stay resident in device memory owned by *out until
+ * umbir_geometry_free.  Blocks until the tables are built.  The handle is
+ * immutable afterwards and may be shared by streams and threads.
+ * Errors: EINVAL (bad problem), ENOTSUP (attenuation, off-lattice
+ * transducers, unsupported Q), ENOMEM, EDEVICE. */
+int umbir_build_geometry(const umbir_problem* problem, void* stream, umbir_geometry** out);
+
+/* Frees a geometry and its device tables.  NULL is a no-op.  The caller must
+ * make sure no queued call still uses it. */
+void umbir_geometry_free(umbir_geometry* geom);
+
+/* Device bytes held by a geometry, and an estimate for a problem before it is
+ * built (0 if the problem is invalid).  Workspace is not included. */
+size_t umbir_geometry_bytes(const umbir_geometry* geom);
+size_t umbir_estimate_bytes(const umbir_problem* problem);
+
+/* Workspace bytes needed by a compute call of the given kind. */
+enum { UMBIR_WORK_FORWARD = 0, UMBIR_WORK_ADJOINT = 1, UMBIR_WORK_RECONSTRUCT = 2 };
+size_t umbir_workspace_bytes(const umbir_geometry* geom, int kind);
+
+/* y = A x (accumulate == 0) or y += A x (accumulate != 0), Eq. (13):
+ * y[i][j][m] = sum_v W_ij(v) x(v) h~(m / fs - T_ij(v)) with the tabulated,
+ * linearly interpolated h~, W = tau(v) phi^(beta)(v).  Scan positions are
+ * separate firings stacked as rows of y.  x_dev: [nz][nx]; y_dev: [P][K][M]. */
+int umbir_forward(const umbir_geometry* geom, const float* x_dev, float* y_dev,
+                  int accumulate, void* work, size_t work_bytes, void* stream);
+
+/* x = A^T r, the exact transpose of umbir_forward (same W, delays and
+ * interpolation).  r_dev: [P][K][M]; x_dev: [nz][nx].  Deterministic: the
+ * same inputs give bitwise the same output. */
+int umbir_adjoint(const umbir_geometry* geom, const float* r_dev, float* x_dev,
+                  void* work, size_t work_bytes, void* stream);
+
+/* y = D g (accumulate == 0) or y += D g: column (i, j) of D is the tabulated
+ * pulse delayed by the direct path |x_rx - x_tx| / c_1 in layer 0 (Eq. (1)).
+ * g_dev: [P][K]; y_dev: [P][K][M]. */
+int umbir_direct(const umbir_geometry* geom, const float* g_dev, float* y_dev,
+                 int accumulate, void* stream);
+
+/* d = |A|^T |A| 1 / sigma^2, the separable-surrogate curvature of the data
+ * term of Eq. (18), with |A| built from |W| and the absolute tabulated pulse
+ * (an entrywise upper bound of |A|).  d_dev: [nz][nx]. */
+int umbir_sqs_denominator(const umbir_geometry* geom, double sigma, float* d_dev,
+                          void* work, size_t work_bytes, void* stream);
+
+/* MAP reconstruction of Eq. (18) by n_iter separable-surrogate iterations,
+ * each one A x and one A^T e: residual e = y - A x - D g, exact per-trace g
+ * update (if estimate_direct), then the simultaneous surrogate step for x
+ * with the QGGMRF prior on the 8-neighbourhood.  x_io_dev ([nz][nx]) and
+ * g_io_dev ([P][K]) hold the warm start on entry and the result on exit.
+ * cost_dev (float64, n_iter + 1 entries, may be NULL) receives the MAP cost
+ * before every iteration and after the last one.  y_dev: [P][K][M].
+ * Errors: EINVAL (prior), ENOMEM, EDEVICE.  Cost divergence is not checked
+ * on the device (the call stays asynchronous); callers compare cost_dev. */
+int umbir_reconstruct(const umbir_geometry* geom, const umbir_prior* prior,
+                      const float* y_dev, int n_iter, float* x_io_dev, float* g_io_dev,
+                      double* cost_dev, void* work, size_t work_bytes, void* stream);
+
+/* Dimensions of a built geometry, for callers that size buffers. */
+typedef struct {
+    int nx, nz, n_scans, n_rx, n_samples;
+    int n_off;        /* lateral lattice positions per leg-table row */
+    int window;       /* L_h */
+    int oversample;   /* Q */
+    int n_layers;
+} umbir_dims;
+int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
+
+/* Copies a resident table to host memory (synchronous), for inspection:
+ *  UMBIR_TABLE_DELAY  int64 [nz][n_off]  one-way leg delay, Q32.32 samples
+ *  UMBIR_TABLE_APOD   float [nz][n_off]  cos^beta of the leg's angle sum
+ *  UMBIR_TABLE_TAU    float [nz]         transmittance product of the row
+ *  UMBIR_TABLE_BANK   float [Q*L_h + 2]  tabulated windowed pulse (+ zero pad)
+ *  UMBIR_TABLE_DBASIS float [P][K][M]    direct-arrival columns of D
+ *  UMBIR_TABLE_OFFSET int32 [P + P*K]    lattice index base of each transducer
+ * `bytes` must equal the table's size.  Errors: EINVAL, EDEVICE. */
+enum { UMBIR_TABLE_DELAY = 0, UMBIR_TABLE_APOD = 1, UMBIR_TABLE_TAU = 2,
+       UMBIR_TABLE_BANK = 3, UMBIR_TABLE_DBASIS = 4, UMBIR_TABLE_OFFSET = 5 };
+int umbir_copy_table(const umbir_geometry* geom, int which, void* host_dst, size_t bytes);
+
+const char* umbir_strerror(int status);
+const char* umbir_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UMBIR_H */

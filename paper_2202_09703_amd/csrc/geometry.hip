@@ -1,0 +1,476 @@
+// Geometry build: validation, FP64 Snell leg table, tabulated pulse and the
+// direct-arrival basis, plus the handle, error and workspace plumbing.
+//
+// Legs (Sec. 2, Eqs. (4)-(6)).  A one-way path from a point on the array face
+// to a voxel centre at depth z and lateral distance X crosses layer l over a
+// vertical extent eta_l.  Snell's law keeps sin(theta_l)/c_l equal to one ray
+// parameter kappa, and the lateral offset of Eq. (5),
+//     X(kappa) = sum_l eta_l kappa c_l / sqrt(1 - kappa^2 c_l^2),
+// increases with kappa, so kappa is found by binary search, as the paper does
+// for the incidence angle.  The search runs on kappa in [0, 1/c_max) with c_max
+// the fastest crossed layer: the paper's range theta_1 in [0, pi/2] reaches
+// past the critical angle of any faster deeper layer, where Eq. (6) has no
+// solution, whereas every X >= 0 has a kappa in [0, 1/c_max).
+// The travel time is evaluated as T = kappa X + sum_l eta_l cos(theta_l)/c_l,
+// which equals sum_l eta_l / (c_l cos theta_l) of Eq. (4) at the exact root and
+// is stationary in kappa there, so the last-bit error of the search does not
+// reach T to first order.
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace umbir {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr int kBisectSteps = 60;
+
+__global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double half_dx,
+                       double fs, int beta, int64_t* __restrict__ delay,
+                       float* __restrict__ apod) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nz * n_off) return;
+  const int row = idx / n_off;
+  const int o = idx - row * n_off;
+  const double z = z0 + (row + 0.5) * dz;
+  const double X = o * half_dx;
+  double eta[kMaxLayers];
+  double cmax = 0.0;
+#pragma unroll
+  for (int l = 0; l < kMaxLayers; ++l) {
+    double e = 0.0;
+    if (l < L.n) {
+      e = fmin(z, L.bottom[l]) - L.top[l];
+      e = e > 0.0 ? e : 0.0;
+      if (e > 0.0) cmax = fmax(cmax, L.speed[l]);
+    }
+    eta[l] = e;
+  }
+  double kap = 0.0;
+  if (X > 0.0) {
+    double lo = 0.0, hi = 1.0 / cmax;
+    for (int it = 0; it < kBisectSteps; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      double xm = 0.0;
+#pragma unroll
+      for (int l = 0; l < kMaxLayers; ++l) {
+        if (eta[l] > 0.0) {
+          const double s = mid * L.speed[l];
+          xm += eta[l] * s / sqrt((1.0 - s) * (1.0 + s));
+        }
+      }
+      if (xm < X) lo = mid; else hi = mid;
+    }
+    kap = 0.5 * (lo + hi);
+  }
+  double T = kap * X;
+  double theta = 0.0;
+#pragma unroll
+  for (int l = 0; l < kMaxLayers; ++l) {
+    if (eta[l] > 0.0) {
+      const double s = kap * L.speed[l];
+      T += eta[l] * sqrt((1.0 - s) * (1.0 + s)) / L.speed[l];
+      theta += asin(s);
+    }
+  }
+  // cos^beta by repeated squaring (beta is a non-negative integer)
+  double base = cos(theta), pw = 1.0;
+  for (int b = beta; b > 0; b >>= 1) {
+    if (b & 1) pw *= base;
+    base *= base;
+  }
+  delay[idx] = __double2ll_rn(fs * T * kTwo32);
+  apod[idx] = static_cast<float>(pw);
+}
+
+// Windowed pulse of Eq. (10) at fine-grid index n (time n / (Q fs)): the
+// Gaussian-windowed sine, zero outside the open window 0 < n < Q L_h.
+__device__ double pulse_at(long n, int QLh, double dt, double f_c, double inv2s2, double t_c) {
+  if (n <= 0 || n >= QLh) return 0.0;
+  const double u = n * dt - t_c;
+  return sin(2.0 * M_PI * f_c * u) * exp(-u * u * inv2s2);
+}
+
+__global__ void k_bank(int Q, int Lh, double dt, double f_c, double inv2s2, double t_c,
+                       float* __restrict__ bank, float* __restrict__ h,
+                       float* __restrict__ habs) {
+  const int QLh = Q * Lh;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < QLh + 2) bank[idx] = static_cast<float>(pulse_at(idx, QLh, dt, f_c, inv2s2, t_c));
+  if (idx < QLh) {
+    const int k = idx / Q, t = idx - k * Q;
+    const float v = static_cast<float>(pulse_at(long(k + 1) * Q - t, QLh, dt, f_c, inv2s2, t_c));
+    h[idx] = v;
+    habs[idx] = fabsf(v);
+  }
+}
+
+// Column (i, j) of D: the tabulated pulse delayed by td[ij] samples, linearly
+// interpolated on the fine grid; also its squared norm.
+__global__ void k_dbasis(const float* __restrict__ bank, const double* __restrict__ td, int M,
+                         int Q, int Lh, float* __restrict__ d, float* __restrict__ dnorm) {
+  const int ij = blockIdx.x;
+  const double t0 = td[ij];
+  const int QLh = Q * Lh;
+  double acc = 0.0;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const double z = (m - t0) * Q;
+    float v = 0.0f;
+    if (z > 0.0 && z < QLh) {
+      const double n = floor(z);
+      const double f = z - n;
+      const int ni = static_cast<int>(n);
+      v = static_cast<float>((1.0 - f) * bank[ni] + f * bank[ni + 1]);
+    }
+    d[size_t(ij) * M + m] = v;
+    acc += double(v) * double(v);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dnorm[ij] = static_cast<float>(red[0]);
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Lattice base of a transducer at x: 2 (x0 - x) / dx + 1 must be an integer.
+bool lattice_base(double x0, double dx, double x, long* out) {
+  const double b = 2.0 * (x0 - x) / dx + 1.0;
+  const double r = std::nearbyint(b);
+  if (std::fabs(b - r) > 1e-6) return false;
+  *out = static_cast<long>(r);
+  return true;
+}
+
+struct Derived {
+  int Lh = 0, n_off = 0;
+  std::vector<int> base;  // [P + P*K]
+};
+
+int validate(const umbir_problem* pb, Derived* dv) {
+  if (!pb) return fail(UMBIR_EINVAL, "problem is NULL");
+  const umbir_medium& md = pb->medium;
+  if (md.n_layers < 1 || md.n_layers > kMaxLayers)
+    return fail(UMBIR_EINVAL, "n_layers must be in 1..8");
+  if (!md.speed || !md.density) return fail(UMBIR_EINVAL, "medium speed/density is NULL");
+  if (md.n_layers > 1 && !md.thickness) return fail(UMBIR_EINVAL, "medium thickness is NULL");
+  for (int l = 0; l < md.n_layers; ++l) {
+    if (!finite_pos(md.speed[l])) return fail(UMBIR_EINVAL, "layer speed must be finite and > 0");
+    if (!finite_pos(md.density[l])) return fail(UMBIR_EINVAL, "layer density must be finite and > 0");
+    if (l + 1 < md.n_layers && !finite_pos(md.thickness[l]))
+      return fail(UMBIR_EINVAL, "layer thickness must be finite and > 0");
+    if (md.atten) {
+      if (!std::isfinite(md.atten[l]) || md.atten[l] < 0.0)
+        return fail(UMBIR_EINVAL, "attenuation must be finite and >= 0");
+      if (md.atten[l] != 0.0)
+        return fail(UMBIR_ENOTSUP, "attenuation (alpha > 0) is not implemented in this build");
+    }
+  }
+  const umbir_grid& g = pb->grid;
+  if (g.nx < 1 || g.nz < 1) return fail(UMBIR_EINVAL, "grid must have nx, nz >= 1");
+  if (double(g.nx) * g.nz > double(1 << 26)) return fail(UMBIR_EINVAL, "grid too large");
+  if (!finite_pos(g.dx) || !finite_pos(g.dz)) return fail(UMBIR_EINVAL, "dx, dz must be > 0");
+  if (!std::isfinite(g.x0) || !std::isfinite(g.z0) || g.z0 < 0.0)
+    return fail(UMBIR_EINVAL, "x0 must be finite and z0 finite and >= 0");
+  const umbir_array& a = pb->array;
+  if (a.n_scans < 1 || a.n_rx < 1) return fail(UMBIR_EINVAL, "need n_scans, n_rx >= 1");
+  if (double(a.n_scans) * a.n_rx > double(1 << 20)) return fail(UMBIR_EINVAL, "too many traces");
+  if (!a.tx_x || !a.rx_offset) return fail(UMBIR_EINVAL, "array positions are NULL");
+  if (a.beta < 0 || a.beta > 64) return fail(UMBIR_EINVAL, "beta must be an integer in 0..64");
+  const umbir_acq& q = pb->acq;
+  if (q.n_samples < 1 || q.n_samples > (1 << 22)) return fail(UMBIR_EINVAL, "n_samples out of range");
+  if (!finite_pos(q.fs) || !finite_pos(q.f_c) || !finite_pos(q.sigma_t) || !finite_pos(q.t_win))
+    return fail(UMBIR_EINVAL, "fs, f_c, sigma_t, t_win must be finite and > 0");
+  const double lh = q.t_win * q.fs;
+  const long lhi = std::lround(lh);
+  if (std::fabs(lh - double(lhi)) > 1e-9 * std::max(1.0, lh) || lhi < 2)
+    return fail(UMBIR_EINVAL, "t_win * fs must be an integer >= 2");
+  if (q.oversample < 1 || q.oversample > 64 || (q.oversample & (q.oversample - 1)))
+    return fail(UMBIR_ENOTSUP, "oversample must be a power of two in 1..64");
+  // the dense kernels stage the taps, padded to a multiple of 16 rows, in 64 KiB of LDS
+  if ((lhi + 15) / 16 * 16 * q.oversample > 16384)
+    return fail(UMBIR_ENOTSUP, "window (rounded up to 16) * oversample must be <= 16384");
+  if (double(q.n_samples) * q.oversample > double(1 << 28))
+    return fail(UMBIR_ENOTSUP, "n_samples * oversample too large");
+  dv->Lh = int(lhi);
+  dv->base.assign(size_t(a.n_scans) * (1 + a.n_rx), 0);
+  long omax = 0;
+  auto add = [&](size_t slot, double x) -> bool {
+    if (!std::isfinite(x)) return false;
+    long b;
+    if (!lattice_base(g.x0, g.dx, x, &b)) return false;
+    const long lo = std::labs(b), hi = std::labs(b + 2L * (g.nx - 1));
+    omax = std::max(omax, std::max(lo, hi));
+    dv->base[slot] = int(b);
+    return true;
+  };
+  for (int i = 0; i < a.n_scans; ++i) {
+    if (!add(i, a.tx_x[i]))
+      return fail(UMBIR_ENOTSUP, "transmitter off the half-voxel lattice (2 (x0 - x) / dx not an integer)");
+    for (int j = 0; j < a.n_rx; ++j)
+      if (!add(a.n_scans + size_t(i) * a.n_rx + j, a.tx_x[i] + a.rx_offset[j]))
+        return fail(UMBIR_ENOTSUP, "receiver off the half-voxel lattice (2 (x0 - x) / dx not an integer)");
+  }
+  if (omax + 1 > (1 << 24)) return fail(UMBIR_EINVAL, "lateral extent too large");
+  dv->n_off = int(omax + 1);
+  return UMBIR_OK;
+}
+
+int choose_trace_groups(int n_vox, int n_traces) {
+  const int vox_blocks = (n_vox + 255) / 256;
+  int g = (2048 + vox_blocks - 1) / vox_blocks;
+  if (g > n_traces) g = n_traces;
+  if (g < 1) g = 1;
+  return g;
+}
+
+size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh) {
+  const size_t legs = size_t(nz) * n_off;
+  return legs * (sizeof(int64_t) + sizeof(float)) + size_t(nz) * sizeof(float) +
+         size_t(P) * (1 + K) * sizeof(int) + size_t(Q * Lh + 2) * sizeof(float) +
+         2 * size_t(Q) * Lh * sizeof(float) + size_t(P) * K * M * sizeof(float) +
+         size_t(P) * K * sizeof(float);
+}
+
+}  // namespace
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return UMBIR_OK;
+  return fail(e == hipErrorOutOfMemory ? UMBIR_ENOMEM : UMBIR_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int Workspace::acquire(void* user, size_t user_bytes, size_t need, hipStream_t s) {
+  stream = s;
+  if (user) {
+    if (user_bytes < need)
+      return fail(UMBIR_EINVAL, "workspace smaller than umbir_workspace_bytes()");
+    ptr = user;
+    return UMBIR_OK;
+  }
+  int st = check_hip(hipMallocAsync(&ptr, need ? need : 256, s), "hipMallocAsync(workspace)");
+  if (st) {
+    ptr = nullptr;
+    return st;
+  }
+  owned = true;
+  return UMBIR_OK;
+}
+
+Workspace::~Workspace() {
+  if (owned && ptr) (void)hipFreeAsync(ptr, stream);
+}
+
+}  // namespace umbir
+
+using namespace umbir;
+
+extern "C" {
+
+const char* umbir_strerror(int status) {
+  switch (status) {
+    case UMBIR_OK: return "success";
+    case UMBIR_EINVAL: return "invalid argument";
+    case UMBIR_ENOMEM: return "out of device memory";
+    case UMBIR_EDEVICE: return "HIP device error";
+    case UMBIR_ENOTSUP: return "not supported by this build";
+    case UMBIR_EDIVERGED: return "MAP cost diverged";
+    default: return "unknown status";
+  }
+}
+
+const char* umbir_last_error(void) { return g_last_error.c_str(); }
+
+size_t umbir_estimate_bytes(const umbir_problem* pb) {
+  Derived dv;
+  std::string keep = g_last_error;
+  if (validate(pb, &dv) != UMBIR_OK) {
+    g_last_error = keep;
+    return 0;
+  }
+  return table_bytes(pb->grid.nz, dv.n_off, pb->array.n_scans, pb->array.n_rx,
+                     pb->acq.n_samples, pb->acq.oversample, dv.Lh);
+}
+
+void umbir_geometry_free(umbir_geometry* G) {
+  if (!G) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (G->device >= 0) (void)hipSetDevice(G->device);
+  void* ptrs[] = {G->delay, G->apod, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete G;
+}
+
+int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry** out) {
+  if (!out) return fail(UMBIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived dv;
+  int st = validate(pb, &dv);
+  if (st) return st;
+
+  int dev = -1;
+  if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice"))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  auto* G = new umbir_geometry();
+  G->device = dev;
+  const umbir_medium& md = pb->medium;
+  G->layers.n = md.n_layers;
+  double top = 0.0;
+  for (int l = 0; l < md.n_layers; ++l) {
+    G->layers.speed[l] = md.speed[l];
+    G->layers.top[l] = top;
+    const double bot = (l + 1 < md.n_layers) ? top + md.thickness[l] : INFINITY;
+    G->layers.bottom[l] = bot;
+    G->density[l] = md.density[l];
+    top = bot;
+  }
+  G->nx = pb->grid.nx;
+  G->nz = pb->grid.nz;
+  G->dx = pb->grid.dx;
+  G->dz = pb->grid.dz;
+  G->x0 = pb->grid.x0;
+  G->z0 = pb->grid.z0;
+  G->P = pb->array.n_scans;
+  G->K = pb->array.n_rx;
+  G->beta = pb->array.beta;
+  G->tx_x.assign(pb->array.tx_x, pb->array.tx_x + G->P);
+  G->rx_off.assign(pb->array.rx_offset, pb->array.rx_offset + G->K);
+  G->M = pb->acq.n_samples;
+  G->Q = pb->acq.oversample;
+  G->Lh = dv.Lh;
+  G->fs = pb->acq.fs;
+  G->f_c = pb->acq.f_c;
+  G->sigma_t = pb->acq.sigma_t;
+  G->t_win = pb->acq.t_win;
+  G->n_off = dv.n_off;
+  G->trace_groups = choose_trace_groups(G->voxels(), G->traces());
+
+  const size_t legs = size_t(G->nz) * G->n_off;
+  const size_t PK = size_t(G->P) * G->K;
+  const int QLh = G->Q * G->Lh;
+  auto alloc = [&](void** p, size_t bytes) {
+    G->bytes += bytes;
+    return check_hip(hipMalloc(p, bytes ? bytes : 4), "hipMalloc(geometry)");
+  };
+  double* td_dev = nullptr;
+  if ((st = alloc((void**)&G->delay, legs * sizeof(int64_t))) ||
+      (st = alloc((void**)&G->apod, legs * sizeof(float))) ||
+      (st = alloc((void**)&G->tau, G->nz * sizeof(float))) ||
+      (st = alloc((void**)&G->base, dv.base.size() * sizeof(int))) ||
+      (st = alloc((void**)&G->bank, (QLh + 2) * sizeof(float))) ||
+      (st = alloc((void**)&G->h, QLh * sizeof(float))) ||
+      (st = alloc((void**)&G->habs, QLh * sizeof(float))) ||
+      (st = alloc((void**)&G->dbasis, PK * G->M * sizeof(float))) ||
+      (st = alloc((void**)&G->dnorm, PK * sizeof(float)))) {
+    umbir_geometry_free(G);
+    return st;
+  }
+  // transmittance product per row (Eqs. (3), (7)); reading: each interface
+  // between layers a and b passes 4 Z_a Z_b / (Z_a + Z_b)^2 of the pressure
+  // both ways at normal incidence, Z = rho c; layer 0 has tau = 1.
+  std::vector<float> tau(G->nz);
+  for (int r = 0; r < G->nz; ++r) {
+    const double z = G->z0 + (r + 0.5) * G->dz;
+    double t = 1.0;
+    for (int l = 0; l + 1 < G->layers.n; ++l) {
+      if (z > G->layers.bottom[l]) {
+        const double za = G->density[l] * G->layers.speed[l];
+        const double zb = G->density[l + 1] * G->layers.speed[l + 1];
+        t *= 4.0 * za * zb / ((za + zb) * (za + zb));
+      }
+    }
+    tau[r] = float(t);
+  }
+  // direct-arrival delay of each trace in samples: |x_rx - x_tx| / c_0
+  std::vector<double> td(PK);
+  for (int i = 0; i < G->P; ++i)
+    for (int j = 0; j < G->K; ++j)
+      td[size_t(i) * G->K + j] = G->fs * std::fabs(G->rx_off[j]) / G->layers.speed[0];
+
+  if ((st = check_hip(hipMallocAsync((void**)&td_dev, PK * sizeof(double), s), "hipMallocAsync")) ||
+      (st = check_hip(hipMemcpyAsync(td_dev, td.data(), PK * sizeof(double), hipMemcpyHostToDevice, s),
+                      "hipMemcpyAsync")) ||
+      (st = check_hip(hipMemcpyAsync(G->tau, tau.data(), G->nz * sizeof(float), hipMemcpyHostToDevice, s),
+                      "hipMemcpyAsync")) ||
+      (st = check_hip(hipMemcpyAsync(G->base, dv.base.data(), dv.base.size() * sizeof(int),
+                                     hipMemcpyHostToDevice, s),
+                      "hipMemcpyAsync"))) {
+    if (td_dev) (void)hipFreeAsync(td_dev, s);
+    (void)hipStreamSynchronize(s);
+    umbir_geometry_free(G);
+    return st;
+  }
+  {
+    const int n = int(legs);
+    hipLaunchKernelGGL(k_legs, dim3((n + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off,
+                       G->z0, G->dz, 0.5 * G->dx, G->fs, G->beta, G->delay, G->apod);
+    const double dt = 1.0 / (double(G->Q) * G->fs);
+    hipLaunchKernelGGL(k_bank, dim3((QLh + 2 + 255) / 256), dim3(256), 0, s, G->Q, G->Lh, dt, G->f_c,
+                       1.0 / (2.0 * G->sigma_t * G->sigma_t), 0.5 * G->t_win, G->bank, G->h, G->habs);
+    hipLaunchKernelGGL(k_dbasis, dim3(unsigned(PK)), dim3(256), 0, s, G->bank, td_dev, G->M, G->Q,
+                       G->Lh, G->dbasis, G->dnorm);
+  }
+  st = check_hip(hipGetLastError(), "geometry kernels");
+  (void)hipFreeAsync(td_dev, s);
+  const int st2 = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(build_geometry)");
+  if (!st) st = st2;
+  if (st) {
+    umbir_geometry_free(G);
+    return st;
+  }
+  *out = G;
+  return UMBIR_OK;
+}
+
+size_t umbir_geometry_bytes(const umbir_geometry* G) { return G ? G->bytes : 0; }
+
+int umbir_get_dims(const umbir_geometry* G, umbir_dims* d) {
+  if (!G || !d) return fail(UMBIR_EINVAL, "NULL argument");
+  d->nx = G->nx;
+  d->nz = G->nz;
+  d->n_scans = G->P;
+  d->n_rx = G->K;
+  d->n_samples = G->M;
+  d->n_off = G->n_off;
+  d->window = G->Lh;
+  d->oversample = G->Q;
+  d->n_layers = G->layers.n;
+  return UMBIR_OK;
+}
+
+int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes) {
+  if (!G || !dst) return fail(UMBIR_EINVAL, "NULL argument");
+  const void* src = nullptr;
+  size_t need = 0;
+  const size_t legs = size_t(G->nz) * G->n_off;
+  switch (which) {
+    case UMBIR_TABLE_DELAY: src = G->delay; need = legs * sizeof(int64_t); break;
+    case UMBIR_TABLE_APOD: src = G->apod; need = legs * sizeof(float); break;
+    case UMBIR_TABLE_TAU: src = G->tau; need = G->nz * sizeof(float); break;
+    case UMBIR_TABLE_BANK: src = G->bank; need = (G->Q * G->Lh + 2) * sizeof(float); break;
+    case UMBIR_TABLE_DBASIS: src = G->dbasis; need = size_t(G->traces()) * G->M * sizeof(float); break;
+    case UMBIR_TABLE_OFFSET: src = G->base; need = size_t(G->P) * (1 + G->K) * sizeof(int); break;
+    default: return fail(UMBIR_EINVAL, "unknown table");
+  }
+  if (bytes != need) return fail(UMBIR_EINVAL, "bytes does not match the table size");
+  return check_hip(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost), "hipMemcpy(table)");
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations of the umbir HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "umbir.h"
+
+namespace umbir {
+
+constexpr int kMaxLayers = UMBIR_MAX_LAYERS;
+constexpr double kTwo32 = 4294967296.0;
+
+// Planar layer stack passed to kernels by value.  top/bottom are depths of
+// each layer's faces; the last bottom is +inf.
+struct Layers {
+  int n;
+  double speed[kMaxLayers];
+  double top[kMaxLayers];
+  double bottom[kMaxLayers];
+};
+
+// Records `msg` as the calling thread's last error and returns `status`.
+int fail(int status, const std::string& msg);
+
+// Returns UMBIR_EDEVICE (with the HIP error text) if `e` is not hipSuccess.
+int check_hip(hipError_t e, const char* what);
+
+// Workspace carved out of one device buffer; offsets are 256-byte aligned.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Owns a workspace: the caller's buffer, or one allocated in stream order.
+struct Workspace {
+  void* ptr = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  int acquire(void* user, size_t user_bytes, size_t need, hipStream_t s);
+  ~Workspace();
+};
+
+}  // namespace umbir
+
+struct umbir_geometry {
+  int device = -1;
+  // problem, as validated
+  umbir::Layers layers{};
+  double density[umbir::kMaxLayers] = {};
+  int nx = 0, nz = 0;
+  double dx = 0, dz = 0, x0 = 0, z0 = 0;
+  int P = 0, K = 0, beta = 0;
+  std::vector<double> tx_x, rx_off;
+  int M = 0, Q = 0, Lh = 0;
+  double fs = 0, f_c = 0, sigma_t = 0, t_win = 0;
+  // derived
+  int n_off = 0;        // lattice positions per leg-table row
+  int trace_groups = 1; // traces are split into this many groups in voxel-parallel kernels
+  // resident device tables
+  int64_t* delay = nullptr;  // [nz][n_off] one-way delay, Q32.32 samples
+  float* apod = nullptr;     // [nz][n_off] cos^beta(angle sum)
+  float* tau = nullptr;      // [nz] transmittance product of the row's layer
+  int* base = nullptr;       // [P + P*K] lattice base: offset index = |base + 2 col|
+  float* bank = nullptr;     // [Q*Lh + 2] tabulated windowed pulse, zero padded
+  float* h = nullptr;        // [Lh][Q] polyphase taps h_t[k] = bank[(k+1)Q - t]
+  float* habs = nullptr;     // [Lh][Q] |h|
+  float* dbasis = nullptr;   // [P*K][M] direct-arrival columns of D
+  float* dnorm = nullptr;    // [P*K] squared norms of the columns of D
+  size_t bytes = 0;
+
+  int traces() const { return P * K; }
+  int voxels() const { return nx * nz; }
+  size_t fine_per_trace() const { return size_t(M) * Q; }
+};
+
+namespace umbir {
+
+// Kernel launchers shared between translation units.  All return a status.
+int launch_fill(float* p, size_t n, float v, hipStream_t s);
+int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
+
+// y = base + sign * A x - g D   (base, g may be NULL; x NULL means all ones).
+// `abs_op` builds the operator from |W| and |h|.  fine: P*K*M*Q floats.
+int run_forward(const umbir_geometry& G, const float* x, float* out, const float* base,
+                float sign, const float* g, bool abs_op, float* fine, hipStream_t s);
+
+// out = scale * A^T r.  fine: P*K*M*Q floats; partial: trace_groups * N floats.
+int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale, bool abs_op,
+                float* fine, float* partial, hipStream_t s);
+
+size_t forward_work_bytes(const umbir_geometry& G);
+size_t adjoint_work_bytes(const umbir_geometry& G);
+
+}  // namespace umbir

@@ -1,0 +1,444 @@
+// The system matrix A of Eq. (13) and its transpose, matrix-free.
+//
+// Entry (trace ij, sample m; voxel v) of A is W_ij(v) * I((m - D) Q), where
+// D = fs T_ij(v) is the voxel's delay in samples, W = tau(v) phi^(beta)(v), and
+// I linearly interpolates the tabulated windowed pulse b[n] = h~(n / (Q fs))
+// (Eq. (10)), which is zero at both ends of its window.  Writing
+// D Q = J + phi (J integer, 0 <= phi < 1), the interpolation weights fall on
+// the two fine-grid positions J and J + 1:
+//     I((m - D) Q) = (1 - phi) b[mQ - J] + phi b[mQ - J - 1].
+// So A = C o S, exactly:
+//   S (splat): each voxel deposits W x (1 - phi) at fine position J and
+//      W x phi at J + 1 of its trace's fine-grid signal s[J], J < M Q;
+//   C (polyphase convolution): y[m] = sum_J s[J] b[mQ - J]
+//      = sum_{t<Q} sum_{k<L_h} s[(m-1-k) Q + t] h_t[k],  h_t[k] = b[(k+1) Q - t].
+// The transpose is A^T = S^T o C^T:
+//   C^T (polyphase correlation): c[nQ + t] = sum_{k<L_h} r[n+1+k] h_t[k];
+//   S^T (gather): (A^T r)(v) = sum_ij W ((1 - phi) c[J] + phi c[J+1]).
+// C and C^T are dense, register-blocked and coalesced; S and S^T touch two
+// fine-grid positions per (trace, voxel) pair.  Delays are Q32.32 fixed point
+// (sum of two one-way legs, added exactly as integers), so J and phi are exact.
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace umbir {
+namespace {
+
+constexpr int kR = 16;  // outputs per lane in the dense kernels (register block)
+
+__global__ void k_fill(float* __restrict__ p, size_t n, float v) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  float4* p4 = reinterpret_cast<float4*>(p);
+  const size_t n4 = n / 4;
+  const float4 v4 = make_float4(v, v, v, v);
+  for (size_t k = i; k < n4; k += stride) p4[k] = v4;
+  for (size_t k = n4 * 4 + i; k < n; k += stride) p[k] = v;
+}
+
+__global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, size_t n) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += stride) d[k] = s[k];
+}
+
+// Per-(trace, voxel) terms shared by the splat and the gather: the fine-grid
+// position J, the fraction phi and W / tau (tau is applied per voxel).
+struct Pair {
+  long J;
+  float phi;
+  float w;
+};
+
+__device__ __forceinline__ Pair pair_terms(const int64_t* __restrict__ drow,
+                                           const float* __restrict__ arow, int otx, int orx, int Q) {
+  const uint64_t DQ = uint64_t(drow[otx] + drow[orx]) * uint64_t(Q);
+  Pair p;
+  p.J = long(DQ >> 32);
+  p.phi = float(uint32_t(DQ)) * 2.3283064365386963e-10f;  // 2^-32
+  p.w = arow[otx] * arow[orx];
+  return p;
+}
+
+// S: scatter W x into the fine-grid signal.  Thread = voxel, loop over the
+// traces of group blockIdx.y.  x == NULL means x = 1.
+template <bool ABSW>
+__global__ __launch_bounds__(256) void k_splat(
+    const float* __restrict__ x, int nx, int nz, int n_off, const int64_t* __restrict__ delay,
+    const float* __restrict__ apod, const float* __restrict__ tau, const int* __restrict__ base,
+    int P, int K, int Q, long MQ, int tpg, float* __restrict__ fine) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nx * nz) return;
+  float xv = x ? x[v] : 1.0f;
+  if (xv == 0.0f) return;
+  const int row = v / nx, col = v - row * nx;
+  const int64_t* drow = delay + size_t(row) * n_off;
+  const float* arow = apod + size_t(row) * n_off;
+  float wr = tau[row] * xv;
+  if (ABSW) wr = fabsf(wr);
+  const int PK = P * K;
+  const int t0 = blockIdx.y * tpg;
+  const int t1 = min(t0 + tpg, PK);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t / K;
+    const int otx = abs(base[i] + 2 * col);
+    const int orx = abs(base[P + t] + 2 * col);
+    const Pair p = pair_terms(drow, arow, otx, orx, Q);
+    float w = p.w;
+    if (ABSW) w = fabsf(w);
+    w *= wr;
+    float* s = fine + size_t(t) * MQ;
+    if (p.J < MQ) unsafeAtomicAdd(s + p.J, w * (1.0f - p.phi));
+    if (p.J + 1 < MQ) unsafeAtomicAdd(s + p.J + 1, w * p.phi);
+  }
+}
+
+// S^T: per voxel, sum over the traces of group blockIdx.y; one partial image
+// per group, summed in a fixed order by k_reduce_groups.
+template <bool ABSW>
+__global__ __launch_bounds__(256) void k_gather(
+    const float* __restrict__ fine, int nx, int nz, int n_off, const int64_t* __restrict__ delay,
+    const float* __restrict__ apod, const float* __restrict__ tau, const int* __restrict__ base,
+    int P, int K, int Q, long MQ, int tpg, float* __restrict__ partial) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = nx * nz;
+  if (v >= N) return;
+  const int row = v / nx, col = v - row * nx;
+  const int64_t* drow = delay + size_t(row) * n_off;
+  const float* arow = apod + size_t(row) * n_off;
+  const int PK = P * K;
+  const int t0 = blockIdx.y * tpg;
+  const int t1 = min(t0 + tpg, PK);
+  float acc = 0.0f;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t / K;
+    const int otx = abs(base[i] + 2 * col);
+    const int orx = abs(base[P + t] + 2 * col);
+    const Pair p = pair_terms(drow, arow, otx, orx, Q);
+    float w = p.w;
+    if (ABSW) w = fabsf(w);
+    const float* c = fine + size_t(t) * MQ;
+    const float c0 = p.J < MQ ? c[p.J] : 0.0f;
+    const float c1 = p.J + 1 < MQ ? c[p.J + 1] : 0.0f;
+    acc = fmaf(w, fmaf(p.phi, c1 - c0, c0), acc);
+  }
+  float tr = tau[row];
+  if (ABSW) tr = fabsf(tr);
+  partial[size_t(blockIdx.y) * N + v] = acc * tr;
+}
+
+__global__ void k_reduce_groups(const float* __restrict__ partial, int groups, int N, float scale,
+                                float* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  float acc = 0.0f;
+  for (int g = 0; g < groups; ++g) acc += partial[size_t(g) * N + v];
+  out[v] = acc * scale;
+}
+
+// Stage the polyphase taps [L_h][Q] into LDS, zero-padded to LhPad rows.
+__device__ __forceinline__ void stage_taps(float* sh, const float* __restrict__ hq, int Lh, int LhPad,
+                                           int Q) {
+  for (int i = threadIdx.x; i < LhPad * Q; i += blockDim.x) sh[i] = i < Lh * Q ? hq[i] : 0.0f;
+  __syncthreads();
+}
+
+// C: y[m] = sum_t sum_k s[(m-1-k)Q + t] h_t[k].  Lane = (phase t, block of R
+// outputs); the phase sum is a cross-lane reduction at the end.
+//   out[m] = (base ? base[m] : 0) + sign * y[m] - (g ? g[ij] d_ij[m] : 0)
+// base may alias out.
+template <int Q>
+__global__ __launch_bounds__(256) void k_conv(const float* __restrict__ fine,
+                                              const float* __restrict__ hq, int M, int Lh, int LhPad,
+                                              const float* base, float sign,
+                                              const float* __restrict__ g,
+                                              const float* __restrict__ dbasis, float* out) {
+  constexpr int R = kR;
+  constexpr int MB = 64 / Q;
+  constexpr int PER_WAVE = MB * R;
+  extern __shared__ float sh[];
+  stage_taps(sh, hq, Lh, LhPad, Q);
+  const int ij = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = lane & (Q - 1), mb = lane / Q;
+  const int m0 = blockIdx.x * (4 * PER_WAVE) + wave * PER_WAVE + mb * R;
+  const float* s = fine + size_t(ij) * M * Q + t;
+  auto ld = [&](int n) -> float { return (n >= 0 && n < M) ? s[size_t(n) * Q] : 0.0f; };
+  float acc[R];
+  float buf[2 * R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+  // buf[q] holds s at n = m0 - k0 - R + q for the current tap block k0
+#pragma unroll
+  for (int q = 0; q < 2 * R - 1; ++q) buf[q] = ld(m0 - R + q);
+  for (int k0 = 0; k0 < LhPad; k0 += R) {
+#pragma unroll
+    for (int kk = 0; kk < R; ++kk) {
+      const float hv = sh[(k0 + kk) * Q + t];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = fmaf(buf[r - kk + R - 1], hv, acc[r]);
+    }
+#pragma unroll
+    for (int q = R - 2; q >= 0; --q) buf[q + R] = buf[q];
+    const int nb = m0 - k0 - 2 * R;
+#pragma unroll
+    for (int q = 0; q < R; ++q) buf[q] = ld(nb + q);
+  }
+#pragma unroll
+  for (int off = Q / 2; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += __shfl_xor(acc[r], off);
+  }
+  const float gv = g ? g[ij] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int m = m0 + r;
+    if ((r & (Q - 1)) == t && m < M) {
+      const size_t idx = size_t(ij) * M + m;
+      float val = sign * acc[r];
+      if (base) val += base[idx];
+      if (g) val -= gv * dbasis[idx];
+      out[idx] = val;
+    }
+  }
+}
+
+// C^T: c[nQ + t] = sum_k r[n+1+k] h_t[k], for n < M.  Lane = (phase t, block
+// of R consecutive n); writes are coalesced along t.
+template <int Q>
+__global__ __launch_bounds__(256) void k_corr(const float* __restrict__ rt,
+                                              const float* __restrict__ hq, int M, int Lh, int LhPad,
+                                              float* __restrict__ fine) {
+  constexpr int R = kR;
+  constexpr int NB = 64 / Q;
+  constexpr int PER_WAVE = NB * R;
+  extern __shared__ float sh[];
+  stage_taps(sh, hq, Lh, LhPad, Q);
+  const int ij = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = lane & (Q - 1), nb = lane / Q;
+  const int n0 = blockIdx.x * (4 * PER_WAVE) + wave * PER_WAVE + nb * R;
+  const float* r = rt + size_t(ij) * M;
+  auto ld = [&](int m) -> float { return m < M ? r[m] : 0.0f; };
+  float acc[R];
+  float buf[2 * R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+  // buf[p] holds r[n0 + 1 + k0 + p] for the current tap block k0
+#pragma unroll
+  for (int p = 0; p < 2 * R - 1; ++p) buf[p] = ld(n0 + 1 + p);
+  for (int k0 = 0; k0 < LhPad; k0 += R) {
+#pragma unroll
+    for (int kk = 0; kk < R; ++kk) {
+      const float hv = sh[(k0 + kk) * Q + t];
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = fmaf(buf[q + kk], hv, acc[q]);
+    }
+#pragma unroll
+    for (int p = 0; p < R - 1; ++p) buf[p] = buf[p + R];
+    const int mb = n0 + 1 + k0 + R;
+#pragma unroll
+    for (int p = R - 1; p < 2 * R - 1; ++p) buf[p] = ld(mb + p);
+  }
+  float* c = fine + size_t(ij) * M * Q + t;
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (n0 + q < M) c[size_t(n0 + q) * Q] = acc[q];
+}
+
+__global__ void k_direct(const float* __restrict__ g, const float* __restrict__ dbasis, int M,
+                         size_t total, int accumulate, float* __restrict__ y) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < total; k += stride) {
+    const float v = g[k / M] * dbasis[k];
+    y[k] = accumulate ? y[k] + v : v;
+  }
+}
+
+int grid_1d(size_t n) {
+  size_t b = (n + 255) / 256;
+  return int(b > 8192 ? 8192 : (b ? b : 1));
+}
+
+int lh_pad(int Lh) { return (Lh + kR - 1) / kR * kR; }
+
+template <int Q>
+void launch_conv_q(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
+                   float sign, const float* g, float* out, hipStream_t s) {
+  constexpr int per_block = 4 * (64 / Q) * kR;
+  const int LhP = lh_pad(G.Lh);
+  dim3 grid((G.M + per_block - 1) / per_block, G.traces());
+  hipLaunchKernelGGL(k_conv<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, fine, hq, G.M,
+                     G.Lh, LhP, base, sign, g, G.dbasis, out);
+}
+
+template <int Q>
+void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, float* fine,
+                   hipStream_t s) {
+  constexpr int per_block = 4 * (64 / Q) * kR;
+  const int LhP = lh_pad(G.Lh);
+  dim3 grid((G.M + per_block - 1) / per_block, G.traces());
+  hipLaunchKernelGGL(k_corr<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, r, hq, G.M,
+                     G.Lh, LhP, fine);
+}
+
+void launch_conv(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
+                 float sign, const float* g, float* out, hipStream_t s) {
+  switch (G.Q) {
+    case 1: launch_conv_q<1>(G, fine, hq, base, sign, g, out, s); break;
+    case 2: launch_conv_q<2>(G, fine, hq, base, sign, g, out, s); break;
+    case 4: launch_conv_q<4>(G, fine, hq, base, sign, g, out, s); break;
+    case 8: launch_conv_q<8>(G, fine, hq, base, sign, g, out, s); break;
+    case 16: launch_conv_q<16>(G, fine, hq, base, sign, g, out, s); break;
+    case 32: launch_conv_q<32>(G, fine, hq, base, sign, g, out, s); break;
+    default: launch_conv_q<64>(G, fine, hq, base, sign, g, out, s); break;
+  }
+}
+
+void launch_corr(const umbir_geometry& G, const float* r, const float* hq, float* fine,
+                 hipStream_t s) {
+  switch (G.Q) {
+    case 1: launch_corr_q<1>(G, r, hq, fine, s); break;
+    case 2: launch_corr_q<2>(G, r, hq, fine, s); break;
+    case 4: launch_corr_q<4>(G, r, hq, fine, s); break;
+    case 8: launch_corr_q<8>(G, r, hq, fine, s); break;
+    case 16: launch_corr_q<16>(G, r, hq, fine, s); break;
+    case 32: launch_corr_q<32>(G, r, hq, fine, s); break;
+    default: launch_corr_q<64>(G, r, hq, fine, s); break;
+  }
+}
+
+size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+int launch_fill(float* p, size_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_1d(n / 4 + 1)), dim3(256), 0, s, p, n, v);
+  return check_hip(hipGetLastError(), "k_fill");
+}
+
+int launch_copy(float* dst, const float* src, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_1d(n)), dim3(256), 0, s, dst, src, n);
+  return check_hip(hipGetLastError(), "k_copy");
+}
+
+size_t forward_work_bytes(const umbir_geometry& G) {
+  return aligned(size_t(G.traces()) * G.fine_per_trace() * sizeof(float)) + 256;
+}
+
+size_t adjoint_work_bytes(const umbir_geometry& G) {
+  return forward_work_bytes(G) + aligned(size_t(G.trace_groups) * G.voxels() * sizeof(float)) + 256;
+}
+
+int run_forward(const umbir_geometry& G, const float* x, float* out, const float* base, float sign,
+                const float* g, bool abs_op, float* fine, hipStream_t s) {
+  const long MQ = long(G.fine_per_trace());
+  int st = launch_fill(fine, size_t(G.traces()) * MQ, 0.0f, s);
+  if (st) return st;
+  const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
+  dim3 grid((G.voxels() + 255) / 256, G.trace_groups);
+  if (abs_op)
+    hipLaunchKernelGGL(k_splat<true>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay, G.apod,
+                       G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, fine);
+  else
+    hipLaunchKernelGGL(k_splat<false>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay,
+                       G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, fine);
+  if ((st = check_hip(hipGetLastError(), "k_splat"))) return st;
+  launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
+  return check_hip(hipGetLastError(), "k_conv");
+}
+
+int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale, bool abs_op,
+                float* fine, float* partial, hipStream_t s) {
+  const long MQ = long(G.fine_per_trace());
+  launch_corr(G, r, abs_op ? G.habs : G.h, fine, s);
+  int st = check_hip(hipGetLastError(), "k_corr");
+  if (st) return st;
+  const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
+  dim3 grid((G.voxels() + 255) / 256, G.trace_groups);
+  if (abs_op)
+    hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
+                       G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, partial);
+  else
+    hipLaunchKernelGGL(k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
+                       G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, partial);
+  if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
+  hipLaunchKernelGGL(k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
+                     G.trace_groups, G.voxels(), scale, out);
+  return check_hip(hipGetLastError(), "k_reduce_groups");
+}
+
+}  // namespace umbir
+
+using namespace umbir;
+
+extern "C" {
+
+size_t umbir_workspace_bytes(const umbir_geometry* G, int kind) {
+  if (!G) return 0;
+  switch (kind) {
+    case UMBIR_WORK_FORWARD: return forward_work_bytes(*G);
+    case UMBIR_WORK_ADJOINT: return adjoint_work_bytes(*G);
+    case UMBIR_WORK_RECONSTRUCT: {
+      const size_t N = G->voxels(), PK = G->traces();
+      const size_t nblk = (N + 255) / 256 + 1;
+      return adjoint_work_bytes(*G) + aligned(PK * G->M * sizeof(float)) + 5 * aligned(N * sizeof(float)) +
+             aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + 16 * 256;
+    }
+    default: return 0;
+  }
+}
+
+int umbir_forward(const umbir_geometry* G, const float* x, float* y, int accumulate, void* work,
+                  size_t work_bytes, void* stream) {
+  if (!G || !x || !y) return fail(UMBIR_EINVAL, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  int st = ws.acquire(work, work_bytes, forward_work_bytes(*G), s);
+  if (st) return st;
+  Carve cv{static_cast<char*>(ws.ptr)};
+  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace());
+  return run_forward(*G, x, y, accumulate ? y : nullptr, 1.0f, nullptr, false, fine, s);
+}
+
+int umbir_adjoint(const umbir_geometry* G, const float* r, float* x, void* work, size_t work_bytes,
+                  void* stream) {
+  if (!G || !r || !x) return fail(UMBIR_EINVAL, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  int st = ws.acquire(work, work_bytes, adjoint_work_bytes(*G), s);
+  if (st) return st;
+  Carve cv{static_cast<char*>(ws.ptr)};
+  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace());
+  float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
+  return run_adjoint(*G, r, x, 1.0f, false, fine, partial, s);
+}
+
+int umbir_direct(const umbir_geometry* G, const float* g, float* y, int accumulate, void* stream) {
+  if (!G || !g || !y) return fail(UMBIR_EINVAL, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t total = size_t(G->traces()) * G->M;
+  hipLaunchKernelGGL(k_direct, dim3(grid_1d(total)), dim3(256), 0, s, g, G->dbasis, G->M, total,
+                     accumulate, y);
+  return check_hip(hipGetLastError(), "k_direct");
+}
+
+int umbir_sqs_denominator(const umbir_geometry* G, double sigma, float* d, void* work,
+                          size_t work_bytes, void* stream) {
+  if (!G || !d) return fail(UMBIR_EINVAL, "NULL argument");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(UMBIR_EINVAL, "sigma must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = adjoint_work_bytes(*G) + aligned(size_t(G->traces()) * G->M * sizeof(float)) + 256;
+  Workspace ws;
+  int st = ws.acquire(work, work_bytes, need, s);
+  if (st) return st;
+  Carve cv{static_cast<char*>(ws.ptr)};
+  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace());
+  float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
+  float* col = cv.take<float>(size_t(G->traces()) * G->M);
+  if ((st = run_forward(*G, nullptr, col, nullptr, 1.0f, nullptr, true, fine, s))) return st;
+  return run_adjoint(*G, col, d, float(1.0 / (sigma * sigma)), true, fine, partial, s);
+}
+
+}  // extern "C"

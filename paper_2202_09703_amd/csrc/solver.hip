@@ -1,0 +1,248 @@
+// MAP reconstruction of Eq. (18) with the QGGMRF prior of Eqs. (14)-(17).
+//
+// The paper minimises the cost with ICD.  Here every voxel is updated at once
+// from one A x and one A^T e per iteration, by a separable surrogate of the
+// cost (data term: curvature d = |A|^T |A| 1 / sigma^2, which bounds A^T A /
+// sigma^2 because |A| >= |entries of A| and all its entries are >= 0; prior
+// term: each pair potential bounded by the quadratic through rho at the
+// current difference with the same slope, split evenly between the two
+// voxels).  Each step lowers the cost, and the cost being strictly convex
+// (Sec. 2, "Optimization") the iteration shares ICD's minimiser.
+//
+// Iteration n (from x^n, g^n):
+//   1. e = y - A x - D g                        (k_conv epilogue)
+//   2. record C(x^n, g^n); if estimating g: g += <d_ij, e_ij> / |d_ij|^2 per
+//      trace and e -= d_ij * dg (the columns of D have disjoint rows)
+//   3. u = A^T e
+//   4. for every voxel s, over its 8 neighbours r (Eq. (14) cliques):
+//        B = b_sr rho'(x_s - x_r) / (2 (x_s - x_r))
+//        x_s -= (-u_s / sigma^2 + sum_r 2 B (x_s - x_r)) / (d_s + sum_r 4 B)
+// Reading of the clique weights (not given in the paper): the 8-neighbourhood
+// with weights proportional to inverse centre distance, normalised so an
+// interior voxel's eight weights sum to one; missing neighbours at the border
+// are dropped.  The scale of Eq. (16) uses m_s of Eq. (17) with depth = the
+// voxel-centre depth and maximum depth = the deepest centre.
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace umbir {
+namespace {
+
+struct PriorConst {
+  float inv_sigma2;
+  float p;
+  float T;
+  float sigma0;
+  double m, a;
+  double z0, dz;
+};
+
+__device__ __forceinline__ float depth_mod(int row, int nz, const PriorConst& pc) {
+  const double depth = pc.z0 + (row + 0.5) * pc.dz;
+  const double dmax = pc.z0 + (nz - 0.5) * pc.dz;
+  return float(1.0 + (pc.m - 1.0) * pow(depth / dmax, pc.a));
+}
+
+// Half curvature rho'(D) / (2 D) of Eq. (15) with q = 2 (finite at D = 0):
+// (T sg)^(p-2) / (2 sg^p) * (2/p + u^(2-p)) / (1 + u^(2-p))^2, u = |D| / (T sg).
+// Also rho(D) = |D|^p / (p sg^p) * u^(2-p) / (1 + u^(2-p)).
+__device__ __forceinline__ void qggmrf(float delta, float sg, const PriorConst& pc, float* half_curv,
+                                       float* rho) {
+  const float a = fabsf(delta);
+  const float tsg = pc.T * sg;
+  const float sgp = powf(sg, pc.p);
+  const float uq = powf(a / tsg, 2.0f - pc.p);
+  const float den = 1.0f + uq;
+  *half_curv = powf(tsg, pc.p - 2.0f) / (2.0f * sgp) * (2.0f / pc.p + uq) / (den * den);
+  *rho = powf(a, pc.p) / (pc.p * sgp) * uq / den;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Per trace: |e|^2 before the g step, then the exact g step.
+__global__ __launch_bounds__(256) void k_gstep(float* __restrict__ e, const float* __restrict__ d,
+                                               const float* __restrict__ dnorm, float* __restrict__ g,
+                                               int M, int estimate, double* __restrict__ ess) {
+  __shared__ double sh[256];
+  __shared__ float dg_sh;
+  const int ij = blockIdx.x;
+  float* et = e + size_t(ij) * M;
+  const float* dt = d + size_t(ij) * M;
+  double ee = 0.0, de = 0.0;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const double ev = et[m];
+    ee += ev * ev;
+    de += double(dt[m]) * ev;
+  }
+  ee = block_sum(ee, sh);
+  de = block_sum(de, sh);
+  if (threadIdx.x == 0) {
+    ess[ij] = ee;
+    float dg = 0.0f;
+    if (estimate && dnorm[ij] > 0.0f) {
+      dg = float(de / double(dnorm[ij]));
+      g[ij] += dg;
+    }
+    dg_sh = dg;
+  }
+  __syncthreads();
+  const float dg = dg_sh;
+  if (dg != 0.0f)
+    for (int m = threadIdx.x; m < M; m += blockDim.x) et[m] = fmaf(-dg, dt[m], et[m]);
+}
+
+// Prior cost of x (pairs counted once) into pcost[block]; with UPDATE also the
+// surrogate step into xout.
+template <bool UPDATE>
+__global__ __launch_bounds__(256) void k_prior(const float* __restrict__ x, const float* __restrict__ u,
+                                               const float* __restrict__ den, int nx, int nz,
+                                               PriorConst pc, float* __restrict__ xout,
+                                               double* __restrict__ pcost) {
+  __shared__ double sh[256];
+  const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
+  const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double cost = 0.0;
+  if (v < nx * nz) {
+    const int row = v / nx, col = v - row * nx;
+    const float xs = x[v];
+    const float ms = depth_mod(row, nz, pc);
+    float slope = 0.0f, curv = 0.0f;
+#pragma unroll
+    for (int dr = -1; dr <= 1; ++dr) {
+      const int r2 = row + dr;
+      if (r2 < 0 || r2 >= nz) continue;
+      const float sg = pc.sigma0 * sqrtf(ms * depth_mod(r2, nz, pc));
+#pragma unroll
+      for (int dc = -1; dc <= 1; ++dc) {
+        const int c2 = col + dc;
+        if ((dr == 0 && dc == 0) || c2 < 0 || c2 >= nx) continue;
+        const float bw = (dr == 0 || dc == 0) ? b_edge : b_diag;
+        const float delta = xs - x[r2 * nx + c2];
+        float hc, rho;
+        qggmrf(delta, sg, pc, &hc, &rho);
+        const float B = bw * hc;
+        slope = fmaf(2.0f * B, delta, slope);
+        curv = fmaf(4.0f, B, curv);
+        // each unordered pair once: the neighbour to the right or below
+        if (dr == 1 || (dr == 0 && dc == 1)) cost += double(bw) * double(rho);
+      }
+    }
+    if (UPDATE) {
+      const float grad = fmaf(-u[v], pc.inv_sigma2, slope);
+      xout[v] = xs - grad / (den[v] + curv);
+    }
+  }
+  cost = block_sum(cost, sh);
+  if (threadIdx.x == 0) pcost[blockIdx.x] = cost;
+}
+
+__global__ __launch_bounds__(256) void k_cost(const double* __restrict__ ess, int n_ess,
+                                              const double* __restrict__ pcost, int n_p,
+                                              double inv_2sigma2, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n_ess; i += blockDim.x) a += ess[i];
+  for (int i = threadIdx.x; i < n_p; i += blockDim.x) b += pcost[i];
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) *out = a * inv_2sigma2 + b;
+}
+
+int validate_prior(const umbir_prior* pr) {
+  if (!pr) return fail(UMBIR_EINVAL, "prior is NULL");
+  auto fin = [](double v) { return std::isfinite(v); };
+  if (!fin(pr->sigma) || pr->sigma <= 0.0) return fail(UMBIR_EINVAL, "sigma must be > 0");
+  if (!fin(pr->q) || pr->q != 2.0) return fail(UMBIR_EINVAL, "q must equal 2 (Sec. 2: 1 < p < q = 2)");
+  if (!fin(pr->p) || !(pr->p > 1.0) || pr->p > pr->q)
+    return fail(UMBIR_EINVAL, "p must satisfy 1 < p <= q");
+  if (!fin(pr->T) || pr->T <= 0.0) return fail(UMBIR_EINVAL, "T must be > 0");
+  if (!fin(pr->sigma0) || pr->sigma0 <= 0.0) return fail(UMBIR_EINVAL, "sigma0 must be > 0");
+  if (!fin(pr->m) || pr->m <= 0.0) return fail(UMBIR_EINVAL, "m must be > 0");
+  if (!fin(pr->a) || pr->a < 0.0) return fail(UMBIR_EINVAL, "a must be >= 0");
+  return UMBIR_OK;
+}
+
+size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace umbir
+
+using namespace umbir;
+
+extern "C" int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const float* y,
+                                 int n_iter, float* x_io, float* g_io, double* cost, void* work,
+                                 size_t work_bytes, void* stream) {
+  if (!G || !y || !x_io || !g_io) return fail(UMBIR_EINVAL, "NULL argument");
+  if (n_iter < 0) return fail(UMBIR_EINVAL, "n_iter must be >= 0");
+  int st = validate_prior(pr);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  if ((st = ws.acquire(work, work_bytes, umbir_workspace_bytes(G, UMBIR_WORK_RECONSTRUCT), s))) return st;
+  const size_t N = G->voxels(), PK = G->traces();
+  const int nblk = int((N + 255) / 256);
+  Carve cv{static_cast<char*>(ws.ptr)};
+  float* fine = cv.take<float>(PK * G->fine_per_trace());
+  float* partial = cv.take<float>(size_t(G->trace_groups) * N);
+  float* e = cv.take<float>(PK * G->M);
+  float* u = cv.take<float>(N);
+  float* den = cv.take<float>(N);
+  float* xa = cv.take<float>(N);
+  float* xb = cv.take<float>(N);
+  double* ess = cv.take<double>(PK);
+  double* pcost = cv.take<double>(nblk);
+
+  PriorConst pc;
+  pc.inv_sigma2 = float(1.0 / (pr->sigma * pr->sigma));
+  pc.p = float(pr->p);
+  pc.T = float(pr->T);
+  pc.sigma0 = float(pr->sigma0);
+  pc.m = pr->m;
+  pc.a = pr->a;
+  pc.z0 = G->z0;
+  pc.dz = G->dz;
+  const double inv_2s2 = 0.5 / (pr->sigma * pr->sigma);
+  const int est = pr->estimate_direct ? 1 : 0;
+
+  // data-term curvature d = |A|^T |A| 1 / sigma^2
+  if ((st = run_forward(*G, nullptr, e, nullptr, 1.0f, nullptr, true, fine, s))) return st;
+  if ((st = run_adjoint(*G, e, den, pc.inv_sigma2, true, fine, partial, s))) return st;
+  if ((st = launch_copy(xa, x_io, N, s))) return st;
+
+  for (int it = 0; it <= n_iter; ++it) {
+    const bool last = it == n_iter;
+    if ((st = run_forward(*G, xa, e, y, -1.0f, g_io, false, fine, s))) return st;
+    hipLaunchKernelGGL(k_gstep, dim3(unsigned(PK)), dim3(256), 0, s, e, G->dbasis, G->dnorm, g_io,
+                       G->M, last ? 0 : est, ess);
+    if ((st = check_hip(hipGetLastError(), "k_gstep"))) return st;
+    if (last) {
+      hipLaunchKernelGGL(k_prior<false>, dim3(nblk), dim3(256), 0, s, xa, nullptr, nullptr, G->nx,
+                         G->nz, pc, nullptr, pcost);
+    } else {
+      if ((st = run_adjoint(*G, e, u, 1.0f, false, fine, partial, s))) return st;
+      hipLaunchKernelGGL(k_prior<true>, dim3(nblk), dim3(256), 0, s, xa, u, den, G->nx, G->nz, pc, xb,
+                         pcost);
+    }
+    if ((st = check_hip(hipGetLastError(), "k_prior"))) return st;
+    if (cost) {
+      hipLaunchKernelGGL(k_cost, dim3(1), dim3(256), 0, s, ess, int(PK), pcost, nblk, inv_2s2,
+                         cost + it);
+      if ((st = check_hip(hipGetLastError(), "k_cost"))) return st;
+    }
+    if (!last) std::swap(xa, xb);
+  }
+  return launch_copy(x_io, xa, N, s);
+}

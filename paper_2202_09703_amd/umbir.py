@@ -1,0 +1,316 @@
+"""Python binding of libumbir.so (include/umbir.h): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch supplies device memory and
+the current stream.  The functions keep the C names without the prefix:
+build_geometry, forward, adjoint, direct, sqs_denominator, reconstruct.
+If the library has not been built, importing this module raises ImportError:
+there is no fallback path.
+
+Problem descriptions are duck-typed: any object with `medium` (speed,
+thickness, atten, density), `grid` (nx, nz, dx, dz, x0, z0), `array` (tx_x,
+rx_offset, beta) and `acq` (n_samples, fs, f_c, sigma_t, t_win, oversample)
+attributes, in SI units, describes a problem.  A prior is any object with
+p, q, T, sigma0, m, a and estimate_direct attributes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+# torch goes first: it loads its own HIP runtime (SONAME libamdhip64.so.7), and
+# the library's dependency on that SONAME then binds to the same copy, so one
+# process never holds two HIP/HSA runtimes.
+import torch  # noqa: E402,F401
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libumbir.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2202_09703_amd.build`")
+_lib = C.CDLL(_LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, EDIVERGED = 0, -1, -2, -3, -4, -5
+WORK_FORWARD, WORK_ADJOINT, WORK_RECONSTRUCT = 0, 1, 2
+TABLE_DELAY, TABLE_APOD, TABLE_TAU, TABLE_BANK, TABLE_DBASIS, TABLE_OFFSET = range(6)
+MAX_LAYERS = 8
+
+_dp = C.POINTER(C.c_double)
+
+
+class _Medium(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("speed", _dp), ("thickness", _dp), ("atten", _dp),
+                ("density", _dp)]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("dx", C.c_double), ("dz", C.c_double),
+                ("x0", C.c_double), ("z0", C.c_double)]
+
+
+class _Array(C.Structure):
+    _fields_ = [("n_scans", C.c_int), ("tx_x", _dp), ("n_rx", C.c_int), ("rx_offset", _dp),
+                ("beta", C.c_int)]
+
+
+class _Acq(C.Structure):
+    _fields_ = [("n_samples", C.c_int), ("fs", C.c_double), ("f_c", C.c_double),
+                ("sigma_t", C.c_double), ("t_win", C.c_double), ("oversample", C.c_int)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("medium", _Medium), ("grid", _Grid), ("array", _Array), ("acq", _Acq)]
+
+
+class _Prior(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("p", C.c_double), ("q", C.c_double), ("T", C.c_double),
+                ("sigma0", C.c_double), ("m", C.c_double), ("a", C.c_double),
+                ("estimate_direct", C.c_int)]
+
+
+class _Dims(C.Structure):
+    _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("n_scans", C.c_int), ("n_rx", C.c_int),
+                ("n_samples", C.c_int), ("n_off", C.c_int), ("window", C.c_int),
+                ("oversample", C.c_int), ("n_layers", C.c_int)]
+
+
+_vp, _sz, _i = C.c_void_p, C.c_size_t, C.c_int
+_SIGS = {
+    "umbir_build_geometry": (_i, [C.POINTER(_Problem), _vp, C.POINTER(_vp)]),
+    "umbir_geometry_free": (None, [_vp]),
+    "umbir_geometry_bytes": (_sz, [_vp]),
+    "umbir_estimate_bytes": (_sz, [C.POINTER(_Problem)]),
+    "umbir_workspace_bytes": (_sz, [_vp, _i]),
+    "umbir_forward": (_i, [_vp, _vp, _vp, _i, _vp, _sz, _vp]),
+    "umbir_adjoint": (_i, [_vp, _vp, _vp, _vp, _sz, _vp]),
+    "umbir_direct": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "umbir_sqs_denominator": (_i, [_vp, C.c_double, _vp, _vp, _sz, _vp]),
+    "umbir_reconstruct": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "umbir_get_dims": (_i, [_vp, C.POINTER(_Dims)]),
+    "umbir_copy_table": (_i, [_vp, _i, _vp, _sz]),
+    "umbir_strerror": (C.c_char_p, [_i]),
+    "umbir_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTS = tuple(_SIGS)
+
+
+class UmbirError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = _lib.umbir_last_error().decode()
+        super().__init__(f"{where}: {_lib.umbir_strerror(status).decode()} ({status}): {detail}")
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise UmbirError(status, where)
+
+
+def _darr(values):
+    vals = [float(v) for v in values]
+    return (C.c_double * max(1, len(vals)))(*vals)
+
+
+class Problem:
+    """A ctypes umbir_problem built from a card-like object; keeps its arrays alive."""
+
+    def __init__(self, card):
+        med, g, a, q = card.medium, card.grid, card.array, card.acq
+        n = len(med.speed)
+        self._keep = [_darr(med.speed), _darr(med.thickness), _darr(med.atten or [0.0] * n),
+                      _darr(med.density), _darr(a.tx_x), _darr(a.rx_offset)]
+        sp, th, at, de, tx, rx = self._keep
+        self.c = _Problem(
+            _Medium(n, sp, th, at, de),
+            _Grid(int(g.nx), int(g.nz), float(g.dx), float(g.dz), float(g.x0), float(g.z0)),
+            _Array(len(a.tx_x), tx, len(a.rx_offset), rx, int(a.beta)),
+            _Acq(int(q.n_samples), float(q.fs), float(q.f_c), float(q.sigma_t), float(q.t_win),
+                 int(q.oversample)))
+
+
+def estimate_bytes(card) -> int:
+    return int(_lib.umbir_estimate_bytes(C.byref(Problem(card).c)))
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, name, shape=None, dtype=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Geometry:
+    """Owns a built umbir_geometry (device tables resident until freed)."""
+
+    def __init__(self, handle: C.c_void_p, device: int):
+        self._h = handle
+        self.device = device
+        d = _Dims()
+        _check(_lib.umbir_get_dims(self._h, C.byref(d)), "umbir_get_dims")
+        self.nx, self.nz = d.nx, d.nz
+        self.n_scans, self.n_rx, self.n_samples = d.n_scans, d.n_rx, d.n_samples
+        self.n_off, self.window, self.oversample, self.n_layers = d.n_off, d.window, d.oversample, d.n_layers
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("geometry has been freed")
+        return self._h
+
+    @property
+    def image_shape(self):
+        return (self.nz, self.nx)
+
+    @property
+    def trace_shape(self):
+        return (self.n_scans, self.n_rx, self.n_samples)
+
+    @property
+    def bytes(self) -> int:
+        return int(_lib.umbir_geometry_bytes(self.handle))
+
+    def workspace_bytes(self, kind: int) -> int:
+        return int(_lib.umbir_workspace_bytes(self.handle, kind))
+
+    def workspace(self, kind: int):
+        import torch
+        return torch.empty(self.workspace_bytes(kind), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def table(self, which: int) -> np.ndarray:
+        P, K, M = self.trace_shape
+        spec = {
+            TABLE_DELAY: (np.int64, (self.nz, self.n_off)),
+            TABLE_APOD: (np.float32, (self.nz, self.n_off)),
+            TABLE_TAU: (np.float32, (self.nz,)),
+            TABLE_BANK: (np.float32, (self.oversample * self.window + 2,)),
+            TABLE_DBASIS: (np.float32, (P, K, M)),
+            TABLE_OFFSET: (np.int32, (P + P * K,)),
+        }[which]
+        out = np.empty(spec[1], dtype=spec[0])
+        _check(_lib.umbir_copy_table(self.handle, which, out.ctypes.data_as(C.c_void_p), out.nbytes),
+               "umbir_copy_table")
+        return out
+
+    def free(self):
+        if self._h:
+            _lib.umbir_geometry_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_geometry(card, stream=None) -> Geometry:
+    import torch
+    pb = Problem(card)
+    h = C.c_void_p()
+    _check(_lib.umbir_build_geometry(C.byref(pb.c), _stream(stream), C.byref(h)), "umbir_build_geometry")
+    return Geometry(h, torch.cuda.current_device())
+
+
+def _work(geom, work, kind):
+    if work is None:
+        work = geom.workspace(kind)
+    return _ptr(work, "work"), C.c_size_t(work.numel() * work.element_size())
+
+
+def forward(geom: Geometry, x, y=None, accumulate: bool = False, work=None, stream=None):
+    """y = A x (or y += A x); x: [nz][nx] float32, y: [P][K][M] float32."""
+    import torch
+    if y is None:
+        y = torch.empty(geom.trace_shape, dtype=torch.float32, device=x.device)
+    wp, wb = _work(geom, work, WORK_FORWARD)
+    _check(_lib.umbir_forward(geom.handle, _ptr(x, "x", geom.image_shape, torch.float32),
+                              _ptr(y, "y", geom.trace_shape, torch.float32), int(bool(accumulate)),
+                              wp, wb, _stream(stream)), "umbir_forward")
+    return y
+
+
+def adjoint(geom: Geometry, r, x=None, work=None, stream=None):
+    """x = A^T r; r: [P][K][M] float32, x: [nz][nx] float32."""
+    import torch
+    if x is None:
+        x = torch.empty(geom.image_shape, dtype=torch.float32, device=r.device)
+    wp, wb = _work(geom, work, WORK_ADJOINT)
+    _check(_lib.umbir_adjoint(geom.handle, _ptr(r, "r", geom.trace_shape, torch.float32),
+                              _ptr(x, "x", geom.image_shape, torch.float32), wp, wb, _stream(stream)),
+           "umbir_adjoint")
+    return x
+
+
+def direct(geom: Geometry, g, y=None, accumulate: bool = False, stream=None):
+    """y = D g (or y += D g); g: [P][K] float32."""
+    import torch
+    if y is None:
+        y = torch.empty(geom.trace_shape, dtype=torch.float32, device=g.device)
+    _check(_lib.umbir_direct(geom.handle, _ptr(g, "g", geom.trace_shape[:2], torch.float32),
+                             _ptr(y, "y", geom.trace_shape, torch.float32), int(bool(accumulate)),
+                             _stream(stream)), "umbir_direct")
+    return y
+
+
+def sqs_denominator(geom: Geometry, sigma: float, d=None, work=None, stream=None):
+    """d = |A|^T |A| 1 / sigma^2 as [nz][nx] float32."""
+    import torch
+    dev = f"cuda:{geom.device}"
+    if d is None:
+        d = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
+    wp, wb = _work(geom, work, WORK_RECONSTRUCT)
+    _check(_lib.umbir_sqs_denominator(geom.handle, float(sigma), _ptr(d, "d", geom.image_shape, torch.float32),
+                                      wp, wb, _stream(stream)), "umbir_sqs_denominator")
+    return d
+
+
+def make_prior(prior, sigma: float) -> _Prior:
+    return _Prior(float(sigma), float(prior.p), float(prior.q), float(prior.T), float(prior.sigma0),
+                  float(prior.m), float(prior.a), int(bool(prior.estimate_direct)))
+
+
+def reconstruct(geom: Geometry, prior, sigma: float, y, n_iter: int, x=None, g=None, cost=None,
+                work=None, stream=None):
+    """MAP reconstruction (Eq. (18)); returns (x, g, cost) as device tensors.
+
+    x, g: warm start (zeros if None), updated in place; cost: float64 of
+    n_iter + 1 entries (allocated if None)."""
+    import torch
+    dev = y.device
+    if x is None:
+        x = torch.zeros(geom.image_shape, dtype=torch.float32, device=dev)
+    if g is None:
+        g = torch.zeros(geom.trace_shape[:2], dtype=torch.float32, device=dev)
+    if cost is None:
+        cost = torch.empty(n_iter + 1, dtype=torch.float64, device=dev)
+    pr = make_prior(prior, sigma)
+    wp, wb = _work(geom, work, WORK_RECONSTRUCT)
+    _check(_lib.umbir_reconstruct(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, torch.float32),
+                                  int(n_iter), _ptr(x, "x", geom.image_shape, torch.float32),
+                                  _ptr(g, "g", geom.trace_shape[:2], torch.float32),
+                                  _ptr(cost, "cost", (n_iter + 1,), torch.float64), wp, wb,
+                                  _stream(stream)), "umbir_reconstruct")
+    return x, g, cost
+
+
+def library_path() -> str:
+    return _LIB_PATH

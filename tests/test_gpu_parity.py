@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Tolerance for float32 results: relative L2 <= 1e-5
+(element by element on the sizes the oracle runs in seconds; on sampled
+outputs at the full plain-FP32 workload)."""
+import numpy as np
+import pytest
+
+from synth import card_c1, card_c2, tiny_card, random_vector, phantom
+from synth.cards import Prior
+from oracle import geometry as og, operator as oo, pulse as op, solver as osv, data as odata
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+umbir = pytest.importorskip("paper_2202_09703_amd.umbir")
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def t32(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+
+
+TINY = [dict(n_layers=1), dict(n_layers=2), dict(n_layers=3, beta=3), dict(n_layers=4),
+        dict(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=16),
+        dict(n_layers=2, nx=1, nz=1, n_scans=1, n_rx=1),
+        dict(n_layers=3, oversample=1, beta=0),
+        dict(n_layers=3, n_samples=40)]  # record shorter than many echoes: truncation
+
+
+def _cards():
+    return [("tiny%d" % k, tiny_card(**kw)) for k, kw in enumerate(TINY)] + [("c1", card_c1())]
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_leg_table(dev, name, card):
+    geom = umbir.build_geometry(card)
+    dl = geom.table(umbir.TABLE_DELAY).astype(np.float64) / 2.0 ** 32
+    ap = geom.table(umbir.TABLE_APOD).astype(np.float64)
+    depth = og.voxel_depths(card.grid)[:, None]
+    X = np.arange(geom.n_off)[None, :] * card.grid.dx / 2
+    T, th, _ = og.leg(card.medium, depth + 0 * X, X + 0 * depth)
+    err = np.max(np.abs(dl - card.acq.fs * T))
+    print(f"{name}: max leg delay error {err:.2e} samples")
+    assert err < 1e-6
+    np.testing.assert_allclose(ap, np.cos(th) ** card.array.beta, rtol=1e-6, atol=1e-7)
+    tau = geom.table(umbir.TABLE_TAU)
+    np.testing.assert_allclose(tau, og.transmittance(card.medium, og.voxel_depths(card.grid)), rtol=1e-6)
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_bank_and_direct_basis(dev, name, card):
+    geom = umbir.build_geometry(card)
+    bank = geom.table(umbir.TABLE_BANK).astype(np.float64)
+    ref = op.template(card.acq)
+    np.testing.assert_allclose(bank[:len(ref)], ref, rtol=0, atol=1e-7)
+    assert np.all(bank[len(ref):] == 0)
+    d = geom.table(umbir.TABLE_DBASIS)
+    np.testing.assert_allclose(d, oo.direct_basis(card), rtol=0, atol=3e-7)
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_forward_parity(dev, name, card):
+    geom = umbir.build_geometry(card)
+    g = card.grid
+    for x in (phantom(card) if card.phantom.n_reflectors <= g.nx * g.nz // 8 else None,
+              random_vector((g.nz, g.nx), seed=11)):
+        if x is None:
+            continue
+        y = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+        ref = oo.forward(card, x)
+        e = rel(y, ref)
+        print(f"{name}: forward rel L2 {e:.2e}")
+        assert e <= TOL
+    # accumulate mode adds to what is there
+    x = random_vector((g.nz, g.nx), seed=12)
+    y0 = t32(random_vector(geom.trace_shape, seed=13), dev)
+    y1 = umbir.forward(geom, t32(x, dev), y0.clone(), accumulate=True).cpu().numpy()
+    assert rel(y1, y0.cpu().numpy() + oo.forward(card, x)) <= TOL
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_adjoint_parity_and_identity(dev, name, card):
+    geom = umbir.build_geometry(card)
+    g = card.grid
+    r = random_vector(geom.trace_shape, seed=21)
+    xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy()
+    ref = oo.adjoint(card, r)
+    e = rel(xa, ref)
+    print(f"{name}: adjoint rel L2 {e:.2e}")
+    assert e <= TOL
+    # the GPU pair is an exact transpose up to float rounding
+    x = random_vector((g.nz, g.nx), seed=22)
+    ax = umbir.forward(geom, t32(x, dev)).cpu().numpy().astype(np.float64)
+    lhs, rhs = float(np.sum(ax * r)), float(np.sum(x * xa))
+    scale = np.linalg.norm(ax) * np.linalg.norm(r)
+    assert abs(lhs - rhs) <= TOL * scale
+
+
+def test_adjoint_is_deterministic(dev):
+    card = card_c1()
+    geom = umbir.build_geometry(card)
+    r = t32(random_vector(geom.trace_shape, seed=31), dev)
+    a = umbir.adjoint(geom, r)
+    b = umbir.adjoint(geom, r)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name,card", _cards()[:3] + _cards()[-1:])
+def test_direct_parity(dev, name, card):
+    geom = umbir.build_geometry(card)
+    gvals = random_vector(geom.trace_shape[:2], seed=41)
+    y = umbir.direct(geom, t32(gvals, dev)).cpu().numpy()
+    assert rel(y, oo.apply_direct(card, gvals)) <= TOL
+
+
+@pytest.mark.parametrize("name,card", [_cards()[2], _cards()[-1]])
+def test_sqs_denominator_parity(dev, name, card):
+    geom = umbir.build_geometry(card)
+    sigma = 0.01
+    d = umbir.sqs_denominator(geom, sigma).cpu().numpy()
+    e = rel(d, osv.sqs_denominator(card, sigma))
+    print(f"{name}: sqs denominator rel L2 {e:.2e}")
+    assert e <= TOL
+
+
+def _recon_case():
+    card = card_c1()
+    x_true, y, sigma = odata.synthesize(card)
+    return card, y, sigma
+
+
+def test_reconstruct_parity_c1(dev):
+    """20 iterations on the 64x64 workload: per-iteration cost and final image
+    against the oracle's surrogate iteration."""
+    card, y, sigma = _recon_case()
+    geom = umbir.build_geometry(card)
+    pr = card.prior
+    n = card.n_iter
+    x, g, cost = umbir.reconstruct(geom, pr, sigma, t32(y, dev), n)
+    cost = cost.cpu().numpy()
+    xo, go, co, its = osv.sqs(card, y, sigma, pr, n, history=True)
+    ce = np.max(np.abs(cost - co) / np.abs(co))
+    xe = rel(x.cpu().numpy(), xo)
+    ge = rel(g.cpu().numpy(), go) if np.linalg.norm(go) > 0 else float(np.max(np.abs(g.cpu().numpy())))
+    print(f"c1 recon: max cost rel err {ce:.2e}, x rel L2 {xe:.2e}, g err {ge:.2e}")
+    assert ce <= 1e-5
+    assert xe <= 1e-4
+    # monotone within float32 rounding
+    assert np.all(np.diff(cost) <= 1e-6 * np.abs(cost[:-1]))
+    # one iteration, element by element
+    x1, g1, _ = umbir.reconstruct(geom, pr, sigma, t32(y, dev), 1)
+    assert rel(x1.cpu().numpy(), its[0][0]) <= TOL
+
+
+def test_reconstruct_resume(dev):
+    card, y, sigma = _recon_case()
+    geom = umbir.build_geometry(card)
+    yt = t32(y, dev)
+    x20, g20, c20 = umbir.reconstruct(geom, card.prior, sigma, yt, 20)
+    x10, g10, c10 = umbir.reconstruct(geom, card.prior, sigma, yt, 10)
+    x2, g2, c2 = umbir.reconstruct(geom, card.prior, sigma, yt, 10, x=x10, g=g10)
+    assert rel(x2.cpu().numpy(), x20.cpu().numpy()) <= 1e-5
+    assert np.max(np.abs(c2.cpu().numpy() - c20.cpu().numpy()[10:]) / c20.cpu().numpy()[10:]) <= 1e-6
+
+
+def test_reconstruct_with_direct_arrivals(dev):
+    """Data with injected direct arrivals: g is estimated and matches the oracle."""
+    card = tiny_card(n_layers=3, nx=12, nz=10, n_scans=2, n_rx=3, n_samples=200)
+    x_true, y, sigma = odata.synthesize(card)
+    g_true = np.array([[0.5, -0.3, 0.8], [0.2, 0.9, -0.4]])
+    y = y + oo.apply_direct(card, g_true)
+    geom = umbir.build_geometry(card)
+    x, g, cost = umbir.reconstruct(geom, card.prior, sigma, t32(y, dev), 8)
+    xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
+    assert rel(g.cpu().numpy(), go) <= 1e-5
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    assert np.max(np.abs(cost.cpu().numpy() - co) / co) <= 1e-5
+
+
+# ---- full-size plain FP32 workload (256x256, 32 x 16 traces, 2048 samples): sampled outputs
+
+
+@pytest.fixture(scope="module")
+def c2geom(dev):
+    card = card_c2()
+    return card, umbir.build_geometry(card)
+
+
+def test_c2_forward_sampled(dev, c2geom):
+    card, geom = c2geom
+    x = phantom(card)
+    y = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+    rng = np.random.default_rng(5)
+    traces = [(int(rng.integers(card.array.n_scans)), int(rng.integers(card.array.n_rx))) for _ in range(3)]
+    ref = oo.forward(card, x, traces=traces)
+    for i, j in traces:
+        e = rel(y[i, j], ref[i, j])
+        print(f"c2 forward trace ({i},{j}) rel L2 {e:.2e}")
+        assert e <= TOL
+
+
+def test_c2_adjoint_sampled(dev, c2geom):
+    card, geom = c2geom
+    r = random_vector(geom.trace_shape, seed=51)
+    xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy().reshape(-1)
+    vox = np.random.default_rng(6).choice(card.n_voxels, 24, replace=False)
+    ref = oo.adjoint_voxels(card, r, vox)
+    e = rel(xa[vox], ref)
+    print(f"c2 adjoint sampled rel L2 {e:.2e}")
+    assert e <= TOL
+    # property at full size: adjoint identity against the GPU forward
+    x = random_vector((card.grid.nz, card.grid.nx), seed=52)
+    ax = umbir.forward(geom, t32(x, dev)).cpu().numpy().astype(np.float64)
+    lhs, rhs = float(np.sum(ax * r)), float(np.sum(x.reshape(-1) * xa))
+    assert abs(lhs - rhs) <= TOL * np.linalg.norm(ax) * np.linalg.norm(r)
+
+
+def test_c2_leg_table(dev, c2geom):
+    card, geom = c2geom
+    dl = geom.table(umbir.TABLE_DELAY).astype(np.float64) / 2.0 ** 32
+    rows = np.arange(0, card.grid.nz, 7)
+    depth = og.voxel_depths(card.grid)[rows][:, None]
+    X = np.arange(geom.n_off)[None, :] * card.grid.dx / 2
+    T, _, _ = og.leg(card.medium, depth + 0 * X, X + 0 * depth)
+    err = np.max(np.abs(dl[rows] - card.acq.fs * T))
+    print(f"c2 max leg delay error {err:.2e} samples")
+    assert err < 1e-6
