@@ -1,0 +1,227 @@
+"""Benchmark of the MAP reconstruction hot path on one MI355X.
+
+One step = one whole reconstruction of the plain FP32 workload (256 x 256
+grid, 0.5 mm voxels, water/steel/cement, 32 scan positions x 16 receivers,
+2048 samples at 20 MHz, 50 surrogate iterations): build the geometry (leg
+table, template, direct-arrival columns), the data-term curvature (one |A|
+and one |A|^T), then per iteration one A x with the residual and g step, one
+A^T e, the prior-weighted image update and the cost.
+
+value = A+A^T voxel-receiver evals per second of whole-job time:
+P K N (n_iter + 1) / (seconds per step); the +1 is the curvature pass.
+Inputs are resident in HBM before the timed region; the data are synthetic
+(seeded phantom, A x_true plus seeded Gaussian noise at 15 dB).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published fp32 vector FLOP/s
+PEAK_HBM = 8.0e12             # MI355X published HBM3E bytes/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="skip parity sampling and the CPU baseline")
+    return ap.parse_args()
+
+
+def kernel_work(name, card, n_traces, n_vox):
+    """Algorithmic work of one launch: (amount, unit kind) for the roofline."""
+    acq = card.acq
+    lh = int(round(acq.t_win * acq.fs))
+    if name in ("conv", "corr"):
+        # dense polyphase convolution / correlation: M Q outputs x L_h taps per trace
+        return 2.0 * n_traces * acq.n_samples * acq.oversample * lh, "flop"
+    if name in ("splat", "gather"):
+        # per (trace, voxel): two one-way leg records (8 B delay + 4 B apodization each)
+        # and two fine-grid values (8 B); per launch also the image (4 B per voxel)
+        return float(n_traces) * n_vox * 32 + 4.0 * n_vox, "byte"
+    return None, None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "path is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2202_09703_amd import umbir
+    from synth import card_c2, phantom, noise
+
+    dev = torch.device("cuda:0")
+    card = card_c2()
+    P, K, M = card.array.n_scans, card.array.n_rx, card.acq.n_samples
+    N = card.n_voxels
+    n_iter = card.n_iter
+    triples = P * K * N
+
+    # ---- synthetic inputs, resident in HBM before timing
+    geom = umbir.build_geometry(card)
+    x_true = torch.tensor(phantom(card), dtype=torch.float32, device=dev)
+    clean = umbir.forward(geom, x_true)
+    sigma = float(torch.sqrt(torch.mean(clean.double() ** 2) / 10.0 ** (card.snr_db / 10.0)))
+    y = clean + sigma * torch.tensor(noise(card), dtype=torch.float32, device=dev)
+    work = geom.workspace(umbir.WORK_RECONSTRUCT)
+    x = torch.zeros(geom.image_shape, dtype=torch.float32, device=dev)
+    g = torch.zeros(geom.trace_shape[:2], dtype=torch.float32, device=dev)
+    cost = torch.empty(n_iter + 1, dtype=torch.float64, device=dev)
+    geom.free()
+    torch.cuda.synchronize()
+
+    def step():
+        gm = umbir.build_geometry(card)
+        x.zero_()
+        g.zero_()
+        umbir.reconstruct(gm, card.prior, sigma, y, n_iter, x=x, g=g, cost=cost, work=work)
+        return gm
+
+    for _ in range(args.warmup):
+        step().free()
+    torch.cuda.synchronize()
+
+    umbir.profile_enable(True)
+    umbir.profile_collect()
+    lat = []
+    keep = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        keep.append(step())
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    umbir.profile_enable(False)
+    prof = umbir.profile_collect()
+    for gm in keep:
+        gm.free()
+
+    sec_per_step = elapsed / args.steps
+    evals_per_step = triples * (n_iter + 1)
+    value = evals_per_step / sec_per_step
+    costs = cost.cpu().numpy()
+
+    # ---- per-operator rates (plain calls, HIP events on the current stream)
+    gm = umbir.build_geometry(card)
+    wf = gm.workspace(umbir.WORK_ADJOINT)
+    xr = torch.randn(geom.image_shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    yr = torch.empty(geom.trace_shape, dtype=torch.float32, device=dev)
+    xo = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
+    reps = 10
+    for _ in range(2):
+        umbir.forward(gm, xr, yr, work=wf)
+        umbir.adjoint(gm, yr, xo, work=wf)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        umbir.forward(gm, xr, yr, work=wf)
+    ev[1].record()
+    for _ in range(reps):
+        umbir.adjoint(gm, yr, xo, work=wf)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_fwd = ev[0].elapsed_time(ev[1]) / reps / 1e3
+    t_adj = ev[1].elapsed_time(ev[2]) / reps / 1e3
+
+    # ---- roofline of the dominant kernel (largest share of the timed region)
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (dlaunch, dms) = dom
+    avg_s = dms / dlaunch / 1e3
+    amount, kind = kernel_work(dname, card, P * K, N)
+    if kind == "flop":
+        achieved = amount / avg_s
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None}
+    elif kind == "byte":
+        achieved = amount / avg_s
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": None}
+    else:
+        roof = None
+    if roof is not None:
+        roof.update({"kernel": dname, "avg_launch_us": avg_s * 1e6, "launches": dlaunch,
+                     "work_per_launch": amount, "work_unit": kind})
+
+    out = {
+        "metric": "A+Aᵀ voxel-receiver evals/sec",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain FP32 MBIR 256x256, 3 layers, 32 scans x 16 rx, 2048 samples "
+                               "@ 20 MHz, 50 iterations", "grid": [256, 256], "scans": P, "receivers": K,
+                   "samples": M, "iterations": n_iter, "triples_per_sweep": triples},
+        "recon_per_s": 1.0 / sec_per_step,
+        "latency_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+        "latency_ms_p99": float(np.percentile(np.array(lat) * 1e3, 99)),
+        "A_evals_per_s": triples / t_fwd,
+        "AT_evals_per_s": triples / t_adj,
+        "A_ms": t_fwd * 1e3,
+        "AT_ms": t_adj * 1e3,
+        "cost_first_last": [float(costs[0]), float(costs[-1])],
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items())},
+        "roofline": roof,
+    }
+
+    if not args.quick:
+        from oracle import operator as oo
+        xs = x_true.cpu().numpy().astype(np.float64)
+        yf = umbir.forward(gm, x_true).cpu().numpy()
+        i, j = 13, 5
+        ref = oo.forward(card, xs, traces=[(i, j)])[i, j]
+        fe = float(np.linalg.norm(yf[i, j] - ref) / np.linalg.norm(ref))
+        rr = np.asarray(noise(card), np.float64)
+        xa = umbir.adjoint(gm, torch.tensor(rr, dtype=torch.float32, device=dev)).cpu().numpy().reshape(-1)
+        vox = np.random.default_rng(9).choice(N, 8, replace=False)
+        refa = oo.adjoint_voxels(card, rr, vox)
+        ae = float(np.linalg.norm(xa[vox] - refa) / np.linalg.norm(refa))
+        out["parity_vs_oracle"] = {"forward_rel_l2_trace": fe, "adjoint_rel_l2_8_voxels": ae,
+                                   "tolerance": 1e-5}
+
+    if not args.quick and not args.no_cpu:
+        # oracle (FP64 numpy) on a bounded sample: one scan position and its
+        # first KS receivers, A and A^T over all voxels; evals = KS N
+        import dataclasses
+        from oracle import operator as oo
+        KS = 6
+        sub = dataclasses.replace(card, array=dataclasses.replace(
+            card.array, tx_x=(card.array.tx_x[P // 2],), rx_offset=card.array.rx_offset[:KS]))
+        xs = phantom(card).astype(np.float64)
+        t0 = time.perf_counter()
+        ys = oo.forward(sub, xs)
+        oo.adjoint(sub, ys)
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": KS * N / tc, "unit": "evals/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{KS} traces (one scan position) of the same workload: one A and "
+                                         f"one A^T over all {N} voxels in FP64 numpy, {tc:.1f} s"}
+    gm.free()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

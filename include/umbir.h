@@ -207,6 +207,21 @@ enum { UMBIR_TABLE_DELAY = 0, UMBIR_TABLE_APOD = 1, UMBIR_TABLE_TAU = 2,
        UMBIR_TABLE_BANK = 3, UMBIR_TABLE_DBASIS = 4, UMBIR_TABLE_OFFSET = 5 };
 int umbir_copy_table(const umbir_geometry* geom, int which, void* host_dst, size_t bytes);
 
+/* Opt-in per-kernel timing for callers that measure the library (benchmarks,
+ * profilers).  While enabled, every kernel launch is bracketed by two HIP
+ * events on its stream (this adds event records between launches).
+ * umbir_profile_collect waits for the recorded events, writes one entry per
+ * kernel name (launch count and summed duration since the last collect) into
+ * out[0 .. max_entries), sets *n_out to the number of names, and resets the
+ * totals.  Process-wide; thread-safe.  Errors: EINVAL, EDEVICE. */
+typedef struct {
+    char name[48];
+    long long launches;
+    double total_ms;
+} umbir_kernel_time;
+void umbir_profile_enable(int on);
+int umbir_profile_collect(umbir_kernel_time* out, int max_entries, int* n_out);
+
 const char* umbir_strerror(int status);
 const char* umbir_last_error(void);
 

@@ -419,12 +419,12 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   }
   {
     const int n = int(legs);
-    hipLaunchKernelGGL(k_legs, dim3((n + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off,
+    UMBIR_LAUNCH("legs", k_legs, dim3((n + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off,
                        G->z0, G->dz, 0.5 * G->dx, G->fs, G->beta, G->delay, G->apod);
     const double dt = 1.0 / (double(G->Q) * G->fs);
-    hipLaunchKernelGGL(k_bank, dim3((QLh + 2 + 255) / 256), dim3(256), 0, s, G->Q, G->Lh, dt, G->f_c,
+    UMBIR_LAUNCH("bank", k_bank, dim3((QLh + 2 + 255) / 256), dim3(256), 0, s, G->Q, G->Lh, dt, G->f_c,
                        1.0 / (2.0 * G->sigma_t * G->sigma_t), 0.5 * G->t_win, G->bank, G->h, G->habs);
-    hipLaunchKernelGGL(k_dbasis, dim3(unsigned(PK)), dim3(256), 0, s, G->bank, td_dev, G->M, G->Q,
+    UMBIR_LAUNCH("dbasis", k_dbasis, dim3(unsigned(PK)), dim3(256), 0, s, G->bank, td_dev, G->M, G->Q,
                        G->Lh, G->dbasis, G->dnorm);
   }
   st = check_hip(hipGetLastError(), "geometry kernels");

@@ -29,6 +29,19 @@ int fail(int status, const std::string& msg);
 // Returns UMBIR_EDEVICE (with the HIP error text) if `e` is not hipSuccess.
 int check_hip(hipError_t e, const char* what);
 
+// Optional per-kernel timing (umbir_profile_enable): when on, every launch is
+// bracketed by two events on its stream; umbir_profile_collect sums them.
+bool prof_on();
+hipEvent_t prof_start(hipStream_t s);
+void prof_stop(const char* name, hipStream_t s, hipEvent_t start);
+
+#define UMBIR_LAUNCH(name, kernel, grid, block, shmem, stream, ...)          \
+  do {                                                                       \
+    hipEvent_t umbir_e0_ = umbir::prof_on() ? umbir::prof_start(stream) : nullptr; \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);     \
+    if (umbir_e0_) umbir::prof_stop(name, stream, umbir_e0_);                \
+  } while (0)
+
 // Workspace carved out of one device buffer; offsets are 256-byte aligned.
 struct Carve {
   char* base;

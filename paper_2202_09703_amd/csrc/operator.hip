@@ -269,7 +269,7 @@ void launch_conv_q(const umbir_geometry& G, const float* fine, const float* hq, 
   constexpr int per_block = 4 * (64 / Q) * kR;
   const int LhP = lh_pad(G.Lh);
   dim3 grid((G.M + per_block - 1) / per_block, G.traces());
-  hipLaunchKernelGGL(k_conv<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, fine, hq, G.M,
+  UMBIR_LAUNCH("conv", k_conv<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, fine, hq, G.M,
                      G.Lh, LhP, base, sign, g, G.dbasis, out);
 }
 
@@ -279,7 +279,7 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
   constexpr int per_block = 4 * (64 / Q) * kR;
   const int LhP = lh_pad(G.Lh);
   dim3 grid((G.M + per_block - 1) / per_block, G.traces());
-  hipLaunchKernelGGL(k_corr<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, r, hq, G.M,
+  UMBIR_LAUNCH("corr", k_corr<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, r, hq, G.M,
                      G.Lh, LhP, fine);
 }
 
@@ -314,12 +314,12 @@ size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
 int launch_fill(float* p, size_t n, float v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3(grid_1d(n / 4 + 1)), dim3(256), 0, s, p, n, v);
+  UMBIR_LAUNCH("fill", k_fill, dim3(grid_1d(n / 4 + 1)), dim3(256), 0, s, p, n, v);
   return check_hip(hipGetLastError(), "k_fill");
 }
 
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy, dim3(grid_1d(n)), dim3(256), 0, s, dst, src, n);
+  UMBIR_LAUNCH("copy", k_copy, dim3(grid_1d(n)), dim3(256), 0, s, dst, src, n);
   return check_hip(hipGetLastError(), "k_copy");
 }
 
@@ -339,10 +339,10 @@ int run_forward(const umbir_geometry& G, const float* x, float* out, const float
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
   dim3 grid((G.voxels() + 255) / 256, G.trace_groups);
   if (abs_op)
-    hipLaunchKernelGGL(k_splat<true>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay, G.apod,
+    UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay, G.apod,
                        G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, fine);
   else
-    hipLaunchKernelGGL(k_splat<false>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay,
+    UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay,
                        G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, fine);
   if ((st = check_hip(hipGetLastError(), "k_splat"))) return st;
   launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
@@ -358,13 +358,13 @@ int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
   dim3 grid((G.voxels() + 255) / 256, G.trace_groups);
   if (abs_op)
-    hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
+    UMBIR_LAUNCH("gather", k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
                        G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, partial);
   else
-    hipLaunchKernelGGL(k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
+    UMBIR_LAUNCH("gather", k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
                        G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, partial);
   if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
-  hipLaunchKernelGGL(k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
+  UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
                      G.trace_groups, G.voxels(), scale, out);
   return check_hip(hipGetLastError(), "k_reduce_groups");
 }
@@ -419,7 +419,7 @@ int umbir_direct(const umbir_geometry* G, const float* g, float* y, int accumula
   if (!G || !g || !y) return fail(UMBIR_EINVAL, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t total = size_t(G->traces()) * G->M;
-  hipLaunchKernelGGL(k_direct, dim3(grid_1d(total)), dim3(256), 0, s, g, G->dbasis, G->M, total,
+  UMBIR_LAUNCH("direct", k_direct, dim3(grid_1d(total)), dim3(256), 0, s, g, G->dbasis, G->M, total,
                      accumulate, y);
   return check_hip(hipGetLastError(), "k_direct");
 }

@@ -225,20 +225,20 @@ extern "C" int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr,
   for (int it = 0; it <= n_iter; ++it) {
     const bool last = it == n_iter;
     if ((st = run_forward(*G, xa, e, y, -1.0f, g_io, false, fine, s))) return st;
-    hipLaunchKernelGGL(k_gstep, dim3(unsigned(PK)), dim3(256), 0, s, e, G->dbasis, G->dnorm, g_io,
+    UMBIR_LAUNCH("gstep", k_gstep, dim3(unsigned(PK)), dim3(256), 0, s, e, G->dbasis, G->dnorm, g_io,
                        G->M, last ? 0 : est, ess);
     if ((st = check_hip(hipGetLastError(), "k_gstep"))) return st;
     if (last) {
-      hipLaunchKernelGGL(k_prior<false>, dim3(nblk), dim3(256), 0, s, xa, nullptr, nullptr, G->nx,
+      UMBIR_LAUNCH("prior", k_prior<false>, dim3(nblk), dim3(256), 0, s, xa, nullptr, nullptr, G->nx,
                          G->nz, pc, nullptr, pcost);
     } else {
       if ((st = run_adjoint(*G, e, u, 1.0f, false, fine, partial, s))) return st;
-      hipLaunchKernelGGL(k_prior<true>, dim3(nblk), dim3(256), 0, s, xa, u, den, G->nx, G->nz, pc, xb,
+      UMBIR_LAUNCH("prior", k_prior<true>, dim3(nblk), dim3(256), 0, s, xa, u, den, G->nx, G->nz, pc, xb,
                          pcost);
     }
     if ((st = check_hip(hipGetLastError(), "k_prior"))) return st;
     if (cost) {
-      hipLaunchKernelGGL(k_cost, dim3(1), dim3(256), 0, s, ess, int(PK), pcost, nblk, inv_2s2,
+      UMBIR_LAUNCH("cost", k_cost, dim3(1), dim3(256), 0, s, ess, int(PK), pcost, nblk, inv_2s2,
                          cost + it);
       if ((st = check_hip(hipGetLastError(), "k_cost"))) return st;
     }

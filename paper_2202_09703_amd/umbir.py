@@ -73,6 +73,10 @@ class _Dims(C.Structure):
                 ("oversample", C.c_int), ("n_layers", C.c_int)]
 
 
+class _KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_longlong), ("total_ms", C.c_double)]
+
+
 _vp, _sz, _i = C.c_void_p, C.c_size_t, C.c_int
 _SIGS = {
     "umbir_build_geometry": (_i, [C.POINTER(_Problem), _vp, C.POINTER(_vp)]),
@@ -87,6 +91,8 @@ _SIGS = {
     "umbir_reconstruct": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "umbir_get_dims": (_i, [_vp, C.POINTER(_Dims)]),
     "umbir_copy_table": (_i, [_vp, _i, _vp, _sz]),
+    "umbir_profile_enable": (None, [_i]),
+    "umbir_profile_collect": (_i, [C.POINTER(_KernelTime), _i, C.POINTER(_i)]),
     "umbir_strerror": (C.c_char_p, [_i]),
     "umbir_last_error": (C.c_char_p, []),
 }
@@ -310,6 +316,19 @@ def reconstruct(geom: Geometry, prior, sigma: float, y, n_iter: int, x=None, g=N
                                   _ptr(cost, "cost", (n_iter + 1,), torch.float64), wp, wb,
                                   _stream(stream)), "umbir_reconstruct")
     return x, g, cost
+
+
+def profile_enable(on: bool = True):
+    """Turn per-kernel event timing on or off (process-wide)."""
+    _lib.umbir_profile_enable(int(bool(on)))
+
+
+def profile_collect() -> dict:
+    """{kernel name: (launches, total ms)} since the last collect; resets the totals."""
+    buf = (_KernelTime * 64)()
+    n = C.c_int()
+    _check(_lib.umbir_profile_collect(buf, 64, C.byref(n)), "umbir_profile_collect")
+    return {buf[k].name.decode(): (int(buf[k].launches), float(buf[k].total_ms)) for k in range(min(n.value, 64))}
 
 
 def library_path() -> str:
