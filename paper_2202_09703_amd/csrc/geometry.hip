@@ -198,6 +198,9 @@ int validate(const umbir_problem* pb, Derived* dv) {
   // the dense kernels stage the taps, padded to a multiple of 16 rows, in 64 KiB of LDS
   if ((lhi + 15) / 16 * 16 * q.oversample > 16384)
     return fail(UMBIR_ENOTSUP, "window (rounded up to 16) * oversample must be <= 16384");
+  // the splat keeps one row pointer per (column, layer) in LDS beside a 32 KiB tile
+  if (long(g.nx) * md.n_layers > 8192)
+    return fail(UMBIR_ENOTSUP, "nx * n_layers must be <= 8192");
   if (double(q.n_samples) * q.oversample > double(1 << 28))
     return fail(UMBIR_ENOTSUP, "n_samples * oversample too large");
   dv->Lh = int(lhi);
@@ -361,6 +364,32 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   G->t_win = pb->acq.t_win;
   G->n_off = dv.n_off;
   G->trace_groups = choose_trace_groups(G->voxels(), G->traces());
+  {
+    // layer segments of the rows: a row belongs to the deepest layer whose top
+    // lies above its centre (the legs' crossing extents use the same rule)
+    int prev = -1;
+    for (int r = 0; r < G->nz; ++r) {
+      const double z = G->z0 + (r + 0.5) * G->dz;
+      int l = 0;
+      while (l + 1 < G->layers.n && z > G->layers.top[l + 1]) ++l;
+      if (l != prev) {
+        G->seg_lo[G->n_seg] = r;
+        ++G->n_seg;
+        prev = l;
+      }
+      G->seg_hi[G->n_seg - 1] = r + 1;
+    }
+    // fine-grid chunks and LDS tiles of the splat sweep: aim for >= 2048 workgroups
+    const long MQ = long(G->M) * G->Q;
+    const long min_chunk = 1024;
+    long chunks = (2048 + G->traces() - 1) / G->traces();
+    const long max_chunks = (MQ + min_chunk - 1) / min_chunk;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    G->chunks = int(chunks);
+    G->chunk_bins = (MQ + chunks - 1) / chunks;
+    G->tile_bins = int(std::min<long>(8192, G->chunk_bins));
+  }
 
   const size_t legs = size_t(G->nz) * G->n_off;
   const size_t PK = size_t(G->P) * G->K;

@@ -80,6 +80,15 @@ struct umbir_geometry {
   // derived
   int n_off = 0;        // lattice positions per leg-table row
   int trace_groups = 1; // traces are split into this many groups in voxel-parallel kernels
+  // rows of each layer: [seg_lo[s], seg_hi[s]) for the n_seg layers the grid reaches;
+  // within one segment a voxel's delay grows strictly with its row
+  int n_seg = 0;
+  int seg_lo[umbir::kMaxLayers] = {}, seg_hi[umbir::kMaxLayers] = {};
+  // fine-grid sweep of the splat: each trace is cut into `chunks` ranges of
+  // chunk_bins fine positions, swept in LDS tiles of tile_bins
+  int chunks = 1;
+  long chunk_bins = 0;
+  int tile_bins = 0;
   // resident device tables
   int64_t* delay = nullptr;  // [nz][n_off] one-way delay, Q32.32 samples
   float* apod = nullptr;     // [nz][n_off] cos^beta(angle sum)

@@ -61,36 +61,95 @@ __device__ __forceinline__ Pair pair_terms(const int64_t* __restrict__ drow,
   return p;
 }
 
-// S: scatter W x into the fine-grid signal.  Thread = voxel, loop over the
-// traces of group blockIdx.y.  x == NULL means x = 1.
+// Row ranges of the layers the grid reaches, passed by value.
+struct Segments {
+  int n;
+  int lo[kMaxLayers];
+  int hi[kMaxLayers];
+};
+
+__device__ __forceinline__ long fine_pos(const int64_t* __restrict__ delay, int n_off, int row, int otx,
+                                         int orx, int Q) {
+  const int64_t* drow = delay + size_t(row) * n_off;
+  return long((uint64_t(drow[otx] + drow[orx]) * uint64_t(Q)) >> 32);
+}
+
+// S: the fine-grid signal of one trace, one chunk of fine positions per
+// workgroup, built in LDS tiles without global atomics.  Within a layer a
+// voxel's delay grows strictly with depth, so for each (column, layer) the
+// voxels reach the fine grid in row order: one pointer per (column, layer)
+// walks forward through the rows as the tiles advance, and every voxel is
+// visited once.  A voxel at position J adds W x (1 - phi) to J and W x phi to
+// J + 1; the tile keeps one extra slot for J + 1 = the next tile's first
+// position.  x == NULL means x = 1.  Tiles are written out whole (coalesced),
+// so the fine buffer needs no clearing.
 template <bool ABSW>
 __global__ __launch_bounds__(256) void k_splat(
-    const float* __restrict__ x, int nx, int nz, int n_off, const int64_t* __restrict__ delay,
+    const float* __restrict__ x, int nx, int n_off, const int64_t* __restrict__ delay,
     const float* __restrict__ apod, const float* __restrict__ tau, const int* __restrict__ base,
-    int P, int K, int Q, long MQ, int tpg, float* __restrict__ fine) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nx * nz) return;
-  float xv = x ? x[v] : 1.0f;
-  if (xv == 0.0f) return;
-  const int row = v / nx, col = v - row * nx;
-  const int64_t* drow = delay + size_t(row) * n_off;
-  const float* arow = apod + size_t(row) * n_off;
-  float wr = tau[row] * xv;
-  if (ABSW) wr = fabsf(wr);
-  const int PK = P * K;
-  const int t0 = blockIdx.y * tpg;
-  const int t1 = min(t0 + tpg, PK);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t / K;
-    const int otx = abs(base[i] + 2 * col);
-    const int orx = abs(base[P + t] + 2 * col);
-    const Pair p = pair_terms(drow, arow, otx, orx, Q);
-    float w = p.w;
-    if (ABSW) w = fabsf(w);
-    w *= wr;
-    float* s = fine + size_t(t) * MQ;
-    if (p.J < MQ) unsafeAtomicAdd(s + p.J, w * (1.0f - p.phi));
-    if (p.J + 1 < MQ) unsafeAtomicAdd(s + p.J + 1, w * p.phi);
+    int P, int K, int Q, long MQ, Segments seg, long chunk_bins, int tile_bins,
+    float* __restrict__ fine) {
+  extern __shared__ float sm[];
+  float* tile = sm;                                           // [tile_bins + 1]
+  int* ptr = reinterpret_cast<int*>(sm + ((tile_bins + 1 + 3) & ~3));  // [seg.n][nx]
+  const int ij = blockIdx.y;
+  const long J_begin = long(blockIdx.x) * chunk_bins;
+  const long J_end = min(J_begin + chunk_bins, MQ);
+  if (J_begin >= J_end) return;  // uniform over the block
+  const int btx = base[ij / K];
+  const int brx = base[P + ij];
+  float* out = fine + size_t(ij) * MQ;
+
+  // first row of each (column, layer) whose position is >= J_begin - 1
+  for (int c = threadIdx.x; c < nx; c += blockDim.x) {
+    const int otx = abs(btx + 2 * c), orx = abs(brx + 2 * c);
+    for (int sg = 0; sg < seg.n; ++sg) {
+      int lo = seg.lo[sg], hi = seg.hi[sg];
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (fine_pos(delay, n_off, mid, otx, orx, Q) < J_begin - 1) lo = mid + 1; else hi = mid;
+      }
+      ptr[sg * nx + c] = lo;
+    }
+  }
+  for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0.0f;
+  __syncthreads();
+
+  for (long J0 = J_begin; J0 < J_end; J0 += tile_bins) {
+    const long J1 = min(J0 + long(tile_bins), J_end);
+    for (int c = threadIdx.x; c < nx; c += blockDim.x) {
+      const int otx = abs(btx + 2 * c), orx = abs(brx + 2 * c);
+      for (int sg = 0; sg < seg.n; ++sg) {
+        int r = ptr[sg * nx + c];
+        const int hi = seg.hi[sg];
+        for (; r < hi; ++r) {
+          const int64_t* drow = delay + size_t(r) * n_off;
+          const uint64_t DQ = uint64_t(drow[otx] + drow[orx]) * uint64_t(Q);
+          const long J = long(DQ >> 32);
+          if (J >= J1) break;
+          if (J + 1 < J0) continue;  // cannot happen while delays grow with depth in a layer
+          float xv = x ? x[r * nx + c] : 1.0f;
+          if (xv == 0.0f) continue;
+          const float* arow = apod + size_t(r) * n_off;
+          float w = tau[r] * xv * (arow[otx] * arow[orx]);
+          if (ABSW) w = fabsf(w);
+          const float phi = float(uint32_t(DQ)) * 2.3283064365386963e-10f;  // 2^-32
+          if (J >= J0) atomicAdd(&tile[J - J0], w * (1.0f - phi));
+          atomicAdd(&tile[J + 1 - J0], w * phi);  // J + 1 - J0 in [0, tile_bins]
+        }
+        ptr[sg * nx + c] = r;
+      }
+    }
+    __syncthreads();
+    const int n = int(J1 - J0);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) out[J0 + k] = tile[k];
+    __syncthreads();
+    const float carry = tile[n];
+    __syncthreads();
+    for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0.0f;
+    __syncthreads();
+    if (threadIdx.x == 0) tile[0] = carry;
+    __syncthreads();
   }
 }
 
@@ -334,17 +393,22 @@ size_t adjoint_work_bytes(const umbir_geometry& G) {
 int run_forward(const umbir_geometry& G, const float* x, float* out, const float* base, float sign,
                 const float* g, bool abs_op, float* fine, hipStream_t s) {
   const long MQ = long(G.fine_per_trace());
-  int st = launch_fill(fine, size_t(G.traces()) * MQ, 0.0f, s);
-  if (st) return st;
-  const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
-  dim3 grid((G.voxels() + 255) / 256, G.trace_groups);
+  Segments seg;
+  seg.n = G.n_seg;
+  for (int k = 0; k < kMaxLayers; ++k) {
+    seg.lo[k] = G.seg_lo[k];
+    seg.hi[k] = G.seg_hi[k];
+  }
+  const size_t lds = size_t((G.tile_bins + 1 + 3) & ~3) * sizeof(float) + size_t(G.n_seg) * G.nx * sizeof(int);
+  dim3 grid(G.chunks, G.traces());
   if (abs_op)
-    UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay, G.apod,
-                       G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, fine);
+    UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.delay, G.apod,
+                 G.tau, G.base, G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
   else
-    UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), 0, s, x, G.nx, G.nz, G.n_off, G.delay,
-                       G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, fine);
-  if ((st = check_hip(hipGetLastError(), "k_splat"))) return st;
+    UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.delay, G.apod,
+                 G.tau, G.base, G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
+  int st = check_hip(hipGetLastError(), "k_splat");
+  if (st) return st;
   launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
   return check_hip(hipGetLastError(), "k_conv");
 }
