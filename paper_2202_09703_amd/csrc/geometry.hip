@@ -30,8 +30,7 @@ thread_local std::string g_last_error;
 constexpr int kBisectSteps = 60;
 
 __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double half_dx,
-                       double fs, int beta, int64_t* __restrict__ delay,
-                       float* __restrict__ apod) {
+                       double fs, int beta, Leg* __restrict__ legs) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nz * n_off) return;
   const int row = idx / n_off;
@@ -83,8 +82,11 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
     if (b & 1) pw *= base;
     base *= base;
   }
-  delay[idx] = __double2ll_rn(fs * T * kTwo32);
-  apod[idx] = static_cast<float>(pw);
+  Leg rec;
+  rec.delay = __double2ll_rn(fs * T * kTwo32);
+  rec.apod = static_cast<float>(pw);
+  rec.pad = 0.0f;
+  legs[idx] = rec;
 }
 
 // Windowed pulse of Eq. (10) at fine-grid index n (time n / (Q fs)): the
@@ -227,9 +229,13 @@ int validate(const umbir_problem* pb, Derived* dv) {
   return UMBIR_OK;
 }
 
+// Trace groups of the voxel-parallel gather: enough workgroups to fill the
+// chip, and a multiple of the 8 XCDs when there are enough traces, because
+// group g runs on XCD g mod 8 (it is the fastest-varying block index).
 int choose_trace_groups(int n_vox, int n_traces) {
   const int vox_blocks = (n_vox + 255) / 256;
   int g = (2048 + vox_blocks - 1) / vox_blocks;
+  if (n_traces >= 8) g = (g + 7) / 8 * 8;
   if (g > n_traces) g = n_traces;
   if (g < 1) g = 1;
   return g;
@@ -237,7 +243,7 @@ int choose_trace_groups(int n_vox, int n_traces) {
 
 size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh) {
   const size_t legs = size_t(nz) * n_off;
-  return legs * (sizeof(int64_t) + sizeof(float)) + size_t(nz) * sizeof(float) +
+  return legs * sizeof(Leg) + size_t(nz) * sizeof(float) +
          size_t(P) * (1 + K) * sizeof(int) + size_t(Q * Lh + 2) * sizeof(float) +
          2 * size_t(Q) * Lh * sizeof(float) + size_t(P) * K * M * sizeof(float) +
          size_t(P) * K * sizeof(float);
@@ -313,7 +319,7 @@ void umbir_geometry_free(umbir_geometry* G) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (G->device >= 0) (void)hipSetDevice(G->device);
-  void* ptrs[] = {G->delay, G->apod, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm};
+  void* ptrs[] = {G->legs, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (cur >= 0) (void)hipSetDevice(cur);
@@ -399,8 +405,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     return check_hip(hipMalloc(p, bytes ? bytes : 4), "hipMalloc(geometry)");
   };
   double* td_dev = nullptr;
-  if ((st = alloc((void**)&G->delay, legs * sizeof(int64_t))) ||
-      (st = alloc((void**)&G->apod, legs * sizeof(float))) ||
+  if ((st = alloc((void**)&G->legs, legs * sizeof(Leg))) ||
       (st = alloc((void**)&G->tau, G->nz * sizeof(float))) ||
       (st = alloc((void**)&G->base, dv.base.size() * sizeof(int))) ||
       (st = alloc((void**)&G->bank, (QLh + 2) * sizeof(float))) ||
@@ -449,7 +454,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   {
     const int n = int(legs);
     UMBIR_LAUNCH("legs", k_legs, dim3((n + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off,
-                       G->z0, G->dz, 0.5 * G->dx, G->fs, G->beta, G->delay, G->apod);
+                       G->z0, G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs);
     const double dt = 1.0 / (double(G->Q) * G->fs);
     UMBIR_LAUNCH("bank", k_bank, dim3((QLh + 2 + 255) / 256), dim3(256), 0, s, G->Q, G->Lh, dt, G->f_c,
                        1.0 / (2.0 * G->sigma_t * G->sigma_t), 0.5 * G->t_win, G->bank, G->h, G->habs);
@@ -490,8 +495,8 @@ int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes
   size_t need = 0;
   const size_t legs = size_t(G->nz) * G->n_off;
   switch (which) {
-    case UMBIR_TABLE_DELAY: src = G->delay; need = legs * sizeof(int64_t); break;
-    case UMBIR_TABLE_APOD: src = G->apod; need = legs * sizeof(float); break;
+    case UMBIR_TABLE_DELAY: need = legs * sizeof(int64_t); break;
+    case UMBIR_TABLE_APOD: need = legs * sizeof(float); break;
     case UMBIR_TABLE_TAU: src = G->tau; need = G->nz * sizeof(float); break;
     case UMBIR_TABLE_BANK: src = G->bank; need = (G->Q * G->Lh + 2) * sizeof(float); break;
     case UMBIR_TABLE_DBASIS: src = G->dbasis; need = size_t(G->traces()) * G->M * sizeof(float); break;
@@ -499,7 +504,17 @@ int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes
     default: return fail(UMBIR_EINVAL, "unknown table");
   }
   if (bytes != need) return fail(UMBIR_EINVAL, "bytes does not match the table size");
-  return check_hip(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost), "hipMemcpy(table)");
+  if (src) return check_hip(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost), "hipMemcpy(table)");
+  // leg tables: one field of the packed records
+  std::vector<Leg> rec(legs);
+  int st = check_hip(hipMemcpy(rec.data(), G->legs, legs * sizeof(Leg), hipMemcpyDeviceToHost),
+                     "hipMemcpy(legs)");
+  if (st) return st;
+  for (size_t k = 0; k < legs; ++k) {
+    if (which == UMBIR_TABLE_DELAY) static_cast<int64_t*>(dst)[k] = rec[k].delay;
+    else static_cast<float*>(dst)[k] = rec[k].apod;
+  }
+  return UMBIR_OK;
 }
 
 }  // extern "C"

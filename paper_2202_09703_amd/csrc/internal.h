@@ -14,6 +14,15 @@ namespace umbir {
 constexpr int kMaxLayers = UMBIR_MAX_LAYERS;
 constexpr double kTwo32 = 4294967296.0;
 
+// One-way leg record: delay in Q32.32 fixed-point samples and cos^beta of the
+// leg's angle sum, stored row-major [nz][n_off]: neighbouring columns of one
+// row read neighbouring records.
+struct __align__(16) Leg {
+  int64_t delay;
+  float apod;
+  float pad;
+};
+
 // Planar layer stack passed to kernels by value.  top/bottom are depths of
 // each layer's faces; the last bottom is +inf.
 struct Layers {
@@ -90,8 +99,7 @@ struct umbir_geometry {
   long chunk_bins = 0;
   int tile_bins = 0;
   // resident device tables
-  int64_t* delay = nullptr;  // [nz][n_off] one-way delay, Q32.32 samples
-  float* apod = nullptr;     // [nz][n_off] cos^beta(angle sum)
+  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta)
   float* tau = nullptr;      // [nz] transmittance product of the row's layer
   int* base = nullptr;       // [P + P*K] lattice base: offset index = |base + 2 col|
   float* bank = nullptr;     // [Q*Lh + 2] tabulated windowed pulse, zero padded

@@ -43,24 +43,6 @@ __global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, size_
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += stride) d[k] = s[k];
 }
 
-// Per-(trace, voxel) terms shared by the splat and the gather: the fine-grid
-// position J, the fraction phi and W / tau (tau is applied per voxel).
-struct Pair {
-  long J;
-  float phi;
-  float w;
-};
-
-__device__ __forceinline__ Pair pair_terms(const int64_t* __restrict__ drow,
-                                           const float* __restrict__ arow, int otx, int orx, int Q) {
-  const uint64_t DQ = uint64_t(drow[otx] + drow[orx]) * uint64_t(Q);
-  Pair p;
-  p.J = long(DQ >> 32);
-  p.phi = float(uint32_t(DQ)) * 2.3283064365386963e-10f;  // 2^-32
-  p.w = arow[otx] * arow[orx];
-  return p;
-}
-
 // Row ranges of the layers the grid reaches, passed by value.
 struct Segments {
   int n;
@@ -68,29 +50,30 @@ struct Segments {
   int hi[kMaxLayers];
 };
 
-__device__ __forceinline__ long fine_pos(const int64_t* __restrict__ delay, int n_off, int row, int otx,
-                                         int orx, int Q) {
-  const int64_t* drow = delay + size_t(row) * n_off;
-  return long((uint64_t(drow[otx] + drow[orx]) * uint64_t(Q)) >> 32);
+// Fine-grid position J = floor(D Q) of a (trace, voxel) pair from its two legs.
+__device__ __forceinline__ uint64_t fine_q(int64_t dtx, int64_t drx, int Q) {
+  return uint64_t(dtx + drx) * uint64_t(Q);
 }
+
+constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // S: the fine-grid signal of one trace, one chunk of fine positions per
 // workgroup, built in LDS tiles without global atomics.  Within a layer a
 // voxel's delay grows strictly with depth, so for each (column, layer) the
 // voxels reach the fine grid in row order: one pointer per (column, layer)
 // walks forward through the rows as the tiles advance, and every voxel is
-// visited once.  A voxel at position J adds W x (1 - phi) to J and W x phi to
-// J + 1; the tile keeps one extra slot for J + 1 = the next tile's first
-// position.  x == NULL means x = 1.  Tiles are written out whole (coalesced),
-// so the fine buffer needs no clearing.
+// visited once.  Thread = column: neighbouring threads usually sit on the same
+// row, so their leg records and image entries are neighbours.  A voxel at position J adds
+// W x (1 - phi) to J and W x phi to J + 1; the tile keeps one extra slot for
+// J + 1 = the next tile's first position.  x == NULL means x = 1.  Tiles are
+// written out whole (coalesced), so the fine buffer needs no clearing.
 template <bool ABSW>
 __global__ __launch_bounds__(256) void k_splat(
-    const float* __restrict__ x, int nx, int n_off, const int64_t* __restrict__ delay,
-    const float* __restrict__ apod, const float* __restrict__ tau, const int* __restrict__ base,
-    int P, int K, int Q, long MQ, Segments seg, long chunk_bins, int tile_bins,
-    float* __restrict__ fine) {
+    const float* __restrict__ x, int nx, int n_off, const Leg* __restrict__ legs,
+    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int Q, long MQ,
+    Segments seg, long chunk_bins, int tile_bins, float* __restrict__ fine) {
   extern __shared__ float sm[];
-  float* tile = sm;                                           // [tile_bins + 1]
+  float* tile = sm;                                                    // [tile_bins + 1]
   int* ptr = reinterpret_cast<int*>(sm + ((tile_bins + 1 + 3) & ~3));  // [seg.n][nx]
   const int ij = blockIdx.y;
   const long J_begin = long(blockIdx.x) * chunk_bins;
@@ -102,12 +85,15 @@ __global__ __launch_bounds__(256) void k_splat(
 
   // first row of each (column, layer) whose position is >= J_begin - 1
   for (int c = threadIdx.x; c < nx; c += blockDim.x) {
-    const int otx = abs(btx + 2 * c), orx = abs(brx + 2 * c);
+    const Leg* ltx = legs + abs(btx + 2 * c);
+    const Leg* lrx = legs + abs(brx + 2 * c);
     for (int sg = 0; sg < seg.n; ++sg) {
       int lo = seg.lo[sg], hi = seg.hi[sg];
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (fine_pos(delay, n_off, mid, otx, orx, Q) < J_begin - 1) lo = mid + 1; else hi = mid;
+        const size_t o = size_t(mid) * n_off;
+        if (long(fine_q(ltx[o].delay, lrx[o].delay, Q) >> 32) < J_begin - 1) lo = mid + 1;
+        else hi = mid;
       }
       ptr[sg * nx + c] = lo;
     }
@@ -118,22 +104,23 @@ __global__ __launch_bounds__(256) void k_splat(
   for (long J0 = J_begin; J0 < J_end; J0 += tile_bins) {
     const long J1 = min(J0 + long(tile_bins), J_end);
     for (int c = threadIdx.x; c < nx; c += blockDim.x) {
-      const int otx = abs(btx + 2 * c), orx = abs(brx + 2 * c);
+      const Leg* ltx = legs + abs(btx + 2 * c);
+      const Leg* lrx = legs + abs(brx + 2 * c);
       for (int sg = 0; sg < seg.n; ++sg) {
         int r = ptr[sg * nx + c];
         const int hi = seg.hi[sg];
         for (; r < hi; ++r) {
-          const int64_t* drow = delay + size_t(r) * n_off;
-          const uint64_t DQ = uint64_t(drow[otx] + drow[orx]) * uint64_t(Q);
+          const size_t o = size_t(r) * n_off;
+          const Leg a = ltx[o], b = lrx[o];
+          const uint64_t DQ = fine_q(a.delay, b.delay, Q);
           const long J = long(DQ >> 32);
           if (J >= J1) break;
           if (J + 1 < J0) continue;  // cannot happen while delays grow with depth in a layer
-          float xv = x ? x[r * nx + c] : 1.0f;
+          const float xv = x ? x[r * nx + c] : 1.0f;
           if (xv == 0.0f) continue;
-          const float* arow = apod + size_t(r) * n_off;
-          float w = tau[r] * xv * (arow[otx] * arow[orx]);
+          float w = tau[r] * xv * (a.apod * b.apod);
           if (ABSW) w = fabsf(w);
-          const float phi = float(uint32_t(DQ)) * 2.3283064365386963e-10f;  // 2^-32
+          const float phi = float(uint32_t(DQ)) * kTwoM32;
           if (J >= J0) atomicAdd(&tile[J - J0], w * (1.0f - phi));
           atomicAdd(&tile[J + 1 - J0], w * phi);  // J + 1 - J0 in [0, tile_bins]
         }
@@ -153,38 +140,41 @@ __global__ __launch_bounds__(256) void k_splat(
   }
 }
 
-// S^T: per voxel, sum over the traces of group blockIdx.y; one partial image
-// per group, summed in a fixed order by k_reduce_groups.
+// S^T: thread = voxel (row-major: neighbouring threads read neighbouring leg
+// records), summing over the traces of group blockIdx.x; one partial image per
+// group, summed in a fixed order by k_reduce_groups.  The group is the fastest
+// block index, so group g stays on XCD g mod 8 and that XCD's L2 holds the
+// fine-grid data of its own traces only.
 template <bool ABSW>
 __global__ __launch_bounds__(256) void k_gather(
-    const float* __restrict__ fine, int nx, int nz, int n_off, const int64_t* __restrict__ delay,
-    const float* __restrict__ apod, const float* __restrict__ tau, const int* __restrict__ base,
-    int P, int K, int Q, long MQ, int tpg, float* __restrict__ partial) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int Q, long MQ,
+    int tpg, float* __restrict__ partial) {
+  const int v = blockIdx.y * blockDim.x + threadIdx.x;
   const int N = nx * nz;
   if (v >= N) return;
   const int row = v / nx, col = v - row * nx;
-  const int64_t* drow = delay + size_t(row) * n_off;
-  const float* arow = apod + size_t(row) * n_off;
+  const Leg* lrow = legs + size_t(row) * n_off;
   const int PK = P * K;
-  const int t0 = blockIdx.y * tpg;
+  const int t0 = blockIdx.x * tpg;
   const int t1 = min(t0 + tpg, PK);
   float acc = 0.0f;
   for (int t = t0; t < t1; ++t) {
-    const int i = t / K;
-    const int otx = abs(base[i] + 2 * col);
-    const int orx = abs(base[P + t] + 2 * col);
-    const Pair p = pair_terms(drow, arow, otx, orx, Q);
-    float w = p.w;
+    const Leg a = lrow[abs(base[t / K] + 2 * col)];
+    const Leg b = lrow[abs(base[P + t] + 2 * col)];
+    const uint64_t DQ = fine_q(a.delay, b.delay, Q);
+    const long J = long(DQ >> 32);
+    const float phi = float(uint32_t(DQ)) * kTwoM32;
+    float w = a.apod * b.apod;
     if (ABSW) w = fabsf(w);
     const float* c = fine + size_t(t) * MQ;
-    const float c0 = p.J < MQ ? c[p.J] : 0.0f;
-    const float c1 = p.J + 1 < MQ ? c[p.J + 1] : 0.0f;
-    acc = fmaf(w, fmaf(p.phi, c1 - c0, c0), acc);
+    const float c0 = J < MQ ? c[J] : 0.0f;
+    const float c1 = J + 1 < MQ ? c[J + 1] : 0.0f;
+    acc = fmaf(w, fmaf(phi, c1 - c0, c0), acc);
   }
   float tr = tau[row];
   if (ABSW) tr = fabsf(tr);
-  partial[size_t(blockIdx.y) * N + v] = acc * tr;
+  partial[size_t(blockIdx.x) * N + v] = acc * tr;
 }
 
 __global__ void k_reduce_groups(const float* __restrict__ partial, int groups, int N, float scale,
@@ -218,10 +208,10 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ fine,
   constexpr int PER_WAVE = MB * R;
   extern __shared__ float sh[];
   stage_taps(sh, hq, Lh, LhPad, Q);
-  const int ij = blockIdx.y;
+  const int ij = blockIdx.x;  // trace fastest: all blocks of a trace share an XCD and its L2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = lane & (Q - 1), mb = lane / Q;
-  const int m0 = blockIdx.x * (4 * PER_WAVE) + wave * PER_WAVE + mb * R;
+  const int m0 = blockIdx.y * (4 * PER_WAVE) + wave * PER_WAVE + mb * R;
   const float* s = fine + size_t(ij) * M * Q + t;
   auto ld = [&](int n) -> float { return (n >= 0 && n < M) ? s[size_t(n) * Q] : 0.0f; };
   float acc[R];
@@ -274,10 +264,10 @@ __global__ __launch_bounds__(256) void k_corr(const float* __restrict__ rt,
   constexpr int PER_WAVE = NB * R;
   extern __shared__ float sh[];
   stage_taps(sh, hq, Lh, LhPad, Q);
-  const int ij = blockIdx.y;
+  const int ij = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = lane & (Q - 1), nb = lane / Q;
-  const int n0 = blockIdx.x * (4 * PER_WAVE) + wave * PER_WAVE + nb * R;
+  const int n0 = blockIdx.y * (4 * PER_WAVE) + wave * PER_WAVE + nb * R;
   const float* r = rt + size_t(ij) * M;
   auto ld = [&](int m) -> float { return m < M ? r[m] : 0.0f; };
   float acc[R];
@@ -327,7 +317,7 @@ void launch_conv_q(const umbir_geometry& G, const float* fine, const float* hq, 
                    float sign, const float* g, float* out, hipStream_t s) {
   constexpr int per_block = 4 * (64 / Q) * kR;
   const int LhP = lh_pad(G.Lh);
-  dim3 grid((G.M + per_block - 1) / per_block, G.traces());
+  dim3 grid(G.traces(), (G.M + per_block - 1) / per_block);
   UMBIR_LAUNCH("conv", k_conv<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, fine, hq, G.M,
                      G.Lh, LhP, base, sign, g, G.dbasis, out);
 }
@@ -337,7 +327,7 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
                    hipStream_t s) {
   constexpr int per_block = 4 * (64 / Q) * kR;
   const int LhP = lh_pad(G.Lh);
-  dim3 grid((G.M + per_block - 1) / per_block, G.traces());
+  dim3 grid(G.traces(), (G.M + per_block - 1) / per_block);
   UMBIR_LAUNCH("corr", k_corr<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, r, hq, G.M,
                      G.Lh, LhP, fine);
 }
@@ -402,11 +392,11 @@ int run_forward(const umbir_geometry& G, const float* x, float* out, const float
   const size_t lds = size_t((G.tile_bins + 1 + 3) & ~3) * sizeof(float) + size_t(G.n_seg) * G.nx * sizeof(int);
   dim3 grid(G.chunks, G.traces());
   if (abs_op)
-    UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.delay, G.apod,
-                 G.tau, G.base, G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
+    UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
+                 G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
   else
-    UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.delay, G.apod,
-                 G.tau, G.base, G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
+    UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
+                 G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
   int st = check_hip(hipGetLastError(), "k_splat");
   if (st) return st;
   launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
@@ -420,16 +410,16 @@ int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale
   int st = check_hip(hipGetLastError(), "k_corr");
   if (st) return st;
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
-  dim3 grid((G.voxels() + 255) / 256, G.trace_groups);
+  dim3 grid(G.trace_groups, (G.voxels() + 255) / 256);
   if (abs_op)
-    UMBIR_LAUNCH("gather", k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
-                       G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, partial);
+    UMBIR_LAUNCH("gather", k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs, G.tau,
+                 G.base, G.P, G.K, G.Q, MQ, tpg, partial);
   else
-    UMBIR_LAUNCH("gather", k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.delay,
-                       G.apod, G.tau, G.base, G.P, G.K, G.Q, MQ, tpg, partial);
+    UMBIR_LAUNCH("gather", k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs, G.tau,
+                 G.base, G.P, G.K, G.Q, MQ, tpg, partial);
   if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
-                     G.trace_groups, G.voxels(), scale, out);
+               G.trace_groups, G.voxels(), scale, out);
   return check_hip(hipGetLastError(), "k_reduce_groups");
 }
 
