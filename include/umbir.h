@@ -150,7 +150,8 @@ size_t umbir_workspace_bytes(const umbir_geometry* geom, int kind);
 /* y = A x (accumulate == 0) or y += A x (accumulate != 0), Eq. (13):
  * y[i][j][m] = sum_v W_ij(v) x(v) h~(m / fs - T_ij(v)) with the tabulated,
  * linearly interpolated h~, W = tau(v) phi^(beta)(v).  Scan positions are
- * separate firings stacked as rows of y.  x_dev: [nz][nx]; y_dev: [P][K][M]. */
+ * separate firings stacked as rows of y.  x_dev: [nz][nx]; y_dev: [P][K][M].
+ * Deterministic: the same inputs give bitwise the same output. */
 int umbir_forward(const umbir_geometry* geom, const float* x_dev, float* y_dev,
                   int accumulate, void* work, size_t work_bytes, void* stream);
 

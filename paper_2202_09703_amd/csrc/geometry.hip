@@ -34,7 +34,9 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nz * n_off) return;
   const int row = idx / n_off;
-  const int o = idx - row * n_off;
+  const int slot = idx - row * n_off;
+  const int half = n_off / 2;
+  const int o = slot < half ? 2 * slot : 2 * (slot - half) + 1;
   const double z = z0 + (row + 0.5) * dz;
   const double X = o * half_dx;
   double eta[kMaxLayers];
@@ -225,7 +227,7 @@ int validate(const umbir_problem* pb, Derived* dv) {
         return fail(UMBIR_ENOTSUP, "receiver off the half-voxel lattice (2 (x0 - x) / dx not an integer)");
   }
   if (omax + 1 > (1 << 24)) return fail(UMBIR_EINVAL, "lateral extent too large");
-  dv->n_off = int(omax + 1);
+  dv->n_off = int((omax + 2) & ~1L);  // even, for the parity split of each row
   return UMBIR_OK;
 }
 
@@ -394,7 +396,9 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     if (chunks < 1) chunks = 1;
     G->chunks = int(chunks);
     G->chunk_bins = (MQ + chunks - 1) / chunks;
-    G->tile_bins = int(std::min<long>(8192, G->chunk_bins));
+    // 16 KiB tiles: small enough for 8 workgroups per CU, which the splat's
+    // memory round trips need to overlap
+    G->tile_bins = int(std::min<long>(4096, G->chunk_bins));
   }
 
   const size_t legs = size_t(G->nz) * G->n_off;
@@ -510,10 +514,14 @@ int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes
   int st = check_hip(hipMemcpy(rec.data(), G->legs, legs * sizeof(Leg), hipMemcpyDeviceToHost),
                      "hipMemcpy(legs)");
   if (st) return st;
-  for (size_t k = 0; k < legs; ++k) {
-    if (which == UMBIR_TABLE_DELAY) static_cast<int64_t*>(dst)[k] = rec[k].delay;
-    else static_cast<float*>(dst)[k] = rec[k].apod;
-  }
+  const int half = G->n_off / 2;
+  for (int r = 0; r < G->nz; ++r)
+    for (int o = 0; o < G->n_off; ++o) {
+      const Leg& L = rec[size_t(r) * G->n_off + leg_slot(o, half)];
+      const size_t k = size_t(r) * G->n_off + o;
+      if (which == UMBIR_TABLE_DELAY) static_cast<int64_t*>(dst)[k] = L.delay;
+      else static_cast<float*>(dst)[k] = L.apod;
+    }
   return UMBIR_OK;
 }
 

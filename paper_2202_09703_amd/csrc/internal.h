@@ -15,13 +15,17 @@ constexpr int kMaxLayers = UMBIR_MAX_LAYERS;
 constexpr double kTwo32 = 4294967296.0;
 
 // One-way leg record: delay in Q32.32 fixed-point samples and cos^beta of the
-// leg's angle sum, stored row-major [nz][n_off]: neighbouring columns of one
-// row read neighbouring records.
+// leg's angle sum, stored row-major [nz][n_off].  Within a row the lattice
+// offsets are split by parity (even offsets first, then odd): one transducer
+// only ever uses offsets of one parity, so neighbouring columns read
+// neighbouring records.  n_off is even.
 struct __align__(16) Leg {
   int64_t delay;
   float apod;
   float pad;
 };
+
+__host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >> 1) + (o & 1) * half; }
 
 // Planar layer stack passed to kernels by value.  top/bottom are depths of
 // each layer's faces; the last bottom is +inf.
@@ -99,7 +103,7 @@ struct umbir_geometry {
   long chunk_bins = 0;
   int tile_bins = 0;
   // resident device tables
-  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta)
+  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows
   float* tau = nullptr;      // [nz] transmittance product of the row's layer
   int* base = nullptr;       // [P + P*K] lattice base: offset index = |base + 2 col|
   float* bank = nullptr;     // [Q*Lh + 2] tabulated windowed pulse, zero padded

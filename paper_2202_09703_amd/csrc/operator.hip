@@ -19,6 +19,7 @@
 // fine-grid positions per (trace, voxel) pair.  Delays are Q32.32 fixed point
 // (sum of two one-way legs, added exactly as integers), so J and phi are exact.
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -50,90 +51,149 @@ struct Segments {
   int hi[kMaxLayers];
 };
 
-// Fine-grid position J = floor(D Q) of a (trace, voxel) pair from its two legs.
-__device__ __forceinline__ uint64_t fine_q(int64_t dtx, int64_t drx, int Q) {
-  return uint64_t(dtx + drx) * uint64_t(Q);
+constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
+
+// Largest |x| as float bits (non-negative floats order like their bits), for
+// the fixed-point scale of the splat.  x == NULL means x = 1.
+__global__ void k_absmax(const float* __restrict__ x, int n, unsigned* __restrict__ out) {
+  unsigned m = 0;
+  if (x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+      m = max(m, __float_as_uint(fabsf(x[i])));
+  } else {
+    m = __float_as_uint(1.0f);
+  }
+  for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
+  __shared__ unsigned wmax[16];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) m = max(m, wmax[w]);
+    atomicMax(out, m);  // one atomic per block
+  }
 }
 
-constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
+// Fixed-point exponent of the splat: contributions are scaled by 2^k with
+// 2^k * max|x| * N <= 2^62, so no tile position can overflow int64 even if
+// every voxel of the trace landed on it (|W| <= 1 and the two weights of a
+// voxel sum to 1).  Power-of-two scaling is exact in both directions.
+__device__ __forceinline__ int splat_exponent(unsigned maxbits, int n_vox) {
+  int e = 0;
+  (void)frexpf(__uint_as_float(maxbits), &e);  // max|x| < 2^e
+  int lg = 0;
+  while ((1 << lg) < n_vox) ++lg;
+  return 62 - lg - e;
+}
 
 // S: the fine-grid signal of one trace, one chunk of fine positions per
 // workgroup, built in LDS tiles without global atomics.  Within a layer a
 // voxel's delay grows strictly with depth, so for each (column, layer) the
 // voxels reach the fine grid in row order: one pointer per (column, layer)
-// walks forward through the rows as the tiles advance, and every voxel is
-// visited once.  Thread = column: neighbouring threads usually sit on the same
-// row, so their leg records and image entries are neighbours.  A voxel at position J adds
+// moves forward through the rows as the tiles advance, and every voxel is
+// visited once.  A wave takes 8 neighbouring columns x 8 consecutive rows per
+// step (lanes of one column stop together, and the 8 columns of a row read
+// neighbouring leg records); the rows of a column that fall in the tile are a
+// prefix of the 8, counted with a ballot.  A voxel at position J adds
 // W x (1 - phi) to J and W x phi to J + 1; the tile keeps one extra slot for
-// J + 1 = the next tile's first position.  x == NULL means x = 1.  Tiles are
-// written out whole (coalesced), so the fine buffer needs no clearing.
+// J + 1 = the next tile's first position.  The tile accumulates in 64-bit
+// fixed point (integer LDS atomics: fast on CDNA, and the sum does not depend
+// on the order of the adds, so the result is bitwise reproducible), scaled by
+// 2^k from splat_exponent.  x == NULL means x = 1.  Tiles are written out
+// whole (coalesced), so the fine buffer needs no clearing.
 template <bool ABSW>
 __global__ __launch_bounds__(256) void k_splat(
     const float* __restrict__ x, int nx, int n_off, const Leg* __restrict__ legs,
-    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int Q, long MQ,
-    Segments seg, long chunk_bins, int tile_bins, float* __restrict__ fine) {
-  extern __shared__ float sm[];
-  float* tile = sm;                                                    // [tile_bins + 1]
-  int* ptr = reinterpret_cast<int*>(sm + ((tile_bins + 1 + 3) & ~3));  // [seg.n][nx]
+    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
+    Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
+    float* __restrict__ fine) {
+  extern __shared__ unsigned long long smem[];
+  unsigned long long* tile = smem;                                   // [tile_bins + 1]
+  int* ptr = reinterpret_cast<int*>(smem + ((tile_bins + 2) & ~1));  // [seg.n][nx]
+  const int kx = splat_exponent(*xmax, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
   const int ij = blockIdx.y;
-  const long J_begin = long(blockIdx.x) * chunk_bins;
-  const long J_end = min(J_begin + chunk_bins, MQ);
+  const int J_begin = blockIdx.x * chunk_bins;
+  const int J_end = min(J_begin + chunk_bins, MQ);
   if (J_begin >= J_end) return;  // uniform over the block
   const int btx = base[ij / K];
   const int brx = base[P + ij];
+  const int half = n_off / 2;
+  const int sh = 32 - qs;  // J = (D_tx + D_rx) >> (32 - log2 Q)
   float* out = fine + size_t(ij) * MQ;
 
   // first row of each (column, layer) whose position is >= J_begin - 1
   for (int c = threadIdx.x; c < nx; c += blockDim.x) {
-    const Leg* ltx = legs + abs(btx + 2 * c);
-    const Leg* lrx = legs + abs(brx + 2 * c);
+    const Leg* ltx = legs + leg_slot(abs(btx + 2 * c), half);
+    const Leg* lrx = legs + leg_slot(abs(brx + 2 * c), half);
     for (int sg = 0; sg < seg.n; ++sg) {
       int lo = seg.lo[sg], hi = seg.hi[sg];
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         const size_t o = size_t(mid) * n_off;
-        if (long(fine_q(ltx[o].delay, lrx[o].delay, Q) >> 32) < J_begin - 1) lo = mid + 1;
-        else hi = mid;
+        const int J = int(uint64_t(ltx[o].delay + lrx[o].delay) >> sh);
+        if (J < J_begin - 1) lo = mid + 1; else hi = mid;
       }
       ptr[sg * nx + c] = lo;
     }
   }
-  for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0.0f;
+  for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0ull;
   __syncthreads();
 
-  for (long J0 = J_begin; J0 < J_end; J0 += tile_bins) {
-    const long J1 = min(J0 + long(tile_bins), J_end);
-    for (int c = threadIdx.x; c < nx; c += blockDim.x) {
-      const Leg* ltx = legs + abs(btx + 2 * c);
-      const Leg* lrx = legs + abs(brx + 2 * c);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cc = lane & 7, rr = lane >> 3;
+  const unsigned long long colmask = 0x0101010101010101ull << cc;
+  const int n_groups = (nx + 7) >> 3;
+  for (int J0 = J_begin; J0 < J_end; J0 += tile_bins) {
+    const int J1 = min(J0 + tile_bins, J_end);
+    for (int grp = wave; grp < n_groups; grp += 4) {
+      const int c = grp * 8 + cc;
+      const bool col_ok = c < nx;
+      const Leg* ltx = legs + (col_ok ? leg_slot(abs(btx + 2 * c), half) : 0);
+      const Leg* lrx = legs + (col_ok ? leg_slot(abs(brx + 2 * c), half) : 0);
       for (int sg = 0; sg < seg.n; ++sg) {
-        int r = ptr[sg * nx + c];
         const int hi = seg.hi[sg];
-        for (; r < hi; ++r) {
-          const size_t o = size_t(r) * n_off;
-          const Leg a = ltx[o], b = lrx[o];
-          const uint64_t DQ = fine_q(a.delay, b.delay, Q);
-          const long J = long(DQ >> 32);
-          if (J >= J1) break;
-          if (J + 1 < J0) continue;  // cannot happen while delays grow with depth in a layer
-          const float xv = x ? x[r * nx + c] : 1.0f;
-          if (xv == 0.0f) continue;
-          float w = tau[r] * xv * (a.apod * b.apod);
-          if (ABSW) w = fabsf(w);
-          const float phi = float(uint32_t(DQ)) * kTwoM32;
-          if (J >= J0) atomicAdd(&tile[J - J0], w * (1.0f - phi));
-          atomicAdd(&tile[J + 1 - J0], w * phi);  // J + 1 - J0 in [0, tile_bins]
+        int r0 = col_ok ? ptr[sg * nx + c] : hi;
+        bool live = r0 < hi;  // this column may still have rows in the tile
+        while (__any(live)) {
+          const int r = r0 + rr;
+          bool in = live && r < hi;
+          uint64_t D = 0;
+          Leg a, b;
+          float xv = 0.0f, tr = 0.0f;
+          if (in) {  // all four loads in flight together
+            a = ltx[size_t(r) * n_off];
+            b = lrx[size_t(r) * n_off];
+            xv = x ? x[r * nx + c] : 1.0f;
+            tr = tau[r];
+            D = uint64_t(a.delay + b.delay);
+            in = int(D >> sh) < J1;
+          }
+          if (in) {
+            const int J = int(D >> sh);
+            // J + 1 >= J0 holds while delays grow with depth within a layer
+            if (xv != 0.0f && J + 1 >= J0) {
+              float w = tr * xv * (a.apod * b.apod);
+              if (ABSW) w = fabsf(w);
+              const float phi = float(uint32_t(D) << qs) * kTwoM32;
+              const float w1 = w * phi;
+              if (J >= J0)
+                atomicAdd(&tile[J - J0], (unsigned long long)(long long)ldexpf(w - w1, kx));
+              atomicAdd(&tile[J + 1 - J0], (unsigned long long)(long long)ldexpf(w1, kx));
+            }
+          }
+          const int cnt = __popcll(__ballot(in) & colmask);  // rows of column c taken
+          r0 += cnt;
+          live = live && cnt == 8;
         }
-        ptr[sg * nx + c] = r;
+        if (col_ok && rr == 0) ptr[sg * nx + c] = r0;
       }
     }
     __syncthreads();
-    const int n = int(J1 - J0);
-    for (int k = threadIdx.x; k < n; k += blockDim.x) out[J0 + k] = tile[k];
+    const int n = J1 - J0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) out[J0 + k] = ldexpf(float((long long)tile[k]), -kx);
     __syncthreads();
-    const float carry = tile[n];
+    const unsigned long long carry = tile[n];
     __syncthreads();
-    for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0.0f;
+    for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) tile[0] = carry;
     __syncthreads();
@@ -148,7 +208,7 @@ __global__ __launch_bounds__(256) void k_splat(
 template <bool ABSW>
 __global__ __launch_bounds__(256) void k_gather(
     const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
-    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int Q, long MQ,
+    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
     int tpg, float* __restrict__ partial) {
   const int v = blockIdx.y * blockDim.x + threadIdx.x;
   const int N = nx * nz;
@@ -158,18 +218,21 @@ __global__ __launch_bounds__(256) void k_gather(
   const int PK = P * K;
   const int t0 = blockIdx.x * tpg;
   const int t1 = min(t0 + tpg, PK);
+  const int sh = 32 - qs;
+  const int half = n_off / 2;
   float acc = 0.0f;
   for (int t = t0; t < t1; ++t) {
-    const Leg a = lrow[abs(base[t / K] + 2 * col)];
-    const Leg b = lrow[abs(base[P + t] + 2 * col)];
-    const uint64_t DQ = fine_q(a.delay, b.delay, Q);
-    const long J = long(DQ >> 32);
-    const float phi = float(uint32_t(DQ)) * kTwoM32;
+    const Leg a = lrow[leg_slot(abs(base[t / K] + 2 * col), half)];
+    const Leg b = lrow[leg_slot(abs(base[P + t] + 2 * col), half)];
+    const uint64_t D = uint64_t(a.delay + b.delay);
+    const int J = int(D >> sh);
+    const float phi = float(uint32_t(D) << qs) * kTwoM32;
     float w = a.apod * b.apod;
     if (ABSW) w = fabsf(w);
     const float* c = fine + size_t(t) * MQ;
-    const float c0 = J < MQ ? c[J] : 0.0f;
-    const float c1 = J + 1 < MQ ? c[J + 1] : 0.0f;
+    // unsigned compares: a position past 2^31 (never reached by a valid record) reads nothing
+    const float c0 = unsigned(J) < unsigned(MQ) ? c[J] : 0.0f;
+    const float c1 = unsigned(J + 1) < unsigned(MQ) ? c[J + 1] : 0.0f;
     acc = fmaf(w, fmaf(phi, c1 - c0, c0), acc);
   }
   float tr = tau[row];
@@ -373,30 +436,44 @@ int launch_copy(float* dst, const float* src, size_t n, hipStream_t s) {
 }
 
 size_t forward_work_bytes(const umbir_geometry& G) {
-  return aligned(size_t(G.traces()) * G.fine_per_trace() * sizeof(float)) + 256;
+  // fine buffer followed by one scalar (see run_forward)
+  return aligned((size_t(G.traces()) * G.fine_per_trace() + 1) * sizeof(float)) + 256;
 }
 
 size_t adjoint_work_bytes(const umbir_geometry& G) {
   return forward_work_bytes(G) + aligned(size_t(G.trace_groups) * G.voxels() * sizeof(float)) + 256;
 }
 
+int log2_int(int q) {
+  int k = 0;
+  while ((1 << k) < q) ++k;
+  return k;
+}
+
 int run_forward(const umbir_geometry& G, const float* x, float* out, const float* base, float sign,
                 const float* g, bool abs_op, float* fine, hipStream_t s) {
+  // one scalar after the fine buffer: the largest |x| (as float bits)
+  unsigned* xmax = reinterpret_cast<unsigned*>(fine + G.traces() * G.fine_per_trace());
   const long MQ = long(G.fine_per_trace());
+  const int qs = log2_int(G.Q);
   Segments seg;
   seg.n = G.n_seg;
   for (int k = 0; k < kMaxLayers; ++k) {
     seg.lo[k] = G.seg_lo[k];
     seg.hi[k] = G.seg_hi[k];
   }
-  const size_t lds = size_t((G.tile_bins + 1 + 3) & ~3) * sizeof(float) + size_t(G.n_seg) * G.nx * sizeof(int);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(xmax), size_t(1), 0.0f);
+  UMBIR_LAUNCH("absmax", k_absmax, dim3(x ? std::min(32, (G.voxels() + 1023) / 1024) : 1), dim3(1024), 0, s,
+               x, G.voxels(), xmax);
+  const size_t lds = size_t((G.tile_bins + 2) & ~1) * sizeof(unsigned long long) +
+                     size_t(G.n_seg) * G.nx * sizeof(int);
   dim3 grid(G.chunks, G.traces());
   if (abs_op)
     UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
-                 G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
+                 G.P, G.K, qs, int(MQ), seg, int(G.chunk_bins), G.tile_bins, xmax, fine);
   else
     UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
-                 G.P, G.K, G.Q, MQ, seg, G.chunk_bins, G.tile_bins, fine);
+                 G.P, G.K, qs, int(MQ), seg, int(G.chunk_bins), G.tile_bins, xmax, fine);
   int st = check_hip(hipGetLastError(), "k_splat");
   if (st) return st;
   launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
@@ -406,6 +483,7 @@ int run_forward(const umbir_geometry& G, const float* x, float* out, const float
 int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale, bool abs_op,
                 float* fine, float* partial, hipStream_t s) {
   const long MQ = long(G.fine_per_trace());
+  const int qs = log2_int(G.Q);
   launch_corr(G, r, abs_op ? G.habs : G.h, fine, s);
   int st = check_hip(hipGetLastError(), "k_corr");
   if (st) return st;
@@ -413,10 +491,10 @@ int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale
   dim3 grid(G.trace_groups, (G.voxels() + 255) / 256);
   if (abs_op)
     UMBIR_LAUNCH("gather", k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs, G.tau,
-                 G.base, G.P, G.K, G.Q, MQ, tpg, partial);
+                 G.base, G.P, G.K, qs, int(MQ), tpg, partial);
   else
     UMBIR_LAUNCH("gather", k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs, G.tau,
-                 G.base, G.P, G.K, G.Q, MQ, tpg, partial);
+                 G.base, G.P, G.K, qs, int(MQ), tpg, partial);
   if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
                G.trace_groups, G.voxels(), scale, out);
@@ -452,7 +530,7 @@ int umbir_forward(const umbir_geometry* G, const float* x, float* y, int accumul
   int st = ws.acquire(work, work_bytes, forward_work_bytes(*G), s);
   if (st) return st;
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace());
+  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace() + 1);
   return run_forward(*G, x, y, accumulate ? y : nullptr, 1.0f, nullptr, false, fine, s);
 }
 
@@ -464,7 +542,7 @@ int umbir_adjoint(const umbir_geometry* G, const float* r, float* x, void* work,
   int st = ws.acquire(work, work_bytes, adjoint_work_bytes(*G), s);
   if (st) return st;
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace());
+  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace() + 1);
   float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
   return run_adjoint(*G, r, x, 1.0f, false, fine, partial, s);
 }
@@ -488,7 +566,7 @@ int umbir_sqs_denominator(const umbir_geometry* G, double sigma, float* d, void*
   int st = ws.acquire(work, work_bytes, need, s);
   if (st) return st;
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace());
+  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace() + 1);
   float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
   float* col = cv.take<float>(size_t(G->traces()) * G->M);
   if ((st = run_forward(*G, nullptr, col, nullptr, 1.0f, nullptr, true, fine, s))) return st;

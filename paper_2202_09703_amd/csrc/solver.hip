@@ -195,7 +195,7 @@ extern "C" int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr,
   const size_t N = G->voxels(), PK = G->traces();
   const int nblk = int((N + 255) / 256);
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(PK * G->fine_per_trace());
+  float* fine = cv.take<float>(PK * G->fine_per_trace() + 1);
   float* partial = cv.take<float>(size_t(G->trace_groups) * N);
   float* e = cv.take<float>(PK * G->M);
   float* u = cv.take<float>(N);
