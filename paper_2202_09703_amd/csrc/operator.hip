@@ -359,6 +359,69 @@ __global__ __launch_bounds__(256) void k_corr(const float* __restrict__ rt,
     if (n0 + q < M) c[size_t(n0 + q) * Q] = acc[q];
 }
 
+// C^T on the matrix cores, for Q a multiple of 32: per trace the correlation
+// is a dense product c[n][t] = sum_k R[n][k] H[k][t] with the Hankel matrix
+// R[n][k] = r[n+1+k] and the taps H[k][t] = h_t[k], so it runs as FP32 MFMA
+// (v_mfma_f32_32x32x2f32: A lane l = R[l%32][l/32], B lane l = H[l/32][l%32],
+// D register i of lane l = row 8(i/4) + 4(l/32) + i%4, column l%32).  A wave
+// computes NT tiles of 32 rows x Q phases; the block stages its trace segment
+// and the taps (zero-padded to an even count) in LDS.  Writes are coalesced
+// along t.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int QT, int NT>
+__global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
+                                                   const float* __restrict__ hq, int M, int Lh,
+                                                   float* __restrict__ fine) {
+  constexpr int Q = 32 * QT;
+  constexpr int ROWS = 4 * NT * 32;  // n per block
+  extern __shared__ float sm[];
+  const int LhE = (Lh + 1) & ~1;
+  float* taps = sm;                  // [LhE][Q]
+  float* seg = sm + LhE * Q;         // [ROWS + LhE]: r[n_blk + 1 + j]
+  const int ij = blockIdx.x;
+  const int n_blk = blockIdx.y * ROWS;
+  const float* r = rt + size_t(ij) * M;
+  for (int i = threadIdx.x; i < LhE * Q; i += blockDim.x) taps[i] = i < Lh * Q ? hq[i] : 0.0f;
+  for (int j = threadIdx.x; j < ROWS + LhE; j += blockDim.x) {
+    const int m = n_blk + 1 + j;
+    seg[j] = m < M ? r[m] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  floatx16 acc[NT][QT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < QT; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+  const int row0 = wave * NT * 32;
+  for (int k0 = 0; k0 < LhE; k0 += 2) {
+    float bv[QT];
+#pragma unroll
+    for (int b = 0; b < QT; ++b) bv[b] = taps[(k0 + lk) * Q + b * 32 + li];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const float av = seg[row0 + a * 32 + li + k0 + lk];
+#pragma unroll
+      for (int b = 0; b < QT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+  float* c = fine + size_t(ij) * M * Q;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int n = n_blk + row0 + a * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
+      if (n < M) {
+#pragma unroll
+        for (int b = 0; b < QT; ++b) c[size_t(n) * Q + b * 32 + li] = acc[a][b][i];
+      }
+    }
+}
+
 __global__ void k_direct(const float* __restrict__ g, const float* __restrict__ dbasis, int M,
                          size_t total, int accumulate, float* __restrict__ y) {
   const size_t stride = size_t(gridDim.x) * blockDim.x;
@@ -408,8 +471,21 @@ void launch_conv(const umbir_geometry& G, const float* fine, const float* hq, co
   }
 }
 
+template <int QT>
+void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine,
+                      hipStream_t s) {
+  constexpr int NT = 2;
+  constexpr int rows = 4 * NT * 32;
+  const int LhE = (G.Lh + 1) & ~1;
+  const size_t lds = (size_t(LhE) * 32 * QT + rows + LhE) * sizeof(float);
+  dim3 grid(G.traces(), (G.M + rows - 1) / rows);
+  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, fine);
+}
+
 void launch_corr(const umbir_geometry& G, const float* r, const float* hq, float* fine,
                  hipStream_t s) {
+  if (G.Q == 32) return launch_corr_mfma<1>(G, r, hq, fine, s);
+  if (G.Q == 64) return launch_corr_mfma<2>(G, r, hq, fine, s);
   switch (G.Q) {
     case 1: launch_corr_q<1>(G, r, hq, fine, s); break;
     case 2: launch_corr_q<2>(G, r, hq, fine, s); break;
