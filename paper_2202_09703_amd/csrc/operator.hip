@@ -422,6 +422,125 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
     }
 }
 
+// C on the matrix cores, for Q in {32, 64}: the convolution of one trace has a
+// single output column, so traces are batched as the N dimension:
+//   Y[m][tr] = sum_{(n,t)} H[m-1-n][t] S_tr[n Q + t],
+// A = the banded Toeplitz tile built from the taps (zero where m - 1 - n is
+// outside the window), B = the fine-grid signals of 32 traces.  A block owns a
+// 32 (m) x 32 (trace) output tile; its four waves split the (n, t) range
+// between them in 64-wide chunks, stage their chunk of B through LDS with
+// coalesced loads, and the four partial tiles are summed in LDS at the end.
+// Epilogue as in k_conv.  Taps are stored with row stride Q + 1 and staged
+// chunks with stride 65 so neither operand read hits one LDS bank twice.
+template <int Q>
+__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
+                                                   const float* __restrict__ hq, int M, int Lh,
+                                                   int PK, const float* base, float sign,
+                                                   const float* __restrict__ g,
+                                                   const float* __restrict__ dbasis, float* out) {
+  constexpr int CK = 64;        // (n, t) pairs per chunk
+  constexpr int CN = CK / Q;    // rows n per chunk
+  constexpr int SB = CK + 1;    // staged row stride
+  extern __shared__ float sm[];
+  float* taps = sm;                                   // [Lh][Q + 1]
+  float* stage = sm + Lh * (Q + 1);                   // [4 waves][32 traces][SB]
+  const int tr0 = blockIdx.x * 32;
+  const int m0 = blockIdx.y * 32;
+  const long MQ = long(M) * Q;
+  for (int i = threadIdx.x; i < Lh * Q; i += blockDim.x) taps[(i / Q) * (Q + 1) + (i % Q)] = hq[i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  float* st = stage + wave * 32 * SB;
+  // rows n that meet an output m in [m0, m0 + 32): m0 - Lh <= n <= m0 + 30
+  const int n_lo = max(0, m0 - Lh);
+  const int n_hi = min(M, m0 + 31);
+  const int n_chunks = (max(0, n_hi - n_lo) + CN - 1) / CN;
+  const int rounds = (n_chunks + 3) / 4;
+  floatx16 acc[2];  // two independent accumulation chains (even / odd k pairs)
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.0f;
+  // B chunk of one wave: 32 traces x CK values, 16 lanes x float4 per trace,
+  // 4 traces per load instruction, 8 instructions; prefetched one chunk ahead
+  const int sub = lane & 15, tq = lane >> 4;
+  float4 pre[8];
+  auto fetch = [&](int ch) {
+    const int nc = n_lo + ch * CN;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int tr = u * 4 + tq;
+      const int kp = sub * 4;  // first of four consecutive (n, t) values
+      const int n = nc + kp / Q;
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (ch < n_chunks && n < n_hi && tr0 + tr < PK)
+        v = *reinterpret_cast<const float4*>(fine + size_t(tr0 + tr) * MQ + size_t(nc) * Q + kp);
+      pre[u] = v;
+    }
+  };
+  const int m = m0 + li;
+  __syncthreads();  // taps staged
+  fetch(wave);
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int ch = rd * 4 + wave;
+    const int nc = n_lo + ch * CN;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      float* d = st + (u * 4 + tq) * SB + sub * 4;
+      d[0] = pre[u].x;
+      d[1] = pre[u].y;
+      d[2] = pre[u].z;
+      d[3] = pre[u].w;
+    }
+    __builtin_amdgcn_wave_barrier();  // the staging buffer is private to this wave
+    fetch(ch + 4);
+    if (ch < n_chunks) {
+      // row nc + r of the chunk meets output m through tap k = m - 1 - nc - r;
+      // outside the window the A value is zero (pointer clamped, value masked)
+      const float* trow[CN];
+      float tmask[CN];
+#pragma unroll
+      for (int r = 0; r < CN; ++r) {
+        const int k = m - 1 - nc - r;
+        const bool ok = k >= 0 && k < Lh;
+        trow[r] = taps + (ok ? k : 0) * (Q + 1) + lk - r * Q;
+        tmask[r] = ok ? 1.0f : 0.0f;
+      }
+      const float* srow = st + li * SB + lk;
+#pragma unroll
+      for (int kk = 0; kk < CK; kk += 2) {
+        const int r = kk / Q;  // compile-time: kk + lk stays in row kk / Q
+        const float av = trow[r][kk] * tmask[r];
+        const float bv = srow[kk];
+        acc[(kk >> 1) & 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[(kk >> 1) & 1], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[0][i] += acc[1][i];
+  // sum the four partial tiles: red[wave][row][col]
+  float* red = stage;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
+    red[(wave * 32 + row) * 33 + li] = acc[0][i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int col = e >> 5, row = e & 31;  // consecutive threads: consecutive m of one trace
+    const int m = m0 + row, tr = tr0 + col;
+    if (m < M && tr < PK) {
+      const float v = red[(0 * 32 + row) * 33 + col] + red[(1 * 32 + row) * 33 + col] +
+                      red[(2 * 32 + row) * 33 + col] + red[(3 * 32 + row) * 33 + col];
+      const size_t idx = size_t(tr) * M + m;
+      float val = sign * v;
+      if (base) val += base[idx];
+      if (g) val -= g[tr] * dbasis[idx];
+      out[idx] = val;
+    }
+  }
+}
+
 __global__ void k_direct(const float* __restrict__ g, const float* __restrict__ dbasis, int M,
                          size_t total, int accumulate, float* __restrict__ y) {
   const size_t stride = size_t(gridDim.x) * blockDim.x;
@@ -458,8 +577,20 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
                      G.Lh, LhP, fine);
 }
 
+template <int Q>
+void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
+                      float sign, const float* g, float* out, hipStream_t s) {
+  const size_t stage = std::max<size_t>(4 * 32 * 65, 4 * 32 * 33);
+  const size_t lds = (size_t(G.Lh) * (Q + 1) + stage) * sizeof(float);
+  dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
+  UMBIR_LAUNCH("conv", k_conv_mfma<Q>, grid, dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
+               sign, g, G.dbasis, out);
+}
+
 void launch_conv(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
                  float sign, const float* g, float* out, hipStream_t s) {
+  if (G.Q == 32) return launch_conv_mfma<32>(G, fine, hq, base, sign, g, out, s);
+  if (G.Q == 64) return launch_conv_mfma<64>(G, fine, hq, base, sign, g, out, s);
   switch (G.Q) {
     case 1: launch_conv_q<1>(G, fine, hq, base, sign, g, out, s); break;
     case 2: launch_conv_q<2>(G, fine, hq, base, sign, g, out, s); break;
