@@ -27,8 +27,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR = 157.3e12   # MI355X published fp32 vector FLOP/s
-PEAK_HBM = 8.0e12             # MI355X published HBM3E bytes/s
+PEAK_FP32 = 157.3e12   # MI355X published fp32 FLOP/s (vector and dense matrix)
+PEAK_HBM = 8.0e12      # MI355X published HBM3E bytes/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_256x256.json")
 
 
 def parse():
@@ -40,7 +41,54 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="skip parity sampling and the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the per-kernel HBM traffic file from four rocprofv3 --pmc counter CSVs")
     return ap.parse_args()
+
+
+def source_digest():
+    """SHA-256 over the HIP sources: traffic counters are valid for this exact source only."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_09703_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel, scaled so a
+    plain 1 GiB copy reads and writes 1 GiB, written to TRAFFIC_FILE."""
+    import csv
+    import re
+
+    def per_kernel(path):
+        acc = {}
+        for row in csv.DictReader(open(path)):
+            m = re.search(r"k_([a-z_]+)", row["Kernel_Name"])
+            if not m:
+                continue
+            n, v = acc.setdefault(m.group(1), [0, 0.0]), float(row["Counter_Value"])
+            n[0] += 1
+            n[1] += v
+        return {k: v[1] / v[0] for k, v in acc.items()}
+
+    def copy_kib(path):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if "copyBuffer" in r["Kernel_Name"]]
+        return sum(vals) / len(vals)
+
+    gib_kib = float(1 << 20)
+    kf, kw = gib_kib / copy_kib(copy_fetch_csv), gib_kib / copy_kib(copy_write_csv)
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    doc = {"source_sha256": source_digest(),
+           "calibration": {"fetch_scale": kf, "write_scale": kw,
+                           "note": "a 1 GiB device copy defines the scale of each counter"},
+           "kernels": {k: {"fetch_bytes": fetch[k] * kf * 1024, "write_bytes": write.get(k, 0.0) * kw * 1024}
+                       for k in sorted(fetch)}}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    print(json.dumps(doc["kernels"], indent=1))
 
 
 def copy_calibration():
@@ -56,22 +104,51 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
-def kernel_work(name, card, n_traces, n_vox):
-    """Algorithmic work of one launch: (amount, unit kind) for the roofline."""
+def kernel_work(name, card, n_off, trace_groups):
+    """Algorithmic work of one launch and its bound.
+
+    conv / corr: the polyphase convolution and correlation, 2 M Q L_h flop per
+    trace (on the matrix cores when Q is 32 or 64).  splat / gather: compulsory
+    HBM bytes -- the leg table, the image and the fine-grid signal (written by
+    the splat, read by the gather, M Q floats per trace), plus the gather's
+    partial images."""
     acq = card.acq
+    P, K, M, Q = card.array.n_scans, card.array.n_rx, acq.n_samples, acq.oversample
     lh = int(round(acq.t_win * acq.fs))
+    N, nz = card.n_voxels, card.grid.nz
+    legs = nz * n_off * 16
+    fine = P * K * M * Q * 4
     if name in ("conv", "corr"):
-        # dense polyphase convolution / correlation: M Q outputs x L_h taps per trace
-        return 2.0 * n_traces * acq.n_samples * acq.oversample * lh, "flop"
-    if name in ("splat", "gather"):
-        # per (trace, voxel): two one-way leg records (8 B delay + 4 B apodization each)
-        # and two fine-grid values (8 B); per launch also the image (4 B per voxel)
-        return float(n_traces) * n_vox * 32 + 4.0 * n_vox, "byte"
+        return 2.0 * P * K * M * Q * lh, ("mfma" if Q in (32, 64) else "alu")
+    if name == "splat":
+        return float(legs + 4 * N + 4 * nz + fine), "hbm"
+    if name == "gather":
+        return float(legs + 4 * nz + fine + 4 * N * trace_groups), "hbm"
     return None, None
+
+
+def roofline(name, prof, steps, card, n_off, trace_groups):
+    if name not in prof:
+        return None
+    launches, ms = prof[name]
+    avg_s = ms / launches / 1e3
+    amount, bound = kernel_work(name, card, n_off, trace_groups)
+    if bound is None:
+        return None
+    achieved = amount / avg_s
+    peak = PEAK_HBM if bound == "hbm" else PEAK_FP32
+    unit, div = ("GB/s", 1e9) if bound == "hbm" else ("TFLOP/s", 1e12)
+    return {"bound": bound, "achieved": achieved / div, "peak": peak / div, "unit": unit,
+            "frac": achieved / peak, "kernel": name, "avg_launch_us": avg_s * 1e6,
+            "launches_per_step": launches / steps, "work_per_launch": amount,
+            "work_unit": "byte" if bound == "hbm" else "flop"}
 
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -159,24 +236,21 @@ def main():
     t_fwd = ev[0].elapsed_time(ev[1]) / reps / 1e3
     t_adj = ev[1].elapsed_time(ev[2]) / reps / 1e3
 
-    # ---- roofline of the dominant kernel (largest share of the timed region)
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    dname, (dlaunch, dms) = dom
-    avg_s = dms / dlaunch / 1e3
-    amount, kind = kernel_work(dname, card, P * K, N)
-    if kind == "flop":
-        achieved = amount / avg_s
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None}
-    elif kind == "byte":
-        achieved = amount / avg_s
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": None}
-    else:
-        roof = None
+    # ---- rooflines: every sweep kernel, and the dominant one (largest share of the timed region)
+    tg = gm.trace_groups
+    kernels = {k: roofline(k, prof, args.steps, card, gm.n_off, tg) for k in ("splat", "conv", "corr", "gather")}
+    dname = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    roof = kernels.get(dname) or roofline(dname, prof, args.steps, card, gm.n_off, tg)
+    traffic = None
+    try:
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("source_sha256") == source_digest() and dname in tf["kernels"]:
+            t = tf["kernels"][dname]
+            traffic = t["fetch_bytes"] + t["write_bytes"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
     if roof is not None:
-        roof.update({"kernel": dname, "avg_launch_us": avg_s * 1e6, "launches": dlaunch,
-                     "work_per_launch": amount, "work_unit": kind})
+        roof["traffic"] = traffic
 
     out = {
         "metric": "A+Aᵀ voxel-receiver evals/sec",
@@ -204,6 +278,7 @@ def main():
         "cost_first_last": [float(costs[0]), float(costs[-1])],
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items())},
         "roofline": roof,
+        "sweep_kernels": kernels,
     }
 
     if not args.quick:

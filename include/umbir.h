@@ -193,6 +193,7 @@ typedef struct {
     int window;       /* L_h */
     int oversample;   /* Q */
     int n_layers;
+    int trace_groups; /* traces are summed in this many groups by the adjoint's gather */
 } umbir_dims;
 int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
 

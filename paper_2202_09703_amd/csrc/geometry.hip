@@ -490,6 +490,7 @@ int umbir_get_dims(const umbir_geometry* G, umbir_dims* d) {
   d->window = G->Lh;
   d->oversample = G->Q;
   d->n_layers = G->layers.n;
+  d->trace_groups = G->trace_groups;
   return UMBIR_OK;
 }
 

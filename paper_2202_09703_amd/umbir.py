@@ -70,7 +70,7 @@ class _Prior(C.Structure):
 class _Dims(C.Structure):
     _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("n_scans", C.c_int), ("n_rx", C.c_int),
                 ("n_samples", C.c_int), ("n_off", C.c_int), ("window", C.c_int),
-                ("oversample", C.c_int), ("n_layers", C.c_int)]
+                ("oversample", C.c_int), ("n_layers", C.c_int), ("trace_groups", C.c_int)]
 
 
 class _KernelTime(C.Structure):
@@ -175,6 +175,7 @@ class Geometry:
         self.nx, self.nz = d.nx, d.nz
         self.n_scans, self.n_rx, self.n_samples = d.n_scans, d.n_rx, d.n_samples
         self.n_off, self.window, self.oversample, self.n_layers = d.n_off, d.window, d.oversample, d.n_layers
+        self.trace_groups = d.trace_groups
 
     @property
     def handle(self):
