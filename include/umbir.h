@@ -186,6 +186,35 @@ int umbir_reconstruct(const umbir_geometry* geom, const umbir_prior* prior,
                       const float* y_dev, int n_iter, float* x_io_dev, float* g_io_dev,
                       double* cost_dev, void* work, size_t work_bytes, void* stream);
 
+/* Resident MAP solver for one problem (the serving building block): owns a
+ * copy of y, the iterate state (x, g), the data-term curvature, a cost history
+ * of max_iter + 1 entries and its workspace, all allocated at creation, and
+ * one captured HIP graph per iteration so that stepping launches no kernels
+ * individually and allocates nothing.  The iteration is the one of
+ * umbir_reconstruct (Eq. (18), QGGMRF prior of Eqs. (14)-(17)); a session
+ * stepped n times holds bitwise the result of umbir_reconstruct with n
+ * iterations.  The geometry must outlive the session.
+ *
+ * umbir_solver_create: x0_dev ([nz][nx]) and g0_dev ([P][K]) may be NULL
+ *   (zeros); y_dev ([P][K][M]) is copied.  Blocks until the state is ready.
+ * umbir_solver_step: queues n_iter iterations on `stream` (asynchronous);
+ *   EINVAL if the total would exceed max_iter.
+ * umbir_solver_read: queues copies of the current x and g (either may be
+ *   NULL) and, if cost_dev is not NULL, evaluates the cost of the current
+ *   state and copies iterations() + 1 history entries (float64) to cost_dev.
+ * umbir_solver_bytes: device bytes a session would hold (for admission).
+ * One session must not be stepped from two streams at once. */
+typedef struct umbir_solver umbir_solver;
+size_t umbir_solver_bytes(const umbir_geometry* geom, int max_iter);
+int umbir_solver_create(const umbir_geometry* geom, const umbir_prior* prior, const float* y_dev,
+                        const float* x0_dev, const float* g0_dev, int max_iter, void* stream,
+                        umbir_solver** out);
+int umbir_solver_step(umbir_solver* solver, int n_iter, void* stream);
+int umbir_solver_iterations(const umbir_solver* solver);
+int umbir_solver_read(umbir_solver* solver, float* x_dev, float* g_dev, double* cost_dev, void* stream);
+size_t umbir_solver_state_bytes(const umbir_solver* solver);
+void umbir_solver_free(umbir_solver* solver);
+
 /* Dimensions of a built geometry, for callers that size buffers. */
 typedef struct {
     int nx, nz, n_scans, n_rx, n_samples;

@@ -720,9 +720,11 @@ size_t umbir_workspace_bytes(const umbir_geometry* G, int kind) {
     case UMBIR_WORK_FORWARD: return forward_work_bytes(*G);
     case UMBIR_WORK_ADJOINT: return adjoint_work_bytes(*G);
     case UMBIR_WORK_RECONSTRUCT: {
+      // the iteration buffers (fine grid, partial images, residual, A^T e,
+      // curvature, reductions) plus the two images of the ping-pong
       const size_t N = G->voxels(), PK = G->traces();
       const size_t nblk = (N + 255) / 256 + 1;
-      return adjoint_work_bytes(*G) + aligned(PK * G->M * sizeof(float)) + 5 * aligned(N * sizeof(float)) +
+      return adjoint_work_bytes(*G) + aligned(PK * G->M * sizeof(float)) + 4 * aligned(N * sizeof(float)) +
              aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + 16 * 256;
     }
     default: return 0;

@@ -32,6 +32,9 @@ std::map<std::string, Totals> g_totals;
 bool prof_on() { return g_on.load(std::memory_order_relaxed); }
 
 hipEvent_t prof_start(hipStream_t s) {
+  // launches recorded into a graph are not timed (the events would be captured too)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   if (hipEventRecord(e, s) != hipSuccess) {

@@ -149,17 +149,30 @@ __global__ __launch_bounds__(256) void k_prior(const float* __restrict__ x, cons
   if (threadIdx.x == 0) pcost[blockIdx.x] = cost;
 }
 
+// Cost = data term + prior term, written to out[*counter] (then the counter
+// advances) or to out[0] when counter is NULL.  The device-side counter lets a
+// captured iteration graph append to the history wherever it is replayed.
 __global__ __launch_bounds__(256) void k_cost(const double* __restrict__ ess, int n_ess,
                                               const double* __restrict__ pcost, int n_p,
-                                              double inv_2sigma2, double* __restrict__ out) {
+                                              double inv_2sigma2, double* __restrict__ out,
+                                              int* __restrict__ counter) {
   __shared__ double sh[256];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < n_ess; i += blockDim.x) a += ess[i];
   for (int i = threadIdx.x; i < n_p; i += blockDim.x) b += pcost[i];
   a = block_sum(a, sh);
   b = block_sum(b, sh);
-  if (threadIdx.x == 0) *out = a * inv_2sigma2 + b;
+  if (threadIdx.x == 0) {
+    if (counter) {
+      out[*counter] = a * inv_2sigma2 + b;
+      *counter += 1;
+    } else {
+      *out = a * inv_2sigma2 + b;
+    }
+  }
 }
+
+__global__ void k_zero_int(int* p) { *p = 0; }
 
 int validate_prior(const umbir_prior* pr) {
   if (!pr) return fail(UMBIR_EINVAL, "prior is NULL");
@@ -177,14 +190,151 @@ int validate_prior(const umbir_prior* pr) {
 
 size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 
+PriorConst prior_const(const umbir_geometry& G, const umbir_prior& pr) {
+  PriorConst pc;
+  pc.inv_sigma2 = float(1.0 / (pr.sigma * pr.sigma));
+  pc.p = float(pr.p);
+  pc.T = float(pr.T);
+  pc.sigma0 = float(pr.sigma0);
+  pc.m = pr.m;
+  pc.a = pr.a;
+  pc.z0 = G.z0;
+  pc.dz = G.dz;
+  return pc;
+}
+
+// Buffers of one MAP iteration (workspace or resident session state).
+struct IterBuffers {
+  float* fine;
+  float* partial;
+  float* e;
+  float* u;
+  float* den;
+  double* ess;
+  double* pcost;
+  int nblk;
+};
+
+IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
+  const size_t N = G.voxels(), PK = G.traces();
+  IterBuffers b;
+  b.nblk = int((N + 255) / 256);
+  b.fine = cv.take<float>(PK * G.fine_per_trace() + 1);
+  b.partial = cv.take<float>(size_t(G.trace_groups) * N);
+  b.e = cv.take<float>(PK * G.M);
+  b.u = cv.take<float>(N);
+  b.den = cv.take<float>(N);
+  b.ess = cv.take<double>(PK);
+  b.pcost = cv.take<double>(b.nblk);
+  return b;
+}
+
+size_t iter_bytes(const umbir_geometry& G) {
+  const size_t N = G.voxels(), PK = G.traces();
+  return adjoint_work_bytes(G) + aligned(PK * G.M * sizeof(float)) + 2 * aligned(N * sizeof(float)) +
+         aligned(PK * sizeof(double)) + aligned(((N + 255) / 256 + 1) * sizeof(double)) + 8 * 256;
+}
+
+int enqueue_curvature(const umbir_geometry& G, const IterBuffers& b, const PriorConst& pc, hipStream_t s) {
+  int st = run_forward(G, nullptr, b.e, nullptr, 1.0f, nullptr, true, b.fine, s);
+  if (st) return st;
+  return run_adjoint(G, b.e, b.den, pc.inv_sigma2, true, b.fine, b.partial, s);
+}
+
+// One surrogate iteration from x_in to x_out (or, with last, only the cost of
+// x_in); the cost goes to cost_out[*counter] (counter != NULL) or cost_out[0].
+int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const PriorConst& pc, double inv_2s2,
+                      int est, const float* y, const float* x_in, float* x_out, float* g, bool last,
+                      double* cost_out, int* counter, hipStream_t s) {
+  const int PK = G.traces();
+  int st = run_forward(G, x_in, b.e, y, -1.0f, g, false, b.fine, s);
+  if (st) return st;
+  UMBIR_LAUNCH("gstep", k_gstep, dim3(unsigned(PK)), dim3(256), 0, s, b.e, G.dbasis, G.dnorm, g, G.M,
+               last ? 0 : est, b.ess);
+  if ((st = check_hip(hipGetLastError(), "k_gstep"))) return st;
+  if (last) {
+    UMBIR_LAUNCH("prior", k_prior<false>, dim3(b.nblk), dim3(256), 0, s, x_in, nullptr, nullptr, G.nx, G.nz,
+                 pc, nullptr, b.pcost);
+  } else {
+    if ((st = run_adjoint(G, b.e, b.u, 1.0f, false, b.fine, b.partial, s))) return st;
+    UMBIR_LAUNCH("prior", k_prior<true>, dim3(b.nblk), dim3(256), 0, s, x_in, b.u, b.den, G.nx, G.nz, pc,
+                 x_out, b.pcost);
+  }
+  if ((st = check_hip(hipGetLastError(), "k_prior"))) return st;
+  if (cost_out) {
+    UMBIR_LAUNCH("cost", k_cost, dim3(1), dim3(256), 0, s, b.ess, PK, b.pcost, b.nblk, inv_2s2, cost_out,
+                 counter);
+    if ((st = check_hip(hipGetLastError(), "k_cost"))) return st;
+  }
+  return UMBIR_OK;
+}
+
 }  // namespace
 }  // namespace umbir
 
 using namespace umbir;
 
-extern "C" int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const float* y,
-                                 int n_iter, float* x_io, float* g_io, double* cost, void* work,
-                                 size_t work_bytes, void* stream) {
+struct umbir_solver {
+  const umbir_geometry* G = nullptr;
+  umbir_prior prior{};
+  PriorConst pc{};
+  double inv_2s2 = 0.0;
+  int est = 0;
+  int device = -1;
+  int max_iter = 0;
+  int done = 0;     // iterations run so far
+  int parity = 0;   // 0: the current image is xa, 1: xb
+  void* mem = nullptr;
+  size_t bytes = 0;
+  IterBuffers b{};
+  float *y = nullptr, *xa = nullptr, *xb = nullptr, *g = nullptr;
+  double* cost = nullptr;  // [max_iter + 1]
+  int* counter = nullptr;
+  hipStream_t cap = nullptr;       // private stream used to capture the graphs
+  hipGraphExec_t step[2] = {nullptr, nullptr};  // xa -> xb and xb -> xa
+};
+
+namespace {
+
+size_t solver_bytes(const umbir_geometry& G, int max_iter) {
+  const size_t N = G.voxels(), PK = G.traces();
+  return iter_bytes(G) + aligned(PK * G.M * sizeof(float)) + 2 * aligned(N * sizeof(float)) +
+         aligned(PK * sizeof(float)) + aligned((size_t(max_iter) + 1) * sizeof(double)) + aligned(sizeof(int)) +
+         8 * 256;
+}
+
+void solver_release(umbir_solver* S) {
+  if (!S) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (S->device >= 0) (void)hipSetDevice(S->device);
+  for (hipGraphExec_t& ge : S->step)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  if (S->cap) (void)hipStreamDestroy(S->cap);
+  if (S->mem) (void)hipFree(S->mem);
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete S;
+}
+
+int capture_step(umbir_solver* S, const float* x_in, float* x_out, hipGraphExec_t* out) {
+  hipGraph_t graph = nullptr;
+  int st = check_hip(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (st) return st;
+  const int st_enq = enqueue_iteration(*S->G, S->b, S->pc, S->inv_2s2, S->est, S->y, x_in, x_out, S->g, false,
+                                       S->cost, S->counter, S->cap);
+  st = check_hip(hipStreamEndCapture(S->cap, &graph), "hipStreamEndCapture");
+  if (st_enq) st = st_enq;
+  if (!st) st = check_hip(hipGraphInstantiate(out, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (graph) (void)hipGraphDestroy(graph);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const float* y, int n_iter,
+                      float* x_io, float* g_io, double* cost, void* work, size_t work_bytes, void* stream) {
   if (!G || !y || !x_io || !g_io) return fail(UMBIR_EINVAL, "NULL argument");
   if (n_iter < 0) return fail(UMBIR_EINVAL, "n_iter must be >= 0");
   int st = validate_prior(pr);
@@ -192,57 +342,135 @@ extern "C" int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr,
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws;
   if ((st = ws.acquire(work, work_bytes, umbir_workspace_bytes(G, UMBIR_WORK_RECONSTRUCT), s))) return st;
-  const size_t N = G->voxels(), PK = G->traces();
-  const int nblk = int((N + 255) / 256);
+  const size_t N = G->voxels();
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(PK * G->fine_per_trace() + 1);
-  float* partial = cv.take<float>(size_t(G->trace_groups) * N);
-  float* e = cv.take<float>(PK * G->M);
-  float* u = cv.take<float>(N);
-  float* den = cv.take<float>(N);
+  const IterBuffers b = carve_iter(cv, *G);
   float* xa = cv.take<float>(N);
   float* xb = cv.take<float>(N);
-  double* ess = cv.take<double>(PK);
-  double* pcost = cv.take<double>(nblk);
-
-  PriorConst pc;
-  pc.inv_sigma2 = float(1.0 / (pr->sigma * pr->sigma));
-  pc.p = float(pr->p);
-  pc.T = float(pr->T);
-  pc.sigma0 = float(pr->sigma0);
-  pc.m = pr->m;
-  pc.a = pr->a;
-  pc.z0 = G->z0;
-  pc.dz = G->dz;
+  const PriorConst pc = prior_const(*G, *pr);
   const double inv_2s2 = 0.5 / (pr->sigma * pr->sigma);
   const int est = pr->estimate_direct ? 1 : 0;
 
-  // data-term curvature d = |A|^T |A| 1 / sigma^2
-  if ((st = run_forward(*G, nullptr, e, nullptr, 1.0f, nullptr, true, fine, s))) return st;
-  if ((st = run_adjoint(*G, e, den, pc.inv_sigma2, true, fine, partial, s))) return st;
+  if ((st = enqueue_curvature(*G, b, pc, s))) return st;
   if ((st = launch_copy(xa, x_io, N, s))) return st;
-
   for (int it = 0; it <= n_iter; ++it) {
     const bool last = it == n_iter;
-    if ((st = run_forward(*G, xa, e, y, -1.0f, g_io, false, fine, s))) return st;
-    UMBIR_LAUNCH("gstep", k_gstep, dim3(unsigned(PK)), dim3(256), 0, s, e, G->dbasis, G->dnorm, g_io,
-                       G->M, last ? 0 : est, ess);
-    if ((st = check_hip(hipGetLastError(), "k_gstep"))) return st;
-    if (last) {
-      UMBIR_LAUNCH("prior", k_prior<false>, dim3(nblk), dim3(256), 0, s, xa, nullptr, nullptr, G->nx,
-                         G->nz, pc, nullptr, pcost);
-    } else {
-      if ((st = run_adjoint(*G, e, u, 1.0f, false, fine, partial, s))) return st;
-      UMBIR_LAUNCH("prior", k_prior<true>, dim3(nblk), dim3(256), 0, s, xa, u, den, G->nx, G->nz, pc, xb,
-                         pcost);
-    }
-    if ((st = check_hip(hipGetLastError(), "k_prior"))) return st;
-    if (cost) {
-      UMBIR_LAUNCH("cost", k_cost, dim3(1), dim3(256), 0, s, ess, int(PK), pcost, nblk, inv_2s2,
-                         cost + it);
-      if ((st = check_hip(hipGetLastError(), "k_cost"))) return st;
-    }
+    if ((st = enqueue_iteration(*G, b, pc, inv_2s2, est, y, xa, xb, g_io, last, cost ? cost + it : nullptr,
+                                nullptr, s)))
+      return st;
     if (!last) std::swap(xa, xb);
   }
   return launch_copy(x_io, xa, N, s);
 }
+
+size_t umbir_solver_bytes(const umbir_geometry* G, int max_iter) {
+  if (!G || max_iter < 0) return 0;
+  return solver_bytes(*G, max_iter);
+}
+
+int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const float* y_dev,
+                        const float* x0_dev, const float* g0_dev, int max_iter, void* stream,
+                        umbir_solver** out) {
+  if (!out) return fail(UMBIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!G || !y_dev) return fail(UMBIR_EINVAL, "NULL argument");
+  if (max_iter < 0 || max_iter > (1 << 24)) return fail(UMBIR_EINVAL, "max_iter out of range");
+  int st = validate_prior(pr);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* S = new umbir_solver();
+  S->G = G;
+  S->prior = *pr;
+  S->pc = prior_const(*G, *pr);
+  S->inv_2s2 = 0.5 / (pr->sigma * pr->sigma);
+  S->est = pr->estimate_direct ? 1 : 0;
+  S->max_iter = max_iter;
+  (void)hipGetDevice(&S->device);
+  S->bytes = solver_bytes(*G, max_iter);
+  if ((st = check_hip(hipMalloc(&S->mem, S->bytes), "hipMalloc(solver)"))) {
+    S->mem = nullptr;
+    solver_release(S);
+    return st;
+  }
+  const size_t N = G->voxels(), PK = G->traces();
+  Carve cv{static_cast<char*>(S->mem)};
+  S->b = carve_iter(cv, *G);
+  S->y = cv.take<float>(PK * G->M);
+  S->xa = cv.take<float>(N);
+  S->xb = cv.take<float>(N);
+  S->g = cv.take<float>(PK);
+  S->cost = cv.take<double>(size_t(max_iter) + 1);
+  S->counter = cv.take<int>(1);
+  if ((st = check_hip(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking), "hipStreamCreate"))) {
+    S->cap = nullptr;
+    solver_release(S);
+    return st;
+  }
+  // state: copy of y, warm start (or zeros), curvature, cost counter at 0
+  if ((st = launch_copy(S->y, y_dev, PK * G->M, s)) ||
+      (st = x0_dev ? launch_copy(S->xa, x0_dev, N, s) : launch_fill(S->xa, N, 0.0f, s)) ||
+      (st = g0_dev ? launch_copy(S->g, g0_dev, PK, s) : launch_fill(S->g, PK, 0.0f, s)) ||
+      (st = enqueue_curvature(*G, S->b, S->pc, s))) {
+    (void)hipStreamSynchronize(s);
+    solver_release(S);
+    return st;
+  }
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, S->counter);
+  if ((st = check_hip(hipGetLastError(), "k_zero_int")) ||
+      (st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(solver_create)"))) {
+    solver_release(S);
+    return st;
+  }
+  // one iteration graph per direction of the image ping-pong
+  st = capture_step(S, S->xa, S->xb, &S->step[0]);
+  if (!st) st = capture_step(S, S->xb, S->xa, &S->step[1]);
+  if (st) {
+    solver_release(S);
+    return st;
+  }
+  *out = S;
+  return UMBIR_OK;
+}
+
+int umbir_solver_step(umbir_solver* S, int n_iter, void* stream) {
+  if (!S) return fail(UMBIR_EINVAL, "solver is NULL");
+  if (n_iter < 0 || S->done + n_iter > S->max_iter)
+    return fail(UMBIR_EINVAL, "n_iter would exceed the solver's max_iter");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int k = 0; k < n_iter; ++k) {
+    const int st = check_hip(hipGraphLaunch(S->step[S->parity], s), "hipGraphLaunch");
+    if (st) return st;
+    S->parity ^= 1;
+    S->done += 1;
+  }
+  return UMBIR_OK;
+}
+
+int umbir_solver_iterations(const umbir_solver* S) { return S ? S->done : -1; }
+
+int umbir_solver_read(umbir_solver* S, float* x_dev, float* g_dev, double* cost_dev, void* stream) {
+  if (!S) return fail(UMBIR_EINVAL, "solver is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const umbir_geometry& G = *S->G;
+  float* x = S->parity ? S->xb : S->xa;
+  int st;
+  if (cost_dev) {
+    // cost of the current (x, g) into the slot after the history, then copy out
+    if ((st = enqueue_iteration(G, S->b, S->pc, S->inv_2s2, S->est, S->y, x, nullptr, S->g, true,
+                                S->cost + S->done, nullptr, s)))
+      return st;
+    if ((st = check_hip(hipMemcpyAsync(cost_dev, S->cost, (size_t(S->done) + 1) * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s),
+                        "hipMemcpyAsync(cost)")))
+      return st;
+  }
+  if (x_dev && (st = launch_copy(x_dev, x, G.voxels(), s))) return st;
+  if (g_dev && (st = launch_copy(g_dev, S->g, G.traces(), s))) return st;
+  return UMBIR_OK;
+}
+
+size_t umbir_solver_state_bytes(const umbir_solver* S) { return S ? S->bytes : 0; }
+
+void umbir_solver_free(umbir_solver* S) { solver_release(S); }
+
+}  // extern "C"

@@ -91,6 +91,13 @@ _SIGS = {
     "umbir_reconstruct": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "umbir_get_dims": (_i, [_vp, C.POINTER(_Dims)]),
     "umbir_copy_table": (_i, [_vp, _i, _vp, _sz]),
+    "umbir_solver_bytes": (_sz, [_vp, _i]),
+    "umbir_solver_create": (_i, [_vp, C.POINTER(_Prior), _vp, _vp, _vp, _i, _vp, C.POINTER(_vp)]),
+    "umbir_solver_step": (_i, [_vp, _i, _vp]),
+    "umbir_solver_iterations": (_i, [_vp]),
+    "umbir_solver_read": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "umbir_solver_state_bytes": (_sz, [_vp]),
+    "umbir_solver_free": (None, [_vp]),
     "umbir_profile_enable": (None, [_i]),
     "umbir_profile_collect": (_i, [C.POINTER(_KernelTime), _i, C.POINTER(_i)]),
     "umbir_strerror": (C.c_char_p, [_i]),
@@ -317,6 +324,71 @@ def reconstruct(geom: Geometry, prior, sigma: float, y, n_iter: int, x=None, g=N
                                   _ptr(cost, "cost", (n_iter + 1,), torch.float64), wp, wb,
                                   _stream(stream)), "umbir_reconstruct")
     return x, g, cost
+
+
+class Solver:
+    """Resident MAP solver session (umbir_solver_*): state, curvature and one
+    captured graph per iteration live on the device until free()."""
+
+    def __init__(self, geom: Geometry, prior, sigma: float, y, max_iter: int, x0=None, g0=None, stream=None):
+        import torch
+        self.geom = geom
+        self.max_iter = int(max_iter)
+        pr = make_prior(prior, sigma)
+        h = C.c_void_p()
+        _check(_lib.umbir_solver_create(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, torch.float32),
+                                        _ptr(x0, "x0", geom.image_shape, torch.float32),
+                                        _ptr(g0, "g0", geom.trace_shape[:2], torch.float32), self.max_iter,
+                                        _stream(stream), C.byref(h)), "umbir_solver_create")
+        self._h = h
+        self.device = y.device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("solver has been freed")
+        return self._h
+
+    @property
+    def iterations(self) -> int:
+        return int(_lib.umbir_solver_iterations(self.handle))
+
+    @property
+    def bytes(self) -> int:
+        return int(_lib.umbir_solver_state_bytes(self.handle))
+
+    def step(self, n_iter: int, stream=None):
+        _check(_lib.umbir_solver_step(self.handle, int(n_iter), _stream(stream)), "umbir_solver_step")
+
+    def read(self, x=None, g=None, with_cost: bool = True, stream=None):
+        """Queues copies of (x, g) and the cost history; returns device tensors."""
+        import torch
+        geom = self.geom
+        if x is None:
+            x = torch.empty(geom.image_shape, dtype=torch.float32, device=self.device)
+        if g is None:
+            g = torch.empty(geom.trace_shape[:2], dtype=torch.float32, device=self.device)
+        cost = torch.empty(self.iterations + 1, dtype=torch.float64, device=self.device) if with_cost else None
+        _check(_lib.umbir_solver_read(self.handle, _ptr(x, "x", geom.image_shape, torch.float32),
+                                      _ptr(g, "g", geom.trace_shape[:2], torch.float32),
+                                      _ptr(cost, "cost", None, torch.float64) if cost is not None else None,
+                                      _stream(stream)), "umbir_solver_read")
+        return x, g, cost
+
+    def free(self):
+        if self._h:
+            _lib.umbir_solver_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def solver_bytes(geom: Geometry, max_iter: int) -> int:
+    return int(_lib.umbir_solver_bytes(geom.handle, int(max_iter)))
 
 
 def profile_enable(on: bool = True):

@@ -115,3 +115,20 @@ def test_null_arguments():
     lib.umbir_geometry_free(None)
     assert lib.umbir_geometry_bytes(None) == 0
     assert lib.umbir_workspace_bytes(None, 0) == 0
+
+
+def test_solver_arguments_checked_before_any_device_call():
+    lib = umbir._lib
+    fake = C.c_void_p(16)
+    out = C.c_void_p()
+    pr = umbir.make_prior(Prior(), 0.01)
+    assert lib.umbir_solver_create(None, C.byref(pr), fake, None, None, 5, None, C.byref(out)) == umbir.EINVAL
+    assert lib.umbir_solver_create(fake, C.byref(pr), None, None, None, 5, None, C.byref(out)) == umbir.EINVAL
+    assert lib.umbir_solver_create(fake, C.byref(pr), fake, None, None, -1, None, C.byref(out)) == umbir.EINVAL
+    bad = umbir.make_prior(Prior(p=0.9), 0.01)
+    assert lib.umbir_solver_create(fake, C.byref(bad), fake, None, None, 5, None, C.byref(out)) == umbir.EINVAL
+    assert lib.umbir_solver_step(None, 1, None) == umbir.EINVAL
+    assert lib.umbir_solver_read(None, None, None, None, None) == umbir.EINVAL
+    assert lib.umbir_solver_iterations(None) == -1
+    assert lib.umbir_solver_bytes(None, 3) == 0
+    lib.umbir_solver_free(None)

@@ -257,3 +257,47 @@ def test_c2_leg_table(dev, c2geom):
     err = np.max(np.abs(dl[rows] - card.acq.fs * T))
     print(f"c2 max leg delay error {err:.2e} samples")
     assert err < 1e-6
+
+
+# ---- resident solver sessions (captured iteration graphs)
+
+
+def test_solver_session_matches_reconstruct(dev):
+    """A session stepped in chunks, with eager reads and synchronisations between
+    the graph replays, holds bitwise the result of the one-shot reconstruction
+    after every chunk."""
+    card, y, sigma = _recon_case()
+    geom = umbir.build_geometry(card)
+    yt = t32(y, dev)
+    sess = umbir.Solver(geom, card.prior, sigma, yt, max_iter=20)
+    done = 0
+    for chunk in (1, 4, 5, 10):
+        sess.step(chunk)
+        done += chunk
+        xs, gs, cs = sess.read()
+        torch.cuda.synchronize()
+        xr, gr, cr = umbir.reconstruct(geom, card.prior, sigma, yt, done)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, xr) and torch.equal(gs, gr), f"after {done} iterations"
+        assert torch.equal(cs, cr)
+    assert sess.iterations == 20
+    with pytest.raises(umbir.UmbirError):
+        sess.step(1)  # past max_iter
+    sess.free()
+
+
+def test_solver_session_warm_start_and_direct(dev):
+    card = tiny_card(n_layers=3, nx=12, nz=10, n_scans=2, n_rx=3, n_samples=200)
+    x_true, y, sigma = odata.synthesize(card)
+    y = y + oo.apply_direct(card, np.array([[0.5, -0.3, 0.8], [0.2, 0.9, -0.4]]))
+    geom = umbir.build_geometry(card)
+    yt = t32(y, dev)
+    x4, g4, _ = umbir.reconstruct(geom, card.prior, sigma, yt, 4)
+    sess = umbir.Solver(geom, card.prior, sigma, yt, max_iter=4, x0=x4.clone(), g0=g4.clone())
+    sess.step(4)
+    xs, gs, cs = sess.read()
+    x8, g8, c8 = umbir.reconstruct(geom, card.prior, sigma, yt, 8)
+    assert torch.equal(xs, x8) and torch.equal(gs, g8)
+    assert torch.equal(cs, c8[4:])
+    xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
+    assert rel(xs.cpu().numpy(), xo) <= 1e-4
