@@ -16,6 +16,7 @@
 // is stationary in kappa there, so the last-bit error of the search does not
 // reach T to first order.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -231,16 +232,17 @@ int validate(const umbir_problem* pb, Derived* dv) {
   return UMBIR_OK;
 }
 
-// Trace groups of the voxel-parallel gather: enough workgroups to fill the
-// chip, and a multiple of the 8 XCDs when there are enough traces, because
-// group g runs on XCD g mod 8 (it is the fastest-varying block index).
+// Trace groups of the adjoint's gather: the gather runs one generation of at
+// most 1024 blocks (groups x voxel blocks of 1024 voxels), so the voxel block
+// count fixes how many groups fit; groups are a multiple of the 8 XCDs when
+// there are enough traces, because group g runs on XCD g mod 8 (it is the
+// fastest-varying block index).
 int choose_trace_groups(int n_vox, int n_traces) {
-  const int vox_blocks = (n_vox + 255) / 256;
-  int g = (2048 + vox_blocks - 1) / vox_blocks;
-  if (n_traces >= 8) g = (g + 7) / 8 * 8;
+  const int vox_blocks = (n_vox + 1023) / 1024;
+  int g = std::max(1, 1024 / vox_blocks);
+  if (n_traces >= 8) g = std::max(8, g / 8 * 8);
   if (g > n_traces) g = n_traces;
-  if (g < 1) g = 1;
-  return g;
+  return std::max(g, 1);
 }
 
 size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh) {

@@ -200,44 +200,87 @@ __global__ __launch_bounds__(256) void k_splat(
   }
 }
 
-// S^T: thread = voxel (row-major: neighbouring threads read neighbouring leg
-// records), summing over the traces of group blockIdx.x; one partial image per
-// group, summed in a fixed order by k_reduce_groups.  The group is the fastest
-// block index, so group g stays on XCD g mod 8 and that XCD's L2 holds the
-// fine-grid data of its own traces only.
-template <bool ABSW>
+// S^T: per voxel, sum over the traces of group blockIdx.x of W ((1 - phi) c[J]
+// + phi c[J + 1]); one partial image per group, summed in a fixed order by
+// k_reduce_groups.  The group is the fastest block index, so group g runs on
+// XCD g mod 8 and that XCD's L2 only ever holds its own traces' fine-grid
+// data.  One launch covers a small batch of each group's traces (about 2 MB of
+// fine-grid data per XCD, so the batch stays in L2 while every block of the
+// XCD reads it; blocks cannot be kept in step within a launch, but launch
+// boundaries are barriers), and the partial images accumulate across launches
+// in a fixed order.  The grid is one generation (at most four blocks per CU).  A thread accumulates VPT voxels (row-major, so
+// neighbouring threads read neighbouring leg records) with all their loads for
+// one trace in flight together; blocks take chunks of 256 VPT voxels in the
+// same order.
+template <bool ABSW, int VPT>
 __global__ __launch_bounds__(256) void k_gather(
     const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
-    int tpg, float* __restrict__ partial) {
-  const int v = blockIdx.y * blockDim.x + threadIdx.x;
+    int tpg, int t_off, int t_cnt, int vox_per_block, float* __restrict__ partial) {
   const int N = nx * nz;
-  if (v >= N) return;
-  const int row = v / nx, col = v - row * nx;
-  const Leg* lrow = legs + size_t(row) * n_off;
+  const int v_begin = blockIdx.y * vox_per_block;
+  const int v_end = min(N, v_begin + vox_per_block);
   const int PK = P * K;
-  const int t0 = blockIdx.x * tpg;
-  const int t1 = min(t0 + tpg, PK);
+  // this launch covers traces [t_off, t_off + t_cnt) of each group; the first
+  // launch writes the partial image, later ones add to it
+  const int g_end = min((blockIdx.x + 1) * tpg, PK);
+  const int t0 = blockIdx.x * tpg + t_off;
+  const int t1 = min(t0 + t_cnt, g_end);
+  if (t0 >= t1 && t_off > 0) return;  // uniform over the block: nothing to add
   const int sh = 32 - qs;
   const int half = n_off / 2;
-  float acc = 0.0f;
-  for (int t = t0; t < t1; ++t) {
-    const Leg a = lrow[leg_slot(abs(base[t / K] + 2 * col), half)];
-    const Leg b = lrow[leg_slot(abs(base[P + t] + 2 * col), half)];
-    const uint64_t D = uint64_t(a.delay + b.delay);
-    const int J = int(D >> sh);
-    const float phi = float(uint32_t(D) << qs) * kTwoM32;
-    float w = a.apod * b.apod;
-    if (ABSW) w = fabsf(w);
-    const float* c = fine + size_t(t) * MQ;
-    // unsigned compares: a position past 2^31 (never reached by a valid record) reads nothing
-    const float c0 = unsigned(J) < unsigned(MQ) ? c[J] : 0.0f;
-    const float c1 = unsigned(J + 1) < unsigned(MQ) ? c[J + 1] : 0.0f;
-    acc = fmaf(w, fmaf(phi, c1 - c0, c0), acc);
+  for (int vc = v_begin; vc < v_end; vc += blockDim.x * VPT) {
+    int col[VPT];
+    const Leg* lrow[VPT];
+    bool ok[VPT];
+    float acc[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int v = vc + u * blockDim.x + threadIdx.x;
+      ok[u] = v < v_end;
+      const int vv = ok[u] ? v : v_begin;
+      const int row = vv / nx;
+      col[u] = vv - row * nx;
+      lrow[u] = legs + size_t(row) * n_off;
+      acc[u] = 0.0f;
+    }
+    for (int t = t0; t < t1; ++t) {
+      const int btx = base[t / K], brx = base[P + t];
+      const float* c = fine + size_t(t) * MQ;
+      Leg a[VPT], b[VPT];
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        a[u] = lrow[u][leg_slot(abs(btx + 2 * col[u]), half)];
+        b[u] = lrow[u][leg_slot(abs(brx + 2 * col[u]), half)];
+      }
+      float c0[VPT], c1[VPT];
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int J = int(uint64_t(a[u].delay + b[u].delay) >> sh);
+        // unsigned compares: a position past 2^31 (never reached by a valid record) reads nothing
+        c0[u] = unsigned(J) < unsigned(MQ) ? c[J] : 0.0f;
+        c1[u] = unsigned(J + 1) < unsigned(MQ) ? c[J + 1] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const uint64_t D = uint64_t(a[u].delay + b[u].delay);
+        const float phi = float(uint32_t(D) << qs) * kTwoM32;
+        float w = a[u].apod * b[u].apod;
+        if (ABSW) w = fabsf(w);
+        acc[u] = fmaf(w, fmaf(phi, c1[u] - c0[u], c0[u]), acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int v = vc + u * blockDim.x + threadIdx.x;
+      if (ok[u]) {
+        float tr = tau[v / nx];
+        if (ABSW) tr = fabsf(tr);
+        float* pv = partial + size_t(blockIdx.x) * N + v;
+        *pv = t_off == 0 ? acc[u] * tr : fmaf(acc[u], tr, *pv);
+      }
+    }
   }
-  float tr = tau[row];
-  if (ABSW) tr = fabsf(tr);
-  partial[size_t(blockIdx.x) * N + v] = acc * tr;
 }
 
 __global__ void k_reduce_groups(const float* __restrict__ partial, int groups, int N, float scale,
@@ -695,13 +738,27 @@ int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale
   int st = check_hip(hipGetLastError(), "k_corr");
   if (st) return st;
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
-  dim3 grid(G.trace_groups, (G.voxels() + 255) / 256);
-  if (abs_op)
-    UMBIR_LAUNCH("gather", k_gather<true>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs, G.tau,
-                 G.base, G.P, G.K, qs, int(MQ), tpg, partial);
-  else
-    UMBIR_LAUNCH("gather", k_gather<false>, grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs, G.tau,
-                 G.base, G.P, G.K, qs, int(MQ), tpg, partial);
+  // one generation: at most 1024 blocks (four per CU), chunks of 256 * 4 voxels
+  constexpr int VPT = 4;
+  const int chunk = 256 * VPT;
+  int nb = (G.voxels() + chunk - 1) / chunk;
+  nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
+  const int vpb = (G.voxels() + nb - 1) / nb;
+  dim3 grid(G.trace_groups, nb);
+  // traces per launch: all of a group when its fine-grid data fit the XCD's L2
+  // twice over, else batches of about 2 MB
+  const size_t trace_bytes = size_t(MQ) * sizeof(float);
+  const int batch = size_t(tpg) * trace_bytes <= (size_t(8) << 20)
+                        ? tpg
+                        : std::max(1, std::min(tpg, int((size_t(2) << 20) / trace_bytes)));
+  for (int t_off = 0; t_off < tpg; t_off += batch) {
+    if (abs_op)
+      UMBIR_LAUNCH("gather", (k_gather<true, VPT>), grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs,
+                   G.tau, G.base, G.P, G.K, qs, int(MQ), tpg, t_off, batch, vpb, partial);
+    else
+      UMBIR_LAUNCH("gather", (k_gather<false, VPT>), grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs,
+                   G.tau, G.base, G.P, G.K, qs, int(MQ), tpg, t_off, batch, vpb, partial);
+  }
   if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
                G.trace_groups, G.voxels(), scale, out);

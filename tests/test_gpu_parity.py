@@ -301,3 +301,36 @@ def test_solver_session_warm_start_and_direct(dev):
     assert torch.equal(cs, c8[4:])
     xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
     assert rel(xs.cpu().numpy(), xo) <= 1e-4
+
+
+# ---- full-size 512x512 four-layer workload (2048 traces, 4096 samples): sampled outputs
+
+
+@pytest.fixture(scope="module")
+def c3geom(dev):
+    from synth import card_c3
+    card = card_c3()
+    return card, umbir.build_geometry(card)
+
+
+def test_c3_forward_and_adjoint_sampled(dev, c3geom):
+    card, geom = c3geom
+    x = phantom(card)
+    y = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+    traces = [(5, 3), (40, 30)]
+    ref = oo.forward(card, x, traces=traces)
+    for i, j in traces:
+        e = rel(y[i, j], ref[i, j])
+        print(f"c3 forward trace ({i},{j}) rel L2 {e:.2e}")
+        assert e <= TOL
+    r = random_vector(geom.trace_shape, seed=61)
+    xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy().reshape(-1)
+    vox = np.random.default_rng(7).choice(card.n_voxels, 6, replace=False)
+    refa = oo.adjoint_voxels(card, r, vox)
+    e = rel(xa[vox], refa)
+    print(f"c3 adjoint sampled rel L2 {e:.2e}")
+    assert e <= TOL
+    xr = random_vector((card.grid.nz, card.grid.nx), seed=62)
+    ax = umbir.forward(geom, t32(xr, dev)).cpu().numpy().astype(np.float64)
+    lhs, rhs = float(np.sum(ax * r)), float(np.sum(xr.reshape(-1) * xa))
+    assert abs(lhs - rhs) <= TOL * np.linalg.norm(ax) * np.linalg.norm(r)
