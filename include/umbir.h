@@ -16,7 +16,8 @@
  *    for the calling thread's last failure.
  *  - Device pointers ("_dev") are HIP device memory on the device that was
  *    current when the geometry was built; the caller owns them.  All device
- *    arrays are dense, row-major float32 unless stated.
+ *    arrays are dense and row-major.  Images and g are float32; trace buffers
+ *    (void*) hold the problem's storage type (umbir_acq.storage).
  *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
  *    Every call except umbir_build_geometry is asynchronous in stream order.
  *  - Argument checks (null pointers, sizes, parameter ranges) run before any
@@ -91,7 +92,13 @@ typedef struct {
  * open window (0, t_win).  L_h = t_win * fs must be an integer >= 2.  The
  * windowed response is tabulated once on a grid `oversample` (Q) times finer
  * than the sampling grid and interpolated linearly between grid points;
- * Q must be a power of two in 1..64. */
+ * Q must be a power of two in 1..64.
+ * `storage` is the element type of every trace buffer (y, r, residuals), of
+ * the tabulated pulse as the sweeps use it and of the fine-grid workspace:
+ * UMBIR_STORAGE_F32, _F16 (IEEE half) or _BF16 (bfloat16, passed as 16-bit
+ * words).  Images, direct-arrival weights and all accumulation stay FP32 and
+ * the leg search FP64 in every mode.  16-bit storage needs Q = 32 or 64. */
+enum { UMBIR_STORAGE_F32 = 0, UMBIR_STORAGE_F16 = 1, UMBIR_STORAGE_BF16 = 2 };
 typedef struct {
     int n_samples;             /* M >= 1 */
     double fs;                 /* sampling rate [Hz] */
@@ -99,6 +106,7 @@ typedef struct {
     double sigma_t;            /* Gaussian width [s] */
     double t_win;              /* window t_0 of Eq. (10) [s] */
     int oversample;            /* Q */
+    int storage;               /* UMBIR_STORAGE_* */
 } umbir_acq;
 
 typedef struct {
@@ -152,19 +160,19 @@ size_t umbir_workspace_bytes(const umbir_geometry* geom, int kind);
  * linearly interpolated h~, W = tau(v) phi^(beta)(v).  Scan positions are
  * separate firings stacked as rows of y.  x_dev: [nz][nx]; y_dev: [P][K][M].
  * Deterministic: the same inputs give bitwise the same output. */
-int umbir_forward(const umbir_geometry* geom, const float* x_dev, float* y_dev,
+int umbir_forward(const umbir_geometry* geom, const float* x_dev, void* y_dev,
                   int accumulate, void* work, size_t work_bytes, void* stream);
 
 /* x = A^T r, the exact transpose of umbir_forward (same W, delays and
  * interpolation).  r_dev: [P][K][M]; x_dev: [nz][nx].  Deterministic: the
  * same inputs give bitwise the same output. */
-int umbir_adjoint(const umbir_geometry* geom, const float* r_dev, float* x_dev,
+int umbir_adjoint(const umbir_geometry* geom, const void* r_dev, float* x_dev,
                   void* work, size_t work_bytes, void* stream);
 
 /* y = D g (accumulate == 0) or y += D g: column (i, j) of D is the tabulated
  * pulse delayed by the direct path |x_rx - x_tx| / c_1 in layer 0 (Eq. (1)).
  * g_dev: [P][K]; y_dev: [P][K][M]. */
-int umbir_direct(const umbir_geometry* geom, const float* g_dev, float* y_dev,
+int umbir_direct(const umbir_geometry* geom, const float* g_dev, void* y_dev,
                  int accumulate, void* stream);
 
 /* d = |A|^T |A| 1 / sigma^2, the separable-surrogate curvature of the data
@@ -183,7 +191,7 @@ int umbir_sqs_denominator(const umbir_geometry* geom, double sigma, float* d_dev
  * Errors: EINVAL (prior), ENOMEM, EDEVICE.  Cost divergence is not checked
  * on the device (the call stays asynchronous); callers compare cost_dev. */
 int umbir_reconstruct(const umbir_geometry* geom, const umbir_prior* prior,
-                      const float* y_dev, int n_iter, float* x_io_dev, float* g_io_dev,
+                      const void* y_dev, int n_iter, float* x_io_dev, float* g_io_dev,
                       double* cost_dev, void* work, size_t work_bytes, void* stream);
 
 /* Resident MAP solver for one problem (the serving building block): owns a
@@ -206,7 +214,7 @@ int umbir_reconstruct(const umbir_geometry* geom, const umbir_prior* prior,
  * One session must not be stepped from two streams at once. */
 typedef struct umbir_solver umbir_solver;
 size_t umbir_solver_bytes(const umbir_geometry* geom, int max_iter);
-int umbir_solver_create(const umbir_geometry* geom, const umbir_prior* prior, const float* y_dev,
+int umbir_solver_create(const umbir_geometry* geom, const umbir_prior* prior, const void* y_dev,
                         const float* x0_dev, const float* g0_dev, int max_iter, void* stream,
                         umbir_solver** out);
 int umbir_solver_step(umbir_solver* solver, int n_iter, void* stream);
@@ -223,6 +231,7 @@ typedef struct {
     int oversample;   /* Q */
     int n_layers;
     int trace_groups; /* traces are summed in this many groups by the adjoint's gather */
+    int storage;      /* UMBIR_STORAGE_* of trace buffers */
 } umbir_dims;
 int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
 

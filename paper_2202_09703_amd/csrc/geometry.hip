@@ -200,6 +200,10 @@ int validate(const umbir_problem* pb, Derived* dv) {
     return fail(UMBIR_EINVAL, "t_win * fs must be an integer >= 2");
   if (q.oversample < 1 || q.oversample > 64 || (q.oversample & (q.oversample - 1)))
     return fail(UMBIR_ENOTSUP, "oversample must be a power of two in 1..64");
+  if (q.storage != UMBIR_STORAGE_F32 && q.storage != UMBIR_STORAGE_F16 && q.storage != UMBIR_STORAGE_BF16)
+    return fail(UMBIR_EINVAL, "storage must be UMBIR_STORAGE_F32, _F16 or _BF16");
+  if (q.storage != UMBIR_STORAGE_F32 && q.oversample != 32 && q.oversample != 64)
+    return fail(UMBIR_ENOTSUP, "16-bit storage needs oversample 32 or 64");
   // the dense kernels stage the taps, padded to a multiple of 16 rows, in 64 KiB of LDS
   if ((lhi + 15) / 16 * 16 * q.oversample > 16384)
     return fail(UMBIR_ENOTSUP, "window (rounded up to 16) * oversample must be <= 16384");
@@ -367,6 +371,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   G->rx_off.assign(pb->array.rx_offset, pb->array.rx_offset + G->K);
   G->M = pb->acq.n_samples;
   G->Q = pb->acq.oversample;
+  G->storage = pb->acq.storage;
   G->Lh = dv.Lh;
   G->fs = pb->acq.fs;
   G->f_c = pb->acq.f_c;
@@ -493,6 +498,7 @@ int umbir_get_dims(const umbir_geometry* G, umbir_dims* d) {
   d->oversample = G->Q;
   d->n_layers = G->layers.n;
   d->trace_groups = G->trace_groups;
+  d->storage = G->storage;
   return UMBIR_OK;
 }
 

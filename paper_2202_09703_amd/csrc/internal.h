@@ -92,6 +92,7 @@ struct umbir_geometry {
   int M = 0, Q = 0, Lh = 0;
   double fs = 0, f_c = 0, sigma_t = 0, t_win = 0;
   // derived
+  int storage = UMBIR_STORAGE_F32;  // element type of traces, fine grid and taps in the sweeps
   int n_off = 0;        // lattice positions per leg-table row
   int trace_groups = 1; // traces are split into this many groups in voxel-parallel kernels
   // rows of each layer: [seg_lo[s], seg_hi[s]) for the n_seg layers the grid reaches;
@@ -117,6 +118,10 @@ struct umbir_geometry {
   int traces() const { return P * K; }
   int voxels() const { return nx * nz; }
   size_t fine_per_trace() const { return size_t(M) * Q; }
+  size_t elem() const { return storage == UMBIR_STORAGE_F32 ? 4 : 2; }
+  // fine-grid workspace: P K M Q elements, then one 32-bit scalar
+  size_t fine_bytes() const { return ((size_t(traces()) * fine_per_trace() * elem() + 15) & ~size_t(15)) + 16; }
+  size_t trace_bytes() const { return size_t(traces()) * M * elem(); }
 };
 
 namespace umbir {
@@ -126,13 +131,17 @@ int launch_fill(float* p, size_t n, float v, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 
 // y = base + sign * A x - g D   (base, g may be NULL; x NULL means all ones).
-// `abs_op` builds the operator from |W| and |h|.  fine: P*K*M*Q floats.
-int run_forward(const umbir_geometry& G, const float* x, float* out, const float* base,
-                float sign, const float* g, bool abs_op, float* fine, hipStream_t s);
+// `abs_op` builds the operator from |W| and |h|.  Trace buffers (out, base) hold
+// the geometry's storage type; fine: G.fine_bytes() of workspace.
+int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base,
+                float sign, const float* g, bool abs_op, void* fine, hipStream_t s);
 
-// out = scale * A^T r.  fine: P*K*M*Q floats; partial: trace_groups * N floats.
-int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale, bool abs_op,
-                float* fine, float* partial, hipStream_t s);
+// out = scale * A^T r (r in the storage type).  partial: trace_groups * N floats.
+int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
+                void* fine, float* partial, hipStream_t s);
+
+// y = D g (or y += D g), y in the storage type.
+int launch_direct(const umbir_geometry& G, const float* g, void* y, int accumulate, hipStream_t s);
 
 size_t forward_work_bytes(const umbir_geometry& G);
 size_t adjoint_work_bytes(const umbir_geometry& G);

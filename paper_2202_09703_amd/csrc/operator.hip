@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "storage.h"
 
 namespace umbir {
 namespace {
@@ -100,12 +101,12 @@ __device__ __forceinline__ int splat_exponent(unsigned maxbits, int n_vox) {
 // on the order of the adds, so the result is bitwise reproducible), scaled by
 // 2^k from splat_exponent.  x == NULL means x = 1.  Tiles are written out
 // whole (coalesced), so the fine buffer needs no clearing.
-template <bool ABSW>
+template <bool ABSW, int ST>
 __global__ __launch_bounds__(256) void k_splat(
     const float* __restrict__ x, int nx, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
     Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
-    float* __restrict__ fine) {
+    typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
   unsigned long long* tile = smem;                                   // [tile_bins + 1]
   int* ptr = reinterpret_cast<int*>(smem + ((tile_bins + 2) & ~1));  // [seg.n][nx]
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256) void k_splat(
   const int brx = base[P + ij];
   const int half = n_off / 2;
   const int sh = 32 - qs;  // J = (D_tx + D_rx) >> (32 - log2 Q)
-  float* out = fine + size_t(ij) * MQ;
+  typename Store<ST>::T* out = fine + size_t(ij) * MQ;
 
   // first row of each (column, layer) whose position is >= J_begin - 1
   for (int c = threadIdx.x; c < nx; c += blockDim.x) {
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(256) void k_splat(
     }
     __syncthreads();
     const int n = J1 - J0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) out[J0 + k] = ldexpf(float((long long)tile[k]), -kx);
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+      out[J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[k]), -kx));
     __syncthreads();
     const unsigned long long carry = tile[n];
     __syncthreads();
@@ -212,9 +214,9 @@ __global__ __launch_bounds__(256) void k_splat(
 // neighbouring threads read neighbouring leg records) with all their loads for
 // one trace in flight together; blocks take chunks of 256 VPT voxels in the
 // same order.
-template <bool ABSW, int VPT>
+template <bool ABSW, int VPT, int ST>
 __global__ __launch_bounds__(256) void k_gather(
-    const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
     int tpg, int t_off, int t_cnt, int vox_per_block, float* __restrict__ partial) {
   const int N = nx * nz;
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(256) void k_gather(
     }
     for (int t = t0; t < t1; ++t) {
       const int btx = base[t / K], brx = base[P + t];
-      const float* c = fine + size_t(t) * MQ;
+      const typename Store<ST>::T* c = fine + size_t(t) * MQ;
       Leg a[VPT], b[VPT];
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
@@ -258,8 +260,8 @@ __global__ __launch_bounds__(256) void k_gather(
       for (int u = 0; u < VPT; ++u) {
         const int J = int(uint64_t(a[u].delay + b[u].delay) >> sh);
         // unsigned compares: a position past 2^31 (never reached by a valid record) reads nothing
-        c0[u] = unsigned(J) < unsigned(MQ) ? c[J] : 0.0f;
-        c1[u] = unsigned(J + 1) < unsigned(MQ) ? c[J + 1] : 0.0f;
+        c0[u] = unsigned(J) < unsigned(MQ) ? Store<ST>::get(c[J]) : 0.0f;
+        c1[u] = unsigned(J + 1) < unsigned(MQ) ? Store<ST>::get(c[J + 1]) : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
@@ -584,12 +586,196 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   }
 }
 
+// C on the matrix cores with 16-bit storage (Q in {32, 64}): as k_conv_mfma,
+// with v_mfma_f32_32x32x8 {f16, bf16}: each lane holds four consecutive
+// (n, t) values of A (taps of one row, read as one 8-byte LDS word) and of B
+// (one staged trace).  Taps are converted to the storage type while staged.
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_conv_mfma16(const typename Store<ST>::T* __restrict__ fine,
+                                                     const float* __restrict__ hq, int M, int Lh, int PK,
+                                                     const typename Store<ST>::T* base, float sign,
+                                                     const float* __restrict__ g,
+                                                     const float* __restrict__ dbasis,
+                                                     typename Store<ST>::T* out) {
+  using T = typename Store<ST>::T;
+  constexpr int CK = 64;       // (n, t) pairs per chunk
+  constexpr int CN = CK / Q;   // rows n per chunk
+  constexpr int TS = Q + 4;    // tap row stride (8-byte aligned rows)
+  constexpr int SB = CK + 4;   // staged row stride
+  extern __shared__ __align__(16) char smc[];
+  T* taps = reinterpret_cast<T*>(smc);                               // [Lh][TS]
+  T* stage = taps + ((Lh * TS + 7) & ~7);                            // [4 waves][32 traces][SB]
+  float* red = reinterpret_cast<float*>(stage);                       // reused at the end
+  const int tr0 = blockIdx.x * 32;
+  const int m0 = blockIdx.y * 32;
+  const long MQ = long(M) * Q;
+  for (int i = threadIdx.x; i < Lh * TS; i += blockDim.x) {
+    const int k = i / TS, t = i - k * TS;
+    taps[i] = Store<ST>::put(t < Q ? hq[k * Q + t] : 0.0f);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  T* st = stage + wave * 32 * SB;
+  const int n_lo = max(0, m0 - Lh);
+  const int n_hi = min(M, m0 + 31);
+  const int n_chunks = (max(0, n_hi - n_lo) + CN - 1) / CN;
+  const int rounds = (n_chunks + 3) / 4;
+  floatx16 acc[2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.0f;
+  // B chunk of one wave: 32 traces x 64 values = 32 x 128 bytes; 8 lanes x 16 bytes per
+  // trace, 8 traces per load instruction, 4 instructions; prefetched one chunk ahead
+  const int sub = lane & 7, tq = lane >> 3;
+  uint4 pre[4];
+  auto fetch = [&](int ch) {
+    const int nc = n_lo + ch * CN;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tr = u * 8 + tq;
+      const int kp = sub * 8;  // first of eight consecutive (n, t) values
+      const int n = nc + kp / Q;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (ch < n_chunks && n < n_hi && tr0 + tr < PK)
+        v = *reinterpret_cast<const uint4*>(fine + size_t(tr0 + tr) * MQ + size_t(nc) * Q + kp);
+      pre[u] = v;
+    }
+  };
+  const int m = m0 + li;
+  __syncthreads();  // taps staged
+  fetch(wave);
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int ch = rd * 4 + wave;
+    const int nc = n_lo + ch * CN;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      uint2* d = reinterpret_cast<uint2*>(st + (u * 8 + tq) * SB + sub * 8);
+      d[0] = make_uint2(pre[u].x, pre[u].y);
+      d[1] = make_uint2(pre[u].z, pre[u].w);
+    }
+    __builtin_amdgcn_wave_barrier();  // the staging buffer is private to this wave
+    fetch(ch + 4);
+    if (ch < n_chunks) {
+      const T* trow[CN];
+      bool tok[CN];
+#pragma unroll
+      for (int r = 0; r < CN; ++r) {
+        const int k = m - 1 - nc - r;
+        tok[r] = k >= 0 && k < Lh;
+        trow[r] = taps + (tok[r] ? k : 0) * TS + 4 * lk - r * Q;
+      }
+      const T* srow = st + li * SB + 4 * lk;
+#pragma unroll
+      for (int kk = 0; kk < CK; kk += 8) {
+        const int r = kk / Q;  // compile-time: kk + 4 lk + 3 stays in row kk / Q
+        uint2 av = *reinterpret_cast<const uint2*>(trow[r] + kk);
+        if (!tok[r]) av = make_uint2(0u, 0u);
+        const uint2 bv = *reinterpret_cast<const uint2*>(srow + kk);
+        acc[(kk >> 3) & 1] = Store<ST>::mfma(av, bv, acc[(kk >> 3) & 1]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[0][i] += acc[1][i];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
+    red[(wave * 32 + row) * 33 + li] = acc[0][i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int col = e >> 5, row = e & 31;
+    const int mm = m0 + row, tr = tr0 + col;
+    if (mm < M && tr < PK) {
+      const float v = red[(0 * 32 + row) * 33 + col] + red[(1 * 32 + row) * 33 + col] +
+                      red[(2 * 32 + row) * 33 + col] + red[(3 * 32 + row) * 33 + col];
+      const size_t idx = size_t(tr) * M + mm;
+      float val = sign * v;
+      if (base) val += Store<ST>::get(base[idx]);
+      if (g) val -= g[tr] * dbasis[idx];
+      out[idx] = Store<ST>::put(val);
+    }
+  }
+}
+
+// C^T on the matrix cores with 16-bit storage: as k_corr_mfma with
+// v_mfma_f32_32x32x8 {f16, bf16}.  A = Hankel rows: the trace segment is kept
+// as overlapping quads q[j] = (r[j], r[j+1], r[j+2], r[j+3]) so every lane's
+// four consecutive values are one aligned 8-byte LDS word; B = taps stored
+// transposed [t][k] for the same reason.
+template <int QT, int NT, int ST>
+__global__ __launch_bounds__(256) void k_corr_mfma16(const typename Store<ST>::T* __restrict__ rt,
+                                                     const float* __restrict__ hq, int M, int Lh,
+                                                     typename Store<ST>::T* __restrict__ fine) {
+  using T = typename Store<ST>::T;
+  constexpr int Q = 32 * QT;
+  constexpr int ROWS = 4 * NT * 32;
+  extern __shared__ __align__(16) char smc[];
+  const int L8 = (Lh + 7) & ~7;    // taps padded to a multiple of the K step
+  const int KS = L8 + 4;           // transposed tap row stride
+  T* tapsT = reinterpret_cast<T*>(smc);                                    // [Q][KS]
+  uint2* quad = reinterpret_cast<uint2*>(tapsT + ((Q * KS + 3) & ~3));     // [ROWS + L8]
+  const int ij = blockIdx.x;
+  const int n_blk = blockIdx.y * ROWS;
+  const T* r = rt + size_t(ij) * M;
+  for (int i = threadIdx.x; i < Q * KS; i += blockDim.x) {
+    const int t = i / KS, k = i - t * KS;
+    tapsT[i] = Store<ST>::put(k < Lh ? hq[k * Q + t] : 0.0f);
+  }
+  for (int j = threadIdx.x; j < ROWS + L8; j += blockDim.x) {
+    T v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int mm = n_blk + 1 + j + e;
+      v[e] = mm < M ? r[mm] : Store<ST>::put(0.0f);
+    }
+    uint2 w;
+    __builtin_memcpy(&w, v, 8);
+    quad[j] = w;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  floatx16 acc[NT][QT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < QT; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+  const int row0 = wave * NT * 32;
+  for (int k0 = 0; k0 < L8; k0 += 8) {
+    uint2 bv[QT];
+#pragma unroll
+    for (int b = 0; b < QT; ++b) bv[b] = *reinterpret_cast<const uint2*>(tapsT + (b * 32 + li) * KS + k0 + 4 * lk);
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const uint2 av = quad[row0 + a * 32 + li + k0 + 4 * lk];
+#pragma unroll
+      for (int b = 0; b < QT; ++b) acc[a][b] = Store<ST>::mfma(av, bv[b], acc[a][b]);
+    }
+  }
+  T* c = fine + size_t(ij) * M * Q;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int n = n_blk + row0 + a * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
+      if (n < M) {
+#pragma unroll
+        for (int b = 0; b < QT; ++b) c[size_t(n) * Q + b * 32 + li] = Store<ST>::put(acc[a][b][i]);
+      }
+    }
+}
+
+template <int ST>
 __global__ void k_direct(const float* __restrict__ g, const float* __restrict__ dbasis, int M,
-                         size_t total, int accumulate, float* __restrict__ y) {
+                         size_t total, int accumulate, typename Store<ST>::T* __restrict__ y) {
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < total; k += stride) {
     const float v = g[k / M] * dbasis[k];
-    y[k] = accumulate ? y[k] + v : v;
+    y[k] = Store<ST>::put(accumulate ? Store<ST>::get(y[k]) + v : v);
   }
 }
 
@@ -607,7 +793,7 @@ void launch_conv_q(const umbir_geometry& G, const float* fine, const float* hq, 
   const int LhP = lh_pad(G.Lh);
   dim3 grid(G.traces(), (G.M + per_block - 1) / per_block);
   UMBIR_LAUNCH("conv", k_conv<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, fine, hq, G.M,
-                     G.Lh, LhP, base, sign, g, G.dbasis, out);
+               G.Lh, LhP, base, sign, g, G.dbasis, out);
 }
 
 template <int Q>
@@ -617,7 +803,7 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
   const int LhP = lh_pad(G.Lh);
   dim3 grid(G.traces(), (G.M + per_block - 1) / per_block);
   UMBIR_LAUNCH("corr", k_corr<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, r, hq, G.M,
-                     G.Lh, LhP, fine);
+               G.Lh, LhP, fine);
 }
 
 template <int Q>
@@ -630,8 +816,31 @@ void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* h
                sign, g, G.dbasis, out);
 }
 
-void launch_conv(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
-                 float sign, const float* g, float* out, hipStream_t s) {
+template <int Q, int ST>
+void launch_conv_mfma16(const umbir_geometry& G, const void* fine, const float* hq, const void* base,
+                        float sign, const float* g, void* out, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  const size_t taps = (size_t(G.Lh) * (Q + 4) + 7) & ~size_t(7);
+  const size_t stage = std::max<size_t>(4 * 32 * (64 + 4) * sizeof(T), 4 * 32 * 33 * sizeof(float));
+  const size_t lds = taps * sizeof(T) + stage;
+  dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
+  UMBIR_LAUNCH("conv", (k_conv_mfma16<Q, ST>), grid, dim3(256), lds, s, static_cast<const T*>(fine), hq, G.M,
+               G.Lh, G.traces(), static_cast<const T*>(base), sign, g, G.dbasis, static_cast<T*>(out));
+}
+
+void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, const void* base_v,
+                 float sign, const float* g, void* out_v, hipStream_t s) {
+  if (G.storage == UMBIR_STORAGE_F16) {
+    if (G.Q == 32) return launch_conv_mfma16<32, UMBIR_STORAGE_F16>(G, fine_v, hq, base_v, sign, g, out_v, s);
+    return launch_conv_mfma16<64, UMBIR_STORAGE_F16>(G, fine_v, hq, base_v, sign, g, out_v, s);
+  }
+  if (G.storage == UMBIR_STORAGE_BF16) {
+    if (G.Q == 32) return launch_conv_mfma16<32, UMBIR_STORAGE_BF16>(G, fine_v, hq, base_v, sign, g, out_v, s);
+    return launch_conv_mfma16<64, UMBIR_STORAGE_BF16>(G, fine_v, hq, base_v, sign, g, out_v, s);
+  }
+  const float* fine = static_cast<const float*>(fine_v);
+  const float* base = static_cast<const float*>(base_v);
+  float* out = static_cast<float*>(out_v);
   if (G.Q == 32) return launch_conv_mfma<32>(G, fine, hq, base, sign, g, out, s);
   if (G.Q == 64) return launch_conv_mfma<64>(G, fine, hq, base, sign, g, out, s);
   switch (G.Q) {
@@ -639,9 +848,7 @@ void launch_conv(const umbir_geometry& G, const float* fine, const float* hq, co
     case 2: launch_conv_q<2>(G, fine, hq, base, sign, g, out, s); break;
     case 4: launch_conv_q<4>(G, fine, hq, base, sign, g, out, s); break;
     case 8: launch_conv_q<8>(G, fine, hq, base, sign, g, out, s); break;
-    case 16: launch_conv_q<16>(G, fine, hq, base, sign, g, out, s); break;
-    case 32: launch_conv_q<32>(G, fine, hq, base, sign, g, out, s); break;
-    default: launch_conv_q<64>(G, fine, hq, base, sign, g, out, s); break;
+    default: launch_conv_q<16>(G, fine, hq, base, sign, g, out, s); break;
   }
 }
 
@@ -656,8 +863,29 @@ void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, 
   UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, fine);
 }
 
-void launch_corr(const umbir_geometry& G, const float* r, const float* hq, float* fine,
+template <int QT, int ST>
+void launch_corr_mfma16(const umbir_geometry& G, const void* r, const float* hq, void* fine, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  constexpr int NT = 2;
+  constexpr int rows = 4 * NT * 32;
+  const int L8 = (G.Lh + 7) & ~7;
+  const size_t tapsT = (size_t(32 * QT) * (L8 + 4) + 3) & ~size_t(3);
+  const size_t lds = tapsT * sizeof(T) + size_t(rows + L8) * 8;
+  dim3 grid(G.traces(), (G.M + rows - 1) / rows);
+  UMBIR_LAUNCH("corr", (k_corr_mfma16<QT, NT, ST>), grid, dim3(256), lds, s, static_cast<const T*>(r), hq, G.M,
+               G.Lh, static_cast<T*>(fine));
+}
+
+void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void* fine_v,
                  hipStream_t s) {
+  if (G.storage == UMBIR_STORAGE_F16)
+    return G.Q == 32 ? launch_corr_mfma16<1, UMBIR_STORAGE_F16>(G, r_v, hq, fine_v, s)
+                     : launch_corr_mfma16<2, UMBIR_STORAGE_F16>(G, r_v, hq, fine_v, s);
+  if (G.storage == UMBIR_STORAGE_BF16)
+    return G.Q == 32 ? launch_corr_mfma16<1, UMBIR_STORAGE_BF16>(G, r_v, hq, fine_v, s)
+                     : launch_corr_mfma16<2, UMBIR_STORAGE_BF16>(G, r_v, hq, fine_v, s);
+  const float* r = static_cast<const float*>(r_v);
+  float* fine = static_cast<float*>(fine_v);
   if (G.Q == 32) return launch_corr_mfma<1>(G, r, hq, fine, s);
   if (G.Q == 64) return launch_corr_mfma<2>(G, r, hq, fine, s);
   switch (G.Q) {
@@ -665,13 +893,36 @@ void launch_corr(const umbir_geometry& G, const float* r, const float* hq, float
     case 2: launch_corr_q<2>(G, r, hq, fine, s); break;
     case 4: launch_corr_q<4>(G, r, hq, fine, s); break;
     case 8: launch_corr_q<8>(G, r, hq, fine, s); break;
-    case 16: launch_corr_q<16>(G, r, hq, fine, s); break;
-    case 32: launch_corr_q<32>(G, r, hq, fine, s); break;
-    default: launch_corr_q<64>(G, r, hq, fine, s); break;
+    default: launch_corr_q<16>(G, r, hq, fine, s); break;
   }
 }
 
 size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
+
+template <int ST>
+void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, const float* x, int qs, int MQ,
+                  const Segments& seg, const unsigned* xmax, void* fine, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  if (abs_op)
+    UMBIR_LAUNCH("splat", (k_splat<true, ST>), grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
+                 G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, static_cast<T*>(fine));
+  else
+    UMBIR_LAUNCH("splat", (k_splat<false, ST>), grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
+                 G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, static_cast<T*>(fine));
+}
+
+template <int ST>
+void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
+                   int batch, int vpb, const void* fine, float* partial, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  constexpr int VPT = 4;
+  if (abs_op)
+    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST>), grid, dim3(256), 0, s, static_cast<const T*>(fine), G.nx,
+                 G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, partial);
+  else
+    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST>), grid, dim3(256), 0, s, static_cast<const T*>(fine), G.nx,
+                 G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, partial);
+}
 
 }  // namespace
 
@@ -685,10 +936,7 @@ int launch_copy(float* dst, const float* src, size_t n, hipStream_t s) {
   return check_hip(hipGetLastError(), "k_copy");
 }
 
-size_t forward_work_bytes(const umbir_geometry& G) {
-  // fine buffer followed by one scalar (see run_forward)
-  return aligned((size_t(G.traces()) * G.fine_per_trace() + 1) * sizeof(float)) + 256;
-}
+size_t forward_work_bytes(const umbir_geometry& G) { return aligned(G.fine_bytes()) + 256; }
 
 size_t adjoint_work_bytes(const umbir_geometry& G) {
   return forward_work_bytes(G) + aligned(size_t(G.trace_groups) * G.voxels() * sizeof(float)) + 256;
@@ -700,11 +948,11 @@ int log2_int(int q) {
   return k;
 }
 
-int run_forward(const umbir_geometry& G, const float* x, float* out, const float* base, float sign,
-                const float* g, bool abs_op, float* fine, hipStream_t s) {
-  // one scalar after the fine buffer: the largest |x| (as float bits)
-  unsigned* xmax = reinterpret_cast<unsigned*>(fine + G.traces() * G.fine_per_trace());
-  const long MQ = long(G.fine_per_trace());
+int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base, float sign,
+                const float* g, bool abs_op, void* fine, hipStream_t s) {
+  // one 32-bit scalar after the fine grid: the largest |x| (as float bits)
+  unsigned* xmax = reinterpret_cast<unsigned*>(static_cast<char*>(fine) + G.fine_bytes() - 16);
+  const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
   Segments seg;
   seg.n = G.n_seg;
@@ -718,51 +966,73 @@ int run_forward(const umbir_geometry& G, const float* x, float* out, const float
   const size_t lds = size_t((G.tile_bins + 2) & ~1) * sizeof(unsigned long long) +
                      size_t(G.n_seg) * G.nx * sizeof(int);
   dim3 grid(G.chunks, G.traces());
-  if (abs_op)
-    UMBIR_LAUNCH("splat", k_splat<true>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
-                 G.P, G.K, qs, int(MQ), seg, int(G.chunk_bins), G.tile_bins, xmax, fine);
-  else
-    UMBIR_LAUNCH("splat", k_splat<false>, grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
-                 G.P, G.K, qs, int(MQ), seg, int(G.chunk_bins), G.tile_bins, xmax, fine);
+  switch (G.storage) {
+    case UMBIR_STORAGE_F16: launch_splat<UMBIR_STORAGE_F16>(G, abs_op, grid, lds, x, qs, MQ, seg, xmax, fine, s); break;
+    case UMBIR_STORAGE_BF16: launch_splat<UMBIR_STORAGE_BF16>(G, abs_op, grid, lds, x, qs, MQ, seg, xmax, fine, s); break;
+    default: launch_splat<UMBIR_STORAGE_F32>(G, abs_op, grid, lds, x, qs, MQ, seg, xmax, fine, s); break;
+  }
   int st = check_hip(hipGetLastError(), "k_splat");
   if (st) return st;
   launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
   return check_hip(hipGetLastError(), "k_conv");
 }
 
-int run_adjoint(const umbir_geometry& G, const float* r, float* out, float scale, bool abs_op,
-                float* fine, float* partial, hipStream_t s) {
-  const long MQ = long(G.fine_per_trace());
+int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
+                void* fine, float* partial, hipStream_t s) {
+  const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
   launch_corr(G, r, abs_op ? G.habs : G.h, fine, s);
   int st = check_hip(hipGetLastError(), "k_corr");
   if (st) return st;
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
   // one generation: at most 1024 blocks (four per CU), chunks of 256 * 4 voxels
-  constexpr int VPT = 4;
-  const int chunk = 256 * VPT;
+  const int chunk = 256 * 4;
   int nb = (G.voxels() + chunk - 1) / chunk;
   nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
   const int vpb = (G.voxels() + nb - 1) / nb;
   dim3 grid(G.trace_groups, nb);
   // traces per launch: all of a group when its fine-grid data fit the XCD's L2
   // twice over, else batches of about 2 MB
-  const size_t trace_bytes = size_t(MQ) * sizeof(float);
+  const size_t trace_bytes = size_t(MQ) * G.elem();
   const int batch = size_t(tpg) * trace_bytes <= (size_t(8) << 20)
                         ? tpg
                         : std::max(1, std::min(tpg, int((size_t(2) << 20) / trace_bytes)));
   for (int t_off = 0; t_off < tpg; t_off += batch) {
-    if (abs_op)
-      UMBIR_LAUNCH("gather", (k_gather<true, VPT>), grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs,
-                   G.tau, G.base, G.P, G.K, qs, int(MQ), tpg, t_off, batch, vpb, partial);
-    else
-      UMBIR_LAUNCH("gather", (k_gather<false, VPT>), grid, dim3(256), 0, s, fine, G.nx, G.nz, G.n_off, G.legs,
-                   G.tau, G.base, G.P, G.K, qs, int(MQ), tpg, t_off, batch, vpb, partial);
+    switch (G.storage) {
+      case UMBIR_STORAGE_F16:
+        launch_gather<UMBIR_STORAGE_F16>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, fine, partial, s);
+        break;
+      case UMBIR_STORAGE_BF16:
+        launch_gather<UMBIR_STORAGE_BF16>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, fine, partial, s);
+        break;
+      default:
+        launch_gather<UMBIR_STORAGE_F32>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, fine, partial, s);
+        break;
+    }
   }
   if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
                G.trace_groups, G.voxels(), scale, out);
   return check_hip(hipGetLastError(), "k_reduce_groups");
+}
+
+int launch_direct(const umbir_geometry& G, const float* g, void* y, int accumulate, hipStream_t s) {
+  const size_t total = size_t(G.traces()) * G.M;
+  switch (G.storage) {
+    case UMBIR_STORAGE_F16:
+      UMBIR_LAUNCH("direct", k_direct<UMBIR_STORAGE_F16>, dim3(grid_1d(total)), dim3(256), 0, s, g, G.dbasis, G.M,
+                   total, accumulate, static_cast<Store<UMBIR_STORAGE_F16>::T*>(y));
+      break;
+    case UMBIR_STORAGE_BF16:
+      UMBIR_LAUNCH("direct", k_direct<UMBIR_STORAGE_BF16>, dim3(grid_1d(total)), dim3(256), 0, s, g, G.dbasis,
+                   G.M, total, accumulate, static_cast<Store<UMBIR_STORAGE_BF16>::T*>(y));
+      break;
+    default:
+      UMBIR_LAUNCH("direct", k_direct<UMBIR_STORAGE_F32>, dim3(grid_1d(total)), dim3(256), 0, s, g, G.dbasis, G.M,
+                   total, accumulate, static_cast<float*>(y));
+      break;
+  }
+  return check_hip(hipGetLastError(), "k_direct");
 }
 
 }  // namespace umbir
@@ -781,14 +1051,14 @@ size_t umbir_workspace_bytes(const umbir_geometry* G, int kind) {
       // curvature, reductions) plus the two images of the ping-pong
       const size_t N = G->voxels(), PK = G->traces();
       const size_t nblk = (N + 255) / 256 + 1;
-      return adjoint_work_bytes(*G) + aligned(PK * G->M * sizeof(float)) + 4 * aligned(N * sizeof(float)) +
+      return adjoint_work_bytes(*G) + aligned(G->trace_bytes()) + 4 * aligned(N * sizeof(float)) +
              aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + 16 * 256;
     }
     default: return 0;
   }
 }
 
-int umbir_forward(const umbir_geometry* G, const float* x, float* y, int accumulate, void* work,
+int umbir_forward(const umbir_geometry* G, const float* x, void* y, int accumulate, void* work,
                   size_t work_bytes, void* stream) {
   if (!G || !x || !y) return fail(UMBIR_EINVAL, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -796,11 +1066,11 @@ int umbir_forward(const umbir_geometry* G, const float* x, float* y, int accumul
   int st = ws.acquire(work, work_bytes, forward_work_bytes(*G), s);
   if (st) return st;
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace() + 1);
+  void* fine = cv.take<char>(G->fine_bytes());
   return run_forward(*G, x, y, accumulate ? y : nullptr, 1.0f, nullptr, false, fine, s);
 }
 
-int umbir_adjoint(const umbir_geometry* G, const float* r, float* x, void* work, size_t work_bytes,
+int umbir_adjoint(const umbir_geometry* G, const void* r, float* x, void* work, size_t work_bytes,
                   void* stream) {
   if (!G || !r || !x) return fail(UMBIR_EINVAL, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -808,18 +1078,14 @@ int umbir_adjoint(const umbir_geometry* G, const float* r, float* x, void* work,
   int st = ws.acquire(work, work_bytes, adjoint_work_bytes(*G), s);
   if (st) return st;
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace() + 1);
+  void* fine = cv.take<char>(G->fine_bytes());
   float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
   return run_adjoint(*G, r, x, 1.0f, false, fine, partial, s);
 }
 
-int umbir_direct(const umbir_geometry* G, const float* g, float* y, int accumulate, void* stream) {
+int umbir_direct(const umbir_geometry* G, const float* g, void* y, int accumulate, void* stream) {
   if (!G || !g || !y) return fail(UMBIR_EINVAL, "NULL argument");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t total = size_t(G->traces()) * G->M;
-  UMBIR_LAUNCH("direct", k_direct, dim3(grid_1d(total)), dim3(256), 0, s, g, G->dbasis, G->M, total,
-                     accumulate, y);
-  return check_hip(hipGetLastError(), "k_direct");
+  return launch_direct(*G, g, y, accumulate, static_cast<hipStream_t>(stream));
 }
 
 int umbir_sqs_denominator(const umbir_geometry* G, double sigma, float* d, void* work,
@@ -827,14 +1093,14 @@ int umbir_sqs_denominator(const umbir_geometry* G, double sigma, float* d, void*
   if (!G || !d) return fail(UMBIR_EINVAL, "NULL argument");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(UMBIR_EINVAL, "sigma must be > 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t need = adjoint_work_bytes(*G) + aligned(size_t(G->traces()) * G->M * sizeof(float)) + 256;
+  const size_t need = adjoint_work_bytes(*G) + aligned(G->trace_bytes()) + 256;
   Workspace ws;
   int st = ws.acquire(work, work_bytes, need, s);
   if (st) return st;
   Carve cv{static_cast<char*>(ws.ptr)};
-  float* fine = cv.take<float>(size_t(G->traces()) * G->fine_per_trace() + 1);
+  void* fine = cv.take<char>(G->fine_bytes());
   float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
-  float* col = cv.take<float>(size_t(G->traces()) * G->M);
+  void* col = cv.take<char>(G->trace_bytes());
   if ((st = run_forward(*G, nullptr, col, nullptr, 1.0f, nullptr, true, fine, s))) return st;
   return run_adjoint(*G, col, d, float(1.0 / (sigma * sigma)), true, fine, partial, s);
 }

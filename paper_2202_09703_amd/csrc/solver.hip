@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "storage.h"
 
 namespace umbir {
 namespace {
@@ -71,18 +72,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Per trace: |e|^2 before the g step, then the exact g step.
-__global__ __launch_bounds__(256) void k_gstep(float* __restrict__ e, const float* __restrict__ d,
+// Per trace: |e|^2 before the g step, then the exact g step (e in the storage type).
+template <int ST>
+__global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict__ e, const float* __restrict__ d,
                                                const float* __restrict__ dnorm, float* __restrict__ g,
                                                int M, int estimate, double* __restrict__ ess) {
   __shared__ double sh[256];
   __shared__ float dg_sh;
   const int ij = blockIdx.x;
-  float* et = e + size_t(ij) * M;
+  typename Store<ST>::T* et = e + size_t(ij) * M;
   const float* dt = d + size_t(ij) * M;
   double ee = 0.0, de = 0.0;
   for (int m = threadIdx.x; m < M; m += blockDim.x) {
-    const double ev = et[m];
+    const double ev = Store<ST>::get(et[m]);
     ee += ev * ev;
     de += double(dt[m]) * ev;
   }
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(256) void k_gstep(float* __restrict__ e, const floa
   __syncthreads();
   const float dg = dg_sh;
   if (dg != 0.0f)
-    for (int m = threadIdx.x; m < M; m += blockDim.x) et[m] = fmaf(-dg, dt[m], et[m]);
+    for (int m = threadIdx.x; m < M; m += blockDim.x) et[m] = Store<ST>::put(fmaf(-dg, dt[m], Store<ST>::get(et[m])));
 }
 
 // Prior cost of x (pairs counted once) into pcost[block]; with UPDATE also the
@@ -205,9 +207,9 @@ PriorConst prior_const(const umbir_geometry& G, const umbir_prior& pr) {
 
 // Buffers of one MAP iteration (workspace or resident session state).
 struct IterBuffers {
-  float* fine;
+  void* fine;
   float* partial;
-  float* e;
+  void* e;  // residual, in the storage type
   float* u;
   float* den;
   double* ess;
@@ -219,9 +221,9 @@ IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
   const size_t N = G.voxels(), PK = G.traces();
   IterBuffers b;
   b.nblk = int((N + 255) / 256);
-  b.fine = cv.take<float>(PK * G.fine_per_trace() + 1);
+  b.fine = cv.take<char>(G.fine_bytes());
   b.partial = cv.take<float>(size_t(G.trace_groups) * N);
-  b.e = cv.take<float>(PK * G.M);
+  b.e = cv.take<char>(G.trace_bytes());
   b.u = cv.take<float>(N);
   b.den = cv.take<float>(N);
   b.ess = cv.take<double>(PK);
@@ -231,7 +233,7 @@ IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
 
 size_t iter_bytes(const umbir_geometry& G) {
   const size_t N = G.voxels(), PK = G.traces();
-  return adjoint_work_bytes(G) + aligned(PK * G.M * sizeof(float)) + 2 * aligned(N * sizeof(float)) +
+  return adjoint_work_bytes(G) + aligned(G.trace_bytes()) + 2 * aligned(N * sizeof(float)) +
          aligned(PK * sizeof(double)) + aligned(((N + 255) / 256 + 1) * sizeof(double)) + 8 * 256;
 }
 
@@ -244,13 +246,25 @@ int enqueue_curvature(const umbir_geometry& G, const IterBuffers& b, const Prior
 // One surrogate iteration from x_in to x_out (or, with last, only the cost of
 // x_in); the cost goes to cost_out[*counter] (counter != NULL) or cost_out[0].
 int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const PriorConst& pc, double inv_2s2,
-                      int est, const float* y, const float* x_in, float* x_out, float* g, bool last,
+                      int est, const void* y, const float* x_in, float* x_out, float* g, bool last,
                       double* cost_out, int* counter, hipStream_t s) {
   const int PK = G.traces();
   int st = run_forward(G, x_in, b.e, y, -1.0f, g, false, b.fine, s);
   if (st) return st;
-  UMBIR_LAUNCH("gstep", k_gstep, dim3(unsigned(PK)), dim3(256), 0, s, b.e, G.dbasis, G.dnorm, g, G.M,
-               last ? 0 : est, b.ess);
+  switch (G.storage) {
+    case UMBIR_STORAGE_F16:
+      UMBIR_LAUNCH("gstep", k_gstep<UMBIR_STORAGE_F16>, dim3(unsigned(PK)), dim3(256), 0, s,
+                   static_cast<Store<UMBIR_STORAGE_F16>::T*>(b.e), G.dbasis, G.dnorm, g, G.M, last ? 0 : est, b.ess);
+      break;
+    case UMBIR_STORAGE_BF16:
+      UMBIR_LAUNCH("gstep", k_gstep<UMBIR_STORAGE_BF16>, dim3(unsigned(PK)), dim3(256), 0, s,
+                   static_cast<Store<UMBIR_STORAGE_BF16>::T*>(b.e), G.dbasis, G.dnorm, g, G.M, last ? 0 : est, b.ess);
+      break;
+    default:
+      UMBIR_LAUNCH("gstep", k_gstep<UMBIR_STORAGE_F32>, dim3(unsigned(PK)), dim3(256), 0, s, static_cast<float*>(b.e),
+                   G.dbasis, G.dnorm, g, G.M, last ? 0 : est, b.ess);
+      break;
+  }
   if ((st = check_hip(hipGetLastError(), "k_gstep"))) return st;
   if (last) {
     UMBIR_LAUNCH("prior", k_prior<false>, dim3(b.nblk), dim3(256), 0, s, x_in, nullptr, nullptr, G.nx, G.nz,
@@ -287,7 +301,8 @@ struct umbir_solver {
   void* mem = nullptr;
   size_t bytes = 0;
   IterBuffers b{};
-  float *y = nullptr, *xa = nullptr, *xb = nullptr, *g = nullptr;
+  void* y = nullptr;  // copy of the data, storage type
+  float *xa = nullptr, *xb = nullptr, *g = nullptr;
   double* cost = nullptr;  // [max_iter + 1]
   int* counter = nullptr;
   hipStream_t cap = nullptr;       // private stream used to capture the graphs
@@ -298,7 +313,7 @@ namespace {
 
 size_t solver_bytes(const umbir_geometry& G, int max_iter) {
   const size_t N = G.voxels(), PK = G.traces();
-  return iter_bytes(G) + aligned(PK * G.M * sizeof(float)) + 2 * aligned(N * sizeof(float)) +
+  return iter_bytes(G) + aligned(G.trace_bytes()) + 2 * aligned(N * sizeof(float)) +
          aligned(PK * sizeof(float)) + aligned((size_t(max_iter) + 1) * sizeof(double)) + aligned(sizeof(int)) +
          8 * 256;
 }
@@ -333,7 +348,7 @@ int capture_step(umbir_solver* S, const float* x_in, float* x_out, hipGraphExec_
 
 extern "C" {
 
-int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const float* y, int n_iter,
+int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const void* y, int n_iter,
                       float* x_io, float* g_io, double* cost, void* work, size_t work_bytes, void* stream) {
   if (!G || !y || !x_io || !g_io) return fail(UMBIR_EINVAL, "NULL argument");
   if (n_iter < 0) return fail(UMBIR_EINVAL, "n_iter must be >= 0");
@@ -368,7 +383,7 @@ size_t umbir_solver_bytes(const umbir_geometry* G, int max_iter) {
   return solver_bytes(*G, max_iter);
 }
 
-int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const float* y_dev,
+int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const void* y_dev,
                         const float* x0_dev, const float* g0_dev, int max_iter, void* stream,
                         umbir_solver** out) {
   if (!out) return fail(UMBIR_EINVAL, "out is NULL");
@@ -395,7 +410,7 @@ int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const fl
   const size_t N = G->voxels(), PK = G->traces();
   Carve cv{static_cast<char*>(S->mem)};
   S->b = carve_iter(cv, *G);
-  S->y = cv.take<float>(PK * G->M);
+  S->y = cv.take<char>(G->trace_bytes());
   S->xa = cv.take<float>(N);
   S->xb = cv.take<float>(N);
   S->g = cv.take<float>(PK);
@@ -407,7 +422,8 @@ int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const fl
     return st;
   }
   // state: copy of y, warm start (or zeros), curvature, cost counter at 0
-  if ((st = launch_copy(S->y, y_dev, PK * G->M, s)) ||
+  if ((st = check_hip(hipMemcpyAsync(S->y, y_dev, G->trace_bytes(), hipMemcpyDeviceToDevice, s),
+                      "hipMemcpyAsync(y)")) ||
       (st = x0_dev ? launch_copy(S->xa, x0_dev, N, s) : launch_fill(S->xa, N, 0.0f, s)) ||
       (st = g0_dev ? launch_copy(S->g, g0_dev, PK, s) : launch_fill(S->g, PK, 0.0f, s)) ||
       (st = enqueue_curvature(*G, S->b, S->pc, s))) {

@@ -30,6 +30,8 @@ if not os.path.exists(_LIB_PATH):
 _lib = C.CDLL(_LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, EDIVERGED = 0, -1, -2, -3, -4, -5
+STORAGE_F32, STORAGE_F16, STORAGE_BF16 = 0, 1, 2
+TRACE_DTYPES = {STORAGE_F32: torch.float32, STORAGE_F16: torch.float16, STORAGE_BF16: torch.bfloat16}
 WORK_FORWARD, WORK_ADJOINT, WORK_RECONSTRUCT = 0, 1, 2
 TABLE_DELAY, TABLE_APOD, TABLE_TAU, TABLE_BANK, TABLE_DBASIS, TABLE_OFFSET = range(6)
 MAX_LAYERS = 8
@@ -54,7 +56,8 @@ class _Array(C.Structure):
 
 class _Acq(C.Structure):
     _fields_ = [("n_samples", C.c_int), ("fs", C.c_double), ("f_c", C.c_double),
-                ("sigma_t", C.c_double), ("t_win", C.c_double), ("oversample", C.c_int)]
+                ("sigma_t", C.c_double), ("t_win", C.c_double), ("oversample", C.c_int),
+                ("storage", C.c_int)]
 
 
 class _Problem(C.Structure):
@@ -70,7 +73,8 @@ class _Prior(C.Structure):
 class _Dims(C.Structure):
     _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("n_scans", C.c_int), ("n_rx", C.c_int),
                 ("n_samples", C.c_int), ("n_off", C.c_int), ("window", C.c_int),
-                ("oversample", C.c_int), ("n_layers", C.c_int), ("trace_groups", C.c_int)]
+                ("oversample", C.c_int), ("n_layers", C.c_int), ("trace_groups", C.c_int),
+                ("storage", C.c_int)]
 
 
 class _KernelTime(C.Structure):
@@ -142,7 +146,7 @@ class Problem:
             _Grid(int(g.nx), int(g.nz), float(g.dx), float(g.dz), float(g.x0), float(g.z0)),
             _Array(len(a.tx_x), tx, len(a.rx_offset), rx, int(a.beta)),
             _Acq(int(q.n_samples), float(q.fs), float(q.f_c), float(q.sigma_t), float(q.t_win),
-                 int(q.oversample)))
+                 int(q.oversample), int(getattr(q, "storage", STORAGE_F32))))
 
 
 def estimate_bytes(card) -> int:
@@ -183,6 +187,8 @@ class Geometry:
         self.n_scans, self.n_rx, self.n_samples = d.n_scans, d.n_rx, d.n_samples
         self.n_off, self.window, self.oversample, self.n_layers = d.n_off, d.window, d.oversample, d.n_layers
         self.trace_groups = d.trace_groups
+        self.storage = d.storage
+        self.trace_dtype = TRACE_DTYPES[d.storage]
 
     @property
     def handle(self):
@@ -251,36 +257,36 @@ def _work(geom, work, kind):
 
 
 def forward(geom: Geometry, x, y=None, accumulate: bool = False, work=None, stream=None):
-    """y = A x (or y += A x); x: [nz][nx] float32, y: [P][K][M] float32."""
+    """y = A x (or y += A x); x: [nz][nx] float32, y: [P][K][M] in the storage type."""
     import torch
     if y is None:
-        y = torch.empty(geom.trace_shape, dtype=torch.float32, device=x.device)
+        y = torch.empty(geom.trace_shape, dtype=geom.trace_dtype, device=x.device)
     wp, wb = _work(geom, work, WORK_FORWARD)
     _check(_lib.umbir_forward(geom.handle, _ptr(x, "x", geom.image_shape, torch.float32),
-                              _ptr(y, "y", geom.trace_shape, torch.float32), int(bool(accumulate)),
+                              _ptr(y, "y", geom.trace_shape, geom.trace_dtype), int(bool(accumulate)),
                               wp, wb, _stream(stream)), "umbir_forward")
     return y
 
 
 def adjoint(geom: Geometry, r, x=None, work=None, stream=None):
-    """x = A^T r; r: [P][K][M] float32, x: [nz][nx] float32."""
+    """x = A^T r; r: [P][K][M] in the storage type, x: [nz][nx] float32."""
     import torch
     if x is None:
         x = torch.empty(geom.image_shape, dtype=torch.float32, device=r.device)
     wp, wb = _work(geom, work, WORK_ADJOINT)
-    _check(_lib.umbir_adjoint(geom.handle, _ptr(r, "r", geom.trace_shape, torch.float32),
+    _check(_lib.umbir_adjoint(geom.handle, _ptr(r, "r", geom.trace_shape, geom.trace_dtype),
                               _ptr(x, "x", geom.image_shape, torch.float32), wp, wb, _stream(stream)),
            "umbir_adjoint")
     return x
 
 
 def direct(geom: Geometry, g, y=None, accumulate: bool = False, stream=None):
-    """y = D g (or y += D g); g: [P][K] float32."""
+    """y = D g (or y += D g); g: [P][K] float32, y in the storage type."""
     import torch
     if y is None:
-        y = torch.empty(geom.trace_shape, dtype=torch.float32, device=g.device)
+        y = torch.empty(geom.trace_shape, dtype=geom.trace_dtype, device=g.device)
     _check(_lib.umbir_direct(geom.handle, _ptr(g, "g", geom.trace_shape[:2], torch.float32),
-                             _ptr(y, "y", geom.trace_shape, torch.float32), int(bool(accumulate)),
+                             _ptr(y, "y", geom.trace_shape, geom.trace_dtype), int(bool(accumulate)),
                              _stream(stream)), "umbir_direct")
     return y
 
@@ -318,7 +324,7 @@ def reconstruct(geom: Geometry, prior, sigma: float, y, n_iter: int, x=None, g=N
         cost = torch.empty(n_iter + 1, dtype=torch.float64, device=dev)
     pr = make_prior(prior, sigma)
     wp, wb = _work(geom, work, WORK_RECONSTRUCT)
-    _check(_lib.umbir_reconstruct(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, torch.float32),
+    _check(_lib.umbir_reconstruct(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, geom.trace_dtype),
                                   int(n_iter), _ptr(x, "x", geom.image_shape, torch.float32),
                                   _ptr(g, "g", geom.trace_shape[:2], torch.float32),
                                   _ptr(cost, "cost", (n_iter + 1,), torch.float64), wp, wb,
@@ -336,7 +342,7 @@ class Solver:
         self.max_iter = int(max_iter)
         pr = make_prior(prior, sigma)
         h = C.c_void_p()
-        _check(_lib.umbir_solver_create(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, torch.float32),
+        _check(_lib.umbir_solver_create(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, geom.trace_dtype),
                                         _ptr(x0, "x0", geom.image_shape, torch.float32),
                                         _ptr(g0, "g0", geom.trace_shape[:2], torch.float32), self.max_iter,
                                         _stream(stream), C.byref(h)), "umbir_solver_create")

@@ -67,6 +67,7 @@ class Acquisition:
     sigma_t: float     # pulse Gaussian width [s]
     t_win: float       # window length t_0 of Eq. (10) [s]
     oversample: int    # template oversampling factor Q
+    storage: int = 0   # element type of traces in the sweeps: 0 FP32, 1 FP16, 2 BF16
 
 
 @dataclass(frozen=True)

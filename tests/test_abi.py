@@ -66,6 +66,10 @@ def _with(card, **changes):
     ({"acq__oversample": 48}, umbir.ENOTSUP),
     ({"acq__oversample": 0}, umbir.ENOTSUP),
     ({"acq__fs": 0.0}, umbir.EINVAL),
+    ({"acq__storage": 3}, umbir.EINVAL),
+    ({"acq__storage": -1}, umbir.EINVAL),
+    ({"acq__storage": 1, "acq__oversample": 16}, umbir.ENOTSUP),  # 16-bit needs Q = 32 or 64
+    ({"acq__storage": 2, "acq__oversample": 8}, umbir.ENOTSUP),
 ])
 def test_invalid_problems_rejected_without_device(changes, status):
     st, msg = _build_status(_with(card_c1(), **changes))
