@@ -139,7 +139,8 @@ typedef struct umbir_geometry umbir_geometry;
  * umbir_geometry_free.  Blocks until the tables are built.  The handle is
  * immutable afterwards and may be shared by streams and threads.
  * Errors: EINVAL (bad problem), ENOTSUP (attenuation, off-lattice
- * transducers, unsupported Q), ENOMEM, EDEVICE. */
+ * transducers, unsupported Q, 16-bit storage with Q other than 32 or 64,
+ * nx * n_layers > 4096, window * Q > 16384), ENOMEM, EDEVICE. */
 int umbir_build_geometry(const umbir_problem* problem, void* stream, umbir_geometry** out);
 
 /* Frees a geometry and its device tables.  NULL is a no-op.  The caller must

@@ -207,9 +207,10 @@ int validate(const umbir_problem* pb, Derived* dv) {
   // the dense kernels stage the taps, padded to a multiple of 16 rows, in 64 KiB of LDS
   if ((lhi + 15) / 16 * 16 * q.oversample > 16384)
     return fail(UMBIR_ENOTSUP, "window (rounded up to 16) * oversample must be <= 16384");
-  // the splat keeps one row pointer per (column, layer) in LDS beside a 32 KiB tile
-  if (long(g.nx) * md.n_layers > 8192)
-    return fail(UMBIR_ENOTSUP, "nx * n_layers must be <= 8192");
+  // the splat keeps a row pointer and its fine position per (column, layer) in
+  // LDS beside a 32 KiB tile
+  if (long(g.nx) * md.n_layers > 4096)
+    return fail(UMBIR_ENOTSUP, "nx * n_layers must be <= 4096");
   if (double(q.n_samples) * q.oversample > double(1 << 28))
     return fail(UMBIR_ENOTSUP, "n_samples * oversample too large");
   dv->Lh = int(lhi);
@@ -233,6 +234,9 @@ int validate(const umbir_problem* pb, Derived* dv) {
   }
   if (omax + 1 > (1 << 24)) return fail(UMBIR_EINVAL, "lateral extent too large");
   dv->n_off = int((omax + 2) & ~1L);  // even, for the parity split of each row
+  // the splat addresses the leg table and the image with 32-bit byte offsets
+  if (double(g.nz) * dv->n_off * sizeof(Leg) >= double(1u << 31) || double(g.nz) * g.nx * 4 >= double(1u << 31))
+    return fail(UMBIR_ENOTSUP, "leg table or image of 2 GiB or more");
   return UMBIR_OK;
 }
 

@@ -119,8 +119,10 @@ struct umbir_geometry {
   int voxels() const { return nx * nz; }
   size_t fine_per_trace() const { return size_t(M) * Q; }
   size_t elem() const { return storage == UMBIR_STORAGE_F32 ? 4 : 2; }
-  // fine-grid workspace: P K M Q elements, then one 32-bit scalar
-  size_t fine_bytes() const { return ((size_t(traces()) * fine_per_trace() * elem() + 15) & ~size_t(15)) + 16; }
+  // fine-grid workspace: P K M Q elements, then the splat's prescaled image
+  // (nz nx floats), then one 32-bit scalar
+  size_t fine_grid_bytes() const { return (size_t(traces()) * fine_per_trace() * elem() + 15) & ~size_t(15); }
+  size_t fine_bytes() const { return fine_grid_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 16; }
   size_t trace_bytes() const { return size_t(traces()) * M * elem(); }
 };
 

@@ -54,15 +54,16 @@ struct Segments {
 
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
-// Largest |x| as float bits (non-negative floats order like their bits), for
-// the fixed-point scale of the splat.  x == NULL means x = 1.
-__global__ void k_absmax(const float* __restrict__ x, int n, unsigned* __restrict__ out) {
+// The splat's input image with the row transmittance folded in, xt = tau x
+// (x == NULL means x = 1), and the largest |xt| as float bits (non-negative
+// floats order like their bits) for the fixed-point scale of the splat.
+__global__ void k_prescale(const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
+                           float* __restrict__ xt, unsigned* __restrict__ out) {
   unsigned m = 0;
-  if (x) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-      m = max(m, __float_as_uint(fabsf(x[i])));
-  } else {
-    m = __float_as_uint(1.0f);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float v = tau[i / nx] * (x ? x[i] : 1.0f);
+    xt[i] = v;
+    m = max(m, __float_as_uint(fabsf(v)));
   }
   for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
   __shared__ unsigned wmax[16];
@@ -75,15 +76,80 @@ __global__ void k_absmax(const float* __restrict__ x, int n, unsigned* __restric
 }
 
 // Fixed-point exponent of the splat: contributions are scaled by 2^k with
-// 2^k * max|x| * N <= 2^62, so no tile position can overflow int64 even if
-// every voxel of the trace landed on it (|W| <= 1 and the two weights of a
-// voxel sum to 1).  Power-of-two scaling is exact in both directions.
+// 2^k * max|xt| * N <= 2^62, so no tile position can overflow int64 even if
+// every voxel of the trace landed on it (the two apodisations and the two
+// interpolation weights of a voxel are at most 1).  Power-of-two scaling is
+// exact in both directions.
 __device__ __forceinline__ int splat_exponent(unsigned maxbits, int n_vox) {
   int e = 0;
-  (void)frexpf(__uint_as_float(maxbits), &e);  // max|x| < 2^e
+  (void)frexpf(__uint_as_float(maxbits), &e);  // max|xt| < 2^e
   int lg = 0;
   while ((1 << lg) < n_vox) ++lg;
   return 62 - lg - e;
+}
+
+// One contribution v * scale as a 64-bit integer.  For N > 1024 voxels
+// |v * scale| < 2^51 and the sum with 1.5 * 2^52 in double precision, which
+// has unit spacing there, leaves the value rounded to the nearest integer in
+// its low mantissa bits in two's complement (the constant's low word is zero,
+// so the subtraction touches only the high word): three instructions.  Small
+// problems (WIDE) use the general conversion, truncating toward zero.
+template <bool WIDE>
+__device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
+  if (WIDE) return (unsigned long long)(long long)(double(v) * scale);
+  const double d = fma(double(v), scale, 6755399441055744.0);
+  return (unsigned long long)(__double_as_longlong(d) - 0x4338000000000000ll);
+}
+constexpr int kSplatNarrowMin = 1025;  // voxels from which to_fixed<false> is exact
+
+constexpr int kSplatWaves = 8;
+constexpr int kNoRow = 0x7fffffff;
+// Word 3 of a raw buffer resource on CDNA: 32-bit data format, no swizzle.
+constexpr int kBufferWord3 = 0x00020000;
+
+// S: the fine-grid signal of one trace, one chunk of fine positions per
+// workgroup, built in LDS tiles without global atomics.  Within a layer a
+// voxel's delay grows strictly with depth, so for each (column, layer) the
+// voxels reach the fine grid in row order: one pointer per (column, layer)
+// moves forward through the rows as the tiles advance, and every voxel is
+// visited once.  Beside the pointer the block keeps the fine position of the
+// row it points at, so a (column, layer) with nothing in the current tile
+// costs no load, and per layer the range of positions its voxels reach, so a
+// layer outside the tile is skipped whole.  A wave takes 8 neighbouring
+// columns x 8 consecutive rows per step (the 8 columns of a row read
+// neighbouring leg records) and loads the next step's rows while the current
+// one is added: a column continues only after all 8 of its rows fell in the
+// tile, so the next rows are known in advance.  The rows of a column that fall
+// in the tile are a prefix of the 8, counted with a ballot.  A voxel at
+// position J adds W x (1 - phi) to J and W x phi to J + 1; the tile keeps one
+// extra slot for J + 1 = the next tile's first position.  The tile
+// accumulates in 64-bit fixed point (integer LDS atomics: the sum does not
+// depend on the order of the adds, so the result is bitwise reproducible),
+// scaled by 2^k from splat_exponent.  Tiles are written out whole
+// (coalesced), so the fine buffer needs no clearing.
+// First row of a layer segment [lo, hi) whose fine position pos(r) is
+// >= target, given jl = pos(lo) and jh = pos(hi - 1); *jfirst receives its
+// position (kNoRow if none).  pos is nondecreasing in r and close to linear,
+// so each round probes the interpolated row and its successor together (two
+// loads in flight); every other round bisects instead, which bounds the
+// rounds by twice those of a plain bisection.
+template <typename Pos>
+__device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int jh, int target, int* jfirst) {
+  if (jl >= target) { *jfirst = jl; return lo; }
+  if (jh < target) { *jfirst = kNoRow; return hi; }
+  int a = lo, b = hi - 1, ja = jl, jb = jh;  // pos(a) < target <= pos(b)
+  for (int round = 0; b - a > 1; ++round) {
+    int m = (round & 1) ? ((a + b) >> 1)
+                        : a + int((long long)(target - ja) * (b - a) / max(jb - ja, 1));
+    m = min(max(m, a + 1), b - 1);
+    const int jm = pos(m);
+    const int jn = m + 1 < b ? pos(m + 1) : jb;
+    if (jm >= target) { b = m; jb = jm; }
+    else if (jn >= target) { a = m; ja = jm; b = m + 1; jb = jn; }
+    else { a = m + 1; ja = jn; }
+  }
+  *jfirst = jb;
+  return b;
 }
 
 // S: the fine-grid signal of one trace, one chunk of fine positions per
@@ -91,26 +157,35 @@ __device__ __forceinline__ int splat_exponent(unsigned maxbits, int n_vox) {
 // voxel's delay grows strictly with depth, so for each (column, layer) the
 // voxels reach the fine grid in row order: one pointer per (column, layer)
 // moves forward through the rows as the tiles advance, and every voxel is
-// visited once.  A wave takes 8 neighbouring columns x 8 consecutive rows per
-// step (lanes of one column stop together, and the 8 columns of a row read
-// neighbouring leg records); the rows of a column that fall in the tile are a
-// prefix of the 8, counted with a ballot.  A voxel at position J adds
-// W x (1 - phi) to J and W x phi to J + 1; the tile keeps one extra slot for
-// J + 1 = the next tile's first position.  The tile accumulates in 64-bit
-// fixed point (integer LDS atomics: fast on CDNA, and the sum does not depend
-// on the order of the adds, so the result is bitwise reproducible), scaled by
-// 2^k from splat_exponent.  x == NULL means x = 1.  Tiles are written out
-// whole (coalesced), so the fine buffer needs no clearing.
-template <bool ABSW, int ST>
-__global__ __launch_bounds__(256) void k_splat(
-    const float* __restrict__ x, int nx, int n_off, const Leg* __restrict__ legs,
-    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
-    Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
+// visited once.  Beside the pointer the block keeps the fine position of the
+// row it points at, so a (column, layer) with nothing in the current tile
+// costs no load, and per layer the range of positions its voxels reach, so a
+// layer outside the tile is skipped whole.  A wave takes 8 neighbouring
+// columns x 8 consecutive rows per step (the 8 columns of a row read
+// neighbouring leg records) and loads the next step's rows into a second
+// register set while the current one is added: a column continues only after
+// all 8 of its rows fell in the tile, so the next rows are known in advance.
+// The rows of a column that fall in the tile are a prefix of the 8, counted
+// with a ballot.  A voxel at position J adds W x (1 - phi) to J and W x phi to
+// J + 1; the tile keeps one extra slot for J + 1 = the next tile's first
+// position and one never-read slot that takes the J part of a voxel at J0 - 1
+// (added in the previous tile).  The tile accumulates in 64-bit fixed point
+// (integer LDS atomics: the sum does not depend on the order of the adds, so
+// the result is bitwise reproducible), scaled by 2^k from splat_exponent.
+// Tiles are written out whole (coalesced), so the fine buffer needs no
+// clearing.
+template <bool ABSW, bool WIDE, int ST>
+__global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
+    const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const int* __restrict__ base,
+    int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
     typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
-  unsigned long long* tile = smem;                                   // [tile_bins + 1]
-  int* ptr = reinterpret_cast<int*>(smem + ((tile_bins + 2) & ~1));  // [seg.n][nx]
+  unsigned long long* tile = smem;                                   // [tile_bins + 2]
+  int* ptr = reinterpret_cast<int*>(smem + tile_bins + 2);           // [seg.n][nx] next row
+  int* nxt = ptr + seg.n * nx;                                       // [seg.n][nx] its fine position
+  __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
   const int kx = splat_exponent(*xmax, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
+  const double scale = ldexp(1.0, kx);
   const int ij = blockIdx.y;
   const int J_begin = blockIdx.x * chunk_bins;
   const int J_end = min(J_begin + chunk_bins, MQ);
@@ -121,20 +196,27 @@ __global__ __launch_bounds__(256) void k_splat(
   const int sh = 32 - qs;  // J = (D_tx + D_rx) >> (32 - log2 Q)
   typename Store<ST>::T* out = fine + size_t(ij) * MQ;
 
+  if (threadIdx.x < kMaxLayers) {
+    lay_lo[threadIdx.x] = kNoRow;
+    lay_hi[threadIdx.x] = -kNoRow;
+  }
+  __syncthreads();
   // first row of each (column, layer) whose position is >= J_begin - 1
-  for (int c = threadIdx.x; c < nx; c += blockDim.x) {
+  for (int i = threadIdx.x; i < seg.n * nx; i += blockDim.x) {
+    const int sg = i / nx, c = i - sg * nx;
     const Leg* ltx = legs + leg_slot(abs(btx + 2 * c), half);
     const Leg* lrx = legs + leg_slot(abs(brx + 2 * c), half);
-    for (int sg = 0; sg < seg.n; ++sg) {
-      int lo = seg.lo[sg], hi = seg.hi[sg];
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const size_t o = size_t(mid) * n_off;
-        const int J = int(uint64_t(ltx[o].delay + lrx[o].delay) >> sh);
-        if (J < J_begin - 1) lo = mid + 1; else hi = mid;
-      }
-      ptr[sg * nx + c] = lo;
-    }
+    auto pos = [&](int r) {
+      const size_t o = size_t(r) * n_off;
+      return int(uint64_t(ltx[o].delay + lrx[o].delay) >> sh);
+    };
+    const int lo = seg.lo[sg], hi = seg.hi[sg];  // segments are never empty
+    const int jl = pos(lo), jh = pos(hi - 1);
+    atomicMin(&lay_lo[sg], jl);
+    atomicMax(&lay_hi[sg], jh);
+    int jf;
+    ptr[i] = first_row_at(pos, lo, hi, jl, jh, J_begin - 1, &jf);
+    nxt[i] = jf;
   }
   for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0ull;
   __syncthreads();
@@ -143,49 +225,87 @@ __global__ __launch_bounds__(256) void k_splat(
   const int cc = lane & 7, rr = lane >> 3;
   const unsigned long long colmask = 0x0101010101010101ull << cc;
   const int n_groups = (nx + 7) >> 3;
+  // The step loads are raw buffer loads: unconditional (so the next step's
+  // loads never wait behind a branch), with 32-bit byte offsets, and the
+  // hardware range check returns zeros past the end of a table.  Rows past
+  // the layer are read too but never used.
+  const int rows = seg.hi[seg.n - 1];
+  const __amdgpu_buffer_rsrc_t leg_rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, rows * n_off * int(sizeof(Leg)), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t xt_rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xt), 0, rows * nx * 4, kBufferWord3);
+  const unsigned lstep = 8u * unsigned(n_off) * unsigned(sizeof(Leg));  // bytes between a lane's steps
+  const unsigned xstep = 8u * unsigned(nx) * 4u;
+  struct Rows {
+    int64_t da, db;
+    float pa, pb, xv;
+  };
   for (int J0 = J_begin; J0 < J_end; J0 += tile_bins) {
     const int J1 = min(J0 + tile_bins, J_end);
-    for (int grp = wave; grp < n_groups; grp += 4) {
-      const int c = grp * 8 + cc;
-      const bool col_ok = c < nx;
-      const Leg* ltx = legs + (col_ok ? leg_slot(abs(btx + 2 * c), half) : 0);
-      const Leg* lrx = legs + (col_ok ? leg_slot(abs(brx + 2 * c), half) : 0);
-      for (int sg = 0; sg < seg.n; ++sg) {
-        const int hi = seg.hi[sg];
-        int r0 = col_ok ? ptr[sg * nx + c] : hi;
-        bool live = r0 < hi;  // this column may still have rows in the tile
-        while (__any(live)) {
-          const int r = r0 + rr;
-          bool in = live && r < hi;
-          uint64_t D = 0;
-          Leg a, b;
-          float xv = 0.0f, tr = 0.0f;
-          if (in) {  // all four loads in flight together
-            a = ltx[size_t(r) * n_off];
-            b = lrx[size_t(r) * n_off];
-            xv = x ? x[r * nx + c] : 1.0f;
-            tr = tau[r];
-            D = uint64_t(a.delay + b.delay);
-            in = int(D >> sh) < J1;
-          }
-          if (in) {
-            const int J = int(D >> sh);
-            // J + 1 >= J0 holds while delays grow with depth within a layer
-            if (xv != 0.0f && J + 1 >= J0) {
-              float w = tr * xv * (a.apod * b.apod);
-              if (ABSW) w = fabsf(w);
-              const float phi = float(uint32_t(D) << qs) * kTwoM32;
-              const float w1 = w * phi;
-              if (J >= J0)
-                atomicAdd(&tile[J - J0], (unsigned long long)(long long)ldexpf(w - w1, kx));
-              atomicAdd(&tile[J + 1 - J0], (unsigned long long)(long long)ldexpf(w1, kx));
-            }
+    for (int sg = 0; sg < seg.n; ++sg) {
+      if (lay_lo[sg] >= J1 || lay_hi[sg] < J0 - 1) continue;  // uniform: no voxel of the layer here
+      const int hi = seg.hi[sg];
+      for (int grp = wave; grp < n_groups; grp += kSplatWaves) {
+        const int c = grp * 8 + cc;
+        const int slot = sg * nx + c;
+        int r0 = hi;
+        bool live = false;
+        if (c < nx) {
+          r0 = ptr[slot];
+          live = r0 < hi && nxt[slot] < J1;
+        }
+        if (!__any(live)) continue;
+        const int cl = min(c, nx - 1);  // addresses of lanes past the last column stay in the tables
+        int r = r0 + rr;
+        unsigned oa = (unsigned(leg_slot(abs(btx + 2 * cl), half)) + unsigned(r) * unsigned(n_off)) * unsigned(sizeof(Leg));
+        unsigned ob = (unsigned(leg_slot(abs(brx + 2 * cl), half)) + unsigned(r) * unsigned(n_off)) * unsigned(sizeof(Leg));
+        unsigned ox = (unsigned(r) * unsigned(nx) + unsigned(cl)) * 4u;
+        auto load = [&](Rows& v, unsigned k) {  // rows r + 8 k of this lane
+          // delay and apodisation as a 64-bit and a 32-bit load (the compiler
+          // merges them into one 12-byte load)
+          const int ka = int(oa + k * lstep), kb = int(ob + k * lstep);
+          const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ka, 0, 0);
+          const auto b = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, kb, 0, 0);
+          v.pa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ka + 8, 0, 0));
+          v.pb = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, kb + 8, 0, 0));
+          v.xv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xt_rs, int(ox + k * xstep), 0, 0));
+          v.da = int64_t((uint64_t(a[1]) << 32) | a[0]);
+          v.db = int64_t((uint64_t(b[1]) << 32) | b[0]);
+        };
+        // adds this lane's row r; false once no column of the wave continues
+        auto add = [&](const Rows& v) {
+          const bool have = live && r < hi;
+          const uint64_t D = uint64_t(v.da + v.db);
+          const int J = int(D >> sh);
+          const bool in = have && J < J1;
+          // J + 1 >= J0 holds while delays grow with depth within a layer
+          if (in && v.xv != 0.0f && J + 1 >= J0) {
+            float w = v.xv * (v.pa * v.pb);
+            if (ABSW) w = fabsf(w);
+            const float phi = float(uint32_t(D) << qs) * kTwoM32;
+            const float w1 = w * phi;
+            atomicAdd(&tile[J >= J0 ? J - J0 : tile_bins + 1], to_fixed<WIDE>(w - w1, scale));
+            atomicAdd(&tile[J + 1 - J0], to_fixed<WIDE>(w1, scale));
           }
           const int cnt = __popcll(__ballot(in) & colmask);  // rows of column c taken
+          if (live && rr == cnt) nxt[slot] = have ? J : kNoRow;  // first row left for later tiles
           r0 += cnt;
           live = live && cnt == 8;
+          r += 8;
+          oa += lstep;
+          ob += lstep;
+          ox += xstep;
+          return __any(live);
+        };
+        Rows s0, s1;
+        load(s0, 0);
+        while (true) {
+          load(s1, 1);
+          if (!add(s0)) break;
+          load(s0, 1);
+          if (!add(s1)) break;
         }
-        if (col_ok && rr == 0) ptr[sg * nx + c] = r0;
+        if (c < nx && rr == 0) ptr[slot] = r0;
       }
     }
     __syncthreads();
@@ -899,16 +1019,25 @@ void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void
 
 size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 
-template <int ST>
-void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, const float* x, int qs, int MQ,
-                  const Segments& seg, const unsigned* xmax, void* fine, hipStream_t s) {
+template <bool ABSW, bool WIDE, int ST>
+void launch_splat_k(const umbir_geometry& G, dim3 grid, size_t lds, const float* xt, int qs, int MQ,
+                    const Segments& seg, const unsigned* xmax, void* fine, hipStream_t s) {
   using T = typename Store<ST>::T;
-  if (abs_op)
-    UMBIR_LAUNCH("splat", (k_splat<true, ST>), grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
-                 G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, static_cast<T*>(fine));
-  else
-    UMBIR_LAUNCH("splat", (k_splat<false, ST>), grid, dim3(256), lds, s, x, G.nx, G.n_off, G.legs, G.tau, G.base,
-                 G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, static_cast<T*>(fine));
+  UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx, G.n_off,
+               G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, static_cast<T*>(fine));
+}
+
+template <int ST>
+void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, const float* xt, int qs, int MQ,
+                  const Segments& seg, const unsigned* xmax, void* fine, hipStream_t s) {
+  const bool wide = G.nx * (seg.hi[seg.n - 1] - seg.lo[0]) < kSplatNarrowMin;
+  if (abs_op) {
+    if (wide) launch_splat_k<true, true, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
+    else launch_splat_k<true, false, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
+  } else {
+    if (wide) launch_splat_k<false, true, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
+    else launch_splat_k<false, false, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
+  }
 }
 
 template <int ST>
@@ -950,7 +1079,9 @@ int log2_int(int q) {
 
 int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base, float sign,
                 const float* g, bool abs_op, void* fine, hipStream_t s) {
-  // one 32-bit scalar after the fine grid: the largest |x| (as float bits)
+  // after the fine grid: the prescaled image tau x, then one 32-bit scalar,
+  // the largest |tau x|
+  float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.fine_grid_bytes());
   unsigned* xmax = reinterpret_cast<unsigned*>(static_cast<char*>(fine) + G.fine_bytes() - 16);
   const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
@@ -961,15 +1092,15 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     seg.hi[k] = G.seg_hi[k];
   }
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(xmax), size_t(1), 0.0f);
-  UMBIR_LAUNCH("absmax", k_absmax, dim3(x ? std::min(32, (G.voxels() + 1023) / 1024) : 1), dim3(1024), 0, s,
-               x, G.voxels(), xmax);
-  const size_t lds = size_t((G.tile_bins + 2) & ~1) * sizeof(unsigned long long) +
-                     size_t(G.n_seg) * G.nx * sizeof(int);
+  UMBIR_LAUNCH("prescale", k_prescale, dim3(std::min(128, (G.voxels() + 1023) / 1024)), dim3(1024), 0, s, x,
+               G.tau, G.nx, G.voxels(), xt, xmax);
+  const size_t lds = size_t(G.tile_bins + 2) * sizeof(unsigned long long) +
+                     2 * size_t(G.n_seg) * G.nx * sizeof(int);
   dim3 grid(G.chunks, G.traces());
   switch (G.storage) {
-    case UMBIR_STORAGE_F16: launch_splat<UMBIR_STORAGE_F16>(G, abs_op, grid, lds, x, qs, MQ, seg, xmax, fine, s); break;
-    case UMBIR_STORAGE_BF16: launch_splat<UMBIR_STORAGE_BF16>(G, abs_op, grid, lds, x, qs, MQ, seg, xmax, fine, s); break;
-    default: launch_splat<UMBIR_STORAGE_F32>(G, abs_op, grid, lds, x, qs, MQ, seg, xmax, fine, s); break;
+    case UMBIR_STORAGE_F16: launch_splat<UMBIR_STORAGE_F16>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
+    case UMBIR_STORAGE_BF16: launch_splat<UMBIR_STORAGE_BF16>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
+    default: launch_splat<UMBIR_STORAGE_F32>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
   }
   int st = check_hip(hipGetLastError(), "k_splat");
   if (st) return st;
