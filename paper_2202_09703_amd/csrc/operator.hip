@@ -587,104 +587,122 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
     }
 }
 
+// Chunk order of the banded convolutions on the matrix cores.  The rows n a
+// block needs are its window [m0 - Lh, m0 + 30], walked in chunks of CN rows.
+// Every block walks a window of the same length, P chunks from m0 - Lh,
+// rotated so that at step s it reads rows congruent to s CN modulo P CN: the
+// blocks of one trace tile, resident together on one XCD, then read the same
+// rows at about the same time, and the L2 serves the repeats that a plain
+// order leaves to memory.  Rows outside [0, M) read as zero.
+constexpr int kConvTapPad = 32;  // zero tap rows on each side in k_conv_mfma
+
+struct ChunkOrder {
+  int v_lo, P, rot, CN;
+  __device__ ChunkOrder(int m0, int Lh, int cn) : CN(cn) {
+    v_lo = m0 - Lh;
+    P = (Lh + 31 + CN - 1) / CN;
+    const int fl = v_lo >= 0 ? v_lo / CN : -((-v_lo + CN - 1) / CN);  // floor(v_lo / CN)
+    rot = ((-fl) % P + P) % P;
+  }
+  __device__ int row(int s) const { return v_lo + ((s + rot) % P) * CN; }
+};
+
 // C on the matrix cores, for Q in {32, 64}: the convolution of one trace has a
 // single output column, so traces are batched as the N dimension:
 //   Y[m][tr] = sum_{(n,t)} H[m-1-n][t] S_tr[n Q + t],
 // A = the banded Toeplitz tile built from the taps (zero where m - 1 - n is
 // outside the window), B = the fine-grid signals of 32 traces.  A block owns a
-// 32 (m) x 32 (trace) output tile; its four waves split the (n, t) range
-// between them in 64-wide chunks, stage their chunk of B through LDS with
-// coalesced loads, and the four partial tiles are summed in LDS at the end.
-// Epilogue as in k_conv.  Taps are stored with row stride Q + 1 and staged
-// chunks with stride 65 so neither operand read hits one LDS bank twice.
+// 32 (m) x 32 (trace) output tile; its four waves take the window's 64-wide
+// chunks of (n, t) in turn (ChunkOrder) and their partial tiles are summed in
+// LDS at the end.  The contraction index of the 32x32x2 product is labelled
+// so that lane half lk holds chunk positions [32 lk, 32 lk + 32): a lane's A
+// values are then 32 consecutive taps of one row (read as 16-byte LDS words)
+// and its B values 32 consecutive fine-grid samples of one trace, loaded from
+// memory straight into registers one chunk ahead, with no staging.  Taps are
+// kept with zero rows on both sides of the window (no masking) and a row
+// stride of Q + 4 words, which spreads 16 lanes' 16-byte reads over all
+// banks.  Epilogue as in k_conv.
 template <int Q>
 __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
                                                    const float* __restrict__ dbasis, float* out) {
-  constexpr int CK = 64;        // (n, t) pairs per chunk
+  constexpr int CK = 64;        // (n, t) positions per chunk
   constexpr int CN = CK / Q;    // rows n per chunk
-  constexpr int SB = CK + 1;    // staged row stride
-  extern __shared__ float sm[];
-  float* taps = sm;                                   // [Lh][Q + 1]
-  float* stage = sm + Lh * (Q + 1);                   // [4 waves][32 traces][SB]
+  constexpr int TS = Q + 4;     // tap row stride
+  constexpr int KP = kConvTapPad;
+  extern __shared__ __align__(16) float sm[];
+  float* taps = sm;  // [KP + Lh + KP][TS], tap rows -KP .. Lh + KP - 1
   const int tr0 = blockIdx.x * 32;
   const int m0 = blockIdx.y * 32;
   const long MQ = long(M) * Q;
-  for (int i = threadIdx.x; i < Lh * Q; i += blockDim.x) taps[(i / Q) * (Q + 1) + (i % Q)] = hq[i];
+  for (int i = threadIdx.x; i < (Lh + 2 * KP) * TS; i += blockDim.x) {
+    const int k = i / TS - KP, t = i % TS;
+    taps[i] = (k >= 0 && k < Lh && t < Q) ? hq[k * Q + t] : 0.0f;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
-  float* st = stage + wave * 32 * SB;
+  const int ro = (32 * lk) / Q, t0 = (32 * lk) % Q;  // this lane's row and first tap within a chunk
   // rows n that meet an output m in [m0, m0 + 32): m0 - Lh <= n <= m0 + 30
-  const int n_lo = max(0, m0 - Lh);
-  const int n_hi = min(M, m0 + 31);
-  const int n_chunks = (max(0, n_hi - n_lo) + CN - 1) / CN;
-  const int rounds = (n_chunks + 3) / 4;
-  floatx16 acc[2];  // two independent accumulation chains (even / odd k pairs)
+  const ChunkOrder co(m0, Lh, CN);
+  const int rounds = (co.P + 3) / 4;
+  floatx16 acc[2];  // two independent accumulation chains
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.0f;
-  // B chunk of one wave: 32 traces x CK values, 16 lanes x float4 per trace,
-  // 4 traces per load instruction, 8 instructions; prefetched one chunk ahead
-  const int sub = lane & 15, tq = lane >> 4;
-  float4 pre[8];
-  auto fetch = [&](int ch) {
-    const int nc = n_lo + ch * CN;
+  // B: trace tr0 + li (traces past the last read the last one: they only feed
+  // output columns that are never written).  Loads are unconditional, from a
+  // row clamped into [0, M); a row outside [0, M), or a step past the window,
+  // takes the A row of zeros instead, so B needs no masking.
+  const float* src = fine + size_t(min(tr0 + li, PK - 1)) * MQ + t0;
+  // the chunk of step ch = rd 4 + wave advances by 4 per round, modulo P
+  int jf = (wave + co.rot) % co.P, jm = jf;  // fetch and multiply positions
+  int sf = wave, sm_ = wave;                  // their steps
+  auto next_row = [&](int& j, int& step) {
+    const int nc = step < co.P ? co.v_lo + j * CN : -(1 << 30);  // past the window: no row
+    step += 4;
+    j += 4;
+    while (j >= co.P) j -= co.P;
+    return nc;
+  };
+  auto fetch = [&](float4 (&b)[8]) {
+    const int nc = next_row(jf, sf);
+    const int n = min(max(nc + ro, 0), M - 1);
+    const float4* p = reinterpret_cast<const float4*>(src + long(n) * Q);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int tr = u * 4 + tq;
-      const int kp = sub * 4;  // first of four consecutive (n, t) values
-      const int n = nc + kp / Q;
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (ch < n_chunks && n < n_hi && tr0 + tr < PK)
-        v = *reinterpret_cast<const float4*>(fine + size_t(tr0 + tr) * MQ + size_t(nc) * Q + kp);
-      pre[u] = v;
-    }
+    for (int u = 0; u < 8; ++u) b[u] = p[u];
   };
   const int m = m0 + li;
-  __syncthreads();  // taps staged
-  fetch(wave);
-  for (int rd = 0; rd < rounds; ++rd) {
-    const int ch = rd * 4 + wave;
-    const int nc = n_lo + ch * CN;
+  auto multiply = [&](const float4 (&b)[8]) {
+    const int nc = next_row(jm, sm_);
+    const int n = nc + ro;
+    // tap row k = m - 1 - n, within [-KP, Lh + KP) for every chunk of the window
+    const int k = (n >= 0 && n < M) ? m - 1 - n : -KP;
+    const float4* arow = reinterpret_cast<const float4*>(taps + (k + KP) * TS + t0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      float* d = st + (u * 4 + tq) * SB + sub * 4;
-      d[0] = pre[u].x;
-      d[1] = pre[u].y;
-      d[2] = pre[u].z;
-      d[3] = pre[u].w;
+      const float4 av = arow[u];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b[u].x, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b[u].y, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b[u].z, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc[1], 0, 0, 0);
     }
-    __builtin_amdgcn_wave_barrier();  // the staging buffer is private to this wave
-    fetch(ch + 4);
-    if (ch < n_chunks) {
-      // row nc + r of the chunk meets output m through tap k = m - 1 - nc - r;
-      // outside the window the A value is zero (pointer clamped, value masked)
-      const float* trow[CN];
-      float tmask[CN];
-#pragma unroll
-      for (int r = 0; r < CN; ++r) {
-        const int k = m - 1 - nc - r;
-        const bool ok = k >= 0 && k < Lh;
-        trow[r] = taps + (ok ? k : 0) * (Q + 1) + lk - r * Q;
-        tmask[r] = ok ? 1.0f : 0.0f;
-      }
-      const float* srow = st + li * SB + lk;
-#pragma unroll
-      for (int kk = 0; kk < CK; kk += 2) {
-        const int r = kk / Q;  // compile-time: kk + lk stays in row kk / Q
-        const float av = trow[r][kk] * tmask[r];
-        const float bv = srow[kk];
-        acc[(kk >> 1) & 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[(kk >> 1) & 1], 0, 0, 0);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
+  };
+  __syncthreads();  // taps staged
+  // two register sets in turn: the next chunk is in flight while one multiplies
+  float4 b0[8], b1[8];
+  fetch(b0);
+  for (int rd = 0; rd < rounds; rd += 2) {
+    fetch(b1);
+    multiply(b0);
+    fetch(b0);
+    multiply(b1);
   }
-  __syncthreads();
+  __syncthreads();  // every wave is done with the taps: reuse them for the reduction
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[0][i] += acc[1][i];
   // sum the four partial tiles: red[wave][row][col]
-  float* red = stage;
+  float* red = sm;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
@@ -693,11 +711,11 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
     const int col = e >> 5, row = e & 31;  // consecutive threads: consecutive m of one trace
-    const int m = m0 + row, tr = tr0 + col;
-    if (m < M && tr < PK) {
+    const int mm = m0 + row, tr = tr0 + col;
+    if (mm < M && tr < PK) {
       const float v = red[(0 * 32 + row) * 33 + col] + red[(1 * 32 + row) * 33 + col] +
                       red[(2 * 32 + row) * 33 + col] + red[(3 * 32 + row) * 33 + col];
-      const size_t idx = size_t(tr) * M + m;
+      const size_t idx = size_t(tr) * M + mm;
       float val = sign * v;
       if (base) val += base[idx];
       if (g) val -= g[tr] * dbasis[idx];
@@ -736,10 +754,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma16(const typename Store<ST>::T
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
   T* st = stage + wave * 32 * SB;
-  const int n_lo = max(0, m0 - Lh);
-  const int n_hi = min(M, m0 + 31);
-  const int n_chunks = (max(0, n_hi - n_lo) + CN - 1) / CN;
-  const int rounds = (n_chunks + 3) / 4;
+  const ChunkOrder co(m0, Lh, CN);
+  const int rounds = (co.P + 3) / 4;
   floatx16 acc[2];
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.0f;
@@ -748,14 +764,14 @@ __global__ __launch_bounds__(256) void k_conv_mfma16(const typename Store<ST>::T
   const int sub = lane & 7, tq = lane >> 3;
   uint4 pre[4];
   auto fetch = [&](int ch) {
-    const int nc = n_lo + ch * CN;
+    const int nc = ch < co.P ? co.row(ch) : -CN;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int tr = u * 8 + tq;
       const int kp = sub * 8;  // first of eight consecutive (n, t) values
       const int n = nc + kp / Q;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (ch < n_chunks && n < n_hi && tr0 + tr < PK)
+      if (n >= 0 && n < M && tr0 + tr < PK)
         v = *reinterpret_cast<const uint4*>(fine + size_t(tr0 + tr) * MQ + size_t(nc) * Q + kp);
       pre[u] = v;
     }
@@ -765,7 +781,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma16(const typename Store<ST>::T
   fetch(wave);
   for (int rd = 0; rd < rounds; ++rd) {
     const int ch = rd * 4 + wave;
-    const int nc = n_lo + ch * CN;
+    const int nc = ch < co.P ? co.row(ch) : -CN;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       uint2* d = reinterpret_cast<uint2*>(st + (u * 8 + tq) * SB + sub * 8);
@@ -774,7 +790,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma16(const typename Store<ST>::T
     }
     __builtin_amdgcn_wave_barrier();  // the staging buffer is private to this wave
     fetch(ch + 4);
-    if (ch < n_chunks) {
+    if (nc + CN > 0 && nc < M) {
       const T* trow[CN];
       bool tok[CN];
 #pragma unroll
@@ -929,8 +945,8 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
 template <int Q>
 void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
                       float sign, const float* g, float* out, hipStream_t s) {
-  const size_t stage = std::max<size_t>(4 * 32 * 65, 4 * 32 * 33);
-  const size_t lds = (size_t(G.Lh) * (Q + 1) + stage) * sizeof(float);
+  // padded taps, reused for the four partial tiles at the end
+  const size_t lds = std::max<size_t>(size_t(G.Lh + 2 * kConvTapPad) * (Q + 4), 4 * 32 * 33) * sizeof(float);
   dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
   UMBIR_LAUNCH("conv", k_conv_mfma<Q>, grid, dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
                sign, g, G.dbasis, out);
