@@ -530,61 +530,132 @@ __global__ __launch_bounds__(256) void k_corr(const float* __restrict__ rt,
 // (v_mfma_f32_32x32x2f32: A lane l = R[l%32][l/32], B lane l = H[l/32][l%32],
 // D register i of lane l = row 8(i/4) + 4(l/32) + i%4, column l%32).  A wave
 // computes NT tiles of 32 rows x Q phases; the block stages its trace segment
-// and the taps (zero-padded to an even count) in LDS.  Writes are coalesced
-// along t.
+// and the taps (zero-padded to 2 CorrHalf) in LDS.  The contraction index is
+// labelled so that lane half lk takes taps k in [lk H, lk H + H): each lane
+// then walks its own run of consecutive k, and the operands of the next four
+// k are read while the current four multiply.  The second half of the taps
+// and a second copy of the segment (shifted by H) sit 32 banks away from the
+// first, so the two lane halves never read the same bank.  Writes are
+// coalesced along t.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Half the padded tap count of k_corr_mfma: a multiple of 8 with 2 H >= Lh.
+__host__ __device__ inline int corr_half(int Lh) { return (Lh + 15) / 16 * 8; }
+// LDS words of k_corr_mfma: taps (two halves, 32 words apart), then the two
+// segment copies (the second one 32 banks from the first).
+__host__ __device__ inline int corr_seg_len(int rows, int H) { return rows + H; }
+__host__ __device__ inline int corr_seg_gap(int rows, int H) { return (rows + H + 63) / 64 * 64 + 32; }
+__host__ __device__ inline int corr_lds_words(int Q, int rows, int H) {
+  return 2 * H * Q + 32 + corr_seg_gap(rows, H) + corr_seg_len(rows, H);
+}
 
 template <int QT, int NT>
 __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
-                                                   const float* __restrict__ hq, int M, int Lh,
+                                                   const float* __restrict__ hq, int M, int Lh, int rb_per_block,
                                                    float* __restrict__ fine) {
   constexpr int Q = 32 * QT;
-  constexpr int ROWS = 4 * NT * 32;  // n per block
+  constexpr int ROWS = 4 * NT * 32;  // n per row block
+  constexpr int KB = 4;              // k per lane per step
   extern __shared__ float sm[];
-  const int LhE = (Lh + 1) & ~1;
-  float* taps = sm;                  // [LhE][Q]
-  float* seg = sm + LhE * Q;         // [ROWS + LhE]: r[n_blk + 1 + j]
+  const int H = corr_half(Lh);
+  const int SL = corr_seg_len(ROWS, H);
+  float* taps0 = sm;                                   // taps rows [0, H)
+  float* taps1 = sm + H * Q + 32;                      // taps rows [H, 2H)
+  float* seg0 = taps1 + H * Q;                         // seg0[x] = r[n_blk + 1 + x]
+  float* seg1 = seg0 + corr_seg_gap(ROWS, H);          // seg1[x] = r[n_blk + 1 + H + x]
   const int ij = blockIdx.x;
-  const int n_blk = blockIdx.y * ROWS;
   const float* r = rt + size_t(ij) * M;
-  for (int i = threadIdx.x; i < LhE * Q; i += blockDim.x) taps[i] = i < Lh * Q ? hq[i] : 0.0f;
-  for (int j = threadIdx.x; j < ROWS + LhE; j += blockDim.x) {
-    const int m = n_blk + 1 + j;
-    seg[j] = m < M ? r[m] : 0.0f;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 31, lk = lane >> 5;
-  floatx16 acc[NT][QT];
-#pragma unroll
-  for (int a = 0; a < NT; ++a)
-#pragma unroll
-    for (int b = 0; b < QT; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
-  const int row0 = wave * NT * 32;
-  for (int k0 = 0; k0 < LhE; k0 += 2) {
-    float bv[QT];
-#pragma unroll
-    for (int b = 0; b < QT; ++b) bv[b] = taps[(k0 + lk) * Q + b * 32 + li];
-#pragma unroll
-    for (int a = 0; a < NT; ++a) {
-      const float av = seg[row0 + a * 32 + li + k0 + lk];
-#pragma unroll
-      for (int b = 0; b < QT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[b], acc[a][b], 0, 0, 0);
-    }
-  }
   float* c = fine + size_t(ij) * M * Q;
+  for (int i = threadIdx.x; i < 2 * H * Q; i += blockDim.x) {
+    const int k = i / Q;
+    const float v = k < Lh ? hq[i] : 0.0f;
+    if (k < H) taps0[i] = v;
+    else taps1[i - H * Q] = v;
+  }
+  // the block's row blocks, in order; each thread carries its share of the
+  // next segment in registers while the current one multiplies
+  const int rb0 = blockIdx.y * rb_per_block;
+  const int rb_end = min(rb0 + rb_per_block, (M + ROWS - 1) / ROWS);
+  constexpr int SEG_PER_THREAD = 4;  // ceil((ROWS + H) / 256) for H <= 768
+  float s0[SEG_PER_THREAD], s1[SEG_PER_THREAD];
+  auto seg_load = [&](int rb) {
+    const int n_blk = rb * ROWS;
 #pragma unroll
-  for (int a = 0; a < NT; ++a)
+    for (int u = 0; u < SEG_PER_THREAD; ++u) {
+      const int x = threadIdx.x + u * 256;
+      const int m = n_blk + 1 + x;
+      s0[u] = x < SL && m < M ? r[m] : 0.0f;
+      s1[u] = x < SL && m + H < M ? r[m + H] : 0.0f;
+    }
+  };
+  auto seg_store = [&]() {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int n = n_blk + row0 + a * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
-      if (n < M) {
-#pragma unroll
-        for (int b = 0; b < QT; ++b) c[size_t(n) * Q + b * 32 + li] = acc[a][b][i];
+    for (int u = 0; u < SEG_PER_THREAD; ++u) {
+      const int x = threadIdx.x + u * 256;
+      if (x < SL) {
+        seg0[x] = s0[u];
+        seg1[x] = s1[u];
       }
     }
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  const int row0 = wave * NT * 32;
+  const float* sa = (lk ? seg1 : seg0) + row0 + li;  // + a 32 + j
+  const float* sb = (lk ? taps1 : taps0) + li;       // + j Q + b 32
+  if (rb0 < rb_end) seg_load(rb0);
+  for (int rb = rb0; rb < rb_end; ++rb) {
+    __syncthreads();  // the previous row block is done with the segment
+    seg_store();
+    __syncthreads();
+    if (rb + 1 < rb_end) seg_load(rb + 1);
+    floatx16 acc[NT][QT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = 0; b < QT; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+    float av[2][NT][KB], bv[2][QT][KB];
+    auto load = [&](int buf, int j) {
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+#pragma unroll
+        for (int a = 0; a < NT; ++a) av[buf][a][t] = sa[a * 32 + j + t];
+#pragma unroll
+        for (int b = 0; b < QT; ++b) bv[buf][b][t] = sb[(j + t) * Q + b * 32];
+      }
+    };
+    auto multiply = [&](int buf) {
+#pragma unroll
+      for (int t = 0; t < KB; ++t)
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = 0; b < QT; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[buf][a][t], bv[buf][b][t], acc[a][b], 0, 0, 0);
+    };
+    // H is a multiple of 2 KB: the steps pair up; loads past the end are
+    // clamped to the last step (read, never used)
+    load(0, 0);
+    for (int j = 0; j < H; j += 2 * KB) {
+      load(1, j + KB);
+      multiply(0);
+      load(0, min(j + 2 * KB, H - KB));
+      multiply(1);
+    }
+    const int n_blk = rb * ROWS;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int n = n_blk + row0 + a * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
+        if (n < M) {
+#pragma unroll
+          for (int b = 0; b < QT; ++b) c[size_t(n) * Q + b * 32 + li] = acc[a][b][i];
+        }
+      }
+  }
 }
 
 // Chunk order of the banded convolutions on the matrix cores.  The rows n a
@@ -993,10 +1064,13 @@ void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, 
                       hipStream_t s) {
   constexpr int NT = 2;
   constexpr int rows = 4 * NT * 32;
-  const int LhE = (G.Lh + 1) & ~1;
-  const size_t lds = (size_t(LhE) * 32 * QT + rows + LhE) * sizeof(float);
-  dim3 grid(G.traces(), (G.M + rows - 1) / rows);
-  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, fine);
+  const size_t lds = size_t(corr_lds_words(32 * QT, rows, corr_half(G.Lh))) * sizeof(float);
+  // about four blocks per CU, each walking several row blocks of one trace
+  // with the taps staged once
+  const int nrb = (G.M + rows - 1) / rows;
+  const int per = std::max(1, int((long(G.traces()) * nrb) / 1024));
+  dim3 grid(G.traces(), (nrb + per - 1) / per);
+  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine);
 }
 
 template <int QT, int ST>
