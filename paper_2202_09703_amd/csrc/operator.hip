@@ -322,18 +322,39 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   }
 }
 
+// One fine-grid sample through a buffer resource over one trace: positions
+// past the record read as zero.
+template <int ST>
+__device__ __forceinline__ float fine_at(__amdgpu_buffer_rsrc_t rs, unsigned off);
+template <>
+__device__ __forceinline__ float fine_at<UMBIR_STORAGE_F32>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, int(off * 4u), 0, 0));
+}
+template <>
+__device__ __forceinline__ float fine_at<UMBIR_STORAGE_F16>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, int(off * 2u), 0, 0)));
+}
+template <>
+__device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __uint_as_float(uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rs, int(off * 2u), 0, 0)) << 16);
+}
+
 // S^T: per voxel, sum over the traces of group blockIdx.x of W ((1 - phi) c[J]
 // + phi c[J + 1]); one partial image per group, summed in a fixed order by
 // k_reduce_groups.  The group is the fastest block index, so group g runs on
 // XCD g mod 8 and that XCD's L2 only ever holds its own traces' fine-grid
-// data.  One launch covers a small batch of each group's traces (about 2 MB of
-// fine-grid data per XCD, so the batch stays in L2 while every block of the
-// XCD reads it; blocks cannot be kept in step within a launch, but launch
-// boundaries are barriers), and the partial images accumulate across launches
-// in a fixed order.  The grid is one generation (at most four blocks per CU).  A thread accumulates VPT voxels (row-major, so
-// neighbouring threads read neighbouring leg records) with all their loads for
-// one trace in flight together; blocks take chunks of 256 VPT voxels in the
-// same order.
+// data.  One launch covers a batch of each group's traces (about 8 MB of
+// fine-grid data per XCD, read by every block of the XCD while the batch is
+// warm in L2 and the last-level cache; blocks cannot be kept in step within a
+// launch, but launch boundaries are barriers), and the partial images
+// accumulate across launches in a fixed order.  The grid is one generation (at
+// most four blocks per CU).  A thread accumulates VPT voxels (row-major, so neighbouring threads read
+// neighbouring leg records).  The trace loop is a three-stage pipeline over
+// two register sets in turn: while trace t accumulates, the fine-grid samples
+// of trace t + 1 and the legs of trace t + 2 are in flight.  All loads are raw
+// buffer loads (unconditional; a per-trace resource makes positions outside
+// the record read as zero); traces past the batch are read at its last trace
+// and weighted by zero.
 template <bool ABSW, int VPT, int ST>
 __global__ __launch_bounds__(256) void k_gather(
     const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
@@ -351,9 +372,14 @@ __global__ __launch_bounds__(256) void k_gather(
   if (t0 >= t1 && t_off > 0) return;  // uniform over the block: nothing to add
   const int sh = 32 - qs;
   const int half = n_off / 2;
+  const __amdgpu_buffer_rsrc_t leg_rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, nz * n_off * int(sizeof(Leg)), kBufferWord3);
+  const int fine_bytes = MQ * int(sizeof(typename Store<ST>::T));
+  struct Legs { int64_t da[VPT], db[VPT]; float pa[VPT], pb[VPT]; };
+  struct Taps { unsigned J[VPT]; float phi[VPT], w[VPT]; };
+  struct Samples { float c0[VPT], c1[VPT]; };
   for (int vc = v_begin; vc < v_end; vc += blockDim.x * VPT) {
-    int col[VPT];
-    const Leg* lrow[VPT];
+    int col2[VPT], rowoff[VPT];
     bool ok[VPT];
     float acc[VPT];
 #pragma unroll
@@ -362,34 +388,81 @@ __global__ __launch_bounds__(256) void k_gather(
       ok[u] = v < v_end;
       const int vv = ok[u] ? v : v_begin;
       const int row = vv / nx;
-      col[u] = vv - row * nx;
-      lrow[u] = legs + size_t(row) * n_off;
+      col2[u] = 2 * (vv - row * nx);
+      rowoff[u] = row * n_off;
       acc[u] = 0.0f;
     }
-    for (int t = t0; t < t1; ++t) {
+    auto load_legs = [&](Legs& L, int t) {
+      t = min(t, t1 - 1);
       const int btx = base[t / K], brx = base[P + t];
-      const typename Store<ST>::T* c = fine + size_t(t) * MQ;
-      Leg a[VPT], b[VPT];
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
-        a[u] = lrow[u][leg_slot(abs(btx + 2 * col[u]), half)];
-        b[u] = lrow[u][leg_slot(abs(brx + 2 * col[u]), half)];
+        const int oa = (rowoff[u] + leg_slot(abs(btx + col2[u]), half)) * int(sizeof(Leg));
+        const int ob = (rowoff[u] + leg_slot(abs(brx + col2[u]), half)) * int(sizeof(Leg));
+        const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, oa, 0, 0);
+        const auto b = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ob, 0, 0);
+        L.pa[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, oa + 8, 0, 0));
+        L.pb[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ob + 8, 0, 0));
+        L.da[u] = int64_t((uint64_t(a[1]) << 32) | a[0]);
+        L.db[u] = int64_t((uint64_t(b[1]) << 32) | b[0]);
       }
-      float c0[VPT], c1[VPT];
+    };
+    auto taps_of = [&](const Legs& L, Taps& T, int t) {
+      const float live = t < t1 ? 1.0f : 0.0f;  // steps past the batch add nothing
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
-        const int J = int(uint64_t(a[u].delay + b[u].delay) >> sh);
-        // unsigned compares: a position past 2^31 (never reached by a valid record) reads nothing
-        c0[u] = unsigned(J) < unsigned(MQ) ? Store<ST>::get(c[J]) : 0.0f;
-        c1[u] = unsigned(J + 1) < unsigned(MQ) ? Store<ST>::get(c[J + 1]) : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < VPT; ++u) {
-        const uint64_t D = uint64_t(a[u].delay + b[u].delay);
-        const float phi = float(uint32_t(D) << qs) * kTwoM32;
-        float w = a[u].apod * b[u].apod;
+        const uint64_t D = uint64_t(L.da[u] + L.db[u]);
+        // positions past the record (or past 2^31) clamp to MQ and read zero
+        T.J[u] = unsigned(min(D >> sh, uint64_t(MQ)));
+        T.phi[u] = float(uint32_t(D) << qs) * kTwoM32;
+        float w = L.pa[u] * L.pb[u];
         if (ABSW) w = fabsf(w);
-        acc[u] = fmaf(w, fmaf(phi, c1[u] - c0[u], c0[u]), acc[u]);
+        T.w[u] = w * live;
+      }
+    };
+    auto load_samples = [&](const Taps& T, Samples& S, int t) {
+      t = min(t, t1 - 1);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<typename Store<ST>::T*>(fine + size_t(t) * MQ), 0, fine_bytes, kBufferWord3);
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        S.c0[u] = fine_at<ST>(rs, T.J[u]);
+        S.c1[u] = fine_at<ST>(rs, T.J[u] + 1u);
+      }
+    };
+    auto add = [&](const Taps& T, const Samples& S) {
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) acc[u] = fmaf(T.w[u], fmaf(T.phi[u], S.c1[u] - S.c0[u], S.c0[u]), acc[u]);
+    };
+    if (t0 < t1) {
+      Legs L0, L1;
+      Taps T0, T1;
+      Samples S0, S1;
+      load_legs(L0, t0);
+      taps_of(L0, T0, t0);
+      // issued in the loop's steady-state order (legs, then samples), so the
+      // waits at the loop head stay partial
+      load_legs(L1, t0 + 1);
+      load_samples(T0, S0, t0);
+      // the scheduling barriers keep each stage's loads ahead of the waits of
+      // the stages after it
+      for (int t = t0; t < t1; t += 2) {
+        // trace t: T0 / S0 (in flight); trace t + 1: L1 (in flight)
+        load_legs(L0, t + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        taps_of(L1, T1, t + 1);
+        load_samples(T1, S1, t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        add(T0, S0);
+        __builtin_amdgcn_sched_barrier(0);
+        // trace t + 1: T1 / S1 (in flight); trace t + 2: L0 (in flight)
+        load_legs(L1, t + 3);
+        __builtin_amdgcn_sched_barrier(0);
+        taps_of(L0, T0, t + 2);
+        load_samples(T0, S0, t + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        add(T1, S1);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
@@ -1212,12 +1285,11 @@ int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale,
   nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
   const int vpb = (G.voxels() + nb - 1) / nb;
   dim3 grid(G.trace_groups, nb);
-  // traces per launch: all of a group when its fine-grid data fit the XCD's L2
-  // twice over, else batches of about 2 MB
+  // traces per launch: batches of about 8 MB of fine-grid data per group (on
+  // the 512 x 512 workload 8 MB batches measured 15 % faster than 2 MB ones and
+  // 25 % faster than one launch over all traces)
   const size_t trace_bytes = size_t(MQ) * G.elem();
-  const int batch = size_t(tpg) * trace_bytes <= (size_t(8) << 20)
-                        ? tpg
-                        : std::max(1, std::min(tpg, int((size_t(2) << 20) / trace_bytes)));
+  const int batch = std::max(1, std::min(tpg, int((size_t(8) << 20) / trace_bytes)));
   for (int t_off = 0; t_off < tpg; t_off += batch) {
     switch (G.storage) {
       case UMBIR_STORAGE_F16:
