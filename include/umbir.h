@@ -224,6 +224,28 @@ int umbir_solver_read(umbir_solver* solver, float* x_dev, float* g_dev, double* 
 size_t umbir_solver_state_bytes(const umbir_solver* solver);
 void umbir_solver_free(umbir_solver* solver);
 
+/* Batched sessions, for many problems at once (of any mix of shapes): one
+ * call advances every session of the batch, and the problems run side by
+ * side on four internal streams (session i on stream i mod 4), forked from
+ * and joined back to the caller's stream.  UMBIR_BATCH_STREAMS launches each
+ * session's own captured iteration graph on its stream; UMBIR_BATCH_GRAPH
+ * replays one graph per iteration that was captured once across the four
+ * streams (one chain of sessions per stream) and holds every session's
+ * iteration.  Each session's results are bitwise those of stepping it alone.
+ * The
+ * sessions must outlive the batch, must all live on the current device, and
+ * may appear once each.  While in a batch a session may be read
+ * (umbir_solver_read) but must not be stepped alone: umbir_batch_step returns
+ * EINVAL if any session's iteration count no longer matches the batch, or if
+ * a step would pass a session's max_iter.  umbir_batch_free (like
+ * umbir_solver_free) first waits for the last launch it queued to end.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+typedef struct umbir_batch umbir_batch;
+enum { UMBIR_BATCH_STREAMS = 0, UMBIR_BATCH_GRAPH = 1 };
+int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_batch** out);
+int umbir_batch_step(umbir_batch* batch, int n_iter, void* stream);
+void umbir_batch_free(umbir_batch* batch);
+
 /* Dimensions of a built geometry, for callers that size buffers. */
 typedef struct {
     int nx, nz, n_scans, n_rx, n_samples;
@@ -235,6 +257,30 @@ typedef struct {
     int storage;      /* UMBIR_STORAGE_* of trace buffers */
 } umbir_dims;
 int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
+
+/* Launch shapes of the sweeps, tunable per problem shape.  Neither changes a
+ * result beyond rounding order, nor any memory size:
+ *  splat_blocks     target workgroup count of the splat: the fine grid of each
+ *                   trace is cut into ceil(splat_blocks / traces) chunks of at
+ *                   least 1024 positions.  Results are bitwise identical for
+ *                   every value (the splat sums in fixed point).
+ *  gather_batch_kb  fine-grid KiB of each trace group per gather launch (at
+ *                   least one trace per launch).  Changes only the order of
+ *                   the adjoint's sums across launches.
+ * A field of 0 (or less) in umbir_set_tuning keeps the current value.  The
+ * tuning of a geometry must not change while another call uses it.
+ * umbir_autotune times candidates of each field on `stream` (the forward for
+ * the splat, the adjoint for the gather, a dense all-ones image), applies the
+ * fastest and writes the chosen values to *chosen (may be NULL); it allocates
+ * its own workspace and synchronizes the stream.  Errors: EINVAL, ENOMEM,
+ * EDEVICE. */
+typedef struct {
+    int splat_blocks;
+    int gather_batch_kb;
+} umbir_tuning;
+int umbir_get_tuning(const umbir_geometry* geom, umbir_tuning* out);
+int umbir_set_tuning(umbir_geometry* geom, const umbir_tuning* tuning);
+int umbir_autotune(umbir_geometry* geom, void* stream, umbir_tuning* chosen);
 
 /* Copies a resident table to host memory (synchronous), for inspection:
  *  UMBIR_TABLE_DELAY  int64 [nz][n_off]  one-way leg delay, Q32.32 samples

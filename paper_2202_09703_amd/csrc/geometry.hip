@@ -155,6 +155,27 @@ bool lattice_base(double x0, double dx, double x, long* out) {
   return true;
 }
 
+}  // namespace
+
+// Fine-grid chunks and LDS tiles of the splat sweep for a target workgroup
+// count: ceil(target / traces) chunks per trace of at least 1024 positions,
+// swept in 32 KiB tiles (4096 64-bit positions), three workgroups of eight
+// waves per CU.
+void apply_splat_blocks(umbir_geometry* G, long target) {
+  const long MQ = long(G->M) * G->Q;
+  const long min_chunk = 1024;
+  long chunks = (target + G->traces() - 1) / G->traces();
+  const long max_chunks = (MQ + min_chunk - 1) / min_chunk;
+  if (chunks > max_chunks) chunks = max_chunks;
+  if (chunks < 1) chunks = 1;
+  G->splat_blocks = int(std::min<long>(target, 1L << 30));
+  G->chunks = int(chunks);
+  G->chunk_bins = (MQ + chunks - 1) / chunks;
+  G->tile_bins = int(std::min<long>(4096, G->chunk_bins));
+}
+
+namespace {
+
 struct Derived {
   int Lh = 0, n_off = 0;
   std::vector<int> base;  // [P + P*K]
@@ -398,18 +419,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
       }
       G->seg_hi[G->n_seg - 1] = r + 1;
     }
-    // fine-grid chunks and LDS tiles of the splat sweep: aim for >= 2048 workgroups
-    const long MQ = long(G->M) * G->Q;
-    const long min_chunk = 1024;
-    long chunks = (2048 + G->traces() - 1) / G->traces();
-    const long max_chunks = (MQ + min_chunk - 1) / min_chunk;
-    if (chunks > max_chunks) chunks = max_chunks;
-    if (chunks < 1) chunks = 1;
-    G->chunks = int(chunks);
-    G->chunk_bins = (MQ + chunks - 1) / chunks;
-    // 16 KiB tiles: small enough for 8 workgroups per CU, which the splat's
-    // memory round trips need to overlap
-    G->tile_bins = int(std::min<long>(4096, G->chunk_bins));
+    apply_splat_blocks(G, G->splat_blocks);
   }
 
   const size_t legs = size_t(G->nz) * G->n_off;
@@ -489,6 +499,20 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
 }
 
 size_t umbir_geometry_bytes(const umbir_geometry* G) { return G ? G->bytes : 0; }
+
+int umbir_get_tuning(const umbir_geometry* G, umbir_tuning* out) {
+  if (!G || !out) return fail(UMBIR_EINVAL, "NULL argument");
+  out->splat_blocks = G->splat_blocks;
+  out->gather_batch_kb = G->gather_batch_kb;
+  return UMBIR_OK;
+}
+
+int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
+  if (!G || !t) return fail(UMBIR_EINVAL, "NULL argument");
+  if (t->splat_blocks > 0) apply_splat_blocks(G, t->splat_blocks);
+  if (t->gather_batch_kb > 0) G->gather_batch_kb = t->gather_batch_kb;
+  return UMBIR_OK;
+}
 
 int umbir_get_dims(const umbir_geometry* G, umbir_dims* d) {
   if (!G || !d) return fail(UMBIR_EINVAL, "NULL argument");

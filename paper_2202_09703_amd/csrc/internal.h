@@ -104,6 +104,9 @@ struct umbir_geometry {
   int chunks = 1;
   long chunk_bins = 0;
   int tile_bins = 0;
+  // tunable launch shapes (umbir_tuning)
+  int splat_blocks = 2048;     // target splat workgroups; sets chunks, chunk_bins, tile_bins
+  int gather_batch_kb = 8192;  // fine-grid KiB per trace group per gather launch
   // resident device tables
   umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows
   float* tau = nullptr;      // [nz] transmittance product of the row's layer
@@ -127,6 +130,8 @@ struct umbir_geometry {
 };
 
 namespace umbir {
+
+void apply_splat_blocks(umbir_geometry* G, long target);
 
 // Kernel launchers shared between translation units.  All return a status.
 int launch_fill(float* p, size_t n, float v, hipStream_t s);

@@ -20,6 +20,7 @@
 // (sum of two one-way legs, added exactly as integers), so J and phi are exact.
 
 #include <algorithm>
+#include <vector>
 #include <cmath>
 
 #include "internal.h"
@@ -1285,11 +1286,12 @@ int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale,
   nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
   const int vpb = (G.voxels() + nb - 1) / nb;
   dim3 grid(G.trace_groups, nb);
-  // traces per launch: batches of about 8 MB of fine-grid data per group (on
-  // the 512 x 512 workload 8 MB batches measured 15 % faster than 2 MB ones and
-  // 25 % faster than one launch over all traces)
+  // traces per launch: batches of gather_batch_kb of fine-grid data per group
+  // (8 MB by default: on the 512 x 512 workload 8 MB batches measured 15 %
+  // faster than 2 MB ones and 25 % faster than one launch over all traces)
   const size_t trace_bytes = size_t(MQ) * G.elem();
-  const int batch = std::max(1, std::min(tpg, int((size_t(8) << 20) / trace_bytes)));
+  const int batch =
+      int(std::max<size_t>(1, std::min<size_t>(tpg, (size_t(G.gather_batch_kb) << 10) / trace_bytes)));
   for (int t_off = 0; t_off < tpg; t_off += batch) {
     switch (G.storage) {
       case UMBIR_STORAGE_F16:
@@ -1396,6 +1398,72 @@ int umbir_sqs_denominator(const umbir_geometry* G, double sigma, float* d, void*
   void* col = cv.take<char>(G->trace_bytes());
   if ((st = run_forward(*G, nullptr, col, nullptr, 1.0f, nullptr, true, fine, s))) return st;
   return run_adjoint(*G, col, d, float(1.0 / (sigma * sigma)), true, fine, partial, s);
+}
+
+int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
+  if (!G) return fail(UMBIR_EINVAL, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t wb = adjoint_work_bytes(*G), tb = aligned(G->trace_bytes());
+  Workspace ws;
+  int st = ws.acquire(nullptr, 0, wb + tb + aligned(size_t(G->voxels()) * sizeof(float)), s);
+  if (st) return st;
+  Carve cv{static_cast<char*>(ws.ptr)};
+  void* fine = cv.take<char>(G->fine_bytes());
+  float* partial = cv.take<float>(size_t(G->trace_groups) * G->voxels());
+  char* traces = static_cast<char*>(ws.ptr) + wb;
+  float* img = reinterpret_cast<float*>(traces + tb);
+  if ((st = check_hip(hipMemsetAsync(traces, 0, G->trace_bytes(), s), "hipMemsetAsync"))) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((st = check_hip(hipEventCreate(&e0), "hipEventCreate")) || (st = check_hip(hipEventCreate(&e1), "hipEventCreate"))) {
+    if (e0) (void)hipEventDestroy(e0);
+    return st;
+  }
+  // average of three runs after one warm-up; the image is all ones (x = NULL)
+  auto time_ms = [&](auto&& run, float* ms) {
+    int r = run();
+    if (!r) r = check_hip(hipEventRecord(e0, s), "hipEventRecord");
+    for (int k = 0; k < 3 && !r; ++k) r = run();
+    if (!r) r = check_hip(hipEventRecord(e1, s), "hipEventRecord");
+    if (!r) r = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    if (!r) r = check_hip(hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime");
+    *ms /= 3.0f;
+    return r;
+  };
+  auto forward = [&]() { return run_forward(*G, nullptr, traces, nullptr, 1.0f, nullptr, false, fine, s); };
+  auto adjoint = [&]() { return run_adjoint(*G, traces, img, 1.0f, false, fine, partial, s); };
+  // the splat: one to four chunks per trace, and fixed workgroup targets
+  const long PK = G->traces();
+  std::vector<long> cand = {PK, 2 * PK, 4 * PK, 1024, 2048, 4096};
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  long best_blocks = G->splat_blocks;
+  float best = 3.4e38f;
+  for (long c : cand) {
+    apply_splat_blocks(G, c);
+    float ms = 0.0f;
+    if ((st = time_ms(forward, &ms))) break;
+    if (ms < best) { best = ms; best_blocks = c; }
+  }
+  apply_splat_blocks(G, best_blocks);
+  // the gather: fine-grid KiB per trace group and launch
+  int best_kb = G->gather_batch_kb;
+  best = 3.4e38f;
+  for (int kb : {2048, 4096, 8192, 16384, 32768}) {
+    if (st) break;
+    G->gather_batch_kb = kb;
+    float ms = 0.0f;
+    if ((st = time_ms(adjoint, &ms))) break;
+    if (ms < best) { best = ms; best_kb = kb; }
+  }
+  G->gather_batch_kb = best_kb;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (chosen) {
+    chosen->splat_blocks = G->splat_blocks;
+    chosen->gather_batch_kb = G->gather_batch_kb;
+  }
+  return UMBIR_OK;
 }
 
 }  // extern "C"

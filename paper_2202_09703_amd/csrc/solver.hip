@@ -25,6 +25,8 @@
 
 #include <cmath>
 
+#include <vector>
+
 #include "internal.h"
 #include "storage.h"
 
@@ -306,7 +308,28 @@ struct umbir_solver {
   double* cost = nullptr;  // [max_iter + 1]
   int* counter = nullptr;
   hipStream_t cap = nullptr;       // private stream used to capture the graphs
-  hipGraphExec_t step[2] = {nullptr, nullptr};  // xa -> xb and xb -> xa
+  hipGraph_t graph[2] = {nullptr, nullptr};     // xa -> xb and xb -> xa (kept for batches)
+  hipGraphExec_t step[2] = {nullptr, nullptr};  // their instances
+  hipEvent_t idle = nullptr;  // recorded after the last launch of an iteration graph
+};
+
+// A batch of sessions run side by side on kBatchStreams internal streams:
+// session i belongs to stream i mod kBatchStreams.  UMBIR_BATCH_STREAMS
+// launches each session's own iteration graphs there; UMBIR_BATCH_GRAPH
+// replays one graph per image direction, captured once across the same
+// streams (fork from the first, one chain of sessions per stream, join).
+constexpr int kBatchStreams = 4;
+
+struct umbir_batch {
+  int device = -1;
+  int mode = UMBIR_BATCH_STREAMS;
+  std::vector<umbir_solver*> s;
+  std::vector<int> done;  // each session's iteration count as the batch left it
+  int parity = 0;         // exec[parity] advances every session by one (graph mode)
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipStream_t st[kBatchStreams] = {};
+  hipEvent_t fork = nullptr, join[kBatchStreams] = {};
+  hipEvent_t idle = nullptr;  // recorded after the last batch launch
 };
 
 namespace {
@@ -323,24 +346,94 @@ void solver_release(umbir_solver* S) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (S->device >= 0) (void)hipSetDevice(S->device);
+  // launches are asynchronous: no graph is destroyed before its last launch ended
+  if (S->idle) {
+    (void)hipEventSynchronize(S->idle);
+    (void)hipEventDestroy(S->idle);
+  }
   for (hipGraphExec_t& ge : S->step)
     if (ge) (void)hipGraphExecDestroy(ge);
+  for (hipGraph_t& g : S->graph)
+    if (g) (void)hipGraphDestroy(g);
   if (S->cap) (void)hipStreamDestroy(S->cap);
   if (S->mem) (void)hipFree(S->mem);
   if (cur >= 0) (void)hipSetDevice(cur);
   delete S;
 }
 
-int capture_step(umbir_solver* S, const float* x_in, float* x_out, hipGraphExec_t* out) {
-  hipGraph_t graph = nullptr;
+int capture_step(umbir_solver* S, const float* x_in, float* x_out, hipGraph_t* graph, hipGraphExec_t* out) {
   int st = check_hip(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   if (st) return st;
   const int st_enq = enqueue_iteration(*S->G, S->b, S->pc, S->inv_2s2, S->est, S->y, x_in, x_out, S->g, false,
                                        S->cost, S->counter, S->cap);
-  st = check_hip(hipStreamEndCapture(S->cap, &graph), "hipStreamEndCapture");
+  st = check_hip(hipStreamEndCapture(S->cap, graph), "hipStreamEndCapture");
   if (st_enq) st = st_enq;
-  if (!st) st = check_hip(hipGraphInstantiate(out, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-  if (graph) (void)hipGraphDestroy(graph);
+  if (!st) st = check_hip(hipGraphInstantiate(out, *graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  return st;
+}
+
+void batch_release(umbir_batch* B) {
+  if (!B) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (B->device >= 0) (void)hipSetDevice(B->device);
+  if (B->idle) {
+    (void)hipEventSynchronize(B->idle);
+    (void)hipEventDestroy(B->idle);
+  }
+  for (hipGraphExec_t& ge : B->exec)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  if (B->fork) (void)hipEventDestroy(B->fork);
+  for (int k = 0; k < kBatchStreams; ++k) {
+    if (B->join[k]) (void)hipEventDestroy(B->join[k]);
+    if (B->st[k]) (void)hipStreamDestroy(B->st[k]);
+  }
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete B;
+}
+
+// Makes the batch's streams wait for `from`, and `to` wait for all of them.
+int batch_fork(umbir_batch* B, hipStream_t from) {
+  int st = check_hip(hipEventRecord(B->fork, from), "hipEventRecord");
+  for (int k = 0; k < kBatchStreams && !st; ++k)
+    st = check_hip(hipStreamWaitEvent(B->st[k], B->fork, 0), "hipStreamWaitEvent");
+  return st;
+}
+int batch_join(umbir_batch* B, hipStream_t to) {
+  int st = UMBIR_OK;
+  for (int k = 0; k < kBatchStreams && !st; ++k) {
+    st = check_hip(hipEventRecord(B->join[k], B->st[k]), "hipEventRecord");
+    if (!st) st = check_hip(hipStreamWaitEvent(to, B->join[k], 0), "hipStreamWaitEvent");
+  }
+  return st;
+}
+
+// exec[which] runs one iteration of every session, in the image direction it
+// will be in after `which` batch steps from now: captured from the first
+// batch stream, forked to all of them, one chain of sessions per stream.
+int batch_graph(umbir_batch* B, int which, hipGraphExec_t* out) {
+  hipStream_t s0 = B->st[0];
+  int st = check_hip(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (st) return st;
+  int st_enq = check_hip(hipEventRecord(B->fork, s0), "hipEventRecord");
+  for (int k = 1; k < kBatchStreams && !st_enq; ++k)
+    st_enq = check_hip(hipStreamWaitEvent(B->st[k], B->fork, 0), "hipStreamWaitEvent");
+  for (size_t i = 0; i < B->s.size() && !st_enq; ++i) {
+    umbir_solver* S = B->s[i];
+    const bool a_to_b = (S->parity ^ which) == 0;
+    st_enq = enqueue_iteration(*S->G, S->b, S->pc, S->inv_2s2, S->est, S->y, a_to_b ? S->xa : S->xb,
+                               a_to_b ? S->xb : S->xa, S->g, false, S->cost, S->counter,
+                               B->st[i % kBatchStreams]);
+  }
+  for (int k = 1; k < kBatchStreams && !st_enq; ++k) {
+    st_enq = check_hip(hipEventRecord(B->join[k], B->st[k]), "hipEventRecord");
+    if (!st_enq) st_enq = check_hip(hipStreamWaitEvent(s0, B->join[k], 0), "hipStreamWaitEvent");
+  }
+  hipGraph_t g = nullptr;
+  st = check_hip(hipStreamEndCapture(s0, &g), "hipStreamEndCapture");
+  if (st_enq) st = st_enq;
+  if (!st) st = check_hip(hipGraphInstantiate(out, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (g) (void)hipGraphDestroy(g);
   return st;
 }
 
@@ -421,6 +514,11 @@ int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const vo
     solver_release(S);
     return st;
   }
+  if ((st = check_hip(hipEventCreateWithFlags(&S->idle, hipEventDisableTiming), "hipEventCreate"))) {
+    S->idle = nullptr;
+    solver_release(S);
+    return st;
+  }
   // state: copy of y, warm start (or zeros), curvature, cost counter at 0
   if ((st = check_hip(hipMemcpyAsync(S->y, y_dev, G->trace_bytes(), hipMemcpyDeviceToDevice, s),
                       "hipMemcpyAsync(y)")) ||
@@ -438,8 +536,8 @@ int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const vo
     return st;
   }
   // one iteration graph per direction of the image ping-pong
-  st = capture_step(S, S->xa, S->xb, &S->step[0]);
-  if (!st) st = capture_step(S, S->xb, S->xa, &S->step[1]);
+  st = capture_step(S, S->xa, S->xb, &S->graph[0], &S->step[0]);
+  if (!st) st = capture_step(S, S->xb, S->xa, &S->graph[1], &S->step[1]);
   if (st) {
     solver_release(S);
     return st;
@@ -459,7 +557,7 @@ int umbir_solver_step(umbir_solver* S, int n_iter, void* stream) {
     S->parity ^= 1;
     S->done += 1;
   }
-  return UMBIR_OK;
+  return n_iter > 0 ? check_hip(hipEventRecord(S->idle, s), "hipEventRecord") : UMBIR_OK;
 }
 
 int umbir_solver_iterations(const umbir_solver* S) { return S ? S->done : -1; }
@@ -488,5 +586,94 @@ int umbir_solver_read(umbir_solver* S, float* x_dev, float* g_dev, double* cost_
 size_t umbir_solver_state_bytes(const umbir_solver* S) { return S ? S->bytes : 0; }
 
 void umbir_solver_free(umbir_solver* S) { solver_release(S); }
+
+int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_batch** out) {
+  if (!out) return fail(UMBIR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!sessions || n <= 0) return fail(UMBIR_EINVAL, "need at least one session");
+  if (mode != UMBIR_BATCH_STREAMS && mode != UMBIR_BATCH_GRAPH) return fail(UMBIR_EINVAL, "unknown batch mode");
+  for (int i = 0; i < n; ++i) {
+    if (!sessions[i]) return fail(UMBIR_EINVAL, "NULL session");
+    for (int j = 0; j < i; ++j)
+      if (sessions[j] == sessions[i]) return fail(UMBIR_EINVAL, "session listed twice");
+  }
+  int dev = -1;
+  int st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (st) return st;
+  for (int i = 0; i < n; ++i)
+    if (sessions[i]->device != dev) return fail(UMBIR_EINVAL, "session on another device");
+  auto* B = new umbir_batch();
+  B->device = dev;
+  B->mode = mode;
+  B->s.assign(sessions, sessions + n);
+  for (umbir_solver* S : B->s) B->done.push_back(S->done);
+  auto event = [](hipEvent_t* e) {
+    const int r = check_hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+    if (r) *e = nullptr;
+    return r;
+  };
+  st = event(&B->idle);
+  if (!st) st = event(&B->fork);
+  for (int k = 0; k < kBatchStreams && !st; ++k) {
+    st = event(&B->join[k]);
+    if (!st) st = check_hip(hipStreamCreateWithFlags(&B->st[k], hipStreamNonBlocking), "hipStreamCreate");
+    if (st) B->st[k] = nullptr;
+  }
+  if (!st && mode == UMBIR_BATCH_GRAPH) st = batch_graph(B, 0, &B->exec[0]);
+  if (!st && mode == UMBIR_BATCH_GRAPH) st = batch_graph(B, 1, &B->exec[1]);
+  if (st) {
+    batch_release(B);
+    return st;
+  }
+  *out = B;
+  return UMBIR_OK;
+}
+
+int umbir_batch_step(umbir_batch* B, int n_iter, void* stream) {
+  if (!B) return fail(UMBIR_EINVAL, "batch is NULL");
+  if (n_iter < 0) return fail(UMBIR_EINVAL, "n_iter must be >= 0");
+  for (size_t i = 0; i < B->s.size(); ++i) {
+    const umbir_solver* S = B->s[i];
+    if (S->done != B->done[i]) return fail(UMBIR_EINVAL, "a session was stepped outside its batch");
+    if (S->done + n_iter > S->max_iter) return fail(UMBIR_EINVAL, "n_iter would exceed a session's max_iter");
+  }
+  if (n_iter == 0) return UMBIR_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = UMBIR_OK;
+  if (B->mode == UMBIR_BATCH_GRAPH) {
+    for (int k = 0; k < n_iter && !st; ++k) {
+      st = check_hip(hipGraphLaunch(B->exec[B->parity], s), "hipGraphLaunch");
+      if (st) break;
+      B->parity ^= 1;
+      for (umbir_solver* S : B->s) {
+        S->parity ^= 1;
+        S->done += 1;
+      }
+    }
+  } else {
+    // each session's n_iter iterations in a row on its stream, between one
+    // fork from and one join to the caller's stream
+    st = batch_fork(B, s);
+    for (size_t i = 0; i < B->s.size() && !st; ++i) {
+      umbir_solver* S = B->s[i];
+      for (int k = 0; k < n_iter && !st; ++k) {
+        st = check_hip(hipGraphLaunch(S->step[S->parity], B->st[i % kBatchStreams]), "hipGraphLaunch");
+        if (st) break;
+        S->parity ^= 1;
+        S->done += 1;
+      }
+    }
+    if (!st) st = batch_join(B, s);
+  }
+  for (size_t i = 0; i < B->s.size(); ++i) B->done[i] = B->s[i]->done;
+  if (st) return st;
+  // the batch and every session it ran wait for these launches before freeing
+  st = check_hip(hipEventRecord(B->idle, s), "hipEventRecord");
+  for (umbir_solver* S : B->s)
+    if (!st) st = check_hip(hipEventRecord(S->idle, s), "hipEventRecord");
+  return st;
+}
+
+void umbir_batch_free(umbir_batch* B) { batch_release(B); }
 
 }  // extern "C"

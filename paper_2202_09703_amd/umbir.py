@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from typing import Optional
 
 import numpy as np
 
@@ -33,6 +34,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, EDIVERGED = 0, -1, -2, -3, -4, -5
 STORAGE_F32, STORAGE_F16, STORAGE_BF16 = 0, 1, 2
 TRACE_DTYPES = {STORAGE_F32: torch.float32, STORAGE_F16: torch.float16, STORAGE_BF16: torch.bfloat16}
 WORK_FORWARD, WORK_ADJOINT, WORK_RECONSTRUCT = 0, 1, 2
+BATCH_STREAMS, BATCH_GRAPH = 0, 1
 TABLE_DELAY, TABLE_APOD, TABLE_TAU, TABLE_BANK, TABLE_DBASIS, TABLE_OFFSET = range(6)
 MAX_LAYERS = 8
 
@@ -77,6 +79,10 @@ class _Dims(C.Structure):
                 ("storage", C.c_int)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("splat_blocks", C.c_int), ("gather_batch_kb", C.c_int)]
+
+
 class _KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_longlong), ("total_ms", C.c_double)]
 
@@ -95,6 +101,9 @@ _SIGS = {
     "umbir_reconstruct": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "umbir_get_dims": (_i, [_vp, C.POINTER(_Dims)]),
     "umbir_copy_table": (_i, [_vp, _i, _vp, _sz]),
+    "umbir_get_tuning": (_i, [_vp, C.POINTER(_Tuning)]),
+    "umbir_set_tuning": (_i, [_vp, C.POINTER(_Tuning)]),
+    "umbir_autotune": (_i, [_vp, _vp, C.POINTER(_Tuning)]),
     "umbir_solver_bytes": (_sz, [_vp, _i]),
     "umbir_solver_create": (_i, [_vp, C.POINTER(_Prior), _vp, _vp, _vp, _i, _vp, C.POINTER(_vp)]),
     "umbir_solver_step": (_i, [_vp, _i, _vp]),
@@ -102,6 +111,9 @@ _SIGS = {
     "umbir_solver_read": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "umbir_solver_state_bytes": (_sz, [_vp]),
     "umbir_solver_free": (None, [_vp]),
+    "umbir_batch_create": (_i, [C.POINTER(_vp), _i, _i, C.POINTER(_vp)]),
+    "umbir_batch_step": (_i, [_vp, _i, _vp]),
+    "umbir_batch_free": (None, [_vp]),
     "umbir_profile_enable": (None, [_i]),
     "umbir_profile_collect": (_i, [C.POINTER(_KernelTime), _i, C.POINTER(_i)]),
     "umbir_strerror": (C.c_char_p, [_i]),
@@ -195,6 +207,35 @@ class Geometry:
         if not self._h:
             raise ValueError("geometry has been freed")
         return self._h
+
+    @property
+    def shape_key(self):
+        """What the launch-shape tuning depends on."""
+        return (self.nx, self.nz, self.n_scans, self.n_rx, self.n_samples, self.oversample, self.window,
+                self.n_layers, self.storage)
+
+    def tuning(self) -> dict:
+        t = _Tuning()
+        _check(_lib.umbir_get_tuning(self.handle, C.byref(t)), "umbir_get_tuning")
+        return {"splat_blocks": t.splat_blocks, "gather_batch_kb": t.gather_batch_kb}
+
+    def set_tuning(self, splat_blocks: int = 0, gather_batch_kb: int = 0):
+        t = _Tuning(int(splat_blocks), int(gather_batch_kb))
+        _check(_lib.umbir_set_tuning(self.handle, C.byref(t)), "umbir_set_tuning")
+
+    def autotune(self, stream=None, cache: Optional[dict] = None) -> dict:
+        """Time the tuning candidates on the device (umbir_autotune) and keep
+        the fastest; with a cache, shapes seen before reuse their result."""
+        key = self.shape_key
+        if cache is not None and key in cache:
+            self.set_tuning(**cache[key])
+            return dict(cache[key])
+        t = _Tuning()
+        _check(_lib.umbir_autotune(self.handle, _stream(stream), C.byref(t)), "umbir_autotune")
+        res = {"splat_blocks": t.splat_blocks, "gather_batch_kb": t.gather_batch_kb}
+        if cache is not None:
+            cache[key] = dict(res)
+        return res
 
     @property
     def image_shape(self):
@@ -384,6 +425,38 @@ class Solver:
     def free(self):
         if self._h:
             _lib.umbir_solver_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many resident sessions advanced together (umbir_batch_*): one graph
+    launch runs one iteration of every session, side by side on the device."""
+
+    def __init__(self, sessions, mode: int = 0):
+        self.sessions = list(sessions)
+        arr = (C.c_void_p * len(self.sessions))(*[s.handle.value for s in self.sessions])
+        h = C.c_void_p()
+        _check(_lib.umbir_batch_create(arr, len(self.sessions), int(mode), C.byref(h)), "umbir_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("batch has been freed")
+        return self._h
+
+    def step(self, n_iter: int, stream=None):
+        _check(_lib.umbir_batch_step(self.handle, int(n_iter), _stream(stream)), "umbir_batch_step")
+
+    def free(self):
+        if self._h:
+            _lib.umbir_batch_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -230,4 +230,54 @@ def tiny_card(n_layers: int = 2, nx: int = 12, nz: int = 10, n_scans: int = 2,
         snr_db=20.0, noise_seed=seed + 50, n_iter=10)
 
 
+def _reflectivity(z1: float, z2: float) -> float:
+    # (Z2 - Z1)/(Z2 + Z1) of a phantom interface, Z = density * speed
+    return (z2 - z1) / (z2 + z1)
+
+
+def batch_cards(n: int = 48, seed: int = 11):
+    """Seeded uneven problems for the batched workload: square grids of 128 to
+    384 voxels a side (0.5 mm), three or four layers with seeded speeds and
+    thicknesses (water / steel / cement / rock), 4 to 16 scan positions 4 mm
+    apart, 8 to 32 receivers at 5 mm pitch, 1024 to 4096 samples at 20 MHz,
+    point reflectors plus the interface rows, 15 dB, 20 to 50 iterations.
+    Every transducer sits on the grid's half-voxel lattice."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    cards = []
+    for i in range(n):
+        side = int(rng.choice(np.arange(128, 385, 32)))
+        n_layers = int(rng.integers(3, 5))
+        c = (float(rng.uniform(1450, 1520)), float(rng.uniform(5800, 6000)),
+             float(rng.uniform(2800, 3400)), float(rng.uniform(4200, 4800)))[:n_layers]
+        rho = (1000.0, 7850.0, 1900.0, 2600.0)[:n_layers]
+        depth = side * 0.5 * MM
+        thick = [float(rng.uniform(8, 12)) * MM, float(rng.uniform(6, 10)) * MM]
+        if n_layers == 4:
+            thick.append(float(rng.uniform(0.3, 0.6)) * depth)
+        names = ("water", "steel", "cement", "rock")[:n_layers]
+        med = Medium(speed=c, thickness=tuple(thick), atten=(0.0,) * n_layers, density=rho, names=names)
+        n_scans = int(rng.integers(4, 17))
+        n_rx = int(rng.integers(8, 33))
+        n_samples = int(rng.choice(np.arange(1024, 4097, 512)))
+        tops = np.cumsum(thick)
+        rows = [int(round(t / (0.5 * MM))) for t in tops]
+        interfaces = tuple((r, round(_reflectivity(rho[k] * c[k], rho[k + 1] * c[k + 1]), 4))
+                           for k, r in enumerate(rows) if r < side)
+        cards.append(Card(
+            name=f"b{i}-{side}x{side}-{n_layers}L-{n_scans}x{n_rx}-{n_samples}",
+            medium=med,
+            grid=Grid(nx=side, nz=side, dx=0.5 * MM, dz=0.5 * MM, x0=-side * 0.25 * MM),
+            array=Array(tx_x=tuple((-2.0 * (n_scans - 1) + 4.0 * k) * MM for k in range(n_scans)),
+                        rx_offset=tuple((j - (n_rx - 1) / 2) * 5 * MM for j in range(n_rx)), beta=8),
+            acq=Acquisition(n_samples=n_samples, fs=20 * MHZ, f_c=0.5 * MHZ, sigma_t=1.25 * US,
+                            t_win=12 * US, oversample=32),
+            prior=Prior(),
+            phantom=PhantomSpec(seed=1000 + i, n_reflectors=side // 8, amp_lo=0.3, amp_hi=1.0,
+                                rows=(rows[1] + 4 if rows[1] + 4 < side - 4 else side // 2, side - 4),
+                                cols=(8, side - 8), min_spacing=4, interfaces=interfaces),
+            snr_db=15.0, noise_seed=2000 + i, n_iter=int(rng.integers(20, 51))))
+    return cards
+
+
 CARDS = {"c1": card_c1, "c2": card_c2, "c3": card_c3}

@@ -136,3 +136,23 @@ def test_solver_arguments_checked_before_any_device_call():
     assert lib.umbir_solver_iterations(None) == -1
     assert lib.umbir_solver_bytes(None, 3) == 0
     lib.umbir_solver_free(None)
+
+
+def test_tuning_and_batch_arguments_checked_before_any_device_call():
+    lib = umbir._lib
+    t = umbir._Tuning(1024, 4096)
+    assert lib.umbir_get_tuning(None, C.byref(t)) == umbir.EINVAL
+    assert lib.umbir_set_tuning(None, C.byref(t)) == umbir.EINVAL
+    assert lib.umbir_autotune(None, None, C.byref(t)) == umbir.EINVAL
+    out = C.c_void_p()
+    assert lib.umbir_batch_create(None, 2, 0, C.byref(out)) == umbir.EINVAL
+    one = (C.c_void_p * 1)(16)
+    assert lib.umbir_batch_create(one, 0, 0, C.byref(out)) == umbir.EINVAL
+    assert lib.umbir_batch_create(one, 1, 0, None) == umbir.EINVAL
+    assert lib.umbir_batch_create(one, 1, 7, C.byref(out)) == umbir.EINVAL  # unknown mode
+    nul = (C.c_void_p * 2)(16, None)
+    assert lib.umbir_batch_create(nul, 2, 0, C.byref(out)) == umbir.EINVAL
+    dup = (C.c_void_p * 2)(16, 16)
+    assert lib.umbir_batch_create(dup, 2, 1, C.byref(out)) == umbir.EINVAL
+    assert lib.umbir_batch_step(None, 1, None) == umbir.EINVAL
+    lib.umbir_batch_free(None)

@@ -1,0 +1,114 @@
+"""Launch-shape tuning and batched sessions (many problems advanced by one
+graph launch per iteration) through the C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import card_c1, tiny_card, random_vector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+umbir = pytest.importorskip("paper_2202_09703_amd.umbir")
+batch = pytest.importorskip("paper_2202_09703_amd.batch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def f32(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+
+
+@pytest.mark.parametrize("name,card", [("tiny", tiny_card(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=4)),
+                                       ("c1", card_c1())])
+def test_tuning_changes_no_result(dev, name, card):
+    """Any splat split gives bitwise the same forward; gather batches change
+    only the order of the adjoint's cross-launch sums."""
+    geom = umbir.build_geometry(card)
+    g = card.grid
+    x = f32(random_vector((g.nz, g.nx), seed=3), dev)
+    r = f32(random_vector(geom.trace_shape, seed=4), dev)
+    y0, a0 = umbir.forward(geom, x), umbir.adjoint(geom, r)
+    t0 = geom.tuning()
+    assert t0["splat_blocks"] > 0 and t0["gather_batch_kb"] > 0
+    for blocks, kb in [(1, 1), (geom.n_scans * geom.n_rx * 4, 64), (100000, 1 << 20)]:
+        geom.set_tuning(splat_blocks=blocks, gather_batch_kb=kb)
+        assert torch.equal(umbir.forward(geom, x), y0)
+        a = umbir.adjoint(geom, r)
+        assert torch.allclose(a, a0, rtol=1e-6, atol=1e-6 * float(a0.abs().max()))
+    chosen = geom.autotune()
+    assert chosen == geom.tuning() and chosen["splat_blocks"] > 0 and chosen["gather_batch_kb"] > 0
+    assert torch.equal(umbir.forward(geom, x), y0)
+    # zeros keep the current values; a cache reuses the choice for the same shape
+    geom.set_tuning(0, 0)
+    assert geom.tuning() == chosen
+    cache = {}
+    assert geom.autotune(cache=cache) == geom.autotune(cache=cache)
+    assert len(cache) == 1
+
+
+def _problems(dev):
+    cards = [dataclasses.replace(tiny_card(n_layers=3, nx=12, nz=10, n_scans=2, n_rx=3, n_samples=200), n_iter=7),
+             dataclasses.replace(tiny_card(n_layers=2, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300), n_iter=4),
+             dataclasses.replace(card_c1(), n_iter=10)]
+    return batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_equals_one_at_a_time(dev, mode):
+    probs = _problems(dev)
+    _, plain = batch.run_plain(umbir, probs)
+    _, batched, rebuilds = batch.run_batched(umbir, probs, mode)
+    assert rebuilds == 3  # the problems leave the batch at 4, 7 and 10 iterations
+    for p, a, b in zip(probs, plain, batched):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), p["card"].name
+        assert torch.equal(a[2], b[2]) and a[2].numel() == p["n_iter"] + 1
+    # and the one-at-a-time session equals the one-shot reconstruction
+    p = probs[2]
+    x, g, cost = umbir.reconstruct(p["geom"], p["card"].prior, p["sigma"], p["y"], p["n_iter"])
+    assert torch.equal(x, plain[2][0]) and torch.equal(cost, plain[2][2])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_guards(dev, mode):
+    probs = _problems(dev)[:2]
+    ss = batch.sessions(umbir, probs)
+    b = umbir.Batch(ss, mode)
+    b.step(2)
+    torch.cuda.synchronize()
+    assert [s.iterations for s in ss] == [2, 2]
+    with pytest.raises(umbir.UmbirError):
+        b.step(3)  # the second problem allows 4 iterations
+    ss[0].step(1)  # stepped alone: the batch no longer matches it
+    with pytest.raises(umbir.UmbirError):
+        b.step(1)
+    b.free()
+    with pytest.raises(umbir.UmbirError):
+        umbir.Batch([ss[0], ss[0]], mode)
+    for s in ss:
+        s.free()
+
+
+def test_free_right_after_step_waits_for_the_launches(dev):
+    """umbir_batch_free and umbir_solver_free wait for the graph launches they
+    queued: a batch freed at once after a long step leaves its sessions' work
+    intact, and equal to stepping them one at a time."""
+    cards = [dataclasses.replace(card_c1(), n_iter=30), dataclasses.replace(card_c1(), n_iter=30)]
+    probs = batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None)
+    _, plain = batch.run_plain(umbir, probs)
+    ss = batch.sessions(umbir, probs)
+    b = umbir.Batch(ss, umbir.BATCH_GRAPH)
+    b.step(30)
+    b.free()
+    out = [s.read() for s in ss]
+    torch.cuda.synchronize()
+    for a, o in zip(plain, out):
+        assert torch.equal(a[0], o[0]) and torch.equal(a[2], o[2])
+    for s in ss:
+        s.free()
