@@ -105,7 +105,7 @@ struct umbir_geometry {
   long chunk_bins = 0;
   int tile_bins = 0;
   // tunable launch shapes (umbir_tuning)
-  int splat_blocks = 2048;     // target splat workgroups; sets chunks, chunk_bins, tile_bins
+  int splat_blocks = 512;      // target splat workgroups; sets chunks, chunk_bins, tile_bins
   int gather_batch_kb = 8192;  // fine-grid KiB per trace group per gather launch
   // resident device tables
   umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows

@@ -182,8 +182,8 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
   unsigned long long* tile = smem;                                   // [tile_bins + 2]
-  int* ptr = reinterpret_cast<int*>(smem + tile_bins + 2);           // [seg.n][nx] next row
-  int* nxt = ptr + seg.n * nx;                                       // [seg.n][nx] its fine position
+  int2* pn = reinterpret_cast<int2*>(smem + tile_bins + 2);          // [seg.n][nx] {next row, its position}
+  int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of row 0's records
   __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
   const int kx = splat_exponent(*xmax, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
   const double scale = ldexp(1.0, kx);
@@ -201,12 +201,15 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     lay_lo[threadIdx.x] = kNoRow;
     lay_hi[threadIdx.x] = -kNoRow;
   }
+  for (int c = threadIdx.x; c < nx; c += blockDim.x)
+    colofs[c] = make_int2(leg_slot(abs(btx + 2 * c), half) * int(sizeof(Leg)),
+                          leg_slot(abs(brx + 2 * c), half) * int(sizeof(Leg)));
   __syncthreads();
   // first row of each (column, layer) whose position is >= J_begin - 1
   for (int i = threadIdx.x; i < seg.n * nx; i += blockDim.x) {
     const int sg = i / nx, c = i - sg * nx;
-    const Leg* ltx = legs + leg_slot(abs(btx + 2 * c), half);
-    const Leg* lrx = legs + leg_slot(abs(brx + 2 * c), half);
+    const Leg* ltx = legs + colofs[c].x / int(sizeof(Leg));
+    const Leg* lrx = legs + colofs[c].y / int(sizeof(Leg));
     auto pos = [&](int r) {
       const size_t o = size_t(r) * n_off;
       return int(uint64_t(ltx[o].delay + lrx[o].delay) >> sh);
@@ -216,8 +219,8 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     atomicMin(&lay_lo[sg], jl);
     atomicMax(&lay_hi[sg], jh);
     int jf;
-    ptr[i] = first_row_at(pos, lo, hi, jl, jh, J_begin - 1, &jf);
-    nxt[i] = jf;
+    const int first = first_row_at(pos, lo, hi, jl, jh, J_begin - 1, &jf);
+    pn[i] = make_int2(first, jf);
   }
   for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0ull;
   __syncthreads();
@@ -235,7 +238,8 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
       __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, rows * n_off * int(sizeof(Leg)), kBufferWord3);
   const __amdgpu_buffer_rsrc_t xt_rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xt), 0, rows * nx * 4, kBufferWord3);
-  const unsigned lstep = 8u * unsigned(n_off) * unsigned(sizeof(Leg));  // bytes between a lane's steps
+  const unsigned rowbytes = unsigned(n_off) * unsigned(sizeof(Leg));
+  const unsigned lstep = 8u * rowbytes;  // bytes between a lane's steps
   const unsigned xstep = 8u * unsigned(nx) * 4u;
   struct Rows {
     int64_t da, db;
@@ -249,17 +253,14 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
       for (int grp = wave; grp < n_groups; grp += kSplatWaves) {
         const int c = grp * 8 + cc;
         const int slot = sg * nx + c;
-        int r0 = hi;
-        bool live = false;
-        if (c < nx) {
-          r0 = ptr[slot];
-          live = r0 < hi && nxt[slot] < J1;
-        }
+        const int2 pv = c < nx ? pn[slot] : make_int2(hi, kNoRow);
+        bool live = pv.x < hi && pv.y < J1;
         if (!__any(live)) continue;
         const int cl = min(c, nx - 1);  // addresses of lanes past the last column stay in the tables
-        int r = r0 + rr;
-        unsigned oa = (unsigned(leg_slot(abs(btx + 2 * cl), half)) + unsigned(r) * unsigned(n_off)) * unsigned(sizeof(Leg));
-        unsigned ob = (unsigned(leg_slot(abs(brx + 2 * cl), half)) + unsigned(r) * unsigned(n_off)) * unsigned(sizeof(Leg));
+        const int2 co = colofs[cl];
+        int r = pv.x + rr;
+        unsigned oa = unsigned(co.x) + unsigned(r) * rowbytes;
+        unsigned ob = unsigned(co.y) + unsigned(r) * rowbytes;
         unsigned ox = (unsigned(r) * unsigned(nx) + unsigned(cl)) * 4u;
         auto load = [&](Rows& v, unsigned k) {  // rows r + 8 k of this lane
           // delay and apodisation as a 64-bit and a 32-bit load (the compiler
@@ -273,7 +274,9 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
           v.da = int64_t((uint64_t(a[1]) << 32) | a[0]);
           v.db = int64_t((uint64_t(b[1]) << 32) | b[0]);
         };
-        // adds this lane's row r; false once no column of the wave continues
+        // adds this lane's row r; false once no column of the wave continues.
+        // The first lane of a column left out of the tile stores that row and
+        // its position for the next tile.
         auto add = [&](const Rows& v) {
           const bool have = live && r < hi;
           const uint64_t D = uint64_t(v.da + v.db);
@@ -289,8 +292,7 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
             atomicAdd(&tile[J + 1 - J0], to_fixed<WIDE>(w1, scale));
           }
           const int cnt = __popcll(__ballot(in) & colmask);  // rows of column c taken
-          if (live && rr == cnt) nxt[slot] = have ? J : kNoRow;  // first row left for later tiles
-          r0 += cnt;
+          if (live && rr == cnt) pn[slot] = make_int2(r, have ? J : kNoRow);
           live = live && cnt == 8;
           r += 8;
           oa += lstep;
@@ -306,19 +308,22 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
           load(s0, 1);
           if (!add(s1)) break;
         }
-        if (c < nx && rr == 0) ptr[slot] = r0;
       }
     }
     __syncthreads();
+    // flush: write the tile out and clear it in one pass; the carry slot n is
+    // outside the pass and becomes the next tile's first position
     const int n = J1 - J0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-      out[J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[k]), -kx));
-    __syncthreads();
     const unsigned long long carry = tile[n];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      out[J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[k]), -kx));
+      tile[k] = 0ull;
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0ull;
-    __syncthreads();
-    if (threadIdx.x == 0) tile[0] = carry;
+    if (threadIdx.x == 0) {
+      tile[0] = carry;
+      tile[n] = 0ull;
+    }
     __syncthreads();
   }
 }
@@ -1259,7 +1264,7 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   UMBIR_LAUNCH("prescale", k_prescale, dim3(std::min(128, (G.voxels() + 1023) / 1024)), dim3(1024), 0, s, x,
                G.tau, G.nx, G.voxels(), xt, xmax);
   const size_t lds = size_t(G.tile_bins + 2) * sizeof(unsigned long long) +
-                     2 * size_t(G.n_seg) * G.nx * sizeof(int);
+                     size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   dim3 grid(G.chunks, G.traces());
   switch (G.storage) {
     case UMBIR_STORAGE_F16: launch_splat<UMBIR_STORAGE_F16>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
