@@ -69,7 +69,9 @@ def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
             m = re.search(r"k_([a-z_]+)", row["Kernel_Name"])
             if not m:
                 continue
-            n, v = acc.setdefault(m.group(1), [0, 0.0]), float(row["Counter_Value"])
+            # the library's launch names: k_conv_mfma / k_conv_mfma16 launch as "conv"
+            name = re.sub(r"_mfma(16)?$", "", m.group(1))
+            n, v = acc.setdefault(name, [0, 0.0]), float(row["Counter_Value"])
             n[0] += 1
             n[1] += v
         return {k: v[1] / v[0] for k, v in acc.items()}
@@ -153,8 +155,9 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "path is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): sharding over several "
+              "GPUs is designed (scan positions per GPU, one all-reduce of the adjoint image per "
+              "iteration) but not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2202_09703_amd import umbir
@@ -241,16 +244,19 @@ def main():
     kernels = {k: roofline(k, prof, args.steps, card, gm.n_off, tg) for k in ("splat", "conv", "corr", "gather")}
     dname = max(prof.items(), key=lambda kv: kv[1][1])[0]
     roof = kernels.get(dname) or roofline(dname, prof, args.steps, card, gm.n_off, tg)
-    traffic = None
+    # measured HBM bytes per launch, valid only for the exact sources they were taken on
+    measured = {}
     try:
         tf = json.load(open(TRAFFIC_FILE))
-        if tf.get("source_sha256") == source_digest() and dname in tf["kernels"]:
-            t = tf["kernels"][dname]
-            traffic = t["fetch_bytes"] + t["write_bytes"]
+        if tf.get("source_sha256") == source_digest():
+            measured = {k: t["fetch_bytes"] + t["write_bytes"] for k, t in tf["kernels"].items()}
     except (OSError, ValueError, KeyError):
-        traffic = None
+        measured = {}
+    for k, r in kernels.items():
+        if r is not None:
+            r["traffic"] = measured.get(k)
     if roof is not None:
-        roof["traffic"] = traffic
+        roof["traffic"] = measured.get(dname)
 
     out = {
         "metric": "A+Aᵀ voxel-receiver evals/sec",
