@@ -126,7 +126,31 @@ def kernel_work(name, card, n_off, trace_groups):
         return float(legs + 4 * N + 4 * nz + fine), "hbm"
     if name == "gather":
         return float(legs + 4 * nz + fine + 4 * N * trace_groups), "hbm"
+    if name == "gstep":  # residual and g step: read e and the direct-arrival columns, write e
+        return float(12 * P * K * M), "hbm"
+    if name == "prior":  # image update: read x, A^T e and the curvature, write x
+        return float(16 * N), "hbm"
     return None, None
+
+
+def copy_rate():
+    """Bytes per second of a plain 1 GiB device copy (read + write), the
+    practical HBM ceiling the small update kernels are measured against."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 5 * 8.0 * n / (e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return rate
 
 
 def roofline(name, prof, steps, card, n_off, trace_groups):
@@ -286,6 +310,16 @@ def main():
         "roofline": roof,
         "sweep_kernels": kernels,
     }
+    # the HBM-bound update kernels against the published peak and a measured copy
+    crate = copy_rate()
+    small = {}
+    for k in ("gstep", "prior"):
+        r = roofline(k, prof, args.steps, card, gm.n_off, tg)
+        if r is not None:
+            r["copy_GBps"] = crate / 1e9
+            r["frac_of_copy"] = r["achieved"] * 1e9 / crate
+            small[k] = r
+    out["update_kernels"] = small
 
     if not args.quick:
         from oracle import operator as oo
