@@ -152,7 +152,7 @@ def receiver_x(card, i: int, j: int) -> float:
     return card.array.tx_x[i] + card.array.rx_offset[j]
 
 
-def trace_geometry(card, i: int, j: int, vox=None):
+def trace_geometry(card, i: int, j: int, vox=None, legs: bool = False):
     """Per-voxel delay, weight and attenuation for trace (scan i, receiver j).
 
     vox: optional flat voxel indices (v = row * nx + col); default all voxels.
@@ -160,6 +160,8 @@ def trace_geometry(card, i: int, j: int, vox=None):
       delay   fs * (T_tx + T_rx), the echo's start in samples after firing
       weight  tau(v) * phi^(beta)(v)   (tau of Eq. (7), phi of Eq. (12))
       gamma   total attenuation exponent gamma(v) of Eq. (7)
+    With legs=True the attenuation comes as its two one-way parts
+    (gamma_tx, gamma_rx) instead of their sum.
     """
     g = card.grid
     if vox is None:
@@ -173,6 +175,8 @@ def trace_geometry(card, i: int, j: int, vox=None):
     t_rx, th_rx, a_rx = leg(card.medium, z, xv - xr)
     delay = card.acq.fs * (t_tx + t_rx)
     weight = transmittance(card.medium, z) * apodization(th_tx, th_rx, card.array.beta)
+    if legs:
+        return delay, weight, (a_tx, a_rx)
     return delay, weight, a_tx + a_rx
 
 

@@ -20,39 +20,64 @@ dropped.  The transpose is written out from the same sum.
 
 D (Eq. (1)) has one column per trace: the template placed at the direct-arrival
 delay of that trace, in that trace's rows only.
+
+With attenuation (some alpha_l > 0) the template is chosen per (trace, voxel)
+from the bank of attenuation.py; `b` may be a single template [len] or such a
+bank [G][len].  Reading: the direct arrival keeps the gamma = 0 template.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import geometry, pulse
+from . import attenuation, geometry, pulse
 
 _CHUNK = 8192
 
 
-def _taps(delay, acq, b):
+def default_bank(card, absolute: bool = False) -> np.ndarray:
+    """The templates the operator uses: [1][len] without attenuation."""
+    if attenuation.n_bins(card) == 1:
+        b = pulse.template(card.acq)[None, :]
+        return np.abs(b) if absolute else b
+    return attenuation.bank(card, absolute)
+
+
+def _bank(card, b):
+    return default_bank(card) if b is None else np.atleast_2d(np.asarray(b, float))
+
+
+def _rows(card, bank, legs):
+    """Template index per voxel from its legs' attenuations (all zero for a
+    single template)."""
+    if bank.shape[0] == 1:
+        return np.zeros(np.shape(legs[0]), np.int64)
+    if bank.shape[0] != attenuation.n_bins(card):
+        raise ValueError("template bank does not match the card's attenuation bins")
+    return attenuation.bins_of(legs, attenuation.step(card), bank.shape[0])
+
+
+def _taps(delay, acq, bank, rows):
     """Sample indices and values of every voxel's interpolated template."""
     lh = pulse.window_samples(acq)
     m0 = np.floor(delay).astype(np.int64)
     k = np.arange(lh + 2)
     m = m0[:, None] + k[None, :]
-    val = pulse.interp(b, (m - delay[:, None]) * acq.oversample)
+    val = pulse.interp(bank, (m - delay[:, None]) * acq.oversample, rows)
     return m, val
 
 
 def forward_trace(card, i, j, x_flat, b=None, weight_abs=False):
     """Trace (i, j) of A x, shape (M,).  x_flat: image in raster order (nz * nx)."""
     acq = card.acq
-    if b is None:
-        b = pulse.template(acq)
+    bank = _bank(card, b)
     n_vox = card.grid.nx * card.grid.nz
     y = np.zeros(acq.n_samples)
     for s in range(0, n_vox, _CHUNK):
         vox = np.arange(s, min(s + _CHUNK, n_vox))
-        delay, w, _ = geometry.trace_geometry(card, i, j, vox)
+        delay, w, legs = geometry.trace_geometry(card, i, j, vox, legs=True)
         if weight_abs:
             w = np.abs(w)
-        m, val = _taps(delay, acq, b)
+        m, val = _taps(delay, acq, bank, _rows(card, bank, legs))
         contrib = val * (w * x_flat[vox])[:, None]
         keep = (m >= 0) & (m < acq.n_samples)
         y += np.bincount(m[keep], weights=contrib[keep], minlength=acq.n_samples)
@@ -66,16 +91,16 @@ def forward(card, x, traces=None, b=None, weight_abs=False):
     x_flat = np.asarray(x, float).reshape(-1)
     if traces is None:
         traces = [(i, j) for i in range(a.n_scans) for j in range(a.n_rx)]
+    bank = _bank(card, b)
     for i, j in traces:
-        y[i, j] = forward_trace(card, i, j, x_flat, b, weight_abs)
+        y[i, j] = forward_trace(card, i, j, x_flat, bank, weight_abs)
     return y
 
 
 def adjoint_voxels(card, r, vox, b=None, weight_abs=False):
     """(A^T r) at the flat voxel indices `vox`; r has shape (P, K, M)."""
     acq = card.acq
-    if b is None:
-        b = pulse.template(acq)
+    bank = _bank(card, b)
     vox = np.asarray(vox, np.int64)
     out = np.zeros(len(vox))
     a = card.array
@@ -84,10 +109,10 @@ def adjoint_voxels(card, r, vox, b=None, weight_abs=False):
             rij = r[i, j]
             for s in range(0, len(vox), _CHUNK):
                 sl = slice(s, s + _CHUNK)
-                delay, w, _ = geometry.trace_geometry(card, i, j, vox[sl])
+                delay, w, legs = geometry.trace_geometry(card, i, j, vox[sl], legs=True)
                 if weight_abs:
                     w = np.abs(w)
-                m, val = _taps(delay, acq, b)
+                m, val = _taps(delay, acq, bank, _rows(card, bank, legs))
                 keep = (m >= 0) & (m < acq.n_samples)
                 rv = np.where(keep, rij[np.clip(m, 0, acq.n_samples - 1)], 0.0)
                 out[sl] += w * np.sum(rv * val, axis=1)
@@ -104,16 +129,15 @@ def adjoint(card, r, b=None, weight_abs=False):
 def dense(card, b=None) -> np.ndarray:
     """A as a dense (P K M, N) matrix, column v = trace response of voxel v."""
     g, a, acq = card.grid, card.array, card.acq
-    if b is None:
-        b = pulse.template(acq)
+    bank = _bank(card, b)
     n_vox = g.nx * g.nz
     mat = np.zeros((a.n_scans * a.n_rx * acq.n_samples, n_vox))
     vox = np.arange(n_vox)
     for i in range(a.n_scans):
         for j in range(a.n_rx):
             row0 = (i * a.n_rx + j) * acq.n_samples
-            delay, w, _ = geometry.trace_geometry(card, i, j, vox)
-            m, val = _taps(delay, acq, b)
+            delay, w, legs = geometry.trace_geometry(card, i, j, vox, legs=True)
+            m, val = _taps(delay, acq, bank, _rows(card, bank, legs))
             keep = (m >= 0) & (m < acq.n_samples)
             cols = np.broadcast_to(vox[:, None], m.shape)
             np.add.at(mat, (row0 + m[keep], cols[keep]), (val * w[:, None])[keep])
@@ -123,8 +147,7 @@ def dense(card, b=None) -> np.ndarray:
 def direct_basis(card, b=None) -> np.ndarray:
     """Columns of D as traces d[i, j, :] (P, K, M)."""
     a, acq = card.array, card.acq
-    if b is None:
-        b = pulse.template(acq)
+    b = pulse.template(acq) if b is None else np.atleast_2d(np.asarray(b, float))[0]
     m = np.arange(acq.n_samples)
     d = np.zeros((a.n_scans, a.n_rx, acq.n_samples))
     for i in range(a.n_scans):

@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import operator, prior as qprior, pulse
+from . import operator, prior as qprior
 
 
 def data_cost(e, sigma) -> float:
@@ -40,7 +40,7 @@ def map_cost(card, y, x, g, sigma, pr) -> float:
 
 def sqs_denominator(card, sigma) -> np.ndarray:
     """d = Abar^T (Abar 1) / sigma^2, image-shaped."""
-    babs = operator.abs_template(card.acq)
+    babs = operator.default_bank(card, absolute=True)
     ones = np.ones((card.grid.nz, card.grid.nx))
     col = operator.forward(card, ones, b=babs, weight_abs=True)
     return operator.adjoint(card, col, b=babs, weight_abs=True) / sigma ** 2
@@ -59,7 +59,7 @@ def sqs(card, y, sigma, pr, n_iter, x0=None, g0=None, estimate_direct=True, den=
     grid, a = card.grid, card.array
     x = np.zeros((grid.nz, grid.nx)) if x0 is None else np.array(x0, float)
     g = np.zeros((a.n_scans, a.n_rx)) if g0 is None else np.array(g0, float)
-    b = pulse.template(card.acq)
+    b = operator.default_bank(card)
     dbasis = operator.direct_basis(card, b)
     if den is None:
         den = sqs_denominator(card, sigma)

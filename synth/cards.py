@@ -68,6 +68,7 @@ class Acquisition:
     t_win: float       # window length t_0 of Eq. (10) [s]
     oversample: int    # template oversampling factor Q
     storage: int = 0   # element type of traces in the sweeps: 0 FP32, 1 FP16, 2 BF16
+    n_gamma: int = 16  # attenuation templates when some alpha_l > 0 (2..64)
 
 
 @dataclass(frozen=True)
@@ -228,6 +229,23 @@ def tiny_card(n_layers: int = 2, nx: int = 12, nz: int = 10, n_scans: int = 2,
                             rows=(2, nz - 1), cols=(1, nx - 1), min_spacing=2,
                             interfaces=()),
         snr_db=20.0, noise_seed=seed + 50, n_iter=10)
+
+
+# attenuation of water and concrete, taken as the paper's per-Hz figures per
+# MHz (Sec. 3), in s/m; steel and rock are left lossless
+ALPHA_WATER = 2e-6
+ALPHA_CEMENT = 30e-6
+
+
+def attenuated_card(n_gamma: int = 16, nx: int = 12, nz: int = 16, oversample: int = 8,
+                    n_scans: int = 2, n_rx: int = 3, seed: int = 7, storage: int = 0) -> Card:
+    """tiny_card with three layers (water, steel, cement) and attenuation in
+    water and cement; 16 rows reach 3 mm into the cement."""
+    c = tiny_card(n_layers=3, nx=nx, nz=nz, n_scans=n_scans, n_rx=n_rx, oversample=oversample, seed=seed,
+                  atten=(ALPHA_WATER, 0.0, ALPHA_CEMENT))
+    acq = Acquisition(**{**asdict(c.acq), "n_gamma": n_gamma, "storage": storage})
+    return Card(**{**{f: getattr(c, f) for f in c.__dataclass_fields__}, "acq": acq,
+                   "name": f"attenuated-{nx}x{nz}-G{n_gamma}"})
 
 
 def _reflectivity(z1: float, z2: float) -> float:
