@@ -57,7 +57,8 @@ enum {
  * Fig. 1).  Layer 0 starts at z = 0; the last layer is unbounded.
  * speed c_l [m/s] > 0, thickness [m] > 0 of layers 0..n_layers-2,
  * atten alpha_l [s/m] (Eq. (3)) >= 0, density [kg/m^3] > 0.
- * This build implements alpha = 0 only (ENOTSUP otherwise). */
+ * With some alpha_l > 0 the pulse of each (trace, voxel) pair is attenuated
+ * by its path (Eqs. (7), (9)): see umbir_acq.n_gamma. */
 typedef struct {
     int n_layers;              /* 1..UMBIR_MAX_LAYERS */
     const double* speed;       /* [n_layers] */
@@ -107,6 +108,15 @@ typedef struct {
     double t_win;              /* window t_0 of Eq. (10) [s] */
     int oversample;            /* Q */
     int storage;               /* UMBIR_STORAGE_* */
+    /* Attenuation templates (used only when some alpha_l > 0; 0 means 16,
+     * else 2..64; needs FP32 storage).  Eq. (9) gives every pair its own
+     * h(gamma(v), t); the templates are tabulated once at gamma_g = g dgamma,
+     * g = 0 .. n_gamma - 1, dgamma = 2 Gamma_max / (n_gamma - 1), Gamma_max the
+     * largest one-way path attenuation sum_l alpha_l eta_l / cos(theta_l) of
+     * the problem's legs, and each pair uses the template nearest its gamma
+     * (decided per leg in units of 2^-24 of dgamma).  The operators then run
+     * one pass per template: about n_gamma times the work. */
+    int n_gamma;
 } umbir_acq;
 
 typedef struct {
@@ -138,9 +148,13 @@ typedef struct umbir_geometry umbir_geometry;
  * The tables stay resident in device memory owned by *out until
  * umbir_geometry_free.  Blocks until the tables are built.  The handle is
  * immutable afterwards and may be shared by streams and threads.
- * Errors: EINVAL (bad problem), ENOTSUP (attenuation, off-lattice
- * transducers, unsupported Q, 16-bit storage with Q other than 32 or 64,
- * nx * n_layers > 4096, window * Q > 16384), ENOMEM, EDEVICE. */
+ * With attenuation it also builds each leg's path attenuation (Eq. (3)) in
+ * template units and the n_gamma attenuated templates (Eq. (9), by float64
+ * quadrature of the pulse spectrum times e^{-gamma |f|}).
+ * Errors: EINVAL (bad problem, n_gamma out of range), ENOTSUP (attenuation
+ * with 16-bit storage, off-lattice transducers, unsupported Q, 16-bit
+ * storage with Q other than 32 or 64, nx * n_layers > 4096,
+ * window * Q > 16384), ENOMEM, EDEVICE. */
 int umbir_build_geometry(const umbir_problem* problem, void* stream, umbir_geometry** out);
 
 /* Frees a geometry and its device tables.  NULL is a no-op.  The caller must
@@ -255,6 +269,8 @@ typedef struct {
     int n_layers;
     int trace_groups; /* traces are summed in this many groups by the adjoint's gather */
     int storage;      /* UMBIR_STORAGE_* of trace buffers */
+    int n_gamma;      /* attenuation templates in use (1 without attenuation) */
+    double gamma_step;/* dgamma [s] between templates (0 with one template) */
 } umbir_dims;
 int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
 
@@ -286,12 +302,16 @@ int umbir_autotune(umbir_geometry* geom, void* stream, umbir_tuning* chosen);
  *  UMBIR_TABLE_DELAY  int64 [nz][n_off]  one-way leg delay, Q32.32 samples
  *  UMBIR_TABLE_APOD   float [nz][n_off]  cos^beta of the leg's angle sum
  *  UMBIR_TABLE_TAU    float [nz]         transmittance product of the row
- *  UMBIR_TABLE_BANK   float [Q*L_h + 2]  tabulated windowed pulse (+ zero pad)
+ *  UMBIR_TABLE_BANK   float [n_gamma][Q*L_h + 2]  tabulated windowed responses
+ *                                        (+ zero pad), one per attenuation template
  *  UMBIR_TABLE_DBASIS float [P][K][M]    direct-arrival columns of D
  *  UMBIR_TABLE_OFFSET int32 [P + P*K]    lattice index base of each transducer
+ *  UMBIR_TABLE_ATTEN  int32 [nz][n_off]  leg path attenuation in units of
+ *                                        2^-24 gamma_step (0 without attenuation)
  * `bytes` must equal the table's size.  Errors: EINVAL, EDEVICE. */
 enum { UMBIR_TABLE_DELAY = 0, UMBIR_TABLE_APOD = 1, UMBIR_TABLE_TAU = 2,
-       UMBIR_TABLE_BANK = 3, UMBIR_TABLE_DBASIS = 4, UMBIR_TABLE_OFFSET = 5 };
+       UMBIR_TABLE_BANK = 3, UMBIR_TABLE_DBASIS = 4, UMBIR_TABLE_OFFSET = 5,
+       UMBIR_TABLE_ATTEN = 6 };
 int umbir_copy_table(const umbir_geometry* geom, int which, void* host_dst, size_t bytes);
 
 /* Opt-in per-kernel timing for callers that measure the library (benchmarks,

@@ -30,8 +30,13 @@ thread_local std::string g_last_error;
 
 constexpr int kBisectSteps = 60;
 
+// One leg per thread: the Snell ray parameter kappa = sin(theta_l) / c_l by
+// bisection on the lateral offset it reaches (Eqs. (5)-(6)), then the travel
+// time (Eq. (4)), cos^beta of the angle sum (Eq. (12)) and, when `gam` is not
+// NULL, the path attenuation sum_l alpha_l eta_l / cos(theta_l) (gamma_l of
+// Eq. (3) summed over the leg's layers).
 __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double half_dx,
-                       double fs, int beta, Leg* __restrict__ legs) {
+                       double fs, int beta, Leg* __restrict__ legs, double* __restrict__ gam) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nz * n_off) return;
   const int row = idx / n_off;
@@ -70,13 +75,15 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
     kap = 0.5 * (lo + hi);
   }
   double T = kap * X;
-  double theta = 0.0;
+  double theta = 0.0, att = 0.0;
 #pragma unroll
   for (int l = 0; l < kMaxLayers; ++l) {
     if (eta[l] > 0.0) {
       const double s = kap * L.speed[l];
-      T += eta[l] * sqrt((1.0 - s) * (1.0 + s)) / L.speed[l];
+      const double cv = sqrt((1.0 - s) * (1.0 + s));
+      T += eta[l] * cv / L.speed[l];
       theta += asin(s);
+      att += L.atten[l] * eta[l] / cv;
     }
   }
   // cos^beta by repeated squaring (beta is a non-negative integer)
@@ -88,8 +95,17 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
   Leg rec;
   rec.delay = __double2ll_rn(fs * T * kTwo32);
   rec.apod = static_cast<float>(pw);
-  rec.pad = 0.0f;
+  rec.atten = 0;
   legs[idx] = rec;
+  if (gam) gam[idx] = att;
+}
+
+// Leg attenuation in units of 2^-24 template bins: round(Gamma / dgamma * 2^24),
+// ties to even.
+__global__ void k_leg_units(int n, const double* __restrict__ gam, double step, Leg* __restrict__ legs) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  legs[idx].atten = int(__double2ll_rn(gam[idx] / step * double(1 << kGammaFracBits)));
 }
 
 // Windowed pulse of Eq. (10) at fine-grid index n (time n / (Q fs)): the
@@ -112,6 +128,43 @@ __global__ void k_bank(int Q, int Lh, double dt, double f_c, double inv2s2, doub
     h[idx] = v;
     habs[idx] = fabsf(v);
   }
+}
+
+// Attenuated templates g = 1 .. n_gamma - 1 (Eqs. (9)-(10)): with S the
+// spectrum of the Gaussian-windowed sine, h(gamma, t) = int_0^inf
+// [G(f - f_c) - G(f + f_c)] e^{-gamma f} sin(2 pi f (t - t_c)) df, G the
+// spectrum of the Gaussian.  `nodes` holds the quadrature: frequencies f_k,
+// then amplitudes w_k [G(f_k - f_c) - G(f_k + f_c)].  Row g of the bank (stride
+// Q L_h + 2) is written at the fine indices n = 0 .. Q L_h + 1, zero outside
+// the open window.
+__global__ void k_bank_att(int QLh, double dt, double t_c, double step, int n_nodes,
+                           const double* __restrict__ nodes, float* __restrict__ bank) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y + 1;
+  if (n >= QLh + 2) return;
+  double acc = 0.0;
+  if (n > 0 && n < QLh) {
+    const double gamma = g * step;
+    const double w = 2.0 * M_PI * (n * dt - t_c);
+    for (int k = 0; k < n_nodes; ++k) {
+      const double f = nodes[k];
+      acc += nodes[n_nodes + k] * exp(-gamma * f) * sin(w * f);
+    }
+  }
+  bank[size_t(g) * (QLh + 2) + n] = static_cast<float>(acc);
+}
+
+// Polyphase taps of bank rows g0 .. G-1: h_t[k] = b[(k + 1) Q - t], and |h|.
+__global__ void k_polyphase(int Q, int Lh, int g0, int G, const float* __restrict__ bank, float* __restrict__ h,
+                            float* __restrict__ habs) {
+  const int QLh = Q * Lh;
+  const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x + long(g0) * QLh;
+  if (idx >= long(G) * QLh) return;
+  const int g = int(idx / QLh), r = int(idx - long(g) * QLh);
+  const int k = r / Q, t = r - k * Q;
+  const float v = bank[size_t(g) * (QLh + 2) + size_t(k + 1) * Q - t];
+  h[idx] = v;
+  habs[idx] = fabsf(v);
 }
 
 // Column (i, j) of D: the tabulated pulse delayed by td[ij] samples, linearly
@@ -178,8 +231,64 @@ namespace {
 
 struct Derived {
   int Lh = 0, n_off = 0;
+  long omax = 0;          // largest lattice offset any transducer uses
+  int n_gamma = 1;        // attenuation templates asked for (1 without attenuation)
   std::vector<int> base;  // [P + P*K]
 };
+
+// Composite Gauss-Legendre rule on [0, fmax]: `panels` panels of kGaussNodes
+// nodes each.  The nodes of one panel are the roots of the Legendre polynomial
+// P_n, found by Newton's method from the asymptotic guesses
+// cos(pi (i + 3/4) / (n + 1/2)); the weights are 2 / ((1 - x^2) P_n'(x)^2).
+constexpr int kGaussNodes = 20;
+
+void gauss_legendre(std::vector<double>* x, std::vector<double>* w) {
+  const int n = kGaussNodes;
+  x->assign(n, 0.0);
+  w->assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;  // P_0, P_1, then the three-term recurrence
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    (*x)[i] = z;
+    (*w)[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Frequencies and amplitudes of the attenuated-template quadrature, laid out
+// as k_bank_att reads them.  The Gaussian factor of the spectrum is below
+// e^-72 of its peak past f_c + 6 / (pi sigma_t); a panel spans at most 1/8 of
+// a period of the sine at the window's largest |t - t_c| = t_0 / 2.
+std::vector<double> spectrum_nodes(double f_c, double sigma_t, double t_win) {
+  std::vector<double> gx, gw;
+  gauss_legendre(&gx, &gw);
+  const double fmax = f_c + 6.0 / (M_PI * sigma_t);
+  const int panels = std::max(16, int(std::ceil(8.0 * fmax * 0.5 * t_win)));
+  const int n = panels * kGaussNodes;
+  std::vector<double> out(2 * size_t(n));
+  const double c = sigma_t * std::sqrt(2.0 * M_PI);
+  const double hw = 0.5 * fmax / panels;
+  for (int p = 0; p < panels; ++p) {
+    const double mid = (p + 0.5) * (fmax / panels);
+    for (int i = 0; i < kGaussNodes; ++i) {
+      const double f = mid + hw * gx[i];
+      const double a = M_PI * sigma_t * (f - f_c), b = M_PI * sigma_t * (f + f_c);
+      out[size_t(p) * kGaussNodes + i] = f;
+      out[n + size_t(p) * kGaussNodes + i] = hw * gw[i] * c * (std::exp(-2.0 * a * a) - std::exp(-2.0 * b * b));
+    }
+  }
+  return out;
+}
 
 int validate(const umbir_problem* pb, Derived* dv) {
   if (!pb) return fail(UMBIR_EINVAL, "problem is NULL");
@@ -196,8 +305,7 @@ int validate(const umbir_problem* pb, Derived* dv) {
     if (md.atten) {
       if (!std::isfinite(md.atten[l]) || md.atten[l] < 0.0)
         return fail(UMBIR_EINVAL, "attenuation must be finite and >= 0");
-      if (md.atten[l] != 0.0)
-        return fail(UMBIR_ENOTSUP, "attenuation (alpha > 0) is not implemented in this build");
+      if (md.atten[l] != 0.0) dv->n_gamma = 0;  // decided below
     }
   }
   const umbir_grid& g = pb->grid;
@@ -225,6 +333,13 @@ int validate(const umbir_problem* pb, Derived* dv) {
     return fail(UMBIR_EINVAL, "storage must be UMBIR_STORAGE_F32, _F16 or _BF16");
   if (q.storage != UMBIR_STORAGE_F32 && q.oversample != 32 && q.oversample != 64)
     return fail(UMBIR_ENOTSUP, "16-bit storage needs oversample 32 or 64");
+  if (dv->n_gamma == 0) {  // some alpha > 0
+    dv->n_gamma = q.n_gamma == 0 ? 16 : q.n_gamma;
+    if (dv->n_gamma < 2 || dv->n_gamma > kMaxGamma)
+      return fail(UMBIR_EINVAL, "n_gamma must be 0 (16) or in 2..64 when some alpha > 0");
+    if (q.storage != UMBIR_STORAGE_F32)
+      return fail(UMBIR_ENOTSUP, "attenuation (alpha > 0) needs FP32 storage");
+  }
   // the dense kernels stage the taps, padded to a multiple of 16 rows, in 64 KiB of LDS
   if ((lhi + 15) / 16 * 16 * q.oversample > 16384)
     return fail(UMBIR_ENOTSUP, "window (rounded up to 16) * oversample must be <= 16384");
@@ -254,6 +369,7 @@ int validate(const umbir_problem* pb, Derived* dv) {
         return fail(UMBIR_ENOTSUP, "receiver off the half-voxel lattice (2 (x0 - x) / dx not an integer)");
   }
   if (omax + 1 > (1 << 24)) return fail(UMBIR_EINVAL, "lateral extent too large");
+  dv->omax = omax;
   dv->n_off = int((omax + 2) & ~1L);  // even, for the parity split of each row
   // the splat addresses the leg table and the image with 32-bit byte offsets
   if (double(g.nz) * dv->n_off * sizeof(Leg) >= double(1u << 31) || double(g.nz) * g.nx * 4 >= double(1u << 31))
@@ -274,11 +390,11 @@ int choose_trace_groups(int n_vox, int n_traces) {
   return std::max(g, 1);
 }
 
-size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh) {
+size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh, int n_gamma) {
   const size_t legs = size_t(nz) * n_off;
   return legs * sizeof(Leg) + size_t(nz) * sizeof(float) +
-         size_t(P) * (1 + K) * sizeof(int) + size_t(Q * Lh + 2) * sizeof(float) +
-         2 * size_t(Q) * Lh * sizeof(float) + size_t(P) * K * M * sizeof(float) +
+         size_t(P) * (1 + K) * sizeof(int) + size_t(n_gamma) * (Q * Lh + 2) * sizeof(float) +
+         2 * size_t(n_gamma) * Q * Lh * sizeof(float) + size_t(P) * K * M * sizeof(float) +
          size_t(P) * K * sizeof(float);
 }
 
@@ -344,7 +460,7 @@ size_t umbir_estimate_bytes(const umbir_problem* pb) {
     return 0;
   }
   return table_bytes(pb->grid.nz, dv.n_off, pb->array.n_scans, pb->array.n_rx,
-                     pb->acq.n_samples, pb->acq.oversample, dv.Lh);
+                     pb->acq.n_samples, pb->acq.oversample, dv.Lh, dv.n_gamma);
 }
 
 void umbir_geometry_free(umbir_geometry* G) {
@@ -377,6 +493,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   double top = 0.0;
   for (int l = 0; l < md.n_layers; ++l) {
     G->layers.speed[l] = md.speed[l];
+    G->layers.atten[l] = md.atten ? md.atten[l] : 0.0;
     G->layers.top[l] = top;
     const double bot = (l + 1 < md.n_layers) ? top + md.thickness[l] : INFINITY;
     G->layers.bottom[l] = bot;
@@ -433,9 +550,6 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   if ((st = alloc((void**)&G->legs, legs * sizeof(Leg))) ||
       (st = alloc((void**)&G->tau, G->nz * sizeof(float))) ||
       (st = alloc((void**)&G->base, dv.base.size() * sizeof(int))) ||
-      (st = alloc((void**)&G->bank, (QLh + 2) * sizeof(float))) ||
-      (st = alloc((void**)&G->h, QLh * sizeof(float))) ||
-      (st = alloc((void**)&G->habs, QLh * sizeof(float))) ||
       (st = alloc((void**)&G->dbasis, PK * G->M * sizeof(float))) ||
       (st = alloc((void**)&G->dnorm, PK * sizeof(float)))) {
     umbir_geometry_free(G);
@@ -476,16 +590,71 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     umbir_geometry_free(G);
     return st;
   }
+  // legs; with attenuation also each leg's path attenuation, from which the
+  // template bins follow
+  double* gam_dev = nullptr;
+  double* nodes_dev = nullptr;
+  auto bail = [&](int code) {
+    if (td_dev) (void)hipFreeAsync(td_dev, s);
+    if (gam_dev) (void)hipFreeAsync(gam_dev, s);
+    if (nodes_dev) (void)hipFreeAsync(nodes_dev, s);
+    (void)hipStreamSynchronize(s);
+    umbir_geometry_free(G);
+    return code;
+  };
+  if (dv.n_gamma > 1 &&
+      (st = check_hip(hipMallocAsync((void**)&gam_dev, legs * sizeof(double), s), "hipMallocAsync")))
+    return bail(st);
+  const int n_legs = int(legs);
+  UMBIR_LAUNCH("legs", k_legs, dim3((n_legs + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off, G->z0,
+               G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, gam_dev);
+  if ((st = check_hip(hipGetLastError(), "k_legs"))) return bail(st);
+  if (dv.n_gamma > 1) {
+    // Gamma_max: at a fixed depth a leg's attenuation grows with its lateral
+    // offset, so every row's largest is at the largest offset in use
+    std::vector<double> gam(legs);
+    if ((st = check_hip(hipMemcpyAsync(gam.data(), gam_dev, legs * sizeof(double), hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync")) ||
+        (st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")))
+      return bail(st);
+    const int slot = leg_slot(int(dv.omax), G->n_off / 2);
+    double gmax = 0.0;
+    for (int r = 0; r < G->nz; ++r) gmax = std::max(gmax, gam[size_t(r) * G->n_off + slot]);
+    if (gmax > 0.0) {
+      G->n_gamma = dv.n_gamma;
+      G->gamma_step = 2.0 * gmax / (G->n_gamma - 1);
+      UMBIR_LAUNCH("leg_units", k_leg_units, dim3((n_legs + 255) / 256), dim3(256), 0, s, n_legs, gam_dev,
+                   G->gamma_step, G->legs);
+    }
+  }
+  const int NG = G->n_gamma;
+  if ((st = alloc((void**)&G->bank, size_t(NG) * (QLh + 2) * sizeof(float))) ||
+      (st = alloc((void**)&G->h, size_t(NG) * QLh * sizeof(float))) ||
+      (st = alloc((void**)&G->habs, size_t(NG) * QLh * sizeof(float))))
+    return bail(st);
   {
-    const int n = int(legs);
-    UMBIR_LAUNCH("legs", k_legs, dim3((n + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off,
-                       G->z0, G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs);
     const double dt = 1.0 / (double(G->Q) * G->fs);
     UMBIR_LAUNCH("bank", k_bank, dim3((QLh + 2 + 255) / 256), dim3(256), 0, s, G->Q, G->Lh, dt, G->f_c,
                        1.0 / (2.0 * G->sigma_t * G->sigma_t), 0.5 * G->t_win, G->bank, G->h, G->habs);
+    if (NG > 1) {
+      const std::vector<double> nodes = spectrum_nodes(G->f_c, G->sigma_t, G->t_win);
+      const int n_nodes = int(nodes.size() / 2);
+      if ((st = check_hip(hipMallocAsync((void**)&nodes_dev, nodes.size() * sizeof(double), s),
+                          "hipMallocAsync")) ||
+          (st = check_hip(hipMemcpyAsync(nodes_dev, nodes.data(), nodes.size() * sizeof(double),
+                                         hipMemcpyHostToDevice, s), "hipMemcpyAsync")))
+        return bail(st);
+      UMBIR_LAUNCH("bank_att", k_bank_att, dim3((QLh + 2 + 255) / 256, NG - 1), dim3(256), 0, s, QLh, dt,
+                   0.5 * G->t_win, G->gamma_step, n_nodes, nodes_dev, G->bank);
+      const long rest = long(NG - 1) * QLh;
+      UMBIR_LAUNCH("polyphase", k_polyphase, dim3(unsigned((rest + 255) / 256)), dim3(256), 0, s, G->Q, G->Lh, 1,
+                   NG, G->bank, G->h, G->habs);
+    }
     UMBIR_LAUNCH("dbasis", k_dbasis, dim3(unsigned(PK)), dim3(256), 0, s, G->bank, td_dev, G->M, G->Q,
                        G->Lh, G->dbasis, G->dnorm);
   }
+  if (gam_dev) (void)hipFreeAsync(gam_dev, s);
+  if (nodes_dev) (void)hipFreeAsync(nodes_dev, s);
   st = check_hip(hipGetLastError(), "geometry kernels");
   (void)hipFreeAsync(td_dev, s);
   const int st2 = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(build_geometry)");
@@ -527,6 +696,8 @@ int umbir_get_dims(const umbir_geometry* G, umbir_dims* d) {
   d->n_layers = G->layers.n;
   d->trace_groups = G->trace_groups;
   d->storage = G->storage;
+  d->n_gamma = G->n_gamma;
+  d->gamma_step = G->gamma_step;
   return UMBIR_OK;
 }
 
@@ -539,9 +710,10 @@ int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes
     case UMBIR_TABLE_DELAY: need = legs * sizeof(int64_t); break;
     case UMBIR_TABLE_APOD: need = legs * sizeof(float); break;
     case UMBIR_TABLE_TAU: src = G->tau; need = G->nz * sizeof(float); break;
-    case UMBIR_TABLE_BANK: src = G->bank; need = (G->Q * G->Lh + 2) * sizeof(float); break;
+    case UMBIR_TABLE_BANK: src = G->bank; need = size_t(G->n_gamma) * (G->Q * G->Lh + 2) * sizeof(float); break;
     case UMBIR_TABLE_DBASIS: src = G->dbasis; need = size_t(G->traces()) * G->M * sizeof(float); break;
     case UMBIR_TABLE_OFFSET: src = G->base; need = size_t(G->P) * (1 + G->K) * sizeof(int); break;
+    case UMBIR_TABLE_ATTEN: need = legs * sizeof(int); break;
     default: return fail(UMBIR_EINVAL, "unknown table");
   }
   if (bytes != need) return fail(UMBIR_EINVAL, "bytes does not match the table size");
@@ -557,6 +729,7 @@ int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes
       const Leg& L = rec[size_t(r) * G->n_off + leg_slot(o, half)];
       const size_t k = size_t(r) * G->n_off + o;
       if (which == UMBIR_TABLE_DELAY) static_cast<int64_t*>(dst)[k] = L.delay;
+      else if (which == UMBIR_TABLE_ATTEN) static_cast<int*>(dst)[k] = L.atten;
       else static_cast<float*>(dst)[k] = L.apod;
     }
   return UMBIR_OK;

@@ -15,16 +15,26 @@ namespace umbir {
 constexpr int kMaxLayers = UMBIR_MAX_LAYERS;
 constexpr double kTwo32 = 4294967296.0;
 
-// One-way leg record: delay in Q32.32 fixed-point samples and cos^beta of the
-// leg's angle sum, stored row-major [nz][n_off].  Within a row the lattice
-// offsets are split by parity (even offsets first, then odd): one transducer
-// only ever uses offsets of one parity, so neighbouring columns read
-// neighbouring records.  n_off is even.
+// One-way leg record: delay in Q32.32 fixed-point samples, cos^beta of the
+// leg's angle sum and, with attenuation, the leg's path attenuation in units
+// of 2^-24 template bins (0 without), stored row-major [nz][n_off].  Within a
+// row the lattice offsets are split by parity (even offsets first, then odd):
+// one transducer only ever uses offsets of one parity, so neighbouring columns
+// read neighbouring records.  n_off is even.
 struct __align__(16) Leg {
   int64_t delay;
   float apod;
-  float pad;
+  int atten;
 };
+
+// Attenuation bins: a (trace, voxel) pair whose legs carry u_tx and u_rx uses
+// template (u_tx + u_rx + 2^23) >> 24, at most n_gamma - 1.
+constexpr int kGammaFracBits = 24;
+constexpr int kMaxGamma = 64;
+__host__ __device__ __forceinline__ int gamma_bin(int u, int last) {
+  const int b = (u + (1 << (kGammaFracBits - 1))) >> kGammaFracBits;
+  return b < last ? b : last;
+}
 
 __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >> 1) + (o & 1) * half; }
 
@@ -33,6 +43,7 @@ __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >>
 struct Layers {
   int n;
   double speed[kMaxLayers];
+  double atten[kMaxLayers];  // alpha_l [s/m]
   double top[kMaxLayers];
   double bottom[kMaxLayers];
 };
@@ -107,13 +118,16 @@ struct umbir_geometry {
   // tunable launch shapes (umbir_tuning)
   int splat_blocks = 512;      // target splat workgroups; sets chunks, chunk_bins, tile_bins
   int gather_batch_kb = 8192;  // fine-grid KiB per trace group per gather launch
+  // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)
+  int n_gamma = 1;
+  double gamma_step = 0.0;
   // resident device tables
-  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows
+  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta, attenuation units), parity-split rows
   float* tau = nullptr;      // [nz] transmittance product of the row's layer
   int* base = nullptr;       // [P + P*K] lattice base: offset index = |base + 2 col|
-  float* bank = nullptr;     // [Q*Lh + 2] tabulated windowed pulse, zero padded
-  float* h = nullptr;        // [Lh][Q] polyphase taps h_t[k] = bank[(k+1)Q - t]
-  float* habs = nullptr;     // [Lh][Q] |h|
+  float* bank = nullptr;     // [n_gamma][Q*Lh + 2] tabulated windowed responses, zero padded
+  float* h = nullptr;        // [n_gamma][Lh][Q] polyphase taps h_t[k] = bank[(k+1)Q - t]
+  float* habs = nullptr;     // [n_gamma][Lh][Q] |h|
   float* dbasis = nullptr;   // [P*K][M] direct-arrival columns of D
   float* dnorm = nullptr;    // [P*K] squared norms of the columns of D
   size_t bytes = 0;
@@ -127,6 +141,7 @@ struct umbir_geometry {
   size_t fine_grid_bytes() const { return (size_t(traces()) * fine_per_trace() * elem() + 15) & ~size_t(15); }
   size_t fine_bytes() const { return fine_grid_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 16; }
   size_t trace_bytes() const { return size_t(traces()) * M * elem(); }
+  size_t taps_per_bin() const { return size_t(Q) * Lh; }
 };
 
 namespace umbir {

@@ -174,12 +174,13 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 // (integer LDS atomics: the sum does not depend on the order of the adds, so
 // the result is bitwise reproducible), scaled by 2^k from splat_exponent.
 // Tiles are written out whole (coalesced), so the fine buffer needs no
-// clearing.
-template <bool ABSW, bool WIDE, int ST>
+// clearing.  With ATT only the voxels whose attenuation bin (from the two
+// legs' units) is `gbin` are added: one pass per template.
+template <bool ABSW, bool WIDE, int ST, bool ATT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const int* __restrict__ base,
     int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
-    typename Store<ST>::T* __restrict__ fine) {
+    int gbin, int glast, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
   unsigned long long* tile = smem;                                   // [tile_bins + 2]
   int2* pn = reinterpret_cast<int2*>(smem + tile_bins + 2);          // [seg.n][nx] {next row, its position}
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   struct Rows {
     int64_t da, db;
     float pa, pb, xv;
+    int ua, ub;
   };
   for (int J0 = J_begin; J0 < J_end; J0 += tile_bins) {
     const int J1 = min(J0 + tile_bins, J_end);
@@ -268,8 +270,17 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
           const int ka = int(oa + k * lstep), kb = int(ob + k * lstep);
           const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ka, 0, 0);
           const auto b = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, kb, 0, 0);
-          v.pa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ka + 8, 0, 0));
-          v.pb = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, kb + 8, 0, 0));
+          if constexpr (ATT) {  // apodisation and attenuation units together
+            const auto ea = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ka + 8, 0, 0);
+            const auto eb = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, kb + 8, 0, 0);
+            v.pa = __builtin_bit_cast(float, ea[0]);
+            v.pb = __builtin_bit_cast(float, eb[0]);
+            v.ua = int(ea[1]);
+            v.ub = int(eb[1]);
+          } else {
+            v.pa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ka + 8, 0, 0));
+            v.pb = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, kb + 8, 0, 0));
+          }
           v.xv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xt_rs, int(ox + k * xstep), 0, 0));
           v.da = int64_t((uint64_t(a[1]) << 32) | a[0]);
           v.db = int64_t((uint64_t(b[1]) << 32) | b[0]);
@@ -283,7 +294,9 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
           const int J = int(D >> sh);
           const bool in = have && J < J1;
           // J + 1 >= J0 holds while delays grow with depth within a layer
-          if (in && v.xv != 0.0f && J + 1 >= J0) {
+          bool mine = true;
+          if constexpr (ATT) mine = gamma_bin(v.ua + v.ub, glast) == gbin;
+          if (in && mine && v.xv != 0.0f && J + 1 >= J0) {
             float w = v.xv * (v.pa * v.pb);
             if (ABSW) w = fabsf(w);
             const float phi = float(uint32_t(D) << qs) * kTwoM32;
@@ -360,12 +373,15 @@ __device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsr
 // of trace t + 1 and the legs of trace t + 2 are in flight.  All loads are raw
 // buffer loads (unconditional; a per-trace resource makes positions outside
 // the record read as zero); traces past the batch are read at its last trace
-// and weighted by zero.
-template <bool ABSW, int VPT, int ST>
+// and weighted by zero.  With ATT only the pairs whose attenuation bin is
+// `gbin` are weighted (one pass per template), and with `accum` the first
+// launch adds to the partial image too.
+template <bool ABSW, int VPT, int ST, bool ATT>
 __global__ __launch_bounds__(256) void k_gather(
     const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
-    int tpg, int t_off, int t_cnt, int vox_per_block, float* __restrict__ partial) {
+    int tpg, int t_off, int t_cnt, int vox_per_block, int gbin, int glast, int accum,
+    float* __restrict__ partial) {
   const int N = nx * nz;
   const int v_begin = blockIdx.y * vox_per_block;
   const int v_end = min(N, v_begin + vox_per_block);
@@ -375,13 +391,13 @@ __global__ __launch_bounds__(256) void k_gather(
   const int g_end = min((blockIdx.x + 1) * tpg, PK);
   const int t0 = blockIdx.x * tpg + t_off;
   const int t1 = min(t0 + t_cnt, g_end);
-  if (t0 >= t1 && t_off > 0) return;  // uniform over the block: nothing to add
+  if (t0 >= t1 && (t_off > 0 || accum)) return;  // uniform over the block: nothing to add
   const int sh = 32 - qs;
   const int half = n_off / 2;
   const __amdgpu_buffer_rsrc_t leg_rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, nz * n_off * int(sizeof(Leg)), kBufferWord3);
   const int fine_bytes = MQ * int(sizeof(typename Store<ST>::T));
-  struct Legs { int64_t da[VPT], db[VPT]; float pa[VPT], pb[VPT]; };
+  struct Legs { int64_t da[VPT], db[VPT]; float pa[VPT], pb[VPT]; int ua[VPT], ub[VPT]; };
   struct Taps { unsigned J[VPT]; float phi[VPT], w[VPT]; };
   struct Samples { float c0[VPT], c1[VPT]; };
   for (int vc = v_begin; vc < v_end; vc += blockDim.x * VPT) {
@@ -407,8 +423,17 @@ __global__ __launch_bounds__(256) void k_gather(
         const int ob = (rowoff[u] + leg_slot(abs(brx + col2[u]), half)) * int(sizeof(Leg));
         const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, oa, 0, 0);
         const auto b = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ob, 0, 0);
-        L.pa[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, oa + 8, 0, 0));
-        L.pb[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ob + 8, 0, 0));
+        if constexpr (ATT) {  // apodisation and attenuation units together
+          const auto ea = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, oa + 8, 0, 0);
+          const auto eb = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ob + 8, 0, 0);
+          L.pa[u] = __builtin_bit_cast(float, ea[0]);
+          L.pb[u] = __builtin_bit_cast(float, eb[0]);
+          L.ua[u] = int(ea[1]);
+          L.ub[u] = int(eb[1]);
+        } else {
+          L.pa[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, oa + 8, 0, 0));
+          L.pb[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ob + 8, 0, 0));
+        }
         L.da[u] = int64_t((uint64_t(a[1]) << 32) | a[0]);
         L.db[u] = int64_t((uint64_t(b[1]) << 32) | b[0]);
       }
@@ -423,6 +448,7 @@ __global__ __launch_bounds__(256) void k_gather(
         T.phi[u] = float(uint32_t(D) << qs) * kTwoM32;
         float w = L.pa[u] * L.pb[u];
         if (ABSW) w = fabsf(w);
+        if constexpr (ATT) w = gamma_bin(L.ua[u] + L.ub[u], glast) == gbin ? w : 0.0f;
         T.w[u] = w * live;
       }
     };
@@ -478,7 +504,7 @@ __global__ __launch_bounds__(256) void k_gather(
         float tr = tau[v / nx];
         if (ABSW) tr = fabsf(tr);
         float* pv = partial + size_t(blockIdx.x) * N + v;
-        *pv = t_off == 0 ? acc[u] * tr : fmaf(acc[u], tr, *pv);
+        *pv = (t_off == 0 && !accum) ? acc[u] * tr : fmaf(acc[u], tr, *pv);
       }
     }
   }
@@ -1188,38 +1214,42 @@ void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void
 
 size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 
-template <bool ABSW, bool WIDE, int ST>
+template <bool ABSW, bool WIDE, int ST, bool ATT>
 void launch_splat_k(const umbir_geometry& G, dim3 grid, size_t lds, const float* xt, int qs, int MQ,
-                    const Segments& seg, const unsigned* xmax, void* fine, hipStream_t s) {
+                    const Segments& seg, const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
   using T = typename Store<ST>::T;
-  UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx, G.n_off,
-               G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, static_cast<T*>(fine));
+  UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx, G.n_off,
+               G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, gbin, G.n_gamma - 1,
+               static_cast<T*>(fine));
 }
 
-template <int ST>
+// ATT: the splat pass of template gbin (attenuation bins, FP32 storage only)
+template <int ST, bool ATT>
 void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, const float* xt, int qs, int MQ,
-                  const Segments& seg, const unsigned* xmax, void* fine, hipStream_t s) {
+                  const Segments& seg, const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
   const bool wide = G.nx * (seg.hi[seg.n - 1] - seg.lo[0]) < kSplatNarrowMin;
   if (abs_op) {
-    if (wide) launch_splat_k<true, true, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
-    else launch_splat_k<true, false, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
+    if (wide) launch_splat_k<true, true, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    else launch_splat_k<true, false, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
   } else {
-    if (wide) launch_splat_k<false, true, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
-    else launch_splat_k<false, false, ST>(G, grid, lds, xt, qs, MQ, seg, xmax, fine, s);
+    if (wide) launch_splat_k<false, true, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    else launch_splat_k<false, false, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
   }
 }
 
-template <int ST>
+template <int ST, bool ATT>
 void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
-                   int batch, int vpb, const void* fine, float* partial, hipStream_t s) {
+                   int batch, int vpb, int gbin, int accum, const void* fine, float* partial, hipStream_t s) {
   using T = typename Store<ST>::T;
   constexpr int VPT = 4;
   if (abs_op)
-    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST>), grid, dim3(256), 0, s, static_cast<const T*>(fine), G.nx,
-                 G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, partial);
+    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST, ATT>), grid, dim3(256), 0, s, static_cast<const T*>(fine), G.nx,
+                 G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
+                 G.n_gamma - 1, accum, partial);
   else
-    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST>), grid, dim3(256), 0, s, static_cast<const T*>(fine), G.nx,
-                 G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, partial);
+    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST, ATT>), grid, dim3(256), 0, s, static_cast<const T*>(fine),
+                 G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
+                 G.n_gamma - 1, accum, partial);
 }
 
 }  // namespace
@@ -1266,24 +1296,36 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   const size_t lds = size_t(G.tile_bins + 2) * sizeof(unsigned long long) +
                      size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   dim3 grid(G.chunks, G.traces());
-  switch (G.storage) {
-    case UMBIR_STORAGE_F16: launch_splat<UMBIR_STORAGE_F16>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
-    case UMBIR_STORAGE_BF16: launch_splat<UMBIR_STORAGE_BF16>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
-    default: launch_splat<UMBIR_STORAGE_F32>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, fine, s); break;
+  // one splat + convolution per attenuation template (one without
+  // attenuation); later passes add to the traces the first one wrote
+  for (int gb = 0; gb < G.n_gamma; ++gb) {
+    switch (G.storage) {
+      case UMBIR_STORAGE_F16:
+        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, 0, fine, s);
+        break;
+      case UMBIR_STORAGE_BF16:
+        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, 0, fine, s);
+        break;
+      default:
+        if (G.n_gamma > 1)
+          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, gb, fine, s);
+        else
+          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, 0, fine, s);
+        break;
+    }
+    int st = check_hip(hipGetLastError(), "k_splat");
+    if (st) return st;
+    const float* taps = (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin();
+    launch_conv(G, fine, taps, gb == 0 ? base : out, sign, gb == 0 ? g : nullptr, out, s);
+    if ((st = check_hip(hipGetLastError(), "k_conv"))) return st;
   }
-  int st = check_hip(hipGetLastError(), "k_splat");
-  if (st) return st;
-  launch_conv(G, fine, abs_op ? G.habs : G.h, base, sign, g, out, s);
-  return check_hip(hipGetLastError(), "k_conv");
+  return UMBIR_OK;
 }
 
 int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
                 void* fine, float* partial, hipStream_t s) {
   const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
-  launch_corr(G, r, abs_op ? G.habs : G.h, fine, s);
-  int st = check_hip(hipGetLastError(), "k_corr");
-  if (st) return st;
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
   // one generation: at most 1024 blocks (four per CU), chunks of 256 * 4 voxels
   const int chunk = 256 * 4;
@@ -1297,20 +1339,35 @@ int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale,
   const size_t trace_bytes = size_t(MQ) * G.elem();
   const int batch =
       int(std::max<size_t>(1, std::min<size_t>(tpg, (size_t(G.gather_batch_kb) << 10) / trace_bytes)));
-  for (int t_off = 0; t_off < tpg; t_off += batch) {
-    switch (G.storage) {
-      case UMBIR_STORAGE_F16:
-        launch_gather<UMBIR_STORAGE_F16>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, fine, partial, s);
-        break;
-      case UMBIR_STORAGE_BF16:
-        launch_gather<UMBIR_STORAGE_BF16>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, fine, partial, s);
-        break;
-      default:
-        launch_gather<UMBIR_STORAGE_F32>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, fine, partial, s);
-        break;
+  int st = UMBIR_OK;
+  // one correlation + gather per attenuation template (one without
+  // attenuation); later passes add to the partial images
+  for (int gb = 0; gb < G.n_gamma; ++gb) {
+    launch_corr(G, r, (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin(), fine, s);
+    if ((st = check_hip(hipGetLastError(), "k_corr"))) return st;
+    const int accum = gb > 0;
+    for (int t_off = 0; t_off < tpg; t_off += batch) {
+      switch (G.storage) {
+        case UMBIR_STORAGE_F16:
+          launch_gather<UMBIR_STORAGE_F16, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
+                                                  partial, s);
+          break;
+        case UMBIR_STORAGE_BF16:
+          launch_gather<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
+                                                   partial, s);
+          break;
+        default:
+          if (G.n_gamma > 1)
+            launch_gather<UMBIR_STORAGE_F32, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gb, accum,
+                                                   fine, partial, s);
+          else
+            launch_gather<UMBIR_STORAGE_F32, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
+                                                    partial, s);
+          break;
+      }
     }
+    if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   }
-  if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
                G.trace_groups, G.voxels(), scale, out);
   return check_hip(hipGetLastError(), "k_reduce_groups");

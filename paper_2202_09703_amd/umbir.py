@@ -35,7 +35,7 @@ STORAGE_F32, STORAGE_F16, STORAGE_BF16 = 0, 1, 2
 TRACE_DTYPES = {STORAGE_F32: torch.float32, STORAGE_F16: torch.float16, STORAGE_BF16: torch.bfloat16}
 WORK_FORWARD, WORK_ADJOINT, WORK_RECONSTRUCT = 0, 1, 2
 BATCH_STREAMS, BATCH_GRAPH = 0, 1
-TABLE_DELAY, TABLE_APOD, TABLE_TAU, TABLE_BANK, TABLE_DBASIS, TABLE_OFFSET = range(6)
+TABLE_DELAY, TABLE_APOD, TABLE_TAU, TABLE_BANK, TABLE_DBASIS, TABLE_OFFSET, TABLE_ATTEN = range(7)
 MAX_LAYERS = 8
 
 _dp = C.POINTER(C.c_double)
@@ -59,7 +59,7 @@ class _Array(C.Structure):
 class _Acq(C.Structure):
     _fields_ = [("n_samples", C.c_int), ("fs", C.c_double), ("f_c", C.c_double),
                 ("sigma_t", C.c_double), ("t_win", C.c_double), ("oversample", C.c_int),
-                ("storage", C.c_int)]
+                ("storage", C.c_int), ("n_gamma", C.c_int)]
 
 
 class _Problem(C.Structure):
@@ -76,7 +76,7 @@ class _Dims(C.Structure):
     _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("n_scans", C.c_int), ("n_rx", C.c_int),
                 ("n_samples", C.c_int), ("n_off", C.c_int), ("window", C.c_int),
                 ("oversample", C.c_int), ("n_layers", C.c_int), ("trace_groups", C.c_int),
-                ("storage", C.c_int)]
+                ("storage", C.c_int), ("n_gamma", C.c_int), ("gamma_step", C.c_double)]
 
 
 class _Tuning(C.Structure):
@@ -158,7 +158,7 @@ class Problem:
             _Grid(int(g.nx), int(g.nz), float(g.dx), float(g.dz), float(g.x0), float(g.z0)),
             _Array(len(a.tx_x), tx, len(a.rx_offset), rx, int(a.beta)),
             _Acq(int(q.n_samples), float(q.fs), float(q.f_c), float(q.sigma_t), float(q.t_win),
-                 int(q.oversample), int(getattr(q, "storage", STORAGE_F32))))
+                 int(q.oversample), int(getattr(q, "storage", STORAGE_F32)), int(getattr(q, "n_gamma", 0))))
 
 
 def estimate_bytes(card) -> int:
@@ -201,6 +201,7 @@ class Geometry:
         self.trace_groups = d.trace_groups
         self.storage = d.storage
         self.trace_dtype = TRACE_DTYPES[d.storage]
+        self.n_gamma, self.gamma_step = d.n_gamma, d.gamma_step
 
     @property
     def handle(self):
@@ -212,7 +213,7 @@ class Geometry:
     def shape_key(self):
         """What the launch-shape tuning depends on."""
         return (self.nx, self.nz, self.n_scans, self.n_rx, self.n_samples, self.oversample, self.window,
-                self.n_layers, self.storage)
+                self.n_layers, self.storage, self.n_gamma)
 
     def tuning(self) -> dict:
         t = _Tuning()
@@ -262,9 +263,10 @@ class Geometry:
             TABLE_DELAY: (np.int64, (self.nz, self.n_off)),
             TABLE_APOD: (np.float32, (self.nz, self.n_off)),
             TABLE_TAU: (np.float32, (self.nz,)),
-            TABLE_BANK: (np.float32, (self.oversample * self.window + 2,)),
+            TABLE_BANK: (np.float32, (self.n_gamma, self.oversample * self.window + 2)),
             TABLE_DBASIS: (np.float32, (P, K, M)),
             TABLE_OFFSET: (np.int32, (P + P * K,)),
+            TABLE_ATTEN: (np.int32, (self.nz, self.n_off)),
         }[which]
         out = np.empty(spec[1], dtype=spec[0])
         _check(_lib.umbir_copy_table(self.handle, which, out.ctypes.data_as(C.c_void_p), out.nbytes),

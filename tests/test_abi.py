@@ -56,7 +56,10 @@ def _with(card, **changes):
     ({"medium__speed": (1480.0, -5900.0, 3000.0)}, umbir.EINVAL),
     ({"medium__thickness": (10e-3, 0.0)}, umbir.EINVAL),
     ({"medium__density": (1000.0, 7850.0, float("nan"))}, umbir.EINVAL),
-    ({"medium__atten": (0.0, 2e-6, 0.0)}, umbir.ENOTSUP),
+    ({"medium__atten": (0.0, -2e-6, 0.0)}, umbir.EINVAL),
+    ({"medium__atten": (0.0, 2e-6, 0.0), "acq__storage": 1}, umbir.ENOTSUP),  # attenuation needs FP32
+    ({"medium__atten": (0.0, 2e-6, 0.0), "acq__n_gamma": 1}, umbir.EINVAL),
+    ({"medium__atten": (0.0, 2e-6, 0.0), "acq__n_gamma": 65}, umbir.EINVAL),
     ({"grid__nx": 0}, umbir.EINVAL),
     ({"grid__dz": -1e-3}, umbir.EINVAL),
     ({"array__beta": -1}, umbir.EINVAL),

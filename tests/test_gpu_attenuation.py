@@ -1,0 +1,130 @@
+"""GPU parity with attenuation (alpha > 0): leg attenuation units, the
+attenuated template bank, A, A^T, the surrogate's curvature and the
+reconstruction against the FP64 oracle on the same seeded inputs.  Tolerance
+for float32 results: relative L2 <= 1e-5, as without attenuation; the template
+bin of every (trace, voxel) pair is an integer decision and must match."""
+import numpy as np
+import pytest
+
+from synth import attenuated_card, tiny_card, random_vector, phantom
+from oracle import attenuation as oa, geometry as og, operator as oo, solver as osv, data as odata
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+umbir = pytest.importorskip("paper_2202_09703_amd.umbir")
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def t32(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+
+
+def _cards():
+    return [
+        ("a16-q8", attenuated_card()),
+        ("a16-q32", attenuated_card(oversample=32)),  # matrix-core convolution and correlation
+        ("a4-ragged", attenuated_card(n_gamma=4, nx=17, nz=21, n_scans=3, n_rx=4, oversample=16)),
+        ("a8-narrow", attenuated_card(n_gamma=8, nx=40, nz=30)),  # > 1024 voxels: 64-bit splat scaling
+        ("a16-4layer", tiny_card(n_layers=4, nz=24, atten=(2e-6, 1e-6, 30e-6, 5e-6))),
+    ]
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_bins_and_leg_units(dev, name, card):
+    geom = umbir.build_geometry(card)
+    assert geom.n_gamma == oa.n_bins(card)
+    assert geom.gamma_step == pytest.approx(oa.step(card), rel=1e-12)
+    u = geom.table(umbir.TABLE_ATTEN).astype(np.int64)
+    depth = og.voxel_depths(card.grid)[:, None]
+    X = np.arange(geom.n_off)[None, :] * card.grid.dx / 2
+    _, _, att = og.leg(card.medium, depth + 0 * X, X + 0 * depth)
+    ref = oa.leg_units(att, oa.step(card))
+    diff = np.abs(u - ref)
+    print(f"{name}: G {geom.n_gamma}, leg units differing {int(np.count_nonzero(diff))} of {diff.size}")
+    assert diff.max() <= 1
+    assert np.count_nonzero(diff) <= diff.size // 1000
+
+
+@pytest.mark.parametrize("name,card", _cards()[:3])
+def test_attenuated_bank(dev, name, card):
+    geom = umbir.build_geometry(card)
+    bank = geom.table(umbir.TABLE_BANK).astype(np.float64)
+    ref = oa.bank(card)
+    assert bank.shape == (ref.shape[0], ref.shape[1] + 1)
+    np.testing.assert_allclose(bank[:, :ref.shape[1]], ref, rtol=0, atol=1e-7)
+    assert np.all(bank[:, ref.shape[1]:] == 0)
+    # the direct arrivals keep the unattenuated pulse
+    np.testing.assert_allclose(geom.table(umbir.TABLE_DBASIS), oo.direct_basis(card), rtol=0, atol=3e-7)
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_forward_parity_attenuated(dev, name, card):
+    geom = umbir.build_geometry(card)
+    g = card.grid
+    for x in (phantom(card), random_vector((g.nz, g.nx), seed=51)):
+        y = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+        e = rel(y, oo.forward(card, x))
+        print(f"{name}: forward rel L2 {e:.2e}")
+        assert e <= TOL
+    x = random_vector((g.nz, g.nx), seed=52)
+    y0 = t32(random_vector(geom.trace_shape, seed=53), dev)
+    y1 = umbir.forward(geom, t32(x, dev), y0.clone(), accumulate=True).cpu().numpy()
+    assert rel(y1, y0.cpu().numpy() + oo.forward(card, x)) <= TOL
+
+
+@pytest.mark.parametrize("name,card", _cards())
+def test_adjoint_parity_attenuated(dev, name, card):
+    geom = umbir.build_geometry(card)
+    g = card.grid
+    r = random_vector(geom.trace_shape, seed=61)
+    xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy()
+    e = rel(xa, oo.adjoint(card, r))
+    print(f"{name}: adjoint rel L2 {e:.2e}")
+    assert e <= TOL
+    x = random_vector((g.nz, g.nx), seed=62)
+    ax = umbir.forward(geom, t32(x, dev)).cpu().numpy().astype(np.float64)
+    lhs, rhs = float(np.sum(ax * r)), float(np.sum(x * xa))
+    assert abs(lhs - rhs) <= TOL * np.linalg.norm(ax) * np.linalg.norm(r)
+    # both sweeps stay bitwise reproducible across the template passes
+    rt, xt = t32(r, dev), t32(x, dev)
+    assert torch.equal(umbir.adjoint(geom, rt), umbir.adjoint(geom, rt))
+    assert torch.equal(umbir.forward(geom, xt), umbir.forward(geom, xt))
+
+
+@pytest.mark.parametrize("name,card", [_cards()[0], _cards()[2]])
+def test_sqs_denominator_attenuated(dev, name, card):
+    geom = umbir.build_geometry(card)
+    d = umbir.sqs_denominator(geom, 0.01).cpu().numpy()
+    e = rel(d, osv.sqs_denominator(card, 0.01))
+    print(f"{name}: sqs denominator rel L2 {e:.2e}")
+    assert e <= TOL
+
+
+def test_reconstruct_parity_attenuated(dev):
+    """Eight surrogate iterations with attenuation and direct arrivals: cost,
+    image and direct-arrival weights against the oracle."""
+    card = attenuated_card()
+    _, y, sigma = odata.synthesize(card)
+    g_true = np.array([[0.5, -0.3, 0.8], [0.2, 0.9, -0.4]])
+    y = y + oo.apply_direct(card, g_true)
+    geom = umbir.build_geometry(card)
+    x, g, cost = umbir.reconstruct(geom, card.prior, sigma, t32(y, dev), 8)
+    xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
+    ce = float(np.max(np.abs(cost.cpu().numpy() - co) / co))
+    xe, ge = rel(x.cpu().numpy(), xo), rel(g.cpu().numpy(), go)
+    print(f"attenuated recon: cost {ce:.2e}, x {xe:.2e}, g {ge:.2e}")
+    assert ce <= 1e-5 and xe <= 1e-4 and ge <= 1e-5

@@ -64,6 +64,8 @@ def test_leg_table(dev, name, card):
 def test_bank_and_direct_basis(dev, name, card):
     geom = umbir.build_geometry(card)
     bank = geom.table(umbir.TABLE_BANK).astype(np.float64)
+    assert bank.shape[0] == 1
+    bank = bank[0]
     ref = op.template(card.acq)
     np.testing.assert_allclose(bank[:len(ref)], ref, rtol=0, atol=1e-7)
     assert np.all(bank[len(ref):] == 0)
