@@ -97,6 +97,26 @@ def forward(card, x, traces=None, b=None, weight_abs=False):
     return y
 
 
+def forward_columns(card, vox, coef, b=None, weight_abs=False):
+    """sum over v in vox of coef[v] A[:, v], as traces (P, K, M): A x for an x
+    that is zero outside the voxels `vox`."""
+    acq, a = card.acq, card.array
+    bank = _bank(card, b)
+    vox = np.asarray(vox, np.int64)
+    coef = np.asarray(coef, float)
+    y = np.zeros((a.n_scans, a.n_rx, acq.n_samples))
+    for i in range(a.n_scans):
+        for j in range(a.n_rx):
+            delay, w, legs = geometry.trace_geometry(card, i, j, vox, legs=True)
+            if weight_abs:
+                w = np.abs(w)
+            m, val = _taps(delay, acq, bank, _rows(card, bank, legs))
+            contrib = val * (w * coef)[:, None]
+            keep = (m >= 0) & (m < acq.n_samples)
+            y[i, j] = np.bincount(m[keep], weights=contrib[keep], minlength=acq.n_samples)
+    return y
+
+
 def adjoint_voxels(card, r, vox, b=None, weight_abs=False):
     """(A^T r) at the flat voxel indices `vox`; r has shape (P, K, M)."""
     acq = card.acq

@@ -19,6 +19,19 @@ sqs():  the parity solver.  Reading: the paper minimises with ICD, whose
         of the final (x, g) is appended, so the history has n_iter + 1 entries.
 icd():  the paper's solver (Sec. 2, "Optimization"), in raster voxel order, on
         a dense A; one g update per sweep.  Used only on tiny problems.
+icd_grouped():
+        ICD over a lattice of voxel groups: group (a, b) holds the voxels with
+        row % R == a and column % S == b (R, S >= 2, so no two members are
+        8-neighbours), visited in the order a = 0..R-1, b = 0..S-1.  The
+        members of a group move together, each by its one-voxel ICD step with
+        the prior's neighbours held fixed and the data curvature
+        d^G_v = (Abar^T Abar 1_G)_v / sigma^2 in place of ||A_v||^2 / sigma^2
+        (Abar as for sqs; 1_G the group's indicator).  diag(Abar^T Abar 1_G)
+        bounds A_G^T A_G, so every group step lowers the cost; members whose
+        columns share no sample move exactly as sequential ICD with the
+        curvature ||Abar_v||^2 would.  Reading: the paper's ICD runs one
+        voxel at a time (its pseudocode is in a cited work); this is the
+        grouped form a parallel device runs.
 Both decrease C monotonically and, the cost being strictly convex, share its
 minimiser.
 """
@@ -110,4 +123,61 @@ def icd(card, y, sigma, pr, n_sweeps, x0=None, g0=None, estimate_direct=True, am
             x[v] += step
             e -= amat[:, v] * step
     costs.append(data_cost(e, sigma) + qprior.cost(x, grid, pr))
+    return x.reshape(grid.nz, grid.nx), g, np.array(costs)
+
+
+def icd_groups(grid, rows: int, cols: int):
+    """Flat voxel indices of each lattice group, in visiting order."""
+    if rows < 2 or cols < 2:
+        raise ValueError("group lattice must be at least 2 x 2")
+    idx = np.arange(grid.nz * grid.nx).reshape(grid.nz, grid.nx)
+    return [idx[a::rows, b::cols].reshape(-1) for a in range(rows) for b in range(cols)]
+
+
+def group_denominator(card, groups) -> np.ndarray:
+    """d^G_v = (Abar^T Abar 1_G)_v for every voxel v of every group G (not yet
+    divided by sigma^2), as a flat array."""
+    babs = operator.default_bank(card, absolute=True)
+    d = np.zeros(card.grid.nz * card.grid.nx)
+    for grp in groups:
+        col = operator.forward_columns(card, grp, np.ones(len(grp)), b=babs, weight_abs=True)
+        d[grp] = operator.adjoint_voxels(card, col, grp, b=babs, weight_abs=True)
+    return d
+
+
+def icd_grouped(card, y, sigma, pr, n_sweeps, rows: int = 8, cols: int = 8, x0=None, g0=None,
+                estimate_direct=True, den=None, history=False):
+    """Grouped ICD sweeps; returns (x, g, cost[n_sweeps + 1]) (+ iterate after
+    each sweep).  Each sweep records the cost, takes the exact g step, then
+    visits the groups in order."""
+    grid, a = card.grid, card.array
+    groups = icd_groups(grid, rows, cols)
+    if den is None:
+        den = group_denominator(card, groups)
+    bank = operator.default_bank(card)
+    dbasis = operator.direct_basis(card, bank)
+    x = np.zeros(grid.nz * grid.nx) if x0 is None else np.array(x0, float).reshape(-1)
+    g = np.zeros((a.n_scans, a.n_rx)) if g0 is None else np.array(g0, float)
+    e = y - operator.forward(card, x.reshape(grid.nz, grid.nx), b=bank) - dbasis * g[:, :, None]
+    costs, iterates = [], []
+    for _ in range(n_sweeps):
+        costs.append(data_cost(e, sigma) + qprior.cost(x, grid, pr))
+        if estimate_direct:
+            dg = direct_step(dbasis, e)
+            g = g + dg
+            e = e - dbasis * dg[:, :, None]
+        for grp in groups:
+            theta1 = -operator.adjoint_voxels(card, e, grp, b=bank) / sigma ** 2
+            theta2 = den[grp] / sigma ** 2
+            step = np.zeros(len(grp))
+            for k, v in enumerate(grp):
+                slope, curv = qprior.icd_terms(x, grid, pr, int(v))
+                if theta2[k] + curv > 0:
+                    step[k] = -(theta1[k] + slope) / (theta2[k] + curv)
+            x[grp] += step
+            e = e - operator.forward_columns(card, grp, step, b=bank)
+        iterates.append((x.reshape(grid.nz, grid.nx).copy(), g.copy()))
+    costs.append(data_cost(e, sigma) + qprior.cost(x, grid, pr))
+    if history:
+        return x.reshape(grid.nz, grid.nx), g, np.array(costs), iterates
     return x.reshape(grid.nz, grid.nx), g, np.array(costs)
