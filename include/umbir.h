@@ -209,6 +209,31 @@ int umbir_reconstruct(const umbir_geometry* geom, const umbir_prior* prior,
                       const void* y_dev, int n_iter, float* x_io_dev, float* g_io_dev,
                       double* cost_dev, void* work, size_t work_bytes, void* stream);
 
+/* MAP reconstruction of Eq. (18) by ICD (Sec. 2, "Optimization") run over a
+ * lattice of voxel groups.  Group (a, b), a < group_rows, b < group_cols,
+ * holds the voxels with row % group_rows == a and col % group_cols == b
+ * (both >= 2, so no two members are 8-neighbours); groups are visited in the
+ * order a, then b.  A group moves at once: member v takes its one-voxel ICD
+ * step with the prior's neighbours held fixed and the data curvature
+ * (Abar^T Abar 1_G)_v / sigma^2 (Abar: the operator of |W| and |b|; 1_G the
+ * group's indicator), which bounds the group's block of A^T A, so every group
+ * step lowers the cost; the residual is then updated by the group's columns.
+ * A sweep records the cost, takes the exact per-trace g step (if
+ * estimate_direct), then visits every group.  The curvatures cost one
+ * |A| + |A|^T pair per group at the start of the call.  x_io_dev, g_io_dev:
+ * warm start in, result out (updated in place as the sweeps run); cost_dev
+ * (float64, n_sweeps + 1 entries, may be NULL): the cost before every sweep
+ * and after the last.  Deterministic (bitwise reproducible).
+ * work: at least umbir_icd_workspace_bytes() bytes, or NULL (allocated in
+ * stream order).  Errors: EINVAL (prior, group sizes), ENOTSUP (16-bit
+ * storage, attenuation, 8 n_samples + 4 (window * Q + 2) > 64512), ENOMEM,
+ * EDEVICE. */
+int umbir_reconstruct_icd(const umbir_geometry* geom, const umbir_prior* prior, const void* y_dev,
+                          int n_sweeps, int group_rows, int group_cols, float* x_io_dev,
+                          float* g_io_dev, double* cost_dev, void* work, size_t work_bytes,
+                          void* stream);
+size_t umbir_icd_workspace_bytes(const umbir_geometry* geom, int group_rows, int group_cols);
+
 /* Resident MAP solver for one problem (the serving building block): owns a
  * copy of y, the iterate state (x, g), the data-term curvature, a cost history
  * of max_iter + 1 entries and its workspace, all allocated at creation, and

@@ -165,6 +165,8 @@ int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale,
 // y = D g (or y += D g), y in the storage type.
 int launch_direct(const umbir_geometry& G, const float* g, void* y, int accumulate, hipStream_t s);
 
+int log2_int(int q);  // smallest k with 2^k >= q
+
 size_t forward_work_bytes(const umbir_geometry& G);
 size_t adjoint_work_bytes(const umbir_geometry& G);
 

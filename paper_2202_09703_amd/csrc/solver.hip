@@ -285,6 +285,229 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
   return UMBIR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Grouped ICD (Sec. 2, "Optimization").  The paper's ICD moves one voxel at a
+// time.  Here the voxels are split into the lattice groups (row % R, col % S)
+// (R, S >= 2: no two members are 8-neighbours) and a group moves at once:
+// member v takes its one-voxel step
+//   x_v -= (-(A_v^T e) / sigma^2 + slope_v) / (dG_v / sigma^2 + curv_v)
+// with the prior's neighbours held fixed (slope, curvature sum_r 2 B_sr
+// (x_v - x_r) and sum_r 2 B_sr) and dG = (Abar^T Abar 1_G)_v, which bounds
+// the group's block of A^T A, so every group step lowers the cost.  Then
+// e -= A (step on the group).  Per group three kernels: window dot products
+// per trace, the step per member (trace sums in a fixed order), and the
+// residual update per trace (integer LDS accumulation: bitwise reproducible).
+// A member's column in trace t is W * I_b(m Q - D Q): with J = floor(D Q) and
+// phi = D Q - J, sample m holds W (phi b[k - 1] + (1 - phi) b[k]), k = m Q - J,
+// nonzero for 1 <= k <= Q L_h.
+struct IcdGroup {
+  int r0, c0;  // first row and column of the class
+  int gc;      // columns in the group
+  int size;    // members
+};
+
+__device__ __forceinline__ void icd_member(const IcdGroup& gp, int Sr, int Sc, int i, int* row, int* col) {
+  const int rr = i / gp.gc;
+  *row = gp.r0 + rr * Sr;
+  *col = gp.c0 + (i - rr * gp.gc) * Sc;
+}
+
+// delay (Q32.32 samples) and weight of voxel (row, col) in trace t
+__device__ __forceinline__ void icd_pair(const Leg* __restrict__ legs, int n_off, const int* __restrict__ base, int P,
+                                         int K, const float* __restrict__ tau, int t, int row, int col, int64_t* D,
+                                         float* W) {
+  const int half = n_off / 2;
+  const Leg a = legs[size_t(row) * n_off + leg_slot(abs(base[t / K] + 2 * col), half)];
+  const Leg b = legs[size_t(row) * n_off + leg_slot(abs(base[P + t] + 2 * col), half)];
+  *D = a.delay + b.delay;
+  *W = tau[row] * (a.apod * b.apod);
+}
+
+struct IcdWindow {
+  long J;
+  float phi;
+  int m_lo, m_hi;  // inclusive, empty when m_lo > m_hi
+};
+
+__device__ __forceinline__ IcdWindow icd_window(int64_t D, int qs, int Q, int QLh, int M) {
+  IcdWindow w;
+  w.J = long(uint64_t(D) >> (32 - qs));
+  w.phi = float(uint32_t(uint64_t(D)) << qs) * 2.3283064365386963e-10f;
+  const long lo = (w.J + Q) / Q;  // ceil((J + 1) / Q)
+  const long hi = (w.J + QLh) / Q;
+  w.m_lo = int(lo < 0 ? 0 : (lo > M ? M : lo));
+  w.m_hi = int(hi >= M ? M - 1 : hi);
+  return w;
+}
+
+constexpr int kIcdThreads = 1024;
+
+// partial[t][i] = A_{t, v_i}^T e_t for the members i of the group (ABS: the
+// operator of |W| and |b|).  Block (0, 0) also clears the group's step
+// maximum for k_icd_step.
+template <bool ABS>
+__global__ __launch_bounds__(kIcdThreads) void k_icd_dots(const float* __restrict__ e, int M,
+                                                          const float* __restrict__ bank, int Q, int qs, int QLh,
+                                                          const Leg* __restrict__ legs, int n_off,
+                                                          const int* __restrict__ base, int P, int K,
+                                                          const float* __restrict__ tau, IcdGroup gp, int Sr, int Sc,
+                                                          float* __restrict__ partial, unsigned* __restrict__ dmax) {
+  extern __shared__ float sm[];
+  float* se = sm;      // [M]
+  float* sb = sm + M;  // [QLh + 2]
+  const int t = blockIdx.x;
+  if (dmax && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *dmax = 0u;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) se[m] = e[size_t(t) * M + m];
+  for (int n = threadIdx.x; n < QLh + 2; n += blockDim.x) sb[n] = ABS ? fabsf(bank[n]) : bank[n];
+  __syncthreads();
+  for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < gp.size; i += gridDim.y * blockDim.x) {
+    int row, col;
+    icd_member(gp, Sr, Sc, i, &row, &col);
+    int64_t D;
+    float W;
+    icd_pair(legs, n_off, base, P, K, tau, t, row, col, &D, &W);
+    if (ABS) W = fabsf(W);
+    const IcdWindow w = icd_window(D, qs, Q, QLh, M);
+    float acc = 0.0f;
+    for (int m = w.m_lo; m <= w.m_hi; ++m) {
+      const int k = int(long(m) * Q - w.J);
+      acc = fmaf(se[m], fmaf(w.phi, sb[k - 1] - sb[k], sb[k]), acc);
+    }
+    partial[size_t(t) * gp.size + i] = W * acc;
+  }
+}
+
+// One wave per member: the trace sum of its partials (lane strides, then a
+// fixed shuffle tree).  CURV: den[v] = that sum.  Otherwise the member step:
+// x_v += step_i, delta[i] = step_i, and the largest |step| into *dmax.
+template <bool CURV>
+__global__ __launch_bounds__(256) void k_icd_step(const float* __restrict__ partial, int PK, IcdGroup gp, int Sr,
+                                                  int Sc, int nx, int nz, PriorConst pc, float* __restrict__ den,
+                                                  float* __restrict__ x, float* __restrict__ delta,
+                                                  unsigned* __restrict__ dmax) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (i >= gp.size) return;  // uniform over the wave
+  int row, col;
+  icd_member(gp, Sr, Sc, i, &row, &col);
+  const int v = row * nx + col;
+  double acc = 0.0;
+  for (int t = lane; t < PK; t += 64) acc += partial[size_t(t) * gp.size + i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane != 0) return;
+  if (CURV) {
+    den[v] = float(acc);
+    return;
+  }
+  const float theta1 = -float(acc) * pc.inv_sigma2;
+  const float theta2 = den[v] * pc.inv_sigma2;
+  const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
+  const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
+  const float xs = x[v];
+  const float ms = depth_mod(row, nz, pc);
+  float slope = 0.0f, curv = 0.0f;
+  for (int dr = -1; dr <= 1; ++dr) {
+    const int r2 = row + dr;
+    if (r2 < 0 || r2 >= nz) continue;
+    const float sg = pc.sigma0 * sqrtf(ms * depth_mod(r2, nz, pc));
+    for (int dc = -1; dc <= 1; ++dc) {
+      const int c2 = col + dc;
+      if ((dr == 0 && dc == 0) || c2 < 0 || c2 >= nx) continue;
+      const float bw = (dr == 0 || dc == 0) ? b_edge : b_diag;
+      const float d = xs - x[r2 * nx + c2];
+      float hc, rho;
+      qggmrf(d, sg, pc, &hc, &rho);
+      const float B = bw * hc;
+      slope = fmaf(2.0f * B, d, slope);
+      curv = fmaf(2.0f, B, curv);
+    }
+  }
+  const float h = theta2 + curv;
+  const float step = h > 0.0f ? -(theta1 + slope) / h : 0.0f;
+  x[v] = xs + step;
+  delta[i] = step;
+  atomicMax(dmax, __float_as_uint(fabsf(step)));  // non-negative floats order as their bits
+}
+
+// e_t -= sum_i delta_i A_{t, v_i} (ABS: the operator of |W| and |b|), summed
+// in 64-bit fixed point in LDS.  Every term is at most max|delta| = *dmax
+// (weights, template and interpolation are <= 1) and at most `size` terms
+// meet at a sample, so the scale 2^kx keeps every sum below 2^62.
+template <bool ABS>
+__global__ __launch_bounds__(kIcdThreads) void k_icd_scatter(float* __restrict__ e, int M,
+                                                             const float* __restrict__ bank, int Q, int qs, int QLh,
+                                                             const Leg* __restrict__ legs, int n_off,
+                                                             const int* __restrict__ base, int P, int K,
+                                                             const float* __restrict__ tau, IcdGroup gp, int Sr,
+                                                             int Sc, const float* __restrict__ delta,
+                                                             const unsigned* __restrict__ dmax_bits) {
+  extern __shared__ unsigned long long acc[];  // [M], then the bank as floats
+  float* sb = reinterpret_cast<float*>(acc + M);
+  const int t = blockIdx.x;
+  const float dmax = __uint_as_float(*dmax_bits);
+  if (!(dmax > 0.0f)) return;  // uniform: nothing moved
+  for (int m = threadIdx.x; m < M; m += blockDim.x) acc[m] = 0ull;
+  for (int n = threadIdx.x; n < QLh + 2; n += blockDim.x) sb[n] = ABS ? fabsf(bank[n]) : bank[n];
+  __syncthreads();
+  int lg = 0;
+  while ((1 << lg) < gp.size) ++lg;
+  const int kx = 61 - lg - ilogbf(dmax);
+  const double scale = ldexp(1.0, kx);
+  for (int i = threadIdx.x; i < gp.size; i += blockDim.x) {
+    const float dl = delta[i];
+    if (dl == 0.0f) continue;
+    int row, col;
+    icd_member(gp, Sr, Sc, i, &row, &col);
+    int64_t D;
+    float W;
+    icd_pair(legs, n_off, base, P, K, tau, t, row, col, &D, &W);
+    if (ABS) W = fabsf(W);
+    const IcdWindow w = icd_window(D, qs, Q, QLh, M);
+    const float s = dl * W;
+    for (int m = w.m_lo; m <= w.m_hi; ++m) {
+      const int k = int(long(m) * Q - w.J);
+      const float v = s * fmaf(w.phi, sb[k - 1] - sb[k], sb[k]);
+      atomicAdd(&acc[m], static_cast<unsigned long long>(__double2ll_rn(double(v) * scale)));
+    }
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const long long a = static_cast<long long>(acc[m]);
+    if (a != 0) e[size_t(t) * M + m] -= float(ldexp(double(a), -kx));
+  }
+}
+
+// delta[i] = -1 for every member and *dmax = 1: a scatter then adds the
+// group's columns (e -= -1 * column)
+__global__ void k_icd_unit(int n, float* __restrict__ delta, unsigned* __restrict__ dmax) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) delta[i] = -1.0f;
+  if (i == 0) *dmax = __float_as_uint(1.0f);
+}
+
+IcdGroup icd_group(const umbir_geometry& G, int Sr, int Sc, int k) {
+  IcdGroup gp;
+  gp.r0 = k / Sc;
+  gp.c0 = k % Sc;
+  const int gr = gp.r0 < G.nz ? (G.nz - gp.r0 + Sr - 1) / Sr : 0;
+  gp.gc = gp.c0 < G.nx ? (G.nx - gp.c0 + Sc - 1) / Sc : 0;
+  gp.size = gr * gp.gc;
+  return gp;
+}
+
+int icd_max_group(const umbir_geometry& G, int Sr, int Sc) {
+  return ((G.nz + Sr - 1) / Sr) * ((G.nx + Sc - 1) / Sc);
+}
+
+size_t icd_bytes(const umbir_geometry& G, int Sr, int Sc) {
+  const size_t N = G.voxels(), PK = G.traces();
+  const size_t gmax = size_t(icd_max_group(G, Sr, Sc));
+  const size_t nblk = (N + 255) / 256 + 1;
+  return forward_work_bytes(G) + 2 * aligned(G.trace_bytes()) + aligned(N * sizeof(float)) +
+         aligned(PK * gmax * sizeof(float)) + aligned(gmax * sizeof(float)) + aligned(PK * sizeof(double)) +
+         aligned(nblk * sizeof(double)) + 16 * 256;
+}
+
 }  // namespace
 }  // namespace umbir
 
@@ -469,6 +692,112 @@ int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const void
     if (!last) std::swap(xa, xb);
   }
   return launch_copy(x_io, xa, N, s);
+}
+
+size_t umbir_icd_workspace_bytes(const umbir_geometry* G, int group_rows, int group_cols) {
+  if (!G || group_rows < 2 || group_cols < 2) return 0;
+  return icd_bytes(*G, group_rows, group_cols);
+}
+
+int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const void* y, int n_sweeps,
+                          int group_rows, int group_cols, float* x_io, float* g_io, double* cost, void* work,
+                          size_t work_bytes, void* stream) {
+  if (!G || !y || !x_io || !g_io) return fail(UMBIR_EINVAL, "NULL argument");
+  if (n_sweeps < 0) return fail(UMBIR_EINVAL, "n_sweeps must be >= 0");
+  if (group_rows < 2 || group_cols < 2 || group_rows > 4096 || group_cols > 4096)
+    return fail(UMBIR_EINVAL, "group_rows and group_cols must be in 2..4096");
+  int st = validate_prior(pr);
+  if (st) return st;
+  if (G->storage != UMBIR_STORAGE_F32) return fail(UMBIR_ENOTSUP, "ICD needs FP32 storage");
+  if (G->n_gamma != 1) return fail(UMBIR_ENOTSUP, "ICD does not take attenuation templates");
+  // a trace's residual (64-bit sums in the update) and the template stay in 64 KiB of LDS
+  if (size_t(G->M) * 8 + (G->taps_per_bin() + 2) * 4 + 1024 > 65536)
+    return fail(UMBIR_ENOTSUP, "ICD needs 8 n_samples + 4 (window * oversample + 2) <= 64512 bytes");
+  const int Sr = group_rows, Sc = group_cols;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  if ((st = ws.acquire(work, work_bytes, icd_bytes(*G, Sr, Sc), s))) return st;
+  const size_t N = G->voxels();
+  const int PK = G->traces(), M = G->M, Q = G->Q, QLh = int(G->taps_per_bin());
+  const int qs = log2_int(Q);
+  const int nblk = int((N + 255) / 256);
+  const int gmax = icd_max_group(*G, Sr, Sc);
+  Carve cv{static_cast<char*>(ws.ptr)};
+  void* fine = cv.take<char>(G->fine_bytes());
+  float* e = cv.take<float>(size_t(PK) * M);
+  float* etmp = cv.take<float>(size_t(PK) * M);
+  float* den = cv.take<float>(N);
+  float* part = cv.take<float>(size_t(PK) * gmax);
+  float* delta = cv.take<float>(size_t(gmax));
+  double* ess = cv.take<double>(PK);
+  double* pcost = cv.take<double>(nblk);
+  unsigned* dmax = cv.take<unsigned>(1);
+  const PriorConst pc = prior_const(*G, *pr);
+  const double inv_2s2 = 0.5 / (pr->sigma * pr->sigma);
+  const int est = pr->estimate_direct ? 1 : 0;
+  const int n_groups = Sr * Sc;
+
+  const size_t lds_dots = (size_t(M) + QLh + 2) * sizeof(float);
+  const size_t lds_scatter = size_t(M) * sizeof(unsigned long long) + (size_t(QLh) + 2) * sizeof(float);
+  auto dots = [&](bool abs_op, const IcdGroup& gp, const float* ev, unsigned* clear) {
+    // spread a trace's members over a few blocks when there are few traces
+    const int ych = std::max(1, std::min((gp.size + kIcdThreads - 1) / kIcdThreads, 512 / std::max(PK, 1)));
+    const dim3 grid{unsigned(PK), unsigned(ych), 1u};
+    if (abs_op)
+      UMBIR_LAUNCH("icd_dots", k_icd_dots<true>, grid, dim3(kIcdThreads), lds_dots, s, ev, M, G->bank, Q, qs, QLh,
+                   G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, part, clear);
+    else
+      UMBIR_LAUNCH("icd_dots", k_icd_dots<false>, grid, dim3(kIcdThreads), lds_dots, s, ev, M, G->bank, Q, qs, QLh,
+                   G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, part, clear);
+  };
+  auto scatter = [&](bool abs_op, const IcdGroup& gp, float* ev) {
+    if (abs_op)
+      UMBIR_LAUNCH("icd_scatter", k_icd_scatter<true>, dim3(unsigned(PK)), dim3(kIcdThreads), lds_scatter, s, ev, M,
+                   G->bank, Q, qs, QLh, G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, delta, dmax);
+    else
+      UMBIR_LAUNCH("icd_scatter", k_icd_scatter<false>, dim3(unsigned(PK)), dim3(kIcdThreads), lds_scatter, s, ev,
+                   M, G->bank, Q, qs, QLh, G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, delta, dmax);
+  };
+  const dim3 sblk(256);
+  auto sgrid = [](const IcdGroup& gp) { return dim3(unsigned((gp.size + 3) / 4)); };
+
+  // group curvatures dG = (Abar^T Abar 1_G) on each group's members: the
+  // group's |A| columns summed into a cleared trace buffer, then |A|^T of it
+  for (int k = 0; k < n_groups; ++k) {
+    const IcdGroup gp = icd_group(*G, Sr, Sc, k);
+    if (gp.size == 0) continue;
+    if ((st = launch_fill(etmp, size_t(PK) * M, 0.0f, s))) return st;
+    UMBIR_LAUNCH("icd_unit", k_icd_unit, dim3(unsigned((gp.size + 255) / 256)), dim3(256), 0, s, gp.size, delta,
+                 dmax);
+    scatter(true, gp, etmp);
+    dots(true, gp, etmp, nullptr);
+    UMBIR_LAUNCH("icd_step", k_icd_step<true>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc, den,
+                 nullptr, nullptr, nullptr);
+  }
+  if ((st = check_hip(hipGetLastError(), "icd curvature"))) return st;
+  // e = y - A x - D g
+  if ((st = run_forward(*G, x_io, e, y, -1.0f, g_io, false, fine, s))) return st;
+  for (int sw = 0; sw <= n_sweeps; ++sw) {
+    const bool last = sw == n_sweeps;
+    UMBIR_LAUNCH("gstep", k_gstep<UMBIR_STORAGE_F32>, dim3(unsigned(PK)), dim3(256), 0, s, e, G->dbasis, G->dnorm,
+                 g_io, M, last ? 0 : est, ess);
+    UMBIR_LAUNCH("prior", k_prior<false>, dim3(nblk), dim3(256), 0, s, x_io, nullptr, nullptr, G->nx, G->nz, pc,
+                 nullptr, pcost);
+    if (cost)
+      UMBIR_LAUNCH("cost", k_cost, dim3(1), dim3(256), 0, s, ess, PK, pcost, nblk, inv_2s2, cost + sw, nullptr);
+    if ((st = check_hip(hipGetLastError(), "icd cost"))) return st;
+    if (last) break;
+    for (int k = 0; k < n_groups; ++k) {
+      const IcdGroup gp = icd_group(*G, Sr, Sc, k);
+      if (gp.size == 0) continue;
+      dots(false, gp, e, dmax);
+      UMBIR_LAUNCH("icd_step", k_icd_step<false>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc,
+                   den, x_io, delta, dmax);
+      scatter(false, gp, e);
+    }
+    if ((st = check_hip(hipGetLastError(), "icd sweep"))) return st;
+  }
+  return UMBIR_OK;
 }
 
 size_t umbir_solver_bytes(const umbir_geometry* G, int max_iter) {

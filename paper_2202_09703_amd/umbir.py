@@ -99,6 +99,8 @@ _SIGS = {
     "umbir_direct": (_i, [_vp, _vp, _vp, _i, _vp]),
     "umbir_sqs_denominator": (_i, [_vp, C.c_double, _vp, _vp, _sz, _vp]),
     "umbir_reconstruct": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "umbir_reconstruct_icd": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "umbir_icd_workspace_bytes": (_sz, [_vp, _i, _i]),
     "umbir_get_dims": (_i, [_vp, C.POINTER(_Dims)]),
     "umbir_copy_table": (_i, [_vp, _i, _vp, _sz]),
     "umbir_get_tuning": (_i, [_vp, C.POINTER(_Tuning)]),
@@ -373,6 +375,33 @@ def reconstruct(geom: Geometry, prior, sigma: float, y, n_iter: int, x=None, g=N
                                   _ptr(cost, "cost", (n_iter + 1,), torch.float64), wp, wb,
                                   _stream(stream)), "umbir_reconstruct")
     return x, g, cost
+
+
+def reconstruct_icd(geom: Geometry, prior, sigma: float, y, n_sweeps: int, group=(8, 8), x=None, g=None,
+                    cost=None, stream=None):
+    """MAP reconstruction (Eq. (18)) by ICD over a group_rows x group_cols
+    lattice of voxel groups; returns (x, g, cost) as device tensors (cost:
+    float64, n_sweeps + 1 entries).  x, g: warm start, updated in place."""
+    import torch
+    dev = y.device
+    if x is None:
+        x = torch.zeros(geom.image_shape, dtype=torch.float32, device=dev)
+    if g is None:
+        g = torch.zeros(geom.trace_shape[:2], dtype=torch.float32, device=dev)
+    if cost is None:
+        cost = torch.empty(n_sweeps + 1, dtype=torch.float64, device=dev)
+    pr = make_prior(prior, sigma)
+    rows, cols = int(group[0]), int(group[1])
+    _check(_lib.umbir_reconstruct_icd(geom.handle, C.byref(pr), _ptr(y, "y", geom.trace_shape, geom.trace_dtype),
+                                      int(n_sweeps), rows, cols, _ptr(x, "x", geom.image_shape, torch.float32),
+                                      _ptr(g, "g", geom.trace_shape[:2], torch.float32),
+                                      _ptr(cost, "cost", (n_sweeps + 1,), torch.float64), None, 0,
+                                      _stream(stream)), "umbir_reconstruct_icd")
+    return x, g, cost
+
+
+def icd_workspace_bytes(geom: Geometry, group=(8, 8)) -> int:
+    return int(_lib.umbir_icd_workspace_bytes(geom.handle, int(group[0]), int(group[1])))
 
 
 class Solver:

@@ -1,0 +1,91 @@
+"""GPU parity of grouped ICD (umbir_reconstruct_icd) against the FP64 oracle's
+icd_grouped on the same seeded data: image, direct-arrival weights and cost
+history, element by element.  The data carry injected direct arrivals, which
+dominate y, so the FP32 residual after the g step is a difference of larger
+terms; tolerances are those of the surrogate solver on such data: image
+1e-4 relative L2, g and cost 1e-5."""
+import numpy as np
+import pytest
+
+from synth import card_c1, tiny_card, attenuated_card
+from oracle import solver as osv, data as odata, operator as oo
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+umbir = pytest.importorskip("paper_2202_09703_amd.umbir")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def t32(a, dev):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+
+
+@pytest.mark.parametrize("name,card,group,sweeps", [
+    ("tiny3-2x2", tiny_card(n_layers=3), (2, 2), 3),
+    ("tiny3-3x4", tiny_card(n_layers=3), (3, 4), 3),  # groups of unequal size
+    ("tiny4-ragged", tiny_card(n_layers=4, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=16),
+     (4, 3), 2),
+    ("c1-8x8", card_c1(), (8, 8), 1),
+])
+def test_icd_parity(dev, name, card, group, sweeps):
+    _, y, sigma = odata.synthesize(card)
+    g_true = np.linspace(-0.5, 0.9, card.n_traces).reshape(card.array.n_scans, card.array.n_rx)
+    y = y + oo.apply_direct(card, g_true)
+    geom = umbir.build_geometry(card)
+    x, g, cost = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), sweeps, group=group)
+    xo, go, co, its = osv.icd_grouped(card, y, sigma, card.prior, sweeps, rows=group[0], cols=group[1],
+                                      history=True)
+    cost = cost.cpu().numpy()
+    ce = float(np.max(np.abs(cost - co) / co))
+    xe, ge = rel(x.cpu().numpy(), xo), rel(g.cpu().numpy(), go)
+    print(f"{name}: {sweeps} sweeps, cost {ce:.2e}, x {xe:.2e}, g {ge:.2e}; cost {co[0]:.4g} -> {co[-1]:.4g}")
+    assert ce <= 1e-5 and ge <= 1e-5 and xe <= 1e-4
+    assert np.all(np.diff(cost) <= 1e-6 * np.abs(cost[:-1]))
+    # one sweep, element by element
+    x1, _, _ = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), 1, group=group)
+    e1 = rel(x1.cpu().numpy(), its[0][0])
+    print(f"{name}: one sweep x {e1:.2e}")
+    assert e1 <= 1e-4
+
+
+def test_icd_deterministic_and_resumable(dev):
+    card = tiny_card(n_layers=3)
+    _, y, sigma = odata.synthesize(card)
+    geom = umbir.build_geometry(card)
+    yt = t32(y, dev)
+    xa, ga, ca = umbir.reconstruct_icd(geom, card.prior, sigma, yt, 4, group=(2, 2))
+    xb, gb, cb = umbir.reconstruct_icd(geom, card.prior, sigma, yt, 4, group=(2, 2))
+    assert torch.equal(xa, xb) and torch.equal(ga, gb) and torch.equal(ca, cb)
+    # the sweeps keep no state beyond (x, g): 2 + 2 sweeps equal 4
+    x2, g2, c2 = umbir.reconstruct_icd(geom, card.prior, sigma, yt, 2, group=(2, 2))
+    x4, g4, c4 = umbir.reconstruct_icd(geom, card.prior, sigma, yt, 2, group=(2, 2), x=x2, g=g2)
+    assert torch.allclose(x4, xa, rtol=0, atol=1e-6 * float(xa.abs().max()))
+    assert np.allclose(c4.cpu().numpy(), ca.cpu().numpy()[2:], rtol=1e-6)
+
+
+def test_icd_rejections(dev):
+    card = tiny_card(n_layers=3)
+    geom = umbir.build_geometry(card)
+    y = torch.zeros(geom.trace_shape, dtype=torch.float32, device=dev)
+    with pytest.raises(umbir.UmbirError) as err:
+        umbir.reconstruct_icd(geom, card.prior, 0.1, y, 1, group=(1, 4))
+    assert err.value.status == umbir.EINVAL
+    assert umbir.icd_workspace_bytes(geom, (2, 2)) > 0
+    assert umbir.icd_workspace_bytes(geom, (1, 2)) == 0
+    ag = umbir.build_geometry(attenuated_card())
+    ya = torch.zeros(ag.trace_shape, dtype=torch.float32, device=dev)
+    with pytest.raises(umbir.UmbirError) as err:
+        umbir.reconstruct_icd(ag, card.prior, 0.1, ya, 1)
+    assert err.value.status == umbir.ENOTSUP
