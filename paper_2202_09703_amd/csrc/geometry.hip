@@ -167,6 +167,26 @@ __global__ void k_polyphase(int Q, int Lh, int g0, int G, const float* __restric
   habs[idx] = fabsf(v);
 }
 
+// Template occupancy: for trace blockIdx.x and voxel v, the template of the
+// pair marks the blocks of its fine positions J and J + 1 (the splat puts its
+// weight on both).
+__global__ void k_bin_mask(const Leg* __restrict__ legs, int n_off, const int* __restrict__ base, int P, int K,
+                           int nx, int N, int qs, long MQ, int last, int nb, unsigned long long* __restrict__ mask) {
+  const int t = blockIdx.x;
+  const int v = blockIdx.y * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int row = v / nx, col = v - row * nx;
+  const int half = n_off / 2;
+  const Leg a = legs[size_t(row) * n_off + leg_slot(abs(base[t / K] + 2 * col), half)];
+  const Leg b = legs[size_t(row) * n_off + leg_slot(abs(base[P + t] + 2 * col), half)];
+  const uint64_t D = uint64_t(a.delay + b.delay);
+  const long J = long(D >> (32 - qs));
+  const unsigned long long bit = 1ull << gamma_bin(a.atten + b.atten, last);
+  if (J < MQ) atomicOr(&mask[size_t(t) * nb + (J >> kMaskShift)], bit);
+  if (J + 1 < MQ && ((J + 1) >> kMaskShift) != (J >> kMaskShift))
+    atomicOr(&mask[size_t(t) * nb + ((J + 1) >> kMaskShift)], bit);
+}
+
 // Column (i, j) of D: the tabulated pulse delayed by td[ij] samples, linearly
 // interpolated on the fine grid; also its squared norm.
 __global__ void k_dbasis(const float* __restrict__ bank, const double* __restrict__ td, int M,
@@ -468,7 +488,7 @@ void umbir_geometry_free(umbir_geometry* G) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (G->device >= 0) (void)hipSetDevice(G->device);
-  void* ptrs[] = {G->legs, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm};
+  void* ptrs[] = {G->legs, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm, G->gmask};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (cur >= 0) (void)hipSetDevice(cur);
@@ -652,6 +672,19 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     }
     UMBIR_LAUNCH("dbasis", k_dbasis, dim3(unsigned(PK)), dim3(256), 0, s, G->bank, td_dev, G->M, G->Q,
                        G->Lh, G->dbasis, G->dnorm);
+  }
+  if (NG > 1) {
+    const long MQ = long(G->M) * G->Q;
+    G->mask_blocks = int((MQ + (1L << kMaskShift) - 1) >> kMaskShift);
+    const size_t mb = PK * size_t(G->mask_blocks) * sizeof(unsigned long long);
+    if ((st = alloc((void**)&G->gmask, mb)) ||
+        (st = check_hip(hipMemsetAsync(G->gmask, 0, mb, s), "hipMemsetAsync(mask)")))
+      return bail(st);
+    int qs = 0;
+    while ((1 << qs) < G->Q) ++qs;
+    UMBIR_LAUNCH("bin_mask", k_bin_mask, dim3(unsigned(PK), unsigned((G->voxels() + 255) / 256)), dim3(256), 0, s,
+                 G->legs, G->n_off, G->base, G->P, G->K, G->nx, G->voxels(), qs, MQ, NG - 1, G->mask_blocks,
+                 G->gmask);
   }
   if (gam_dev) (void)hipFreeAsync(gam_dev, s);
   if (nodes_dev) (void)hipFreeAsync(nodes_dev, s);

@@ -36,6 +36,11 @@ __host__ __device__ __forceinline__ int gamma_bin(int u, int last) {
   return b < last ? b : last;
 }
 
+// Template occupancy (attenuation): one 64-bit mask per (trace, block of
+// 2^kMaskShift fine positions), bit g set when some voxel of template g puts
+// weight on a position of the block.
+constexpr int kMaskShift = 10;
+
 __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >> 1) + (o & 1) * half; }
 
 // Planar layer stack passed to kernels by value.  top/bottom are depths of
@@ -121,6 +126,8 @@ struct umbir_geometry {
   // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)
   int n_gamma = 1;
   double gamma_step = 0.0;
+  unsigned long long* gmask = nullptr;  // [P*K][mask_blocks] template occupancy (n_gamma > 1)
+  int mask_blocks = 0;
   // resident device tables
   umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta, attenuation units), parity-split rows
   float* tau = nullptr;      // [nz] transmittance product of the row's layer

@@ -134,6 +134,33 @@ constexpr int kBufferWord3 = 0x00020000;
 // so each round probes the interpolated row and its successor together (two
 // loads in flight); every other round bisects instead, which bounds the
 // rounds by twice those of a plain bisection.
+// A template pass may skip fine-grid ranges that no voxel of its template
+// reaches: mask NULL means no skipping.
+struct BinSkip {
+  const unsigned long long* mask;  // [traces][nb]
+  int nb, gbin;
+};
+
+// The skipping of attenuation template gbin's pass (gbin < 0: none)
+BinSkip bin_skip(const umbir_geometry& G, int gbin) {
+  BinSkip bs;
+  bs.mask = (G.n_gamma > 1 && gbin >= 0) ? G.gmask : nullptr;
+  bs.nb = G.mask_blocks;
+  bs.gbin = gbin < 0 ? 0 : gbin;
+  return bs;
+}
+
+// Does template bs.gbin reach fine positions [lo, hi) of trace t?
+__device__ __forceinline__ bool bin_reaches(const BinSkip& bs, int t, long lo, long hi) {
+  if (!bs.mask) return true;
+  lo = lo < 0 ? 0 : lo;
+  const long b1 = min((hi - 1) >> kMaskShift, long(bs.nb) - 1);
+  const unsigned long long* m = bs.mask + size_t(t) * bs.nb;
+  for (long b = lo >> kMaskShift; b <= b1; ++b)
+    if ((m[b] >> bs.gbin) & 1ull) return true;
+  return false;
+}
+
 template <typename Pos>
 __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int jh, int target, int* jfirst) {
   if (jl >= target) { *jfirst = jl; return lo; }
@@ -180,7 +207,7 @@ template <bool ABSW, bool WIDE, int ST, bool ATT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const int* __restrict__ base,
     int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
-    int gbin, int glast, typename Store<ST>::T* __restrict__ fine) {
+    int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
   unsigned long long* tile = smem;                                   // [tile_bins + 2]
   int2* pn = reinterpret_cast<int2*>(smem + tile_bins + 2);          // [seg.n][nx] {next row, its position}
@@ -197,6 +224,10 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   const int half = n_off / 2;
   const int sh = 32 - qs;  // J = (D_tx + D_rx) >> (32 - log2 Q)
   typename Store<ST>::T* out = fine + size_t(ij) * MQ;
+  if (ATT && !bin_reaches(bs, ij, J_begin, J_end)) {  // uniform: no voxel of the template here
+    for (int k = J_begin + threadIdx.x; k < J_end; k += blockDim.x) out[k] = Store<ST>::put(0.0f);
+    return;
+  }
 
   if (threadIdx.x < kMaxLayers) {
     lay_lo[threadIdx.x] = kNoRow;
@@ -657,7 +688,7 @@ __host__ __device__ inline int corr_lds_words(int Q, int rows, int H) {
 template <int QT, int NT>
 __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
                                                    const float* __restrict__ hq, int M, int Lh, int rb_per_block,
-                                                   float* __restrict__ fine) {
+                                                   float* __restrict__ fine, BinSkip bs) {
   constexpr int Q = 32 * QT;
   constexpr int ROWS = 4 * NT * 32;  // n per row block
   constexpr int KB = 4;              // k per lane per step
@@ -710,6 +741,12 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   const float* sb = (lk ? taps1 : taps0) + li;       // + j Q + b 32
   if (rb0 < rb_end) seg_load(rb0);
   for (int rb = rb0; rb < rb_end; ++rb) {
+    // a template pass leaves the rows its template never reaches unwritten:
+    // the gather of that template reads none of them (uniform over the block)
+    if (!bin_reaches(bs, ij, long(rb) * ROWS * Q, long(min((rb + 1) * ROWS, M)) * Q)) {
+      if (rb + 1 < rb_end) seg_load(rb + 1);
+      continue;
+    }
     __syncthreads();  // the previous row block is done with the segment
     seg_store();
     __syncthreads();
@@ -803,7 +840,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
-                                                   const float* __restrict__ dbasis, float* out) {
+                                                   const float* __restrict__ dbasis, float* out, BinSkip bs) {
   constexpr int CK = 64;        // (n, t) positions per chunk
   constexpr int CN = CK / Q;    // rows n per chunk
   constexpr int TS = Q + 4;     // tap row stride
@@ -822,7 +859,11 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   const int ro = (32 * lk) / Q, t0 = (32 * lk) % Q;  // this lane's row and first tap within a chunk
   // rows n that meet an output m in [m0, m0 + 32): m0 - Lh <= n <= m0 + 30
   const ChunkOrder co(m0, Lh, CN);
-  const int rounds = (co.P + 3) / 4;
+  // a template pass whose template reaches none of the tile's input rows
+  // multiplies nothing (the epilogue still runs)
+  const bool reach = __syncthreads_or(threadIdx.x < 32 && tr0 + int(threadIdx.x) < PK &&
+                                      bin_reaches(bs, tr0 + threadIdx.x, long(m0 - Lh) * Q, long(m0 + 31) * Q));
+  const int rounds = reach ? (co.P + 3) / 4 : 0;
   floatx16 acc[2];  // two independent accumulation chains
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.0f;
@@ -1120,12 +1161,12 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
 
 template <int Q>
 void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
-                      float sign, const float* g, float* out, hipStream_t s) {
+                      float sign, const float* g, float* out, int gbin, hipStream_t s) {
   // padded taps, reused for the four partial tiles at the end
   const size_t lds = std::max<size_t>(size_t(G.Lh + 2 * kConvTapPad) * (Q + 4), 4 * 32 * 33) * sizeof(float);
   dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
   UMBIR_LAUNCH("conv", k_conv_mfma<Q>, grid, dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
-               sign, g, G.dbasis, out);
+               sign, g, G.dbasis, out, bin_skip(G, gbin));
 }
 
 template <int Q, int ST>
@@ -1140,8 +1181,10 @@ void launch_conv_mfma16(const umbir_geometry& G, const void* fine, const float* 
                G.Lh, G.traces(), static_cast<const T*>(base), sign, g, G.dbasis, static_cast<T*>(out));
 }
 
+// gbin >= 0: the pass of attenuation template gbin (output tiles its template
+// never reaches skip their products)
 void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, const void* base_v,
-                 float sign, const float* g, void* out_v, hipStream_t s) {
+                 float sign, const float* g, void* out_v, int gbin, hipStream_t s) {
   if (G.storage == UMBIR_STORAGE_F16) {
     if (G.Q == 32) return launch_conv_mfma16<32, UMBIR_STORAGE_F16>(G, fine_v, hq, base_v, sign, g, out_v, s);
     return launch_conv_mfma16<64, UMBIR_STORAGE_F16>(G, fine_v, hq, base_v, sign, g, out_v, s);
@@ -1153,8 +1196,8 @@ void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, c
   const float* fine = static_cast<const float*>(fine_v);
   const float* base = static_cast<const float*>(base_v);
   float* out = static_cast<float*>(out_v);
-  if (G.Q == 32) return launch_conv_mfma<32>(G, fine, hq, base, sign, g, out, s);
-  if (G.Q == 64) return launch_conv_mfma<64>(G, fine, hq, base, sign, g, out, s);
+  if (G.Q == 32) return launch_conv_mfma<32>(G, fine, hq, base, sign, g, out, gbin, s);
+  if (G.Q == 64) return launch_conv_mfma<64>(G, fine, hq, base, sign, g, out, gbin, s);
   switch (G.Q) {
     case 1: launch_conv_q<1>(G, fine, hq, base, sign, g, out, s); break;
     case 2: launch_conv_q<2>(G, fine, hq, base, sign, g, out, s); break;
@@ -1165,7 +1208,7 @@ void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, c
 }
 
 template <int QT>
-void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine,
+void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine, int gbin,
                       hipStream_t s) {
   constexpr int NT = 2;
   constexpr int rows = 4 * NT * 32;
@@ -1175,7 +1218,8 @@ void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, 
   const int nrb = (G.M + rows - 1) / rows;
   const int per = std::max(1, int((long(G.traces()) * nrb) / 1024));
   dim3 grid(G.traces(), (nrb + per - 1) / per);
-  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine);
+  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine,
+               bin_skip(G, gbin));
 }
 
 template <int QT, int ST>
@@ -1191,7 +1235,9 @@ void launch_corr_mfma16(const umbir_geometry& G, const void* r, const float* hq,
                G.Lh, static_cast<T*>(fine));
 }
 
-void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void* fine_v,
+// gbin >= 0: the pass of attenuation template gbin (rows its template never
+// reaches are left unwritten)
+void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void* fine_v, int gbin,
                  hipStream_t s) {
   if (G.storage == UMBIR_STORAGE_F16)
     return G.Q == 32 ? launch_corr_mfma16<1, UMBIR_STORAGE_F16>(G, r_v, hq, fine_v, s)
@@ -1201,8 +1247,8 @@ void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void
                      : launch_corr_mfma16<2, UMBIR_STORAGE_BF16>(G, r_v, hq, fine_v, s);
   const float* r = static_cast<const float*>(r_v);
   float* fine = static_cast<float*>(fine_v);
-  if (G.Q == 32) return launch_corr_mfma<1>(G, r, hq, fine, s);
-  if (G.Q == 64) return launch_corr_mfma<2>(G, r, hq, fine, s);
+  if (G.Q == 32) return launch_corr_mfma<1>(G, r, hq, fine, gbin, s);
+  if (G.Q == 64) return launch_corr_mfma<2>(G, r, hq, fine, gbin, s);
   switch (G.Q) {
     case 1: launch_corr_q<1>(G, r, hq, fine, s); break;
     case 2: launch_corr_q<2>(G, r, hq, fine, s); break;
@@ -1220,7 +1266,7 @@ void launch_splat_k(const umbir_geometry& G, dim3 grid, size_t lds, const float*
   using T = typename Store<ST>::T;
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx, G.n_off,
                G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, gbin, G.n_gamma - 1,
-               static_cast<T*>(fine));
+               bin_skip(G, ATT ? gbin : -1), static_cast<T*>(fine));
 }
 
 // ATT: the splat pass of template gbin (attenuation bins, FP32 storage only)
@@ -1316,7 +1362,7 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     int st = check_hip(hipGetLastError(), "k_splat");
     if (st) return st;
     const float* taps = (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin();
-    launch_conv(G, fine, taps, gb == 0 ? base : out, sign, gb == 0 ? g : nullptr, out, s);
+    launch_conv(G, fine, taps, gb == 0 ? base : out, sign, gb == 0 ? g : nullptr, out, G.n_gamma > 1 ? gb : -1, s);
     if ((st = check_hip(hipGetLastError(), "k_conv"))) return st;
   }
   return UMBIR_OK;
@@ -1343,7 +1389,7 @@ int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale,
   // one correlation + gather per attenuation template (one without
   // attenuation); later passes add to the partial images
   for (int gb = 0; gb < G.n_gamma; ++gb) {
-    launch_corr(G, r, (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin(), fine, s);
+    launch_corr(G, r, (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin(), fine, G.n_gamma > 1 ? gb : -1, s);
     if ((st = check_hip(hipGetLastError(), "k_corr"))) return st;
     const int accum = gb > 0;
     for (int t_off = 0; t_off < tpg; t_off += batch) {

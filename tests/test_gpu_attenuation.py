@@ -40,6 +40,7 @@ def _cards():
         ("a4-ragged", attenuated_card(n_gamma=4, nx=17, nz=21, n_scans=3, n_rx=4, oversample=16)),
         ("a8-narrow", attenuated_card(n_gamma=8, nx=40, nz=30)),  # > 1024 voxels: 64-bit splat scaling
         ("a16-4layer", tiny_card(n_layers=4, nz=24, atten=(2e-6, 1e-6, 30e-6, 5e-6))),
+        ("a8-q64", attenuated_card(n_gamma=8, oversample=64, nx=20, nz=24, n_scans=3)),
     ]
 
 
