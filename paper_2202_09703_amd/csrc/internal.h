@@ -169,10 +169,19 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
 int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
                 void* fine, float* partial, hipStream_t s);
 
+// A^T r left as the trace_groups partial images (partial[g][v]); their sum in
+// the order g = 0, 1, ... is run_adjoint's result with scale 1.
+int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, void* fine, float* partial,
+                        hipStream_t s);
+
 // y = D g (or y += D g), y in the storage type.
 int launch_direct(const umbir_geometry& G, const float* g, void* y, int accumulate, hipStream_t s);
 
 int log2_int(int q);  // smallest k with 2^k >= q
+
+// Voxels per block of the prior update (four lanes per voxel): the number of
+// per-block prior-cost partials is ceil(N / kPriorVox).
+constexpr int kPriorVox = 64;
 
 size_t forward_work_bytes(const umbir_geometry& G);
 size_t adjoint_work_bytes(const umbir_geometry& G);

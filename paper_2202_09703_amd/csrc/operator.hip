@@ -1368,8 +1368,8 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   return UMBIR_OK;
 }
 
-int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
-                void* fine, float* partial, hipStream_t s) {
+int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, void* fine, float* partial,
+                        hipStream_t s) {
   const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
   const int tpg = (G.traces() + G.trace_groups - 1) / G.trace_groups;
@@ -1414,6 +1414,13 @@ int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale,
     }
     if ((st = check_hip(hipGetLastError(), "k_gather"))) return st;
   }
+  return UMBIR_OK;
+}
+
+int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
+                void* fine, float* partial, hipStream_t s) {
+  int st = run_adjoint_partial(G, r, abs_op, fine, partial, s);
+  if (st) return st;
   UMBIR_LAUNCH("reduce_groups", k_reduce_groups, dim3((G.voxels() + 255) / 256), dim3(256), 0, s, partial,
                G.trace_groups, G.voxels(), scale, out);
   return check_hip(hipGetLastError(), "k_reduce_groups");
@@ -1453,7 +1460,7 @@ size_t umbir_workspace_bytes(const umbir_geometry* G, int kind) {
       // the iteration buffers (fine grid, partial images, residual, A^T e,
       // curvature, reductions) plus the two images of the ping-pong
       const size_t N = G->voxels(), PK = G->traces();
-      const size_t nblk = (N + 255) / 256 + 1;
+      const size_t nblk = (N + kPriorVox - 1) / kPriorVox + 1;
       return adjoint_work_bytes(*G) + aligned(G->trace_bytes()) + 4 * aligned(N * sizeof(float)) +
              aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + 16 * 256;
     }

@@ -74,12 +74,30 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Sums a and b over a block of four waves: a shuffle tree within each wave,
+// then the four wave sums in order (the same order on every call).  Every
+// thread receives both totals.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh /* [8] */) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = a;
+    sh[4 + w] = b;
+  }
+  __syncthreads();
+  a = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  b = ((sh[4] + sh[5]) + sh[6]) + sh[7];
+}
+
 // Per trace: |e|^2 before the g step, then the exact g step (e in the storage type).
 template <int ST>
 __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict__ e, const float* __restrict__ d,
                                                const float* __restrict__ dnorm, float* __restrict__ g,
                                                int M, int estimate, double* __restrict__ ess) {
-  __shared__ double sh[256];
+  __shared__ double sh[8];
   __shared__ float dg_sh;
   const int ij = blockIdx.x;
   typename Store<ST>::T* et = e + size_t(ij) * M;
@@ -90,8 +108,7 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
     ee += ev * ev;
     de += double(dt[m]) * ev;
   }
-  ee = block_sum(ee, sh);
-  de = block_sum(de, sh);
+  block_sum2(ee, de, sh);  // four waves: launched with 256 threads
   if (threadIdx.x == 0) {
     ess[ij] = ee;
     float dg = 0.0f;
@@ -108,49 +125,69 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
 }
 
 // Prior cost of x (pairs counted once) into pcost[block]; with UPDATE also the
-// surrogate step into xout.
+// surrogate step into xout, with A^T e the sum of the adjoint's `groups`
+// partial images in group order.  Four lanes per voxel, two of its eight
+// neighbours each (then summed across the four lanes); the depth modulation
+// of the rows the block touches is tabulated once per block.
 template <bool UPDATE>
-__global__ __launch_bounds__(256) void k_prior(const float* __restrict__ x, const float* __restrict__ u,
-                                               const float* __restrict__ den, int nx, int nz,
-                                               PriorConst pc, float* __restrict__ xout,
-                                               double* __restrict__ pcost) {
-  __shared__ double sh[256];
+__global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict__ x,
+                                                         const float* __restrict__ part, int groups,
+                                                         const float* __restrict__ den, int nx, int nz,
+                                                         PriorConst pc, float* __restrict__ xout,
+                                                         double* __restrict__ pcost) {
+  __shared__ double sh[4];
+  __shared__ float ms_tab[kPriorVox + 4];  // rows r_lo ..: the block's rows and one on each side
   const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
   const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = nx * nz;
+  const int q = threadIdx.x & 3;
+  const int v0 = blockIdx.x * kPriorVox;
+  const int v = v0 + (threadIdx.x >> 2);
+  const int r_lo = max(v0 / nx - 1, 0);
+  const int r_hi = min((min(v0 + kPriorVox, N) - 1) / nx + 1, nz - 1);
+  for (int i = threadIdx.x; i <= r_hi - r_lo; i += blockDim.x) ms_tab[i] = depth_mod(r_lo + i, nz, pc);
+  __syncthreads();
   double cost = 0.0;
-  if (v < nx * nz) {
-    const int row = v / nx, col = v - row * nx;
-    const float xs = x[v];
-    const float ms = depth_mod(row, nz, pc);
-    float slope = 0.0f, curv = 0.0f;
+  float slope = 0.0f, curv = 0.0f, xs = 0.0f;
+  int row = 0, col = 0;
+  if (v < N) {
+    row = v / nx;
+    col = v - row * nx;
+    xs = x[v];
+    const float ms = ms_tab[row - r_lo];
 #pragma unroll
-    for (int dr = -1; dr <= 1; ++dr) {
-      const int r2 = row + dr;
-      if (r2 < 0 || r2 >= nz) continue;
-      const float sg = pc.sigma0 * sqrtf(ms * depth_mod(r2, nz, pc));
-#pragma unroll
-      for (int dc = -1; dc <= 1; ++dc) {
-        const int c2 = col + dc;
-        if ((dr == 0 && dc == 0) || c2 < 0 || c2 >= nx) continue;
-        const float bw = (dr == 0 || dc == 0) ? b_edge : b_diag;
-        const float delta = xs - x[r2 * nx + c2];
-        float hc, rho;
-        qggmrf(delta, sg, pc, &hc, &rho);
-        const float B = bw * hc;
-        slope = fmaf(2.0f * B, delta, slope);
-        curv = fmaf(4.0f, B, curv);
-        // each unordered pair once: the neighbour to the right or below
-        if (dr == 1 || (dr == 0 && dc == 1)) cost += double(bw) * double(rho);
-      }
-    }
-    if (UPDATE) {
-      const float grad = fmaf(-u[v], pc.inv_sigma2, slope);
-      xout[v] = xs - grad / (den[v] + curv);
+    for (int k = 2 * q; k < 2 * q + 2; ++k) {
+      const int idx = k < 4 ? k : k + 1;  // the 3 x 3 neighbourhood without its centre
+      const int dr = idx / 3 - 1, dc = idx % 3 - 1;
+      const int r2 = row + dr, c2 = col + dc;
+      if (r2 < 0 || r2 >= nz || c2 < 0 || c2 >= nx) continue;
+      const float sg = pc.sigma0 * sqrtf(ms * ms_tab[r2 - r_lo]);
+      const float bw = (dr == 0 || dc == 0) ? b_edge : b_diag;
+      const float delta = xs - x[r2 * nx + c2];
+      float hc, rho;
+      qggmrf(delta, sg, pc, &hc, &rho);
+      const float B = bw * hc;
+      slope = fmaf(2.0f * B, delta, slope);
+      curv = fmaf(4.0f, B, curv);
+      // each unordered pair once: the neighbour to the right or below
+      if (dr == 1 || (dr == 0 && dc == 1)) cost += double(bw) * double(rho);
     }
   }
-  cost = block_sum(cost, sh);
-  if (threadIdx.x == 0) pcost[blockIdx.x] = cost;
+  // the voxel's four lanes are adjacent: a butterfly gives each the same sums
+  slope += __shfl_xor(slope, 1, 64);
+  slope += __shfl_xor(slope, 2, 64);
+  curv += __shfl_xor(curv, 1, 64);
+  curv += __shfl_xor(curv, 2, 64);
+  if (UPDATE && v < N && q == 0) {
+    float u = 0.0f;
+    for (int g = 0; g < groups; ++g) u += part[size_t(g) * N + v];
+    const float grad = fmaf(-u, pc.inv_sigma2, slope);
+    xout[v] = xs - grad / (den[v] + curv);
+  }
+  for (int off = 32; off > 0; off >>= 1) cost += __shfl_down(cost, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cost;
+  __syncthreads();
+  if (threadIdx.x == 0) pcost[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 // Cost = data term + prior term, written to out[*counter] (then the counter
@@ -222,7 +259,7 @@ struct IterBuffers {
 IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
   const size_t N = G.voxels(), PK = G.traces();
   IterBuffers b;
-  b.nblk = int((N + 255) / 256);
+  b.nblk = int((N + kPriorVox - 1) / kPriorVox);
   b.fine = cv.take<char>(G.fine_bytes());
   b.partial = cv.take<float>(size_t(G.trace_groups) * N);
   b.e = cv.take<char>(G.trace_bytes());
@@ -236,7 +273,7 @@ IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
 size_t iter_bytes(const umbir_geometry& G) {
   const size_t N = G.voxels(), PK = G.traces();
   return adjoint_work_bytes(G) + aligned(G.trace_bytes()) + 2 * aligned(N * sizeof(float)) +
-         aligned(PK * sizeof(double)) + aligned(((N + 255) / 256 + 1) * sizeof(double)) + 8 * 256;
+         aligned(PK * sizeof(double)) + aligned(((N + kPriorVox - 1) / kPriorVox + 1) * sizeof(double)) + 8 * 256;
 }
 
 int enqueue_curvature(const umbir_geometry& G, const IterBuffers& b, const PriorConst& pc, hipStream_t s) {
@@ -269,11 +306,12 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
   }
   if ((st = check_hip(hipGetLastError(), "k_gstep"))) return st;
   if (last) {
-    UMBIR_LAUNCH("prior", k_prior<false>, dim3(b.nblk), dim3(256), 0, s, x_in, nullptr, nullptr, G.nx, G.nz,
-                 pc, nullptr, b.pcost);
+    UMBIR_LAUNCH("prior", k_prior<false>, dim3(b.nblk), dim3(4 * kPriorVox), 0, s, x_in, nullptr, 0, nullptr, G.nx,
+                 G.nz, pc, nullptr, b.pcost);
   } else {
-    if ((st = run_adjoint(G, b.e, b.u, 1.0f, false, b.fine, b.partial, s))) return st;
-    UMBIR_LAUNCH("prior", k_prior<true>, dim3(b.nblk), dim3(256), 0, s, x_in, b.u, b.den, G.nx, G.nz, pc,
+    if ((st = run_adjoint_partial(G, b.e, false, b.fine, b.partial, s))) return st;
+    UMBIR_LAUNCH("prior", k_prior<true>, dim3(b.nblk), dim3(4 * kPriorVox), 0, s, x_in, b.partial, G.trace_groups, b.den,
+                 G.nx, G.nz, pc,
                  x_out, b.pcost);
   }
   if ((st = check_hip(hipGetLastError(), "k_prior"))) return st;
@@ -502,7 +540,7 @@ int icd_max_group(const umbir_geometry& G, int Sr, int Sc) {
 size_t icd_bytes(const umbir_geometry& G, int Sr, int Sc) {
   const size_t N = G.voxels(), PK = G.traces();
   const size_t gmax = size_t(icd_max_group(G, Sr, Sc));
-  const size_t nblk = (N + 255) / 256 + 1;
+  const size_t nblk = (N + kPriorVox - 1) / kPriorVox + 1;
   return forward_work_bytes(G) + 2 * aligned(G.trace_bytes()) + aligned(N * sizeof(float)) +
          aligned(PK * gmax * sizeof(float)) + aligned(gmax * sizeof(float)) + aligned(PK * sizeof(double)) +
          aligned(nblk * sizeof(double)) + 16 * 256;
@@ -720,7 +758,7 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
   const size_t N = G->voxels();
   const int PK = G->traces(), M = G->M, Q = G->Q, QLh = int(G->taps_per_bin());
   const int qs = log2_int(Q);
-  const int nblk = int((N + 255) / 256);
+  const int nblk = int((N + kPriorVox - 1) / kPriorVox);
   const int gmax = icd_max_group(*G, Sr, Sc);
   Carve cv{static_cast<char*>(ws.ptr)};
   void* fine = cv.take<char>(G->fine_bytes());
@@ -781,7 +819,7 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
     const bool last = sw == n_sweeps;
     UMBIR_LAUNCH("gstep", k_gstep<UMBIR_STORAGE_F32>, dim3(unsigned(PK)), dim3(256), 0, s, e, G->dbasis, G->dnorm,
                  g_io, M, last ? 0 : est, ess);
-    UMBIR_LAUNCH("prior", k_prior<false>, dim3(nblk), dim3(256), 0, s, x_io, nullptr, nullptr, G->nx, G->nz, pc,
+    UMBIR_LAUNCH("prior", k_prior<false>, dim3(nblk), dim3(4 * kPriorVox), 0, s, x_io, nullptr, 0, nullptr, G->nx, G->nz, pc,
                  nullptr, pcost);
     if (cost)
       UMBIR_LAUNCH("cost", k_cost, dim3(1), dim3(256), 0, s, ess, PK, pcost, nblk, inv_2s2, cost + sw, nullptr);
