@@ -352,6 +352,10 @@ typedef struct {
     double total_ms;
 } umbir_kernel_time;
 void umbir_profile_enable(int on);
+/* Restricts the timing to the kernels named in `names` (comma-separated, the
+ * names umbir_profile_collect reports); NULL or "" times every kernel.  The
+ * fewer launches are bracketed, the less the events perturb the work timed. */
+void umbir_profile_select(const char* names);
 int umbir_profile_collect(umbir_kernel_time* out, int max_entries, int* n_out);
 
 const char* umbir_strerror(int status);

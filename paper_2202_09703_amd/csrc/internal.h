@@ -61,13 +61,13 @@ int check_hip(hipError_t e, const char* what);
 
 // Optional per-kernel timing (umbir_profile_enable): when on, every launch is
 // bracketed by two events on its stream; umbir_profile_collect sums them.
-bool prof_on();
+bool prof_on(const char* name);  // profiling on and `name` selected
 hipEvent_t prof_start(hipStream_t s);
 void prof_stop(const char* name, hipStream_t s, hipEvent_t start);
 
 #define UMBIR_LAUNCH(name, kernel, grid, block, shmem, stream, ...)          \
   do {                                                                       \
-    hipEvent_t umbir_e0_ = umbir::prof_on() ? umbir::prof_start(stream) : nullptr; \
+    hipEvent_t umbir_e0_ = umbir::prof_on(name) ? umbir::prof_start(stream) : nullptr; \
     hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);     \
     if (umbir_e0_) umbir::prof_stop(name, stream, umbir_e0_);                \
   } while (0)
@@ -122,7 +122,7 @@ struct umbir_geometry {
   int tile_bins = 0;
   // tunable launch shapes (umbir_tuning)
   int splat_blocks = 512;      // target splat workgroups; sets chunks, chunk_bins, tile_bins
-  int gather_batch_kb = 8192;  // fine-grid KiB per trace group per gather launch
+  int gather_batch_kb = 4096;  // fine-grid KiB per trace group per gather launch
   // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)
   int n_gamma = 1;
   double gamma_step = 0.0;

@@ -1380,8 +1380,9 @@ int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, voi
   const int vpb = (G.voxels() + nb - 1) / nb;
   dim3 grid(G.trace_groups, nb);
   // traces per launch: batches of gather_batch_kb of fine-grid data per group
-  // (8 MB by default: on the 512 x 512 workload 8 MB batches measured 15 %
-  // faster than 2 MB ones and 25 % faster than one launch over all traces)
+  // (4 MiB by default, one XCD's L2: the autotuner's choice on the 256 x 256
+  // and 512 x 512 workloads, 1-2 % faster per reconstruction than 8 MiB and
+  // 3-5 % faster than 2 MiB)
   const size_t trace_bytes = size_t(MQ) * G.elem();
   const int batch =
       int(std::max<size_t>(1, std::min<size_t>(tpg, (size_t(G.gather_batch_kb) << 10) / trace_bytes)));

@@ -23,13 +23,22 @@ struct Totals {
 };
 
 std::atomic<bool> g_on{false};
+std::atomic<bool> g_filtered{false};
 std::mutex g_mu;
+std::vector<std::string> g_select;  // kernel names timed while g_filtered
 std::vector<Pending> g_pending;
 std::map<std::string, Totals> g_totals;
 
 }  // namespace
 
-bool prof_on() { return g_on.load(std::memory_order_relaxed); }
+bool prof_on(const char* name) {
+  if (!g_on.load(std::memory_order_relaxed)) return false;
+  if (!g_filtered.load(std::memory_order_relaxed)) return true;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (const std::string& n : g_select)
+    if (n == name) return true;
+  return false;
+}
 
 hipEvent_t prof_start(hipStream_t s) {
   // launches recorded into a graph are not timed (the events would be captured too)
@@ -62,6 +71,24 @@ using namespace umbir;
 extern "C" {
 
 void umbir_profile_enable(int on) { g_on.store(on != 0); }
+
+void umbir_profile_select(const char* names) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_select.clear();
+  if (names) {
+    std::string cur;
+    for (const char* p = names;; ++p) {
+      if (*p == ',' || *p == '\0') {
+        if (!cur.empty()) g_select.push_back(cur);
+        cur.clear();
+        if (*p == '\0') break;
+      } else if (*p != ' ') {
+        cur += *p;
+      }
+    }
+  }
+  g_filtered.store(!g_select.empty());
+}
 
 int umbir_profile_collect(umbir_kernel_time* out, int max_entries, int* n_out) {
   if (max_entries < 0 || (max_entries > 0 && !out)) return fail(UMBIR_EINVAL, "bad output buffer");

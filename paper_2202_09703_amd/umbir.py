@@ -117,6 +117,7 @@ _SIGS = {
     "umbir_batch_step": (_i, [_vp, _i, _vp]),
     "umbir_batch_free": (None, [_vp]),
     "umbir_profile_enable": (None, [_i]),
+    "umbir_profile_select": (None, [C.c_char_p]),
     "umbir_profile_collect": (_i, [C.POINTER(_KernelTime), _i, C.POINTER(_i)]),
     "umbir_strerror": (C.c_char_p, [_i]),
     "umbir_last_error": (C.c_char_p, []),
@@ -504,6 +505,11 @@ def solver_bytes(geom: Geometry, max_iter: int) -> int:
 def profile_enable(on: bool = True):
     """Turn per-kernel event timing on or off (process-wide)."""
     _lib.umbir_profile_enable(int(bool(on)))
+
+
+def profile_select(names=None):
+    """Time only the kernels named (an iterable of names, or None for all)."""
+    _lib.umbir_profile_select(",".join(names).encode() if names else None)
 
 
 def profile_collect() -> dict:
