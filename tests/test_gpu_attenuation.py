@@ -129,3 +129,37 @@ def test_reconstruct_parity_attenuated(dev):
     xe, ge = rel(x.cpu().numpy(), xo), rel(g.cpu().numpy(), go)
     print(f"attenuated recon: cost {ce:.2e}, x {xe:.2e}, g {ge:.2e}")
     assert ce <= 1e-5 and xe <= 1e-4 and ge <= 1e-5
+
+
+def test_attenuated_session_and_batch_match_reconstruct(dev):
+    """The template passes captured in a session's iteration graphs (replayed
+    with eager work between the replays), and a batch of two attenuated
+    sessions, hold bitwise the one-shot reconstruction."""
+    card = attenuated_card(oversample=32)
+    _, y, sigma = odata.synthesize(card)
+    geom = umbir.build_geometry(card)
+    yt = t32(y, dev)
+    sess = umbir.Solver(geom, card.prior, sigma, yt, max_iter=6)
+    done = 0
+    for chunk in (1, 2, 3):
+        sess.step(chunk)
+        done += chunk
+        xs, gs, cs = sess.read()
+        torch.cuda.synchronize()
+        xr, gr, cr = umbir.reconstruct(geom, card.prior, sigma, yt, done)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, xr) and torch.equal(gs, gr) and torch.equal(cs, cr), f"after {done}"
+    sess.free()
+    a = umbir.Solver(geom, card.prior, sigma, yt, max_iter=4)
+    b = umbir.Solver(geom, card.prior, sigma, yt, max_iter=4)
+    batch = umbir.Batch([a, b], umbir.BATCH_GRAPH)
+    batch.step(4)
+    torch.cuda.synchronize()
+    xr, gr, cr = umbir.reconstruct(geom, card.prior, sigma, yt, 4)
+    for s in (a, b):
+        xs, gs, cs = s.read()
+        torch.cuda.synchronize()
+        assert torch.equal(xs, xr) and torch.equal(gs, gr) and torch.equal(cs, cr)
+    batch.free()
+    a.free()
+    b.free()

@@ -38,6 +38,7 @@ def t32(a, dev):
     ("tiny4-ragged", tiny_card(n_layers=4, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=16),
      (4, 3), 2),
     ("c1-8x8", card_c1(), (8, 8), 1),
+    ("tiny2-q64", tiny_card(n_layers=2, oversample=64, nx=10, nz=9), (2, 3), 2),
 ])
 def test_icd_parity(dev, name, card, group, sweeps):
     _, y, sigma = odata.synthesize(card)
@@ -89,3 +90,18 @@ def test_icd_rejections(dev):
     with pytest.raises(umbir.UmbirError) as err:
         umbir.reconstruct_icd(ag, card.prior, 0.1, ya, 1)
     assert err.value.status == umbir.ENOTSUP
+
+
+def test_icd_without_direct_estimate(dev):
+    """estimate_direct = 0 keeps g at its warm start (here zero) and still
+    matches the oracle's sweeps."""
+    import dataclasses
+    card = tiny_card(n_layers=3)
+    card = dataclasses.replace(card, prior=dataclasses.replace(card.prior, estimate_direct=False))
+    _, y, sigma = odata.synthesize(card)
+    geom = umbir.build_geometry(card)
+    x, g, cost = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), 2, group=(2, 2))
+    xo, go, co = osv.icd_grouped(card, y, sigma, card.prior, 2, rows=2, cols=2, estimate_direct=False)
+    assert torch.count_nonzero(g) == 0
+    assert rel(x.cpu().numpy(), xo) <= 1e-5
+    assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-5
