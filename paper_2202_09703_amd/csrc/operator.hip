@@ -406,8 +406,10 @@ __device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsr
 // the record read as zero); traces past the batch are read at its last trace
 // and weighted by zero.  With ATT only the pairs whose attenuation bin is
 // `gbin` are weighted (one pass per template), and with `accum` the first
-// launch adds to the partial image too.
-template <bool ABSW, int VPT, int ST, bool ATT>
+// launch adds to the partial image too.  ONE: every group's traces in this
+// launch belong to one scan position, so the transmit legs are loaded once per
+// voxel chunk and only the receive legs per trace.
+template <bool ABSW, int VPT, int ST, bool ATT, bool ONE>
 __global__ __launch_bounds__(256) void k_gather(
     const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
@@ -445,41 +447,42 @@ __global__ __launch_bounds__(256) void k_gather(
       rowoff[u] = row * n_off;
       acc[u] = 0.0f;
     }
-    auto load_legs = [&](Legs& L, int t) {
-      t = min(t, t1 - 1);
-      const int btx = base[t / K], brx = base[P + t];
+    // one leg record (delay, apodisation, attenuation units) per voxel of the
+    // thread for the transducer with lattice base bt
+    auto load_leg = [&](int bt, int64_t (&d)[VPT], float (&p)[VPT], int (&ua)[VPT]) {
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
-        const int oa = (rowoff[u] + leg_slot(abs(btx + col2[u]), half)) * int(sizeof(Leg));
-        const int ob = (rowoff[u] + leg_slot(abs(brx + col2[u]), half)) * int(sizeof(Leg));
-        const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, oa, 0, 0);
-        const auto b = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ob, 0, 0);
+        const int o = (rowoff[u] + leg_slot(abs(bt + col2[u]), half)) * int(sizeof(Leg));
+        const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, o, 0, 0);
         if constexpr (ATT) {  // apodisation and attenuation units together
-          const auto ea = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, oa + 8, 0, 0);
-          const auto eb = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ob + 8, 0, 0);
-          L.pa[u] = __builtin_bit_cast(float, ea[0]);
-          L.pb[u] = __builtin_bit_cast(float, eb[0]);
-          L.ua[u] = int(ea[1]);
-          L.ub[u] = int(eb[1]);
+          const auto e = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, o + 8, 0, 0);
+          p[u] = __builtin_bit_cast(float, e[0]);
+          ua[u] = int(e[1]);
         } else {
-          L.pa[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, oa + 8, 0, 0));
-          L.pb[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ob + 8, 0, 0));
+          p[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, o + 8, 0, 0));
         }
-        L.da[u] = int64_t((uint64_t(a[1]) << 32) | a[0]);
-        L.db[u] = int64_t((uint64_t(b[1]) << 32) | b[0]);
+        d[u] = int64_t((uint64_t(a[1]) << 32) | a[0]);
       }
+    };
+    Legs TX;  // ONE: the transmit legs of the launch's scan position
+    if constexpr (ONE) load_leg(base[min(t0, t1 - 1) / K], TX.da, TX.pa, TX.ua);
+    auto load_legs = [&](Legs& L, int t) {
+      t = min(t, t1 - 1);
+      if constexpr (!ONE) load_leg(base[t / K], L.da, L.pa, L.ua);
+      load_leg(base[P + t], L.db, L.pb, L.ub);
     };
     auto taps_of = [&](const Legs& L, Taps& T, int t) {
       const float live = t < t1 ? 1.0f : 0.0f;  // steps past the batch add nothing
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
-        const uint64_t D = uint64_t(L.da[u] + L.db[u]);
+        const int64_t da = ONE ? TX.da[u] : L.da[u];
+        const uint64_t D = uint64_t(da + L.db[u]);
         // positions past the record (or past 2^31) clamp to MQ and read zero
         T.J[u] = unsigned(min(D >> sh, uint64_t(MQ)));
         T.phi[u] = float(uint32_t(D) << qs) * kTwoM32;
-        float w = L.pa[u] * L.pb[u];
+        float w = (ONE ? TX.pa[u] : L.pa[u]) * L.pb[u];
         if (ABSW) w = fabsf(w);
-        if constexpr (ATT) w = gamma_bin(L.ua[u] + L.ub[u], glast) == gbin ? w : 0.0f;
+        if constexpr (ATT) w = gamma_bin((ONE ? TX.ua[u] : L.ua[u]) + L.ub[u], glast) == gbin ? w : 0.0f;
         T.w[u] = w * live;
       }
     };
@@ -1283,19 +1286,39 @@ void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, c
   }
 }
 
-template <int ST, bool ATT>
-void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
-                   int batch, int vpb, int gbin, int accum, const void* fine, float* partial, hipStream_t s) {
+template <int ST, bool ATT, bool ONE>
+void launch_gather_k(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
+                     int batch, int vpb, int gbin, int accum, const void* fine, float* partial, hipStream_t s) {
   using T = typename Store<ST>::T;
   constexpr int VPT = 4;
   if (abs_op)
-    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST, ATT>), grid, dim3(256), 0, s, static_cast<const T*>(fine), G.nx,
-                 G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
-                 G.n_gamma - 1, accum, partial);
-  else
-    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST, ATT>), grid, dim3(256), 0, s, static_cast<const T*>(fine),
+    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST, ATT, ONE>), grid, dim3(256), 0, s, static_cast<const T*>(fine),
                  G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
                  G.n_gamma - 1, accum, partial);
+  else
+    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST, ATT, ONE>), grid, dim3(256), 0, s, static_cast<const T*>(fine),
+                 G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
+                 G.n_gamma - 1, accum, partial);
+}
+
+// Does every trace group's range of this launch lie within one scan position?
+bool gather_one_scan(const umbir_geometry& G, int tpg, int t_off, int batch) {
+  const int PK = G.traces();
+  for (int g = 0; g < G.trace_groups; ++g) {
+    const int t0 = g * tpg + t_off;
+    const int t1 = std::min(t0 + batch, std::min((g + 1) * tpg, PK));
+    if (t0 < t1 && t0 / G.K != (t1 - 1) / G.K) return false;
+  }
+  return true;
+}
+
+template <int ST, bool ATT>
+void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
+                   int batch, int vpb, int gbin, int accum, const void* fine, float* partial, hipStream_t s) {
+  if (gather_one_scan(G, tpg, t_off, batch))
+    launch_gather_k<ST, ATT, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gbin, accum, fine, partial, s);
+  else
+    launch_gather_k<ST, ATT, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gbin, accum, fine, partial, s);
 }
 
 }  // namespace
