@@ -163,3 +163,14 @@ def test_attenuated_session_and_batch_match_reconstruct(dev):
     batch.free()
     a.free()
     b.free()
+
+
+def test_attenuated_single_voxel_grid(dev):
+    """One voxel, one trace: a single template is in use, the others stay idle."""
+    card = attenuated_card(nx=1, nz=14, n_scans=1, n_rx=1)
+    geom = umbir.build_geometry(card)
+    x = random_vector((card.grid.nz, card.grid.nx), seed=71)
+    y = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+    assert rel(y, oo.forward(card, x)) <= TOL
+    r = random_vector(geom.trace_shape, seed=72)
+    assert rel(umbir.adjoint(geom, t32(r, dev)).cpu().numpy(), oo.adjoint(card, r)) <= TOL

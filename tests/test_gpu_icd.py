@@ -105,3 +105,20 @@ def test_icd_without_direct_estimate(dev):
     assert torch.count_nonzero(g) == 0
     assert rel(x.cpu().numpy(), xo) <= 1e-5
     assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-5
+
+
+@pytest.mark.parametrize("kw,group", [
+    (dict(n_layers=2, nx=1, nz=1, n_scans=1, n_rx=1), (2, 2)),     # one voxel: three empty groups
+    (dict(n_layers=3, nx=5, nz=3, n_scans=1, n_rx=2), (4, 8)),     # lattice coarser than the grid
+])
+def test_icd_degenerate_grids(dev, kw, group):
+    from synth import random_vector
+    card = tiny_card(**kw)
+    geom = umbir.build_geometry(card)
+    x_true = random_vector((card.grid.nz, card.grid.nx), seed=81)
+    y = oo.forward(card, x_true) + 0.01 * random_vector(geom.trace_shape, seed=82)
+    sigma = 0.01
+    x, g, cost = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), 2, group=group)
+    xo, go, co = osv.icd_grouped(card, y, sigma, card.prior, 2, rows=group[0], cols=group[1])
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-5
