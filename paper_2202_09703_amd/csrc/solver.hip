@@ -37,6 +37,7 @@ struct PriorConst {
   float inv_sigma2;
   float p;
   float T;
+  float T_pm2;  // T^(p - 2)
   float sigma0;
   double m, a;
   double z0, dz;
@@ -48,18 +49,21 @@ __device__ __forceinline__ float depth_mod(int row, int nz, const PriorConst& pc
   return float(1.0 + (pc.m - 1.0) * pow(depth / dmax, pc.a));
 }
 
-// Half curvature rho'(D) / (2 D) of Eq. (15) with q = 2 (finite at D = 0):
-// (T sg)^(p-2) / (2 sg^p) * (2/p + u^(2-p)) / (1 + u^(2-p))^2, u = |D| / (T sg).
-// Also rho(D) = |D|^p / (p sg^p) * u^(2-p) / (1 + u^(2-p)).
+// Half curvature rho'(D) / (2 D) and rho(D) of Eq. (15) with q = 2, u = |D| / (T sg):
+//   rho'(D) / (2 D) = (T sg)^(p-2) / (2 sg^p) * (2/p + u^(2-p)) / (1 + u^(2-p))^2
+//                   = T^(p-2) / (2 sg^2) * (2/p + u^(2-p)) / (1 + u^(2-p))^2,
+//   rho(D) = |D|^p / (p sg^p) * u^(2-p) / (1 + u^(2-p))
+//          = D^2 T^(p-2) / (p sg^2 (1 + u^(2-p)))
+// (|D|^p u^(2-p) = D^2 (T sg)^(p-2)): one power per pair, finite at D = 0.
 __device__ __forceinline__ void qggmrf(float delta, float sg, const PriorConst& pc, float* half_curv,
                                        float* rho) {
   const float a = fabsf(delta);
-  const float tsg = pc.T * sg;
-  const float sgp = powf(sg, pc.p);
-  const float uq = powf(a / tsg, 2.0f - pc.p);
+  const float inv_sg2 = 1.0f / (sg * sg);
+  const float uq = powf(a / (pc.T * sg), 2.0f - pc.p);
   const float den = 1.0f + uq;
-  *half_curv = powf(tsg, pc.p - 2.0f) / (2.0f * sgp) * (2.0f / pc.p + uq) / (den * den);
-  *rho = powf(a, pc.p) / (pc.p * sgp) * uq / den;
+  const float c = pc.T_pm2 * inv_sg2;
+  *half_curv = 0.5f * c * (2.0f / pc.p + uq) / (den * den);
+  *rho = a * a * c / (pc.p * den);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -236,6 +240,7 @@ PriorConst prior_const(const umbir_geometry& G, const umbir_prior& pr) {
   pc.inv_sigma2 = float(1.0 / (pr.sigma * pr.sigma));
   pc.p = float(pr.p);
   pc.T = float(pr.T);
+  pc.T_pm2 = float(std::pow(pr.T, pr.p - 2.0));
   pc.sigma0 = float(pr.sigma0);
   pc.m = pr.m;
   pc.a = pr.a;
