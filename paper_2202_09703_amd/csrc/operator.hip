@@ -1481,11 +1481,11 @@ size_t umbir_workspace_bytes(const umbir_geometry* G, int kind) {
     case UMBIR_WORK_FORWARD: return forward_work_bytes(*G);
     case UMBIR_WORK_ADJOINT: return adjoint_work_bytes(*G);
     case UMBIR_WORK_RECONSTRUCT: {
-      // the iteration buffers (fine grid, partial images, residual, A^T e,
+      // the iteration buffers (fine grid, partial images of A^T e, residual,
       // curvature, reductions) plus the two images of the ping-pong
       const size_t N = G->voxels(), PK = G->traces();
       const size_t nblk = (N + kPriorVox - 1) / kPriorVox + 1;
-      return adjoint_work_bytes(*G) + aligned(G->trace_bytes()) + 4 * aligned(N * sizeof(float)) +
+      return adjoint_work_bytes(*G) + aligned(G->trace_bytes()) + 3 * aligned(N * sizeof(float)) +
              aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + 16 * 256;
     }
     default: return 0;

@@ -254,7 +254,6 @@ struct IterBuffers {
   void* fine;
   float* partial;
   void* e;  // residual, in the storage type
-  float* u;
   float* den;
   double* ess;
   double* pcost;
@@ -268,7 +267,6 @@ IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
   b.fine = cv.take<char>(G.fine_bytes());
   b.partial = cv.take<float>(size_t(G.trace_groups) * N);
   b.e = cv.take<char>(G.trace_bytes());
-  b.u = cv.take<float>(N);
   b.den = cv.take<float>(N);
   b.ess = cv.take<double>(PK);
   b.pcost = cv.take<double>(b.nblk);
@@ -277,7 +275,7 @@ IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
 
 size_t iter_bytes(const umbir_geometry& G) {
   const size_t N = G.voxels(), PK = G.traces();
-  return adjoint_work_bytes(G) + aligned(G.trace_bytes()) + 2 * aligned(N * sizeof(float)) +
+  return adjoint_work_bytes(G) + aligned(G.trace_bytes()) + aligned(N * sizeof(float)) +
          aligned(PK * sizeof(double)) + aligned(((N + kPriorVox - 1) / kPriorVox + 1) * sizeof(double)) + 8 * 256;
 }
 
