@@ -114,8 +114,10 @@ typedef struct {
      * g = 0 .. n_gamma - 1, dgamma = 2 Gamma_max / (n_gamma - 1), Gamma_max the
      * largest one-way path attenuation sum_l alpha_l eta_l / cos(theta_l) of
      * the problem's legs, and each pair uses the template nearest its gamma
-     * (decided per leg in units of 2^-24 of dgamma).  The operators then run
-     * one pass per template: about n_gamma times the work. */
+     * (decided per leg in units of 2^-24 of dgamma).  The forward runs one
+     * splat + convolution per template; the adjoint one correlation per
+     * template, each into its own resident fine grid (its workspace grows
+     * n_gamma-fold), then one gather over all of them. */
     int n_gamma;
 } umbir_acq;
 

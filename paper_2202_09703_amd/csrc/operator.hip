@@ -408,8 +408,11 @@ __device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsr
 // `gbin` are weighted (one pass per template), and with `accum` the first
 // launch adds to the partial image too.  ONE: every group's traces in this
 // launch belong to one scan position, so the transmit legs are loaded once per
-// voxel chunk and only the receive legs per trace.
-template <bool ABSW, int VPT, int ST, bool ATT, bool ONE>
+// voxel chunk and only the receive legs per trace.  MULTI (with ATT): the
+// fine grids of all glast + 1 templates are resident, laid out
+// [trace][template][position], and every pair reads the grid of its own
+// template, so one pass serves all templates.
+template <bool ABSW, int VPT, int ST, bool ATT, bool ONE, bool MULTI>
 __global__ __launch_bounds__(256) void k_gather(
     const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
@@ -429,9 +432,10 @@ __global__ __launch_bounds__(256) void k_gather(
   const int half = n_off / 2;
   const __amdgpu_buffer_rsrc_t leg_rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, nz * n_off * int(sizeof(Leg)), kBufferWord3);
-  const int fine_bytes = MQ * int(sizeof(typename Store<ST>::T));
+  const int grid_elems = MULTI ? (glast + 1) * MQ : MQ;  // one trace's fine data
+  const int fine_bytes = grid_elems * int(sizeof(typename Store<ST>::T));
   struct Legs { int64_t da[VPT], db[VPT]; float pa[VPT], pb[VPT]; int ua[VPT], ub[VPT]; };
-  struct Taps { unsigned J[VPT]; float phi[VPT], w[VPT]; };
+  struct Taps { unsigned J[VPT], J1[VPT]; float phi[VPT], w[VPT]; };
   struct Samples { float c0[VPT], c1[VPT]; };
   for (int vc = v_begin; vc < v_end; vc += blockDim.x * VPT) {
     int col2[VPT], rowoff[VPT];
@@ -478,22 +482,30 @@ __global__ __launch_bounds__(256) void k_gather(
         const int64_t da = ONE ? TX.da[u] : L.da[u];
         const uint64_t D = uint64_t(da + L.db[u]);
         // positions past the record (or past 2^31) clamp to MQ and read zero
-        T.J[u] = unsigned(min(D >> sh, uint64_t(MQ)));
+        const unsigned J = unsigned(min(D >> sh, uint64_t(MQ)));
+        if constexpr (MULTI) {  // the grid of the pair's template; past its record: past the trace's data
+          const unsigned off = unsigned(gamma_bin((ONE ? TX.ua[u] : L.ua[u]) + L.ub[u], glast)) * unsigned(MQ);
+          T.J[u] = J < unsigned(MQ) ? off + J : unsigned(grid_elems);
+          T.J1[u] = J + 1u < unsigned(MQ) ? off + J + 1u : unsigned(grid_elems);
+        } else {
+          T.J[u] = J;
+          T.J1[u] = J + 1u;
+        }
         T.phi[u] = float(uint32_t(D) << qs) * kTwoM32;
         float w = (ONE ? TX.pa[u] : L.pa[u]) * L.pb[u];
         if (ABSW) w = fabsf(w);
-        if constexpr (ATT) w = gamma_bin((ONE ? TX.ua[u] : L.ua[u]) + L.ub[u], glast) == gbin ? w : 0.0f;
+        if constexpr (ATT && !MULTI) w = gamma_bin((ONE ? TX.ua[u] : L.ua[u]) + L.ub[u], glast) == gbin ? w : 0.0f;
         T.w[u] = w * live;
       }
     };
     auto load_samples = [&](const Taps& T, Samples& S, int t) {
       t = min(t, t1 - 1);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<typename Store<ST>::T*>(fine + size_t(t) * MQ), 0, fine_bytes, kBufferWord3);
+          const_cast<typename Store<ST>::T*>(fine + size_t(t) * grid_elems), 0, fine_bytes, kBufferWord3);
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
         S.c0[u] = fine_at<ST>(rs, T.J[u]);
-        S.c1[u] = fine_at<ST>(rs, T.J[u] + 1u);
+        S.c1[u] = fine_at<ST>(rs, T.J1[u]);
       }
     };
     auto add = [&](const Taps& T, const Samples& S) {
@@ -621,11 +633,12 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ fine,
 }
 
 // C^T: c[nQ + t] = sum_k r[n+1+k] h_t[k], for n < M.  Lane = (phase t, block
-// of R consecutive n); writes are coalesced along t.
+// of R consecutive n); writes are coalesced along t.  Trace ij's output
+// starts tstride elements after trace ij - 1's.
 template <int Q>
 __global__ __launch_bounds__(256) void k_corr(const float* __restrict__ rt,
                                               const float* __restrict__ hq, int M, int Lh, int LhPad,
-                                              float* __restrict__ fine) {
+                                              float* __restrict__ fine, long tstride) {
   constexpr int R = kR;
   constexpr int NB = 64 / Q;
   constexpr int PER_WAVE = NB * R;
@@ -657,7 +670,7 @@ __global__ __launch_bounds__(256) void k_corr(const float* __restrict__ rt,
 #pragma unroll
     for (int p = R - 1; p < 2 * R - 1; ++p) buf[p] = ld(mb + p);
   }
-  float* c = fine + size_t(ij) * M * Q + t;
+  float* c = fine + size_t(ij) * tstride + t;
 #pragma unroll
   for (int q = 0; q < R; ++q)
     if (n0 + q < M) c[size_t(n0 + q) * Q] = acc[q];
@@ -691,7 +704,7 @@ __host__ __device__ inline int corr_lds_words(int Q, int rows, int H) {
 template <int QT, int NT>
 __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
                                                    const float* __restrict__ hq, int M, int Lh, int rb_per_block,
-                                                   float* __restrict__ fine, BinSkip bs) {
+                                                   float* __restrict__ fine, long tstride, BinSkip bs) {
   constexpr int Q = 32 * QT;
   constexpr int ROWS = 4 * NT * 32;  // n per row block
   constexpr int KB = 4;              // k per lane per step
@@ -704,7 +717,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   float* seg1 = seg0 + corr_seg_gap(ROWS, H);          // seg1[x] = r[n_blk + 1 + H + x]
   const int ij = blockIdx.x;
   const float* r = rt + size_t(ij) * M;
-  float* c = fine + size_t(ij) * M * Q;
+  float* c = fine + size_t(ij) * tstride;  // trace ij's output (tstride = M Q, or more between templates' grids)
   for (int i = threadIdx.x; i < 2 * H * Q; i += blockDim.x) {
     const int k = i / Q;
     const float v = k < Lh ? hq[i] : 0.0f;
@@ -1153,13 +1166,13 @@ void launch_conv_q(const umbir_geometry& G, const float* fine, const float* hq, 
 }
 
 template <int Q>
-void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, float* fine,
+void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride,
                    hipStream_t s) {
   constexpr int per_block = 4 * (64 / Q) * kR;
   const int LhP = lh_pad(G.Lh);
   dim3 grid(G.traces(), (G.M + per_block - 1) / per_block);
   UMBIR_LAUNCH("corr", k_corr<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, r, hq, G.M,
-               G.Lh, LhP, fine);
+               G.Lh, LhP, fine, tstride);
 }
 
 template <int Q>
@@ -1211,8 +1224,8 @@ void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, c
 }
 
 template <int QT>
-void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine, int gbin,
-                      hipStream_t s) {
+void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride,
+                      int gbin, hipStream_t s) {
   constexpr int NT = 2;
   constexpr int rows = 4 * NT * 32;
   const size_t lds = size_t(corr_lds_words(32 * QT, rows, corr_half(G.Lh))) * sizeof(float);
@@ -1221,7 +1234,7 @@ void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, 
   const int nrb = (G.M + rows - 1) / rows;
   const int per = std::max(1, int((long(G.traces()) * nrb) / 1024));
   dim3 grid(G.traces(), (nrb + per - 1) / per);
-  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine,
+  UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine, tstride,
                bin_skip(G, gbin));
 }
 
@@ -1239,9 +1252,10 @@ void launch_corr_mfma16(const umbir_geometry& G, const void* r, const float* hq,
 }
 
 // gbin >= 0: the pass of attenuation template gbin (rows its template never
-// reaches are left unwritten)
+// reaches are left unwritten).  FP32: trace t's output starts at fine +
+// t * tstride elements (tstride = M Q when 0).
 void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void* fine_v, int gbin,
-                 hipStream_t s) {
+                 hipStream_t s, long tstride = 0) {
   if (G.storage == UMBIR_STORAGE_F16)
     return G.Q == 32 ? launch_corr_mfma16<1, UMBIR_STORAGE_F16>(G, r_v, hq, fine_v, s)
                      : launch_corr_mfma16<2, UMBIR_STORAGE_F16>(G, r_v, hq, fine_v, s);
@@ -1250,14 +1264,15 @@ void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void
                      : launch_corr_mfma16<2, UMBIR_STORAGE_BF16>(G, r_v, hq, fine_v, s);
   const float* r = static_cast<const float*>(r_v);
   float* fine = static_cast<float*>(fine_v);
-  if (G.Q == 32) return launch_corr_mfma<1>(G, r, hq, fine, gbin, s);
-  if (G.Q == 64) return launch_corr_mfma<2>(G, r, hq, fine, gbin, s);
+  const long ts = tstride > 0 ? tstride : long(G.fine_per_trace());
+  if (G.Q == 32) return launch_corr_mfma<1>(G, r, hq, fine, ts, gbin, s);
+  if (G.Q == 64) return launch_corr_mfma<2>(G, r, hq, fine, ts, gbin, s);
   switch (G.Q) {
-    case 1: launch_corr_q<1>(G, r, hq, fine, s); break;
-    case 2: launch_corr_q<2>(G, r, hq, fine, s); break;
-    case 4: launch_corr_q<4>(G, r, hq, fine, s); break;
-    case 8: launch_corr_q<8>(G, r, hq, fine, s); break;
-    default: launch_corr_q<16>(G, r, hq, fine, s); break;
+    case 1: launch_corr_q<1>(G, r, hq, fine, ts, s); break;
+    case 2: launch_corr_q<2>(G, r, hq, fine, ts, s); break;
+    case 4: launch_corr_q<4>(G, r, hq, fine, ts, s); break;
+    case 8: launch_corr_q<8>(G, r, hq, fine, ts, s); break;
+    default: launch_corr_q<16>(G, r, hq, fine, ts, s); break;
   }
 }
 
@@ -1286,19 +1301,19 @@ void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, c
   }
 }
 
-template <int ST, bool ATT, bool ONE>
+template <int ST, bool ATT, bool ONE, bool MULTI>
 void launch_gather_k(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
                      int batch, int vpb, int gbin, int accum, const void* fine, float* partial, hipStream_t s) {
   using T = typename Store<ST>::T;
   constexpr int VPT = 4;
   if (abs_op)
-    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST, ATT, ONE>), grid, dim3(256), 0, s, static_cast<const T*>(fine),
-                 G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
-                 G.n_gamma - 1, accum, partial);
+    UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST, ATT, ONE, MULTI>), grid, dim3(256), 0, s,
+                 static_cast<const T*>(fine), G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg,
+                 t_off, batch, vpb, gbin, G.n_gamma - 1, accum, partial);
   else
-    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST, ATT, ONE>), grid, dim3(256), 0, s, static_cast<const T*>(fine),
-                 G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, vpb, gbin,
-                 G.n_gamma - 1, accum, partial);
+    UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST, ATT, ONE, MULTI>), grid, dim3(256), 0, s,
+                 static_cast<const T*>(fine), G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg,
+                 t_off, batch, vpb, gbin, G.n_gamma - 1, accum, partial);
 }
 
 // Does every trace group's range of this launch lie within one scan position?
@@ -1312,13 +1327,16 @@ bool gather_one_scan(const umbir_geometry& G, int tpg, int t_off, int batch) {
   return true;
 }
 
-template <int ST, bool ATT>
+// MULTI: one pass over the resident grids of all templates (see k_gather)
+template <int ST, bool ATT, bool MULTI = false>
 void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
                    int batch, int vpb, int gbin, int accum, const void* fine, float* partial, hipStream_t s) {
   if (gather_one_scan(G, tpg, t_off, batch))
-    launch_gather_k<ST, ATT, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gbin, accum, fine, partial, s);
+    launch_gather_k<ST, ATT, true, MULTI>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gbin, accum, fine,
+                                          partial, s);
   else
-    launch_gather_k<ST, ATT, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gbin, accum, fine, partial, s);
+    launch_gather_k<ST, ATT, false, MULTI>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gbin, accum, fine,
+                                           partial, s);
 }
 
 }  // namespace
@@ -1406,10 +1424,28 @@ int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, voi
   // (4 MiB by default, one XCD's L2: the autotuner's choice on the 256 x 256
   // and 512 x 512 workloads, 1-2 % faster per reconstruction than 8 MiB and
   // 3-5 % faster than 2 MiB)
+  const bool multi = G.multi_grid();
+  // (with every template's grid resident a pair still reads one grid: the
+  // batch is sized by one grid per trace)
   const size_t trace_bytes = size_t(MQ) * G.elem();
   const int batch =
       int(std::max<size_t>(1, std::min<size_t>(tpg, (size_t(G.gather_batch_kb) << 10) / trace_bytes)));
   int st = UMBIR_OK;
+  if (multi) {
+    // attenuation with every template's grid resident: one correlation per
+    // template into its own grid ([trace][template][position]), then one
+    // gather in which every pair reads its own template's grid
+    const long tstride = long(G.n_gamma) * MQ;
+    for (int gb = 0; gb < G.n_gamma; ++gb) {
+      launch_corr(G, r, (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin(),
+                  static_cast<float*>(fine) + size_t(gb) * MQ, gb, s, tstride);
+      if ((st = check_hip(hipGetLastError(), "k_corr"))) return st;
+    }
+    for (int t_off = 0; t_off < tpg; t_off += batch)
+      launch_gather<UMBIR_STORAGE_F32, true, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
+                                                   partial, s);
+    return check_hip(hipGetLastError(), "k_gather");
+  }
   // one correlation + gather per attenuation template (one without
   // attenuation); later passes add to the partial images
   for (int gb = 0; gb < G.n_gamma; ++gb) {
