@@ -343,14 +343,17 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
 // nonzero for 1 <= k <= Q L_h.
 struct IcdGroup {
   int r0, c0;  // first row and column of the class
-  int gc;      // columns in the group
+  int gr;      // rows in the group
   int size;    // members
 };
 
+// Member i of a group, rows fastest: neighbouring lanes take members of one
+// column Sr rows apart, whose delays differ by far more than those of
+// neighbouring columns, so their windows meet fewer common samples at once.
 __device__ __forceinline__ void icd_member(const IcdGroup& gp, int Sr, int Sc, int i, int* row, int* col) {
-  const int rr = i / gp.gc;
-  *row = gp.r0 + rr * Sr;
-  *col = gp.c0 + (i - rr * gp.gc) * Sc;
+  const int cc = i / gp.gr;
+  *row = gp.r0 + (i - cc * gp.gr) * Sr;
+  *col = gp.c0 + cc * Sc;
 }
 
 // delay (Q32.32 samples) and weight of voxel (row, col) in trace t
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_dots(const float* __restric
       const int k = int(long(m) * Q - w.J);
       acc = fmaf(se[m], fmaf(w.phi, sb[k - 1] - sb[k], sb[k]), acc);
     }
-    partial[size_t(t) * gp.size + i] = W * acc;
+    partial[size_t(i) * gridDim.x + t] = W * acc;  // member-major: the step reads a member's traces together
   }
 }
 
@@ -423,7 +426,8 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_dots(const float* __restric
 // x_v += step_i, delta[i] = step_i, and the largest |step| into *dmax.
 template <bool CURV>
 __global__ __launch_bounds__(256) void k_icd_step(const float* __restrict__ partial, int PK, IcdGroup gp, int Sr,
-                                                  int Sc, int nx, int nz, PriorConst pc, float* __restrict__ den,
+                                                  int Sc, int nx, int nz, PriorConst pc,
+                                                  const float* __restrict__ ms_row, float* __restrict__ den,
                                                   float* __restrict__ x, float* __restrict__ delta,
                                                   unsigned* __restrict__ dmax) {
   const int lane = threadIdx.x & 63;
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(256) void k_icd_step(const float* __restrict__ part
   icd_member(gp, Sr, Sc, i, &row, &col);
   const int v = row * nx + col;
   double acc = 0.0;
-  for (int t = lane; t < PK; t += 64) acc += partial[size_t(t) * gp.size + i];
+  for (int t = lane; t < PK; t += 64) acc += partial[size_t(i) * PK + t];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane != 0) return;
   if (CURV) {
@@ -445,12 +449,12 @@ __global__ __launch_bounds__(256) void k_icd_step(const float* __restrict__ part
   const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
   const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
   const float xs = x[v];
-  const float ms = depth_mod(row, nz, pc);
+  const float ms = ms_row[row];
   float slope = 0.0f, curv = 0.0f;
   for (int dr = -1; dr <= 1; ++dr) {
     const int r2 = row + dr;
     if (r2 < 0 || r2 >= nz) continue;
-    const float sg = pc.sigma0 * sqrtf(ms * depth_mod(r2, nz, pc));
+    const float sg = pc.sigma0 * sqrtf(ms * ms_row[r2]);
     for (int dc = -1; dc <= 1; ++dc) {
       const int c2 = col + dc;
       if ((dr == 0 && dc == 0) || c2 < 0 || c2 >= nx) continue;
@@ -518,6 +522,12 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_scatter(float* __restrict__
   }
 }
 
+// m_s of Eq. (17) per row
+__global__ void k_depth_rows(int nz, PriorConst pc, float* __restrict__ ms_row) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nz) ms_row[r] = depth_mod(r, nz, pc);
+}
+
 // delta[i] = -1 for every member and *dmax = 1: a scatter then adds the
 // group's columns (e -= -1 * column)
 __global__ void k_icd_unit(int n, float* __restrict__ delta, unsigned* __restrict__ dmax) {
@@ -530,9 +540,9 @@ IcdGroup icd_group(const umbir_geometry& G, int Sr, int Sc, int k) {
   IcdGroup gp;
   gp.r0 = k / Sc;
   gp.c0 = k % Sc;
-  const int gr = gp.r0 < G.nz ? (G.nz - gp.r0 + Sr - 1) / Sr : 0;
-  gp.gc = gp.c0 < G.nx ? (G.nx - gp.c0 + Sc - 1) / Sc : 0;
-  gp.size = gr * gp.gc;
+  gp.gr = gp.r0 < G.nz ? (G.nz - gp.r0 + Sr - 1) / Sr : 0;
+  const int gc = gp.c0 < G.nx ? (G.nx - gp.c0 + Sc - 1) / Sc : 0;
+  gp.size = gp.gr * gc;
   return gp;
 }
 
@@ -545,6 +555,7 @@ size_t icd_bytes(const umbir_geometry& G, int Sr, int Sc) {
   const size_t gmax = size_t(icd_max_group(G, Sr, Sc));
   const size_t nblk = (N + kPriorVox - 1) / kPriorVox + 1;
   return forward_work_bytes(G) + 2 * aligned(G.trace_bytes()) + aligned(N * sizeof(float)) +
+         aligned(size_t(G.nz) * sizeof(float)) +
          aligned(PK * gmax * sizeof(float)) + aligned(gmax * sizeof(float)) + aligned(PK * sizeof(double)) +
          aligned(nblk * sizeof(double)) + 16 * 256;
 }
@@ -768,6 +779,7 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
   float* e = cv.take<float>(size_t(PK) * M);
   float* etmp = cv.take<float>(size_t(PK) * M);
   float* den = cv.take<float>(N);
+  float* ms_row = cv.take<float>(G->nz);
   float* part = cv.take<float>(size_t(PK) * gmax);
   float* delta = cv.take<float>(size_t(gmax));
   double* ess = cv.take<double>(PK);
@@ -802,6 +814,7 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
   const dim3 sblk(256);
   auto sgrid = [](const IcdGroup& gp) { return dim3(unsigned((gp.size + 3) / 4)); };
 
+  UMBIR_LAUNCH("depth_rows", k_depth_rows, dim3(unsigned((G->nz + 255) / 256)), dim3(256), 0, s, G->nz, pc, ms_row);
   // group curvatures dG = (Abar^T Abar 1_G) on each group's members: the
   // group's |A| columns summed into a cleared trace buffer, then |A|^T of it
   for (int k = 0; k < n_groups; ++k) {
@@ -812,8 +825,8 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
                  dmax);
     scatter(true, gp, etmp);
     dots(true, gp, etmp, nullptr);
-    UMBIR_LAUNCH("icd_step", k_icd_step<true>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc, den,
-                 nullptr, nullptr, nullptr);
+    UMBIR_LAUNCH("icd_step", k_icd_step<true>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc,
+                 ms_row, den, nullptr, nullptr, nullptr);
   }
   if ((st = check_hip(hipGetLastError(), "icd curvature"))) return st;
   // e = y - A x - D g
@@ -833,7 +846,7 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
       if (gp.size == 0) continue;
       dots(false, gp, e, dmax);
       UMBIR_LAUNCH("icd_step", k_icd_step<false>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc,
-                   den, x_io, delta, dmax);
+                   ms_row, den, x_io, delta, dmax);
       scatter(false, gp, e);
     }
     if ((st = check_hip(hipGetLastError(), "icd sweep"))) return st;
