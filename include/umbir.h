@@ -47,7 +47,7 @@ enum {
     UMBIR_EINVAL = -1,    /* invalid argument, problem or prior */
     UMBIR_ENOMEM = -2,    /* device allocation failed */
     UMBIR_EDEVICE = -3,   /* HIP runtime or kernel launch error, or no device */
-    UMBIR_ENOTSUP = -4,   /* valid input outside what this build implements */
+    UMBIR_ENOTSUP = -4,   /* valid input outside what the library implements */
     UMBIR_EDIVERGED = -5  /* the MAP cost became non-finite */
 };
 

@@ -464,7 +464,7 @@ const char* umbir_strerror(int status) {
     case UMBIR_EINVAL: return "invalid argument";
     case UMBIR_ENOMEM: return "out of device memory";
     case UMBIR_EDEVICE: return "HIP device error";
-    case UMBIR_ENOTSUP: return "not supported by this build";
+    case UMBIR_ENOTSUP: return "not supported by the library";
     case UMBIR_EDIVERGED: return "MAP cost diverged";
     default: return "unknown status";
   }
