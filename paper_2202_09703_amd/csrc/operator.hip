@@ -390,11 +390,12 @@ __device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsr
 }
 
 // S^T: per voxel, sum over the traces of group blockIdx.x of W ((1 - phi) c[J]
-// + phi c[J + 1]); one partial image per group, summed in a fixed order by
-// k_reduce_groups.  The group is the fastest block index, so group g runs on
-// XCD g mod 8 and that XCD's L2 only ever holds its own traces' fine-grid
-// data.  One launch covers a batch of each group's traces (about 8 MB of
-// fine-grid data per XCD, read by every block of the XCD while the batch is
+// + phi c[J + 1]); one partial image per group, summed in a fixed order (by
+// k_reduce_groups, or by the prior update in an iteration).  The group is the
+// fastest block index, so group g runs on XCD g mod 8 and that XCD's L2 only
+// ever holds its own traces' fine-grid data.  One launch covers a batch of
+// each group's traces (4 MiB of fine-grid data per group by default, read by
+// every block of the XCD while the batch is
 // warm in L2 and the last-level cache; blocks cannot be kept in step within a
 // launch, but launch boundaries are barriers), and the partial images
 // accumulate across launches in a fixed order.  The grid is one generation (at
