@@ -146,19 +146,21 @@ struct umbir_geometry {
   // fine-grid workspace: P K M Q elements, then the splat's prescaled image
   // (nz nx floats), then one 32-bit scalar
   size_t fine_grid_bytes() const { return (size_t(traces()) * fine_per_trace() * elem() + 15) & ~size_t(15); }
-  // with attenuation the adjoint keeps every template's grid resident
-  // ([trace][template][position]) when one trace's grids fit 32-bit offsets
+  // with attenuation every template's grid is kept resident when one trace's
+  // grids fit 32-bit offsets (the forward writes them [template][trace]
+  // [position], the adjoint [trace][template][position])
   bool multi_grid() const {
     return n_gamma > 1 && storage == UMBIR_STORAGE_F32 &&
            size_t(n_gamma) * fine_per_trace() * elem() < (size_t(1) << 31);
   }
-  // the fine-grid workspace: the forward's grid, prescaled image and scalar,
-  // or the adjoint's grids of all templates when larger
-  size_t fine_bytes() const {
-    const size_t fwd = fine_grid_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 16;
-    const size_t all = multi_grid() ? (size_t(traces()) * n_gamma * fine_per_trace() * elem() + 15) & ~size_t(15) : 0;
-    return fwd > all ? fwd : all;
+  // the fine grid(s): one, or with multi_grid() one per template
+  size_t grids_bytes() const {
+    return multi_grid() ? (size_t(traces()) * n_gamma * fine_per_trace() * elem() + 15) & ~size_t(15)
+                        : fine_grid_bytes();
   }
+  // the fine-grid workspace: the grid(s), then the forward's prescaled image
+  // and one scalar
+  size_t fine_bytes() const { return grids_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 16; }
   size_t trace_bytes() const { return size_t(traces()) * M * elem(); }
   size_t taps_per_bin() const { return size_t(Q) * Lh; }
 };

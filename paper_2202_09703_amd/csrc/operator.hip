@@ -202,15 +202,21 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 // the result is bitwise reproducible), scaled by 2^k from splat_exponent.
 // Tiles are written out whole (coalesced), so the fine buffer needs no
 // clearing.  With ATT only the voxels whose attenuation bin (from the two
-// legs' units) is `gbin` are added: one pass per template.
-template <bool ABSW, bool WIDE, int ST, bool ATT>
+// legs' units) is `gbin` are added: one pass per template.  With MT (and ATT)
+// the block keeps one tile per template (glast + 1 of them) and every voxel
+// is added to its own template's tile: one pass serves all templates, whose
+// grids are written [template][trace][position] (each template's grid as the
+// convolution reads it).
+template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const int* __restrict__ base,
     int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
-  unsigned long long* tile = smem;                                   // [tile_bins + 2]
-  int2* pn = reinterpret_cast<int2*>(smem + tile_bins + 2);          // [seg.n][nx] {next row, its position}
+  const int NT = MT ? glast + 1 : 1;                                 // tiles
+  const int TS = tile_bins + 2;                                      // a tile, its carry and never-read slots
+  unsigned long long* tile = smem;                                   // [NT][TS]
+  int2* pn = reinterpret_cast<int2*>(smem + NT * TS);                // [seg.n][nx] {next row, its position}
   int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of row 0's records
   __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
   const int kx = splat_exponent(*xmax, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   const int half = n_off / 2;
   const int sh = 32 - qs;  // J = (D_tx + D_rx) >> (32 - log2 Q)
   typename Store<ST>::T* out = fine + size_t(ij) * MQ;
-  if (ATT && !bin_reaches(bs, ij, J_begin, J_end)) {  // uniform: no voxel of the template here
+  if (ATT && !MT && !bin_reaches(bs, ij, J_begin, J_end)) {  // uniform: no voxel of the template here
     for (int k = J_begin + threadIdx.x; k < J_end; k += blockDim.x) out[k] = Store<ST>::put(0.0f);
     return;
   }
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const int first = first_row_at(pos, lo, hi, jl, jh, J_begin - 1, &jf);
     pn[i] = make_int2(first, jf);
   }
-  for (int k = threadIdx.x; k <= tile_bins; k += blockDim.x) tile[k] = 0ull;
+  for (int k = threadIdx.x; k < NT * TS; k += blockDim.x) tile[k] = 0ull;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -326,14 +332,19 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
           const bool in = have && J < J1;
           // J + 1 >= J0 holds while delays grow with depth within a layer
           bool mine = true;
-          if constexpr (ATT) mine = gamma_bin(v.ua + v.ub, glast) == gbin;
+          int tb = 0;  // MT: the tile of the voxel's template
+          if constexpr (ATT) {
+            const int b = gamma_bin(v.ua + v.ub, glast);
+            if constexpr (MT) tb = b * TS;
+            else mine = b == gbin;
+          }
           if (in && mine && v.xv != 0.0f && J + 1 >= J0) {
             float w = v.xv * (v.pa * v.pb);
             if (ABSW) w = fabsf(w);
             const float phi = float(uint32_t(D) << qs) * kTwoM32;
             const float w1 = w * phi;
-            atomicAdd(&tile[J >= J0 ? J - J0 : tile_bins + 1], to_fixed<WIDE>(w - w1, scale));
-            atomicAdd(&tile[J + 1 - J0], to_fixed<WIDE>(w1, scale));
+            atomicAdd(&tile[tb + (J >= J0 ? J - J0 : tile_bins + 1)], to_fixed<WIDE>(w - w1, scale));
+            atomicAdd(&tile[tb + J + 1 - J0], to_fixed<WIDE>(w1, scale));
           }
           const int cnt = __popcll(__ballot(in) & colmask);  // rows of column c taken
           if (live && rr == cnt) pn[slot] = make_int2(r, have ? J : kNoRow);
@@ -358,15 +369,29 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     // flush: write the tile out and clear it in one pass; the carry slot n is
     // outside the pass and becomes the next tile's first position
     const int n = J1 - J0;
-    const unsigned long long carry = tile[n];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-      out[J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[k]), -kx));
-      tile[k] = 0ull;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      tile[0] = carry;
-      tile[n] = 0ull;
+    if constexpr (MT) {
+      const unsigned long long carry = threadIdx.x < NT ? tile[threadIdx.x * TS + n] : 0ull;
+      for (int i = threadIdx.x; i < NT * n; i += blockDim.x) {
+        const int g = i / n, k = i - g * n;
+        out[size_t(g) * P * K * MQ + J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[g * TS + k]), -kx));
+        tile[g * TS + k] = 0ull;
+      }
+      __syncthreads();
+      if (threadIdx.x < NT) {
+        tile[threadIdx.x * TS] = carry;
+        tile[threadIdx.x * TS + n] = 0ull;
+      }
+    } else {
+      const unsigned long long carry = tile[n];
+      for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        out[J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[k]), -kx));
+        tile[k] = 0ull;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        tile[0] = carry;
+        tile[n] = 0ull;
+      }
     }
     __syncthreads();
   }
@@ -582,7 +607,7 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ fine,
                                               const float* __restrict__ hq, int M, int Lh, int LhPad,
                                               const float* base, float sign,
                                               const float* __restrict__ g,
-                                              const float* __restrict__ dbasis, float* out) {
+                                              const float* __restrict__ dbasis, float* out, long tstride) {
   constexpr int R = kR;
   constexpr int MB = 64 / Q;
   constexpr int PER_WAVE = MB * R;
@@ -592,7 +617,7 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ fine,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = lane & (Q - 1), mb = lane / Q;
   const int m0 = blockIdx.y * (4 * PER_WAVE) + wave * PER_WAVE + mb * R;
-  const float* s = fine + size_t(ij) * M * Q + t;
+  const float* s = fine + size_t(ij) * tstride + t;  // trace ij's fine-grid signal
   auto ld = [&](int n) -> float { return (n >= 0 && n < M) ? s[size_t(n) * Q] : 0.0f; };
   float acc[R];
   float buf[2 * R];
@@ -857,7 +882,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
-                                                   const float* __restrict__ dbasis, float* out, BinSkip bs) {
+                                                   const float* __restrict__ dbasis, float* out, long tstride,
+                                                   BinSkip bs) {
   constexpr int CK = 64;        // (n, t) positions per chunk
   constexpr int CN = CK / Q;    // rows n per chunk
   constexpr int TS = Q + 4;     // tap row stride
@@ -888,7 +914,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   // output columns that are never written).  Loads are unconditional, from a
   // row clamped into [0, M); a row outside [0, M), or a step past the window,
   // takes the A row of zeros instead, so B needs no masking.
-  const float* src = fine + size_t(min(tr0 + li, PK - 1)) * MQ + t0;
+  const float* src = fine + size_t(min(tr0 + li, PK - 1)) * tstride + t0;
   // the chunk of step ch = rd 4 + wave advances by 4 per round, modulo P
   int jf = (wave + co.rot) % co.P, jm = jf;  // fetch and multiply positions
   int sf = wave, sm_ = wave;                  // their steps
@@ -1158,12 +1184,12 @@ int lh_pad(int Lh) { return (Lh + kR - 1) / kR * kR; }
 
 template <int Q>
 void launch_conv_q(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
-                   float sign, const float* g, float* out, hipStream_t s) {
+                   float sign, const float* g, float* out, long tstride, hipStream_t s) {
   constexpr int per_block = 4 * (64 / Q) * kR;
   const int LhP = lh_pad(G.Lh);
   dim3 grid(G.traces(), (G.M + per_block - 1) / per_block);
   UMBIR_LAUNCH("conv", k_conv<Q>, grid, dim3(256), size_t(LhP) * Q * sizeof(float), s, fine, hq, G.M,
-               G.Lh, LhP, base, sign, g, G.dbasis, out);
+               G.Lh, LhP, base, sign, g, G.dbasis, out, tstride);
 }
 
 template <int Q>
@@ -1178,12 +1204,12 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
 
 template <int Q>
 void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
-                      float sign, const float* g, float* out, int gbin, hipStream_t s) {
+                      float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
   // padded taps, reused for the four partial tiles at the end
   const size_t lds = std::max<size_t>(size_t(G.Lh + 2 * kConvTapPad) * (Q + 4), 4 * 32 * 33) * sizeof(float);
   dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
   UMBIR_LAUNCH("conv", k_conv_mfma<Q>, grid, dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
-               sign, g, G.dbasis, out, bin_skip(G, gbin));
+               sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
 }
 
 template <int Q, int ST>
@@ -1199,9 +1225,10 @@ void launch_conv_mfma16(const umbir_geometry& G, const void* fine, const float* 
 }
 
 // gbin >= 0: the pass of attenuation template gbin (output tiles its template
-// never reaches skip their products)
+// never reaches skip their products).  FP32: trace t's fine-grid signal starts
+// at fine + t * tstride elements (tstride = M Q when 0).
 void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, const void* base_v,
-                 float sign, const float* g, void* out_v, int gbin, hipStream_t s) {
+                 float sign, const float* g, void* out_v, int gbin, hipStream_t s, long tstride = 0) {
   if (G.storage == UMBIR_STORAGE_F16) {
     if (G.Q == 32) return launch_conv_mfma16<32, UMBIR_STORAGE_F16>(G, fine_v, hq, base_v, sign, g, out_v, s);
     return launch_conv_mfma16<64, UMBIR_STORAGE_F16>(G, fine_v, hq, base_v, sign, g, out_v, s);
@@ -1213,14 +1240,15 @@ void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, c
   const float* fine = static_cast<const float*>(fine_v);
   const float* base = static_cast<const float*>(base_v);
   float* out = static_cast<float*>(out_v);
-  if (G.Q == 32) return launch_conv_mfma<32>(G, fine, hq, base, sign, g, out, gbin, s);
-  if (G.Q == 64) return launch_conv_mfma<64>(G, fine, hq, base, sign, g, out, gbin, s);
+  const long ts = tstride > 0 ? tstride : long(G.fine_per_trace());
+  if (G.Q == 32) return launch_conv_mfma<32>(G, fine, hq, base, sign, g, out, ts, gbin, s);
+  if (G.Q == 64) return launch_conv_mfma<64>(G, fine, hq, base, sign, g, out, ts, gbin, s);
   switch (G.Q) {
-    case 1: launch_conv_q<1>(G, fine, hq, base, sign, g, out, s); break;
-    case 2: launch_conv_q<2>(G, fine, hq, base, sign, g, out, s); break;
-    case 4: launch_conv_q<4>(G, fine, hq, base, sign, g, out, s); break;
-    case 8: launch_conv_q<8>(G, fine, hq, base, sign, g, out, s); break;
-    default: launch_conv_q<16>(G, fine, hq, base, sign, g, out, s); break;
+    case 1: launch_conv_q<1>(G, fine, hq, base, sign, g, out, ts, s); break;
+    case 2: launch_conv_q<2>(G, fine, hq, base, sign, g, out, ts, s); break;
+    case 4: launch_conv_q<4>(G, fine, hq, base, sign, g, out, ts, s); break;
+    case 8: launch_conv_q<8>(G, fine, hq, base, sign, g, out, ts, s); break;
+    default: launch_conv_q<16>(G, fine, hq, base, sign, g, out, ts, s); break;
   }
 }
 
@@ -1279,26 +1307,40 @@ void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void
 
 size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 
-template <bool ABSW, bool WIDE, int ST, bool ATT>
-void launch_splat_k(const umbir_geometry& G, dim3 grid, size_t lds, const float* xt, int qs, int MQ,
-                    const Segments& seg, const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
-  using T = typename Store<ST>::T;
-  UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx, G.n_off,
-               G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), G.tile_bins, xmax, gbin, G.n_gamma - 1,
-               bin_skip(G, ATT ? gbin : -1), static_cast<T*>(fine));
+// Tile of the all-templates splat: one tile per template beside the row
+// pointers in 64 KiB of LDS, a multiple of 64 positions and at most the usual
+// tile; 0 if not even 64 positions per template fit.
+int splat_mt_tile(const umbir_geometry& G) {
+  const long avail = 65536 - 1024 - long(G.n_seg + 1) * G.nx * long(sizeof(int2));
+  const long per = avail / long(sizeof(unsigned long long)) / G.n_gamma - 2;
+  const long t = std::min<long>(G.tile_bins, per / 64 * 64);
+  return t >= 64 ? int(t) : 0;
 }
 
-// ATT: the splat pass of template gbin (attenuation bins, FP32 storage only)
-template <int ST, bool ATT>
-void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, size_t lds, const float* xt, int qs, int MQ,
+template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
+void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs, int MQ, const Segments& seg,
+                    const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  const int nt = MT ? G.n_gamma : 1;
+  const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
+  const size_t lds = size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
+  UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
+               G.n_off, G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, gbin, G.n_gamma - 1,
+               bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine));
+}
+
+// ATT: the splat pass of template gbin (attenuation bins, FP32 storage only);
+// MT (with ATT): one pass over every template's grid
+template <int ST, bool ATT, bool MT = false>
+void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, const float* xt, int qs, int MQ,
                   const Segments& seg, const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
   const bool wide = G.nx * (seg.hi[seg.n - 1] - seg.lo[0]) < kSplatNarrowMin;
   if (abs_op) {
-    if (wide) launch_splat_k<true, true, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
-    else launch_splat_k<true, false, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    if (wide) launch_splat_k<true, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    else launch_splat_k<true, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
   } else {
-    if (wide) launch_splat_k<false, true, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
-    else launch_splat_k<false, false, ST, ATT>(G, grid, lds, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    if (wide) launch_splat_k<false, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    else launch_splat_k<false, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
   }
 }
 
@@ -1366,9 +1408,9 @@ int log2_int(int q) {
 
 int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base, float sign,
                 const float* g, bool abs_op, void* fine, hipStream_t s) {
-  // after the fine grid: the prescaled image tau x, then one 32-bit scalar,
-  // the largest |tau x|
-  float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.fine_grid_bytes());
+  // after the fine grid(s): the prescaled image tau x, then one 32-bit
+  // scalar, the largest |tau x|
+  float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.grids_bytes());
   unsigned* xmax = reinterpret_cast<unsigned*>(static_cast<char*>(fine) + G.fine_bytes() - 16);
   const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
@@ -1381,24 +1423,37 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(xmax), size_t(1), 0.0f);
   UMBIR_LAUNCH("prescale", k_prescale, dim3(std::min(128, (G.voxels() + 1023) / 1024)), dim3(1024), 0, s, x,
                G.tau, G.nx, G.voxels(), xt, xmax);
-  const size_t lds = size_t(G.tile_bins + 2) * sizeof(unsigned long long) +
-                     size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   dim3 grid(G.chunks, G.traces());
+  if (G.multi_grid() && splat_mt_tile(G) > 0) {
+    // attenuation with every template's grid resident: one splat walk fills
+    // them all ([template][trace][position]), then one convolution per
+    // template; later ones add to the traces the first one wrote
+    launch_splat<UMBIR_STORAGE_F32, true, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
+    int st = check_hip(hipGetLastError(), "k_splat");
+    if (st) return st;
+    for (int gb = 0; gb < G.n_gamma; ++gb) {
+      const float* taps = (abs_op ? G.habs : G.h) + size_t(gb) * G.taps_per_bin();
+      launch_conv(G, static_cast<float*>(fine) + size_t(gb) * G.traces() * MQ, taps, gb == 0 ? base : out, sign,
+                  gb == 0 ? g : nullptr, out, gb, s);
+      if ((st = check_hip(hipGetLastError(), "k_conv"))) return st;
+    }
+    return UMBIR_OK;
+  }
   // one splat + convolution per attenuation template (one without
   // attenuation); later passes add to the traces the first one wrote
   for (int gb = 0; gb < G.n_gamma; ++gb) {
     switch (G.storage) {
       case UMBIR_STORAGE_F16:
-        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, 0, fine, s);
+        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
         break;
       case UMBIR_STORAGE_BF16:
-        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, 0, fine, s);
+        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
         break;
       default:
         if (G.n_gamma > 1)
-          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, gb, fine, s);
+          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, gb, fine, s);
         else
-          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, lds, xt, qs, MQ, seg, xmax, 0, fine, s);
+          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
         break;
     }
     int st = check_hip(hipGetLastError(), "k_splat");
