@@ -386,50 +386,71 @@ __device__ __forceinline__ IcdWindow icd_window(int64_t D, int qs, int Q, int QL
 
 constexpr int kIcdThreads = 1024;
 
-// partial[t][i] = A_{t, v_i}^T e_t for the members i of the group (ABS: the
-// operator of |W| and |b|).  Block (0, 0) also clears the group's step
-// maximum for k_icd_step.
+// Window of member i in trace t: its samples lo, lo + 1, ... read the
+// template at bk[d Q - 1] and bk[d Q] (k = lo Q - J + d Q), and its weight.
+struct IcdSpan {
+  const float* bk;
+  int lo, n;  // first sample and count (0: no sample)
+  float phi, W;
+};
+
+template <bool ABS>
+__device__ __forceinline__ IcdSpan icd_span(const float* sb, int Q, int qs, int QLh, int M,
+                                            const Leg* __restrict__ legs, int n_off, const int* __restrict__ base,
+                                            int P, int K, const float* __restrict__ tau, int t, int row, int col) {
+  int64_t D;
+  IcdSpan o;
+  icd_pair(legs, n_off, base, P, K, tau, t, row, col, &D, &o.W);
+  if (ABS) o.W = fabsf(o.W);
+  const IcdWindow w = icd_window(D, qs, Q, QLh, M);
+  o.lo = w.m_lo;
+  o.n = w.m_hi >= w.m_lo ? w.m_hi - w.m_lo + 1 : 0;
+  o.phi = w.phi;
+  o.bk = o.n ? sb + (long(w.m_lo) * Q - w.J) : sb + 1;  // lo Q - J >= 1: delays are non-negative
+  return o;
+}
+
+// partial[i][t] = A_{t, v_i}^T e_t for the members i of the group (ABS: the
+// operator of |W| and |b|): one thread per member over its window, with the
+// trace and the template in LDS.
 template <bool ABS>
 __global__ __launch_bounds__(kIcdThreads) void k_icd_dots(const float* __restrict__ e, int M,
                                                           const float* __restrict__ bank, int Q, int qs, int QLh,
                                                           const Leg* __restrict__ legs, int n_off,
                                                           const int* __restrict__ base, int P, int K,
                                                           const float* __restrict__ tau, IcdGroup gp, int Sr, int Sc,
-                                                          float* __restrict__ partial, unsigned* __restrict__ dmax) {
+                                                          float* __restrict__ partial) {
   extern __shared__ float sm[];
   float* se = sm;      // [M]
   float* sb = sm + M;  // [QLh + 2]
   const int t = blockIdx.x;
-  if (dmax && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *dmax = 0u;
   for (int m = threadIdx.x; m < M; m += blockDim.x) se[m] = e[size_t(t) * M + m];
   for (int n = threadIdx.x; n < QLh + 2; n += blockDim.x) sb[n] = ABS ? fabsf(bank[n]) : bank[n];
   __syncthreads();
   for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < gp.size; i += gridDim.y * blockDim.x) {
     int row, col;
     icd_member(gp, Sr, Sc, i, &row, &col);
-    int64_t D;
-    float W;
-    icd_pair(legs, n_off, base, P, K, tau, t, row, col, &D, &W);
-    if (ABS) W = fabsf(W);
-    const IcdWindow w = icd_window(D, qs, Q, QLh, M);
+    const IcdSpan w = icd_span<ABS>(sb, Q, qs, QLh, M, legs, n_off, base, P, K, tau, t, row, col);
+    const float* ev = se + w.lo;
     float acc = 0.0f;
-    for (int m = w.m_lo; m <= w.m_hi; ++m) {
-      const int k = int(long(m) * Q - w.J);
-      acc = fmaf(se[m], fmaf(w.phi, sb[k - 1] - sb[k], sb[k]), acc);
+#pragma unroll 4
+    for (int d = 0; d < w.n; ++d) {
+      const float* b = w.bk + d * Q;
+      acc = fmaf(ev[d], fmaf(w.phi, b[-1] - b[0], b[0]), acc);
     }
-    partial[size_t(i) * gridDim.x + t] = W * acc;  // member-major: the step reads a member's traces together
+    partial[size_t(i) * gridDim.x + t] = w.W * acc;  // member-major: the step reads a member's traces together
   }
 }
 
 // One wave per member: the trace sum of its partials (lane strides, then a
-// fixed shuffle tree).  CURV: den[v] = that sum.  Otherwise the member step:
-// x_v += step_i, delta[i] = step_i, and the largest |step| into *dmax.
+// fixed shuffle tree).  CURV: den[v] = that sum.  Otherwise the member step
+// x_v += step_i, delta[i] = step_i; the prior's eight neighbour terms are
+// taken by lanes 0..7 and summed in a fixed tree.
 template <bool CURV>
 __global__ __launch_bounds__(256) void k_icd_step(const float* __restrict__ partial, int PK, IcdGroup gp, int Sr,
                                                   int Sc, int nx, int nz, PriorConst pc,
                                                   const float* __restrict__ ms_row, float* __restrict__ den,
-                                                  float* __restrict__ x, float* __restrict__ delta,
-                                                  unsigned* __restrict__ dmax) {
+                                                  float* __restrict__ x, float* __restrict__ delta) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= gp.size) return;  // uniform over the wave
@@ -439,43 +460,44 @@ __global__ __launch_bounds__(256) void k_icd_step(const float* __restrict__ part
   double acc = 0.0;
   for (int t = lane; t < PK; t += 64) acc += partial[size_t(i) * PK + t];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane != 0) return;
   if (CURV) {
-    den[v] = float(acc);
+    if (lane == 0) den[v] = float(acc);
     return;
   }
-  const float theta1 = -float(acc) * pc.inv_sigma2;
-  const float theta2 = den[v] * pc.inv_sigma2;
-  const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
-  const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
   const float xs = x[v];
-  const float ms = ms_row[row];
   float slope = 0.0f, curv = 0.0f;
-  for (int dr = -1; dr <= 1; ++dr) {
-    const int r2 = row + dr;
-    if (r2 < 0 || r2 >= nz) continue;
-    const float sg = pc.sigma0 * sqrtf(ms * ms_row[r2]);
-    for (int dc = -1; dc <= 1; ++dc) {
-      const int c2 = col + dc;
-      if ((dr == 0 && dc == 0) || c2 < 0 || c2 >= nx) continue;
+  if (lane < 8) {
+    const int q = lane < 4 ? lane : lane + 1;  // the 3 x 3 neighbourhood without its centre
+    const int dr = q / 3 - 1, dc = q % 3 - 1;
+    const int r2 = row + dr, c2 = col + dc;
+    if (r2 >= 0 && r2 < nz && c2 >= 0 && c2 < nx) {
+      const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
+      const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
+      const float sg = pc.sigma0 * sqrtf(ms_row[row] * ms_row[r2]);
       const float bw = (dr == 0 || dc == 0) ? b_edge : b_diag;
       const float d = xs - x[r2 * nx + c2];
       float hc, rho;
       qggmrf(d, sg, pc, &hc, &rho);
       const float B = bw * hc;
-      slope = fmaf(2.0f * B, d, slope);
-      curv = fmaf(2.0f, B, curv);
+      slope = 2.0f * B * d;
+      curv = 2.0f * B;
     }
   }
+  for (int off = 4; off > 0; off >>= 1) {
+    slope += __shfl_down(slope, off, 64);
+    curv += __shfl_down(curv, off, 64);
+  }
+  if (lane != 0) return;
+  const float theta1 = -float(acc) * pc.inv_sigma2;
+  const float theta2 = den[v] * pc.inv_sigma2;
   const float h = theta2 + curv;
   const float step = h > 0.0f ? -(theta1 + slope) / h : 0.0f;
   x[v] = xs + step;
   delta[i] = step;
-  atomicMax(dmax, __float_as_uint(fabsf(step)));  // non-negative floats order as their bits
 }
 
 // e_t -= sum_i delta_i A_{t, v_i} (ABS: the operator of |W| and |b|), summed
-// in 64-bit fixed point in LDS.  Every term is at most max|delta| = *dmax
+// in 64-bit fixed point in LDS.  Every term is at most dmax = max_i |delta_i|
 // (weights, template and interpolation are <= 1) and at most `size` terms
 // meet at a sample, so the scale 2^kx keeps every sum below 2^62.
 template <bool ABS>
@@ -484,16 +506,22 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_scatter(float* __restrict__
                                                              const Leg* __restrict__ legs, int n_off,
                                                              const int* __restrict__ base, int P, int K,
                                                              const float* __restrict__ tau, IcdGroup gp, int Sr,
-                                                             int Sc, const float* __restrict__ delta,
-                                                             const unsigned* __restrict__ dmax_bits) {
-  extern __shared__ unsigned long long acc[];  // [M], then the bank as floats
+                                                             int Sc, const float* __restrict__ delta) {
+  extern __shared__ unsigned long long acc[];  // [M], then the template as floats
   float* sb = reinterpret_cast<float*>(acc + M);
+  __shared__ float wmax[kIcdThreads / 64];
   const int t = blockIdx.x;
-  const float dmax = __uint_as_float(*dmax_bits);
-  if (!(dmax > 0.0f)) return;  // uniform: nothing moved
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  float mx = 0.0f;
+  for (int i = threadIdx.x; i < gp.size; i += blockDim.x) mx = fmaxf(mx, fabsf(delta[i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) wmax[threadIdx.x >> 6] = mx;
   for (int m = threadIdx.x; m < M; m += blockDim.x) acc[m] = 0ull;
   for (int n = threadIdx.x; n < QLh + 2; n += blockDim.x) sb[n] = ABS ? fabsf(bank[n]) : bank[n];
   __syncthreads();
+  float dmax = 0.0f;
+  for (int k = 0; k < nw; ++k) dmax = fmaxf(dmax, wmax[k]);
+  if (!(dmax > 0.0f)) return;  // uniform: nothing moved
   int lg = 0;
   while ((1 << lg) < gp.size) ++lg;
   const int kx = 61 - lg - ilogbf(dmax);
@@ -503,16 +531,14 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_scatter(float* __restrict__
     if (dl == 0.0f) continue;
     int row, col;
     icd_member(gp, Sr, Sc, i, &row, &col);
-    int64_t D;
-    float W;
-    icd_pair(legs, n_off, base, P, K, tau, t, row, col, &D, &W);
-    if (ABS) W = fabsf(W);
-    const IcdWindow w = icd_window(D, qs, Q, QLh, M);
-    const float s = dl * W;
-    for (int m = w.m_lo; m <= w.m_hi; ++m) {
-      const int k = int(long(m) * Q - w.J);
-      const float v = s * fmaf(w.phi, sb[k - 1] - sb[k], sb[k]);
-      atomicAdd(&acc[m], static_cast<unsigned long long>(__double2ll_rn(double(v) * scale)));
+    const IcdSpan w = icd_span<ABS>(sb, Q, qs, QLh, M, legs, n_off, base, P, K, tau, t, row, col);
+    const float s = dl * w.W;
+    unsigned long long* av = acc + w.lo;
+#pragma unroll 4
+    for (int d = 0; d < w.n; ++d) {
+      const float* b = w.bk + d * Q;
+      const float v = s * fmaf(w.phi, b[-1] - b[0], b[0]);
+      atomicAdd(&av[d], static_cast<unsigned long long>(__double2ll_rn(double(v) * scale)));
     }
   }
   __syncthreads();
@@ -528,12 +554,11 @@ __global__ void k_depth_rows(int nz, PriorConst pc, float* __restrict__ ms_row) 
   if (r < nz) ms_row[r] = depth_mod(r, nz, pc);
 }
 
-// delta[i] = -1 for every member and *dmax = 1: a scatter then adds the
-// group's columns (e -= -1 * column)
-__global__ void k_icd_unit(int n, float* __restrict__ delta, unsigned* __restrict__ dmax) {
+// delta[i] = -1 for every member: a scatter then adds the group's columns
+// (e -= -1 * column)
+__global__ void k_icd_unit(int n, float* __restrict__ delta) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) delta[i] = -1.0f;
-  if (i == 0) *dmax = __float_as_uint(1.0f);
 }
 
 IcdGroup icd_group(const umbir_geometry& G, int Sr, int Sc, int k) {
@@ -784,7 +809,6 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
   float* delta = cv.take<float>(size_t(gmax));
   double* ess = cv.take<double>(PK);
   double* pcost = cv.take<double>(nblk);
-  unsigned* dmax = cv.take<unsigned>(1);
   const PriorConst pc = prior_const(*G, *pr);
   const double inv_2s2 = 0.5 / (pr->sigma * pr->sigma);
   const int est = pr->estimate_direct ? 1 : 0;
@@ -792,24 +816,24 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
 
   const size_t lds_dots = (size_t(M) + QLh + 2) * sizeof(float);
   const size_t lds_scatter = size_t(M) * sizeof(unsigned long long) + (size_t(QLh) + 2) * sizeof(float);
-  auto dots = [&](bool abs_op, const IcdGroup& gp, const float* ev, unsigned* clear) {
+  auto dots = [&](bool abs_op, const IcdGroup& gp, const float* ev) {
     // spread a trace's members over a few blocks when there are few traces
     const int ych = std::max(1, std::min((gp.size + kIcdThreads - 1) / kIcdThreads, 512 / std::max(PK, 1)));
     const dim3 grid{unsigned(PK), unsigned(ych), 1u};
     if (abs_op)
       UMBIR_LAUNCH("icd_dots", k_icd_dots<true>, grid, dim3(kIcdThreads), lds_dots, s, ev, M, G->bank, Q, qs, QLh,
-                   G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, part, clear);
+                   G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, part);
     else
       UMBIR_LAUNCH("icd_dots", k_icd_dots<false>, grid, dim3(kIcdThreads), lds_dots, s, ev, M, G->bank, Q, qs, QLh,
-                   G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, part, clear);
+                   G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, part);
   };
   auto scatter = [&](bool abs_op, const IcdGroup& gp, float* ev) {
     if (abs_op)
       UMBIR_LAUNCH("icd_scatter", k_icd_scatter<true>, dim3(unsigned(PK)), dim3(kIcdThreads), lds_scatter, s, ev, M,
-                   G->bank, Q, qs, QLh, G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, delta, dmax);
+                   G->bank, Q, qs, QLh, G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, delta);
     else
       UMBIR_LAUNCH("icd_scatter", k_icd_scatter<false>, dim3(unsigned(PK)), dim3(kIcdThreads), lds_scatter, s, ev,
-                   M, G->bank, Q, qs, QLh, G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, delta, dmax);
+                   M, G->bank, Q, qs, QLh, G->legs, G->n_off, G->base, G->P, G->K, G->tau, gp, Sr, Sc, delta);
   };
   const dim3 sblk(256);
   auto sgrid = [](const IcdGroup& gp) { return dim3(unsigned((gp.size + 3) / 4)); };
@@ -821,12 +845,11 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
     const IcdGroup gp = icd_group(*G, Sr, Sc, k);
     if (gp.size == 0) continue;
     if ((st = launch_fill(etmp, size_t(PK) * M, 0.0f, s))) return st;
-    UMBIR_LAUNCH("icd_unit", k_icd_unit, dim3(unsigned((gp.size + 255) / 256)), dim3(256), 0, s, gp.size, delta,
-                 dmax);
+    UMBIR_LAUNCH("icd_unit", k_icd_unit, dim3(unsigned((gp.size + 255) / 256)), dim3(256), 0, s, gp.size, delta);
     scatter(true, gp, etmp);
-    dots(true, gp, etmp, nullptr);
+    dots(true, gp, etmp);
     UMBIR_LAUNCH("icd_step", k_icd_step<true>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc,
-                 ms_row, den, nullptr, nullptr, nullptr);
+                 ms_row, den, nullptr, nullptr);
   }
   if ((st = check_hip(hipGetLastError(), "icd curvature"))) return st;
   // e = y - A x - D g
@@ -844,9 +867,9 @@ int umbir_reconstruct_icd(const umbir_geometry* G, const umbir_prior* pr, const 
     for (int k = 0; k < n_groups; ++k) {
       const IcdGroup gp = icd_group(*G, Sr, Sc, k);
       if (gp.size == 0) continue;
-      dots(false, gp, e, dmax);
+      dots(false, gp, e);
       UMBIR_LAUNCH("icd_step", k_icd_step<false>, sgrid(gp), sblk, 0, s, part, PK, gp, Sr, Sc, G->nx, G->nz, pc,
-                   ms_row, den, x_io, delta, dmax);
+                   ms_row, den, x_io, delta);
       scatter(false, gp, e);
     }
     if ((st = check_hip(hipGetLastError(), "icd sweep"))) return st;
