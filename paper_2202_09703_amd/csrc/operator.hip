@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   constexpr int Q = 32 * QT;
   constexpr int ROWS = 4 * NT * 32;  // n per row block
   constexpr int KB = 4;              // k per lane per step
-  extern __shared__ float sm[];
+  extern __shared__ __align__(16) float sm[];
   const int H = corr_half(Lh);
   const int SL = corr_seg_len(ROWS, H);
   float* taps0 = sm;                                   // taps rows [0, H)
@@ -744,11 +744,24 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   const int ij = blockIdx.x;
   const float* r = rt + size_t(ij) * M;
   float* c = fine + size_t(ij) * tstride;  // trace ij's output (tstride = M Q, or more between templates' grids)
-  for (int i = threadIdx.x; i < 2 * H * Q; i += blockDim.x) {
-    const int k = i / Q;
-    const float v = k < Lh ? hq[i] : 0.0f;
-    if (k < H) taps0[i] = v;
-    else taps1[i - H * Q] = v;
+  {
+    // tap rows [0, 2 H), zero from Lh on, with 16-byte loads, several in
+    // flight per thread; a slot past the end writes into the gap between the
+    // halves (no branch, so the loads stay ahead of every store)
+    const int n4 = 2 * H * Q / 4, h4 = H * Q / 4, l4 = Lh * Q / 4;
+    const float4* g4 = reinterpret_cast<const float4*>(hq);
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < n4; i0 += U * blockDim.x) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = g4[min(i0 + u * int(blockDim.x), l4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * blockDim.x;
+        float* dst = i >= n4 ? taps0 + H * Q : (i < h4 ? taps0 + 4 * i : taps1 + 4 * (i - h4));
+        *reinterpret_cast<float4*>(dst) = i < l4 ? v[u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    }
   }
   // the block's row blocks, in order; each thread carries its share of the
   // next segment in registers while the current one multiplies
@@ -849,7 +862,6 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
 // blocks of one trace tile, resident together on one XCD, then read the same
 // rows at about the same time, and the L2 serves the repeats that a plain
 // order leaves to memory.  Rows outside [0, M) read as zero.
-constexpr int kConvTapPad = 32;  // zero tap rows on each side in k_conv_mfma
 
 struct ChunkOrder {
   int v_lo, P, rot, CN;
@@ -874,9 +886,11 @@ struct ChunkOrder {
 // values are then 32 consecutive taps of one row (read as 16-byte LDS words)
 // and its B values 32 consecutive fine-grid samples of one trace, loaded from
 // memory straight into registers one chunk ahead, with no staging.  Taps are
-// kept with zero rows on both sides of the window (no masking) and a row
-// stride of Q + 4 words, which spreads 16 lanes' 16-byte reads over all
-// banks.  Epilogue as in k_conv.
+// kept with one zero row after the window, which a lane reads for any row
+// outside it, and a row stride of Q + 4 words, which spreads 16 lanes'
+// 16-byte reads over all banks.  With one accumulation chain the kernel fits
+// 128 registers and 35 KB of LDS at Q = 32, so four blocks share a CU.
+// Epilogue as in k_conv.
 template <int Q>
 __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
@@ -887,15 +901,37 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   constexpr int CK = 64;        // (n, t) positions per chunk
   constexpr int CN = CK / Q;    // rows n per chunk
   constexpr int TS = Q + 4;     // tap row stride
-  constexpr int KP = kConvTapPad;
   extern __shared__ __align__(16) float sm[];
-  float* taps = sm;  // [KP + Lh + KP][TS], tap rows -KP .. Lh + KP - 1
+  float* taps = sm;  // [Lh + 1][TS]: tap rows 0 .. Lh - 1, then a zero row
   const int tr0 = blockIdx.x * 32;
   const int m0 = blockIdx.y * 32;
   const long MQ = long(M) * Q;
-  for (int i = threadIdx.x; i < (Lh + 2 * KP) * TS; i += blockDim.x) {
-    const int k = i / TS - KP, t = i % TS;
-    taps[i] = (k >= 0 && k < Lh && t < Q) ? hq[k * Q + t] : 0.0f;
+  {
+    // zero rows and columns first, then the taps with 16-byte loads, several
+    // in flight per thread (hq rows are Q floats, 16-byte aligned)
+    constexpr int R4 = TS / 4, Q4 = Q / 4;
+    float4* t4 = reinterpret_cast<float4*>(taps);
+    for (int i = threadIdx.x; i < (Lh + 1) * R4; i += blockDim.x) {
+      const int r = i / R4, c = i - r * R4;
+      if (r >= Lh || c >= Q4) t4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    const float4* h4 = reinterpret_cast<const float4*>(hq);
+    const int n4 = Lh * Q4;
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < n4; i0 += U * blockDim.x) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = h4[min(i0 + u * int(blockDim.x), n4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // past the end: a zero into the zero row (no branch, so the loads
+        // above stay ahead of every store)
+        const int i = i0 + u * blockDim.x;
+        const bool in = i < n4;
+        const int k = in ? i / Q4 : Lh, c = in ? i - k * Q4 : 0;
+        t4[k * R4 + c] = in ? v[u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
@@ -907,9 +943,9 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   const bool reach = __syncthreads_or(threadIdx.x < 32 && tr0 + int(threadIdx.x) < PK &&
                                       bin_reaches(bs, tr0 + threadIdx.x, long(m0 - Lh) * Q, long(m0 + 31) * Q));
   const int rounds = reach ? (co.P + 3) / 4 : 0;
-  floatx16 acc[2];  // two independent accumulation chains
+  floatx16 acc;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.0f;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
   // B: trace tr0 + li (traces past the last read the last one: they only feed
   // output columns that are never written).  Loads are unconditional, from a
   // row clamped into [0, M); a row outside [0, M), or a step past the window,
@@ -936,16 +972,17 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   auto multiply = [&](const float4 (&b)[8]) {
     const int nc = next_row(jm, sm_);
     const int n = nc + ro;
-    // tap row k = m - 1 - n, within [-KP, Lh + KP) for every chunk of the window
-    const int k = (n >= 0 && n < M) ? m - 1 - n : -KP;
-    const float4* arow = reinterpret_cast<const float4*>(taps + (k + KP) * TS + t0);
+    // tap row k = m - 1 - n; the zero row for rows outside [0, M) or the window
+    int k = m - 1 - n;
+    if (n < 0 || n >= M || unsigned(k) >= unsigned(Lh)) k = Lh;
+    const float4* arow = reinterpret_cast<const float4*>(taps + k * TS + t0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const float4 av = arow[u];
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b[u].x, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b[u].y, acc[1], 0, 0, 0);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b[u].z, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc[1], 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b[u].x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b[u].y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b[u].z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc, 0, 0, 0);
     }
   };
   __syncthreads();  // taps staged
@@ -959,14 +996,12 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
     multiply(b1);
   }
   __syncthreads();  // every wave is done with the taps: reuse them for the reduction
-#pragma unroll
-  for (int i = 0; i < 16; ++i) acc[0][i] += acc[1][i];
   // sum the four partial tiles: red[wave][row][col]
   float* red = sm;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
-    red[(wave * 32 + row) * 33 + li] = acc[0][i];
+    red[(wave * 32 + row) * 33 + li] = acc[i];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
@@ -1206,7 +1241,7 @@ template <int Q>
 void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
                       float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
   // padded taps, reused for the four partial tiles at the end
-  const size_t lds = std::max<size_t>(size_t(G.Lh + 2 * kConvTapPad) * (Q + 4), 4 * 32 * 33) * sizeof(float);
+  const size_t lds = std::max<size_t>(size_t(G.Lh + 1) * (Q + 4), 4 * 32 * 33) * sizeof(float);
   dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
   UMBIR_LAUNCH("conv", k_conv_mfma<Q>, grid, dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
                sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
