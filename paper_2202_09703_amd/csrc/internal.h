@@ -85,6 +85,22 @@ struct Carve {
   }
 };
 
+// Block-wide copy into LDS: store(i, load(i)) for i < n, with eight loads in
+// flight per thread.  The stores are branch-free (a slot past the end repeats
+// element n - 1, with its own value), so the compiler keeps every load of a
+// batch ahead of its stores instead of waiting on each in turn.
+template <typename T, typename Load, typename StoreF>
+__device__ __forceinline__ void stage_block(int n, Load load, StoreF store) {
+  constexpr int U = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * int(blockDim.x)) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load(min(i0 + u * int(blockDim.x), n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u) store(min(i0 + u * int(blockDim.x), n - 1), v[u]);
+  }
+}
+
 // Owns a workspace: the caller's buffer, or one allocated in stream order.
 struct Workspace {
   void* ptr = nullptr;

@@ -594,7 +594,9 @@ __global__ void k_reduce_groups(const float* __restrict__ partial, int groups, i
 // Stage the polyphase taps [L_h][Q] into LDS, zero-padded to LhPad rows.
 __device__ __forceinline__ void stage_taps(float* sh, const float* __restrict__ hq, int Lh, int LhPad,
                                            int Q) {
-  for (int i = threadIdx.x; i < LhPad * Q; i += blockDim.x) sh[i] = i < Lh * Q ? hq[i] : 0.0f;
+  const int n = Lh * Q;
+  stage_block<float>(LhPad * Q, [&](int i) { return hq[min(i, n - 1)]; },
+                     [&](int i, float v) { sh[i] = i < n ? v : 0.0f; });
   __syncthreads();
 }
 
@@ -1042,10 +1044,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma16(const typename Store<ST>::T
   const int tr0 = blockIdx.x * 32;
   const int m0 = blockIdx.y * 32;
   const long MQ = long(M) * Q;
-  for (int i = threadIdx.x; i < Lh * TS; i += blockDim.x) {
-    const int k = i / TS, t = i - k * TS;
-    taps[i] = Store<ST>::put(t < Q ? hq[k * Q + t] : 0.0f);
-  }
+  stage_block<float>(Lh * TS, [&](int i) { const int k = i / TS, t = i - k * TS; return hq[k * Q + min(t, Q - 1)]; },
+                     [&](int i, float v) { taps[i] = Store<ST>::put(i % TS < Q ? v : 0.0f); });
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
   T* st = stage + wave * 32 * SB;
@@ -1150,10 +1150,8 @@ __global__ __launch_bounds__(256) void k_corr_mfma16(const typename Store<ST>::T
   const int ij = blockIdx.x;
   const int n_blk = blockIdx.y * ROWS;
   const T* r = rt + size_t(ij) * M;
-  for (int i = threadIdx.x; i < Q * KS; i += blockDim.x) {
-    const int t = i / KS, k = i - t * KS;
-    tapsT[i] = Store<ST>::put(k < Lh ? hq[k * Q + t] : 0.0f);
-  }
+  stage_block<float>(Q * KS, [&](int i) { const int t = i / KS, k = i - t * KS; return hq[min(k, Lh - 1) * Q + t]; },
+                     [&](int i, float v) { tapsT[i] = Store<ST>::put(i % KS < Lh ? v : 0.0f); });
   for (int j = threadIdx.x; j < ROWS + L8; j += blockDim.x) {
     T v[4];
 #pragma unroll

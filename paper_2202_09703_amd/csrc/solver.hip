@@ -424,8 +424,9 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_dots(const float* __restric
   float* se = sm;      // [M]
   float* sb = sm + M;  // [QLh + 2]
   const int t = blockIdx.x;
-  for (int m = threadIdx.x; m < M; m += blockDim.x) se[m] = e[size_t(t) * M + m];
-  for (int n = threadIdx.x; n < QLh + 2; n += blockDim.x) sb[n] = ABS ? fabsf(bank[n]) : bank[n];
+  const float* et = e + size_t(t) * M;
+  stage_block<float>(M, [&](int m) { return et[m]; }, [&](int m, float v) { se[m] = v; });
+  stage_block<float>(QLh + 2, [&](int n) { return bank[n]; }, [&](int n, float v) { sb[n] = ABS ? fabsf(v) : v; });
   __syncthreads();
   for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < gp.size; i += gridDim.y * blockDim.x) {
     int row, col;
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(kIcdThreads) void k_icd_scatter(float* __restrict__
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   if (lane == 0) wmax[threadIdx.x >> 6] = mx;
   for (int m = threadIdx.x; m < M; m += blockDim.x) acc[m] = 0ull;
-  for (int n = threadIdx.x; n < QLh + 2; n += blockDim.x) sb[n] = ABS ? fabsf(bank[n]) : bank[n];
+  stage_block<float>(QLh + 2, [&](int n) { return bank[n]; }, [&](int n, float v) { sb[n] = ABS ? fabsf(v) : v; });
   __syncthreads();
   float dmax = 0.0f;
   for (int k = 0; k < nw; ++k) dmax = fmaxf(dmax, wmax[k]);
