@@ -987,6 +987,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc, 0, 0, 0);
     }
   };
+  // the epilogue's inputs for this thread's four outputs, fetched now so that
+  // they arrive while the window multiplies
+  float pre_base[4], pre_db[4], pre_g[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * 256;
+    const int mm = min(m0 + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
+    const size_t idx = size_t(tr) * M + mm;
+    pre_base[q] = base ? base[idx] : 0.0f;
+    pre_db[q] = g ? dbasis[idx] : 0.0f;
+    pre_g[q] = g ? g[tr] : 0.0f;
+  }
   __syncthreads();  // taps staged
   // two register sets in turn: the next chunk is in flight while one multiplies
   float4 b0[8], b1[8];
@@ -1006,17 +1018,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
     red[(wave * 32 + row) * 33 + li] = acc[i];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + q * 256;
     const int col = e >> 5, row = e & 31;  // consecutive threads: consecutive m of one trace
     const int mm = m0 + row, tr = tr0 + col;
     if (mm < M && tr < PK) {
       const float v = red[(0 * 32 + row) * 33 + col] + red[(1 * 32 + row) * 33 + col] +
                       red[(2 * 32 + row) * 33 + col] + red[(3 * 32 + row) * 33 + col];
-      const size_t idx = size_t(tr) * M + mm;
       float val = sign * v;
-      if (base) val += base[idx];
-      if (g) val -= g[tr] * dbasis[idx];
-      out[idx] = val;
+      if (base) val += pre_base[q];
+      if (g) val -= pre_g[q] * pre_db[q];
+      out[size_t(tr) * M + mm] = val;
     }
   }
 }
