@@ -37,7 +37,10 @@ TINY = [dict(n_layers=1), dict(n_layers=2), dict(n_layers=3, beta=3), dict(n_lay
         dict(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=16),
         dict(n_layers=2, nx=1, nz=1, n_scans=1, n_rx=1),
         dict(n_layers=3, oversample=1, beta=0),
-        dict(n_layers=3, n_samples=40)]  # record shorter than many echoes: truncation
+        dict(n_layers=3, n_samples=40),  # record shorter than many echoes: truncation
+        # matrix-core convolution and correlation: ragged record and trace count, short window
+        dict(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=32),
+        dict(n_layers=2, nx=9, nz=11, n_scans=2, n_rx=5, n_samples=130, oversample=64)]
 
 
 def _cards():
