@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32 = 157.3e12   # MI355X published fp32 FLOP/s (vector and dense matrix)
 PEAK_HBM = 8.0e12      # MI355X published HBM3E bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_256x256.json")
+LAUNCH_SAMPLE = 5      # the timed steps bracket every 5th launch of the dominant kernel with events
 
 
 def parse():
@@ -230,9 +231,11 @@ def main():
     prof_all = umbir.profile_collect()
     dname = max(prof_all.items(), key=lambda kv: kv[1][1])[0]
 
-    # the timed steps bracket only the dominant kernel's launches (its
-    # duration measured live; fewer events perturb the step less)
+    # the timed steps bracket only the dominant kernel, and only a sample of
+    # its launches (every LAUNCH_SAMPLE-th): its duration measured live, with
+    # few event records in the work timed
     umbir.profile_select([dname])
+    umbir.profile_stride(LAUNCH_SAMPLE)
     umbir.profile_enable(True)
     umbir.profile_collect()
     lat = []
@@ -248,6 +251,7 @@ def main():
     elapsed = time.perf_counter() - t_start
     umbir.profile_enable(False)
     prof = umbir.profile_collect()
+    umbir.profile_stride(1)
     umbir.profile_select(None)
     for gm in keep:
         gm.free()
@@ -284,6 +288,10 @@ def main():
     tg = gm.trace_groups
     kernels = {k: roofline(k, prof_all, 1, card, gm.n_off, tg) for k in ("splat", "conv", "corr", "gather")}
     roof = roofline(dname, prof, args.steps, card, gm.n_off, tg)
+    if roof is not None:  # launches per step from the fully profiled step; the timed ones are a sample
+        roof["launches_per_step"] = prof_all[dname][0]
+        roof["timed_launches"] = prof[dname][0]
+        roof["timed_every"] = LAUNCH_SAMPLE
     # measured HBM bytes per launch, valid only for the exact sources they were taken on
     measured = {}
     try:

@@ -358,6 +358,12 @@ void umbir_profile_enable(int on);
  * names umbir_profile_collect reports); NULL or "" times every kernel.  The
  * fewer launches are bracketed, the less the events perturb the work timed. */
 void umbir_profile_select(const char* names);
+/* While a selection is set, times only every `every`-th launch of each
+ * selected kernel, counted from this call or from the last
+ * umbir_profile_select (every <= 1: every launch).  Launches of identical
+ * work are then measured on a sample, with fewer event records between the
+ * launches of the work being timed. */
+void umbir_profile_stride(int every);
 int umbir_profile_collect(umbir_kernel_time* out, int max_entries, int* n_out);
 
 const char* umbir_strerror(int status);

@@ -26,6 +26,8 @@ std::atomic<bool> g_on{false};
 std::atomic<bool> g_filtered{false};
 std::mutex g_mu;
 std::vector<std::string> g_select;  // kernel names timed while g_filtered
+std::vector<long long> g_seen;      // launches of each selected kernel so far
+int g_every = 1;                    // while g_filtered: time every g_every-th launch
 std::vector<Pending> g_pending;
 std::map<std::string, Totals> g_totals;
 
@@ -35,8 +37,8 @@ bool prof_on(const char* name) {
   if (!g_on.load(std::memory_order_relaxed)) return false;
   if (!g_filtered.load(std::memory_order_relaxed)) return true;
   std::lock_guard<std::mutex> lk(g_mu);
-  for (const std::string& n : g_select)
-    if (n == name) return true;
+  for (size_t k = 0; k < g_select.size(); ++k)
+    if (g_select[k] == name) return g_seen[k]++ % g_every == 0;
   return false;
 }
 
@@ -87,7 +89,14 @@ void umbir_profile_select(const char* names) {
       }
     }
   }
+  g_seen.assign(g_select.size(), 0);
   g_filtered.store(!g_select.empty());
+}
+
+void umbir_profile_stride(int every) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_every = every > 1 ? every : 1;
+  g_seen.assign(g_select.size(), 0);
 }
 
 int umbir_profile_collect(umbir_kernel_time* out, int max_entries, int* n_out) {

@@ -118,6 +118,7 @@ _SIGS = {
     "umbir_batch_free": (None, [_vp]),
     "umbir_profile_enable": (None, [_i]),
     "umbir_profile_select": (None, [C.c_char_p]),
+    "umbir_profile_stride": (None, [_i]),
     "umbir_profile_collect": (_i, [C.POINTER(_KernelTime), _i, C.POINTER(_i)]),
     "umbir_strerror": (C.c_char_p, [_i]),
     "umbir_last_error": (C.c_char_p, []),
@@ -510,6 +511,11 @@ def profile_enable(on: bool = True):
 def profile_select(names=None):
     """Time only the kernels named (an iterable of names, or None for all)."""
     _lib.umbir_profile_select(",".join(names).encode() if names else None)
+
+
+def profile_stride(every: int = 1):
+    """With a selection set, time only every `every`-th launch of each selected kernel."""
+    _lib.umbir_profile_stride(int(every))
 
 
 def profile_collect() -> dict:
