@@ -43,6 +43,10 @@ constexpr int kMaskShift = 10;
 
 __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >> 1) + (o & 1) * half; }
 
+// Blocks of the forward's image prescale: each leaves its max|tau x| for the
+// splat, which takes the largest (no atomic, nothing to clear first).
+constexpr int kPrescaleBlocks = 128;
+
 // Planar layer stack passed to kernels by value.  top/bottom are depths of
 // each layer's faces; the last bottom is +inf.
 struct Layers {
@@ -175,8 +179,10 @@ struct umbir_geometry {
                         : fine_grid_bytes();
   }
   // the fine-grid workspace: the grid(s), then the forward's prescaled image
-  // and one scalar
-  size_t fine_bytes() const { return grids_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 16; }
+  // and the prescale blocks' maxima
+  size_t fine_bytes() const {
+    return grids_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 4 * umbir::kPrescaleBlocks;
+  }
   size_t trace_bytes() const { return size_t(traces()) * M * elem(); }
   size_t taps_per_bin() const { return size_t(Q) * Lh; }
 };

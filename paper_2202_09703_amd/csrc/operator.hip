@@ -56,8 +56,9 @@ struct Segments {
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // The splat's input image with the row transmittance folded in, xt = tau x
-// (x == NULL means x = 1), and the largest |xt| as float bits (non-negative
-// floats order like their bits) for the fixed-point scale of the splat.
+// (x == NULL means x = 1), and per block the largest |xt| as float bits
+// (non-negative floats order like their bits) for the fixed-point scale of
+// the splat: out[blockIdx.x], gridDim.x <= kPrescaleBlocks.
 __global__ void k_prescale(const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
                            float* __restrict__ xt, unsigned* __restrict__ out) {
   unsigned m = 0;
@@ -72,7 +73,7 @@ __global__ void k_prescale(const float* __restrict__ x, const float* __restrict_
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < int(blockDim.x >> 6); ++w) m = max(m, wmax[w]);
-    atomicMax(out, m);  // one atomic per block
+    out[blockIdx.x] = m;
   }
 }
 
@@ -210,7 +211,7 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const int* __restrict__ base,
-    int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax,
+    int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
   const int NT = MT ? glast + 1 : 1;                                 // tiles
@@ -219,8 +220,6 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   int2* pn = reinterpret_cast<int2*>(smem + NT * TS);                // [seg.n][nx] {next row, its position}
   int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of row 0's records
   __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
-  const int kx = splat_exponent(*xmax, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
-  const double scale = ldexp(1.0, kx);
   const int ij = blockIdx.y;
   const int J_begin = blockIdx.x * chunk_bins;
   const int J_end = min(J_begin + chunk_bins, MQ);
@@ -235,6 +234,13 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     return;
   }
 
+  // the largest |tau x| over the prescale blocks' maxima (n_xmax <= blockDim.x)
+  __shared__ unsigned wave_max[kSplatWaves];
+  {
+    unsigned m = int(threadIdx.x) < n_xmax ? xmax[threadIdx.x] : 0u;
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
+  }
   if (threadIdx.x < kMaxLayers) {
     lay_lo[threadIdx.x] = kNoRow;
     lay_hi[threadIdx.x] = -kNoRow;
@@ -243,6 +249,10 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     colofs[c] = make_int2(leg_slot(abs(btx + 2 * c), half) * int(sizeof(Leg)),
                           leg_slot(abs(brx + 2 * c), half) * int(sizeof(Leg)));
   __syncthreads();
+  unsigned maxbits = 0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) maxbits = max(maxbits, wave_max[w]);
+  const int kx = splat_exponent(maxbits, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
+  const double scale = ldexp(1.0, kx);
   // first row of each (column, layer) whose position is >= J_begin - 1
   for (int i = threadIdx.x; i < seg.n * nx; i += blockDim.x) {
     const int sg = i / nx, c = i - sg * nx;
@@ -1363,6 +1373,11 @@ int splat_mt_tile(const umbir_geometry& G) {
   return t >= 64 ? int(t) : 0;
 }
 
+// blocks of k_prescale, one per 1024 voxels up to kPrescaleBlocks
+int prescale_blocks(const umbir_geometry& G) {
+  return int(std::min<size_t>(kPrescaleBlocks, (size_t(G.voxels()) + 1023) / 1024));
+}
+
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs, int MQ, const Segments& seg,
                     const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
@@ -1371,7 +1386,8 @@ void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs,
   const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
   const size_t lds = size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
-               G.n_off, G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, gbin, G.n_gamma - 1,
+               G.n_off, G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, prescale_blocks(G), gbin,
+               G.n_gamma - 1,
                bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine));
 }
 
@@ -1457,7 +1473,7 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   // after the fine grid(s): the prescaled image tau x, then one 32-bit
   // scalar, the largest |tau x|
   float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.grids_bytes());
-  unsigned* xmax = reinterpret_cast<unsigned*>(static_cast<char*>(fine) + G.fine_bytes() - 16);
+  unsigned* xmax = reinterpret_cast<unsigned*>(static_cast<char*>(fine) + G.fine_bytes() - 4 * kPrescaleBlocks);
   const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
   Segments seg;
@@ -1466,9 +1482,8 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     seg.lo[k] = G.seg_lo[k];
     seg.hi[k] = G.seg_hi[k];
   }
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(xmax), size_t(1), 0.0f);
-  UMBIR_LAUNCH("prescale", k_prescale, dim3(std::min(128, (G.voxels() + 1023) / 1024)), dim3(1024), 0, s, x,
-               G.tau, G.nx, G.voxels(), xt, xmax);
+  UMBIR_LAUNCH("prescale", k_prescale, dim3(prescale_blocks(G)), dim3(1024), 0, s, x, G.tau, G.nx, G.voxels(), xt,
+               xmax);
   dim3 grid(G.chunks, G.traces());
   if (G.multi_grid() && splat_mt_tile(G) > 0) {
     // attenuation with every template's grid resident: one splat walk fills
