@@ -38,6 +38,7 @@ def _pairs(geom, x, y, work, n):
 def test_every_kernel_counted(setup):
     geom, x, y, work = setup
     umbir.profile_select(None)
+    umbir.profile_stride(1)
     umbir.profile_enable(True)
     umbir.profile_collect()
     _pairs(geom, x, y, work, 3)
