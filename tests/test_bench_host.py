@@ -1,0 +1,90 @@
+"""Host logic of bench.py that needs no GPU: the refusal of several GPUs, the
+algorithmic work its rooflines divide by, the roofline record, and the HBM
+traffic file written from rocprofv3 counter CSVs (scaled by a plain copy)."""
+import csv
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from synth import card_c2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_work_of_the_workload(bench):
+    card = card_c2()
+    # 512 traces of 2048 samples, Q = 32, a 240-sample window: 2 M Q L_h flop per trace
+    flop, bound = bench.kernel_work("conv", card, 654, 8)
+    assert flop == 2.0 * 512 * 2048 * 32 * 240 == 16106127360.0 and bound == "mfma"
+    assert bench.kernel_work("corr", card, 654, 8) == (flop, "mfma")
+    # splat: leg table (256 rows x 654 records x 16 B), image, transmittances, fine grid
+    fine = 512 * 2048 * 32 * 4
+    assert bench.kernel_work("splat", card, 654, 8) == (float(256 * 654 * 16 + 4 * 65536 + 4 * 256 + fine), "hbm")
+    # gather: the same plus one partial image per trace group, minus the image
+    assert bench.kernel_work("gather", card, 654, 8) == (float(256 * 654 * 16 + 4 * 256 + fine + 4 * 65536 * 8),
+                                                         "hbm")
+    assert bench.kernel_work("k_unknown", card, 654, 8) == (None, None)
+
+
+def test_roofline_record(bench):
+    card = card_c2()
+    prof = {"conv": (20, 20 * 0.125)}  # 20 launches of 125 us
+    r = bench.roofline("conv", prof, 2, card, 654, 8)
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
+    assert r["avg_launch_us"] == pytest.approx(125.0)
+    assert r["achieved"] == pytest.approx(16106127360.0 / 125e-6 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+    assert r["launches_per_step"] == 10
+    assert bench.roofline("gather", prof, 2, card, 654, 8) is None
+
+
+def _counter_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, value in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": "X", "Counter_Value": value})
+
+
+def test_traffic_file(bench, tmp_path, monkeypatch):
+    # a 1 GiB copy that the counters see as 512 MiB read and 1 GiB written:
+    # fetch values scale by 2, write values by 1
+    _counter_csv(tmp_path / "cf.csv", [("__amd_rocclr_copyBuffer", 524288.0)] * 3)
+    _counter_csv(tmp_path / "cw.csv", [("__amd_rocclr_copyBuffer", 1048576.0)] * 3)
+    _counter_csv(tmp_path / "f.csv", [("void umbir::(anonymous namespace)::k_conv_mfma<32>(float const*)", 100.0),
+                                      ("void umbir::(anonymous namespace)::k_conv_mfma<32>(float const*)", 300.0),
+                                      ("void umbir::(anonymous namespace)::k_splat<false>(int)", 10.0),
+                                      ("void at::native::other_kernel", 7.0)])
+    _counter_csv(tmp_path / "w.csv", [("void umbir::(anonymous namespace)::k_conv_mfma<32>(float const*)", 4.0),
+                                      ("void umbir::(anonymous namespace)::k_splat<false>(int)", 128.0)])
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    bench.traffic_from(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"),
+                       str(tmp_path / "cw.csv"))
+    doc = json.load(open(out))
+    assert doc["source_sha256"] == bench.source_digest()
+    assert doc["calibration"]["fetch_scale"] == pytest.approx(2.0)
+    assert doc["calibration"]["write_scale"] == pytest.approx(1.0)
+    assert sorted(doc["kernels"]) == ["conv", "splat"]  # launch names; other kernels ignored
+    assert doc["kernels"]["conv"]["fetch_bytes"] == pytest.approx(200.0 * 2 * 1024)  # mean of 100 and 300 KiB
+    assert doc["kernels"]["conv"]["write_bytes"] == pytest.approx(4.0 * 1024)
+    assert doc["kernels"]["splat"]["write_bytes"] == pytest.approx(128.0 * 1024)
