@@ -735,8 +735,13 @@ __host__ __device__ inline int corr_half(int Lh) { return (Lh + 15) / 16 * 8; }
 // segment copies (the second one 32 banks from the first).
 __host__ __device__ inline int corr_seg_len(int rows, int H) { return rows + H; }
 __host__ __device__ inline int corr_seg_gap(int rows, int H) { return (rows + H + 63) / 64 * 64 + 32; }
+// one segment buffer (both halves), a multiple of 64 words so the two
+// buffers have the same bank layout
+__host__ __device__ inline int corr_seg_words(int rows, int H) {
+  return (corr_seg_gap(rows, H) + corr_seg_len(rows, H) + 63) / 64 * 64;
+}
 __host__ __device__ inline int corr_lds_words(int Q, int rows, int H) {
-  return 2 * H * Q + 32 + corr_seg_gap(rows, H) + corr_seg_len(rows, H);
+  return 2 * H * Q + 32 + 2 * corr_seg_words(rows, H);
 }
 
 template <int QT, int NT>
@@ -751,8 +756,10 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   const int SL = corr_seg_len(ROWS, H);
   float* taps0 = sm;                                   // taps rows [0, H)
   float* taps1 = sm + H * Q + 32;                      // taps rows [H, 2H)
-  float* seg0 = taps1 + H * Q;                         // seg0[x] = r[n_blk + 1 + x]
-  float* seg1 = seg0 + corr_seg_gap(ROWS, H);          // seg1[x] = r[n_blk + 1 + H + x]
+  // two segment buffers, used by alternate row blocks: in buffer b,
+  // seg0(b)[x] = r[n_blk + 1 + x] and seg1(b)[x] = r[n_blk + 1 + H + x]
+  float* const segs = taps1 + H * Q;
+  const int SW = corr_seg_words(ROWS, H), SG = corr_seg_gap(ROWS, H);
   const int ij = blockIdx.x;
   const float* r = rt + size_t(ij) * M;
   float* c = fine + size_t(ij) * tstride;  // trace ij's output (tstride = M Q, or more between templates' grids)
@@ -791,22 +798,24 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
       s1[u] = x < SL && m + H < M ? r[m + H] : 0.0f;
     }
   };
-  auto seg_store = [&]() {
+  auto seg_store = [&](int b) {
+    float* seg0 = segs + b * SW;
 #pragma unroll
     for (int u = 0; u < SEG_PER_THREAD; ++u) {
       const int x = threadIdx.x + u * 256;
       if (x < SL) {
         seg0[x] = s0[u];
-        seg1[x] = s1[u];
+        seg0[SG + x] = s1[u];
       }
     }
   };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
   const int row0 = wave * NT * 32;
-  const float* sa = (lk ? seg1 : seg0) + row0 + li;  // + a 32 + j
+  const float* sa0 = segs + (lk ? SG : 0) + row0 + li;  // + buffer SW + a 32 + j
   const float* sb = (lk ? taps1 : taps0) + li;       // + j Q + b 32
   if (rb0 < rb_end) seg_load(rb0);
+  int sbuf = 0;  // segment buffer: alternates over the row blocks processed
   for (int rb = rb0; rb < rb_end; ++rb) {
     // a template pass leaves the rows its template never reaches unwritten:
     // the gather of that template reads none of them (uniform over the block)
@@ -814,10 +823,13 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
       if (rb + 1 < rb_end) seg_load(rb + 1);
       continue;
     }
-    __syncthreads();  // the previous row block is done with the segment
-    seg_store();
+    // buffer sbuf was last read two processed row blocks ago, which every wave
+    // finished before the barrier of the previous one: one barrier per block
+    seg_store(sbuf);
     __syncthreads();
     if (rb + 1 < rb_end) seg_load(rb + 1);
+    const float* sa = sa0 + sbuf * SW;
+    sbuf ^= 1;
     floatx16 acc[NT][QT];
 #pragma unroll
     for (int a = 0; a < NT; ++a)
