@@ -106,11 +106,33 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
   const int ij = blockIdx.x;
   typename Store<ST>::T* et = e + size_t(ij) * M;
   const float* dt = d + size_t(ij) * M;
+  // traces of up to R blockDim samples stay in registers between the two
+  // passes, their loads all in flight together; the sums run in the same
+  // order either way
+  constexpr int R = 8;
+  const bool held = M <= R * int(blockDim.x);
+  float ec[R], dc[R];
   double ee = 0.0, de = 0.0;
-  for (int m = threadIdx.x; m < M; m += blockDim.x) {
-    const double ev = Store<ST>::get(et[m]);
-    ee += ev * ev;
-    de += double(dt[m]) * ev;
+  if (held) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int m = min(int(threadIdx.x) + u * int(blockDim.x), M - 1);
+      ec[u] = Store<ST>::get(et[m]);
+      dc[u] = dt[m];
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      if (int(threadIdx.x) + u * int(blockDim.x) < M) {
+        const double ev = ec[u];
+        ee += ev * ev;
+        de += double(dc[u]) * ev;
+      }
+  } else {
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+      const double ev = Store<ST>::get(et[m]);
+      ee += ev * ev;
+      de += double(dt[m]) * ev;
+    }
   }
   block_sum2(ee, de, sh);  // four waves: launched with 256 threads
   if (threadIdx.x == 0) {
@@ -124,8 +146,16 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
   }
   __syncthreads();
   const float dg = dg_sh;
-  if (dg != 0.0f)
+  if (dg == 0.0f) return;
+  if (held) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int m = int(threadIdx.x) + u * int(blockDim.x);
+      if (m < M) et[m] = Store<ST>::put(fmaf(-dg, dc[u], ec[u]));
+    }
+  } else {
     for (int m = threadIdx.x; m < M; m += blockDim.x) et[m] = Store<ST>::put(fmaf(-dg, dt[m], Store<ST>::get(et[m])));
+  }
 }
 
 // Prior cost of x (pairs counted once) into pcost[block]; with UPDATE also the
