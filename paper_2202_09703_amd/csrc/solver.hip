@@ -160,7 +160,8 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
 
 // Prior cost of x (pairs counted once) into pcost[block]; with UPDATE also the
 // surrogate step into xout, with A^T e the sum of the adjoint's `groups`
-// partial images in group order.  Four lanes per voxel, two of its eight
+// partial images (lane q of the voxel sums groups q, q + 4, ..., then a fixed
+// butterfly over the four lanes).  Four lanes per voxel, two of its eight
 // neighbours each (then summed across the four lanes); the depth modulation
 // of the rows the block touches is tabulated once per block.
 template <bool UPDATE>
@@ -183,6 +184,13 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict
   __syncthreads();
   double cost = 0.0;
   float slope = 0.0f, curv = 0.0f, xs = 0.0f;
+  // the adjoint's group partials of the voxel, every fourth group per lane,
+  // loaded first so that they arrive while the prior terms are computed
+  float u = 0.0f, dv = 0.0f;
+  if (UPDATE && v < N) {
+    for (int g = q; g < groups; g += 4) u += part[size_t(g) * N + v];
+    if (q == 0) dv = den[v];
+  }
   int row = 0, col = 0;
   if (v < N) {
     row = v / nx;
@@ -212,11 +220,13 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict
   slope += __shfl_xor(slope, 2, 64);
   curv += __shfl_xor(curv, 1, 64);
   curv += __shfl_xor(curv, 2, 64);
+  if (UPDATE) {
+    u += __shfl_xor(u, 1, 64);
+    u += __shfl_xor(u, 2, 64);
+  }
   if (UPDATE && v < N && q == 0) {
-    float u = 0.0f;
-    for (int g = 0; g < groups; ++g) u += part[size_t(g) * N + v];
     const float grad = fmaf(-u, pc.inv_sigma2, slope);
-    xout[v] = xs - grad / (den[v] + curv);
+    xout[v] = xs - grad / (dv + curv);
   }
   for (int off = 32; off > 0; off >>= 1) cost += __shfl_down(cost, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cost;
