@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32 = 157.3e12   # MI355X published fp32 FLOP/s (vector and dense matrix)
 PEAK_HBM = 8.0e12      # MI355X published HBM3E bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_256x256.json")
-LAUNCH_SAMPLE = 5      # the timed steps bracket every 5th launch of the dominant kernel with events
+LAUNCH_SAMPLE = 10     # the timed steps bracket every 10th launch of the dominant kernel with events
 
 
 def parse():
