@@ -238,10 +238,10 @@ def main():
     umbir.profile_stride(LAUNCH_SAMPLE)
     umbir.profile_enable(True)
     umbir.profile_collect()
-    # no synchronisation between steps: the host builds the next problem's
-    # geometry while the GPU still runs the previous reconstruction (as a
-    # service would); per-step latency is the GPU time between stream events
-    # at the step boundaries
+    # no synchronisation between steps: the host part of the next problem's
+    # geometry build runs while the GPU still runs the previous reconstruction
+    # (build_geometry then waits for the stream before it returns); per-step
+    # latency is the GPU time between stream events at the step boundaries
     keep = []
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
