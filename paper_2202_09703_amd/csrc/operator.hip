@@ -1000,6 +1000,10 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
     int k = m - 1 - n;
     if (n < 0 || n >= M || unsigned(k) >= unsigned(Lh)) k = Lh;
     const float4* arow = reinterpret_cast<const float4*>(taps + k * TS + t0);
+    // a wave issuing its chunk's MFMAs takes precedence over waves issuing
+    // loads and address arithmetic (measured: 2-4 % on this kernel; the
+    // correlation, whose operands come from LDS, is slower with it)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const float4 av = arow[u];
@@ -1008,6 +1012,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b[u].z, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc, 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
   };
   // the epilogue's inputs for this thread's four outputs, fetched now so that
   // they arrive while the window multiplies
