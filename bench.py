@@ -107,26 +107,43 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
-def kernel_work(name, card, n_off, trace_groups):
+def gather_launches(card, trace_groups, gather_batch_kb, elem=4):
+    """Launches of the gather per adjoint: each covers a batch of every trace
+    group's traces, gather_batch_kb KiB of fine grid per group (at least one
+    trace)."""
+    acq = card.acq
+    PK = card.array.n_scans * card.array.n_rx
+    tpg = -(-PK // trace_groups)
+    batch = max(1, min(tpg, (gather_batch_kb << 10) // (acq.n_samples * acq.oversample * elem)))
+    return -(-tpg // batch)
+
+
+def kernel_work(name, card, n_off, trace_groups, gather_batch_kb=4096, elem=4):
     """Algorithmic work of one launch and its bound.
 
     conv / corr: the polyphase convolution and correlation, 2 M Q L_h flop per
     trace (on the matrix cores when Q is 32 or 64).  splat / gather: compulsory
-    HBM bytes -- the leg table, the image and the fine-grid signal (written by
-    the splat, read by the gather, M Q floats per trace), plus the gather's
-    partial images."""
+    HBM bytes.  The splat reads the leg table, the image and the row
+    transmittances and writes the fine-grid signal (M Q elements per trace)
+    once.  The adjoint's fine grid is read once over its gather launches, each
+    of which also reads the leg table and the transmittances and writes the
+    trace groups' partial images (the first launch writes them, later ones
+    read and write them): the per-launch figure is that total over the
+    launches."""
     acq = card.acq
     P, K, M, Q = card.array.n_scans, card.array.n_rx, acq.n_samples, acq.oversample
     lh = int(round(acq.t_win * acq.fs))
     N, nz = card.n_voxels, card.grid.nz
     legs = nz * n_off * 16
-    fine = P * K * M * Q * 4
+    fine = P * K * M * Q * elem
     if name in ("conv", "corr"):
         return 2.0 * P * K * M * Q * lh, ("mfma" if Q in (32, 64) else "alu")
     if name == "splat":
         return float(legs + 4 * N + 4 * nz + fine), "hbm"
     if name == "gather":
-        return float(legs + 4 * nz + fine + 4 * N * trace_groups), "hbm"
+        n = gather_launches(card, trace_groups, gather_batch_kb, elem)
+        partial = 4 * N * trace_groups * (2 * n - 1)
+        return float(fine + n * (legs + 4 * nz) + partial) / n, "hbm"
     if name == "gstep":  # residual and g step: read e and the direct-arrival columns, write e
         return float(12 * P * K * M), "hbm"
     if name == "prior":  # image update: read x, A^T e and the curvature, write x
@@ -154,21 +171,180 @@ def copy_rate():
     return rate
 
 
-def roofline(name, prof, steps, card, n_off, trace_groups):
+PEAK_MFMA = {4: 157.3e12, 2: 2.5e15}  # dense matrix peak by element bytes: FP32, FP16/BF16
+
+
+def roofline(name, prof, steps, card, n_off, trace_groups, gather_batch_kb=4096, elem=4):
     if name not in prof:
         return None
     launches, ms = prof[name]
     avg_s = ms / launches / 1e3
-    amount, bound = kernel_work(name, card, n_off, trace_groups)
+    amount, bound = kernel_work(name, card, n_off, trace_groups, gather_batch_kb, elem)
     if bound is None:
         return None
     achieved = amount / avg_s
-    peak = PEAK_HBM if bound == "hbm" else PEAK_FP32
+    peak = PEAK_HBM if bound == "hbm" else (PEAK_MFMA[elem] if bound == "mfma" else PEAK_FP32)
     unit, div = ("GB/s", 1e9) if bound == "hbm" else ("TFLOP/s", 1e12)
     return {"bound": bound, "achieved": achieved / div, "peak": peak / div, "unit": unit,
             "frac": achieved / peak, "kernel": name, "avg_launch_us": avg_s * 1e6,
             "launches_per_step": launches / steps, "work_per_launch": amount,
             "work_unit": "byte" if bound == "hbm" else "flop"}
+
+
+def host_cpu():
+    """The host's core count and CPU model (for the CPU baseline record)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def operator_roofline(card, t_pair, triples):
+    """One A + A^T pair against the two ceilings of the operator's own
+    definition (Eq. (13)): 2 L_h flop per (trace, voxel) per operator on the
+    FP32 units, and the operator's algorithmic HBM bytes (image, traces, leg
+    table and template read or written once per operator)."""
+    acq = card.acq
+    lh = int(round(acq.t_win * acq.fs))
+    flop = 2.0 * 2 * lh * triples
+    return {"pair_ms": t_pair * 1e3, "flop_per_pair": flop, "achieved_TFLOPs": flop / t_pair / 1e12,
+            "frac_of_fp32": flop / t_pair / PEAK_FP32,
+            "note": "operator work as Eq. (13) defines it (2 L_h flop per triple per operator), "
+                    "whichever way the kernels factor it"}
+
+
+def time_pair(umbir, torch, gm, x, y, xo, work, reps=10):
+    """Seconds per A and per A^T (plain calls, events on the current stream)."""
+    for _ in range(2):
+        umbir.forward(gm, x, y, work=work)
+        umbir.adjoint(gm, y, xo, work=work)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        umbir.forward(gm, x, y, work=work)
+    ev[1].record()
+    for _ in range(reps):
+        umbir.adjoint(gm, y, xo, work=work)
+    ev[2].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / reps / 1e3, ev[1].elapsed_time(ev[2]) / reps / 1e3
+
+
+def precision_section(umbir, torch, dev, with_parity):
+    """The 512 x 512 four-layer workload (64 x 32 traces, 4096 samples) per
+    storage type: A and A^T rates, every sweep kernel's roofline from one
+    profiled pair, the dominant one named, and (with_parity) sampled traces and
+    voxels against the FP64 oracle on unrounded inputs."""
+    import dataclasses
+    from synth import card_c3, phantom, random_vector
+    base = card_c3()
+    P, K, M, N = base.array.n_scans, base.array.n_rx, base.acq.n_samples, base.n_voxels
+    triples = P * K * N
+    x_np = phantom(base)
+    r_np = random_vector((P, K, M), seed=61)
+    traces = [(5, 3), (40, 30)]
+    vox = np.random.default_rng(7).choice(N, 16, replace=False)
+    ref = None
+    if with_parity:
+        from oracle import operator as oo
+        ref = (oo.forward(base, x_np, traces=traces, workers=None), oo.adjoint_voxels(base, r_np, vox, workers=None))
+    out = {"workload": "512x512, 4 layers (water/steel/cement/rock), 64 scans x 32 rx, 4096 samples @ 20 MHz",
+           "triples_per_sweep": triples}
+    for name, st in (("f32", umbir.STORAGE_F32), ("f16", umbir.STORAGE_F16), ("bf16", umbir.STORAGE_BF16)):
+        card = dataclasses.replace(base, acq=dataclasses.replace(base.acq, storage=st))
+        gm = umbir.build_geometry(card)
+        work = gm.workspace(umbir.WORK_ADJOINT)
+        x = torch.tensor(x_np, dtype=torch.float32, device=dev)
+        y = torch.empty(gm.trace_shape, dtype=gm.trace_dtype, device=dev)
+        xo = torch.empty(gm.image_shape, dtype=torch.float32, device=dev)
+        t_a, t_at = time_pair(umbir, torch, gm, x, y, xo, work)
+        umbir.profile_select(None)
+        umbir.profile_enable(True)
+        umbir.profile_collect()
+        for _ in range(3):
+            umbir.forward(gm, x, y, work=work)
+            umbir.adjoint(gm, y, xo, work=work)
+        torch.cuda.synchronize()
+        umbir.profile_enable(False)
+        prof = umbir.profile_collect()
+        elem = 4 if st == umbir.STORAGE_F32 else 2
+        kb = gm.tuning()["gather_batch_kb"]
+        kern = {k: roofline(k, prof, 3, card, gm.n_off, gm.trace_groups, kb, elem)
+                for k in ("splat", "conv", "corr", "gather")}
+        dom = max(kern, key=lambda k: kern[k]["avg_launch_us"] * kern[k]["launches_per_step"] if kern[k] else -1)
+        res = {"A_evals_per_s": triples / t_a, "AT_evals_per_s": triples / t_at,
+               "A_plus_AT_evals_per_s": triples / (t_a + t_at), "A_ms": t_a * 1e3, "AT_ms": t_at * 1e3,
+               "dominant_kernel": dom, "roofline": kern[dom], "sweep_kernels": kern,
+               "operator_roofline": operator_roofline(card, t_a + t_at, triples)}
+        if ref is not None:
+            yf = umbir.forward(gm, x).float().cpu().numpy()
+            rt = torch.tensor(r_np, dtype=torch.float32, device=dev).to(gm.trace_dtype)
+            xa = umbir.adjoint(gm, rt).cpu().numpy().reshape(-1)
+            fe = max(float(np.linalg.norm(yf[i, j] - ref[0][i, j]) / np.linalg.norm(ref[0][i, j])) for i, j in traces)
+            ae = float(np.linalg.norm(xa[vox] - ref[1]) / np.linalg.norm(ref[1]))
+            res["parity_vs_oracle"] = {"forward_rel_l2_max_of_2_traces": fe, "adjoint_rel_l2_16_voxels": ae,
+                                       "unit_roundoff": {"f32": 2.0 ** -24, "f16": 2.0 ** -11,
+                                                         "bf16": 2.0 ** -8}[name]}
+        out[name] = res
+        gm.free()
+        del work
+    return out
+
+
+def batch_section(umbir, torch, dev):
+    """48 seeded uneven problems (128^2 to 384^2, 3-4 layers, 8-32 receivers,
+    1024-4096 samples, 20-50 iterations): one at a time against the batched
+    path, both autotuned; results bitwise equal."""
+    from paper_2202_09703_amd import batch
+    from synth import batch_cards
+    cards = batch_cards(48, 11)
+    quiet = lambda *a, **k: None  # noqa: E731
+    probs = batch.prepare(umbir, cards, device=dev, log=quiet)
+    cache = {}
+    batch.tune(umbir, probs, cache, log=quiet)
+    batch.run_plain(umbir, probs)  # warm
+    t_plain, plain = batch.run_plain(umbir, probs)
+    t_batch, batched, rebuilds = batch.run_batched(umbir, probs, umbir.BATCH_STREAMS)
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[2], b[2]) for a, b in zip(plain, batched))
+    work = batch.evals(probs)
+    for p in probs:
+        p["geom"].free()
+    return {"problems": len(cards), "iterations": sum(c.n_iter for c in cards),
+            "plain_s": t_plain, "batched_s": t_batch, "recon_per_s_plain": len(cards) / t_plain,
+            "recon_per_s_batched": len(cards) / t_batch, "speedup": t_plain / t_batch,
+            "evals_per_s_plain": work / t_plain, "evals_per_s_batched": work / t_batch,
+            "batches": rebuilds, "bitwise_equal_to_plain": bool(same)}
+
+
+def cpu_baseline_section(card):
+    """The oracle (FP64 numpy) on bounded samples of the same workload, one A
+    and one A^T over all voxels: 6 traces on one core, and one whole scan
+    position (16 traces) on all host cores (at most 16 processes)."""
+    import dataclasses
+    from oracle import operator as oo
+    from synth import phantom
+    P, N = card.array.n_scans, card.n_voxels
+    xs = phantom(card).astype(np.float64)
+    nproc, model = host_cpu()
+    res = []
+    for ks, workers in ((6, 1), (card.array.n_rx, None)):
+        sub = dataclasses.replace(card, array=dataclasses.replace(
+            card.array, tx_x=(card.array.tx_x[P // 2],), rx_offset=card.array.rx_offset[:ks]))
+        used = min(oo.host_workers(workers), ks)
+        t0 = time.perf_counter()
+        ys = oo.forward(sub, xs, workers=workers)
+        oo.adjoint_voxels(sub, ys, np.arange(N), workers=workers)
+        tc = time.perf_counter() - t0
+        res.append({"value": ks * N / tc, "unit": "evals/s", "cores": used, "kind": "oracle",
+                    "sample": f"{ks} traces (one scan position) of the same workload: one A and one A^T over all "
+                              f"{N} voxels in FP64 numpy on {used} process(es), {tc:.1f} s",
+                    "host_cores": nproc, "host_cpu": model})
+    return res
 
 
 def main():
@@ -187,6 +363,9 @@ def main():
     import torch
     from paper_2202_09703_amd import umbir
     from synth import card_c2, phantom, noise
+
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
     card = card_c2()
@@ -259,6 +438,7 @@ def main():
     umbir.profile_select(None)
     for gm in keep:
         gm.free()
+    say(f"timed {args.steps} reconstructions: {elapsed / args.steps * 1e3:.2f} ms each")
 
     sec_per_step = elapsed / args.steps
     evals_per_step = triples * (n_iter + 1)
@@ -268,30 +448,16 @@ def main():
     # ---- per-operator rates (plain calls, HIP events on the current stream)
     gm = umbir.build_geometry(card)
     wf = gm.workspace(umbir.WORK_ADJOINT)
-    xr = torch.randn(geom.image_shape, generator=torch.Generator().manual_seed(3)).to(dev)
-    yr = torch.empty(geom.trace_shape, dtype=torch.float32, device=dev)
-    xo = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
-    reps = 10
-    for _ in range(2):
-        umbir.forward(gm, xr, yr, work=wf)
-        umbir.adjoint(gm, yr, xo, work=wf)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ev[0].record()
-    for _ in range(reps):
-        umbir.forward(gm, xr, yr, work=wf)
-    ev[1].record()
-    for _ in range(reps):
-        umbir.adjoint(gm, yr, xo, work=wf)
-    ev[2].record()
-    torch.cuda.synchronize()
-    t_fwd = ev[0].elapsed_time(ev[1]) / reps / 1e3
-    t_adj = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    xr = torch.randn(gm.image_shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    yr = torch.empty(gm.trace_shape, dtype=torch.float32, device=dev)
+    xo = torch.empty(gm.image_shape, dtype=torch.float32, device=dev)
+    t_fwd, t_adj = time_pair(umbir, torch, gm, xr, yr, xo, wf)
 
     # ---- rooflines: the dominant kernel from the timed steps; every sweep
     # kernel from the profiled untimed step
-    tg = gm.trace_groups
-    kernels = {k: roofline(k, prof_all, 1, card, gm.n_off, tg) for k in ("splat", "conv", "corr", "gather")}
-    roof = roofline(dname, prof, args.steps, card, gm.n_off, tg)
+    tg, kb = gm.trace_groups, tuning["gather_batch_kb"]
+    kernels = {k: roofline(k, prof_all, 1, card, gm.n_off, tg, kb) for k in ("splat", "conv", "corr", "gather")}
+    roof = roofline(dname, prof, args.steps, card, gm.n_off, tg, kb)
     if roof is not None:  # launches per step from the fully profiled step; the timed ones are a sample
         roof["launches_per_step"] = prof_all[dname][0]
         roof["timed_launches"] = prof[dname][0]
@@ -342,6 +508,7 @@ def main():
         "tuning": tuning,
         "roofline": roof,
         "sweep_kernels": kernels,
+        "operator_roofline": operator_roofline(card, t_fwd + t_adj, triples),
     }
     # the HBM-bound update kernels against the published peak and a measured copy
     crate = copy_rate()
@@ -363,29 +530,26 @@ def main():
         fe = float(np.linalg.norm(yf[i, j] - ref) / np.linalg.norm(ref))
         rr = np.asarray(noise(card), np.float64)
         xa = umbir.adjoint(gm, torch.tensor(rr, dtype=torch.float32, device=dev)).cpu().numpy().reshape(-1)
-        vox = np.random.default_rng(9).choice(N, 8, replace=False)
-        refa = oo.adjoint_voxels(card, rr, vox)
+        vox = np.random.default_rng(9).choice(N, 64, replace=False)
+        refa = oo.adjoint_voxels(card, rr, vox, workers=None)
         ae = float(np.linalg.norm(xa[vox] - refa) / np.linalg.norm(refa))
-        out["parity_vs_oracle"] = {"forward_rel_l2_trace": fe, "adjoint_rel_l2_8_voxels": ae,
+        out["parity_vs_oracle"] = {"forward_rel_l2_trace": fe, "adjoint_rel_l2_64_voxels": ae,
                                    "tolerance": 1e-5}
+        say("parity sampled")
+    gm.free()
+    del wf, work
+
+    if not args.quick:
+        out["precision_512x512"] = precision_section(umbir, torch, dev, with_parity=True)
+        say("512x512 storage types done")
+        out["batch_48"] = batch_section(umbir, torch, dev)
+        say("48-problem batch done")
 
     if not args.quick and not args.no_cpu:
-        # oracle (FP64 numpy) on a bounded sample: one scan position and its
-        # first KS receivers, A and A^T over all voxels; evals = KS N
-        import dataclasses
-        from oracle import operator as oo
-        KS = 6
-        sub = dataclasses.replace(card, array=dataclasses.replace(
-            card.array, tx_x=(card.array.tx_x[P // 2],), rx_offset=card.array.rx_offset[:KS]))
-        xs = phantom(card).astype(np.float64)
-        t0 = time.perf_counter()
-        ys = oo.forward(sub, xs)
-        oo.adjoint(sub, ys)
-        tc = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": KS * N / tc, "unit": "evals/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{KS} traces (one scan position) of the same workload: one A and "
-                                         f"one A^T over all {N} voxels in FP64 numpy, {tc:.1f} s"}
-    gm.free()
+        base = cpu_baseline_section(card)
+        out["cpu_baseline"] = base[0]
+        out["cpu_baseline_all_cores"] = base[1]
+        say("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

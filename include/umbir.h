@@ -113,8 +113,9 @@ typedef struct {
      * h(gamma(v), t); the templates are tabulated once at gamma_g = g dgamma,
      * g = 0 .. n_gamma - 1, dgamma = 2 Gamma_max / (n_gamma - 1), Gamma_max the
      * largest one-way path attenuation sum_l alpha_l eta_l / cos(theta_l) of
-     * the problem's legs, and each pair uses the template nearest its gamma
-     * (decided per leg in units of 2^-24 of dgamma).  The forward runs one
+     * the problem's legs, and each pair uses the template nearest its gamma,
+     * floor((Gamma_tx + Gamma_rx) / dgamma + 1/2) in float64 (at most
+     * n_gamma - 1).  The forward runs one
      * splat + convolution per template; the adjoint one correlation per
      * template, each into its own resident fine grid (its workspace grows
      * n_gamma-fold), then one gather over all of them. */
@@ -333,8 +334,9 @@ int umbir_autotune(umbir_geometry* geom, void* stream, umbir_tuning* chosen);
  *                                        (+ zero pad), one per attenuation template
  *  UMBIR_TABLE_DBASIS float [P][K][M]    direct-arrival columns of D
  *  UMBIR_TABLE_OFFSET int32 [P + P*K]    lattice index base of each transducer
- *  UMBIR_TABLE_ATTEN  int32 [nz][n_off]  leg path attenuation in units of
- *                                        2^-24 gamma_step (0 without attenuation)
+ *  UMBIR_TABLE_ATTEN  double [nz][n_off] leg path attenuation Gamma_leg /
+ *                                        gamma_step in template bins (0 without
+ *                                        attenuation)
  * `bytes` must equal the table's size.  Errors: EINVAL, EDEVICE. */
 enum { UMBIR_TABLE_DELAY = 0, UMBIR_TABLE_APOD = 1, UMBIR_TABLE_TAU = 2,
        UMBIR_TABLE_BANK = 3, UMBIR_TABLE_DBASIS = 4, UMBIR_TABLE_OFFSET = 5,

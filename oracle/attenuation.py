@@ -14,10 +14,12 @@ Readings (the paper gives no binning rule):
     Gamma_max is the largest one-way path attenuation over the problem's legs
     (voxel centres at the largest lateral distance from any transducer, every
     row).  2 Gamma_max bounds gamma(v) = Gamma_tx + Gamma_rx of every trace.
-  * A (trace, voxel) pair uses the template nearest its gamma, decided in
-    integer arithmetic from the legs: u_leg = round(Gamma_leg / dgamma * 2^24)
-    in float64 (ties to even), bin = (u_tx + u_rx + 2^23) >> 24, capped at
-    G - 1.  So |gamma - gamma_bin| <= dgamma / 2 + 2^-24 dgamma.
+  * A (trace, voxel) pair uses the template nearest its gamma:
+    bin = floor(gamma / dgamma + 1/2) in float64, gamma = Gamma_tx + Gamma_rx,
+    capped at G - 1.  So |gamma - gamma_bin| <= dgamma / 2.  A pair whose
+    gamma / dgamma lies within a hair of a half-integer has two equally near
+    templates; near_ties() names such pairs so that a comparison can set them
+    aside.
   * If Gamma_max = 0 (attenuating layers lie below every voxel) G is 1.
 """
 from __future__ import annotations
@@ -26,7 +28,6 @@ import numpy as np
 
 from . import geometry, pulse
 
-FRAC_BITS = 24
 MAX_BINS = 64
 
 
@@ -77,17 +78,37 @@ def bank(card, absolute: bool = False) -> np.ndarray:
     return np.abs(b) if absolute else b
 
 
-def leg_units(gamma_leg, dgamma: float) -> np.ndarray:
-    """u = round(Gamma_leg / dgamma * 2^24) (float64, ties to even)."""
-    return np.rint(np.asarray(gamma_leg, float) / dgamma * 2.0 ** FRAC_BITS).astype(np.int64)
-
-
 def bins_of(legs, dgamma: float, g: int) -> np.ndarray:
-    """Template index per voxel from its two legs' attenuations."""
+    """Template index per voxel: the bin nearest gamma = Gamma_tx + Gamma_rx."""
     if g == 1:
         return np.zeros(np.shape(legs[0]), np.int64)
-    u = leg_units(legs[0], dgamma) + leg_units(legs[1], dgamma)
-    return np.minimum((u + (1 << (FRAC_BITS - 1))) >> FRAC_BITS, g - 1)
+    gamma = np.asarray(legs[0], float) + np.asarray(legs[1], float)
+    return np.minimum(np.floor(gamma / dgamma + 0.5), g - 1).astype(np.int64)
+
+
+def tie_distance(legs, dgamma: float) -> np.ndarray:
+    """Distance of gamma / dgamma from the nearest half-integer, in bins: the
+    margin by which a pair's nearest template is decided."""
+    u = (np.asarray(legs[0], float) + np.asarray(legs[1], float)) / dgamma
+    return np.abs(u - np.floor(u) - 0.5)
+
+
+def near_ties(card, tol: float = 1e-9):
+    """(i, j, v) of every (trace, voxel) pair whose gamma / dgamma lies within
+    `tol` of a half-integer below the last bin: two templates are nearly as
+    near, and an independent computation of gamma may pick the other."""
+    g = n_bins(card)
+    out = []
+    if g == 1:
+        return out
+    dgamma = step(card)
+    for i in range(card.array.n_scans):
+        for j in range(card.array.n_rx):
+            _, _, legs = geometry.trace_geometry(card, i, j, legs=True)
+            u = (legs[0] + legs[1]) / dgamma
+            hit = (tie_distance(legs, dgamma) < tol) & (u < g - 1)
+            out.extend((i, j, int(v)) for v in np.nonzero(hit)[0])
+    return out
 
 
 def trace_bins(card, i: int, j: int, vox) -> np.ndarray:

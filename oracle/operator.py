@@ -21,11 +21,20 @@ dropped.  The transpose is written out from the same sum.
 D (Eq. (1)) has one column per trace: the template placed at the direct-arrival
 delay of that trace, in that trace's rows only.
 
+forward() and adjoint_voxels() take `workers`: with more than one, the traces
+are split into that many contiguous runs, each run is evaluated by the same
+per-trace code in its own process (a spawned pool), and the runs' results are
+put together in run order (the adjoint's partial sums are added in that
+order).  workers=None uses all host cores, at most 16.
+
 With attenuation (some alpha_l > 0) the template is chosen per (trace, voxel)
 from the bank of attenuation.py; `b` may be a single template [len] or such a
 bank [G][len].  Reading: the direct arrival keeps the gamma = 0 template.
 """
 from __future__ import annotations
+
+import multiprocessing as mp
+import os
 
 import numpy as np
 
@@ -84,7 +93,30 @@ def forward_trace(card, i, j, x_flat, b=None, weight_abs=False):
     return y
 
 
-def forward(card, x, traces=None, b=None, weight_abs=False):
+def host_workers(workers=None) -> int:
+    """Processes for the multi-core path: `workers`, or all host cores (at most 16)."""
+    if workers is not None:
+        return max(1, int(workers))
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _runs(items, n):
+    """`items` split into at most n contiguous, non-empty runs, in order."""
+    n = max(1, min(n, len(items)))
+    bounds = np.linspace(0, len(items), n + 1).round().astype(int)
+    return [items[bounds[k]:bounds[k + 1]] for k in range(n)]
+
+
+def _pool(n):
+    return mp.get_context("spawn").Pool(n)
+
+
+def _forward_run(args):
+    card, traces, x_flat, bank, weight_abs = args
+    return [forward_trace(card, i, j, x_flat, bank, weight_abs) for i, j in traces]
+
+
+def forward(card, x, traces=None, b=None, weight_abs=False, workers=1):
     """A x as an array (P, K, M); `traces` restricts to a list of (i, j)."""
     a = card.array
     y = np.zeros((a.n_scans, a.n_rx, card.acq.n_samples))
@@ -92,6 +124,15 @@ def forward(card, x, traces=None, b=None, weight_abs=False):
     if traces is None:
         traces = [(i, j) for i in range(a.n_scans) for j in range(a.n_rx)]
     bank = _bank(card, b)
+    n = host_workers(workers)
+    if n > 1 and len(traces) > 1:
+        runs = _runs(list(traces), n)
+        with _pool(len(runs)) as pool:
+            parts = pool.map(_forward_run, [(card, run, x_flat, bank, weight_abs) for run in runs])
+        for run, part in zip(runs, parts):
+            for (i, j), yt in zip(run, part):
+                y[i, j] = yt
+        return y
     for i, j in traces:
         y[i, j] = forward_trace(card, i, j, x_flat, bank, weight_abs)
     return y
@@ -117,26 +158,45 @@ def forward_columns(card, vox, coef, b=None, weight_abs=False):
     return y
 
 
-def adjoint_voxels(card, r, vox, b=None, weight_abs=False):
-    """(A^T r) at the flat voxel indices `vox`; r has shape (P, K, M)."""
+def _adjoint_traces(card, traces, rows, vox, bank, weight_abs):
+    """sum over the listed traces (i, j) of their part of A^T r at `vox`;
+    rows[k] is trace k's samples."""
     acq = card.acq
+    out = np.zeros(len(vox))
+    for (i, j), rij in zip(traces, rows):
+        for s in range(0, len(vox), _CHUNK):
+            sl = slice(s, s + _CHUNK)
+            delay, w, legs = geometry.trace_geometry(card, i, j, vox[sl], legs=True)
+            if weight_abs:
+                w = np.abs(w)
+            m, val = _taps(delay, acq, bank, _rows(card, bank, legs))
+            keep = (m >= 0) & (m < acq.n_samples)
+            rv = np.where(keep, rij[np.clip(m, 0, acq.n_samples - 1)], 0.0)
+            out[sl] += w * np.sum(rv * val, axis=1)
+    return out
+
+
+def _adjoint_run(args):
+    return _adjoint_traces(*args)
+
+
+def adjoint_voxels(card, r, vox, b=None, weight_abs=False, workers=1):
+    """(A^T r) at the flat voxel indices `vox`; r has shape (P, K, M)."""
     bank = _bank(card, b)
     vox = np.asarray(vox, np.int64)
-    out = np.zeros(len(vox))
     a = card.array
-    for i in range(a.n_scans):
-        for j in range(a.n_rx):
-            rij = r[i, j]
-            for s in range(0, len(vox), _CHUNK):
-                sl = slice(s, s + _CHUNK)
-                delay, w, legs = geometry.trace_geometry(card, i, j, vox[sl], legs=True)
-                if weight_abs:
-                    w = np.abs(w)
-                m, val = _taps(delay, acq, bank, _rows(card, bank, legs))
-                keep = (m >= 0) & (m < acq.n_samples)
-                rv = np.where(keep, rij[np.clip(m, 0, acq.n_samples - 1)], 0.0)
-                out[sl] += w * np.sum(rv * val, axis=1)
-    return out
+    traces = [(i, j) for i in range(a.n_scans) for j in range(a.n_rx)]
+    n = host_workers(workers)
+    if n > 1 and len(traces) > 1:
+        runs = _runs(traces, n)
+        with _pool(len(runs)) as pool:
+            parts = pool.map(_adjoint_run, [(card, run, [r[i, j] for i, j in run], vox, bank, weight_abs)
+                                            for run in runs])
+        out = np.zeros(len(vox))
+        for part in parts:
+            out += part
+        return out
+    return _adjoint_traces(card, traces, [r[i, j] for i, j in traces], vox, bank, weight_abs)
 
 
 def adjoint(card, r, b=None, weight_abs=False):

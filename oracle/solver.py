@@ -59,6 +59,38 @@ def sqs_denominator(card, sigma) -> np.ndarray:
     return operator.adjoint(card, col, b=babs, weight_abs=True) / sigma ** 2
 
 
+def sqs_denominator_voxels(card, sigma, vox, workers=1) -> np.ndarray:
+    """d at the flat voxel indices `vox`: Abar 1 over every trace, then
+    Abar^T of it at those voxels (on `workers` processes, see operator)."""
+    babs = operator.default_bank(card, absolute=True)
+    ones = np.ones((card.grid.nz, card.grid.nx))
+    col = operator.forward(card, ones, b=babs, weight_abs=True, workers=workers)
+    return operator.adjoint_voxels(card, col, vox, b=babs, weight_abs=True, workers=workers) / sigma ** 2
+
+
+def first_step_voxels(card, y, sigma, pr, vox, den_vox, estimate_direct=None, workers=1):
+    """The first surrogate iteration from x = 0, g = 0 at the voxels `vox`
+    (x^1 there, g^1 and the cost C(0, 0)), given d at those voxels: e = y,
+    the exact g step, then x^1_s = -(-(A^T e)_s / sigma^2 + slope_s) /
+    (d_s + curv_s) with the prior surrogate at x = 0."""
+    grid, a = card.grid, card.array
+    if estimate_direct is None:
+        estimate_direct = bool(getattr(pr, "estimate_direct", True))
+    x0 = np.zeros((grid.nz, grid.nx))
+    g = np.zeros((a.n_scans, a.n_rx))
+    dbasis = operator.direct_basis(card)
+    e = np.array(y, float)
+    cost0 = data_cost(e, sigma) + qprior.cost(x0, grid, pr)
+    if estimate_direct:
+        g = direct_step(dbasis, e)
+        e = e - dbasis * g[:, :, None]
+    u = operator.adjoint_voxels(card, e, vox, workers=workers)
+    slope, curv = qprior.surrogate(x0, grid, pr)
+    vox = np.asarray(vox, np.int64)
+    x1 = -(-u / sigma ** 2 + slope.reshape(-1)[vox]) / (np.asarray(den_vox, float) + curv.reshape(-1)[vox])
+    return x1, g, cost0
+
+
 def direct_step(dbasis, e):
     """Per-trace exact g increment: <d_ij, e_ij> / ||d_ij||^2 (zero where d_ij = 0)."""
     nrm = np.sum(dbasis ** 2, axis=2)

@@ -23,14 +23,20 @@ import time
 from typing import Any, Dict, List
 
 
-def prepare(umbir, cards, device="cuda:0", log=print):
+def prepare(umbir, cards, device="cuda:0", log=print, data=None):
     """Geometry and data per card: y = A x_true + sigma * noise made on the
-    device, sigma from the card's SNR."""
+    device, sigma from the card's SNR; or, with `data`, the given host data
+    (a list of (y [P][K][M], sigma) per card) copied to the device."""
     import torch
     from synth import phantom, noise
     probs = []
     for i, card in enumerate(cards):
         g = umbir.build_geometry(card)
+        if data is not None:
+            y = torch.tensor(data[i][0], dtype=torch.float32, device=device)
+            sigma = float(data[i][1])
+            probs.append({"card": card, "geom": g, "y": y, "sigma": sigma, "n_iter": card.n_iter})
+            continue
         xt = torch.tensor(phantom(card), dtype=torch.float32, device=device)
         clean = umbir.forward(g, xt)
         sigma = float(torch.sqrt(torch.mean(clean.double() ** 2) / 10.0 ** (card.snr_db / 10.0)))

@@ -95,17 +95,16 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
   Leg rec;
   rec.delay = __double2ll_rn(fs * T * kTwo32);
   rec.apod = static_cast<float>(pw);
-  rec.atten = 0;
+  rec.spare = 0;
   legs[idx] = rec;
   if (gam) gam[idx] = att;
 }
 
-// Leg attenuation in units of 2^-24 template bins: round(Gamma / dgamma * 2^24),
-// ties to even.
-__global__ void k_leg_units(int n, const double* __restrict__ gam, double step, Leg* __restrict__ legs) {
+// Leg attenuation in template bins: Gamma / dgamma (float64).
+__global__ void k_leg_units(int n, const double* __restrict__ gam, double step, double* __restrict__ gunit) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  legs[idx].atten = int(__double2ll_rn(gam[idx] / step * double(1 << kGammaFracBits)));
+  gunit[idx] = gam[idx] / step;
 }
 
 // Windowed pulse of Eq. (10) at fine-grid index n (time n / (Q fs)): the
@@ -170,18 +169,19 @@ __global__ void k_polyphase(int Q, int Lh, int g0, int G, const float* __restric
 // Template occupancy: for trace blockIdx.x and voxel v, the template of the
 // pair marks the blocks of its fine positions J and J + 1 (the splat puts its
 // weight on both).
-__global__ void k_bin_mask(const Leg* __restrict__ legs, int n_off, const int* __restrict__ base, int P, int K,
-                           int nx, int N, int qs, long MQ, int last, int nb, unsigned long long* __restrict__ mask) {
+__global__ void k_bin_mask(const Leg* __restrict__ legs, const double* __restrict__ gunit, int n_off,
+                           const int* __restrict__ base, int P, int K, int nx, int N, int qs, long MQ, int last, int nb,
+                           unsigned long long* __restrict__ mask) {
   const int t = blockIdx.x;
   const int v = blockIdx.y * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const int row = v / nx, col = v - row * nx;
   const int half = n_off / 2;
-  const Leg a = legs[size_t(row) * n_off + leg_slot(abs(base[t / K] + 2 * col), half)];
-  const Leg b = legs[size_t(row) * n_off + leg_slot(abs(base[P + t] + 2 * col), half)];
-  const uint64_t D = uint64_t(a.delay + b.delay);
+  const size_t ka = size_t(row) * n_off + leg_slot(abs(base[t / K] + 2 * col), half);
+  const size_t kb = size_t(row) * n_off + leg_slot(abs(base[P + t] + 2 * col), half);
+  const uint64_t D = uint64_t(legs[ka].delay + legs[kb].delay);
   const long J = long(D >> (32 - qs));
-  const unsigned long long bit = 1ull << gamma_bin(a.atten + b.atten, last);
+  const unsigned long long bit = 1ull << gamma_bin(gunit[ka] + gunit[kb], last);
   if (J < MQ) atomicOr(&mask[size_t(t) * nb + (J >> kMaskShift)], bit);
   if (J + 1 < MQ && ((J + 1) >> kMaskShift) != (J >> kMaskShift))
     atomicOr(&mask[size_t(t) * nb + ((J + 1) >> kMaskShift)], bit);
@@ -418,10 +418,15 @@ int choose_trace_groups(int n_vox, int n_traces) {
 
 size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh, int n_gamma) {
   const size_t legs = size_t(nz) * n_off;
+  // with attenuation: the legs' attenuation in template bins and the
+  // template occupancy masks
+  const size_t att = n_gamma > 1 ? legs * sizeof(double) + size_t(P) * K *
+                                       ((size_t(M) * Q + (size_t(1) << kMaskShift) - 1) >> kMaskShift) * 8
+                                 : 0;
   return legs * sizeof(Leg) + size_t(nz) * sizeof(float) +
          size_t(P) * (1 + K) * sizeof(int) + size_t(n_gamma) * (Q * Lh + 2) * sizeof(float) +
          2 * size_t(n_gamma) * Q * Lh * sizeof(float) + size_t(P) * K * M * sizeof(float) +
-         size_t(P) * K * sizeof(float);
+         size_t(P) * K * sizeof(float) + att;
 }
 
 }  // namespace
@@ -494,7 +499,7 @@ void umbir_geometry_free(umbir_geometry* G) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (G->device >= 0) (void)hipSetDevice(G->device);
-  void* ptrs[] = {G->legs, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm, G->gmask};
+  void* ptrs[] = {G->legs, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm, G->gmask, G->gunit};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (cur >= 0) (void)hipSetDevice(cur);
@@ -649,8 +654,9 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     if (gmax > 0.0) {
       G->n_gamma = dv.n_gamma;
       G->gamma_step = 2.0 * gmax / (G->n_gamma - 1);
+      if ((st = alloc((void**)&G->gunit, legs * sizeof(double)))) return bail(st);
       UMBIR_LAUNCH("leg_units", k_leg_units, dim3((n_legs + 255) / 256), dim3(256), 0, s, n_legs, gam_dev,
-                   G->gamma_step, G->legs);
+                   G->gamma_step, G->gunit);
     }
   }
   const int NG = G->n_gamma;
@@ -689,8 +695,8 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     int qs = 0;
     while ((1 << qs) < G->Q) ++qs;
     UMBIR_LAUNCH("bin_mask", k_bin_mask, dim3(unsigned(PK), unsigned((G->voxels() + 255) / 256)), dim3(256), 0, s,
-                 G->legs, G->n_off, G->base, G->P, G->K, G->nx, G->voxels(), qs, MQ, NG - 1, G->mask_blocks,
-                 G->gmask);
+                 G->legs, G->gunit, G->n_off, G->base, G->P, G->K, G->nx, G->voxels(), qs, MQ, NG - 1,
+                 G->mask_blocks, G->gmask);
   }
   if (gam_dev) (void)hipFreeAsync(gam_dev, s);
   if (nodes_dev) (void)hipFreeAsync(nodes_dev, s);
@@ -752,23 +758,34 @@ int umbir_copy_table(const umbir_geometry* G, int which, void* dst, size_t bytes
     case UMBIR_TABLE_BANK: src = G->bank; need = size_t(G->n_gamma) * (G->Q * G->Lh + 2) * sizeof(float); break;
     case UMBIR_TABLE_DBASIS: src = G->dbasis; need = size_t(G->traces()) * G->M * sizeof(float); break;
     case UMBIR_TABLE_OFFSET: src = G->base; need = size_t(G->P) * (1 + G->K) * sizeof(int); break;
-    case UMBIR_TABLE_ATTEN: need = legs * sizeof(int); break;
+    case UMBIR_TABLE_ATTEN: need = legs * sizeof(double); break;
     default: return fail(UMBIR_EINVAL, "unknown table");
   }
   if (bytes != need) return fail(UMBIR_EINVAL, "bytes does not match the table size");
   if (src) return check_hip(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost), "hipMemcpy(table)");
+  const int half = G->n_off / 2;
+  if (which == UMBIR_TABLE_ATTEN) {  // zero with a single template
+    std::vector<double> gu(legs, 0.0);
+    if (G->gunit) {
+      int st = check_hip(hipMemcpy(gu.data(), G->gunit, legs * sizeof(double), hipMemcpyDeviceToHost),
+                         "hipMemcpy(attenuation)");
+      if (st) return st;
+    }
+    for (int r = 0; r < G->nz; ++r)
+      for (int o = 0; o < G->n_off; ++o)
+        static_cast<double*>(dst)[size_t(r) * G->n_off + o] = gu[size_t(r) * G->n_off + leg_slot(o, half)];
+    return UMBIR_OK;
+  }
   // leg tables: one field of the packed records
   std::vector<Leg> rec(legs);
   int st = check_hip(hipMemcpy(rec.data(), G->legs, legs * sizeof(Leg), hipMemcpyDeviceToHost),
                      "hipMemcpy(legs)");
   if (st) return st;
-  const int half = G->n_off / 2;
   for (int r = 0; r < G->nz; ++r)
     for (int o = 0; o < G->n_off; ++o) {
       const Leg& L = rec[size_t(r) * G->n_off + leg_slot(o, half)];
       const size_t k = size_t(r) * G->n_off + o;
       if (which == UMBIR_TABLE_DELAY) static_cast<int64_t*>(dst)[k] = L.delay;
-      else if (which == UMBIR_TABLE_ATTEN) static_cast<int*>(dst)[k] = L.atten;
       else static_cast<float*>(dst)[k] = L.apod;
     }
   return UMBIR_OK;

@@ -15,25 +15,26 @@ namespace umbir {
 constexpr int kMaxLayers = UMBIR_MAX_LAYERS;
 constexpr double kTwo32 = 4294967296.0;
 
-// One-way leg record: delay in Q32.32 fixed-point samples, cos^beta of the
-// leg's angle sum and, with attenuation, the leg's path attenuation in units
-// of 2^-24 template bins (0 without), stored row-major [nz][n_off].  Within a
-// row the lattice offsets are split by parity (even offsets first, then odd):
-// one transducer only ever uses offsets of one parity, so neighbouring columns
-// read neighbouring records.  n_off is even.
+// One-way leg record: delay in Q32.32 fixed-point samples and cos^beta of
+// the leg's angle sum, stored row-major [nz][n_off].  Within a row the lattice
+// offsets are split by parity (even offsets first, then odd): one transducer
+// only ever uses offsets of one parity, so neighbouring columns read
+// neighbouring records.  n_off is even.  With attenuation a second table of
+// the same layout holds each leg's path attenuation in template bins
+// (float64, Gamma_leg / dgamma).
 struct __align__(16) Leg {
   int64_t delay;
   float apod;
-  int atten;
+  int spare;  // 0
 };
 
-// Attenuation bins: a (trace, voxel) pair whose legs carry u_tx and u_rx uses
-// template (u_tx + u_rx + 2^23) >> 24, at most n_gamma - 1.
-constexpr int kGammaFracBits = 24;
+// Attenuation bins: a (trace, voxel) pair whose legs carry u_tx and u_rx
+// template bins of attenuation uses the nearest template,
+// floor(u_tx + u_rx + 1/2) in float64, at most n_gamma - 1.
 constexpr int kMaxGamma = 64;
-__host__ __device__ __forceinline__ int gamma_bin(int u, int last) {
-  const int b = (u + (1 << (kGammaFracBits - 1))) >> kGammaFracBits;
-  return b < last ? b : last;
+__host__ __device__ __forceinline__ int gamma_bin(double u, int last) {
+  const double b = floor(u + 0.5);
+  return b < double(last) ? int(b) : last;
 }
 
 // Template occupancy (attenuation): one 64-bit mask per (trace, block of
@@ -147,9 +148,10 @@ struct umbir_geometry {
   int n_gamma = 1;
   double gamma_step = 0.0;
   unsigned long long* gmask = nullptr;  // [P*K][mask_blocks] template occupancy (n_gamma > 1)
+  double* gunit = nullptr;  // [nz][n_off] leg path attenuation / gamma_step, laid out as legs (n_gamma > 1)
   int mask_blocks = 0;
   // resident device tables
-  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta, attenuation units), parity-split rows
+  umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows
   float* tau = nullptr;      // [nz] transmittance product of the row's layer
   int* base = nullptr;       // [P + P*K] lattice base: offset index = |base + 2 col|
   float* bank = nullptr;     // [n_gamma][Q*Lh + 2] tabulated windowed responses, zero padded

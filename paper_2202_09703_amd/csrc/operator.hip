@@ -210,8 +210,9 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 // convolution reads it).
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
-    const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const int* __restrict__ base,
-    int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins, const unsigned* __restrict__ xmax, int n_xmax,
+    const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const double* __restrict__ gunit,
+    const int* __restrict__ base, int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins,
+    const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
   const int NT = MT ? glast + 1 : 1;                                 // tiles
@@ -286,13 +287,17 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
       __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, rows * n_off * int(sizeof(Leg)), kBufferWord3);
   const __amdgpu_buffer_rsrc_t xt_rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xt), 0, rows * nx * 4, kBufferWord3);
+  // ATT: the legs' attenuation in template bins, 8 bytes per leg (byte
+  // offset half that of the leg record)
+  const __amdgpu_buffer_rsrc_t gu_rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(ATT ? gunit : reinterpret_cast<const double*>(legs)), 0, rows * n_off * 8, kBufferWord3);
   const unsigned rowbytes = unsigned(n_off) * unsigned(sizeof(Leg));
   const unsigned lstep = 8u * rowbytes;  // bytes between a lane's steps
   const unsigned xstep = 8u * unsigned(nx) * 4u;
   struct Rows {
     int64_t da, db;
     float pa, pb, xv;
-    int ua, ub;
+    double ua, ub;
   };
   for (int J0 = J_begin; J0 < J_end; J0 += tile_bins) {
     const int J1 = min(J0 + tile_bins, J_end);
@@ -317,16 +322,11 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
           const int ka = int(oa + k * lstep), kb = int(ob + k * lstep);
           const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ka, 0, 0);
           const auto b = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, kb, 0, 0);
-          if constexpr (ATT) {  // apodisation and attenuation units together
-            const auto ea = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, ka + 8, 0, 0);
-            const auto eb = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, kb + 8, 0, 0);
-            v.pa = __builtin_bit_cast(float, ea[0]);
-            v.pb = __builtin_bit_cast(float, eb[0]);
-            v.ua = int(ea[1]);
-            v.ub = int(eb[1]);
-          } else {
-            v.pa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ka + 8, 0, 0));
-            v.pb = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, kb + 8, 0, 0));
+          v.pa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, ka + 8, 0, 0));
+          v.pb = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, kb + 8, 0, 0));
+          if constexpr (ATT) {  // the legs' attenuation in template bins
+            v.ua = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(gu_rs, ka >> 1, 0, 0));
+            v.ub = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(gu_rs, kb >> 1, 0, 0));
           }
           v.xv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xt_rs, int(ox + k * xstep), 0, 0));
           v.da = int64_t((uint64_t(a[1]) << 32) | a[0]);
@@ -451,7 +451,7 @@ __device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsr
 template <bool ABSW, int VPT, int ST, bool ATT, bool ONE, bool MULTI>
 __global__ __launch_bounds__(256) void k_gather(
     const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
-    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
+    const double* __restrict__ gunit, const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
     int tpg, int t_off, int t_cnt, int vox_per_block, int gbin, int glast, int accum,
     float* __restrict__ partial) {
   const int N = nx * nz;
@@ -468,9 +468,12 @@ __global__ __launch_bounds__(256) void k_gather(
   const int half = n_off / 2;
   const __amdgpu_buffer_rsrc_t leg_rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, nz * n_off * int(sizeof(Leg)), kBufferWord3);
+  // ATT: the legs' attenuation in template bins (byte offset half the record's)
+  const __amdgpu_buffer_rsrc_t gu_rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(ATT ? gunit : reinterpret_cast<const double*>(legs)), 0, nz * n_off * 8, kBufferWord3);
   const int grid_elems = MULTI ? (glast + 1) * MQ : MQ;  // one trace's fine data
   const int fine_bytes = grid_elems * int(sizeof(typename Store<ST>::T));
-  struct Legs { int64_t da[VPT], db[VPT]; float pa[VPT], pb[VPT]; int ua[VPT], ub[VPT]; };
+  struct Legs { int64_t da[VPT], db[VPT]; float pa[VPT], pb[VPT]; double ua[VPT], ub[VPT]; };
   struct Taps { unsigned J[VPT], J1[VPT]; float phi[VPT], w[VPT]; };
   struct Samples { float c0[VPT], c1[VPT]; };
   for (int vc = v_begin; vc < v_end; vc += blockDim.x * VPT) {
@@ -487,20 +490,16 @@ __global__ __launch_bounds__(256) void k_gather(
       rowoff[u] = row * n_off;
       acc[u] = 0.0f;
     }
-    // one leg record (delay, apodisation, attenuation units) per voxel of the
-    // thread for the transducer with lattice base bt
-    auto load_leg = [&](int bt, int64_t (&d)[VPT], float (&p)[VPT], int (&ua)[VPT]) {
+    // one leg record (delay, apodisation; with ATT the attenuation in
+    // template bins) per voxel of the thread for the transducer with lattice
+    // base bt
+    auto load_leg = [&](int bt, int64_t (&d)[VPT], float (&p)[VPT], double (&ua)[VPT]) {
 #pragma unroll
       for (int u = 0; u < VPT; ++u) {
         const int o = (rowoff[u] + leg_slot(abs(bt + col2[u]), half)) * int(sizeof(Leg));
         const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, o, 0, 0);
-        if constexpr (ATT) {  // apodisation and attenuation units together
-          const auto e = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, o + 8, 0, 0);
-          p[u] = __builtin_bit_cast(float, e[0]);
-          ua[u] = int(e[1]);
-        } else {
-          p[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, o + 8, 0, 0));
-        }
+        p[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, o + 8, 0, 0));
+        if constexpr (ATT) ua[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(gu_rs, o >> 1, 0, 0));
         d[u] = int64_t((uint64_t(a[1]) << 32) | a[0]);
       }
     };
@@ -1403,7 +1402,7 @@ void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs,
   const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
   const size_t lds = size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
-               G.n_off, G.legs, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, prescale_blocks(G), gbin,
+               G.n_off, G.legs, G.gunit, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, prescale_blocks(G), gbin,
                G.n_gamma - 1,
                bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine));
 }
@@ -1430,11 +1429,11 @@ void launch_gather_k(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, in
   constexpr int VPT = 4;
   if (abs_op)
     UMBIR_LAUNCH("gather", (k_gather<true, VPT, ST, ATT, ONE, MULTI>), grid, dim3(256), 0, s,
-                 static_cast<const T*>(fine), G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg,
+                 static_cast<const T*>(fine), G.nx, G.nz, G.n_off, G.legs, G.gunit, G.tau, G.base, G.P, G.K, qs, MQ, tpg,
                  t_off, batch, vpb, gbin, G.n_gamma - 1, accum, partial);
   else
     UMBIR_LAUNCH("gather", (k_gather<false, VPT, ST, ATT, ONE, MULTI>), grid, dim3(256), 0, s,
-                 static_cast<const T*>(fine), G.nx, G.nz, G.n_off, G.legs, G.tau, G.base, G.P, G.K, qs, MQ, tpg,
+                 static_cast<const T*>(fine), G.nx, G.nz, G.n_off, G.legs, G.gunit, G.tau, G.base, G.P, G.K, qs, MQ, tpg,
                  t_off, batch, vpb, gbin, G.n_gamma - 1, accum, partial);
 }
 

@@ -238,13 +238,18 @@ def make_requests(n: int, rate_hz: float, seed: int, mix=(("c1", 0.5), ("c2", 0.
     return out
 
 
-def synthesize(umbir, cards: Dict[str, Any], specs, device="cuda:0") -> List[Request]:
+def synthesize(umbir, cards: Dict[str, Any], specs, device="cuda:0", host_data=None) -> List[Request]:
     """Requests with data y = A x_true + sigma * noise made on the device (one
-    geometry per kind); sigma from the card's SNR."""
+    geometry per kind); sigma from the card's SNR.  With `host_data`
+    ({kind: (y [P][K][M], sigma)}) those data are copied to the device instead."""
     import torch
     from synth import phantom, noise
     data = {}
     for kind, card in cards.items():
+        if host_data is not None:
+            y, sigma = host_data[kind]
+            data[kind] = (torch.tensor(y, dtype=torch.float32, device=device), float(sigma))
+            continue
         g = umbir.build_geometry(card)
         xt = torch.tensor(phantom(card), dtype=torch.float32, device=device)
         clean = umbir.forward(g, xt)

@@ -270,7 +270,7 @@ class Geometry:
             TABLE_BANK: (np.float32, (self.n_gamma, self.oversample * self.window + 2)),
             TABLE_DBASIS: (np.float32, (P, K, M)),
             TABLE_OFFSET: (np.int32, (P + P * K,)),
-            TABLE_ATTEN: (np.int32, (self.nz, self.n_off)),
+            TABLE_ATTEN: (np.float64, (self.nz, self.n_off)),
         }[which]
         out = np.empty(spec[1], dtype=spec[0])
         _check(_lib.umbir_copy_table(self.handle, which, out.ctypes.data_as(C.c_void_p), out.nbytes),

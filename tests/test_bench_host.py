@@ -39,10 +39,26 @@ def test_kernel_work_of_the_workload(bench):
     # splat: leg table (256 rows x 654 records x 16 B), image, transmittances, fine grid
     fine = 512 * 2048 * 32 * 4
     assert bench.kernel_work("splat", card, 654, 8) == (float(256 * 654 * 16 + 4 * 65536 + 4 * 256 + fine), "hbm")
-    # gather: the same plus one partial image per trace group, minus the image
-    assert bench.kernel_work("gather", card, 654, 8) == (float(256 * 654 * 16 + 4 * 256 + fine + 4 * 65536 * 8),
-                                                         "hbm")
+    # gather: 4 MiB of one group's fine grid per launch = 16 of its 32 traces
+    # (16 groups of 32): two launches per adjoint; per launch half the fine
+    # grid, the leg table and transmittances, and the partial images written
+    # (first launch) or read and written (second): 3 images per group in all
+    assert bench.gather_launches(card, 16, 4096) == 2
+    w, b = bench.kernel_work("gather", card, 654, 16, 4096)
+    assert b == "hbm"
+    assert w == pytest.approx((fine + 2 * (256 * 654 * 16 + 4 * 256) + 3 * 16 * 4 * 65536) / 2)
+    assert 75e6 < w < 77e6
+    # 16-bit storage halves the fine grid per trace: one launch of 32 traces
+    assert bench.gather_launches(card, 16, 4096, elem=2) == 1
     assert bench.kernel_work("k_unknown", card, 654, 8) == (None, None)
+
+
+def test_operator_roofline(bench):
+    card = card_c2()
+    r = bench.operator_roofline(card, 0.5e-3, 512 * 65536)
+    # 2 L_h flop per triple per operator, two operators
+    assert r["flop_per_pair"] == 2 * 2 * 240 * 512 * 65536
+    assert r["frac_of_fp32"] == pytest.approx(r["flop_per_pair"] / 0.5e-3 / 157.3e12)
 
 
 def test_roofline_record(bench):

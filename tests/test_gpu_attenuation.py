@@ -46,18 +46,24 @@ def _cards():
 
 @pytest.mark.parametrize("name,card", _cards())
 def test_bins_and_leg_units(dev, name, card):
+    """Every leg's attenuation in template bins (Gamma_leg / dgamma, float64)
+    against the oracle's own ray solve, and no (trace, voxel) pair of the card
+    within 1e-9 bins of a tie between two templates (such a pair, reported
+    here, would be the only place where the two sides may pick different
+    templates; the parity tests below compare everything else)."""
     geom = umbir.build_geometry(card)
     assert geom.n_gamma == oa.n_bins(card)
     assert geom.gamma_step == pytest.approx(oa.step(card), rel=1e-12)
-    u = geom.table(umbir.TABLE_ATTEN).astype(np.int64)
+    u = geom.table(umbir.TABLE_ATTEN)
     depth = og.voxel_depths(card.grid)[:, None]
     X = np.arange(geom.n_off)[None, :] * card.grid.dx / 2
     _, _, att = og.leg(card.medium, depth + 0 * X, X + 0 * depth)
-    ref = oa.leg_units(att, oa.step(card))
-    diff = np.abs(u - ref)
-    print(f"{name}: G {geom.n_gamma}, leg units differing {int(np.count_nonzero(diff))} of {diff.size}")
-    assert diff.max() <= 1
-    assert np.count_nonzero(diff) <= diff.size // 1000
+    ref = att / oa.step(card)
+    err = float(np.max(np.abs(u - ref)))
+    ties = oa.near_ties(card, 1e-9)
+    print(f"{name}: G {geom.n_gamma}, max leg bin error {err:.2e}, pairs within 1e-9 of a tie: {ties}")
+    assert err <= 1e-11
+    assert ties == []
 
 
 @pytest.mark.parametrize("name,card", _cards()[:3])
@@ -127,8 +133,12 @@ def test_reconstruct_parity_attenuated(dev):
     xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
     ce = float(np.max(np.abs(cost.cpu().numpy() - co) / co))
     xe, ge = rel(x.cpu().numpy(), xo), rel(g.cpu().numpy(), go)
-    print(f"attenuated recon: cost {ce:.2e}, x {xe:.2e}, g {ge:.2e}")
-    assert ce <= 1e-5 and xe <= 1e-4 and ge <= 1e-5
+    # image bar from the size of the injected direct arrivals (see
+    # test_gpu_parity.direct_arrival_bar): the residual's FP32 rounding scales
+    # with ||y||, the fitted part with ||y - D g_true||
+    bar = max(TOL, 1e-6 * float(np.linalg.norm(y) / np.linalg.norm(y - oo.apply_direct(card, g_true))))
+    print(f"attenuated recon: cost {ce:.2e}, x {xe:.2e} (bar {bar:.2e}), g {ge:.2e}")
+    assert ce <= 1e-6 and xe <= bar and ge <= 1e-5
 
 
 def test_attenuated_session_and_batch_match_reconstruct(dev):

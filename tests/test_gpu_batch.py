@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from synth import card_c1, tiny_card, random_vector
+from oracle import data as odata, solver as osv
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +74,34 @@ def test_batch_equals_one_at_a_time(dev, mode):
     p = probs[2]
     x, g, cost = umbir.reconstruct(p["geom"], p["card"].prior, p["sigma"], p["y"], p["n_iter"])
     assert torch.equal(x, plain[2][0]) and torch.equal(cost, plain[2][2])
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_members_match_oracle(dev, mode):
+    """Every member of a batch of uneven problems (data synthesised by the
+    oracle) against the oracle's surrogate iteration for its own iteration
+    count: image within 1e-5 relative L2, cost history within 1e-6."""
+    cards = [dataclasses.replace(tiny_card(n_layers=3, nx=12, nz=10, n_scans=2, n_rx=3, n_samples=200), n_iter=7),
+             dataclasses.replace(tiny_card(n_layers=2, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300), n_iter=4),
+             dataclasses.replace(card_c1(), n_iter=10),
+             dataclasses.replace(tiny_card(n_layers=4, nx=20, nz=14, n_scans=3, n_rx=2, n_samples=256,
+                                           oversample=32), n_iter=6)]
+    data = [odata.synthesize(c)[1:] for c in cards]
+    probs = batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None, data=data)
+    _, batched, _ = batch.run_batched(umbir, probs, mode)
+    for c, (y, sigma), (x, g, cost) in zip(cards, data, batched):
+        xo, go, co = osv.sqs(c, y, sigma, c.prior, c.n_iter)
+        xe = rel(x.cpu().numpy(), xo)
+        ce = float(np.max(np.abs(cost.cpu().numpy() - co) / np.abs(co)))
+        print(f"{c.name} ({c.n_iter} iterations) in the batch: x {xe:.2e}, cost {ce:.2e}")
+        assert xe <= 1e-5 and ce <= 1e-6
+    for p in probs:
+        p["geom"].free()
 
 
 @pytest.mark.parametrize("mode", [0, 1])

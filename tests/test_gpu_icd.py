@@ -1,9 +1,11 @@
 """GPU parity of grouped ICD (umbir_reconstruct_icd) against the FP64 oracle's
 icd_grouped on the same seeded data: image, direct-arrival weights and cost
-history, element by element.  The data carry injected direct arrivals, which
-dominate y, so the FP32 residual after the g step is a difference of larger
-terms; tolerances are those of the surrogate solver on such data: image
-1e-4 relative L2, g and cost 1e-5."""
+history, element by element.  Every lattice runs on plain data (image bar
+1e-5 relative L2, cost 1e-6) and on data with injected direct arrivals, which
+dominate y: the FP32 residual after the g step is then a difference of larger
+terms, whose rounding grows with ||y|| / ||y - D g_true||; the image bar
+follows that ratio (max(1e-5, 1e-6 rho), the error model of the surrogate
+solver's tests), g 1e-5 and cost 1e-6."""
 import numpy as np
 import pytest
 
@@ -32,6 +34,7 @@ def t32(a, dev):
     return torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
 
 
+@pytest.mark.parametrize("direct", [False, True], ids=["plain", "direct"])
 @pytest.mark.parametrize("name,card,group,sweeps", [
     ("tiny3-2x2", tiny_card(n_layers=3), (2, 2), 3),
     ("tiny3-3x4", tiny_card(n_layers=3), (3, 4), 3),  # groups of unequal size
@@ -40,10 +43,14 @@ def t32(a, dev):
     ("c1-8x8", card_c1(), (8, 8), 1),
     ("tiny2-q64", tiny_card(n_layers=2, oversample=64, nx=10, nz=9), (2, 3), 2),
 ])
-def test_icd_parity(dev, name, card, group, sweeps):
+def test_icd_parity(dev, name, card, group, sweeps, direct):
     _, y, sigma = odata.synthesize(card)
-    g_true = np.linspace(-0.5, 0.9, card.n_traces).reshape(card.array.n_scans, card.array.n_rx)
-    y = y + oo.apply_direct(card, g_true)
+    bar = 1e-5
+    if direct:
+        g_true = np.linspace(-0.5, 0.9, card.n_traces).reshape(card.array.n_scans, card.array.n_rx)
+        y_plain = y
+        y = y + oo.apply_direct(card, g_true)
+        bar = max(1e-5, 1e-6 * float(np.linalg.norm(y) / np.linalg.norm(y_plain)))
     geom = umbir.build_geometry(card)
     x, g, cost = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), sweeps, group=group)
     xo, go, co, its = osv.icd_grouped(card, y, sigma, card.prior, sweeps, rows=group[0], cols=group[1],
@@ -51,14 +58,17 @@ def test_icd_parity(dev, name, card, group, sweeps):
     cost = cost.cpu().numpy()
     ce = float(np.max(np.abs(cost - co) / co))
     xe, ge = rel(x.cpu().numpy(), xo), rel(g.cpu().numpy(), go)
-    print(f"{name}: {sweeps} sweeps, cost {ce:.2e}, x {xe:.2e}, g {ge:.2e}; cost {co[0]:.4g} -> {co[-1]:.4g}")
-    assert ce <= 1e-5 and ge <= 1e-5 and xe <= 1e-4
+    print(f"{name}: {sweeps} sweeps, cost {ce:.2e}, x {xe:.2e} (bar {bar:.2e}), g {ge:.2e}; "
+          f"cost {co[0]:.4g} -> {co[-1]:.4g}")
+    assert ce <= 1e-6 and xe <= bar
+    if direct:  # without direct arrivals g only carries the noise's projection
+        assert ge <= 1e-5
     assert np.all(np.diff(cost) <= 1e-6 * np.abs(cost[:-1]))
     # one sweep, element by element
     x1, _, _ = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), 1, group=group)
     e1 = rel(x1.cpu().numpy(), its[0][0])
     print(f"{name}: one sweep x {e1:.2e}")
-    assert e1 <= 1e-4
+    assert e1 <= bar
 
 
 def test_icd_deterministic_and_resumable(dev):
@@ -104,7 +114,7 @@ def test_icd_without_direct_estimate(dev):
     xo, go, co = osv.icd_grouped(card, y, sigma, card.prior, 2, rows=2, cols=2, estimate_direct=False)
     assert torch.count_nonzero(g) == 0
     assert rel(x.cpu().numpy(), xo) <= 1e-5
-    assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-5
+    assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-6
 
 
 @pytest.mark.parametrize("kw,group", [
@@ -120,5 +130,5 @@ def test_icd_degenerate_grids(dev, kw, group):
     sigma = 0.01
     x, g, cost = umbir.reconstruct_icd(geom, card.prior, sigma, t32(y, dev), 2, group=group)
     xo, go, co = osv.icd_grouped(card, y, sigma, card.prior, 2, rows=group[0], cols=group[1])
-    assert rel(x.cpu().numpy(), xo) <= 1e-4
-    assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-5
+    assert rel(x.cpu().numpy(), xo) <= 1e-5
+    assert float(np.max(np.abs(cost.cpu().numpy() - co) / co)) <= 1e-6

@@ -17,6 +17,18 @@ umbir = pytest.importorskip("paper_2202_09703_amd.umbir")
 TOL = 1e-5
 
 
+def direct_arrival_bar(y_with, y_without):
+    """Image bar on data with injected direct arrivals.  The FP32 residual
+    e = y - A x - D g rounds every sample at about u |y|, so its rounding error
+    grows with the size of the data it is formed from, while the part the image
+    is fitted to (y without the direct arrivals) does not.  Without direct
+    arrivals the surrogate iteration holds the image within 1e-6 of the oracle
+    (measured 1e-7 to 3e-7); injected arrivals scale that rounding by
+    rho = ||y_with|| / ||y_without||, so the bar is max(1e-5, 1e-6 rho)."""
+    rho = float(np.linalg.norm(y_with) / np.linalg.norm(y_without))
+    return max(TOL, 1e-6 * rho)
+
+
 @pytest.fixture(scope="module")
 def dev():
     if not torch.cuda.is_available():
@@ -179,8 +191,8 @@ def test_reconstruct_parity_c1(dev):
     xe = rel(x.cpu().numpy(), xo)
     ge = rel(g.cpu().numpy(), go) if np.linalg.norm(go) > 0 else float(np.max(np.abs(g.cpu().numpy())))
     print(f"c1 recon: max cost rel err {ce:.2e}, x rel L2 {xe:.2e}, g err {ge:.2e}")
-    assert ce <= 1e-5
-    assert xe <= 1e-4
+    assert ce <= 1e-6
+    assert xe <= 1e-5
     # monotone within float32 rounding
     assert np.all(np.diff(cost) <= 1e-6 * np.abs(cost[:-1]))
     # one iteration, element by element
@@ -209,9 +221,12 @@ def test_reconstruct_with_direct_arrivals(dev):
     geom = umbir.build_geometry(card)
     x, g, cost = umbir.reconstruct(geom, card.prior, sigma, t32(y, dev), 8)
     xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
+    bar = direct_arrival_bar(y, y - oo.apply_direct(card, g_true))
+    xe = rel(x.cpu().numpy(), xo)
+    print(f"recon with direct arrivals: x rel L2 {xe:.2e} (bar {bar:.2e})")
     assert rel(g.cpu().numpy(), go) <= 1e-5
-    assert rel(x.cpu().numpy(), xo) <= 1e-4
-    assert np.max(np.abs(cost.cpu().numpy() - co) / co) <= 1e-5
+    assert xe <= bar
+    assert np.max(np.abs(cost.cpu().numpy() - co) / co) <= 1e-6
 
 
 # ---- full-size plain FP32 workload (256x256, 32 x 16 traces, 2048 samples): sampled outputs
@@ -305,7 +320,8 @@ def test_solver_session_warm_start_and_direct(dev):
     assert torch.equal(xs, x8) and torch.equal(gs, g8)
     assert torch.equal(cs, c8[4:])
     xo, go, co = osv.sqs(card, y, sigma, card.prior, 8)
-    assert rel(xs.cpu().numpy(), xo) <= 1e-4
+    g_true = np.array([[0.5, -0.3, 0.8], [0.2, 0.9, -0.4]])
+    assert rel(xs.cpu().numpy(), xo) <= direct_arrival_bar(y, y - oo.apply_direct(card, g_true))
 
 
 # ---- full-size 512x512 four-layer workload (2048 traces, 4096 samples): sampled outputs
@@ -339,3 +355,68 @@ def test_c3_forward_and_adjoint_sampled(dev, c3geom):
     ax = umbir.forward(geom, t32(xr, dev)).cpu().numpy().astype(np.float64)
     lhs, rhs = float(np.sum(ax * r)), float(np.sum(xr.reshape(-1) * xa))
     assert abs(lhs - rhs) <= TOL * np.linalg.norm(ax) * np.linalg.norm(r)
+
+
+def test_c3_full_size_solver(dev, c3geom):
+    card, geom = c3geom
+    _full_size_solver_case(dev, card, geom, "c3", 8, 81)
+
+
+# ---- full-size solver parity: curvature, one whole iteration, a whole scan
+# position of the forward and a large voxel sample of the adjoint, against the
+# oracle on all host cores (and, for the curvature, which needs Abar 1 over
+# every voxel of every trace, against oracle values stored by
+# tests/golden/make_full_size_samples.py)
+
+
+def _golden(key):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "full_size_samples.json")
+    doc = json.load(open(path))
+    if key not in doc:
+        pytest.skip(f"no stored oracle samples for {key}")
+    return np.array(doc[key]["voxels"], np.int64), np.array(doc[key]["abs_normal"])
+
+
+def _full_size_solver_case(dev, card, geom, key, n_traces, seed):
+    """d at the stored voxel samples; one reconstruct iteration from x = 0 on
+    seeded data with injected direct arrivals (x^1 at the samples, g^1 in
+    full, cost C(0, 0)); the forward of the given traces; the adjoint at the
+    samples (all on every host core)."""
+    vox, dstore = _golden(key)
+    sigma = 0.05
+    d = umbir.sqs_denominator(geom, sigma).cpu().numpy().reshape(-1)
+    de = rel(d[vox], dstore / sigma ** 2)
+    print(f"{key}: curvature at {len(vox)} voxels rel L2 {de:.2e}")
+    assert de <= TOL
+    a = card.array
+    g_true = np.linspace(-0.4, 0.6, card.n_traces).reshape(a.n_scans, a.n_rx)
+    y = 0.3 * random_vector(geom.trace_shape, seed=seed) + oo.apply_direct(card, g_true)
+    x1, g1, c1 = umbir.reconstruct(geom, card.prior, sigma, t32(y, dev), 1)
+    xo, go, co = osv.first_step_voxels(card, y, sigma, card.prior, vox, dstore / sigma ** 2, workers=None)
+    xe = rel(x1.cpu().numpy().reshape(-1)[vox], xo)
+    ge = rel(g1.cpu().numpy(), go)
+    ce = abs(float(c1.cpu().numpy()[0]) - co) / co
+    print(f"{key}: one iteration x^1 at {len(vox)} voxels {xe:.2e}, g^1 {ge:.2e}, cost[0] {ce:.2e}")
+    assert xe <= TOL and ge <= TOL and ce <= 1e-6
+    # the forward over whole receivers' traces of one scan position
+    x = phantom(card)
+    yf = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+    i = a.n_scans // 3
+    traces = [(i, j) for j in range(min(n_traces, a.n_rx))]
+    ref = oo.forward(card, x, traces=traces, workers=None)
+    fe = rel(yf[i, :len(traces)], ref[i, :len(traces)])
+    print(f"{key}: forward over scan position {i}, {len(traces)} traces, rel L2 {fe:.2e}")
+    assert fe <= TOL
+    # the adjoint at the voxel samples
+    r = random_vector(geom.trace_shape, seed=seed + 1)
+    xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy().reshape(-1)
+    ae = rel(xa[vox], oo.adjoint_voxels(card, r, vox, workers=None))
+    print(f"{key}: adjoint at {len(vox)} voxels rel L2 {ae:.2e}")
+    assert ae <= TOL
+
+
+def test_c2_full_size_solver(dev, c2geom):
+    card, geom = c2geom
+    _full_size_solver_case(dev, card, geom, "c2", 16, 71)

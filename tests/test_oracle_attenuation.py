@@ -94,10 +94,12 @@ def test_no_attenuation_is_one_template():
 @pytest.mark.parametrize("g", [2, 5, 16, 64])
 def test_bins_are_nearest(g):
     """Every (trace, voxel) lands in the bin nearest its exact gamma (the sum of
-    its two legs as trace_geometry returns it), within the 2^-24 rounding of
-    the leg units; 2 Gamma_max bounds every gamma and is nearly reached."""
+    its two legs as trace_geometry returns it): the same index as a brute-force
+    search over all G template attenuations, |gamma - gamma_bin| <= dgamma / 2;
+    2 Gamma_max bounds every gamma and is nearly reached."""
     card = attenuated_card(n_gamma=g)
     step = attenuation.step(card)
+    grid_g = np.arange(g) * step
     top = 0.0
     for i in range(card.array.n_scans):
         for j in range(card.array.n_rx):
@@ -105,10 +107,25 @@ def test_bins_are_nearest(g):
             _, _, legs = geometry.trace_geometry(card, i, j, legs=True)
             b = attenuation.bins_of(legs, step, g)
             assert b.min() >= 0 and b.max() <= g - 1
-            assert np.all(np.abs(gamma - b * step) <= step * (0.5 + 2.0 ** -23))
+            brute = np.argmin(np.abs(gamma[:, None] - grid_g[None, :]), axis=1)
+            clear = attenuation.tie_distance(legs, step) > 1e-9
+            assert np.array_equal(b[clear], brute[clear])
+            assert np.all(np.abs(gamma - b * step) <= step * (0.5 + 1e-12))
             assert np.all(gamma <= (g - 1) * step * (1 + 1e-12))
             top = max(top, float(np.max(np.maximum(legs[0], legs[1]))))
     assert top == pytest.approx(attenuation.max_leg(card), rel=1e-12)
+
+
+def test_near_ties_finds_planted_tie():
+    """near_ties() names a pair whose gamma sits on a half-integer of bins: a
+    card whose dgamma is chosen so (the two legs of one pair summed) that it
+    does; none on the stock attenuated card."""
+    card = attenuated_card(n_gamma=16)
+    assert attenuation.near_ties(card) == []
+    legs = (np.array([0.3, 0.25]), np.array([0.45, 0.1]))
+    d = attenuation.tie_distance(legs, 0.5)  # gamma / dgamma = 1.5 and 0.7
+    assert d[0] == pytest.approx(0.0, abs=1e-15) and d[1] == pytest.approx(0.2)
+    assert list(attenuation.bins_of(legs, 0.5, 16)) == [2, 1]
 
 
 def test_max_leg_is_largest_over_rows_and_offsets():

@@ -136,3 +136,33 @@ def test_resume_equals_continuous_run():
     x2, g2, c2 = solver.sqs(card, y, sigma, pr, 10, x0=x10, g0=g10)
     np.testing.assert_allclose(x2, x20, rtol=0, atol=1e-13 * np.max(np.abs(x20)))
     np.testing.assert_allclose(c2, c20[10:], rtol=1e-13)
+
+
+def test_sampled_curvature_and_first_step_equal_the_full_ones():
+    """The voxel-sampled curvature and first iteration used at full size are
+    the full-image ones restricted to the samples (on a small card, on two
+    worker processes)."""
+    from synth import tiny_card
+    card = tiny_card(n_layers=3, nx=12, nz=10, n_scans=2, n_rx=3, n_samples=200)
+    _, y, sigma = data.synthesize(card)
+    y = y + operator.apply_direct(card, np.array([[0.5, -0.3, 0.8], [0.2, 0.9, -0.4]]))
+    vox = np.array([0, 7, 33, 64, 119])
+    dfull = solver.sqs_denominator(card, sigma).reshape(-1)
+    dvox = solver.sqs_denominator_voxels(card, sigma, vox, workers=2)
+    np.testing.assert_allclose(dvox, dfull[vox], rtol=1e-13)
+    x1, g1, c = solver.sqs(card, y, sigma, card.prior, 1)
+    xs, gs, c0 = solver.first_step_voxels(card, y, sigma, card.prior, vox, dvox, workers=2)
+    np.testing.assert_allclose(xs, x1.reshape(-1)[vox], rtol=1e-12, atol=1e-15 * np.abs(x1).max())
+    np.testing.assert_allclose(gs, g1, rtol=1e-12)
+    assert c0 == pytest.approx(c[0], rel=1e-13)
+
+
+def test_multicore_operator_equals_single_core():
+    from synth import tiny_card, random_vector
+    card = tiny_card(n_layers=3, nx=12, nz=10, n_scans=3, n_rx=3, n_samples=200)
+    x = random_vector((card.grid.nz, card.grid.nx), seed=5)
+    r = random_vector((3, 3, 200), seed=6)
+    np.testing.assert_array_equal(operator.forward(card, x, workers=3), operator.forward(card, x))
+    vox = np.arange(card.n_voxels)
+    np.testing.assert_allclose(operator.adjoint_voxels(card, r, vox, workers=4),
+                               operator.adjoint_voxels(card, r, vox), rtol=1e-13, atol=1e-15)
