@@ -212,6 +212,24 @@ int umbir_reconstruct(const umbir_geometry* geom, const umbir_prior* prior,
                       const void* y_dev, int n_iter, float* x_io_dev, float* g_io_dev,
                       double* cost_dev, void* work, size_t work_bytes, void* stream);
 
+/* umbir_reconstruct for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same iteration, arguments and results (bitwise), with the
+ * workspace taken from a static device array of UMBIR_NOALLOC_SCRATCH_MIB MiB
+ * that the library holds on each GPU it runs on until the process ends, in
+ * place of a caller buffer.  The call allocates and frees nothing.  Every call
+ * on one GPU shares that GPU's array (no clearing is needed: each call writes
+ * every part of it before reading it), so calls whose work may overlap on one
+ * GPU (other streams, other threads) race and must not be made.  The
+ * geometry's device must be current.
+ * Errors: EINVAL (arguments, prior, wrong device), ENOTSUP (the problem needs
+ * more than the scratch holds: umbir_workspace_bytes(geom,
+ * UMBIR_WORK_RECONSTRUCT) > UMBIR_NOALLOC_SCRATCH_MIB MiB; the plain
+ * 256 x 256 workload needs 137 MiB), EDEVICE. */
+#define UMBIR_NOALLOC_SCRATCH_MIB 160
+int umbir_reconstruct_noalloc(const umbir_geometry* geom, const umbir_prior* prior, const void* y_dev,
+                              int n_iter, float* x_io_dev, float* g_io_dev, double* cost_dev, void* stream);
+
 /* MAP reconstruction of Eq. (18) by ICD (Sec. 2, "Optimization") run over a
  * lattice of voxel groups.  Group (a, b), a < group_rows, b < group_cols,
  * holds the voxels with row % group_rows == a and col % group_cols == b

@@ -25,6 +25,8 @@
 
 #include <cmath>
 
+#include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -778,9 +780,62 @@ int batch_graph(umbir_batch* B, int which, hipGraphExec_t* out) {
   return st;
 }
 
+// Scratch of umbir_reconstruct_noalloc: a static device array, one copy per
+// GPU, held from the library's load on that GPU until the process ends.  Host
+// code never names it except to look up its address: on the host the name is
+// only a stand-in, so kernels and copies take the per-device address below.
+constexpr size_t kNoallocBytes = size_t(UMBIR_NOALLOC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};  // device address of `scratch` per device
+
+// The current device's copy of the scratch, looked up once per device (with
+// that device current) and kept.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  int st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (st) return st;
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(UMBIR_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return st;
+    if (!p) return fail(UMBIR_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return UMBIR_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int umbir_reconstruct_noalloc(const umbir_geometry* G, const umbir_prior* pr, const void* y, int n_iter,
+                              float* x_io, float* g_io, double* cost, void* stream) {
+  if (!G || !y || !x_io || !g_io) return fail(UMBIR_EINVAL, "NULL argument");
+  if (n_iter < 0) return fail(UMBIR_EINVAL, "n_iter must be >= 0");
+  int st = validate_prior(pr);
+  if (st) return st;
+  const size_t need = umbir_workspace_bytes(G, UMBIR_WORK_RECONSTRUCT);
+  if (need > kNoallocBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "umbir_reconstruct_noalloc: the problem needs %zu bytes of scratch, the static scratch holds %zu",
+                  need, kNoallocBytes);
+    return fail(UMBIR_ENOTSUP, msg);
+  }
+  int dev = -1;
+  if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice"))) return st;
+  if (dev != G->device) return fail(UMBIR_EINVAL, "the geometry's device must be current");
+  void* work = nullptr;
+  if ((st = noalloc_scratch(&work))) return st;
+  // the iteration needs nothing of the scratch to start at zero: every
+  // buffer carved from it is written before it is read
+  return umbir_reconstruct(G, pr, y, n_iter, x_io, g_io, cost, work, kNoallocBytes, stream);
+}
 
 int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const void* y, int n_iter,
                       float* x_io, float* g_io, double* cost, void* work, size_t work_bytes, void* stream) {

@@ -99,6 +99,7 @@ _SIGS = {
     "umbir_direct": (_i, [_vp, _vp, _vp, _i, _vp]),
     "umbir_sqs_denominator": (_i, [_vp, C.c_double, _vp, _vp, _sz, _vp]),
     "umbir_reconstruct": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "umbir_reconstruct_noalloc": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _vp, _vp, _vp, _vp]),
     "umbir_reconstruct_icd": (_i, [_vp, C.POINTER(_Prior), _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "umbir_icd_workspace_bytes": (_sz, [_vp, _i, _i]),
     "umbir_get_dims": (_i, [_vp, C.POINTER(_Dims)]),
@@ -376,6 +377,25 @@ def reconstruct(geom: Geometry, prior, sigma: float, y, n_iter: int, x=None, g=N
                                   _ptr(g, "g", geom.trace_shape[:2], torch.float32),
                                   _ptr(cost, "cost", (n_iter + 1,), torch.float64), wp, wb,
                                   _stream(stream)), "umbir_reconstruct")
+    return x, g, cost
+
+
+NOALLOC_SCRATCH_BYTES = 160 << 20  # UMBIR_NOALLOC_SCRATCH_MIB
+
+
+def reconstruct_noalloc(geom: Geometry, prior, sigma: float, y, n_iter: int, x, g, cost, stream=None):
+    """umbir_reconstruct_noalloc: as reconstruct, with the library's static
+    device scratch as workspace; x, g (warm start, updated in place) and cost
+    (float64, n_iter + 1 entries) are the caller's tensors (the call itself
+    allocates nothing)."""
+    import torch
+    pr = make_prior(prior, sigma)
+    _check(_lib.umbir_reconstruct_noalloc(geom.handle, C.byref(pr),
+                                          _ptr(y, "y", geom.trace_shape, geom.trace_dtype), int(n_iter),
+                                          _ptr(x, "x", geom.image_shape, torch.float32),
+                                          _ptr(g, "g", geom.trace_shape[:2], torch.float32),
+                                          _ptr(cost, "cost", (n_iter + 1,), torch.float64),
+                                          _stream(stream)), "umbir_reconstruct_noalloc")
     return x, g, cost
 
 
