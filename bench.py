@@ -299,7 +299,8 @@ def precision_section(umbir, torch, dev, with_parity):
 def batch_section(umbir, torch, dev):
     """48 seeded uneven problems (128^2 to 384^2, 3-4 layers, 8-32 receivers,
     1024-4096 samples, 20-50 iterations): one at a time against the batched
-    path, both autotuned; results bitwise equal."""
+    paths (sessions' graphs on four streams; work-list launches per stage over
+    four lanes of problems), all autotuned; results bitwise equal."""
     from paper_2202_09703_amd import batch
     from synth import batch_cards
     cards = batch_cards(48, 11)
@@ -310,7 +311,9 @@ def batch_section(umbir, torch, dev):
     batch.run_plain(umbir, probs)  # warm
     t_plain, plain = batch.run_plain(umbir, probs)
     t_batch, batched, rebuilds = batch.run_batched(umbir, probs, umbir.BATCH_STREAMS)
-    same = all(torch.equal(a[0], b[0]) and torch.equal(a[2], b[2]) for a, b in zip(plain, batched))
+    t_wl, wl, _ = batch.run_batched(umbir, probs, umbir.BATCH_WORKLIST)
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[2], b[2]) and torch.equal(a[0], c[0])
+               and torch.equal(a[2], c[2]) for a, b, c in zip(plain, batched, wl))
     work = batch.evals(probs)
     for p in probs:
         p["geom"].free()
@@ -318,7 +321,8 @@ def batch_section(umbir, torch, dev):
             "plain_s": t_plain, "batched_s": t_batch, "recon_per_s_plain": len(cards) / t_plain,
             "recon_per_s_batched": len(cards) / t_batch, "speedup": t_plain / t_batch,
             "evals_per_s_plain": work / t_plain, "evals_per_s_batched": work / t_batch,
-            "batches": rebuilds, "bitwise_equal_to_plain": bool(same)}
+            "batches": rebuilds, "worklist_s": t_wl, "recon_per_s_worklist": len(cards) / t_wl,
+            "speedup_worklist": t_plain / t_wl, "bitwise_equal_to_plain": bool(same)}
 
 
 def cpu_baseline_section(card):

@@ -285,23 +285,40 @@ size_t umbir_solver_state_bytes(const umbir_solver* solver);
 void umbir_solver_free(umbir_solver* solver);
 
 /* Batched sessions, for many problems at once (of any mix of shapes): one
- * call advances every session of the batch, and the problems run side by
- * side on four internal streams (session i on stream i mod 4), forked from
- * and joined back to the caller's stream.  UMBIR_BATCH_STREAMS launches each
- * session's own captured iteration graph on its stream; UMBIR_BATCH_GRAPH
- * replays one graph per iteration that was captured once across the four
- * streams (one chain of sessions per stream) and holds every session's
- * iteration.  Each session's results are bitwise those of stepping it alone.
- * The
+ * call advances every session of the batch.
+ *  UMBIR_BATCH_STREAMS     the problems run side by side on four internal
+ *                          streams (session i on stream i mod 4), forked from
+ *                          and joined back to the caller's stream, each
+ *                          session's own captured iteration graph on its stream;
+ *  UMBIR_BATCH_GRAPH       one graph per iteration, captured once across the
+ *                          four streams (one chain of sessions per stream),
+ *                          holding every session's iteration;
+ *  UMBIR_BATCH_WORKLIST    the problems split into four lanes of about equal
+ *                          work, one per internal stream; per lane one launch
+ *                          per stage of the iteration (image prescale, splat,
+ *                          convolution with the residual, g step, correlation,
+ *                          gather (one launch per batch of traces), prior
+ *                          update, cost) over all its problems together: the
+ *                          blocks of a launch walk a device work list of
+ *                          (problem, tile) items of the uneven problems, and
+ *                          the lanes' launches of one iteration are one
+ *                          captured graph.  Needs FP32 storage, no attenuation
+ *                          and one oversampling factor (32 or 64) across the
+ *                          batch (ENOTSUP otherwise).
+ *                          A session that reaches its max_iter leaves the
+ *                          batch (its items are skipped from the next
+ *                          iteration on), so one batch can be stepped to the
+ *                          largest max_iter of its sessions.
+ * Each session's results are bitwise those of stepping it alone.  The
  * sessions must outlive the batch, must all live on the current device, and
  * may appear once each.  While in a batch a session may be read
  * (umbir_solver_read) but must not be stepped alone: umbir_batch_step returns
- * EINVAL if any session's iteration count no longer matches the batch, or if
- * a step would pass a session's max_iter.  umbir_batch_free (like
+ * EINVAL if any session's iteration count no longer matches the batch, or
+ * (streams and graph modes) if a step would pass a session's max_iter.  umbir_batch_free (like
  * umbir_solver_free) first waits for the last launch it queued to end.
- * Errors: EINVAL, ENOMEM, EDEVICE. */
+ * Errors: EINVAL, ENOMEM, ENOTSUP, EDEVICE. */
 typedef struct umbir_batch umbir_batch;
-enum { UMBIR_BATCH_STREAMS = 0, UMBIR_BATCH_GRAPH = 1 };
+enum { UMBIR_BATCH_STREAMS = 0, UMBIR_BATCH_GRAPH = 1, UMBIR_BATCH_WORKLIST = 2 };
 int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_batch** out);
 int umbir_batch_step(umbir_batch* batch, int n_iter, void* stream);
 void umbir_batch_free(umbir_batch* batch);
@@ -320,8 +337,8 @@ typedef struct {
 } umbir_dims;
 int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
 
-/* Launch shapes of the sweeps, tunable per problem shape.  Neither changes a
- * result beyond rounding order, nor any memory size:
+/* Launch and tile shapes of the sweeps, tunable per problem shape.  None
+ * changes a result beyond rounding order, nor any memory size:
  *  splat_blocks     target workgroup count of the splat: the fine grid of each
  *                   trace is cut into ceil(splat_blocks / traces) chunks of at
  *                   least 1024 positions.  Results are bitwise identical for
@@ -329,16 +346,29 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *  gather_batch_kb  fine-grid KiB of each trace group per gather launch (at
  *                   least one trace per launch).  Changes only the order of
  *                   the adjoint's sums across launches.
- * A field of 0 (or less) in umbir_set_tuning keeps the current value.  The
- * tuning of a geometry must not change while another call uses it.
+ *  conv_grid        tile order of the matrix-core convolution (32 samples x
+ *                   32 traces per workgroup): 1 trace tiles fastest, 2 sample
+ *                   tiles fastest.  Bitwise identical results.
+ *  corr_tile_rows   rows (output samples) of one wave's tile in the
+ *                   matrix-core correlation: 32, 64 or 128 (a workgroup of
+ *                   four waves covers four tiles).  Bitwise identical results.
+ *  corr_blocks      target workgroup count of the correlation: each workgroup
+ *                   walks ceil(traces x row blocks / corr_blocks) row blocks of
+ *                   one trace with the taps staged once.  Bitwise identical.
+ * A field of 0 (or less) in umbir_set_tuning keeps the current value (EINVAL
+ * for a conv_grid or corr_tile_rows outside the values above).  The tuning of
+ * a geometry must not change while another call uses it.
  * umbir_autotune times candidates of each field on `stream` (the forward for
- * the splat, the adjoint for the gather, a dense all-ones image), applies the
- * fastest and writes the chosen values to *chosen (may be NULL); it allocates
- * its own workspace and synchronizes the stream.  Errors: EINVAL, ENOMEM,
- * EDEVICE. */
+ * the splat and the convolution, the adjoint for the correlation and the
+ * gather, a dense all-ones image), applies the fastest and writes the chosen
+ * values to *chosen (may be NULL); it allocates its own workspace and
+ * synchronizes the stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
 typedef struct {
     int splat_blocks;
     int gather_batch_kb;
+    int conv_grid;
+    int corr_tile_rows;
+    int corr_blocks;
 } umbir_tuning;
 int umbir_get_tuning(const umbir_geometry* geom, umbir_tuning* out);
 int umbir_set_tuning(umbir_geometry* geom, const umbir_tuning* tuning);

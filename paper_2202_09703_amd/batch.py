@@ -82,13 +82,21 @@ def run_plain(umbir, probs):
 def run_batched(umbir, probs, mode: int = 0):
     """All unfinished sessions advanced together by umbir_batch_step (mode
     BATCH_STREAMS: each session's graphs on four streams; BATCH_GRAPH: one
-    graph per iteration captured across them)."""
+    graph per iteration captured across them; BATCH_WORKLIST: per lane of
+    problems one launch per stage of the iteration over all its problems'
+    work items, one batch stepped to the largest iteration count, problems
+    leaving as they reach theirs)."""
     import torch
     ss = sessions(umbir, probs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     live = list(range(len(ss)))
     batches = []  # kept until the device is done with them
+    if mode == umbir.BATCH_WORKLIST:
+        b = umbir.Batch(ss, mode)
+        b.step(max(p["n_iter"] for p in probs))
+        batches.append(b)
+        live = []
     while live:
         k = min(probs[i]["n_iter"] - ss[i].iterations for i in live)
         b = umbir.Batch([ss[i] for i in live], mode)
@@ -153,14 +161,19 @@ def main():
     print(f"batched (streams), tuned: {t_batch:.3f} s ({rebuilds} batches)", flush=True)
     t_graph, graphed, _ = run_batched(umbir, probs, umbir.BATCH_GRAPH)
     print(f"batched (one graph per iteration), tuned: {t_graph:.3f} s", flush=True)
+    t_wl, wl, _ = run_batched(umbir, probs, umbir.BATCH_WORKLIST)
+    print(f"batched (work lists), tuned: {t_wl:.3f} s", flush=True)
     same = all(torch.equal(a[0], b[0]) and torch.equal(a[2], b[2]) and torch.equal(a[0], c[0])
-               and torch.equal(a[2], c[2]) for a, b, c in zip(plain, batched, graphed))
+               and torch.equal(a[2], c[2]) and torch.equal(a[0], d[0]) and torch.equal(a[2], d[2])
+               for a, b, c, d in zip(plain, batched, graphed, wl))
     res = {"problems": len(probs), "iterations": sum(p["n_iter"] for p in probs),
            "evals": work, "plain_default_s": t_default, "plain_tuned_s": t_plain, "batched_s": t_batch,
            "evals_per_s_plain": work / t_plain, "evals_per_s_batched": work / t_batch,
            "recon_per_s_plain": len(probs) / t_plain, "recon_per_s_batched": len(probs) / t_batch,
            "speedup": t_plain / t_batch, "batches": rebuilds, "batched_graph_s": t_graph,
-           "speedup_graph": t_plain / t_graph, "bitwise_equal": bool(same),
+           "speedup_graph": t_plain / t_graph, "batched_worklist_s": t_wl,
+           "speedup_worklist": t_plain / t_wl, "recon_per_s_worklist": len(probs) / t_wl,
+           "bitwise_equal": bool(same),
            "shapes_tuned": len(cache),
            "tuning": {c.name: t for c, t in zip(cards, chosen)}}
     print(json.dumps(res), flush=True)

@@ -718,13 +718,22 @@ int umbir_get_tuning(const umbir_geometry* G, umbir_tuning* out) {
   if (!G || !out) return fail(UMBIR_EINVAL, "NULL argument");
   out->splat_blocks = G->splat_blocks;
   out->gather_batch_kb = G->gather_batch_kb;
+  out->conv_grid = G->conv_grid;
+  out->corr_tile_rows = 32 * G->corr_tiles;
+  out->corr_blocks = G->corr_blocks;
   return UMBIR_OK;
 }
 
 int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (!G || !t) return fail(UMBIR_EINVAL, "NULL argument");
+  if (t->conv_grid > 2) return fail(UMBIR_EINVAL, "conv_grid must be 1 or 2");
+  if (t->corr_tile_rows > 0 && t->corr_tile_rows != 32 && t->corr_tile_rows != 64 && t->corr_tile_rows != 128)
+    return fail(UMBIR_EINVAL, "corr_tile_rows must be 32, 64 or 128");
   if (t->splat_blocks > 0) apply_splat_blocks(G, t->splat_blocks);
   if (t->gather_batch_kb > 0) G->gather_batch_kb = t->gather_batch_kb;
+  if (t->conv_grid > 0) G->conv_grid = t->conv_grid;
+  if (t->corr_tile_rows > 0) G->corr_tiles = t->corr_tile_rows / 32;
+  if (t->corr_blocks > 0) G->corr_blocks = t->corr_blocks;
   return UMBIR_OK;
 }
 

@@ -48,6 +48,25 @@ __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >>
 // splat, which takes the largest (no atomic, nothing to clear first).
 constexpr int kPrescaleBlocks = 128;
 
+// Row ranges of the layers the grid reaches: rows [lo[s], hi[s]) of layer
+// segment s, for the n segments the grid reaches.
+struct Segments {
+  int n;
+  int lo[kMaxLayers];
+  int hi[kMaxLayers];
+};
+
+// Constants of the QGGMRF prior update (Eqs. (15)-(17)) and the noise level.
+struct PriorConst {
+  float inv_sigma2;
+  float p;
+  float T;
+  float T_pm2;  // T^(p - 2)
+  float sigma0;
+  double m, a;
+  double z0, dz;
+};
+
 // Planar layer stack passed to kernels by value.  top/bottom are depths of
 // each layer's faces; the last bottom is +inf.
 struct Layers {
@@ -144,6 +163,9 @@ struct umbir_geometry {
   // tunable launch shapes (umbir_tuning)
   int splat_blocks = 512;      // target splat workgroups; sets chunks, chunk_bins, tile_bins
   int gather_batch_kb = 4096;  // fine-grid KiB per trace group per gather launch
+  int conv_grid = 1;           // matrix-core convolution grid: 1 trace tiles fastest, 2 sample tiles fastest
+  int corr_tiles = 2;          // 32-row tiles per wave of the matrix-core correlation (1, 2 or 4)
+  int corr_blocks = 1024;      // target workgroups of the correlation (sets row blocks per workgroup)
   // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)
   int n_gamma = 1;
   double gamma_step = 0.0;
@@ -223,5 +245,71 @@ constexpr int kPriorVox = 64;
 
 size_t forward_work_bytes(const umbir_geometry& G);
 size_t adjoint_work_bytes(const umbir_geometry& G);
+
+// ---- work-list batches: one launch per stage of a surrogate iteration for
+// many problems at once, each block walking a work list of items
+// (problem, block index x, block index y of that problem's own launch).
+
+// One problem of a work-list batch (FP32 storage, one template, Q = 32 or
+// 64): what every stage of its iteration reads, set from its geometry and
+// its session's buffers.
+struct BatchProb {
+  // geometry
+  const Leg* legs;
+  const int* base;
+  const float* tau;
+  const float* h;       // polyphase taps [Lh][Q]
+  const float* dbasis;  // [P K][M]
+  const float* dnorm;   // [P K]
+  int nx, nz, n_off, P, K, M, Q, qs, Lh, MQ;
+  Segments seg;
+  // launch shapes of the sweeps
+  int prescale_blocks;
+  int chunk_bins, tile_bins, wide;  // splat
+  int corr_per;                     // row blocks per correlation block
+  int groups, tpg, gbatch, vpb;     // gather: trace groups, traces per group and launch, voxels per block
+  int nblk;                         // prior-update blocks
+  // session state
+  const float* y;
+  float* e;
+  float* fine;
+  float* xt;
+  unsigned* xmax;
+  float* partial;
+  float* den;
+  double* ess;
+  double* pcost;
+  float* x[2];  // the image before the batch's step 0, and the other buffer
+  float* g;
+  double* cost;
+  int* counter;
+  PriorConst pc;
+  double inv_2s2;
+  int est;
+};
+
+// Stages of one iteration, in launch order.
+enum BatchStage { kStPrescale = 0, kStSplat, kStConv, kStGstep, kStCorr, kStGather, kStPrior, kStCost, kStages };
+
+// A stage's launch: its items, grid (blocks walk the items with a stride of
+// the grid) and dynamic LDS bytes.
+struct StageLaunch {
+  const int4* items = nullptr;
+  int n_items = 0;
+  int grid = 0;
+  size_t lds = 0;
+};
+
+// Fills the sweep fields of bp from G (the launch shapes of the plain path)
+// and appends problem pi's items of the sweep stages (prescale, splat, conv,
+// corr, gather) to items[stage]; lds[stage] grows to what the problem needs.
+// Gather items carry the index of their launch (batch of traces) in .w.
+void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int4>* items, size_t* lds);
+
+// Launches one sweep stage over the batch; `which` selects the input image
+// of the prescale (probs[i].x[which]); items of problem i run only while
+// active[i] is nonzero.
+int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* active, const StageLaunch& L, int which,
+                       hipStream_t s);
 
 }  // namespace umbir

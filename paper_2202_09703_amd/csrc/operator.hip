@@ -46,23 +46,16 @@ __global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, size_
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += stride) d[k] = s[k];
 }
 
-// Row ranges of the layers the grid reaches, passed by value.
-struct Segments {
-  int n;
-  int lo[kMaxLayers];
-  int hi[kMaxLayers];
-};
-
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // The splat's input image with the row transmittance folded in, xt = tau x
 // (x == NULL means x = 1), and per block the largest |xt| as float bits
 // (non-negative floats order like their bits) for the fixed-point scale of
 // the splat: out[blockIdx.x], gridDim.x <= kPrescaleBlocks.
-__global__ void k_prescale(const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
+__device__ __forceinline__ void prescale_body(int bx, int gx, const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
                            float* __restrict__ xt, unsigned* __restrict__ out) {
   unsigned m = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int i = bx * blockDim.x + threadIdx.x; i < n; i += gx * blockDim.x) {
     const float v = tau[i / nx] * (x ? x[i] : 1.0f);
     xt[i] = v;
     m = max(m, __float_as_uint(fabsf(v)));
@@ -73,8 +66,13 @@ __global__ void k_prescale(const float* __restrict__ x, const float* __restrict_
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < int(blockDim.x >> 6); ++w) m = max(m, wmax[w]);
-    out[blockIdx.x] = m;
+    out[bx] = m;
   }
+}
+
+__global__ void k_prescale(const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
+                           float* __restrict__ xt, unsigned* __restrict__ out) {
+  prescale_body(blockIdx.x, gridDim.x, x, tau, nx, n, xt, out);
 }
 
 // Fixed-point exponent of the splat: contributions are scaled by 2^k with
@@ -209,9 +207,9 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 // grids are written [template][trace][position] (each template's grid as the
 // convolution reads it).
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
-__global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
+__device__ __forceinline__ void splat_body(int bx, int by, 
     const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const double* __restrict__ gunit,
-    const int* __restrict__ base, int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins,
+    const int* __restrict__ base, int P, int K, int qs, int MQ, const Segments& seg, int chunk_bins, int tile_bins,
     const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ unsigned long long smem[];
@@ -221,8 +219,8 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   int2* pn = reinterpret_cast<int2*>(smem + NT * TS);                // [seg.n][nx] {next row, its position}
   int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of row 0's records
   __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
-  const int ij = blockIdx.y;
-  const int J_begin = blockIdx.x * chunk_bins;
+  const int ij = by;
+  const int J_begin = bx * chunk_bins;
   const int J_end = min(J_begin + chunk_bins, MQ);
   if (J_begin >= J_end) return;  // uniform over the block
   const int btx = base[ij / K];
@@ -407,6 +405,15 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
   }
 }
 
+template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
+__global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
+    const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const double* __restrict__ gunit,
+    const int* __restrict__ base, int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins,
+    const unsigned* __restrict__ xmax, int n_xmax,
+    int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
+  splat_body<ABSW, WIDE, ST, ATT, MT>(blockIdx.x, blockIdx.y, xt, nx, n_off, legs, gunit, base, P, K, qs, MQ, seg, chunk_bins, tile_bins, xmax, n_xmax, gbin, glast, bs, fine);
+}
+
 // One fine-grid sample through a buffer resource over one trace: positions
 // past the record read as zero.
 template <int ST>
@@ -449,19 +456,19 @@ __device__ __forceinline__ float fine_at<UMBIR_STORAGE_BF16>(__amdgpu_buffer_rsr
 // [trace][template][position], and every pair reads the grid of its own
 // template, so one pass serves all templates.
 template <bool ABSW, int VPT, int ST, bool ATT, bool ONE, bool MULTI>
-__global__ __launch_bounds__(256) void k_gather(
+__device__ __forceinline__ void gather_body(int bx, int by, 
     const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const double* __restrict__ gunit, const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
     int tpg, int t_off, int t_cnt, int vox_per_block, int gbin, int glast, int accum,
     float* __restrict__ partial) {
   const int N = nx * nz;
-  const int v_begin = blockIdx.y * vox_per_block;
+  const int v_begin = by * vox_per_block;
   const int v_end = min(N, v_begin + vox_per_block);
   const int PK = P * K;
   // this launch covers traces [t_off, t_off + t_cnt) of each group; the first
   // launch writes the partial image, later ones add to it
-  const int g_end = min((blockIdx.x + 1) * tpg, PK);
-  const int t0 = blockIdx.x * tpg + t_off;
+  const int g_end = min((bx + 1) * tpg, PK);
+  const int t0 = bx * tpg + t_off;
   const int t1 = min(t0 + t_cnt, g_end);
   if (t0 >= t1 && (t_off > 0 || accum)) return;  // uniform over the block: nothing to add
   const int sh = 32 - qs;
@@ -584,11 +591,20 @@ __global__ __launch_bounds__(256) void k_gather(
       if (ok[u]) {
         float tr = tau[v / nx];
         if (ABSW) tr = fabsf(tr);
-        float* pv = partial + size_t(blockIdx.x) * N + v;
+        float* pv = partial + size_t(bx) * N + v;
         *pv = (t_off == 0 && !accum) ? acc[u] * tr : fmaf(acc[u], tr, *pv);
       }
     }
   }
+}
+
+template <bool ABSW, int VPT, int ST, bool ATT, bool ONE, bool MULTI>
+__global__ __launch_bounds__(256) void k_gather(
+    const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const double* __restrict__ gunit, const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ,
+    int tpg, int t_off, int t_cnt, int vox_per_block, int gbin, int glast, int accum,
+    float* __restrict__ partial) {
+  gather_body<ABSW, VPT, ST, ATT, ONE, MULTI>(blockIdx.x, blockIdx.y, fine, nx, nz, n_off, legs, gunit, tau, base, P, K, qs, MQ, tpg, t_off, t_cnt, vox_per_block, gbin, glast, accum, partial);
 }
 
 __global__ void k_reduce_groups(const float* __restrict__ partial, int groups, int N, float scale,
@@ -744,7 +760,7 @@ __host__ __device__ inline int corr_lds_words(int Q, int rows, int H) {
 }
 
 template <int QT, int NT>
-__global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
+__device__ __forceinline__ void corr_mfma_body(int bx, int by, const float* __restrict__ rt,
                                                    const float* __restrict__ hq, int M, int Lh, int rb_per_block,
                                                    float* __restrict__ fine, long tstride, BinSkip bs) {
   constexpr int Q = 32 * QT;
@@ -759,7 +775,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   // seg0(b)[x] = r[n_blk + 1 + x] and seg1(b)[x] = r[n_blk + 1 + H + x]
   float* const segs = taps1 + H * Q;
   const int SW = corr_seg_words(ROWS, H), SG = corr_seg_gap(ROWS, H);
-  const int ij = blockIdx.x;
+  const int ij = bx;
   const float* r = rt + size_t(ij) * M;
   float* c = fine + size_t(ij) * tstride;  // trace ij's output (tstride = M Q, or more between templates' grids)
   {
@@ -783,7 +799,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   }
   // the block's row blocks, in order; each thread carries its share of the
   // next segment in registers while the current one multiplies
-  const int rb0 = blockIdx.y * rb_per_block;
+  const int rb0 = by * rb_per_block;
   const int rb_end = min(rb0 + rb_per_block, (M + ROWS - 1) / ROWS);
   constexpr int SEG_PER_THREAD = 4;  // ceil((ROWS + H) / 256) for H <= 768
   float s0[SEG_PER_THREAD], s1[SEG_PER_THREAD];
@@ -878,6 +894,13 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
   }
 }
 
+template <int QT, int NT>
+__global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
+                                                   const float* __restrict__ hq, int M, int Lh, int rb_per_block,
+                                                   float* __restrict__ fine, long tstride, BinSkip bs) {
+  corr_mfma_body<QT, NT>(blockIdx.x, blockIdx.y, rt, hq, M, Lh, rb_per_block, fine, tstride, bs);
+}
+
 // Chunk order of the banded convolutions on the matrix cores.  The rows n a
 // block needs are its window [m0 - Lh, m0 + 30], walked in chunks of CN rows.
 // Every block walks a window of the same length, P chunks from m0 - Lh,
@@ -915,7 +938,7 @@ struct ChunkOrder {
 // 128 registers and 35 KB of LDS at Q = 32, so four blocks share a CU.
 // Epilogue as in k_conv.
 template <int Q>
-__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
+__device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
@@ -926,8 +949,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
   constexpr int TS = Q + 4;     // tap row stride
   extern __shared__ __align__(16) float sm[];
   float* taps = sm;  // [Lh + 1][TS]: tap rows 0 .. Lh - 1, then a zero row
-  const int tr0 = blockIdx.x * 32;
-  const int m0 = blockIdx.y * 32;
+  const int tr0 = bx * 32;
+  const int m0 = by * 32;
   const long MQ = long(M) * Q;
   {
     // zero rows and columns first, then the taps with 16-byte loads, several
@@ -1058,6 +1081,25 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fin
       out[size_t(tr) * M + mm] = val;
     }
   }
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
+                                                   const float* __restrict__ hq, int M, int Lh,
+                                                   int PK, const float* base, float sign,
+                                                   const float* __restrict__ g,
+                                                   const float* __restrict__ dbasis, float* out, long tstride,
+                                                   BinSkip bs) {
+  conv_mfma_body<Q>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+}
+
+// The same with the grid's dimensions swapped (sample tiles fastest).
+template <int Q>
+__global__ __launch_bounds__(256) void k_conv_mfma_t(const float* __restrict__ fine, const float* __restrict__ hq,
+                                                     int M, int Lh, int PK, const float* base, float sign,
+                                                     const float* __restrict__ g, const float* __restrict__ dbasis,
+                                                     float* out, long tstride, BinSkip bs) {
+  conv_mfma_body<Q>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
 }
 
 // C on the matrix cores with 16-bit storage (Q in {32, 64}): as k_conv_mfma,
@@ -1279,9 +1321,13 @@ void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* h
                       float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
   // padded taps, reused for the four partial tiles at the end
   const size_t lds = std::max<size_t>(size_t(G.Lh + 1) * (Q + 4), 4 * 32 * 33) * sizeof(float);
-  dim3 grid((G.traces() + 31) / 32, (G.M + 31) / 32);
-  UMBIR_LAUNCH("conv", k_conv_mfma<Q>, grid, dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
-               sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+  const unsigned tt = unsigned((G.traces() + 31) / 32), mt = unsigned((G.M + 31) / 32);
+  if (G.conv_grid == 2)
+    UMBIR_LAUNCH("conv", k_conv_mfma_t<Q>, dim3(mt, tt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
+                 sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+  else
+    UMBIR_LAUNCH("conv", k_conv_mfma<Q>, dim3(tt, mt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
+                 sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
 }
 
 template <int Q, int ST>
@@ -1324,19 +1370,26 @@ void launch_conv(const umbir_geometry& G, const void* fine_v, const float* hq, c
   }
 }
 
-template <int QT>
-void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride,
-                      int gbin, hipStream_t s) {
-  constexpr int NT = 2;
+template <int QT, int NT>
+void launch_corr_mfma_nt(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride,
+                         int gbin, hipStream_t s) {
   constexpr int rows = 4 * NT * 32;
   const size_t lds = size_t(corr_lds_words(32 * QT, rows, corr_half(G.Lh))) * sizeof(float);
-  // about four blocks per CU, each walking several row blocks of one trace
-  // with the taps staged once
+  // about corr_blocks blocks (four per CU by default), each walking several
+  // row blocks of one trace with the taps staged once
   const int nrb = (G.M + rows - 1) / rows;
-  const int per = std::max(1, int((long(G.traces()) * nrb) / 1024));
+  const int per = std::max(1, int((long(G.traces()) * nrb) / std::max(1, G.corr_blocks)));
   dim3 grid(G.traces(), (nrb + per - 1) / per);
   UMBIR_LAUNCH("corr", (k_corr_mfma<QT, NT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine, tstride,
                bin_skip(G, gbin));
+}
+
+template <int QT>
+void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride,
+                      int gbin, hipStream_t s) {
+  if (G.corr_tiles == 1) return launch_corr_mfma_nt<QT, 1>(G, r, hq, fine, tstride, gbin, s);
+  if (G.corr_tiles == 4) return launch_corr_mfma_nt<QT, 4>(G, r, hq, fine, tstride, gbin, s);
+  return launch_corr_mfma_nt<QT, 2>(G, r, hq, fine, tstride, gbin, s);
 }
 
 template <int QT, int ST>
@@ -1460,7 +1513,197 @@ void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int 
                                            partial, s);
 }
 
+
+// ---- work-list forms of the sweeps for persistent batches: block b takes
+// items b, b + gridDim.x, ...; an item (problem, x, y) runs the block (x, y)
+// of that problem's own launch with the problem's arguments, so every problem
+// gets bitwise the result of its own launches.  A barrier separates items (a
+// block reuses its LDS).
+
+__global__ __launch_bounds__(1024) void k_prescale_list(const BatchProb* __restrict__ probs,
+                                                        const int* __restrict__ active,
+                                                        const int4* __restrict__ items, int n_items, int which) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;  // uniform: the problem left the batch
+    const BatchProb& p = probs[w.x];
+    prescale_body(w.y, p.prescale_blocks, p.x[which], p.tau, p.nx, p.nx * p.nz, p.xt, p.xmax);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64 * kSplatWaves) void k_splat_list(const BatchProb* __restrict__ probs,
+                                                                 const int* __restrict__ active,
+                                                                 const int4* __restrict__ items, int n_items) {
+  const BinSkip none{nullptr, 0, 0};
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    if (p.wide)
+      splat_body<false, true, UMBIR_STORAGE_F32, false, false>(
+          w.y, w.z, p.xt, p.nx, p.n_off, p.legs, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg, p.chunk_bins,
+          p.tile_bins, p.xmax, p.prescale_blocks, 0, 0, none, p.fine);
+    else
+      splat_body<false, false, UMBIR_STORAGE_F32, false, false>(
+          w.y, w.z, p.xt, p.nx, p.n_off, p.legs, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg, p.chunk_bins,
+          p.tile_bins, p.xmax, p.prescale_blocks, 0, 0, none, p.fine);
+    __syncthreads();
+  }
+}
+
+// residual e = y - A x - g D of the iteration
+template <int Q>
+__global__ __launch_bounds__(256) void k_conv_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
+                                                   const int4* __restrict__ items, int n_items) {
+  const BinSkip none{nullptr, 0, 0};
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    conv_mfma_body<Q>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ), none);
+    __syncthreads();
+  }
+}
+
+template <int QT>
+__global__ __launch_bounds__(256) void k_corr_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
+                                                   const int4* __restrict__ items, int n_items) {
+  const BinSkip none{nullptr, 0, 0};
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    corr_mfma_body<QT, 2>(w.y, w.z, p.e, p.h, p.M, p.Lh, p.corr_per, p.fine, long(p.MQ), none);
+    __syncthreads();
+  }
+}
+
+// An item is (problem, trace group, voxel block, batch b): block (group,
+// voxel block) of the plain path's gather launch b, which covers traces
+// [b gbatch, (b + 1) gbatch) of each group and adds to the partial images of
+// the launches before it.  Batches run as separate launches, in order.
+__global__ __launch_bounds__(256) void k_gather_list(const BatchProb* __restrict__ probs,
+                                                     const int* __restrict__ active,
+                                                     const int4* __restrict__ items, int n_items) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    const int PK = p.P * p.K;
+    const int t_off = w.w * p.gbatch;
+    const int t0 = w.y * p.tpg + t_off;
+    const int t1 = min(t0 + p.gbatch, min((w.y + 1) * p.tpg, PK));
+    // the transmit legs are shared when the batch's traces lie in one scan
+    // position (the same values either way, so the same result)
+    if (t0 < t1 && t0 / p.K == (t1 - 1) / p.K)
+      gather_body<false, 4, UMBIR_STORAGE_F32, false, true, false>(
+          w.y, w.z, p.fine, p.nx, p.nz, p.n_off, p.legs, nullptr, p.tau, p.base, p.P, p.K, p.qs, p.MQ, p.tpg,
+          t_off, p.gbatch, p.vpb, 0, 0, 0, p.partial);
+    else
+      gather_body<false, 4, UMBIR_STORAGE_F32, false, false, false>(
+          w.y, w.z, p.fine, p.nx, p.nz, p.n_off, p.legs, nullptr, p.tau, p.base, p.P, p.K, p.qs, p.MQ, p.tpg,
+          t_off, p.gbatch, p.vpb, 0, 0, 0, p.partial);
+  }
+}
+
 }  // namespace
+
+void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int4>* items, size_t* lds) {
+  const int PK = G.traces(), N = G.voxels();
+  bp.legs = G.legs;
+  bp.base = G.base;
+  bp.tau = G.tau;
+  bp.h = G.h;
+  bp.dbasis = G.dbasis;
+  bp.dnorm = G.dnorm;
+  bp.nx = G.nx;
+  bp.nz = G.nz;
+  bp.n_off = G.n_off;
+  bp.P = G.P;
+  bp.K = G.K;
+  bp.M = G.M;
+  bp.Q = G.Q;
+  bp.qs = log2_int(G.Q);
+  bp.Lh = G.Lh;
+  bp.MQ = int(G.fine_per_trace());
+  bp.seg.n = G.n_seg;
+  for (int k = 0; k < kMaxLayers; ++k) {
+    bp.seg.lo[k] = G.seg_lo[k];
+    bp.seg.hi[k] = G.seg_hi[k];
+  }
+  // prescale
+  bp.prescale_blocks = prescale_blocks(G);
+  for (int b = 0; b < bp.prescale_blocks; ++b) items[kStPrescale].push_back(make_int4(pi, b, 0, 0));
+  // splat: as launch_splat_k without attenuation
+  bp.chunk_bins = int(G.chunk_bins);
+  bp.tile_bins = G.tile_bins;
+  bp.wide = G.nx * (G.seg_hi[G.n_seg - 1] - G.seg_lo[0]) < kSplatNarrowMin;
+  lds[kStSplat] = std::max(lds[kStSplat], size_t(G.tile_bins + 2) * sizeof(unsigned long long) +
+                                              size_t(G.n_seg + 1) * G.nx * sizeof(int2));
+  for (int t = 0; t < PK; ++t)
+    for (int c = 0; c < G.chunks; ++c) items[kStSplat].push_back(make_int4(pi, c, t, 0));
+  // convolution: as launch_conv_mfma
+  lds[kStConv] = std::max(lds[kStConv], std::max<size_t>(size_t(G.Lh + 1) * (G.Q + 4), 4 * 32 * 33) * sizeof(float));
+  if (G.conv_grid == 2) {
+    for (int tx = 0; tx < (PK + 31) / 32; ++tx)
+      for (int my = 0; my < (G.M + 31) / 32; ++my) items[kStConv].push_back(make_int4(pi, tx, my, 0));
+  } else {
+    for (int my = 0; my < (G.M + 31) / 32; ++my)
+      for (int tx = 0; tx < (PK + 31) / 32; ++tx) items[kStConv].push_back(make_int4(pi, tx, my, 0));
+  }
+  // correlation: two 32-row tiles per wave whatever the tuning (the tile
+  // shape does not change a result), row blocks per workgroup as tuned
+  {
+    constexpr int rows = 4 * 2 * 32;
+    const int nrb = (G.M + rows - 1) / rows;
+    bp.corr_per = std::max(1, int((long(PK) * nrb) / std::max(1, G.corr_blocks)));
+    lds[kStCorr] = std::max(lds[kStCorr], size_t(corr_lds_words(G.Q, rows, corr_half(G.Lh))) * sizeof(float));
+    for (int rg = 0; rg < (nrb + bp.corr_per - 1) / bp.corr_per; ++rg)
+      for (int t = 0; t < PK; ++t) items[kStCorr].push_back(make_int4(pi, t, rg, 0));
+  }
+  // gather: as run_adjoint_partial without attenuation
+  {
+    bp.groups = G.trace_groups;
+    bp.tpg = (PK + G.trace_groups - 1) / G.trace_groups;
+    int nb = (N + 1023) / 1024;
+    nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
+    bp.vpb = (N + nb - 1) / nb;
+    const size_t trace_bytes = size_t(bp.MQ) * sizeof(float);
+    bp.gbatch = int(std::max<size_t>(1, std::min<size_t>(bp.tpg, (size_t(G.gather_batch_kb) << 10) / trace_bytes)));
+    const int batches = (bp.tpg + bp.gbatch - 1) / bp.gbatch;
+    for (int b = 0; b < batches; ++b)
+      for (int vb = 0; vb < nb; ++vb)
+        for (int gr = 0; gr < G.trace_groups; ++gr) items[kStGather].push_back(make_int4(pi, gr, vb, b));
+  }
+}
+
+int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* active, const StageLaunch& L, int which,
+                       hipStream_t s) {
+  if (L.n_items == 0) return UMBIR_OK;
+  const dim3 grid(unsigned(L.grid));
+  switch (stage) {
+    case kStPrescale:
+      UMBIR_LAUNCH("prescale", k_prescale_list, grid, dim3(1024), L.lds, s, probs, active, L.items, L.n_items, which);
+      break;
+    case kStSplat:
+      UMBIR_LAUNCH("splat", k_splat_list, grid, dim3(64 * kSplatWaves), L.lds, s, probs, active, L.items, L.n_items);
+      break;
+    case kStConv:
+      if (Q == 32) UMBIR_LAUNCH("conv", k_conv_list<32>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      else UMBIR_LAUNCH("conv", k_conv_list<64>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      break;
+    case kStCorr:
+      if (Q == 32) UMBIR_LAUNCH("corr", k_corr_list<1>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      else UMBIR_LAUNCH("corr", k_corr_list<2>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      break;
+    case kStGather:
+      UMBIR_LAUNCH("gather", k_gather_list, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      break;
+    default: return fail(UMBIR_EINVAL, "not a sweep stage");
+  }
+  return check_hip(hipGetLastError(), "work-list sweep");
+}
 
 int launch_fill(float* p, size_t n, float v, hipStream_t s) {
   UMBIR_LAUNCH("fill", k_fill, dim3(grid_1d(n / 4 + 1)), dim3(256), 0, s, p, n, v);
@@ -1753,6 +1996,35 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     if (ms < best) { best = ms; best_blocks = c; }
   }
   apply_splat_blocks(G, best_blocks);
+  // the matrix-core convolution's tile order (FP32, Q of 32 or 64)
+  if (!st && G->storage == UMBIR_STORAGE_F32 && (G->Q == 32 || G->Q == 64)) {
+    int best_grid = G->conv_grid;
+    best = 3.4e38f;
+    for (int cg : {1, 2}) {
+      G->conv_grid = cg;
+      float ms = 0.0f;
+      if ((st = time_ms(forward, &ms))) break;
+      if (ms < best) { best = ms; best_grid = cg; }
+    }
+    G->conv_grid = best_grid;
+  }
+  // the matrix-core correlation's tile rows per wave and workgroup count
+  if (!st && G->storage == UMBIR_STORAGE_F32 && (G->Q == 32 || G->Q == 64)) {
+    int best_t = G->corr_tiles, best_b = G->corr_blocks;
+    best = 3.4e38f;
+    for (int t : {1, 2, 4}) {
+      for (int nb : {512, 1024, 2048}) {
+        G->corr_tiles = t;
+        G->corr_blocks = nb;
+        float ms = 0.0f;
+        if ((st = time_ms(adjoint, &ms))) break;
+        if (ms < best) { best = ms; best_t = t; best_b = nb; }
+      }
+      if (st) break;
+    }
+    G->corr_tiles = best_t;
+    G->corr_blocks = best_b;
+  }
   // the gather: fine-grid KiB per trace group and launch
   int best_kb = G->gather_batch_kb;
   best = 3.4e38f;
@@ -1770,6 +2042,9 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
   if (chosen) {
     chosen->splat_blocks = G->splat_blocks;
     chosen->gather_batch_kb = G->gather_batch_kb;
+    chosen->conv_grid = G->conv_grid;
+    chosen->corr_tile_rows = 32 * G->corr_tiles;
+    chosen->corr_blocks = G->corr_blocks;
   }
   return UMBIR_OK;
 }

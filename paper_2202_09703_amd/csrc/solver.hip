@@ -23,6 +23,7 @@
 // are dropped.  The scale of Eq. (16) uses m_s of Eq. (17) with depth = the
 // voxel-centre depth and maximum depth = the deepest centre.
 
+#include <algorithm>
 #include <cmath>
 
 #include <cstdio>
@@ -34,16 +35,6 @@
 
 namespace umbir {
 namespace {
-
-struct PriorConst {
-  float inv_sigma2;
-  float p;
-  float T;
-  float T_pm2;  // T^(p - 2)
-  float sigma0;
-  double m, a;
-  double z0, dz;
-};
 
 __device__ __forceinline__ float depth_mod(int row, int nz, const PriorConst& pc) {
   const double depth = pc.z0 + (row + 0.5) * pc.dz;
@@ -100,12 +91,12 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh /* [
 
 // Per trace: |e|^2 before the g step, then the exact g step (e in the storage type).
 template <int ST>
-__global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict__ e, const float* __restrict__ d,
+__device__ __forceinline__ void gstep_body(int bx, int by, typename Store<ST>::T* __restrict__ e, const float* __restrict__ d,
                                                const float* __restrict__ dnorm, float* __restrict__ g,
                                                int M, int estimate, double* __restrict__ ess) {
   __shared__ double sh[8];
   __shared__ float dg_sh;
-  const int ij = blockIdx.x;
+  const int ij = bx;
   typename Store<ST>::T* et = e + size_t(ij) * M;
   const float* dt = d + size_t(ij) * M;
   // traces of up to R blockDim samples stay in registers between the two
@@ -160,6 +151,13 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
   }
 }
 
+template <int ST>
+__global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict__ e, const float* __restrict__ d,
+                                               const float* __restrict__ dnorm, float* __restrict__ g,
+                                               int M, int estimate, double* __restrict__ ess) {
+  gstep_body<ST>(blockIdx.x, blockIdx.y, e, d, dnorm, g, M, estimate, ess);
+}
+
 // Prior cost of x (pairs counted once) into pcost[block]; with UPDATE also the
 // surrogate step into xout, with A^T e the sum of the adjoint's `groups`
 // partial images (lane q of the voxel sums groups q, q + 4, ..., then a fixed
@@ -167,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
 // neighbours each (then summed across the four lanes); the depth modulation
 // of the rows the block touches is tabulated once per block.
 template <bool UPDATE>
-__global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict__ x,
+__device__ __forceinline__ void prior_body(int bx, int by, const float* __restrict__ x,
                                                          const float* __restrict__ part, int groups,
                                                          const float* __restrict__ den, int nx, int nz,
                                                          PriorConst pc, float* __restrict__ xout,
@@ -178,7 +176,7 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict
   const float b_diag = float(1.0 / (4.0 + 2.0 * M_SQRT2) / M_SQRT2);
   const int N = nx * nz;
   const int q = threadIdx.x & 3;
-  const int v0 = blockIdx.x * kPriorVox;
+  const int v0 = bx * kPriorVox;
   const int v = v0 + (threadIdx.x >> 2);
   const int r_lo = max(v0 / nx - 1, 0);
   const int r_hi = min((min(v0 + kPriorVox, N) - 1) / nx + 1, nz - 1);
@@ -233,13 +231,22 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict
   for (int off = 32; off > 0; off >>= 1) cost += __shfl_down(cost, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cost;
   __syncthreads();
-  if (threadIdx.x == 0) pcost[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) pcost[bx] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+template <bool UPDATE>
+__global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict__ x,
+                                                         const float* __restrict__ part, int groups,
+                                                         const float* __restrict__ den, int nx, int nz,
+                                                         PriorConst pc, float* __restrict__ xout,
+                                                         double* __restrict__ pcost) {
+  prior_body<UPDATE>(blockIdx.x, blockIdx.y, x, part, groups, den, nx, nz, pc, xout, pcost);
 }
 
 // Cost = data term + prior term, written to out[*counter] (then the counter
 // advances) or to out[0] when counter is NULL.  The device-side counter lets a
 // captured iteration graph append to the history wherever it is replayed.
-__global__ __launch_bounds__(256) void k_cost(const double* __restrict__ ess, int n_ess,
+__device__ __forceinline__ void cost_body(int bx, int by, const double* __restrict__ ess, int n_ess,
                                               const double* __restrict__ pcost, int n_p,
                                               double inv_2sigma2, double* __restrict__ out,
                                               int* __restrict__ counter) {
@@ -256,6 +263,51 @@ __global__ __launch_bounds__(256) void k_cost(const double* __restrict__ ess, in
     } else {
       *out = a * inv_2sigma2 + b;
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cost(const double* __restrict__ ess, int n_ess,
+                                              const double* __restrict__ pcost, int n_p,
+                                              double inv_2sigma2, double* __restrict__ out,
+                                              int* __restrict__ counter) {
+  cost_body(blockIdx.x, blockIdx.y, ess, n_ess, pcost, n_p, inv_2sigma2, out, counter);
+}
+
+// Work-list forms for persistent batches (see the sweeps' in operator.hip):
+// item (problem, x, 0) runs block x of that problem's own launch.
+__global__ __launch_bounds__(256) void k_gstep_list(const BatchProb* __restrict__ probs,
+                                                    const int* __restrict__ active,
+                                                    const int4* __restrict__ items, int n_items) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;  // uniform: the problem left the batch
+    const BatchProb& p = probs[w.x];
+    gstep_body<UMBIR_STORAGE_F32>(w.y, 0, p.e, p.dbasis, p.dnorm, p.g, p.M, p.est, p.ess);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(4 * kPriorVox) void k_prior_list(const BatchProb* __restrict__ probs,
+                                                             const int* __restrict__ active,
+                                                             const int4* __restrict__ items, int n_items,
+                                                             int which) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    prior_body<true>(w.y, 0, p.x[which], p.partial, p.groups, p.den, p.nx, p.nz, p.pc, p.x[which ^ 1], p.pcost);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cost_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
+                                                   const int4* __restrict__ items, int n_items) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    cost_body(0, 0, p.ess, p.P * p.K, p.pcost, p.nblk, p.inv_2s2, p.cost, p.counter);
+    __syncthreads();
   }
 }
 
@@ -666,6 +718,22 @@ constexpr int kBatchStreams = 4;
 struct umbir_batch {
   int device = -1;
   int mode = UMBIR_BATCH_STREAMS;
+  // UMBIR_BATCH_WORKLIST: the problems split into lanes (one per batch
+  // stream); per lane its problems' arguments (BatchProb[m]), their active
+  // flags (int[m]) and every launch's work list in one device buffer, and its
+  // launches.  A session whose max_iter is reached leaves the batch (its flag
+  // is cleared and its items are skipped).
+  struct Lane {
+    std::vector<int> members;  // batch indices of the lane's sessions
+    void* plan = nullptr;
+    int* active = nullptr;
+    std::vector<StageLaunch> launches;
+    std::vector<int> kinds;  // BatchStage of each launch
+  };
+  std::vector<Lane> lanes;
+  std::vector<int> lane_of, slot_of;  // per session: its lane and index there
+  std::vector<char> live;
+  int Q = 0;
   std::vector<umbir_solver*> s;
   std::vector<int> done;  // each session's iteration count as the batch left it
   int parity = 0;         // exec[parity] advances every session by one (graph mode)
@@ -726,6 +794,8 @@ void batch_release(umbir_batch* B) {
   }
   for (hipGraphExec_t& ge : B->exec)
     if (ge) (void)hipGraphExecDestroy(ge);
+  for (auto& L : B->lanes)
+    if (L.plan) (void)hipFree(L.plan);
   if (B->fork) (void)hipEventDestroy(B->fork);
   for (int k = 0; k < kBatchStreams; ++k) {
     if (B->join[k]) (void)hipEventDestroy(B->join[k]);
@@ -778,6 +848,181 @@ int batch_graph(umbir_batch* B, int which, hipGraphExec_t* out) {
   if (!st) st = check_hip(hipGraphInstantiate(out, g, nullptr, nullptr, 0), "hipGraphInstantiate");
   if (g) (void)hipGraphDestroy(g);
   return st;
+}
+
+// One iteration of one lane of a work-list batch: its launches in order,
+// each over the lane's problems' work items; `which` selects each problem's
+// input image (x[which]; the update writes x[which ^ 1]).
+int enqueue_lane(const umbir_batch::Lane& L, int Q, int which, hipStream_t s) {
+  const BatchProb* probs = static_cast<const BatchProb*>(L.plan);
+  const int* active = L.active;
+  int st = UMBIR_OK;
+  for (size_t k = 0; k < L.launches.size() && !st; ++k) {
+    const StageLaunch& SL = L.launches[k];
+    if (SL.n_items == 0) continue;
+    const dim3 grid(unsigned(SL.grid));
+    switch (L.kinds[k]) {
+      case kStGstep:
+        UMBIR_LAUNCH("gstep", k_gstep_list, grid, dim3(256), 0, s, probs, active, SL.items, SL.n_items);
+        st = check_hip(hipGetLastError(), "k_gstep_list");
+        break;
+      case kStPrior:
+        UMBIR_LAUNCH("prior", k_prior_list, grid, dim3(4 * kPriorVox), 0, s, probs, active, SL.items, SL.n_items,
+                     which);
+        st = check_hip(hipGetLastError(), "k_prior_list");
+        break;
+      case kStCost:
+        UMBIR_LAUNCH("cost", k_cost_list, grid, dim3(256), 0, s, probs, active, SL.items, SL.n_items);
+        st = check_hip(hipGetLastError(), "k_cost_list");
+        break;
+      default: st = launch_sweep_stage(L.kinds[k], Q, probs, active, SL, which, s); break;
+    }
+  }
+  return st;
+}
+
+// One graph per image direction: fork from the first batch stream to one
+// stream per lane, each lane's launches, join.
+int worklist_graph(umbir_batch* B, int which, hipGraphExec_t* out) {
+  hipStream_t s0 = B->st[0];
+  const int nl = int(B->lanes.size());
+  int st = check_hip(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (st) return st;
+  int st_enq = check_hip(hipEventRecord(B->fork, s0), "hipEventRecord");
+  for (int k = 1; k < nl && !st_enq; ++k)
+    st_enq = check_hip(hipStreamWaitEvent(B->st[k], B->fork, 0), "hipStreamWaitEvent");
+  for (int k = 0; k < nl && !st_enq; ++k) st_enq = enqueue_lane(B->lanes[k], B->Q, which, B->st[k]);
+  for (int k = 1; k < nl && !st_enq; ++k) {
+    st_enq = check_hip(hipEventRecord(B->join[k], B->st[k]), "hipEventRecord");
+    if (!st_enq) st_enq = check_hip(hipStreamWaitEvent(s0, B->join[k], 0), "hipStreamWaitEvent");
+  }
+  hipGraph_t g = nullptr;
+  st = check_hip(hipStreamEndCapture(s0, &g), "hipStreamEndCapture");
+  if (st_enq) st = st_enq;
+  if (!st) st = check_hip(hipGraphInstantiate(out, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (g) (void)hipGraphDestroy(g);
+  return st;
+}
+
+// Builds one lane: its problems' arguments, active flags and work lists (the
+// launch shapes of each problem's own iteration, so every problem gets
+// bitwise the result of stepping it alone), uploaded to one device buffer,
+// and its launches: prescale, splat, convolution, g step, correlation, one
+// gather launch per batch of traces, prior update, cost.  Each launch has a
+// block per item, so the lanes' launches interleave on the device.
+int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
+  const int n = int(L.members.size());
+  std::vector<BatchProb> probs(n);
+  std::vector<int4> items[kStages];
+  size_t lds[kStages] = {};
+  for (int i = 0; i < n; ++i) {
+    umbir_solver* S = B->s[L.members[i]];
+    const umbir_geometry& G = *S->G;
+    BatchProb& bp = probs[i];
+    plan_sweeps(G, i, bp, items, lds);
+    bp.y = static_cast<const float*>(S->y);
+    bp.e = static_cast<float*>(S->b.e);
+    bp.fine = static_cast<float*>(S->b.fine);
+    bp.xt = reinterpret_cast<float*>(static_cast<char*>(S->b.fine) + G.grids_bytes());
+    bp.xmax = reinterpret_cast<unsigned*>(static_cast<char*>(S->b.fine) + G.fine_bytes() - 4 * kPrescaleBlocks);
+    bp.partial = S->b.partial;
+    bp.den = S->b.den;
+    bp.ess = S->b.ess;
+    bp.pcost = S->b.pcost;
+    bp.nblk = S->b.nblk;
+    bp.x[0] = S->parity ? S->xb : S->xa;  // the current image
+    bp.x[1] = S->parity ? S->xa : S->xb;
+    bp.g = S->g;
+    bp.cost = S->cost;
+    bp.counter = S->counter;
+    bp.pc = S->pc;
+    bp.inv_2s2 = S->inv_2s2;
+    bp.est = S->est;
+    for (int t = 0; t < G.traces(); ++t) items[kStGstep].push_back(make_int4(i, t, 0, 0));
+    for (int b = 0; b < S->b.nblk; ++b) items[kStPrior].push_back(make_int4(i, b, 0, 0));
+    items[kStCost].push_back(make_int4(i, 0, 0, 0));
+  }
+  // the gather's items by launch (batch index), in problem order within one
+  std::stable_sort(items[kStGather].begin(), items[kStGather].end(),
+                   [](const int4& a, const int4& b) { return a.w < b.w; });
+  size_t bytes = aligned(size_t(n) * sizeof(BatchProb)) + aligned(size_t(n) * sizeof(int));
+  for (int k = 0; k < kStages; ++k) bytes += aligned(items[k].size() * sizeof(int4));
+  int st = check_hip(hipMalloc(&L.plan, bytes), "hipMalloc(batch plan)");
+  if (st) return st;
+  char* p = static_cast<char*>(L.plan);
+  if ((st = check_hip(hipMemcpy(p, probs.data(), n * sizeof(BatchProb), hipMemcpyHostToDevice), "hipMemcpy")))
+    return st;
+  size_t off = aligned(size_t(n) * sizeof(BatchProb));
+  L.active = reinterpret_cast<int*>(p + off);
+  std::vector<int> flags(n);
+  for (int i = 0; i < n; ++i) flags[i] = B->live[L.members[i]];
+  if ((st = check_hip(hipMemcpy(L.active, flags.data(), n * sizeof(int), hipMemcpyHostToDevice), "hipMemcpy")))
+    return st;
+  off += aligned(size_t(n) * sizeof(int));
+  const int4* dev_items[kStages];
+  for (int k = 0; k < kStages; ++k) {
+    dev_items[k] = reinterpret_cast<const int4*>(p + off);
+    if (!items[k].empty() &&
+        (st = check_hip(hipMemcpy(p + off, items[k].data(), items[k].size() * sizeof(int4), hipMemcpyHostToDevice),
+                        "hipMemcpy")))
+      return st;
+    off += aligned(items[k].size() * sizeof(int4));
+  }
+  auto add = [&](int kind, const int4* first, int count) {
+    StageLaunch SL;
+    SL.items = first;
+    SL.n_items = count;
+    SL.grid = count;  // a block per item
+    SL.lds = lds[kind];
+    L.launches.push_back(SL);
+    L.kinds.push_back(kind);
+  };
+  for (int k = 0; k < kStages; ++k) {
+    if (k == kStGather) {  // one launch per batch index
+      size_t a = 0;
+      while (a < items[k].size()) {
+        size_t b = a;
+        while (b < items[k].size() && items[k][b].w == items[k][a].w) ++b;
+        add(k, dev_items[k] + a, int(b - a));
+        a = b;
+      }
+    } else {
+      add(k, dev_items[k], int(items[k].size()));
+    }
+  }
+  return UMBIR_OK;
+}
+
+// Splits the batch's problems into lanes of about equal work (largest first,
+// each to the lane with the least so far) and builds every lane.
+int worklist_plan(umbir_batch* B) {
+  const int n = int(B->s.size());
+  B->live.assign(n, 1);
+  for (int i = 0; i < n; ++i) B->live[i] = B->s[i]->done < B->s[i]->max_iter;
+  const int nl = std::min(n, kBatchStreams);
+  B->lanes.resize(nl);
+  std::vector<int> order(n);
+  std::vector<double> work(n), load(nl, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const umbir_solver* S = B->s[i];
+    order[i] = i;
+    work[i] = double(S->max_iter - S->done) * S->G->traces() * S->G->voxels();
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  B->lane_of.assign(n, 0);
+  B->slot_of.assign(n, 0);
+  for (int i : order) {
+    const int l = int(std::min_element(load.begin(), load.end()) - load.begin());
+    load[l] += work[i];
+    B->lane_of[i] = l;
+    B->slot_of[i] = int(B->lanes[l].members.size());
+    B->lanes[l].members.push_back(i);
+  }
+  for (auto& L : B->lanes) {
+    const int st = worklist_lane(B, L);
+    if (st) return st;
+  }
+  return UMBIR_OK;
 }
 
 // Scratch of umbir_reconstruct_noalloc: a static device array, one copy per
@@ -1093,7 +1338,8 @@ int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_bat
   if (!out) return fail(UMBIR_EINVAL, "out is NULL");
   *out = nullptr;
   if (!sessions || n <= 0) return fail(UMBIR_EINVAL, "need at least one session");
-  if (mode != UMBIR_BATCH_STREAMS && mode != UMBIR_BATCH_GRAPH) return fail(UMBIR_EINVAL, "unknown batch mode");
+  if (mode != UMBIR_BATCH_STREAMS && mode != UMBIR_BATCH_GRAPH && mode != UMBIR_BATCH_WORKLIST)
+    return fail(UMBIR_EINVAL, "unknown batch mode");
   for (int i = 0; i < n; ++i) {
     if (!sessions[i]) return fail(UMBIR_EINVAL, "NULL session");
     for (int j = 0; j < i; ++j)
@@ -1104,6 +1350,15 @@ int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_bat
   if (st) return st;
   for (int i = 0; i < n; ++i)
     if (sessions[i]->device != dev) return fail(UMBIR_EINVAL, "session on another device");
+  if (mode == UMBIR_BATCH_WORKLIST) {
+    const int q = sessions[0]->G->Q;
+    for (int i = 0; i < n; ++i) {
+      const umbir_geometry& G = *sessions[i]->G;
+      if (G.storage != UMBIR_STORAGE_F32 || G.n_gamma != 1 || (G.Q != 32 && G.Q != 64) || G.Q != q)
+        return fail(UMBIR_ENOTSUP,
+                    "persistent batches need FP32 storage, one template and one oversampling factor of 32 or 64");
+    }
+  }
   auto* B = new umbir_batch();
   B->device = dev;
   B->mode = mode;
@@ -1123,6 +1378,12 @@ int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_bat
   }
   if (!st && mode == UMBIR_BATCH_GRAPH) st = batch_graph(B, 0, &B->exec[0]);
   if (!st && mode == UMBIR_BATCH_GRAPH) st = batch_graph(B, 1, &B->exec[1]);
+  if (!st && mode == UMBIR_BATCH_WORKLIST) {
+    B->Q = sessions[0]->G->Q;
+    st = worklist_plan(B);
+    if (!st) st = worklist_graph(B, 0, &B->exec[0]);
+    if (!st) st = worklist_graph(B, 1, &B->exec[1]);
+  }
   if (st) {
     batch_release(B);
     return st;
@@ -1137,12 +1398,37 @@ int umbir_batch_step(umbir_batch* B, int n_iter, void* stream) {
   for (size_t i = 0; i < B->s.size(); ++i) {
     const umbir_solver* S = B->s[i];
     if (S->done != B->done[i]) return fail(UMBIR_EINVAL, "a session was stepped outside its batch");
-    if (S->done + n_iter > S->max_iter) return fail(UMBIR_EINVAL, "n_iter would exceed a session's max_iter");
+    if (S->done + n_iter > S->max_iter && B->mode != UMBIR_BATCH_WORKLIST)
+      return fail(UMBIR_EINVAL, "n_iter would exceed a session's max_iter");
   }
   if (n_iter == 0) return UMBIR_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int st = UMBIR_OK;
-  if (B->mode == UMBIR_BATCH_GRAPH) {
+  if (B->mode == UMBIR_BATCH_WORKLIST) {
+    // sessions at their max_iter leave the batch before each iteration
+    for (int k = 0; k < n_iter && !st; ++k) {
+      bool any = false;
+      for (size_t i = 0; i < B->s.size() && !st; ++i) {
+        umbir_solver* S = B->s[i];
+        if (B->live[i] && S->done >= S->max_iter) {
+          B->live[i] = 0;
+          UMBIR_LAUNCH("zero_int", k_zero_int, dim3(1), dim3(1), 0, s,
+                       B->lanes[B->lane_of[i]].active + B->slot_of[i]);
+          st = check_hip(hipGetLastError(), "k_zero_int");
+        }
+        any = any || B->live[i];
+      }
+      if (st || !any) break;
+      st = check_hip(hipGraphLaunch(B->exec[B->parity], s), "hipGraphLaunch");
+      if (st) break;
+      B->parity ^= 1;
+      for (size_t i = 0; i < B->s.size(); ++i)
+        if (B->live[i]) {
+          B->s[i]->parity ^= 1;
+          B->s[i]->done += 1;
+        }
+    }
+  } else if (B->mode == UMBIR_BATCH_GRAPH) {
     for (int k = 0; k < n_iter && !st; ++k) {
       st = check_hip(hipGraphLaunch(B->exec[B->parity], s), "hipGraphLaunch");
       if (st) break;

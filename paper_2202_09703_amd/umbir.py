@@ -34,7 +34,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, EDIVERGED = 0, -1, -2, -3, -4, -5
 STORAGE_F32, STORAGE_F16, STORAGE_BF16 = 0, 1, 2
 TRACE_DTYPES = {STORAGE_F32: torch.float32, STORAGE_F16: torch.float16, STORAGE_BF16: torch.bfloat16}
 WORK_FORWARD, WORK_ADJOINT, WORK_RECONSTRUCT = 0, 1, 2
-BATCH_STREAMS, BATCH_GRAPH = 0, 1
+BATCH_STREAMS, BATCH_GRAPH, BATCH_WORKLIST = 0, 1, 2
 TABLE_DELAY, TABLE_APOD, TABLE_TAU, TABLE_BANK, TABLE_DBASIS, TABLE_OFFSET, TABLE_ATTEN = range(7)
 MAX_LAYERS = 8
 
@@ -80,7 +80,11 @@ class _Dims(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("splat_blocks", C.c_int), ("gather_batch_kb", C.c_int)]
+    _fields_ = [("splat_blocks", C.c_int), ("gather_batch_kb", C.c_int), ("conv_grid", C.c_int),
+                ("corr_tile_rows", C.c_int), ("corr_blocks", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class _KernelTime(C.Structure):
@@ -216,17 +220,20 @@ class Geometry:
 
     @property
     def shape_key(self):
-        """What the launch-shape tuning depends on."""
+        """What the launch- and tile-shape tuning depends on (window L_h, record
+        M, traces P x K, grid nz x nx, storage, and the rest of the shape)."""
         return (self.nx, self.nz, self.n_scans, self.n_rx, self.n_samples, self.oversample, self.window,
                 self.n_layers, self.storage, self.n_gamma)
 
     def tuning(self) -> dict:
         t = _Tuning()
         _check(_lib.umbir_get_tuning(self.handle, C.byref(t)), "umbir_get_tuning")
-        return {"splat_blocks": t.splat_blocks, "gather_batch_kb": t.gather_batch_kb}
+        return t.as_dict()
 
-    def set_tuning(self, splat_blocks: int = 0, gather_batch_kb: int = 0):
-        t = _Tuning(int(splat_blocks), int(gather_batch_kb))
+    def set_tuning(self, splat_blocks: int = 0, gather_batch_kb: int = 0, conv_grid: int = 0,
+                   corr_tile_rows: int = 0, corr_blocks: int = 0):
+        """Launch and tile shapes (umbir_tuning); 0 keeps a field's value."""
+        t = _Tuning(int(splat_blocks), int(gather_batch_kb), int(conv_grid), int(corr_tile_rows), int(corr_blocks))
         _check(_lib.umbir_set_tuning(self.handle, C.byref(t)), "umbir_set_tuning")
 
     def autotune(self, stream=None, cache: Optional[dict] = None) -> dict:
@@ -238,7 +245,7 @@ class Geometry:
             return dict(cache[key])
         t = _Tuning()
         _check(_lib.umbir_autotune(self.handle, _stream(stream), C.byref(t)), "umbir_autotune")
-        res = {"splat_blocks": t.splat_blocks, "gather_batch_kb": t.gather_batch_kb}
+        res = t.as_dict()
         if cache is not None:
             cache[key] = dict(res)
         return res

@@ -5,12 +5,17 @@
                the lossless operator
   icd          grouped ICD sweeps (umbir_reconstruct_icd) against the
                surrogate iteration of umbir_reconstruct, with the cost reached
+  sweeps       --reps A + A^T pairs of the plain operator on a dense random
+               image (the program a profiler wraps to count the sweep
+               kernels); --workload c2 (256 x 256) or c3 (512 x 512, with
+               --storage f32, f16 or bf16)
 
 Data are synthesised on the device (A x_true + seeded noise at the card's
 SNR).  Each line of output is one JSON record.
 
     python -m paper_2202_09703_amd.variants attenuation
     python -m paper_2202_09703_amd.variants icd
+    python -m paper_2202_09703_amd.variants sweeps --reps 5 --workload c2
 """
 from __future__ import annotations
 
@@ -92,15 +97,43 @@ def icd(umbir, dev, reps: int):
     geom.free()
 
 
+def sweeps(umbir, dev, reps: int, workload: str = "c2", storage: str = "f32"):
+    import torch
+    from synth import card_c2, card_c3
+    card = card_c2() if workload == "c2" else card_c3()
+    st = {"f32": umbir.STORAGE_F32, "f16": umbir.STORAGE_F16, "bf16": umbir.STORAGE_BF16}[storage]
+    card = dataclasses.replace(card, acq=dataclasses.replace(card.acq, storage=st))
+    geom = umbir.build_geometry(card)
+    work = geom.workspace(umbir.WORK_ADJOINT)
+    x = torch.randn(geom.image_shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    y = torch.empty(geom.trace_shape, dtype=geom.trace_dtype, device=dev)
+    xo = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        umbir.forward(geom, x, y, work=work)
+        umbir.adjoint(geom, y, xo, work=work)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"variant": "sweeps", "workload": card.name, "storage": storage, "pairs": reps,
+                      "a_plus_at_ms": dt * 1e3}), flush=True)
+    geom.free()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", choices=("attenuation", "icd"))
+    ap.add_argument("which", choices=("attenuation", "icd", "sweeps"))
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--workload", choices=("c2", "c3"), default="c2")
+    ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32")
     args = ap.parse_args()
     import torch
     from paper_2202_09703_amd import umbir
     dev = torch.device("cuda:0")
-    {"attenuation": attenuation, "icd": icd}[args.which](umbir, dev, args.reps)
+    if args.which == "sweeps":
+        sweeps(umbir, dev, args.reps, args.workload, args.storage)
+    else:
+        {"attenuation": attenuation, "icd": icd}[args.which](umbir, dev, args.reps)
 
 
 if __name__ == "__main__":

@@ -27,10 +27,13 @@ def f32(a, dev):
 
 
 @pytest.mark.parametrize("name,card", [("tiny", tiny_card(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=4)),
+                                       ("tiny-q32", tiny_card(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=13,
+                                                              n_samples=700, oversample=32)),
                                        ("c1", card_c1())])
 def test_tuning_changes_no_result(dev, name, card):
-    """Any splat split gives bitwise the same forward; gather batches change
-    only the order of the adjoint's cross-launch sums."""
+    """Any splat split, convolution tile order, correlation tile shape and
+    workgroup count gives bitwise the same forward and adjoint; gather
+    batches change only the order of the adjoint's cross-launch sums."""
     geom = umbir.build_geometry(card)
     g = card.grid
     x = f32(random_vector((g.nz, g.nx), seed=3), dev)
@@ -38,11 +41,21 @@ def test_tuning_changes_no_result(dev, name, card):
     y0, a0 = umbir.forward(geom, x), umbir.adjoint(geom, r)
     t0 = geom.tuning()
     assert t0["splat_blocks"] > 0 and t0["gather_batch_kb"] > 0
+    assert t0["conv_grid"] == 1 and t0["corr_tile_rows"] == 64 and t0["corr_blocks"] == 1024
+    for cg, rows, nb in [(2, 32, 1), (1, 128, 100000), (2, 64, 7)]:
+        geom.set_tuning(conv_grid=cg, corr_tile_rows=rows, corr_blocks=nb)
+        assert torch.equal(umbir.forward(geom, x), y0)
+        assert torch.equal(umbir.adjoint(geom, r), a0)
     for blocks, kb in [(1, 1), (geom.n_scans * geom.n_rx * 4, 64), (100000, 1 << 20)]:
         geom.set_tuning(splat_blocks=blocks, gather_batch_kb=kb)
         assert torch.equal(umbir.forward(geom, x), y0)
         a = umbir.adjoint(geom, r)
         assert torch.allclose(a, a0, rtol=1e-6, atol=1e-6 * float(a0.abs().max()))
+    with pytest.raises(umbir.UmbirError) as err:
+        geom.set_tuning(conv_grid=3)
+    assert err.value.status == umbir.EINVAL
+    with pytest.raises(umbir.UmbirError):
+        geom.set_tuning(corr_tile_rows=48)
     chosen = geom.autotune()
     assert chosen == geom.tuning() and chosen["splat_blocks"] > 0 and chosen["gather_batch_kb"] > 0
     assert torch.equal(umbir.forward(geom, x), y0)
@@ -102,6 +115,61 @@ def test_batch_members_match_oracle(dev, mode):
         assert xe <= 1e-5 and ce <= 1e-6
     for p in probs:
         p["geom"].free()
+
+
+def _q_cards(q):
+    """Uneven problems of one oversampling factor (work-list batches need one):
+    up to and beyond 1024 voxels (both fixed-point conversions of the splat)."""
+    return [dataclasses.replace(tiny_card(n_layers=3, nx=12, nz=10, n_scans=2, n_rx=3, n_samples=200,
+                                          oversample=q), n_iter=7),
+            dataclasses.replace(tiny_card(n_layers=2, nx=40, nz=30, n_scans=3, n_rx=4, n_samples=300,
+                                          oversample=q), n_iter=4),
+            dataclasses.replace(tiny_card(n_layers=4, nx=20, nz=14, n_scans=3, n_rx=2, n_samples=256,
+                                          oversample=q), n_iter=6)]
+
+
+@pytest.mark.parametrize("q", [32, 64])
+def test_worklist_batch(dev, q):
+    """The work-list batch (per lane one launch per stage over its problems'
+    work items, problems leaving as they reach their count) holds bitwise each
+    problem's one-at-a-time result, and that matches the oracle.  One problem
+    runs with small splat chunks and one-trace gather batches, so its items
+    cover several chunks and its gather items several batches."""
+    cards = _q_cards(q) + ([dataclasses.replace(card_c1(), n_iter=5)] if q == 64 else [])
+    data = [odata.synthesize(c)[1:] for c in cards]
+    probs = batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None, data=data)
+    probs[2]["geom"].set_tuning(splat_blocks=probs[2]["geom"].n_scans * probs[2]["geom"].n_rx * 4, gather_batch_kb=1)
+    _, plain = batch.run_plain(umbir, probs)
+    _, wl, n_batches = batch.run_batched(umbir, probs, umbir.BATCH_WORKLIST)
+    assert n_batches == 1
+    for c, (y, sigma), a, b in zip(cards, data, plain, wl):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]), c.name
+        assert b[2].numel() == c.n_iter + 1
+        xo, go, co = osv.sqs(c, y, sigma, c.prior, c.n_iter)
+        xe = rel(b[0].cpu().numpy(), xo)
+        ce = float(np.max(np.abs(b[2].cpu().numpy() - co) / np.abs(co)))
+        print(f"{c.name} ({c.n_iter} iterations) in the work-list batch: x {xe:.2e}, cost {ce:.2e}")
+        assert xe <= 1e-5 and ce <= 1e-6
+    for p in probs:
+        p["geom"].free()
+
+
+def test_worklist_batch_rejections(dev):
+    cards = [tiny_card(n_layers=3, oversample=32), tiny_card(n_layers=3, oversample=64)]
+    probs = batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None)
+    ss = batch.sessions(umbir, probs)
+    with pytest.raises(umbir.UmbirError) as err:  # two oversampling factors
+        umbir.Batch(ss, umbir.BATCH_WORKLIST)
+    assert err.value.status == umbir.ENOTSUP
+    for s in ss:
+        s.free()
+    probs8 = batch.prepare(umbir, [tiny_card(n_layers=3)], device=dev, log=lambda *a, **k: None)  # Q = 8
+    ss = batch.sessions(umbir, probs8)
+    with pytest.raises(umbir.UmbirError) as err:
+        umbir.Batch(ss, umbir.BATCH_WORKLIST)
+    assert err.value.status == umbir.ENOTSUP
+    for s in ss:
+        s.free()
 
 
 @pytest.mark.parametrize("mode", [0, 1])
