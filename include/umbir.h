@@ -302,9 +302,10 @@ void umbir_solver_free(umbir_solver* solver);
  *                          blocks of a launch walk a device work list of
  *                          (problem, tile) items of the uneven problems, and
  *                          the lanes' launches of one iteration are one
- *                          captured graph.  Needs FP32 storage, no attenuation
- *                          and one oversampling factor (32 or 64) across the
- *                          batch (ENOTSUP otherwise).
+ *                          captured graph.  Needs FP32 storage, no attenuation,
+ *                          the factored operator form and one oversampling
+ *                          factor (32 or 64) across the batch (ENOTSUP
+ *                          otherwise).
  *                          A session that reaches its max_iter leaves the
  *                          batch (its items are skipped from the next
  *                          iteration on), so one batch can be stepped to the
@@ -355,20 +356,31 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *  corr_blocks      target workgroup count of the correlation: each workgroup
  *                   walks ceil(traces x row blocks / corr_blocks) row blocks of
  *                   one trace with the taps staged once.  Bitwise identical.
+ *  operator_form    1: the factored form (default): A = splat then polyphase
+ *                   convolution, A^T = polyphase correlation then gather;
+ *                   2: the direct form of Eq. (13): every (trace, voxel) pair
+ *                   sums its window of L_h taps (A: one workgroup per trace
+ *                   accumulating its samples in LDS; A^T: per voxel over the
+ *                   traces).  The same operator summed in another order
+ *                   (results agree to rounding).  Direct needs FP32 storage,
+ *                   no attenuation and 8 M + 4 (Q L_h + 2) <= 65536 (ENOTSUP
+ *                   from umbir_set_tuning otherwise); it suits small problems.
  * A field of 0 (or less) in umbir_set_tuning keeps the current value (EINVAL
  * for a conv_grid or corr_tile_rows outside the values above).  The tuning of
  * a geometry must not change while another call uses it.
- * umbir_autotune times candidates of each field on `stream` (the forward for
- * the splat and the convolution, the adjoint for the correlation and the
- * gather, a dense all-ones image), applies the fastest and writes the chosen
- * values to *chosen (may be NULL); it allocates its own workspace and
- * synchronizes the stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+ * umbir_autotune times candidates of each field on `stream` (an A + A^T pair
+ * for the form, the forward for the splat and the convolution, the adjoint
+ * for the correlation and the gather, a dense all-ones image), applies the
+ * fastest and writes the chosen values to *chosen (may be NULL); it allocates
+ * its own workspace and synchronizes the stream.  Errors: EINVAL, ENOMEM,
+ * EDEVICE. */
 typedef struct {
     int splat_blocks;
     int gather_batch_kb;
     int conv_grid;
     int corr_tile_rows;
     int corr_blocks;
+    int operator_form;
 } umbir_tuning;
 int umbir_get_tuning(const umbir_geometry* geom, umbir_tuning* out);
 int umbir_set_tuning(umbir_geometry* geom, const umbir_tuning* tuning);

@@ -166,6 +166,7 @@ struct umbir_geometry {
   int conv_grid = 1;           // matrix-core convolution grid: 1 trace tiles fastest, 2 sample tiles fastest
   int corr_tiles = 2;          // 32-row tiles per wave of the matrix-core correlation (1, 2 or 4)
   int corr_blocks = 1024;      // target workgroups of the correlation (sets row blocks per workgroup)
+  int form = 1;                // operator form: 1 factored (splat + convolution), 2 direct (Eq. (13) tap by tap)
   // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)
   int n_gamma = 1;
   double gamma_step = 0.0;
@@ -221,9 +222,22 @@ int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 
 // y = base + sign * A x - g D   (base, g may be NULL; x NULL means all ones).
 // `abs_op` builds the operator from |W| and |h|.  Trace buffers (out, base) hold
-// the geometry's storage type; fine: G.fine_bytes() of workspace.
+// the geometry's storage type; fine: G.fine_bytes() of workspace.  With
+// pre_max the workspace already holds tau x for this x (as
+// run_prescale_blocks or the prior update leaves it), whose largest |tau x|
+// is the largest of the n_pre_max words at pre_max, and x is not read.
 int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base,
-                float sign, const float* g, bool abs_op, void* fine, hipStream_t s);
+                float sign, const float* g, bool abs_op, void* fine, hipStream_t s,
+                const unsigned* pre_max = nullptr, int n_pre_max = 0);
+
+// Can the direct form serve this geometry (FP32 storage, one template, the
+// forward's sample accumulators and template within 64 KiB of LDS)?
+bool direct_eligible(const umbir_geometry& G);
+
+// tau x into the forward's workspace `fine` and, per block of 64 voxels, the
+// largest |tau x| into maxima[blocks] (blocks * 64 >= the voxel count).
+int run_prescale_blocks(const umbir_geometry& G, const float* x, void* fine, unsigned* maxima, int blocks,
+                        hipStream_t s);
 
 // out = scale * A^T r (r in the storage type).  partial: trace_groups * N floats.
 int run_adjoint(const umbir_geometry& G, const void* r, float* out, float scale, bool abs_op,
@@ -264,7 +278,6 @@ struct BatchProb {
   int nx, nz, n_off, P, K, M, Q, qs, Lh, MQ;
   Segments seg;
   // launch shapes of the sweeps
-  int prescale_blocks;
   int chunk_bins, tile_bins, wide;  // splat
   int corr_per;                     // row blocks per correlation block
   int groups, tpg, gbatch, vpb;     // gather: trace groups, traces per group and launch, voxels per block
@@ -273,12 +286,12 @@ struct BatchProb {
   const float* y;
   float* e;
   float* fine;
-  float* xt;
-  unsigned* xmax;
+  float* xt;  // tau x of the current image (the splat's input), kept by the prior update
   float* partial;
   float* den;
   double* ess;
   double* pcost;
+  unsigned* pmax;  // per prior-update block (nblk) the largest |tau x| of its voxels
   float* x[2];  // the image before the batch's step 0, and the other buffer
   float* g;
   double* cost;
@@ -301,14 +314,13 @@ struct StageLaunch {
 };
 
 // Fills the sweep fields of bp from G (the launch shapes of the plain path)
-// and appends problem pi's items of the sweep stages (prescale, splat, conv,
-// corr, gather) to items[stage]; lds[stage] grows to what the problem needs.
+// and appends problem pi's items of the sweep stages (splat, conv, corr,
+// gather) to items[stage]; lds[stage] grows to what the problem needs.
 // Gather items carry the index of their launch (batch of traces) in .w.
 void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int4>* items, size_t* lds);
 
-// Launches one sweep stage over the batch; `which` selects the input image
-// of the prescale (probs[i].x[which]); items of problem i run only while
-// active[i] is nonzero.
+// Launches one sweep stage (splat, conv, corr, gather) over the batch; items
+// of problem i run only while active[i] is nonzero.
 int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* active, const StageLaunch& L, int which,
                        hipStream_t s);
 

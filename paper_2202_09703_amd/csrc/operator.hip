@@ -236,7 +236,8 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   // the largest |tau x| over the prescale blocks' maxima (n_xmax <= blockDim.x)
   __shared__ unsigned wave_max[kSplatWaves];
   {
-    unsigned m = int(threadIdx.x) < n_xmax ? xmax[threadIdx.x] : 0u;
+    unsigned m = 0u;
+    for (int i = threadIdx.x; i < n_xmax; i += blockDim.x) m = max(m, xmax[i]);
     for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
     if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
   }
@@ -412,6 +413,146 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   splat_body<ABSW, WIDE, ST, ATT, MT>(blockIdx.x, blockIdx.y, xt, nx, n_off, legs, gunit, base, P, K, qs, MQ, seg, chunk_bins, tile_bins, xmax, n_xmax, gbin, glast, bs, fine);
+}
+
+// ---- the direct (unfactored) form of Eq. (13), an alternative for small
+// problems: every (trace, voxel) pair sums its own window of L_h taps, as the
+// equation is written, instead of the splat + polyphase convolution.  With
+// z = (m - D) Q = n - phi, n = m Q - J, the tap is
+//     I = (1 - phi) b[n] + phi b[n - 1],   1 <= n <= Q L_h
+// (b is zero at both ends of its window), the same interpolation as the
+// factored form, only summed in another order.
+
+// Bytes of LDS the direct forward needs (64-bit sample accumulators and the
+// template); the direct form is offered when this fits 64 KiB.
+size_t direct_fwd_lds(const umbir_geometry& G) {
+  return size_t(G.M) * sizeof(unsigned long long) + (size_t(G.Q) * G.Lh + 2) * sizeof(float);
+}
+
+// A = direct: one block per trace; the trace's M samples accumulate in LDS in
+// 64-bit fixed point (scale 2^k from max|tau x| as the splat's, so the sum is
+// exact and independent of the order of the adds), then
+//   out[m] = (base ? base[m] : 0) + sign * y[m] - (g ? g[ij] d_ij[m] : 0).
+template <bool ABSW, bool WIDE>
+__global__ __launch_bounds__(1024) void k_fwd_direct(
+    const float* __restrict__ xt, int nx, int rows, int n_off, const Leg* __restrict__ legs,
+    const int* __restrict__ base_off, int P, int K, int qs, int Lh, int M, const float* __restrict__ bank,
+    const unsigned* __restrict__ xmax, int n_xmax, const float* ybase, float sign, const float* __restrict__ g,
+    const float* __restrict__ dbasis, float* out) {
+  extern __shared__ unsigned long long dsm[];
+  unsigned long long* acc = dsm;                           // [M]
+  float* b = reinterpret_cast<float*>(dsm + M);            // [Q Lh + 2]
+  const int Q = 1 << qs;
+  const int QLh = Q * Lh;
+  const int ij = blockIdx.x;
+  const int btx = base_off[ij / K], brx = base_off[P + ij];
+  const int half = n_off / 2;
+  const int N = nx * rows;
+  __shared__ unsigned wave_max[16];
+  {
+    unsigned m = 0;
+    for (int i = threadIdx.x; i < n_xmax; i += blockDim.x) m = max(m, xmax[i]);
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
+  }
+  for (int i = threadIdx.x; i < M; i += blockDim.x) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < QLh + 2; i += blockDim.x) b[i] = ABSW ? fabsf(bank[i]) : bank[i];
+  __syncthreads();
+  unsigned maxbits = 0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) maxbits = max(maxbits, wave_max[w]);
+  const int kx = splat_exponent(maxbits, N);
+  const double scale = ldexp(1.0, kx);
+  for (int v = threadIdx.x; v < N; v += blockDim.x) {
+    const float xv = xt[v];
+    if (xv == 0.0f) continue;
+    const int row = v / nx, col = v - row * nx;
+    const Leg a = legs[size_t(row) * n_off + leg_slot(abs(btx + 2 * col), half)];
+    const Leg c = legs[size_t(row) * n_off + leg_slot(abs(brx + 2 * col), half)];
+    const uint64_t D = uint64_t(a.delay + c.delay);
+    const long J = long(D >> (32 - qs));
+    const float phi = float(uint32_t(D) << qs) * kTwoM32;
+    float w = xv * (a.apod * c.apod);
+    if (ABSW) w = fabsf(w);
+    const long m_lo = max((J + Q) >> qs, 0L);                 // first m with n = m Q - J >= 1
+    const long m_hi = min((J + QLh) >> qs, long(M) - 1);      // last m with n <= Q L_h
+    for (long m = m_lo; m <= m_hi; ++m) {
+      const int n = int(m * Q - J);
+      const float tap = fmaf(phi, b[n - 1] - b[n], b[n]);
+      atomicAdd(&acc[m], to_fixed<WIDE>(w * tap, scale));
+    }
+  }
+  __syncthreads();
+  const float gv = g ? g[ij] : 0.0f;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const size_t idx = size_t(ij) * M + m;
+    float val = sign * ldexpf(float((long long)acc[m]), -kx);
+    if (ybase) val += ybase[idx];
+    if (g) val -= gv * dbasis[idx];
+    out[idx] = val;
+  }
+}
+
+// A^T = direct: per voxel, over the traces of group blockIdx.x, W times the
+// window's sum of r[m] times the tap; one partial image per group (summed in
+// a fixed order like the gather's).  The template sits in LDS.
+template <bool ABSW, int VPT>
+__global__ __launch_bounds__(256) void k_adj_direct(
+    const float* __restrict__ rt, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const float* __restrict__ tau, const int* __restrict__ base_off, int P, int K, int qs, int Lh, int M,
+    const float* __restrict__ bank, int tpg, int vox_per_block, float* __restrict__ partial) {
+  extern __shared__ float bsm[];  // [Q Lh + 2]
+  const int Q = 1 << qs;
+  const int QLh = Q * Lh;
+  for (int i = threadIdx.x; i < QLh + 2; i += blockDim.x) bsm[i] = ABSW ? fabsf(bank[i]) : bank[i];
+  __syncthreads();
+  const int N = nx * nz;
+  const int PK = P * K;
+  const int half = n_off / 2;
+  const int v_begin = blockIdx.y * vox_per_block;
+  const int v_end = min(N, v_begin + vox_per_block);
+  const int t0 = blockIdx.x * tpg, t1 = min(t0 + tpg, PK);
+  for (int vc = v_begin; vc < v_end; vc += blockDim.x * VPT) {
+    float acc[VPT];
+    int row[VPT], col2[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int v = min(vc + u * int(blockDim.x) + int(threadIdx.x), v_end - 1);
+      row[u] = v / nx;
+      col2[u] = 2 * (v - row[u] * nx);
+      acc[u] = 0.0f;
+    }
+    for (int t = t0; t < t1; ++t) {
+      const int btx = base_off[t / K], brx = base_off[P + t];
+      const float* r = rt + size_t(t) * M;
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const Leg a = legs[size_t(row[u]) * n_off + leg_slot(abs(btx + col2[u]), half)];
+        const Leg c = legs[size_t(row[u]) * n_off + leg_slot(abs(brx + col2[u]), half)];
+        const uint64_t D = uint64_t(a.delay + c.delay);
+        const long J = long(D >> (32 - qs));
+        const float phi = float(uint32_t(D) << qs) * kTwoM32;
+        float w = a.apod * c.apod;
+        if (ABSW) w = fabsf(w);
+        const long m_lo = max((J + Q) >> qs, 0L);
+        const long m_hi = min((J + QLh) >> qs, long(M) - 1);
+        float s = 0.0f;
+        for (long m = m_lo; m <= m_hi; ++m) {
+          const int n = int(m * Q - J);
+          s = fmaf(r[m], fmaf(phi, bsm[n - 1] - bsm[n], bsm[n]), s);
+        }
+        acc[u] = fmaf(w, s, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int v = vc + u * int(blockDim.x) + int(threadIdx.x);
+      if (v < v_end) {
+        float tr = tau[v / nx];
+        if (ABSW) tr = fabsf(tr);
+        partial[size_t(blockIdx.x) * N + v] = acc[u] * tr;
+      }
+    }
+  }
 }
 
 // One fine-grid sample through a buffer resource over one trace: positions
@@ -1449,13 +1590,13 @@ int prescale_blocks(const umbir_geometry& G) {
 
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs, int MQ, const Segments& seg,
-                    const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
+                    const unsigned* xmax, int n_xmax, int gbin, void* fine, hipStream_t s) {
   using T = typename Store<ST>::T;
   const int nt = MT ? G.n_gamma : 1;
   const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
   const size_t lds = size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
-               G.n_off, G.legs, G.gunit, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, prescale_blocks(G), gbin,
+               G.n_off, G.legs, G.gunit, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, n_xmax, gbin,
                G.n_gamma - 1,
                bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine));
 }
@@ -1464,14 +1605,14 @@ void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs,
 // MT (with ATT): one pass over every template's grid
 template <int ST, bool ATT, bool MT = false>
 void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, const float* xt, int qs, int MQ,
-                  const Segments& seg, const unsigned* xmax, int gbin, void* fine, hipStream_t s) {
+                  const Segments& seg, const unsigned* xmax, int n_xmax, int gbin, void* fine, hipStream_t s) {
   const bool wide = G.nx * (seg.hi[seg.n - 1] - seg.lo[0]) < kSplatNarrowMin;
   if (abs_op) {
-    if (wide) launch_splat_k<true, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
-    else launch_splat_k<true, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    if (wide) launch_splat_k<true, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
+    else launch_splat_k<true, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
   } else {
-    if (wide) launch_splat_k<false, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
-    else launch_splat_k<false, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, gbin, fine, s);
+    if (wide) launch_splat_k<false, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
+    else launch_splat_k<false, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
   }
 }
 
@@ -1520,18 +1661,6 @@ void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int 
 // gets bitwise the result of its own launches.  A barrier separates items (a
 // block reuses its LDS).
 
-__global__ __launch_bounds__(1024) void k_prescale_list(const BatchProb* __restrict__ probs,
-                                                        const int* __restrict__ active,
-                                                        const int4* __restrict__ items, int n_items, int which) {
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const int4 w = items[it];
-    if (!active[w.x]) continue;  // uniform: the problem left the batch
-    const BatchProb& p = probs[w.x];
-    prescale_body(w.y, p.prescale_blocks, p.x[which], p.tau, p.nx, p.nx * p.nz, p.xt, p.xmax);
-    __syncthreads();
-  }
-}
-
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat_list(const BatchProb* __restrict__ probs,
                                                                  const int* __restrict__ active,
                                                                  const int4* __restrict__ items, int n_items) {
@@ -1543,11 +1672,11 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat_list(const BatchProb
     if (p.wide)
       splat_body<false, true, UMBIR_STORAGE_F32, false, false>(
           w.y, w.z, p.xt, p.nx, p.n_off, p.legs, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg, p.chunk_bins,
-          p.tile_bins, p.xmax, p.prescale_blocks, 0, 0, none, p.fine);
+          p.tile_bins, p.pmax, p.nblk, 0, 0, none, p.fine);
     else
       splat_body<false, false, UMBIR_STORAGE_F32, false, false>(
           w.y, w.z, p.xt, p.nx, p.n_off, p.legs, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg, p.chunk_bins,
-          p.tile_bins, p.xmax, p.prescale_blocks, 0, 0, none, p.fine);
+          p.tile_bins, p.pmax, p.nblk, 0, 0, none, p.fine);
     __syncthreads();
   }
 }
@@ -1632,9 +1761,6 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
     bp.seg.lo[k] = G.seg_lo[k];
     bp.seg.hi[k] = G.seg_hi[k];
   }
-  // prescale
-  bp.prescale_blocks = prescale_blocks(G);
-  for (int b = 0; b < bp.prescale_blocks; ++b) items[kStPrescale].push_back(make_int4(pi, b, 0, 0));
   // splat: as launch_splat_k without attenuation
   bp.chunk_bins = int(G.chunk_bins);
   bp.tile_bins = G.tile_bins;
@@ -1683,9 +1809,6 @@ int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* acti
   if (L.n_items == 0) return UMBIR_OK;
   const dim3 grid(unsigned(L.grid));
   switch (stage) {
-    case kStPrescale:
-      UMBIR_LAUNCH("prescale", k_prescale_list, grid, dim3(1024), L.lds, s, probs, active, L.items, L.n_items, which);
-      break;
     case kStSplat:
       UMBIR_LAUNCH("splat", k_splat_list, grid, dim3(64 * kSplatWaves), L.lds, s, probs, active, L.items, L.n_items);
       break;
@@ -1727,12 +1850,26 @@ int log2_int(int q) {
   return k;
 }
 
+
+bool direct_eligible(const umbir_geometry& G) {
+  return G.storage == UMBIR_STORAGE_F32 && G.n_gamma == 1 && direct_fwd_lds(G) <= 65536;
+}
+
+int run_prescale_blocks(const umbir_geometry& G, const float* x, void* fine, unsigned* maxima, int blocks,
+                        hipStream_t s) {
+  float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.grids_bytes());
+  UMBIR_LAUNCH("prescale", k_prescale, dim3(unsigned(blocks)), dim3(64), 0, s, x, G.tau, G.nx, G.voxels(), xt,
+               maxima);
+  return check_hip(hipGetLastError(), "k_prescale");
+}
+
 int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base, float sign,
-                const float* g, bool abs_op, void* fine, hipStream_t s) {
+                const float* g, bool abs_op, void* fine, hipStream_t s, const unsigned* pre_max, int n_pre_max) {
   // after the fine grid(s): the prescaled image tau x, then one 32-bit
   // scalar, the largest |tau x|
   float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.grids_bytes());
   unsigned* xmax = reinterpret_cast<unsigned*>(static_cast<char*>(fine) + G.fine_bytes() - 4 * kPrescaleBlocks);
+  int n_xmax = prescale_blocks(G);
   const int MQ = int(G.fine_per_trace());
   const int qs = log2_int(G.Q);
   Segments seg;
@@ -1741,14 +1878,45 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     seg.lo[k] = G.seg_lo[k];
     seg.hi[k] = G.seg_hi[k];
   }
-  UMBIR_LAUNCH("prescale", k_prescale, dim3(prescale_blocks(G)), dim3(1024), 0, s, x, G.tau, G.nx, G.voxels(), xt,
-               xmax);
+  if (pre_max) {  // tau x is in place, its maxima given
+    xmax = const_cast<unsigned*>(pre_max);
+    n_xmax = n_pre_max;
+  } else {
+    UMBIR_LAUNCH("prescale", k_prescale, dim3(prescale_blocks(G)), dim3(1024), 0, s, x, G.tau, G.nx, G.voxels(), xt,
+                 xmax);
+  }
   dim3 grid(G.chunks, G.traces());
+  if (G.form == 2) {  // the direct form (FP32, one template; see direct_eligible)
+    const bool wide = G.voxels() < kSplatNarrowMin;
+    const size_t lds = direct_fwd_lds(G);
+    const float* yb = static_cast<const float*>(base);
+    float* yo = static_cast<float*>(out);
+    if (abs_op) {
+      if (wide)
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<true, true>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz,
+                     G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb, sign, g,
+                     G.dbasis, yo);
+      else
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<true, false>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz,
+                     G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb, sign, g,
+                     G.dbasis, yo);
+    } else {
+      if (wide)
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<false, true>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz,
+                     G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb, sign, g,
+                     G.dbasis, yo);
+      else
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<false, false>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx,
+                     G.nz, G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb,
+                     sign, g, G.dbasis, yo);
+    }
+    return check_hip(hipGetLastError(), "k_fwd_direct");
+  }
   if (G.multi_grid() && splat_mt_tile(G) > 0) {
     // attenuation with every template's grid resident: one splat walk fills
     // them all ([template][trace][position]), then one convolution per
     // template; later ones add to the traces the first one wrote
-    launch_splat<UMBIR_STORAGE_F32, true, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
+    launch_splat<UMBIR_STORAGE_F32, true, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
     int st = check_hip(hipGetLastError(), "k_splat");
     if (st) return st;
     for (int gb = 0; gb < G.n_gamma; ++gb) {
@@ -1764,16 +1932,16 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   for (int gb = 0; gb < G.n_gamma; ++gb) {
     switch (G.storage) {
       case UMBIR_STORAGE_F16:
-        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
+        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
         break;
       case UMBIR_STORAGE_BF16:
-        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
+        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
         break;
       default:
         if (G.n_gamma > 1)
-          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, gb, fine, s);
+          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, gb, fine, s);
         else
-          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, 0, fine, s);
+          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
         break;
     }
     int st = check_hip(hipGetLastError(), "k_splat");
@@ -1796,6 +1964,17 @@ int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, voi
   nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
   const int vpb = (G.voxels() + nb - 1) / nb;
   dim3 grid(G.trace_groups, nb);
+  if (G.form == 2) {  // the direct form: every trace of a group in one pass
+    const size_t lds = (size_t(G.Q) * G.Lh + 2) * sizeof(float);
+    const float* rr = static_cast<const float*>(r);
+    if (abs_op)
+      UMBIR_LAUNCH("adj_direct", (k_adj_direct<true, 4>), grid, dim3(256), lds, s, rr, G.nx, G.nz, G.n_off, G.legs,
+                   G.tau, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, tpg, vpb, partial);
+    else
+      UMBIR_LAUNCH("adj_direct", (k_adj_direct<false, 4>), grid, dim3(256), lds, s, rr, G.nx, G.nz, G.n_off, G.legs,
+                   G.tau, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, tpg, vpb, partial);
+    return check_hip(hipGetLastError(), "k_adj_direct");
+  }
   // traces per launch: batches of gather_batch_kb of fine-grid data per group
   // (4 MiB by default, one XCD's L2: the autotuner's choice on the 256 x 256
   // and 512 x 512 workloads, 1-2 % faster per reconstruction than 8 MiB and
@@ -1897,8 +2076,10 @@ size_t umbir_workspace_bytes(const umbir_geometry* G, int kind) {
       // curvature, reductions) plus the two images of the ping-pong
       const size_t N = G->voxels(), PK = G->traces();
       const size_t nblk = (N + kPriorVox - 1) / kPriorVox + 1;
+      // + the prior update's per-block image maxima and its arrival counter
       return adjoint_work_bytes(*G) + aligned(G->trace_bytes()) + 3 * aligned(N * sizeof(float)) +
-             aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + 16 * 256;
+             aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + aligned(nblk * sizeof(unsigned)) +
+             256 + 16 * 256;
     }
     default: return 0;
   }
@@ -1982,6 +2163,23 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
   };
   auto forward = [&]() { return run_forward(*G, nullptr, traces, nullptr, 1.0f, nullptr, false, fine, s); };
   auto adjoint = [&]() { return run_adjoint(*G, traces, img, 1.0f, false, fine, partial, s); };
+  // the operator's form: factored (splat + convolution, correlation +
+  // gather) or direct, for an A + A^T pair with the current launch shapes
+  if (direct_eligible(*G)) {
+    int best_form = G->form;
+    float best_pair = 3.4e38f;
+    for (int f : {1, 2}) {
+      G->form = f;
+      float ms = 0.0f;
+      if ((st = time_ms([&]() {
+             int r = forward();
+             return r ? r : adjoint();
+           }, &ms)))
+        break;
+      if (ms < best_pair) { best_pair = ms; best_form = f; }
+    }
+    G->form = best_form;
+  }
   // the splat: one to four chunks per trace, and fixed workgroup targets
   const long PK = G->traces();
   std::vector<long> cand = {PK, 2 * PK, 4 * PK, 1024, 2048, 4096};
@@ -2045,6 +2243,7 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     chosen->conv_grid = G->conv_grid;
     chosen->corr_tile_rows = 32 * G->corr_tiles;
     chosen->corr_blocks = G->corr_blocks;
+    chosen->operator_form = G->form;
   }
   return UMBIR_OK;
 }

@@ -164,12 +164,21 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
 // butterfly over the four lanes).  Four lanes per voxel, two of its eight
 // neighbours each (then summed across the four lanes); the depth modulation
 // of the rows the block touches is tabulated once per block.
+// With xt set, the prior update also prepares the next forward: xt = tau
+// x_out, and per block the largest |tau x_out| of its voxels into pmax[block]
+// (as float bits), from which the forward's splat takes the largest.
+struct PriorFuse {
+  const float* tau;
+  float* xt;
+  unsigned* pmax;
+};
+
 template <bool UPDATE>
 __device__ __forceinline__ void prior_body(int bx, int by, const float* __restrict__ x,
                                                          const float* __restrict__ part, int groups,
                                                          const float* __restrict__ den, int nx, int nz,
                                                          PriorConst pc, float* __restrict__ xout,
-                                                         double* __restrict__ pcost) {
+                                                         double* __restrict__ pcost, const PriorFuse& fz) {
   __shared__ double sh[4];
   __shared__ float ms_tab[kPriorVox + 4];  // rows r_lo ..: the block's rows and one on each side
   const float b_edge = float(1.0 / (4.0 + 2.0 * M_SQRT2));
@@ -224,14 +233,29 @@ __device__ __forceinline__ void prior_body(int bx, int by, const float* __restri
     u += __shfl_xor(u, 1, 64);
     u += __shfl_xor(u, 2, 64);
   }
+  unsigned mbits = 0;  // |tau x_out| as float bits (non-negative floats order like their bits)
   if (UPDATE && v < N && q == 0) {
     const float grad = fmaf(-u, pc.inv_sigma2, slope);
-    xout[v] = xs - grad / (dv + curv);
+    const float xn = xs - grad / (dv + curv);
+    xout[v] = xn;
+    if (fz.xt) {
+      const float t = fz.tau[row] * xn;
+      fz.xt[v] = t;
+      mbits = __float_as_uint(fabsf(t));
+    }
   }
   for (int off = 32; off > 0; off >>= 1) cost += __shfl_down(cost, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cost;
+  __shared__ unsigned wmax[4];
+  if (UPDATE && fz.xt) {
+    for (int off = 32; off >= 1; off >>= 1) mbits = max(mbits, unsigned(__shfl_xor(int(mbits), off)));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mbits;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) pcost[bx] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) {
+    pcost[bx] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    if (UPDATE && fz.xt) fz.pmax[bx] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+  }
 }
 
 template <bool UPDATE>
@@ -240,7 +264,18 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior(const float* __restrict
                                                          const float* __restrict__ den, int nx, int nz,
                                                          PriorConst pc, float* __restrict__ xout,
                                                          double* __restrict__ pcost) {
-  prior_body<UPDATE>(blockIdx.x, blockIdx.y, x, part, groups, den, nx, nz, pc, xout, pcost);
+  prior_body<UPDATE>(blockIdx.x, blockIdx.y, x, part, groups, den, nx, nz, pc, xout, pcost, PriorFuse{});
+}
+
+// The prior update with the cost (and, updating, the forward's prescale of
+// x_out) folded in: see PriorFuse.
+template <bool UPDATE>
+__global__ __launch_bounds__(4 * kPriorVox) void k_prior_fused(const float* __restrict__ x,
+                                                               const float* __restrict__ part, int groups,
+                                                               const float* __restrict__ den, int nx, int nz,
+                                                               PriorConst pc, float* __restrict__ xout,
+                                                               double* __restrict__ pcost, PriorFuse fz) {
+  prior_body<UPDATE>(blockIdx.x, blockIdx.y, x, part, groups, den, nx, nz, pc, xout, pcost, fz);
 }
 
 // Cost = data term + prior term, written to out[*counter] (then the counter
@@ -295,7 +330,8 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior_list(const BatchProb* _
     const int4 w = items[it];
     if (!active[w.x]) continue;
     const BatchProb& p = probs[w.x];
-    prior_body<true>(w.y, 0, p.x[which], p.partial, p.groups, p.den, p.nx, p.nz, p.pc, p.x[which ^ 1], p.pcost);
+    const PriorFuse fz{p.tau, p.xt, p.pmax};
+    prior_body<true>(w.y, 0, p.x[which], p.partial, p.groups, p.den, p.nx, p.nz, p.pc, p.x[which ^ 1], p.pcost, fz);
     __syncthreads();
   }
 }
@@ -351,6 +387,7 @@ struct IterBuffers {
   float* den;
   double* ess;
   double* pcost;
+  unsigned* pmax;  // the prior update's per-block maxima of |tau x|
   int nblk;
 };
 
@@ -364,13 +401,15 @@ IterBuffers carve_iter(Carve& cv, const umbir_geometry& G) {
   b.den = cv.take<float>(N);
   b.ess = cv.take<double>(PK);
   b.pcost = cv.take<double>(b.nblk);
+  b.pmax = cv.take<unsigned>(b.nblk);
   return b;
 }
 
 size_t iter_bytes(const umbir_geometry& G) {
   const size_t N = G.voxels(), PK = G.traces();
+  const size_t nblk = (N + kPriorVox - 1) / kPriorVox + 1;
   return adjoint_work_bytes(G) + aligned(G.trace_bytes()) + aligned(N * sizeof(float)) +
-         aligned(PK * sizeof(double)) + aligned(((N + kPriorVox - 1) / kPriorVox + 1) * sizeof(double)) + 8 * 256;
+         aligned(PK * sizeof(double)) + aligned(nblk * sizeof(double)) + aligned(nblk * sizeof(unsigned)) + 8 * 256;
 }
 
 int enqueue_curvature(const umbir_geometry& G, const IterBuffers& b, const PriorConst& pc, hipStream_t s) {
@@ -385,7 +424,10 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
                       int est, const void* y, const float* x_in, float* x_out, float* g, bool last,
                       double* cost_out, int* counter, hipStream_t s) {
   const int PK = G.traces();
-  int st = run_forward(G, x_in, b.e, y, -1.0f, g, false, b.fine, s);
+  // the workspace holds tau x_in and its block maxima (from
+  // run_prescale_blocks before the first iteration, from the previous
+  // iteration's prior update after that)
+  int st = run_forward(G, x_in, b.e, y, -1.0f, g, false, b.fine, s, b.pmax, b.nblk);
   if (st) return st;
   switch (G.storage) {
     case UMBIR_STORAGE_F16:
@@ -406,10 +448,12 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
     UMBIR_LAUNCH("prior", k_prior<false>, dim3(b.nblk), dim3(4 * kPriorVox), 0, s, x_in, nullptr, 0, nullptr, G.nx,
                  G.nz, pc, nullptr, b.pcost);
   } else {
+    // the update also puts tau x_out and its block maxima in place for the
+    // next iteration's forward
     if ((st = run_adjoint_partial(G, b.e, false, b.fine, b.partial, s))) return st;
-    UMBIR_LAUNCH("prior", k_prior<true>, dim3(b.nblk), dim3(4 * kPriorVox), 0, s, x_in, b.partial, G.trace_groups, b.den,
-                 G.nx, G.nz, pc,
-                 x_out, b.pcost);
+    const PriorFuse fz{G.tau, reinterpret_cast<float*>(static_cast<char*>(b.fine) + G.grids_bytes()), b.pmax};
+    UMBIR_LAUNCH("prior", k_prior_fused<true>, dim3(b.nblk), dim3(4 * kPriorVox), 0, s, x_in, b.partial,
+                 G.trace_groups, b.den, G.nx, G.nz, pc, x_out, b.pcost, fz);
   }
   if ((st = check_hip(hipGetLastError(), "k_prior"))) return st;
   if (cost_out) {
@@ -418,6 +462,12 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
     if ((st = check_hip(hipGetLastError(), "k_cost"))) return st;
   }
   return UMBIR_OK;
+}
+
+// Before the first iteration from x: tau x and its block maxima into place
+// for the forward (the iterations' prior updates keep them in place after).
+int enqueue_start(const umbir_geometry& G, const IterBuffers& b, const float* x, hipStream_t s) {
+  return run_prescale_blocks(G, x, b.fine, b.pmax, b.nblk, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -907,8 +957,8 @@ int worklist_graph(umbir_batch* B, int which, hipGraphExec_t* out) {
 // Builds one lane: its problems' arguments, active flags and work lists (the
 // launch shapes of each problem's own iteration, so every problem gets
 // bitwise the result of stepping it alone), uploaded to one device buffer,
-// and its launches: prescale, splat, convolution, g step, correlation, one
-// gather launch per batch of traces, prior update, cost.  Each launch has a
+// and its launches: splat, convolution, g step, correlation, one gather
+// launch per batch of traces, prior update (with the next prescale), cost.  Each launch has a
 // block per item, so the lanes' launches interleave on the device.
 int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
   const int n = int(L.members.size());
@@ -924,11 +974,11 @@ int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
     bp.e = static_cast<float*>(S->b.e);
     bp.fine = static_cast<float*>(S->b.fine);
     bp.xt = reinterpret_cast<float*>(static_cast<char*>(S->b.fine) + G.grids_bytes());
-    bp.xmax = reinterpret_cast<unsigned*>(static_cast<char*>(S->b.fine) + G.fine_bytes() - 4 * kPrescaleBlocks);
     bp.partial = S->b.partial;
     bp.den = S->b.den;
     bp.ess = S->b.ess;
     bp.pcost = S->b.pcost;
+    bp.pmax = S->b.pmax;
     bp.nblk = S->b.nblk;
     bp.x[0] = S->parity ? S->xb : S->xa;  // the current image
     bp.x[1] = S->parity ? S->xa : S->xb;
@@ -942,6 +992,8 @@ int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
     for (int b = 0; b < S->b.nblk; ++b) items[kStPrior].push_back(make_int4(i, b, 0, 0));
     items[kStCost].push_back(make_int4(i, 0, 0, 0));
   }
+  // (no prescale launch: the prior update keeps each session's tau x of its
+  // current image and the block maxima in place)
   // the gather's items by launch (batch index), in problem order within one
   std::stable_sort(items[kStGather].begin(), items[kStGather].end(),
                    [](const int4& a, const int4& b) { return a.w < b.w; });
@@ -986,7 +1038,7 @@ int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
         add(k, dev_items[k] + a, int(b - a));
         a = b;
       }
-    } else {
+    } else if (!items[k].empty()) {
       add(k, dev_items[k], int(items[k].size()));
     }
   }
@@ -1102,6 +1154,7 @@ int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const void
 
   if ((st = enqueue_curvature(*G, b, pc, s))) return st;
   if ((st = launch_copy(xa, x_io, N, s))) return st;
+  if ((st = enqueue_start(*G, b, xa, s))) return st;
   for (int it = 0; it <= n_iter; ++it) {
     const bool last = it == n_iter;
     if ((st = enqueue_iteration(*G, b, pc, inv_2s2, est, y, xa, xb, g_io, last, cost ? cost + it : nullptr,
@@ -1271,7 +1324,7 @@ int umbir_solver_create(const umbir_geometry* G, const umbir_prior* pr, const vo
                       "hipMemcpyAsync(y)")) ||
       (st = x0_dev ? launch_copy(S->xa, x0_dev, N, s) : launch_fill(S->xa, N, 0.0f, s)) ||
       (st = g0_dev ? launch_copy(S->g, g0_dev, PK, s) : launch_fill(S->g, PK, 0.0f, s)) ||
-      (st = enqueue_curvature(*G, S->b, S->pc, s))) {
+      (st = enqueue_curvature(*G, S->b, S->pc, s)) || (st = enqueue_start(*G, S->b, S->xa, s))) {
     (void)hipStreamSynchronize(s);
     solver_release(S);
     return st;
@@ -1354,9 +1407,10 @@ int umbir_batch_create(umbir_solver* const* sessions, int n, int mode, umbir_bat
     const int q = sessions[0]->G->Q;
     for (int i = 0; i < n; ++i) {
       const umbir_geometry& G = *sessions[i]->G;
-      if (G.storage != UMBIR_STORAGE_F32 || G.n_gamma != 1 || (G.Q != 32 && G.Q != 64) || G.Q != q)
+      if (G.storage != UMBIR_STORAGE_F32 || G.n_gamma != 1 || (G.Q != 32 && G.Q != 64) || G.Q != q || G.form != 1)
         return fail(UMBIR_ENOTSUP,
-                    "persistent batches need FP32 storage, one template and one oversampling factor of 32 or 64");
+                    "work-list batches need FP32 storage, one template, the factored operator and one "
+                    "oversampling factor of 32 or 64");
     }
   }
   auto* B = new umbir_batch();

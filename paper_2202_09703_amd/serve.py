@@ -73,16 +73,24 @@ class Server:
     finish(handle) -> (x, cost);  release(handle);  now() -> seconds;
     wait(dt) (sleep or advance a simulated clock)."""
 
-    def __init__(self, executor, hbm_budget: int, max_slots: int = 8, chunk: int = 5):
-        if chunk < 1 or max_slots < 1:
+    def __init__(self, executor, hbm_budget: int, max_slots: int = 8, chunk=5):
+        """chunk: iterations queued per step of a request, one number or a
+        mapping from request kind to number (kinds not listed take 5)."""
+        chunks = chunk.values() if isinstance(chunk, dict) else [chunk]
+        if any(int(c) < 1 for c in chunks) or max_slots < 1:
             raise ValueError("chunk and max_slots must be >= 1")
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
-        self.chunk = int(chunk)
+        self.chunk = dict(chunk) if isinstance(chunk, dict) else int(chunk)
         self.rejected: List[int] = []
         self.peak_bytes = 0
         self.peak_slots = 0
+
+    def chunk_of(self, req: Request) -> int:
+        if isinstance(self.chunk, dict):
+            return int(self.chunk.get(req.kind, 5))
+        return self.chunk
 
     def run(self, requests: List[Request]) -> List[Result]:
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -113,7 +121,7 @@ class Server:
                 if not self.ex.idle(slot.handle):
                     continue
                 if slot.queued < slot.req.n_iter:
-                    n = min(self.chunk, slot.req.n_iter - slot.queued)
+                    n = min(self.chunk_of(slot.req), slot.req.n_iter - slot.queued)
                     self.ex.advance(slot.handle, n)
                     slot.queued += n
                     progressed = True
@@ -215,9 +223,16 @@ def plain_run(umbir, requests: List[Request], now: Callable[[], float] = time.pe
 def summarize(results: List[Result]) -> Dict[str, float]:
     lat = np.array([r.latency for r in results]) * 1e3
     span = max(r.finished for r in results) - min(r.arrival for r in results)
-    return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-            "recon_per_s": len(results) / span, "span_s": span}
+    out = {"requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+           "recon_per_s": len(results) / span, "span_s": span}
+    kinds = sorted({r.kind for r in results})
+    if len(kinds) > 1:
+        out["per_kind"] = {k: {"requests": int(sum(r.kind == k for r in results)),
+                               "p50_ms": float(np.percentile([r.latency * 1e3 for r in results if r.kind == k], 50)),
+                               "p99_ms": float(np.percentile([r.latency * 1e3 for r in results if r.kind == k], 99))}
+                           for k in kinds}
+    return out
 
 
 # ---------------------------------------------------------------- workload
@@ -268,7 +283,9 @@ def main():
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of plain-path capacity")
     ap.add_argument("--budget-gb", type=float, default=2.0)
     ap.add_argument("--slots", type=int, default=8)
-    ap.add_argument("--chunk", type=int, default=5)
+    ap.add_argument("--chunk", type=int, default=5, help="iterations per scheduling step (c2 and c3 requests)")
+    ap.add_argument("--chunk-small", type=int, default=50,
+                    help="iterations per scheduling step of the small (64 x 64) requests")
     ap.add_argument("--seed", type=int, default=5)
     args = ap.parse_args()
     import torch
@@ -292,8 +309,9 @@ def main():
     print(f"{len(reqs)} requests at {rate:.2f}/s; plain path ...", file=sys.stderr, flush=True)
     plain = plain_run(umbir, reqs)
     print(f"plain done: {summarize(plain)}; served path ...", file=sys.stderr, flush=True)
+    chunk = {"c1": args.chunk_small, "c2": args.chunk, "c3": args.chunk}
     srv = Server(GpuExecutor(umbir), hbm_budget=int(args.budget_gb * (1 << 30)), max_slots=args.slots,
-                 chunk=args.chunk)
+                 chunk=chunk)
     served = srv.run(reqs)
     print(f"served done: {summarize(served)}", file=sys.stderr, flush=True)
     # each result equals its plain (one-at-a-time) result
@@ -307,7 +325,7 @@ def main():
                        f"20-50 iterations, HBM budget {args.budget_gb} GB",
            "plain": summarize(plain), "served": summarize(served),
            "served_rejected": len(srv.rejected), "peak_slots": srv.peak_slots,
-           "peak_bytes": srv.peak_bytes, "chunk": args.chunk,
+           "peak_bytes": srv.peak_bytes, "chunk": chunk,
            "max_rel_diff_served_vs_plain": worst,
            "per_kind_p50_ms": {k: {"plain": float(np.percentile([r.latency * 1e3 for r in plain if r.kind == k], 50)),
                                    "served": float(np.percentile([r.latency * 1e3 for r in served if r.kind == k], 50))}

@@ -5,6 +5,9 @@
                the lossless operator
   icd          grouped ICD sweeps (umbir_reconstruct_icd) against the
                surrogate iteration of umbir_reconstruct, with the cost reached
+  forms        the factored and the direct form of the operator (A + A^T
+               pair and a whole reconstruction) on the 64 x 64, 256 x 256
+               and 512 x 512 workloads
   sweeps       --reps A + A^T pairs of the plain operator on a dense random
                image (the program a profiler wraps to count the sweep
                kernels); --workload c2 (256 x 256) or c3 (512 x 512, with
@@ -15,6 +18,7 @@ SNR).  Each line of output is one JSON record.
 
     python -m paper_2202_09703_amd.variants attenuation
     python -m paper_2202_09703_amd.variants icd
+    python -m paper_2202_09703_amd.variants forms
     python -m paper_2202_09703_amd.variants sweeps --reps 5 --workload c2
 """
 from __future__ import annotations
@@ -97,6 +101,44 @@ def icd(umbir, dev, reps: int):
     geom.free()
 
 
+def forms(umbir, dev, reps: int):
+    import torch
+    from synth import card_c1, card_c2, card_c3
+    for card in (card_c1(), card_c2(), card_c3()):
+        geom, x, y, sigma = _setup(umbir, card, dev)
+        work = geom.workspace(umbir.WORK_RECONSTRUCT)
+        yo = torch.empty_like(y)
+        xo = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
+        out = {"variant": "forms", "workload": card.name, "triples": card.n_traces * card.n_voxels}
+        for form in (1, 2):
+            geom.set_tuning(operator_form=form)
+            for _ in range(2):
+                umbir.forward(geom, x, yo, work=work)
+                umbir.adjoint(geom, yo, xo, work=work)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                umbir.forward(geom, x, yo, work=work)
+                umbir.adjoint(geom, yo, xo, work=work)
+            torch.cuda.synchronize()
+            pair = (time.perf_counter() - t0) / reps
+            n = min(card.n_iter, 20)
+            umbir.reconstruct(geom, card.prior, sigma, y, 1, work=work)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            umbir.reconstruct(geom, card.prior, sigma, y, n, work=work)
+            torch.cuda.synchronize()
+            rec = time.perf_counter() - t0
+            name = "factored" if form == 1 else "direct"
+            out[name] = {"pair_ms": pair * 1e3, "evals_per_s": out["triples"] / pair,
+                         f"reconstruct_{n}_iterations_ms": rec * 1e3}
+        geom.set_tuning(operator_form=1)
+        chosen = geom.autotune()
+        out["autotune_chose"] = "factored" if chosen["operator_form"] == 1 else "direct"
+        print(json.dumps(out), flush=True)
+        geom.free()
+
+
 def sweeps(umbir, dev, reps: int, workload: str = "c2", storage: str = "f32"):
     import torch
     from synth import card_c2, card_c3
@@ -122,7 +164,7 @@ def sweeps(umbir, dev, reps: int, workload: str = "c2", storage: str = "f32"):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", choices=("attenuation", "icd", "sweeps"))
+    ap.add_argument("which", choices=("attenuation", "icd", "forms", "sweeps"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--workload", choices=("c2", "c3"), default="c2")
     ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32")
@@ -133,7 +175,7 @@ def main():
     if args.which == "sweeps":
         sweeps(umbir, dev, args.reps, args.workload, args.storage)
     else:
-        {"attenuation": attenuation, "icd": icd}[args.which](umbir, dev, args.reps)
+        {"attenuation": attenuation, "icd": icd, "forms": forms}[args.which](umbir, dev, args.reps)
 
 
 if __name__ == "__main__":

@@ -58,7 +58,11 @@ def test_tuning_changes_no_result(dev, name, card):
         geom.set_tuning(corr_tile_rows=48)
     chosen = geom.autotune()
     assert chosen == geom.tuning() and chosen["splat_blocks"] > 0 and chosen["gather_batch_kb"] > 0
-    assert torch.equal(umbir.forward(geom, x), y0)
+    if chosen["operator_form"] == 1:
+        assert torch.equal(umbir.forward(geom, x), y0)
+    else:  # the direct form sums the same operator in another order
+        yd = umbir.forward(geom, x)
+        assert float(torch.linalg.norm((yd - y0).double()) / torch.linalg.norm(y0.double())) <= 1e-5
     # zeros keep the current values; a cache reuses the choice for the same shape
     geom.set_tuning(0, 0)
     assert geom.tuning() == chosen

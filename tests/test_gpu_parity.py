@@ -420,3 +420,64 @@ def _full_size_solver_case(dev, card, geom, key, n_traces, seed):
 def test_c2_full_size_solver(dev, c2geom):
     card, geom = c2geom
     _full_size_solver_case(dev, card, geom, "c2", 16, 71)
+
+
+# ---- the direct (unfactored) form of the operator (umbir_tuning.operator_form = 2)
+
+
+DIRECT = [("tiny3", tiny_card(n_layers=3, beta=3)),
+          ("tiny4-ragged", tiny_card(n_layers=4, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=16)),
+          ("tiny-narrow", tiny_card(n_layers=3, nx=40, nz=30, n_scans=2, n_rx=3, n_samples=200, oversample=32)),
+          ("tiny-short", tiny_card(n_layers=3, n_samples=40)),
+          ("c1", card_c1())]
+
+
+@pytest.mark.parametrize("name,card", DIRECT)
+def test_direct_form_parity(dev, name, card):
+    """A, A^T and the curvature in the direct form against the oracle; the
+    forward stays bitwise reproducible (fixed-point sample sums)."""
+    geom = umbir.build_geometry(card)
+    geom.set_tuning(operator_form=2)
+    assert geom.tuning()["operator_form"] == 2
+    g = card.grid
+    x = random_vector((g.nz, g.nx), seed=91)
+    xt = t32(x, dev)
+    y = umbir.forward(geom, xt)
+    fe = rel(y.cpu().numpy(), oo.forward(card, x))
+    r = random_vector(geom.trace_shape, seed=92)
+    xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy()
+    ae = rel(xa, oo.adjoint(card, r))
+    d = umbir.sqs_denominator(geom, 0.01).cpu().numpy()
+    de = rel(d, osv.sqs_denominator(card, 0.01))
+    print(f"{name} direct form: forward {fe:.2e}, adjoint {ae:.2e}, curvature {de:.2e}")
+    assert fe <= TOL and ae <= TOL and de <= TOL
+    assert torch.equal(umbir.forward(geom, xt), y)
+    y0 = t32(random_vector(geom.trace_shape, seed=93), dev)
+    y1 = umbir.forward(geom, xt, y0.clone(), accumulate=True).cpu().numpy()
+    assert rel(y1, y0.cpu().numpy() + oo.forward(card, x)) <= TOL
+
+
+def test_direct_form_reconstruct_c1(dev):
+    card, y, sigma = _recon_case()
+    geom = umbir.build_geometry(card)
+    geom.set_tuning(operator_form=2)
+    x, g, cost = umbir.reconstruct(geom, card.prior, sigma, t32(y, dev), card.n_iter)
+    xo, go, co = osv.sqs(card, y, sigma, card.prior, card.n_iter)
+    xe = rel(x.cpu().numpy(), xo)
+    ce = float(np.max(np.abs(cost.cpu().numpy() - co) / np.abs(co)))
+    print(f"c1 direct-form reconstruction: x {xe:.2e}, cost {ce:.2e}")
+    assert xe <= TOL and ce <= 1e-6
+
+
+def test_direct_form_rejections(dev):
+    import dataclasses
+    geom = umbir.build_geometry(card_c2())  # 8 M + 4 (Q L_h + 2) = 16 KiB + 30 KiB fits
+    geom.set_tuning(operator_form=2)
+    long_rec = dataclasses.replace(card_c1(), acq=dataclasses.replace(card_c1().acq, n_samples=8192))
+    g2 = umbir.build_geometry(long_rec)  # 64 KiB of samples alone
+    with pytest.raises(umbir.UmbirError) as err:
+        g2.set_tuning(operator_form=2)
+    assert err.value.status == umbir.ENOTSUP
+    with pytest.raises(umbir.UmbirError) as err:
+        geom.set_tuning(operator_form=3)
+    assert err.value.status == umbir.EINVAL

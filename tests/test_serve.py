@@ -112,6 +112,27 @@ def test_chunking_respects_iteration_counts():
     assert per[0] == [7, 7, 7, 2] and per[1] == [5]
 
 
+def test_chunk_per_kind():
+    """A mapping gives each kind its own chunk; kinds not listed take 5."""
+    ex = FakeExecutor()
+    Server(ex, hbm_budget=2000, max_slots=3, chunk={"small": 11}).run(
+        _reqs([(0.0, "small", 23), (0.0, "big", 12)]))
+    per = {}
+    for rid, n in ex.log:
+        per.setdefault(rid, []).append(n)
+    assert per[0] == [11, 11, 1] and per[1] == [5, 5, 2]
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(), hbm_budget=10, chunk={"small": 0})
+
+
+def test_summary_per_kind():
+    res = Server(FakeExecutor(), hbm_budget=2000, max_slots=8, chunk=5).run(
+        _reqs([(0.0, "big", 40), (0.001, "small", 5), (0.002, "small", 5)]))
+    s = summarize(res)
+    assert set(s["per_kind"]) == {"big", "small"} and s["per_kind"]["small"]["requests"] == 2
+    assert s["per_kind"]["small"]["p99_ms"] <= s["per_kind"]["big"]["p99_ms"]
+
+
 def test_arrivals_are_seeded_poisson():
     a = make_requests(500, rate_hz=100.0, seed=5)
     b = make_requests(500, rate_hz=100.0, seed=5)
