@@ -36,7 +36,8 @@ constexpr int kBisectSteps = 60;
 // NULL, the path attenuation sum_l alpha_l eta_l / cos(theta_l) (gamma_l of
 // Eq. (3) summed over the leg's layers).
 __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double half_dx,
-                       double fs, int beta, Leg* __restrict__ legs, double* __restrict__ gam) {
+                       double fs, int beta, Leg* __restrict__ legs, int nzp, Leg* __restrict__ legs_t,
+                       double* __restrict__ gam) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nz * n_off) return;
   const int row = idx / n_off;
@@ -97,14 +98,20 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
   rec.apod = static_cast<float>(pw);
   rec.spare = 0;
   legs[idx] = rec;
+  legs_t[size_t(slot) * nzp + row] = rec;
   if (gam) gam[idx] = att;
 }
 
-// Leg attenuation in template bins: Gamma / dgamma (float64).
-__global__ void k_leg_units(int n, const double* __restrict__ gam, double step, double* __restrict__ gunit) {
+// Leg attenuation in template bins: Gamma / dgamma (float64), in the legs'
+// layout and in the transposed one of legs_t.
+__global__ void k_leg_units(int n, int n_off, int nzp, const double* __restrict__ gam, double step,
+                            double* __restrict__ gunit, double* __restrict__ gunit_t) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  gunit[idx] = gam[idx] / step;
+  const double u = gam[idx] / step;
+  const int row = idx / n_off, slot = idx - row * n_off;
+  gunit[idx] = u;
+  gunit_t[size_t(slot) * nzp + row] = u;
 }
 
 // Windowed pulse of Eq. (10) at fine-grid index n (time n / (Q fs)): the
@@ -232,11 +239,11 @@ bool lattice_base(double x0, double dx, double x, long* out) {
 
 // Fine-grid chunks and LDS tiles of the splat sweep for a target workgroup
 // count: ceil(target / traces) chunks per trace of at least 1024 positions,
-// swept in tiles of 64-bit positions as large as fit in 64 KiB beside the
-// row pointers (at least 4096 positions, a multiple of 64, at most a chunk):
-// every tile costs a fixed walk over the (column, layer) pointers and three
-// barriers, so fewer, larger tiles run faster (6976 positions instead of 4096
-// took the 256 x 256 workload's splat from 167 to 147 us).
+// swept in tiles of 64-bit positions as large as fit in the workgroup's LDS
+// (kSplatLdsBytes) beside the row pointers (at least 4096 positions, a
+// multiple of 64, at most a chunk): every tile costs a fixed walk over the
+// (column, layer) pointers, three barriers and a partly used first row block
+// per (column, layer), so fewer, larger tiles run faster.
 void apply_splat_blocks(umbir_geometry* G, long target) {
   const long MQ = long(G->M) * G->Q;
   const long min_chunk = 1024;
@@ -248,7 +255,7 @@ void apply_splat_blocks(umbir_geometry* G, long target) {
   G->chunks = int(chunks);
   G->chunk_bins = (MQ + chunks - 1) / chunks;
   const long pointers = long(G->n_seg + 1) * G->nx * 8;  // per (column, layer) pointers and column offsets
-  long tile = (65536 - 1024 - pointers) / 8 - 2;
+  long tile = (kSplatLdsBytes - 1024 - pointers) / 8 - 2;
   tile = std::max<long>(4096, tile / 64 * 64);
   G->tile_bins = int(std::min<long>(tile, G->chunk_bins));
 }
@@ -398,7 +405,8 @@ int validate(const umbir_problem* pb, Derived* dv) {
   dv->omax = omax;
   dv->n_off = int((omax + 2) & ~1L);  // even, for the parity split of each row
   // the splat addresses the leg table and the image with 32-bit byte offsets
-  if (double(g.nz) * dv->n_off * sizeof(Leg) >= double(1u << 31) || double(g.nz) * g.nx * 4 >= double(1u << 31))
+  const double nzp = double(padded_rows(g.nz));
+  if (nzp * dv->n_off * sizeof(Leg) >= double(1u << 31) || nzp * g.nx * 4 >= double(1u << 31))
     return fail(UMBIR_ENOTSUP, "leg table or image of 2 GiB or more");
   return UMBIR_OK;
 }
@@ -420,10 +428,11 @@ size_t table_bytes(int nz, int n_off, int P, int K, int M, int Q, int Lh, int n_
   const size_t legs = size_t(nz) * n_off;
   // with attenuation: the legs' attenuation in template bins and the
   // template occupancy masks
-  const size_t att = n_gamma > 1 ? legs * sizeof(double) + size_t(P) * K *
+  const size_t legs_t = size_t(n_off) * padded_rows(nz);
+  const size_t att = n_gamma > 1 ? (legs + legs_t) * sizeof(double) + size_t(P) * K *
                                        ((size_t(M) * Q + (size_t(1) << kMaskShift) - 1) >> kMaskShift) * 8
                                  : 0;
-  return legs * sizeof(Leg) + size_t(nz) * sizeof(float) +
+  return (legs + legs_t) * sizeof(Leg) + size_t(nz) * sizeof(float) +
          size_t(P) * (1 + K) * sizeof(int) + size_t(n_gamma) * (Q * Lh + 2) * sizeof(float) +
          2 * size_t(n_gamma) * Q * Lh * sizeof(float) + size_t(P) * K * M * sizeof(float) +
          size_t(P) * K * sizeof(float) + att;
@@ -499,7 +508,8 @@ void umbir_geometry_free(umbir_geometry* G) {
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (G->device >= 0) (void)hipSetDevice(G->device);
-  void* ptrs[] = {G->legs, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm, G->gmask, G->gunit};
+  void* ptrs[] = {G->legs, G->legs_t, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm, G->gmask,
+                  G->gunit, G->gunit_t};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (cur >= 0) (void)hipSetDevice(cur);
@@ -571,6 +581,8 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   }
 
   const size_t legs = size_t(G->nz) * G->n_off;
+  G->nzp = padded_rows(G->nz);
+  const size_t legs_t = size_t(G->nzp) * G->n_off;
   const size_t PK = size_t(G->P) * G->K;
   const int QLh = G->Q * G->Lh;
   auto alloc = [&](void** p, size_t bytes) {
@@ -579,6 +591,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   };
   double* td_dev = nullptr;
   if ((st = alloc((void**)&G->legs, legs * sizeof(Leg))) ||
+      (st = alloc((void**)&G->legs_t, legs_t * sizeof(Leg))) ||
       (st = alloc((void**)&G->tau, G->nz * sizeof(float))) ||
       (st = alloc((void**)&G->base, dv.base.size() * sizeof(int))) ||
       (st = alloc((void**)&G->dbasis, PK * G->M * sizeof(float))) ||
@@ -636,9 +649,12 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   if (dv.n_gamma > 1 &&
       (st = check_hip(hipMallocAsync((void**)&gam_dev, legs * sizeof(double), s), "hipMallocAsync")))
     return bail(st);
+  // the padding rows of the transposed table stay zero
+  if ((st = check_hip(hipMemsetAsync(G->legs_t, 0, legs_t * sizeof(Leg), s), "hipMemsetAsync(legs_t)")))
+    return bail(st);
   const int n_legs = int(legs);
   UMBIR_LAUNCH("legs", k_legs, dim3((n_legs + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off, G->z0,
-               G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, gam_dev);
+               G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, G->nzp, G->legs_t, gam_dev);
   if ((st = check_hip(hipGetLastError(), "k_legs"))) return bail(st);
   if (dv.n_gamma > 1) {
     // Gamma_max: at a fixed depth a leg's attenuation grows with its lateral
@@ -654,9 +670,12 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     if (gmax > 0.0) {
       G->n_gamma = dv.n_gamma;
       G->gamma_step = 2.0 * gmax / (G->n_gamma - 1);
-      if ((st = alloc((void**)&G->gunit, legs * sizeof(double)))) return bail(st);
-      UMBIR_LAUNCH("leg_units", k_leg_units, dim3((n_legs + 255) / 256), dim3(256), 0, s, n_legs, gam_dev,
-                   G->gamma_step, G->gunit);
+      if ((st = alloc((void**)&G->gunit, legs * sizeof(double))) ||
+          (st = alloc((void**)&G->gunit_t, legs_t * sizeof(double))) ||
+          (st = check_hip(hipMemsetAsync(G->gunit_t, 0, legs_t * sizeof(double), s), "hipMemsetAsync(gunit_t)")))
+        return bail(st);
+      UMBIR_LAUNCH("leg_units", k_leg_units, dim3((n_legs + 255) / 256), dim3(256), 0, s, n_legs, G->n_off, G->nzp,
+                   gam_dev, G->gamma_step, G->gunit, G->gunit_t);
     }
   }
   const int NG = G->n_gamma;

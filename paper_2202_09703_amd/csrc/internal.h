@@ -44,6 +44,24 @@ constexpr int kMaskShift = 10;
 
 __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >> 1) + (o & 1) * half; }
 
+// LDS of one splat workgroup: all 160 KiB of a gfx950 CU, one workgroup of
+// 16 waves per CU (measured against 64 KiB and 80 KiB, two workgroups per CU:
+// the larger tiles need fewer passes over the row pointers and fewer partly
+// used row blocks; 120 us against 130 us at 256 x 256, 1.49 ms against
+// 1.80 ms at 512 x 512).
+constexpr long kSplatLdsBytes = 163840;
+
+// Rows per lattice position (per column) of the splat's transposed tables:
+// nz rounded up to a multiple of 8 (one 128-byte line of leg records per
+// 8-row block), and to an odd number of such blocks, so that the columns of
+// one wave step (8 positions apart by whole tables rows) do not all fall on
+// addresses a power of two apart.
+inline int padded_rows(int nz) {
+  int p = (nz + 7) & ~7;
+  if (((p >> 3) & 1) == 0) p += 8;
+  return p;
+}
+
 // Blocks of the forward's image prescale: each leaves its max|tau x| for the
 // splat, which takes the largest (no atomic, nothing to clear first).
 constexpr int kPrescaleBlocks = 128;
@@ -172,9 +190,16 @@ struct umbir_geometry {
   double gamma_step = 0.0;
   unsigned long long* gmask = nullptr;  // [P*K][mask_blocks] template occupancy (n_gamma > 1)
   double* gunit = nullptr;  // [nz][n_off] leg path attenuation / gamma_step, laid out as legs (n_gamma > 1)
+  double* gunit_t = nullptr;  // [n_off][nzp] the same, laid out as legs_t (n_gamma > 1)
   int mask_blocks = 0;
   // resident device tables
   umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows
+  // the same legs by lattice position, the rows of one position contiguous
+  // ([n_off][nzp], rows nz .. nzp - 1 zero): the splat's table, where one
+  // wave step reads 8 consecutive rows of a position as one aligned 128-byte
+  // line
+  umbir::Leg* legs_t = nullptr;
+  int nzp = 0;  // rows per position of legs_t and per column of tau x: padded_rows(nz)
   float* tau = nullptr;      // [nz] transmittance product of the row's layer
   int* base = nullptr;       // [P + P*K] lattice base: offset index = |base + 2 col|
   float* bank = nullptr;     // [n_gamma][Q*Lh + 2] tabulated windowed responses, zero padded
@@ -189,7 +214,8 @@ struct umbir_geometry {
   size_t fine_per_trace() const { return size_t(M) * Q; }
   size_t elem() const { return storage == UMBIR_STORAGE_F32 ? 4 : 2; }
   // fine-grid workspace: P K M Q elements, then the splat's prescaled image
-  // (nz nx floats), then one 32-bit scalar
+  // (nx nzp floats, by column: xt[col * nzp + row]), then the prescale
+  // blocks' maxima
   size_t fine_grid_bytes() const { return (size_t(traces()) * fine_per_trace() * elem() + 15) & ~size_t(15); }
   // with attenuation every template's grid is kept resident when one trace's
   // grids fit 32-bit offsets (the forward writes them [template][trace]
@@ -206,7 +232,7 @@ struct umbir_geometry {
   // the fine-grid workspace: the grid(s), then the forward's prescaled image
   // and the prescale blocks' maxima
   size_t fine_bytes() const {
-    return grids_bytes() + ((size_t(voxels()) * 4 + 15) & ~size_t(15)) + 4 * umbir::kPrescaleBlocks;
+    return grids_bytes() + ((size_t(nx) * nzp * 4 + 15) & ~size_t(15)) + 4 * umbir::kPrescaleBlocks;
   }
   size_t trace_bytes() const { return size_t(traces()) * M * elem(); }
   size_t taps_per_bin() const { return size_t(Q) * Lh; }
@@ -270,12 +296,13 @@ size_t adjoint_work_bytes(const umbir_geometry& G);
 struct BatchProb {
   // geometry
   const Leg* legs;
+  const Leg* legs_t;  // [n_off][nzp]
   const int* base;
   const float* tau;
   const float* h;       // polyphase taps [Lh][Q]
   const float* dbasis;  // [P K][M]
   const float* dnorm;   // [P K]
-  int nx, nz, n_off, P, K, M, Q, qs, Lh, MQ;
+  int nx, nz, nzp, n_off, P, K, M, Q, qs, Lh, MQ;
   Segments seg;
   // launch shapes of the sweeps
   int chunk_bins, tile_bins, wide;  // splat
@@ -286,7 +313,7 @@ struct BatchProb {
   const float* y;
   float* e;
   float* fine;
-  float* xt;  // tau x of the current image (the splat's input), kept by the prior update
+  float* xt;  // tau x of the current image by column ([nx][nzp], the splat's input), kept by the prior update
   float* partial;
   float* den;
   double* ess;

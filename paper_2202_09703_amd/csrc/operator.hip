@@ -49,15 +49,18 @@ __global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, size_
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
 // The splat's input image with the row transmittance folded in, xt = tau x
-// (x == NULL means x = 1), and per block the largest |xt| as float bits
-// (non-negative floats order like their bits) for the fixed-point scale of
-// the splat: out[blockIdx.x], gridDim.x <= kPrescaleBlocks.
-__device__ __forceinline__ void prescale_body(int bx, int gx, const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
-                           float* __restrict__ xt, unsigned* __restrict__ out) {
+// (x == NULL means x = 1), stored by column (xt[col * nzp + row]), and per
+// block the largest |xt| as float bits (non-negative floats order like their
+// bits) for the fixed-point scale of the splat: out[blockIdx.x], gridDim.x <=
+// kPrescaleBlocks.
+__device__ __forceinline__ void prescale_body(int bx, int gx, const float* __restrict__ x,
+                                              const float* __restrict__ tau, int nx, int nzp, int n,
+                                              float* __restrict__ xt, unsigned* __restrict__ out) {
   unsigned m = 0;
   for (int i = bx * blockDim.x + threadIdx.x; i < n; i += gx * blockDim.x) {
-    const float v = tau[i / nx] * (x ? x[i] : 1.0f);
-    xt[i] = v;
+    const int row = i / nx;
+    const float v = tau[row] * (x ? x[i] : 1.0f);
+    xt[size_t(i - row * nx) * nzp + row] = v;
     m = max(m, __float_as_uint(fabsf(v)));
   }
   for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
@@ -70,9 +73,9 @@ __device__ __forceinline__ void prescale_body(int bx, int gx, const float* __res
   }
 }
 
-__global__ void k_prescale(const float* __restrict__ x, const float* __restrict__ tau, int nx, int n,
+__global__ void k_prescale(const float* __restrict__ x, const float* __restrict__ tau, int nx, int nzp, int n,
                            float* __restrict__ xt, unsigned* __restrict__ out) {
-  prescale_body(blockIdx.x, gridDim.x, x, tau, nx, n, xt, out);
+  prescale_body(blockIdx.x, gridDim.x, x, tau, nx, nzp, n, xt, out);
 }
 
 // Fixed-point exponent of the splat: contributions are scaled by 2^k with
@@ -102,7 +105,7 @@ __device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
 }
 constexpr int kSplatNarrowMin = 1025;  // voxels from which to_fixed<false> is exact
 
-constexpr int kSplatWaves = 8;
+constexpr int kSplatWaves = 16;  // waves per splat workgroup (one workgroup per CU)
 constexpr int kNoRow = 0x7fffffff;
 // Word 3 of a raw buffer resource on CDNA: 32-bit data format, no swizzle.
 constexpr int kBufferWord3 = 0x00020000;
@@ -188,13 +191,18 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 // row it points at, so a (column, layer) with nothing in the current tile
 // costs no load, and per layer the range of positions its voxels reach, so a
 // layer outside the tile is skipped whole.  A wave takes 8 neighbouring
-// columns x 8 consecutive rows per step (the 8 columns of a row read
-// neighbouring leg records) and loads the next step's rows into a second
-// register set while the current one is added: a column continues only after
-// all 8 of its rows fell in the tile, so the next rows are known in advance.
-// The rows of a column that fall in the tile are a prefix of the 8, counted
-// with a ballot.  A voxel at position J adds W x (1 - phi) to J and W x phi to
-// J + 1; the tile keeps one extra slot for J + 1 = the next tile's first
+// columns x one aligned block of 8 rows per step (rows 8b .. 8b + 7; in the
+// first block of a column the rows above its pointer are done already) and
+// loads the next block into a second register set while the current one is
+// added: a column continues only after all its rows of a block fell in the
+// tile, so the next rows are known in advance.  The splat's tables hold the
+// rows of one lattice position (legs_t, gunit_t) and of one column (tau x)
+// contiguously, so a block of 8 rows is one aligned 128-byte line of leg
+// records and 32 bytes of the image, read by 8 consecutive lanes: the L1
+// (whose access rate bounds the splat) serves each load of a column's block
+// as one access.  The rows of a column that fall
+// in the tile are a prefix of its rows in the block, counted with a ballot.
+// A voxel at position J adds W x (1 - phi) to J and W x phi to J + 1; the tile keeps one extra slot for J + 1 = the next tile's first
 // position and one never-read slot that takes the J part of a voxel at J0 - 1
 // (added in the previous tile).  The tile accumulates in 64-bit fixed point
 // (integer LDS atomics: the sum does not depend on the order of the adds, so
@@ -207,8 +215,9 @@ __device__ __forceinline__ int first_row_at(Pos pos, int lo, int hi, int jl, int
 // grids are written [template][trace][position] (each template's grid as the
 // convolution reads it).
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
-__device__ __forceinline__ void splat_body(int bx, int by, 
-    const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const double* __restrict__ gunit,
+__device__ __forceinline__ void splat_body(int bx, int by,
+    const float* __restrict__ xt, int nx, int nzp, int n_off, const Leg* __restrict__ legs_t,
+    const double* __restrict__ gunit_t,
     const int* __restrict__ base, int P, int K, int qs, int MQ, const Segments& seg, int chunk_bins, int tile_bins,
     const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
@@ -217,7 +226,7 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   const int TS = tile_bins + 2;                                      // a tile, its carry and never-read slots
   unsigned long long* tile = smem;                                   // [NT][TS]
   int2* pn = reinterpret_cast<int2*>(smem + NT * TS);                // [seg.n][nx] {next row, its position}
-  int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of row 0's records
+  int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of the columns' legs_t rows
   __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
   const int ij = by;
   const int J_begin = bx * chunk_bins;
@@ -246,8 +255,8 @@ __device__ __forceinline__ void splat_body(int bx, int by,
     lay_hi[threadIdx.x] = -kNoRow;
   }
   for (int c = threadIdx.x; c < nx; c += blockDim.x)
-    colofs[c] = make_int2(leg_slot(abs(btx + 2 * c), half) * int(sizeof(Leg)),
-                          leg_slot(abs(brx + 2 * c), half) * int(sizeof(Leg)));
+    colofs[c] = make_int2(leg_slot(abs(btx + 2 * c), half) * nzp * int(sizeof(Leg)),
+                          leg_slot(abs(brx + 2 * c), half) * nzp * int(sizeof(Leg)));
   __syncthreads();
   unsigned maxbits = 0;
   for (int w = 0; w < int(blockDim.x >> 6); ++w) maxbits = max(maxbits, wave_max[w]);
@@ -256,12 +265,9 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   // first row of each (column, layer) whose position is >= J_begin - 1
   for (int i = threadIdx.x; i < seg.n * nx; i += blockDim.x) {
     const int sg = i / nx, c = i - sg * nx;
-    const Leg* ltx = legs + colofs[c].x / int(sizeof(Leg));
-    const Leg* lrx = legs + colofs[c].y / int(sizeof(Leg));
-    auto pos = [&](int r) {
-      const size_t o = size_t(r) * n_off;
-      return int(uint64_t(ltx[o].delay + lrx[o].delay) >> sh);
-    };
+    const Leg* ltx = legs_t + colofs[c].x / int(sizeof(Leg));
+    const Leg* lrx = legs_t + colofs[c].y / int(sizeof(Leg));
+    auto pos = [&](int r) { return int(uint64_t(ltx[r].delay + lrx[r].delay) >> sh); };
     const int lo = seg.lo[sg], hi = seg.hi[sg];  // segments are never empty
     const int jl = pos(lo), jh = pos(hi - 1);
     atomicMin(&lay_lo[sg], jl);
@@ -274,25 +280,27 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cc = lane & 7, rr = lane >> 3;
-  const unsigned long long colmask = 0x0101010101010101ull << cc;
+  // lanes 8 cc .. 8 cc + 7 take the 8 rows of column cc: consecutive lanes
+  // read consecutive records of one line, which the L1 serves as one access
+  const int cc = lane >> 3, rr = lane & 7;
+  const unsigned long long colmask = 0xffull << (8 * cc);
   const int n_groups = (nx + 7) >> 3;
   // The step loads are raw buffer loads: unconditional (so the next step's
   // loads never wait behind a branch), with 32-bit byte offsets, and the
-  // hardware range check returns zeros past the end of a table.  Rows past
-  // the layer are read too but never used.
-  const int rows = seg.hi[seg.n - 1];
-  const __amdgpu_buffer_rsrc_t leg_rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, rows * n_off * int(sizeof(Leg)), kBufferWord3);
+  // hardware range check returns zeros past the end of a table.  Rows outside
+  // the layer (above the pointer or past the layer's end, into the next
+  // position's rows) are read too but never used.
+  const __amdgpu_buffer_rsrc_t leg_rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<Leg*>(legs_t), 0, n_off * nzp * int(sizeof(Leg)), kBufferWord3);
   const __amdgpu_buffer_rsrc_t xt_rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xt), 0, rows * nx * 4, kBufferWord3);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xt), 0, nx * nzp * 4, kBufferWord3);
   // ATT: the legs' attenuation in template bins, 8 bytes per leg (byte
   // offset half that of the leg record)
   const __amdgpu_buffer_rsrc_t gu_rs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<double*>(ATT ? gunit : reinterpret_cast<const double*>(legs)), 0, rows * n_off * 8, kBufferWord3);
-  const unsigned rowbytes = unsigned(n_off) * unsigned(sizeof(Leg));
-  const unsigned lstep = 8u * rowbytes;  // bytes between a lane's steps
-  const unsigned xstep = 8u * unsigned(nx) * 4u;
+      const_cast<double*>(ATT ? gunit_t : reinterpret_cast<const double*>(legs_t)), 0, n_off * nzp * 8,
+      kBufferWord3);
+  constexpr unsigned lstep = 8u * unsigned(sizeof(Leg));  // bytes between a lane's steps: one block of rows
+  constexpr unsigned xstep = 8u * 4u;
   struct Rows {
     int64_t da, db;
     float pa, pb, xv;
@@ -311,10 +319,12 @@ __device__ __forceinline__ void splat_body(int bx, int by,
         if (!__any(live)) continue;
         const int cl = min(c, nx - 1);  // addresses of lanes past the last column stay in the tables
         const int2 co = colofs[cl];
-        int r = pv.x + rr;
-        unsigned oa = unsigned(co.x) + unsigned(r) * rowbytes;
-        unsigned ob = unsigned(co.y) + unsigned(r) * rowbytes;
-        unsigned ox = (unsigned(r) * unsigned(nx) + unsigned(cl)) * 4u;
+        const int p0 = pv.x;                 // the column's first row not yet added
+        int r = (p0 & ~7) + rr;              // this lane's row of the column's current block
+        int k0 = p0 & 7;                     // rows of the block above the pointer (first block only)
+        unsigned oa = unsigned(co.x) + unsigned(r) * unsigned(sizeof(Leg));
+        unsigned ob = unsigned(co.y) + unsigned(r) * unsigned(sizeof(Leg));
+        unsigned ox = (unsigned(cl) * unsigned(nzp) + unsigned(r)) * 4u;
         auto load = [&](Rows& v, unsigned k) {  // rows r + 8 k of this lane
           // delay and apodisation as a 64-bit and a 32-bit load (the compiler
           // merges them into one 12-byte load)
@@ -335,7 +345,7 @@ __device__ __forceinline__ void splat_body(int bx, int by,
         // The first lane of a column left out of the tile stores that row and
         // its position for the next tile.
         auto add = [&](const Rows& v) {
-          const bool have = live && r < hi;
+          const bool have = live && r >= p0 && r < hi;
           const uint64_t D = uint64_t(v.da + v.db);
           const int J = int(D >> sh);
           const bool in = have && J < J1;
@@ -355,9 +365,11 @@ __device__ __forceinline__ void splat_body(int bx, int by,
             atomicAdd(&tile[tb + (J >= J0 ? J - J0 : tile_bins + 1)], to_fixed<WIDE>(w - w1, scale));
             atomicAdd(&tile[tb + J + 1 - J0], to_fixed<WIDE>(w1, scale));
           }
-          const int cnt = __popcll(__ballot(in) & colmask);  // rows of column c taken
-          if (live && rr == cnt) pn[slot] = make_int2(r, have ? J : kNoRow);
-          live = live && cnt == 8;
+          // rows of column c taken: a prefix of its rows in the block from k0
+          const int nxt = k0 + __popcll(__ballot(in) & colmask);
+          if (live && rr == nxt) pn[slot] = make_int2(r, have ? J : kNoRow);
+          live = live && nxt == 8;
+          k0 = 0;
           r += 8;
           oa += lstep;
           ob += lstep;
@@ -408,11 +420,13 @@ __device__ __forceinline__ void splat_body(int bx, int by,
 
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
-    const float* __restrict__ xt, int nx, int n_off, const Leg* __restrict__ legs, const double* __restrict__ gunit,
+    const float* __restrict__ xt, int nx, int nzp, int n_off, const Leg* __restrict__ legs_t,
+    const double* __restrict__ gunit_t,
     const int* __restrict__ base, int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins,
     const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
-  splat_body<ABSW, WIDE, ST, ATT, MT>(blockIdx.x, blockIdx.y, xt, nx, n_off, legs, gunit, base, P, K, qs, MQ, seg, chunk_bins, tile_bins, xmax, n_xmax, gbin, glast, bs, fine);
+  splat_body<ABSW, WIDE, ST, ATT, MT>(blockIdx.x, blockIdx.y, xt, nx, nzp, n_off, legs_t, gunit_t, base, P, K, qs,
+                                      MQ, seg, chunk_bins, tile_bins, xmax, n_xmax, gbin, glast, bs, fine);
 }
 
 // ---- the direct (unfactored) form of Eq. (13), an alternative for small
@@ -435,7 +449,7 @@ size_t direct_fwd_lds(const umbir_geometry& G) {
 //   out[m] = (base ? base[m] : 0) + sign * y[m] - (g ? g[ij] d_ij[m] : 0).
 template <bool ABSW, bool WIDE>
 __global__ __launch_bounds__(1024) void k_fwd_direct(
-    const float* __restrict__ xt, int nx, int rows, int n_off, const Leg* __restrict__ legs,
+    const float* __restrict__ xt, int nx, int rows, int nzp, int n_off, const Leg* __restrict__ legs,
     const int* __restrict__ base_off, int P, int K, int qs, int Lh, int M, const float* __restrict__ bank,
     const unsigned* __restrict__ xmax, int n_xmax, const float* ybase, float sign, const float* __restrict__ g,
     const float* __restrict__ dbasis, float* out) {
@@ -463,9 +477,9 @@ __global__ __launch_bounds__(1024) void k_fwd_direct(
   const int kx = splat_exponent(maxbits, N);
   const double scale = ldexp(1.0, kx);
   for (int v = threadIdx.x; v < N; v += blockDim.x) {
-    const float xv = xt[v];
-    if (xv == 0.0f) continue;
     const int row = v / nx, col = v - row * nx;
+    const float xv = xt[size_t(col) * nzp + row];  // tau x by column
+    if (xv == 0.0f) continue;
     const Leg a = legs[size_t(row) * n_off + leg_slot(abs(btx + 2 * col), half)];
     const Leg c = legs[size_t(row) * n_off + leg_slot(abs(brx + 2 * col), half)];
     const uint64_t D = uint64_t(a.delay + c.delay);
@@ -1574,10 +1588,10 @@ void launch_corr(const umbir_geometry& G, const void* r_v, const float* hq, void
 size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Tile of the all-templates splat: one tile per template beside the row
-// pointers in 64 KiB of LDS, a multiple of 64 positions and at most the usual
-// tile; 0 if not even 64 positions per template fit.
+// pointers in the workgroup's LDS, a multiple of 64 positions and at most the
+// usual tile; 0 if not even 64 positions per template fit.
 int splat_mt_tile(const umbir_geometry& G) {
-  const long avail = 65536 - 1024 - long(G.n_seg + 1) * G.nx * long(sizeof(int2));
+  const long avail = kSplatLdsBytes - 1024 - long(G.n_seg + 1) * G.nx * long(sizeof(int2));
   const long per = avail / long(sizeof(unsigned long long)) / G.n_gamma - 2;
   const long t = std::min<long>(G.tile_bins, per / 64 * 64);
   return t >= 64 ? int(t) : 0;
@@ -1596,7 +1610,8 @@ void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs,
   const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
   const size_t lds = size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
-               G.n_off, G.legs, G.gunit, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax, n_xmax, gbin,
+               G.nzp, G.n_off, G.legs_t, G.gunit_t, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax,
+               n_xmax, gbin,
                G.n_gamma - 1,
                bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine));
 }
@@ -1671,12 +1686,12 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat_list(const BatchProb
     const BatchProb& p = probs[w.x];
     if (p.wide)
       splat_body<false, true, UMBIR_STORAGE_F32, false, false>(
-          w.y, w.z, p.xt, p.nx, p.n_off, p.legs, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg, p.chunk_bins,
-          p.tile_bins, p.pmax, p.nblk, 0, 0, none, p.fine);
+          w.y, w.z, p.xt, p.nx, p.nzp, p.n_off, p.legs_t, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg,
+          p.chunk_bins, p.tile_bins, p.pmax, p.nblk, 0, 0, none, p.fine);
     else
       splat_body<false, false, UMBIR_STORAGE_F32, false, false>(
-          w.y, w.z, p.xt, p.nx, p.n_off, p.legs, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg, p.chunk_bins,
-          p.tile_bins, p.pmax, p.nblk, 0, 0, none, p.fine);
+          w.y, w.z, p.xt, p.nx, p.nzp, p.n_off, p.legs_t, nullptr, p.base, p.P, p.K, p.qs, p.MQ, p.seg,
+          p.chunk_bins, p.tile_bins, p.pmax, p.nblk, 0, 0, none, p.fine);
     __syncthreads();
   }
 }
@@ -1741,6 +1756,8 @@ __global__ __launch_bounds__(256) void k_gather_list(const BatchProb* __restrict
 void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int4>* items, size_t* lds) {
   const int PK = G.traces(), N = G.voxels();
   bp.legs = G.legs;
+  bp.legs_t = G.legs_t;
+  bp.nzp = G.nzp;
   bp.base = G.base;
   bp.tau = G.tau;
   bp.h = G.h;
@@ -1858,8 +1875,8 @@ bool direct_eligible(const umbir_geometry& G) {
 int run_prescale_blocks(const umbir_geometry& G, const float* x, void* fine, unsigned* maxima, int blocks,
                         hipStream_t s) {
   float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.grids_bytes());
-  UMBIR_LAUNCH("prescale", k_prescale, dim3(unsigned(blocks)), dim3(64), 0, s, x, G.tau, G.nx, G.voxels(), xt,
-               maxima);
+  UMBIR_LAUNCH("prescale", k_prescale, dim3(unsigned(blocks)), dim3(64), 0, s, x, G.tau, G.nx, G.nzp, G.voxels(),
+               xt, maxima);
   return check_hip(hipGetLastError(), "k_prescale");
 }
 
@@ -1882,8 +1899,8 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     xmax = const_cast<unsigned*>(pre_max);
     n_xmax = n_pre_max;
   } else {
-    UMBIR_LAUNCH("prescale", k_prescale, dim3(prescale_blocks(G)), dim3(1024), 0, s, x, G.tau, G.nx, G.voxels(), xt,
-                 xmax);
+    UMBIR_LAUNCH("prescale", k_prescale, dim3(prescale_blocks(G)), dim3(1024), 0, s, x, G.tau, G.nx, G.nzp,
+                 G.voxels(), xt, xmax);
   }
   dim3 grid(G.chunks, G.traces());
   if (G.form == 2) {  // the direct form (FP32, one template; see direct_eligible)
@@ -1893,21 +1910,21 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     float* yo = static_cast<float*>(out);
     if (abs_op) {
       if (wide)
-        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<true, true>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz,
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<true, true>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz, G.nzp,
                      G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb, sign, g,
                      G.dbasis, yo);
       else
-        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<true, false>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz,
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<true, false>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz, G.nzp,
                      G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb, sign, g,
                      G.dbasis, yo);
     } else {
       if (wide)
-        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<false, true>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz,
+        UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<false, true>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx, G.nz, G.nzp,
                      G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb, sign, g,
                      G.dbasis, yo);
       else
         UMBIR_LAUNCH("fwd_direct", (k_fwd_direct<false, false>), dim3(G.traces()), dim3(1024), lds, s, xt, G.nx,
-                     G.nz, G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb,
+                     G.nz, G.nzp, G.n_off, G.legs, G.base, G.P, G.K, qs, G.Lh, G.M, G.bank, xmax, n_xmax, yb,
                      sign, g, G.dbasis, yo);
     }
     return check_hip(hipGetLastError(), "k_fwd_direct");

@@ -165,12 +165,14 @@ __global__ __launch_bounds__(256) void k_gstep(typename Store<ST>::T* __restrict
 // neighbours each (then summed across the four lanes); the depth modulation
 // of the rows the block touches is tabulated once per block.
 // With xt set, the prior update also prepares the next forward: xt = tau
-// x_out, and per block the largest |tau x_out| of its voxels into pmax[block]
-// (as float bits), from which the forward's splat takes the largest.
+// x_out by column (xt[col * nzp + row], the splat's layout), and per block
+// the largest |tau x_out| of its voxels into pmax[block] (as float bits),
+// from which the forward's splat takes the largest.
 struct PriorFuse {
   const float* tau;
   float* xt;
   unsigned* pmax;
+  int nzp;
 };
 
 template <bool UPDATE>
@@ -240,7 +242,7 @@ __device__ __forceinline__ void prior_body(int bx, int by, const float* __restri
     xout[v] = xn;
     if (fz.xt) {
       const float t = fz.tau[row] * xn;
-      fz.xt[v] = t;
+      fz.xt[size_t(col) * fz.nzp + row] = t;
       mbits = __float_as_uint(fabsf(t));
     }
   }
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(4 * kPriorVox) void k_prior_list(const BatchProb* _
     const int4 w = items[it];
     if (!active[w.x]) continue;
     const BatchProb& p = probs[w.x];
-    const PriorFuse fz{p.tau, p.xt, p.pmax};
+    const PriorFuse fz{p.tau, p.xt, p.pmax, p.nzp};
     prior_body<true>(w.y, 0, p.x[which], p.partial, p.groups, p.den, p.nx, p.nz, p.pc, p.x[which ^ 1], p.pcost, fz);
     __syncthreads();
   }
@@ -451,7 +453,7 @@ int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const Prior
     // the update also puts tau x_out and its block maxima in place for the
     // next iteration's forward
     if ((st = run_adjoint_partial(G, b.e, false, b.fine, b.partial, s))) return st;
-    const PriorFuse fz{G.tau, reinterpret_cast<float*>(static_cast<char*>(b.fine) + G.grids_bytes()), b.pmax};
+    const PriorFuse fz{G.tau, reinterpret_cast<float*>(static_cast<char*>(b.fine) + G.grids_bytes()), b.pmax, G.nzp};
     UMBIR_LAUNCH("prior", k_prior_fused<true>, dim3(b.nblk), dim3(4 * kPriorVox), 0, s, x_in, b.partial,
                  G.trace_groups, b.den, G.nx, G.nz, pc, x_out, b.pcost, fz);
   }
