@@ -246,15 +246,30 @@ void apply_splat_blocks(umbir_geometry* G, long target);
 int launch_fill(float* p, size_t n, float v, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 
+// The MAP cost of Eq. (18) of the previous iteration, computed inside the
+// next forward's first kernel instead of a launch of its own: out = inv_2s2
+// sum(ess[0 .. n_ess)) + sum(pcost[0 .. n_p)), summed in the same order as
+// the solver's cost kernel (256 strided partial sums, then a halving tree),
+// so both give bitwise the same value.
+struct CostFold {
+  const double* ess;
+  int n_ess;
+  const double* pcost;
+  int n_p;
+  double inv_2s2;
+  double* out;
+};
+
 // y = base + sign * A x - g D   (base, g may be NULL; x NULL means all ones).
 // `abs_op` builds the operator from |W| and |h|.  Trace buffers (out, base) hold
 // the geometry's storage type; fine: G.fine_bytes() of workspace.  With
 // pre_max the workspace already holds tau x for this x (as
 // run_prescale_blocks or the prior update leaves it), whose largest |tau x|
-// is the largest of the n_pre_max words at pre_max, and x is not read.
+// is the largest of the n_pre_max words at pre_max, and x is not read.  With
+// fold, its cost is also computed (before any of the forward's writes).
 int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base,
                 float sign, const float* g, bool abs_op, void* fine, hipStream_t s,
-                const unsigned* pre_max = nullptr, int n_pre_max = 0);
+                const unsigned* pre_max = nullptr, int n_pre_max = 0, const CostFold* fold = nullptr);
 
 // Can the direct form serve this geometry (FP32 storage, one template, the
 // forward's sample accumulators and template within 64 KiB of LDS)?

@@ -418,13 +418,45 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   }
 }
 
+// CostFold's sums by the first 256 threads of a block of at least 256; sh:
+// 256 doubles of LDS, free before and after.
+__device__ void fold_cost(const CostFold& f, double* sh) {
+  const int t = threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (t < 256) {
+    for (int i = t; i < f.n_ess; i += 256) v[0] += f.ess[i];
+    for (int i = t; i < f.n_p; i += 256) v[1] += f.pcost[i];
+  }
+  double r[2];
+  for (int k = 0; k < 2; ++k) {
+    if (t < 256) sh[t] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) sh[t] += sh[t + w];
+      __syncthreads();
+    }
+    r[k] = sh[0];
+    __syncthreads();
+  }
+  if (t == 0) *f.out = r[0] * f.inv_2s2 + r[1];
+}
+
+__global__ __launch_bounds__(256) void k_fold_cost(CostFold f) {
+  __shared__ double sh[256];
+  fold_cost(f, sh);
+}
+
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const float* __restrict__ xt, int nx, int nzp, int n_off, const Leg* __restrict__ legs_t,
     const double* __restrict__ gunit_t,
     const int* __restrict__ base, int P, int K, int qs, int MQ, Segments seg, int chunk_bins, int tile_bins,
     const unsigned* __restrict__ xmax, int n_xmax,
-    int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
+    int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine, CostFold fold) {
+  if (fold.out && blockIdx.x == 0 && blockIdx.y == 0) {  // uniform: the block's LDS is free until the walk
+    extern __shared__ unsigned long long smem[];
+    fold_cost(fold, reinterpret_cast<double*>(smem));
+  }
   splat_body<ABSW, WIDE, ST, ATT, MT>(blockIdx.x, blockIdx.y, xt, nx, nzp, n_off, legs_t, gunit_t, base, P, K, qs,
                                       MQ, seg, chunk_bins, tile_bins, xmax, n_xmax, gbin, glast, bs, fine);
 }
@@ -1604,30 +1636,35 @@ int prescale_blocks(const umbir_geometry& G) {
 
 template <bool ABSW, bool WIDE, int ST, bool ATT, bool MT>
 void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs, int MQ, const Segments& seg,
-                    const unsigned* xmax, int n_xmax, int gbin, void* fine, hipStream_t s) {
+                    const unsigned* xmax, int n_xmax, int gbin, void* fine, hipStream_t s, const CostFold& fold) {
   using T = typename Store<ST>::T;
   const int nt = MT ? G.n_gamma : 1;
   const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
-  const size_t lds = size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
+  // (with a cost to fold, at least the 256 doubles its sums use)
+  const size_t lds = std::max<size_t>(
+      fold.out ? 256 * sizeof(double) : 0,
+      size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2));
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
                G.nzp, G.n_off, G.legs_t, G.gunit_t, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax,
                n_xmax, gbin,
                G.n_gamma - 1,
-               bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine));
+               bin_skip(G, ATT && !MT ? gbin : -1), static_cast<T*>(fine), fold);
 }
 
 // ATT: the splat pass of template gbin (attenuation bins, FP32 storage only);
 // MT (with ATT): one pass over every template's grid
 template <int ST, bool ATT, bool MT = false>
 void launch_splat(const umbir_geometry& G, bool abs_op, dim3 grid, const float* xt, int qs, int MQ,
-                  const Segments& seg, const unsigned* xmax, int n_xmax, int gbin, void* fine, hipStream_t s) {
+                  const Segments& seg, const unsigned* xmax, int n_xmax, int gbin, void* fine, hipStream_t s,
+                  const CostFold* fold = nullptr) {
+  const CostFold f = fold ? *fold : CostFold{};
   const bool wide = G.nx * (seg.hi[seg.n - 1] - seg.lo[0]) < kSplatNarrowMin;
   if (abs_op) {
-    if (wide) launch_splat_k<true, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
-    else launch_splat_k<true, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
+    if (wide) launch_splat_k<true, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s, f);
+    else launch_splat_k<true, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s, f);
   } else {
-    if (wide) launch_splat_k<false, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
-    else launch_splat_k<false, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s);
+    if (wide) launch_splat_k<false, true, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s, f);
+    else launch_splat_k<false, false, ST, ATT, MT>(G, grid, xt, qs, MQ, seg, xmax, n_xmax, gbin, fine, s, f);
   }
 }
 
@@ -1881,7 +1918,8 @@ int run_prescale_blocks(const umbir_geometry& G, const float* x, void* fine, uns
 }
 
 int run_forward(const umbir_geometry& G, const float* x, void* out, const void* base, float sign,
-                const float* g, bool abs_op, void* fine, hipStream_t s, const unsigned* pre_max, int n_pre_max) {
+                const float* g, bool abs_op, void* fine, hipStream_t s, const unsigned* pre_max, int n_pre_max,
+                const CostFold* fold) {
   // after the fine grid(s): the prescaled image tau x, then one 32-bit
   // scalar, the largest |tau x|
   float* xt = reinterpret_cast<float*>(static_cast<char*>(fine) + G.grids_bytes());
@@ -1904,6 +1942,11 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   }
   dim3 grid(G.chunks, G.traces());
   if (G.form == 2) {  // the direct form (FP32, one template; see direct_eligible)
+    if (fold) {
+      UMBIR_LAUNCH("cost", k_fold_cost, dim3(1), dim3(256), 0, s, *fold);
+      const int st = check_hip(hipGetLastError(), "k_fold_cost");
+      if (st) return st;
+    }
     const bool wide = G.voxels() < kSplatNarrowMin;
     const size_t lds = direct_fwd_lds(G);
     const float* yb = static_cast<const float*>(base);
@@ -1933,7 +1976,7 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
     // attenuation with every template's grid resident: one splat walk fills
     // them all ([template][trace][position]), then one convolution per
     // template; later ones add to the traces the first one wrote
-    launch_splat<UMBIR_STORAGE_F32, true, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
+    launch_splat<UMBIR_STORAGE_F32, true, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s, fold);
     int st = check_hip(hipGetLastError(), "k_splat");
     if (st) return st;
     for (int gb = 0; gb < G.n_gamma; ++gb) {
@@ -1947,18 +1990,23 @@ int run_forward(const umbir_geometry& G, const float* x, void* out, const void* 
   // one splat + convolution per attenuation template (one without
   // attenuation); later passes add to the traces the first one wrote
   for (int gb = 0; gb < G.n_gamma; ++gb) {
+    const CostFold* fold_here = gb == 0 ? fold : nullptr;
     switch (G.storage) {
       case UMBIR_STORAGE_F16:
-        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
+        launch_splat<UMBIR_STORAGE_F16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s,
+                                               fold_here);
         break;
       case UMBIR_STORAGE_BF16:
-        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
+        launch_splat<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s,
+                                                fold_here);
         break;
       default:
         if (G.n_gamma > 1)
-          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, gb, fine, s);
+          launch_splat<UMBIR_STORAGE_F32, true>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, gb, fine, s,
+                                                fold_here);
         else
-          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s);
+          launch_splat<UMBIR_STORAGE_F32, false>(G, abs_op, grid, xt, qs, MQ, seg, xmax, n_xmax, 0, fine, s,
+                                                 fold_here);
         break;
     }
     int st = check_hip(hipGetLastError(), "k_splat");

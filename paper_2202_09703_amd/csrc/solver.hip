@@ -421,15 +421,19 @@ int enqueue_curvature(const umbir_geometry& G, const IterBuffers& b, const Prior
 }
 
 // One surrogate iteration from x_in to x_out (or, with last, only the cost of
-// x_in); the cost goes to cost_out[*counter] (counter != NULL) or cost_out[0].
+// x_in); the cost goes to cost_out[*counter] (counter != NULL) or cost_out[0]
+// (none with cost_out NULL).  With prev_cost, the cost of the iteration
+// before (whose sums the buffers still hold) goes to *prev_cost, computed by
+// the forward's first kernel.
 int enqueue_iteration(const umbir_geometry& G, const IterBuffers& b, const PriorConst& pc, double inv_2s2,
                       int est, const void* y, const float* x_in, float* x_out, float* g, bool last,
-                      double* cost_out, int* counter, hipStream_t s) {
+                      double* cost_out, int* counter, hipStream_t s, double* prev_cost = nullptr) {
   const int PK = G.traces();
   // the workspace holds tau x_in and its block maxima (from
   // run_prescale_blocks before the first iteration, from the previous
   // iteration's prior update after that)
-  int st = run_forward(G, x_in, b.e, y, -1.0f, g, false, b.fine, s, b.pmax, b.nblk);
+  const CostFold fold{b.ess, PK, b.pcost, b.nblk, inv_2s2, prev_cost};
+  int st = run_forward(G, x_in, b.e, y, -1.0f, g, false, b.fine, s, b.pmax, b.nblk, prev_cost ? &fold : nullptr);
   if (st) return st;
   switch (G.storage) {
     case UMBIR_STORAGE_F16:
@@ -1157,10 +1161,13 @@ int umbir_reconstruct(const umbir_geometry* G, const umbir_prior* pr, const void
   if ((st = enqueue_curvature(*G, b, pc, s))) return st;
   if ((st = launch_copy(xa, x_io, N, s))) return st;
   if ((st = enqueue_start(*G, b, xa, s))) return st;
+  // the cost of iteration it - 1 is computed by iteration it's first kernel
+  // (no launch of its own); the last iteration's by the cost kernel
   for (int it = 0; it <= n_iter; ++it) {
     const bool last = it == n_iter;
-    if ((st = enqueue_iteration(*G, b, pc, inv_2s2, est, y, xa, xb, g_io, last, cost ? cost + it : nullptr,
-                                nullptr, s)))
+    if ((st = enqueue_iteration(*G, b, pc, inv_2s2, est, y, xa, xb, g_io, last,
+                                cost && last ? cost + it : nullptr, nullptr, s,
+                                cost && it > 0 ? cost + it - 1 : nullptr)))
       return st;
     if (!last) std::swap(xa, xb);
   }
