@@ -347,9 +347,13 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *  gather_batch_kb  fine-grid KiB of each trace group per gather launch (at
  *                   least one trace per launch).  Changes only the order of
  *                   the adjoint's sums across launches.
- *  conv_grid        tile order of the matrix-core convolution (32 samples x
- *                   32 traces per workgroup): 1 trace tiles fastest, 2 sample
- *                   tiles fastest.  Bitwise identical results.
+ *  conv_grid        tile order of the matrix-core convolution (32 traces per
+ *                   workgroup): 1 trace tiles fastest, 2 sample tiles
+ *                   fastest.  Bitwise identical results.
+ *  conv_tile_rows   output samples per matrix-core convolution workgroup:
+ *                   32, 64 (default) or 128; the workgroup's four waves share
+ *                   each fetched chunk of fine-grid rows among its 32-sample
+ *                   tiles.  Changes only the order of the sums.
  *  corr_tile_rows   rows (output samples) of one wave's tile in the
  *                   matrix-core correlation: 32, 64 or 128 (a workgroup of
  *                   four waves covers four tiles).  Bitwise identical results.
@@ -366,7 +370,8 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   no attenuation and 8 M + 4 (Q L_h + 2) <= 65536 (ENOTSUP
  *                   from umbir_set_tuning otherwise); it suits small problems.
  * A field of 0 (or less) in umbir_set_tuning keeps the current value (EINVAL
- * for a conv_grid or corr_tile_rows outside the values above).  The tuning of
+ * for a conv_grid, conv_tile_rows or corr_tile_rows outside the values
+ * above).  The tuning of
  * a geometry must not change while another call uses it.
  * umbir_autotune times candidates of each field on `stream` (an A + A^T pair
  * for the form, the forward for the splat and the convolution, the adjoint
@@ -378,6 +383,7 @@ typedef struct {
     int splat_blocks;
     int gather_batch_kb;
     int conv_grid;
+    int conv_tile_rows;
     int corr_tile_rows;
     int corr_blocks;
     int operator_form;

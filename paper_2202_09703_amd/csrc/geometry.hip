@@ -738,6 +738,7 @@ int umbir_get_tuning(const umbir_geometry* G, umbir_tuning* out) {
   out->splat_blocks = G->splat_blocks;
   out->gather_batch_kb = G->gather_batch_kb;
   out->conv_grid = G->conv_grid;
+  out->conv_tile_rows = 32 * G->conv_tiles;
   out->corr_tile_rows = 32 * G->corr_tiles;
   out->corr_blocks = G->corr_blocks;
   out->operator_form = G->form;
@@ -752,9 +753,12 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
     return fail(UMBIR_ENOTSUP, "the direct form needs FP32 storage, one template and 8 M + 4 (Q L_h + 2) <= 65536");
   if (t->corr_tile_rows > 0 && t->corr_tile_rows != 32 && t->corr_tile_rows != 64 && t->corr_tile_rows != 128)
     return fail(UMBIR_EINVAL, "corr_tile_rows must be 32, 64 or 128");
+  if (t->conv_tile_rows > 0 && t->conv_tile_rows != 32 && t->conv_tile_rows != 64 && t->conv_tile_rows != 128)
+    return fail(UMBIR_EINVAL, "conv_tile_rows must be 32, 64 or 128");
   if (t->splat_blocks > 0) apply_splat_blocks(G, t->splat_blocks);
   if (t->gather_batch_kb > 0) G->gather_batch_kb = t->gather_batch_kb;
   if (t->conv_grid > 0) G->conv_grid = t->conv_grid;
+  if (t->conv_tile_rows > 0) G->conv_tiles = t->conv_tile_rows / 32;
   if (t->corr_tile_rows > 0) G->corr_tiles = t->corr_tile_rows / 32;
   if (t->corr_blocks > 0) G->corr_blocks = t->corr_blocks;
   if (t->operator_form > 0) G->form = t->operator_form;

@@ -182,6 +182,7 @@ struct umbir_geometry {
   int splat_blocks = 512;      // target splat workgroups; sets chunks, chunk_bins, tile_bins
   int gather_batch_kb = 4096;  // fine-grid KiB per trace group per gather launch
   int conv_grid = 1;           // matrix-core convolution grid: 1 trace tiles fastest, 2 sample tiles fastest
+  int conv_tiles = 2;          // 32-sample output tiles per matrix-core convolution workgroup (1, 2 or 4)
   int corr_tiles = 2;          // 32-row tiles per wave of the matrix-core correlation (1, 2 or 4)
   int corr_blocks = 1024;      // target workgroups of the correlation (sets row blocks per workgroup)
   int form = 1;                // operator form: 1 factored (splat + convolution), 2 direct (Eq. (13) tap by tap)
@@ -321,6 +322,7 @@ struct BatchProb {
   Segments seg;
   // launch shapes of the sweeps
   int chunk_bins, tile_bins, wide;  // splat
+  int conv_tiles;                   // output tiles per convolution block
   int corr_per;                     // row blocks per correlation block
   int groups, tpg, gbatch, vpb;     // gather: trace groups, traces per group and launch, voxels per block
   int nblk;                         // prior-update blocks

@@ -1124,7 +1124,7 @@ struct ChunkOrder {
 // 16-byte reads over all banks.  With one accumulation chain the kernel fits
 // 128 registers and 35 KB of LDS at Q = 32, so four blocks share a CU.
 // Epilogue as in k_conv.
-template <int Q>
+template <int Q, int NTC = 1>
 __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
@@ -1137,7 +1137,7 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   extern __shared__ __align__(16) float sm[];
   float* taps = sm;  // [Lh + 1][TS]: tap rows 0 .. Lh - 1, then a zero row
   const int tr0 = bx * 32;
-  const int m0 = by * 32;
+  const int m0 = by * 32 * NTC;  // NTC output tiles of 32 samples, m0 + 32 j
   const long MQ = long(M) * Q;
   {
     // zero rows and columns first, then the taps with 16-byte loads, several
@@ -1169,16 +1169,20 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
   const int ro = (32 * lk) / Q, t0 = (32 * lk) % Q;  // this lane's row and first tap within a chunk
-  // rows n that meet an output m in [m0, m0 + 32): m0 - Lh <= n <= m0 + 30
-  const ChunkOrder co(m0, Lh, CN);
+  // rows n that meet an output m in [m0, m0 + 32 NTC): m0 - Lh <= n <= m0 + 32 NTC - 2
+  constexpr int EXT = 32 * (NTC - 1);
+  const ChunkOrder co(m0 + EXT, Lh + EXT, CN);
   // a template pass whose template reaches none of the tile's input rows
   // multiplies nothing (the epilogue still runs)
   const bool reach = __syncthreads_or(threadIdx.x < 32 && tr0 + int(threadIdx.x) < PK &&
-                                      bin_reaches(bs, tr0 + threadIdx.x, long(m0 - Lh) * Q, long(m0 + 31) * Q));
+                                      bin_reaches(bs, tr0 + threadIdx.x, long(m0 - Lh) * Q,
+                                                  long(m0 + 31 + EXT) * Q));
   const int rounds = reach ? (co.P + 3) / 4 : 0;
-  floatx16 acc;
+  floatx16 acc[NTC];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  for (int j = 0; j < NTC; ++j)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[j][i] = 0.0f;
   // B: trace tr0 + li (traces past the last read the last one: they only feed
   // output columns that are never written).  Loads are unconditional, from a
   // row clamped into [0, M); a row outside [0, M), or a step past the window,
@@ -1205,31 +1209,37 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   auto multiply = [&](const float4 (&b)[8]) {
     const int nc = next_row(jm, sm_);
     const int n = nc + ro;
-    // tap row k = m - 1 - n; the zero row for rows outside [0, M) or the window
-    int k = m - 1 - n;
-    if (n < 0 || n >= M || unsigned(k) >= unsigned(Lh)) k = Lh;
-    const float4* arow = reinterpret_cast<const float4*>(taps + k * TS + t0);
     // a wave issuing its chunk's MFMAs takes precedence over waves issuing
     // loads and address arithmetic (measured: 2-4 % on this kernel; the
     // correlation, whose operands come from LDS, is slower with it)
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float4 av = arow[u];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b[u].x, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b[u].y, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b[u].z, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc, 0, 0, 0);
+    for (int j = 0; j < NTC; ++j) {
+      // tile j needs rows [m0 + 32 j - Lh, m0 + 32 j + 30]: a chunk wholly
+      // outside them is skipped (uniform over the wave)
+      if (NTC > 1 && (nc > m0 + 32 * j + 30 || nc + CN - 1 < m0 + 32 * j - Lh)) continue;
+      // tap row k = m - 1 - n; the zero row for rows outside [0, M) or the window
+      int k = m + 32 * j - 1 - n;
+      if (n < 0 || n >= M || unsigned(k) >= unsigned(Lh)) k = Lh;
+      const float4* arow = reinterpret_cast<const float4*>(taps + k * TS + t0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float4 av = arow[u];
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, b[u].x, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, b[u].y, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, b[u].z, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, b[u].w, acc[j], 0, 0, 0);
+      }
     }
     __builtin_amdgcn_s_setprio(0);
   };
-  // the epilogue's inputs for this thread's four outputs, fetched now so that
-  // they arrive while the window multiplies
-  float pre_base[4], pre_db[4], pre_g[4];
+  // the epilogue's inputs for this thread's 4 NTC outputs, fetched now so
+  // that they arrive while the window multiplies
+  float pre_base[4 * NTC], pre_db[4 * NTC], pre_g[4 * NTC];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = threadIdx.x + q * 256;
-    const int mm = min(m0 + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
+  for (int q = 0; q < 4 * NTC; ++q) {
+    const int e = threadIdx.x + (q & 3) * 256;
+    const int mm = min(m0 + 32 * (q >> 2) + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
     const size_t idx = size_t(tr) * M + mm;
     pre_base[q] = base ? base[idx] : 0.0f;
     pre_db[q] = g ? dbasis[idx] : 0.0f;
@@ -1246,22 +1256,26 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
     multiply(b1);
   }
   __syncthreads();  // every wave is done with the taps: reuse them for the reduction
-  // sum the four partial tiles: red[wave][row][col]
+  // sum the four partial tiles of each output tile: red[j][wave][row][col]
   float* red = sm;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
-    red[(wave * 32 + row) * 33 + li] = acc[i];
-  }
+  for (int j = 0; j < NTC; ++j)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
+      red[((j * 4 + wave) * 32 + row) * 33 + li] = acc[j][i];
+    }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = threadIdx.x + q * 256;
+  for (int q = 0; q < 4 * NTC; ++q) {
+    const int j = q >> 2;
+    const int e = threadIdx.x + (q & 3) * 256;
     const int col = e >> 5, row = e & 31;  // consecutive threads: consecutive m of one trace
-    const int mm = m0 + row, tr = tr0 + col;
+    const int mm = m0 + 32 * j + row, tr = tr0 + col;
     if (mm < M && tr < PK) {
-      const float v = red[(0 * 32 + row) * 33 + col] + red[(1 * 32 + row) * 33 + col] +
-                      red[(2 * 32 + row) * 33 + col] + red[(3 * 32 + row) * 33 + col];
+      const float* rj = red + j * 4 * 32 * 33;
+      const float v = rj[(0 * 32 + row) * 33 + col] + rj[(1 * 32 + row) * 33 + col] +
+                      rj[(2 * 32 + row) * 33 + col] + rj[(3 * 32 + row) * 33 + col];
       float val = sign * v;
       if (base) val += pre_base[q];
       if (g) val -= pre_g[q] * pre_db[q];
@@ -1270,23 +1284,23 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   }
 }
 
-template <int Q>
+template <int Q, int NTC>
 __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
                                                    const float* __restrict__ dbasis, float* out, long tstride,
                                                    BinSkip bs) {
-  conv_mfma_body<Q>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+  conv_mfma_body<Q, NTC>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
 }
 
 // The same with the grid's dimensions swapped (sample tiles fastest).
-template <int Q>
+template <int Q, int NTC>
 __global__ __launch_bounds__(256) void k_conv_mfma_t(const float* __restrict__ fine, const float* __restrict__ hq,
                                                      int M, int Lh, int PK, const float* base, float sign,
                                                      const float* __restrict__ g, const float* __restrict__ dbasis,
                                                      float* out, long tstride, BinSkip bs) {
-  conv_mfma_body<Q>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+  conv_mfma_body<Q, NTC>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
 }
 
 // C on the matrix cores with 16-bit storage (Q in {32, 64}): as k_conv_mfma,
@@ -1503,18 +1517,31 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
                G.Lh, LhP, fine, tstride);
 }
 
+// LDS of the matrix-core convolution: the padded taps, reused at the end for
+// the four waves' partial tiles of each of the NTC output tiles
+size_t conv_mfma_lds(const umbir_geometry& G) {
+  return std::max<size_t>(size_t(G.Lh + 1) * (G.Q + 4), size_t(G.conv_tiles) * 4 * 32 * 33) * sizeof(float);
+}
+
+template <int Q, int NTC>
+void launch_conv_mfma_n(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
+                        float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
+  const size_t lds = conv_mfma_lds(G);
+  const unsigned tt = unsigned((G.traces() + 31) / 32), mt = unsigned((G.M + 32 * NTC - 1) / (32 * NTC));
+  if (G.conv_grid == 2)
+    UMBIR_LAUNCH("conv", (k_conv_mfma_t<Q, NTC>), dim3(mt, tt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(),
+                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+  else
+    UMBIR_LAUNCH("conv", (k_conv_mfma<Q, NTC>), dim3(tt, mt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(),
+                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+}
+
 template <int Q>
 void launch_conv_mfma(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
                       float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
-  // padded taps, reused for the four partial tiles at the end
-  const size_t lds = std::max<size_t>(size_t(G.Lh + 1) * (Q + 4), 4 * 32 * 33) * sizeof(float);
-  const unsigned tt = unsigned((G.traces() + 31) / 32), mt = unsigned((G.M + 31) / 32);
-  if (G.conv_grid == 2)
-    UMBIR_LAUNCH("conv", k_conv_mfma_t<Q>, dim3(mt, tt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
-                 sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
-  else
-    UMBIR_LAUNCH("conv", k_conv_mfma<Q>, dim3(tt, mt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(), base,
-                 sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+  if (G.conv_tiles == 1) return launch_conv_mfma_n<Q, 1>(G, fine, hq, base, sign, g, out, tstride, gbin, s);
+  if (G.conv_tiles == 4) return launch_conv_mfma_n<Q, 4>(G, fine, hq, base, sign, g, out, tstride, gbin, s);
+  return launch_conv_mfma_n<Q, 2>(G, fine, hq, base, sign, g, out, tstride, gbin, s);
 }
 
 template <int Q, int ST>
@@ -1742,7 +1769,16 @@ __global__ __launch_bounds__(256) void k_conv_list(const BatchProb* __restrict__
     const int4 w = items[it];
     if (!active[w.x]) continue;
     const BatchProb& p = probs[w.x];
-    conv_mfma_body<Q>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ), none);
+    // the problem's own tile count (uniform over the block)
+    if (p.conv_tiles == 1)
+      conv_mfma_body<Q, 1>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ),
+                           none);
+    else if (p.conv_tiles == 4)
+      conv_mfma_body<Q, 4>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ),
+                           none);
+    else
+      conv_mfma_body<Q, 2>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ),
+                           none);
     __syncthreads();
   }
 }
@@ -1823,13 +1859,16 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
                                               size_t(G.n_seg + 1) * G.nx * sizeof(int2));
   for (int t = 0; t < PK; ++t)
     for (int c = 0; c < G.chunks; ++c) items[kStSplat].push_back(make_int4(pi, c, t, 0));
-  // convolution: as launch_conv_mfma
-  lds[kStConv] = std::max(lds[kStConv], std::max<size_t>(size_t(G.Lh + 1) * (G.Q + 4), 4 * 32 * 33) * sizeof(float));
+  // convolution: as launch_conv_mfma (the problem's tile count and order,
+  // so its sums run in the order of its own launch)
+  bp.conv_tiles = G.conv_tiles;
+  lds[kStConv] = std::max(lds[kStConv], conv_mfma_lds(G));
+  const int mts = (G.M + 32 * G.conv_tiles - 1) / (32 * G.conv_tiles);
   if (G.conv_grid == 2) {
     for (int tx = 0; tx < (PK + 31) / 32; ++tx)
-      for (int my = 0; my < (G.M + 31) / 32; ++my) items[kStConv].push_back(make_int4(pi, tx, my, 0));
+      for (int my = 0; my < mts; ++my) items[kStConv].push_back(make_int4(pi, tx, my, 0));
   } else {
-    for (int my = 0; my < (G.M + 31) / 32; ++my)
+    for (int my = 0; my < mts; ++my)
       for (int tx = 0; tx < (PK + 31) / 32; ++tx) items[kStConv].push_back(make_int4(pi, tx, my, 0));
   }
   // correlation: two 32-row tiles per wave whatever the tuning (the tile
@@ -2259,17 +2298,23 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     if (ms < best) { best = ms; best_blocks = c; }
   }
   apply_splat_blocks(G, best_blocks);
-  // the matrix-core convolution's tile order (FP32, Q of 32 or 64)
+  // the matrix-core convolution's output tiles per workgroup and tile order
+  // (FP32, Q of 32 or 64)
   if (!st && G->storage == UMBIR_STORAGE_F32 && (G->Q == 32 || G->Q == 64)) {
-    int best_grid = G->conv_grid;
+    int best_grid = G->conv_grid, best_tiles = G->conv_tiles;
     best = 3.4e38f;
-    for (int cg : {1, 2}) {
-      G->conv_grid = cg;
-      float ms = 0.0f;
-      if ((st = time_ms(forward, &ms))) break;
-      if (ms < best) { best = ms; best_grid = cg; }
+    for (int nt : {1, 2, 4}) {
+      for (int cg : {1, 2}) {
+        G->conv_tiles = nt;
+        G->conv_grid = cg;
+        float ms = 0.0f;
+        if ((st = time_ms(forward, &ms))) break;
+        if (ms < best) { best = ms; best_grid = cg; best_tiles = nt; }
+      }
+      if (st) break;
     }
     G->conv_grid = best_grid;
+    G->conv_tiles = best_tiles;
   }
   // the matrix-core correlation's tile rows per wave and workgroup count
   if (!st && G->storage == UMBIR_STORAGE_F32 && (G->Q == 32 || G->Q == 64)) {
@@ -2306,6 +2351,7 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     chosen->splat_blocks = G->splat_blocks;
     chosen->gather_batch_kb = G->gather_batch_kb;
     chosen->conv_grid = G->conv_grid;
+    chosen->conv_tile_rows = 32 * G->conv_tiles;
     chosen->corr_tile_rows = 32 * G->corr_tiles;
     chosen->corr_blocks = G->corr_blocks;
     chosen->operator_form = G->form;

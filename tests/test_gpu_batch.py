@@ -33,7 +33,8 @@ def f32(a, dev):
 def test_tuning_changes_no_result(dev, name, card):
     """Any splat split, convolution tile order, correlation tile shape and
     workgroup count gives bitwise the same forward and adjoint; gather
-    batches change only the order of the adjoint's cross-launch sums."""
+    batches and the convolution's output tiles per workgroup change only the
+    order of sums."""
     geom = umbir.build_geometry(card)
     g = card.grid
     x = f32(random_vector((g.nz, g.nx), seed=3), dev)
@@ -42,10 +43,19 @@ def test_tuning_changes_no_result(dev, name, card):
     t0 = geom.tuning()
     assert t0["splat_blocks"] > 0 and t0["gather_batch_kb"] > 0
     assert t0["conv_grid"] == 1 and t0["corr_tile_rows"] == 64 and t0["corr_blocks"] == 1024
+    assert t0["conv_tile_rows"] == 64
     for cg, rows, nb in [(2, 32, 1), (1, 128, 100000), (2, 64, 7)]:
         geom.set_tuning(conv_grid=cg, corr_tile_rows=rows, corr_blocks=nb)
         assert torch.equal(umbir.forward(geom, x), y0)
         assert torch.equal(umbir.adjoint(geom, r), a0)
+    for ct in (32, 128, 64):
+        geom.set_tuning(conv_tile_rows=ct)
+        assert geom.tuning()["conv_tile_rows"] == ct
+        y = umbir.forward(geom, x)
+        assert torch.allclose(y, y0, rtol=1e-6, atol=1e-6 * float(y0.abs().max()))
+        for cg in (1, 2):  # the tile order changes nothing for a given tile count
+            geom.set_tuning(conv_grid=cg)
+            assert torch.equal(umbir.forward(geom, x), y)
     for blocks, kb in [(1, 1), (geom.n_scans * geom.n_rx * 4, 64), (100000, 1 << 20)]:
         geom.set_tuning(splat_blocks=blocks, gather_batch_kb=kb)
         assert torch.equal(umbir.forward(geom, x), y0)
@@ -56,11 +66,13 @@ def test_tuning_changes_no_result(dev, name, card):
     assert err.value.status == umbir.EINVAL
     with pytest.raises(umbir.UmbirError):
         geom.set_tuning(corr_tile_rows=48)
+    with pytest.raises(umbir.UmbirError):
+        geom.set_tuning(conv_tile_rows=96)
     chosen = geom.autotune()
     assert chosen == geom.tuning() and chosen["splat_blocks"] > 0 and chosen["gather_batch_kb"] > 0
-    if chosen["operator_form"] == 1:
+    if chosen["operator_form"] == 1 and chosen["conv_tile_rows"] == 64:
         assert torch.equal(umbir.forward(geom, x), y0)
-    else:  # the direct form sums the same operator in another order
+    else:  # the direct form, or other convolution tiles, sum in another order
         yd = umbir.forward(geom, x)
         assert float(torch.linalg.norm((yd - y0).double()) / torch.linalg.norm(y0.double())) <= 1e-5
     # zeros keep the current values; a cache reuses the choice for the same shape
