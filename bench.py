@@ -204,18 +204,23 @@ def host_cpu():
     return os.cpu_count() or 1, model
 
 
-def operator_roofline(card, t_pair, triples):
+def operator_roofline(card, t_pair, triples, n_off, elem=4):
     """One A + A^T pair against the two ceilings of the operator's own
     definition (Eq. (13)): 2 L_h flop per (trace, voxel) per operator on the
     FP32 units, and the operator's algorithmic HBM bytes (image, traces, leg
     table and template read or written once per operator)."""
-    acq = card.acq
+    acq, a, g = card.acq, card.array, card.grid
     lh = int(round(acq.t_win * acq.fs))
     flop = 2.0 * 2 * lh * triples
+    per_op = (4.0 * g.nx * g.nz + elem * a.n_scans * a.n_rx * acq.n_samples + 16.0 * g.nz * n_off
+              + 4.0 * (acq.oversample * lh + 2))
     return {"pair_ms": t_pair * 1e3, "flop_per_pair": flop, "achieved_TFLOPs": flop / t_pair / 1e12,
             "frac_of_fp32": flop / t_pair / PEAK_FP32,
+            "algorithmic_bytes_per_pair": 2 * per_op,
+            "hbm_frac_at_algorithmic_bytes": 2 * per_op / t_pair / PEAK_HBM,
             "note": "operator work as Eq. (13) defines it (2 L_h flop per triple per operator), "
-                    "whichever way the kernels factor it"}
+                    "whichever way the kernels factor it; at its algorithmic bytes (image, traces, leg table, "
+                    "template once per operator) HBM is not what bounds a matrix-free sweep"}
 
 
 def time_pair(umbir, torch, gm, x, y, xo, work, reps=10):
@@ -280,7 +285,7 @@ def precision_section(umbir, torch, dev, with_parity):
         res = {"A_evals_per_s": triples / t_a, "AT_evals_per_s": triples / t_at,
                "A_plus_AT_evals_per_s": triples / (t_a + t_at), "A_ms": t_a * 1e3, "AT_ms": t_at * 1e3,
                "dominant_kernel": dom, "roofline": kern[dom], "sweep_kernels": kern,
-               "operator_roofline": operator_roofline(card, t_a + t_at, triples)}
+               "operator_roofline": operator_roofline(card, t_a + t_at, triples, gm.n_off, elem)}
         if ref is not None:
             yf = umbir.forward(gm, x).float().cpu().numpy()
             rt = torch.tensor(r_np, dtype=torch.float32, device=dev).to(gm.trace_dtype)
@@ -512,7 +517,7 @@ def main():
         "tuning": tuning,
         "roofline": roof,
         "sweep_kernels": kernels,
-        "operator_roofline": operator_roofline(card, t_fwd + t_adj, triples),
+        "operator_roofline": operator_roofline(card, t_fwd + t_adj, triples, gm.n_off),
     }
     # the HBM-bound update kernels against the published peak and a measured copy
     crate = copy_rate()

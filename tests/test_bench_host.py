@@ -55,10 +55,16 @@ def test_kernel_work_of_the_workload(bench):
 
 def test_operator_roofline(bench):
     card = card_c2()
-    r = bench.operator_roofline(card, 0.5e-3, 512 * 65536)
+    r = bench.operator_roofline(card, 0.5e-3, 512 * 65536, 654)
     # 2 L_h flop per triple per operator, two operators
     assert r["flop_per_pair"] == 2 * 2 * 240 * 512 * 65536
     assert r["frac_of_fp32"] == pytest.approx(r["flop_per_pair"] / 0.5e-3 / 157.3e12)
+    # per operator: image, traces (512 x 2048 FP32), leg table (256 rows x 654
+    # records x 16 B), template (32 x 240 + 2 floats)
+    per_op = 4 * 65536 + 4 * 512 * 2048 + 16 * 256 * 654 + 4 * (32 * 240 + 2)
+    assert r["algorithmic_bytes_per_pair"] == 2 * per_op
+    assert r["hbm_frac_at_algorithmic_bytes"] == pytest.approx(2 * per_op / 0.5e-3 / 8e12)
+    assert r["hbm_frac_at_algorithmic_bytes"] < 0.01
 
 
 def test_roofline_record(bench):
