@@ -351,7 +351,8 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   workgroup): 1 trace tiles fastest, 2 sample tiles
  *                   fastest.  Bitwise identical results.
  *  conv_tile_rows   output samples per matrix-core convolution workgroup:
- *                   32, 64 (default) or 128; the workgroup's four waves share
+ *                   32, 64 or 128 (default 64 when that leaves at least 512
+ *                   workgroups, else 32); the workgroup's four waves share
  *                   each fetched chunk of fine-grid rows among its 32-sample
  *                   tiles.  Changes only the order of the sums.
  *  corr_tile_rows   rows (output samples) of one wave's tile in the

@@ -578,6 +578,9 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
       G->seg_hi[G->n_seg - 1] = r + 1;
     }
     apply_splat_blocks(G, G->splat_blocks);
+    // two output tiles per convolution workgroup when that still leaves at
+    // least two workgroups per CU (small problems keep the wider grid)
+    G->conv_tiles = long(G->traces() + 31) / 32 * ((G->M + 63) / 64) >= 512 ? 2 : 1;
   }
 
   const size_t legs = size_t(G->nz) * G->n_off;
