@@ -356,8 +356,9 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   each fetched chunk of fine-grid rows among its 32-sample
  *                   tiles.  Changes only the order of the sums.
  *  corr_tile_rows   rows (output samples) of one wave's tile in the
- *                   matrix-core correlation: 32, 64 or 128 (a workgroup of
- *                   four waves covers four tiles).  Bitwise identical results.
+ *                   matrix-core correlation: 32, 64 or 128 (default; a
+ *                   workgroup of four waves covers four tiles).  Bitwise
+ *                   identical results.
  *  corr_blocks      target workgroup count of the correlation: each workgroup
  *                   walks ceil(traces x row blocks / corr_blocks) row blocks of
  *                   one trace with the taps staged once.  Bitwise identical.

@@ -183,7 +183,7 @@ struct umbir_geometry {
   int gather_batch_kb = 4096;  // fine-grid KiB per trace group per gather launch
   int conv_grid = 1;           // matrix-core convolution grid: 1 trace tiles fastest, 2 sample tiles fastest
   int conv_tiles = 2;          // 32-sample output tiles per matrix-core convolution workgroup (1, 2 or 4; by size)
-  int corr_tiles = 2;          // 32-row tiles per wave of the matrix-core correlation (1, 2 or 4)
+  int corr_tiles = 4;          // 32-row tiles per wave of the matrix-core correlation (1, 2 or 4)
   int corr_blocks = 1024;      // target workgroups of the correlation (sets row blocks per workgroup)
   int form = 1;                // operator form: 1 factored (splat + convolution), 2 direct (Eq. (13) tap by tap)
   // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)

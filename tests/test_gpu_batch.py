@@ -42,11 +42,11 @@ def test_tuning_changes_no_result(dev, name, card):
     y0, a0 = umbir.forward(geom, x), umbir.adjoint(geom, r)
     t0 = geom.tuning()
     assert t0["splat_blocks"] > 0 and t0["gather_batch_kb"] > 0
-    assert t0["conv_grid"] == 1 and t0["corr_tile_rows"] == 64 and t0["corr_blocks"] == 1024
+    assert t0["conv_grid"] == 1 and t0["corr_tile_rows"] == 128 and t0["corr_blocks"] == 1024
     # 64-sample tiles when at least 512 workgroups remain, else 32
     tiles = (geom.n_scans * geom.n_rx + 31) // 32 * ((card.acq.n_samples + 63) // 64)
     assert t0["conv_tile_rows"] == (64 if tiles >= 512 else 32)
-    for cg, rows, nb in [(2, 32, 1), (1, 128, 100000), (2, 64, 7)]:
+    for cg, rows, nb in [(2, 32, 1), (1, 64, 100000), (2, 128, 7)]:
         geom.set_tuning(conv_grid=cg, corr_tile_rows=rows, corr_blocks=nb)
         assert torch.equal(umbir.forward(geom, x), y0)
         assert torch.equal(umbir.adjoint(geom, r), a0)
