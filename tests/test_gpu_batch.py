@@ -152,11 +152,15 @@ def test_worklist_batch(dev, q):
     work items, problems leaving as they reach their count) holds bitwise each
     problem's one-at-a-time result, and that matches the oracle.  One problem
     runs with small splat chunks and one-trace gather batches, so its items
-    cover several chunks and its gather items several batches."""
+    cover several chunks and its gather items several batches; the problems
+    take 32-, 64- and 128-sample convolution tiles, so the work list runs each
+    with its own."""
     cards = _q_cards(q) + ([dataclasses.replace(card_c1(), n_iter=5)] if q == 64 else [])
     data = [odata.synthesize(c)[1:] for c in cards]
     probs = batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None, data=data)
     probs[2]["geom"].set_tuning(splat_blocks=probs[2]["geom"].n_scans * probs[2]["geom"].n_rx * 4, gather_batch_kb=1)
+    probs[0]["geom"].set_tuning(conv_tile_rows=64)
+    probs[1]["geom"].set_tuning(conv_tile_rows=128, conv_grid=2)
     _, plain = batch.run_plain(umbir, probs)
     _, wl, n_batches = batch.run_batched(umbir, probs, umbir.BATCH_WORKLIST)
     assert n_batches == 1
