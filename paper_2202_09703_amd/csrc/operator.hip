@@ -105,6 +105,34 @@ __device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
 }
 constexpr int kSplatNarrowMin = 1025;  // voxels from which to_fixed<false> is exact
 
+// A tile sum v (64-bit two's complement) times 2^-k as FP32, with s_hi =
+// 2^(32 - k) and s_lo = 2^-k: the two 32-bit halves are exact in FP64 and so
+// are their scaled values, the FMA adds them with one rounding (none for
+// |v| < 2^53), and the conversion to FP32 rounds once more, so the result is
+// v 2^-k rounded to nearest whenever |v| < 2^53.  Five instructions, against
+// about a dozen for an integer-to-float conversion of 64 bits.
+__device__ __forceinline__ float fixed_to_float(unsigned long long v, double s_hi, double s_lo) {
+  const double hi = double(int(uint32_t(v >> 32)));
+  const double lo = double(uint32_t(v));
+  return float(fma(hi, s_hi, lo * s_lo));
+}
+
+// A tile sum as a stored element.  For FP16 the FP32 value is pinned in a
+// register first: the compiler would otherwise merge the two conversions into
+// one emulated FP64 -> FP16 conversion of some twenty instructions.
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::T fixed_to_store(unsigned long long v, double s_hi, double s_lo) {
+  float f = fixed_to_float(v, s_hi, s_lo);
+  if constexpr (ST == UMBIR_STORAGE_F16) asm("" : "+v"(f));
+  return Store<ST>::put(f);
+}
+
+// Two neighbouring elements of a storage type, for one paired store.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair2 {
+  T a, b;
+};
+
 constexpr int kSplatWaves = 16;  // waves per splat workgroup (one workgroup per CU)
 constexpr int kNoRow = 0x7fffffff;
 // Word 3 of a raw buffer resource on CDNA: 32-bit data format, no swizzle.
@@ -221,7 +249,7 @@ __device__ __forceinline__ void splat_body(int bx, int by,
     const int* __restrict__ base, int P, int K, int qs, int MQ, const Segments& seg, int chunk_bins, int tile_bins,
     const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
-  extern __shared__ unsigned long long smem[];
+  extern __shared__ __align__(16) unsigned long long smem[];
   const int NT = MT ? glast + 1 : 1;                                 // tiles
   const int TS = tile_bins + 2;                                      // a tile, its carry and never-read slots
   unsigned long long* tile = smem;                                   // [NT][TS]
@@ -242,41 +270,65 @@ __device__ __forceinline__ void splat_body(int bx, int by,
     return;
   }
 
-  // the largest |tau x| over the prescale blocks' maxima (n_xmax <= blockDim.x)
+  // Set-up in two phases: first the largest |tau x| over the prescale blocks'
+  // maxima, the column offsets, and the positions of the first and last row
+  // of each (column, layer), parked in its pointer slot (a thread's first
+  // slot is loaded before the maxima, so that their loads are in flight
+  // together); then the scale, the layer ranges and each (column, layer)'s
+  // first row at or after J_begin - 1.
   __shared__ unsigned wave_max[kSplatWaves];
+  auto col_ofs = [&](int c) {
+    return make_int2(leg_slot(abs(btx + 2 * c), half) * nzp * int(sizeof(Leg)),
+                     leg_slot(abs(brx + 2 * c), half) * nzp * int(sizeof(Leg)));
+  };
+  auto pos_at = [&](int2 co, int r) {
+    return int(uint64_t(legs_t[co.x / int(sizeof(Leg)) + r].delay + legs_t[co.y / int(sizeof(Leg)) + r].delay) >> sh);
+  };
   {
+    auto ends = [&](int i) {  // segments are never empty
+      const int sg = i / nx;
+      const int2 co = col_ofs(i - sg * nx);
+      return make_int2(pos_at(co, seg.lo[sg]), pos_at(co, seg.hi[sg] - 1));
+    };
+    const int n_slots = seg.n * nx;
+    const int i0 = min(int(threadIdx.x), n_slots - 1);
+    const int2 e0 = ends(i0);
     unsigned m = 0u;
     for (int i = threadIdx.x; i < n_xmax; i += blockDim.x) m = max(m, xmax[i]);
+    if (int(threadIdx.x) < n_slots) pn[i0] = e0;
+    for (int i = threadIdx.x + blockDim.x; i < n_slots; i += blockDim.x) pn[i] = ends(i);
+    if (threadIdx.x < kMaxLayers) {
+      lay_lo[threadIdx.x] = kNoRow;
+      lay_hi[threadIdx.x] = -kNoRow;
+    }
+    for (int c = threadIdx.x; c < nx; c += blockDim.x) colofs[c] = col_ofs(c);
+    {  // clear the tiles, 16 bytes per store
+      ulonglong2* t2 = reinterpret_cast<ulonglong2*>(tile);
+      for (int k = threadIdx.x; k < NT * TS / 2; k += blockDim.x) t2[k] = make_ulonglong2(0ull, 0ull);
+      if (((NT * TS) & 1) && threadIdx.x == 0) tile[NT * TS - 1] = 0ull;
+    }
     for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
     if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
   }
-  if (threadIdx.x < kMaxLayers) {
-    lay_lo[threadIdx.x] = kNoRow;
-    lay_hi[threadIdx.x] = -kNoRow;
-  }
-  for (int c = threadIdx.x; c < nx; c += blockDim.x)
-    colofs[c] = make_int2(leg_slot(abs(btx + 2 * c), half) * nzp * int(sizeof(Leg)),
-                          leg_slot(abs(brx + 2 * c), half) * nzp * int(sizeof(Leg)));
   __syncthreads();
   unsigned maxbits = 0;
   for (int w = 0; w < int(blockDim.x >> 6); ++w) maxbits = max(maxbits, wave_max[w]);
   const int kx = splat_exponent(maxbits, nx * (seg.hi[seg.n - 1] - seg.lo[0]));
   const double scale = ldexp(1.0, kx);
-  // first row of each (column, layer) whose position is >= J_begin - 1
+  const double s_hi = ldexp(1.0, 32 - kx), s_lo = ldexp(1.0, -kx);  // back from fixed point
+  // first row of each (column, layer) whose position is >= J_begin - 1 (the
+  // same thread wrote the slot's two positions above)
   for (int i = threadIdx.x; i < seg.n * nx; i += blockDim.x) {
     const int sg = i / nx, c = i - sg * nx;
-    const Leg* ltx = legs_t + colofs[c].x / int(sizeof(Leg));
-    const Leg* lrx = legs_t + colofs[c].y / int(sizeof(Leg));
-    auto pos = [&](int r) { return int(uint64_t(ltx[r].delay + lrx[r].delay) >> sh); };
-    const int lo = seg.lo[sg], hi = seg.hi[sg];  // segments are never empty
-    const int jl = pos(lo), jh = pos(hi - 1);
-    atomicMin(&lay_lo[sg], jl);
-    atomicMax(&lay_hi[sg], jh);
+    const int2 co = colofs[c];
+    const int2 jlh = pn[i];
+    atomicMin(&lay_lo[sg], jlh.x);
+    atomicMax(&lay_hi[sg], jlh.y);
     int jf;
-    const int first = first_row_at(pos, lo, hi, jl, jh, J_begin - 1, &jf);
+    const int first = first_row_at([&](int r) { return pos_at(co, r); }, seg.lo[sg], seg.hi[sg], jlh.x, jlh.y,
+                                   J_begin - 1, &jf);
     pn[i] = make_int2(first, jf);
   }
-  for (int k = threadIdx.x; k < NT * TS; k += blockDim.x) tile[k] = 0ull;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -394,7 +446,7 @@ __device__ __forceinline__ void splat_body(int bx, int by,
       const unsigned long long carry = threadIdx.x < NT ? tile[threadIdx.x * TS + n] : 0ull;
       for (int i = threadIdx.x; i < NT * n; i += blockDim.x) {
         const int g = i / n, k = i - g * n;
-        out[size_t(g) * P * K * MQ + J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[g * TS + k]), -kx));
+        out[size_t(g) * P * K * MQ + J0 + k] = fixed_to_store<ST>(tile[g * TS + k], s_hi, s_lo);
         tile[g * TS + k] = 0ull;
       }
       __syncthreads();
@@ -404,9 +456,26 @@ __device__ __forceinline__ void splat_body(int bx, int by,
       }
     } else {
       const unsigned long long carry = tile[n];
-      for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        out[J0 + k] = Store<ST>::put(ldexpf(float((long long)tile[k]), -kx));
-        tile[k] = 0ull;
+      typename Store<ST>::T* o = out + J0;
+      if ((reinterpret_cast<uintptr_t>(o) & (2 * sizeof(*o) - 1)) == 0) {  // uniform
+        // two positions per thread: one 16-byte LDS read and clear, one paired
+        // store; an odd last position by the last thread
+        for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+          ulonglong2* tp = reinterpret_cast<ulonglong2*>(tile) + i;
+          const ulonglong2 v = *tp;
+          *tp = make_ulonglong2(0ull, 0ull);
+          *reinterpret_cast<Pair2<typename Store<ST>::T>*>(o + 2 * i) = {fixed_to_store<ST>(v.x, s_hi, s_lo),
+                                                                         fixed_to_store<ST>(v.y, s_hi, s_lo)};
+        }
+        if ((n & 1) && threadIdx.x == blockDim.x - 1) {
+          o[n - 1] = fixed_to_store<ST>(tile[n - 1], s_hi, s_lo);
+          tile[n - 1] = 0ull;
+        }
+      } else {
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+          o[k] = fixed_to_store<ST>(tile[k], s_hi, s_lo);
+          tile[k] = 0ull;
+        }
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -454,7 +523,7 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat(
     const unsigned* __restrict__ xmax, int n_xmax,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine, CostFold fold) {
   if (fold.out && blockIdx.x == 0 && blockIdx.y == 0) {  // uniform: the block's LDS is free until the walk
-    extern __shared__ unsigned long long smem[];
+    extern __shared__ __align__(16) unsigned long long smem[];
     fold_cost(fold, reinterpret_cast<double*>(smem));
   }
   splat_body<ABSW, WIDE, ST, ATT, MT>(blockIdx.x, blockIdx.y, xt, nx, nzp, n_off, legs_t, gunit_t, base, P, K, qs,
