@@ -36,7 +36,7 @@ constexpr int kBisectSteps = 60;
 // NULL, the path attenuation sum_l alpha_l eta_l / cos(theta_l) (gamma_l of
 // Eq. (3) summed over the leg's layers).
 __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double half_dx,
-                       double fs, int beta, Leg* __restrict__ legs, int nzp, Leg* __restrict__ legs_t,
+                       double fs, int beta, Leg* __restrict__ legs, int nzp, Leg* __restrict__ legs_t, int qs,
                        double* __restrict__ gam) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nz * n_off) return;
@@ -98,6 +98,9 @@ __global__ void k_legs(Layers L, int nz, int n_off, double z0, double dz, double
   rec.apod = static_cast<float>(pw);
   rec.spare = 0;
   legs[idx] = rec;
+  // the position-major copy (the splat's) holds the delay in fine positions:
+  // times Q = 2^qs, exact (travel times stay far below 2^(31 - qs) samples)
+  rec.delay = int64_t(uint64_t(rec.delay) << qs);
   legs_t[size_t(slot) * nzp + row] = rec;
   if (gam) gam[idx] = att;
 }
@@ -657,7 +660,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     return bail(st);
   const int n_legs = int(legs);
   UMBIR_LAUNCH("legs", k_legs, dim3((n_legs + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off, G->z0,
-               G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, G->nzp, G->legs_t, gam_dev);
+               G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, G->nzp, G->legs_t, log2_int(G->Q), gam_dev);
   if ((st = check_hip(hipGetLastError(), "k_legs"))) return bail(st);
   if (dv.n_gamma > 1) {
     // Gamma_max: at a fixed depth a leg's attenuation grows with its lateral

@@ -196,9 +196,9 @@ struct umbir_geometry {
   // resident device tables
   umbir::Leg* legs = nullptr;  // [nz][n_off] one-way legs (delay Q32.32, cos^beta), parity-split rows
   // the same legs by lattice position, the rows of one position contiguous
-  // ([n_off][nzp], rows nz .. nzp - 1 zero): the splat's table, where one
-  // wave step reads 8 consecutive rows of a position as one aligned 128-byte
-  // line
+  // ([n_off][nzp], rows nz .. nzp - 1 zero), delays times Q (Q32.32 in fine
+  // positions): the splat's table, where one wave step reads 8 consecutive
+  // rows of a position as one aligned 128-byte line
   umbir::Leg* legs_t = nullptr;
   int nzp = 0;  // rows per position of legs_t and per column of tau x: padded_rows(nz)
   float* tau = nullptr;      // [nz] transmittance product of the row's layer

@@ -251,9 +251,12 @@ __device__ __forceinline__ void splat_body(int bx, int by,
     int gbin, int glast, BinSkip bs, typename Store<ST>::T* __restrict__ fine) {
   extern __shared__ __align__(16) unsigned long long smem[];
   const int NT = MT ? glast + 1 : 1;                                 // tiles
-  const int TS = tile_bins + 2;                                      // a tile, its carry and never-read slots
-  unsigned long long* tile = smem;                                   // [NT][TS]
-  int2* pn = reinterpret_cast<int2*>(smem + NT * TS);                // [seg.n][nx] {next row, its position}
+  // A tile's slots: 0 takes the part at J0 - 1 (never read), 1 + k position
+  // J0 + k, n + 1 the carry (position J1, the next tile's first).  The tiles
+  // start one word into the LDS, so that slots 1 + 2i are 16-byte aligned.
+  const int TS = tile_bins + 2;
+  unsigned long long* tile = smem + 1;                               // [NT][TS]
+  int2* pn = reinterpret_cast<int2*>(smem + 1 + NT * TS);            // [seg.n][nx] {next row, its position}
   int2* colofs = pn + seg.n * nx;                                    // [nx] byte offsets of the columns' legs_t rows
   __shared__ int lay_lo[kMaxLayers], lay_hi[kMaxLayers];             // positions a layer reaches
   const int ij = by;
@@ -263,7 +266,8 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   const int btx = base[ij / K];
   const int brx = base[P + ij];
   const int half = n_off / 2;
-  const int sh = 32 - qs;  // J = (D_tx + D_rx) >> (32 - log2 Q)
+  // legs_t holds the delays times Q (Q32.32 in fine positions): the fine
+  // position of a pair is the high word of the sum, its fraction the low word
   typename Store<ST>::T* out = fine + size_t(ij) * MQ;
   if (ATT && !MT && !bin_reaches(bs, ij, J_begin, J_end)) {  // uniform: no voxel of the template here
     for (int k = J_begin + threadIdx.x; k < J_end; k += blockDim.x) out[k] = Store<ST>::put(0.0f);
@@ -282,7 +286,7 @@ __device__ __forceinline__ void splat_body(int bx, int by,
                      leg_slot(abs(brx + 2 * c), half) * nzp * int(sizeof(Leg)));
   };
   auto pos_at = [&](int2 co, int r) {
-    return int(uint64_t(legs_t[co.x / int(sizeof(Leg)) + r].delay + legs_t[co.y / int(sizeof(Leg)) + r].delay) >> sh);
+    return int(uint64_t(legs_t[co.x / int(sizeof(Leg)) + r].delay + legs_t[co.y / int(sizeof(Leg)) + r].delay) >> 32);
   };
   {
     auto ends = [&](int i) {  // segments are never empty
@@ -302,10 +306,10 @@ __device__ __forceinline__ void splat_body(int bx, int by,
       lay_hi[threadIdx.x] = -kNoRow;
     }
     for (int c = threadIdx.x; c < nx; c += blockDim.x) colofs[c] = col_ofs(c);
-    {  // clear the tiles, 16 bytes per store
-      ulonglong2* t2 = reinterpret_cast<ulonglong2*>(tile);
-      for (int k = threadIdx.x; k < NT * TS / 2; k += blockDim.x) t2[k] = make_ulonglong2(0ull, 0ull);
-      if (((NT * TS) & 1) && threadIdx.x == 0) tile[NT * TS - 1] = 0ull;
+    {  // clear the tiles (and the alignment word), 16 bytes per store
+      ulonglong2* t2 = reinterpret_cast<ulonglong2*>(smem);
+      for (int k = threadIdx.x; k < (1 + NT * TS) / 2; k += blockDim.x) t2[k] = make_ulonglong2(0ull, 0ull);
+      if (((1 + NT * TS) & 1) && threadIdx.x == 0) smem[NT * TS] = 0ull;
     }
     for (int off = 32; off >= 1; off >>= 1) m = max(m, unsigned(__shfl_xor(int(m), off)));
     if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
@@ -317,17 +321,36 @@ __device__ __forceinline__ void splat_body(int bx, int by,
   const double scale = ldexp(1.0, kx);
   const double s_hi = ldexp(1.0, 32 - kx), s_lo = ldexp(1.0, -kx);  // back from fixed point
   // first row of each (column, layer) whose position is >= J_begin - 1 (the
-  // same thread wrote the slot's two positions above)
-  for (int i = threadIdx.x; i < seg.n * nx; i += blockDim.x) {
-    const int sg = i / nx, c = i - sg * nx;
-    const int2 co = colofs[c];
-    const int2 jlh = pn[i];
-    atomicMin(&lay_lo[sg], jlh.x);
-    atomicMax(&lay_hi[sg], jlh.y);
-    int jf;
-    const int first = first_row_at([&](int r) { return pos_at(co, r); }, seg.lo[sg], seg.hi[sg], jlh.x, jlh.y,
-                                   J_begin - 1, &jf);
-    pn[i] = make_int2(first, jf);
+  // same thread wrote the slot's two positions above).  The layer ranges are
+  // reduced over the wave first when its 64 slots share a layer (atomics of a
+  // whole wave on one LDS word run one lane at a time).
+  for (int b0 = 0; b0 < seg.n * nx; b0 += blockDim.x) {
+    const int i = b0 + threadIdx.x;
+    const bool valid = i < seg.n * nx;
+    const int iv = valid ? i : seg.n * nx - 1;  // past the end: the last slot's layer, neutral range
+    const int sg = iv / nx, c = iv - sg * nx;
+    const int2 jlh = valid ? pn[i] : make_int2(kNoRow, -kNoRow);
+    if (__shfl(sg, 0) == __shfl(sg, 63)) {  // every lane is here (blockDim is a multiple of 64)
+      int lo_v = jlh.x, hi_v = jlh.y;
+      for (int off = 32; off >= 1; off >>= 1) {
+        lo_v = min(lo_v, __shfl_xor(lo_v, off));
+        hi_v = max(hi_v, __shfl_xor(hi_v, off));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        atomicMin(&lay_lo[sg], lo_v);
+        atomicMax(&lay_hi[sg], hi_v);
+      }
+    } else if (valid) {
+      atomicMin(&lay_lo[sg], jlh.x);
+      atomicMax(&lay_hi[sg], jlh.y);
+    }
+    if (valid) {
+      const int2 co = colofs[c];
+      int jf;
+      const int first = first_row_at([&](int r) { return pos_at(co, r); }, seg.lo[sg], seg.hi[sg], jlh.x, jlh.y,
+                                     J_begin - 1, &jf);
+      pn[i] = make_int2(first, jf);
+    }
   }
   __syncthreads();
 
@@ -397,9 +420,9 @@ __device__ __forceinline__ void splat_body(int bx, int by,
         // The first lane of a column left out of the tile stores that row and
         // its position for the next tile.
         auto add = [&](const Rows& v) {
-          const bool have = live && r >= p0 && r < hi;
+          const bool have = live && rr >= k0 && r < hi;  // rows above the pointer: first block only
           const uint64_t D = uint64_t(v.da + v.db);
-          const int J = int(D >> sh);
+          const int J = int(D >> 32);
           const bool in = have && J < J1;
           // J + 1 >= J0 holds while delays grow with depth within a layer
           bool mine = true;
@@ -412,10 +435,11 @@ __device__ __forceinline__ void splat_body(int bx, int by,
           if (in && mine && v.xv != 0.0f && J + 1 >= J0) {
             float w = v.xv * (v.pa * v.pb);
             if (ABSW) w = fabsf(w);
-            const float phi = float(uint32_t(D) << qs) * kTwoM32;
+            const float phi = float(uint32_t(D)) * kTwoM32;
             const float w1 = w * phi;
-            atomicAdd(&tile[tb + (J >= J0 ? J - J0 : tile_bins + 1)], to_fixed<WIDE>(w - w1, scale));
-            atomicAdd(&tile[tb + J + 1 - J0], to_fixed<WIDE>(w1, scale));
+            unsigned long long* t = tile + tb + (J + 1 - J0);  // slot of position J (J = J0 - 1: slot 0)
+            atomicAdd(t, to_fixed<WIDE>(w - w1, scale));
+            atomicAdd(t + 1, to_fixed<WIDE>(w1, scale));
           }
           // rows of column c taken: a prefix of its rows in the block from k0
           const int nxt = k0 + __popcll(__ballot(in) & colmask);
@@ -443,44 +467,44 @@ __device__ __forceinline__ void splat_body(int bx, int by,
     // outside the pass and becomes the next tile's first position
     const int n = J1 - J0;
     if constexpr (MT) {
-      const unsigned long long carry = threadIdx.x < NT ? tile[threadIdx.x * TS + n] : 0ull;
+      const unsigned long long carry = threadIdx.x < NT ? tile[threadIdx.x * TS + n + 1] : 0ull;
       for (int i = threadIdx.x; i < NT * n; i += blockDim.x) {
         const int g = i / n, k = i - g * n;
-        out[size_t(g) * P * K * MQ + J0 + k] = fixed_to_store<ST>(tile[g * TS + k], s_hi, s_lo);
-        tile[g * TS + k] = 0ull;
+        out[size_t(g) * P * K * MQ + J0 + k] = fixed_to_store<ST>(tile[g * TS + 1 + k], s_hi, s_lo);
+        tile[g * TS + 1 + k] = 0ull;
       }
       __syncthreads();
       if (threadIdx.x < NT) {
-        tile[threadIdx.x * TS] = carry;
-        tile[threadIdx.x * TS + n] = 0ull;
+        tile[threadIdx.x * TS + 1] = carry;
+        tile[threadIdx.x * TS + n + 1] = 0ull;
       }
     } else {
-      const unsigned long long carry = tile[n];
+      const unsigned long long carry = tile[n + 1];
       typename Store<ST>::T* o = out + J0;
       if ((reinterpret_cast<uintptr_t>(o) & (2 * sizeof(*o) - 1)) == 0) {  // uniform
         // two positions per thread: one 16-byte LDS read and clear, one paired
         // store; an odd last position by the last thread
         for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
-          ulonglong2* tp = reinterpret_cast<ulonglong2*>(tile) + i;
+          ulonglong2* tp = reinterpret_cast<ulonglong2*>(tile + 1) + i;
           const ulonglong2 v = *tp;
           *tp = make_ulonglong2(0ull, 0ull);
           *reinterpret_cast<Pair2<typename Store<ST>::T>*>(o + 2 * i) = {fixed_to_store<ST>(v.x, s_hi, s_lo),
                                                                          fixed_to_store<ST>(v.y, s_hi, s_lo)};
         }
         if ((n & 1) && threadIdx.x == blockDim.x - 1) {
-          o[n - 1] = fixed_to_store<ST>(tile[n - 1], s_hi, s_lo);
-          tile[n - 1] = 0ull;
+          o[n - 1] = fixed_to_store<ST>(tile[n], s_hi, s_lo);
+          tile[n] = 0ull;
         }
       } else {
         for (int k = threadIdx.x; k < n; k += blockDim.x) {
-          o[k] = fixed_to_store<ST>(tile[k], s_hi, s_lo);
-          tile[k] = 0ull;
+          o[k] = fixed_to_store<ST>(tile[1 + k], s_hi, s_lo);
+          tile[1 + k] = 0ull;
         }
       }
       __syncthreads();
       if (threadIdx.x == 0) {
-        tile[0] = carry;
-        tile[n] = 0ull;
+        tile[1] = carry;
+        tile[n + 1] = 0ull;
       }
     }
     __syncthreads();
@@ -1720,9 +1744,15 @@ size_t aligned(size_t b) { return (b + 255) & ~size_t(255); }
 // usual tile; 0 if not even 64 positions per template fit.
 int splat_mt_tile(const umbir_geometry& G) {
   const long avail = kSplatLdsBytes - 1024 - long(G.n_seg + 1) * G.nx * long(sizeof(int2));
-  const long per = avail / long(sizeof(unsigned long long)) / G.n_gamma - 2;
+  const long per = (avail / long(sizeof(unsigned long long)) - 1) / G.n_gamma - 2;
   const long t = std::min<long>(G.tile_bins, per / 64 * 64);
   return t >= 64 ? int(t) : 0;
+}
+
+// Dynamic LDS of a splat workgroup: one alignment word, nt tiles of tile + 2
+// slots, the row pointers and the column offsets.
+size_t splat_lds_bytes(int nt, int tile, const umbir_geometry& G) {
+  return (1 + size_t(nt) * (tile + 2)) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2);
 }
 
 // blocks of k_prescale, one per 1024 voxels up to kPrescaleBlocks
@@ -1737,9 +1767,7 @@ void launch_splat_k(const umbir_geometry& G, dim3 grid, const float* xt, int qs,
   const int nt = MT ? G.n_gamma : 1;
   const int tile = MT ? splat_mt_tile(G) : G.tile_bins;
   // (with a cost to fold, at least the 256 doubles its sums use)
-  const size_t lds = std::max<size_t>(
-      fold.out ? 256 * sizeof(double) : 0,
-      size_t(nt) * (tile + 2) * sizeof(unsigned long long) + size_t(G.n_seg + 1) * G.nx * sizeof(int2));
+  const size_t lds = std::max<size_t>(fold.out ? 256 * sizeof(double) : 0, splat_lds_bytes(nt, tile, G));
   UMBIR_LAUNCH("splat", (k_splat<ABSW, WIDE, ST, ATT, MT>), grid, dim3(64 * kSplatWaves), lds, s, xt, G.nx,
                G.nzp, G.n_off, G.legs_t, G.gunit_t, G.base, G.P, G.K, qs, MQ, seg, int(G.chunk_bins), tile, xmax,
                n_xmax, gbin,
@@ -1924,8 +1952,7 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
   bp.chunk_bins = int(G.chunk_bins);
   bp.tile_bins = G.tile_bins;
   bp.wide = G.nx * (G.seg_hi[G.n_seg - 1] - G.seg_lo[0]) < kSplatNarrowMin;
-  lds[kStSplat] = std::max(lds[kStSplat], size_t(G.tile_bins + 2) * sizeof(unsigned long long) +
-                                              size_t(G.n_seg + 1) * G.nx * sizeof(int2));
+  lds[kStSplat] = std::max(lds[kStSplat], splat_lds_bytes(1, G.tile_bins, G));
   for (int t = 0; t < PK; ++t)
     for (int c = 0; c < G.chunks; ++c) items[kStSplat].push_back(make_int4(pi, c, t, 0));
   // convolution: as launch_conv_mfma (the problem's tile count and order,
