@@ -351,10 +351,13 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   workgroup): 1 trace tiles fastest, 2 sample tiles
  *                   fastest.  Bitwise identical results.
  *  conv_tile_rows   output samples per matrix-core convolution workgroup:
- *                   32, 64 or 128 (default 64 when that leaves at least 512
- *                   workgroups, else 32); the workgroup's four waves share
- *                   each fetched chunk of fine-grid rows among its 32-sample
- *                   tiles.  Changes only the order of the sums.
+ *                   32, 64 or 128; the workgroup's four waves share each
+ *                   fetched chunk of fine-grid rows among its 32-sample
+ *                   tiles.  Default at build: with bf16-piece products, 128
+ *                   when that leaves at least 256 workgroups, else 64
+ *                   likewise; otherwise 64 when that leaves at least 512
+ *                   workgroups, else 32.  Changes only the order of the
+ *                   sums.
  *  corr_tile_rows   rows (output samples) of one wave's tile in the
  *                   matrix-core correlation: 32, 64 or 128 (default; a
  *                   workgroup of four waves covers four tiles).  Bitwise
@@ -371,9 +374,17 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   (results agree to rounding).  Direct needs FP32 storage,
  *                   no attenuation and 8 M + 4 (Q L_h + 2) <= 65536 (ENOTSUP
  *                   from umbir_set_tuning otherwise); it suits small problems.
+ *  products         how the matrix-core convolution and correlation (FP32
+ *                   storage) form their FP32 products: 1 as FP32 products
+ *                   (v_mfma_f32_32x32x2f32); 2 (default) on the bf16 matrix
+ *                   cores, each factor split exactly into three bf16 pieces
+ *                   and the product taken as the six piece products whose
+ *                   orders sum to at most 4 (v_mfma_f32_32x32x16_bf16, FP32
+ *                   accumulation; the three left out are below 2^-23 of the
+ *                   product).  Results agree to rounding.
  * A field of 0 (or less) in umbir_set_tuning keeps the current value (EINVAL
- * for a conv_grid, conv_tile_rows or corr_tile_rows outside the values
- * above).  The tuning of
+ * for a conv_grid, conv_tile_rows, corr_tile_rows or products outside the
+ * values above).  The tuning of
  * a geometry must not change while another call uses it.
  * umbir_autotune times candidates of each field on `stream` (an A + A^T pair
  * for the form, the forward for the splat and the convolution, the adjoint
@@ -389,6 +400,7 @@ typedef struct {
     int corr_tile_rows;
     int corr_blocks;
     int operator_form;
+    int products;
 } umbir_tuning;
 int umbir_get_tuning(const umbir_geometry* geom, umbir_tuning* out);
 int umbir_set_tuning(umbir_geometry* geom, const umbir_tuning* tuning);

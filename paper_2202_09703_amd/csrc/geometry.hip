@@ -581,9 +581,15 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
       G->seg_hi[G->n_seg - 1] = r + 1;
     }
     apply_splat_blocks(G, G->splat_blocks);
-    // two output tiles per convolution workgroup when that still leaves at
-    // least two workgroups per CU (small problems keep the wider grid)
-    G->conv_tiles = long(G->traces() + 31) / 32 * ((G->M + 63) / 64) >= 512 ? 2 : 1;
+    // output tiles per convolution workgroup: with FP32 products two when
+    // that still leaves at least two workgroups per CU; with bf16 pieces
+    // (whose splitting of the fetched rows more tiles share) four when that
+    // leaves one workgroup per CU, else two likewise (small problems keep the
+    // wider grid)
+    const long tt = (G->traces() + 31) / 32;
+    if (G->split && tt * ((G->M + 127) / 128) >= 256) G->conv_tiles = 4;
+    else if (G->split && tt * ((G->M + 63) / 64) >= 256) G->conv_tiles = 2;
+    else G->conv_tiles = tt * ((G->M + 63) / 64) >= 512 ? 2 : 1;
   }
 
   const size_t legs = size_t(G->nz) * G->n_off;
@@ -748,6 +754,7 @@ int umbir_get_tuning(const umbir_geometry* G, umbir_tuning* out) {
   out->corr_tile_rows = 32 * G->corr_tiles;
   out->corr_blocks = G->corr_blocks;
   out->operator_form = G->form;
+  out->products = G->split ? 2 : 1;
   return UMBIR_OK;
 }
 
@@ -755,6 +762,7 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (!G || !t) return fail(UMBIR_EINVAL, "NULL argument");
   if (t->conv_grid > 2) return fail(UMBIR_EINVAL, "conv_grid must be 1 or 2");
   if (t->operator_form > 2) return fail(UMBIR_EINVAL, "operator_form must be 1 or 2");
+  if (t->products > 2) return fail(UMBIR_EINVAL, "products must be 1 or 2");
   if (t->operator_form == 2 && !direct_eligible(*G))
     return fail(UMBIR_ENOTSUP, "the direct form needs FP32 storage, one template and 8 M + 4 (Q L_h + 2) <= 65536");
   if (t->corr_tile_rows > 0 && t->corr_tile_rows != 32 && t->corr_tile_rows != 64 && t->corr_tile_rows != 128)
@@ -768,6 +776,7 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (t->corr_tile_rows > 0) G->corr_tiles = t->corr_tile_rows / 32;
   if (t->corr_blocks > 0) G->corr_blocks = t->corr_blocks;
   if (t->operator_form > 0) G->form = t->operator_form;
+  if (t->products > 0) G->split = t->products == 2;
   return UMBIR_OK;
 }
 

@@ -186,6 +186,7 @@ struct umbir_geometry {
   int corr_tiles = 4;          // 32-row tiles per wave of the matrix-core correlation (1, 2 or 4)
   int corr_blocks = 1024;      // target workgroups of the correlation (sets row blocks per workgroup)
   int form = 1;                // operator form: 1 factored (splat + convolution), 2 direct (Eq. (13) tap by tap)
+  int split = 1;               // FP32 matrix-core products: 1 as three bf16 pieces each, 0 as FP32 products
   // attenuation: n_gamma templates at gamma_g = g * gamma_step (1 without)
   int n_gamma = 1;
   double gamma_step = 0.0;
@@ -323,6 +324,7 @@ struct BatchProb {
   // launch shapes of the sweeps
   int chunk_bins, tile_bins, wide;  // splat
   int conv_tiles;                   // output tiles per convolution block
+  int conv_split, corr_split;       // products of the dense sweeps as bf16 pieces (umbir_geometry::split)
   int corr_per;                     // row blocks per correlation block
   int groups, tpg, gbatch, vpb;     // gather: trace groups, traces per group and launch, voxels per block
   int nblk;                         // prior-update blocks

@@ -1174,6 +1174,130 @@ __device__ __forceinline__ void corr_mfma_body(int bx, int by, const float* __re
   }
 }
 
+// C^T with the products as three bf16 pieces each (v_mfma_f32_32x32x16_bf16,
+// six per 16 contraction indices; split8_bf16x3).  The contraction index of
+// product s is labelled as in the FP32 kernel, lane half lk holding
+// k = lk H + 8 s + e (e < 8), so a lane reads 8 consecutive taps of its
+// column and 8 consecutive segment samples of its row as one 16-byte word.
+// The Hankel rows would put those 8 samples at every alignment, so a tile's
+// 32 rows are n_blk + 8 i + rho (i < 32) for one residue rho: lane i reads
+// segment words 8 (i + s) + ... of the copy of the segment shifted by rho.
+// A row block is 256 rows, the 8 residues, two per wave; the block stages
+// eight shifted copies of its segment, split into pieces, and the taps once,
+// split and transposed ([piece][t][k], H + 4 words per t: 8 lanes' 16-byte
+// reads on distinct banks).  Writes stay coalesced along t.
+constexpr int kCorrX3Rows = 256;
+
+__host__ __device__ inline int corr_x3_tap_words(int H) { return H + 4; }
+__host__ __device__ inline int corr_x3_seg_words(int H) { return (2 * H + kCorrX3Rows) / 2 + 4; }
+__host__ __device__ inline int corr_x3_lds_words(int Q, int H) {
+  return 3 * Q * corr_x3_tap_words(H) + 8 * 3 * corr_x3_seg_words(H);
+}
+
+// The bf16-piece forms where their LDS fits a workgroup (long templates keep
+// the FP32 products).
+constexpr size_t kMaxWorkgroupLds = 163840;
+inline bool conv_split(const umbir_geometry& G) {
+  return G.split && size_t(G.Lh + 1) * (3 * G.Q / 2 + 4) * sizeof(float) <= kMaxWorkgroupLds;
+}
+inline bool corr_split(const umbir_geometry& G) {
+  return G.split && size_t(corr_x3_lds_words(G.Q, corr_half(G.Lh))) * sizeof(float) <= kMaxWorkgroupLds;
+}
+
+template <int QT>
+__device__ __forceinline__ void corr_x3_body(int bx, int by, const float* __restrict__ rt,
+                                             const float* __restrict__ hq, int M, int Lh, int rb_per_block,
+                                             float* __restrict__ fine, long tstride, BinSkip bs) {
+  constexpr int Q = 32 * QT;
+  constexpr int ROWS = kCorrX3Rows;
+  extern __shared__ __align__(16) float sm[];
+  const int H = corr_half(Lh);
+  const int TW = corr_x3_tap_words(H), SW = corr_x3_seg_words(H);
+  const int SX = 2 * H + ROWS;  // segment positions a row block reads
+  unsigned* taps3 = reinterpret_cast<unsigned*>(sm);  // [3][Q][TW]: piece, column t, taps k in pairs
+  unsigned* seg3 = taps3 + 3 * Q * TW;                // [8][3][SW]: shift rho, piece, positions in pairs
+  const int ij = bx;
+  const float* r = rt + size_t(ij) * M;
+  float* c = fine + size_t(ij) * tstride;
+  // taps: pairs (k, k + 1) of column t, zero from Lh on and in the padding
+  for (int i = threadIdx.x; i < Q * TW; i += blockDim.x) {
+    const int kp = i / Q, t = i - kp * Q;  // consecutive threads: consecutive t of one tap row
+    const int k = 2 * kp;
+    const float h0 = k < Lh && kp < H ? hq[size_t(k) * Q + t] : 0.0f;
+    const float h1 = k + 1 < Lh && kp < H ? hq[size_t(k + 1) * Q + t] : 0.0f;
+    unsigned p1, p2, p3;
+    split_pair_bf16x3(h0, h1, p1, p2, p3);
+    taps3[(0 * Q + t) * TW + kp] = p1;
+    taps3[(1 * Q + t) * TW + kp] = p2;
+    taps3[(2 * Q + t) * TW + kp] = p3;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  const int rb0 = by * rb_per_block;
+  const int rb_end = min(rb0 + rb_per_block, (M + ROWS - 1) / ROWS);
+  for (int rb = rb0; rb < rb_end; ++rb) {
+    const int n_blk = rb * ROWS;
+    if (!bin_reaches(bs, ij, long(n_blk) * Q, long(min(n_blk + ROWS, M)) * Q)) continue;  // uniform
+    __syncthreads();  // the previous row block's segment copies are read
+    // copy rho holds r[n_blk + 1 + rho + x] at position x < SX, split; a
+    // thread writes 8 positions of one copy
+    for (int i = threadIdx.x; i < 8 * (SX / 8); i += blockDim.x) {
+      const int rho = i / (SX / 8), x8 = i - rho * (SX / 8);
+      const int m0 = n_blk + 1 + rho + 8 * x8;
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = m0 + e < M ? r[m0 + e] : 0.0f;
+      const Pieces8 pc = split8_bf16x3(make_float4(v[0], v[1], v[2], v[3]), make_float4(v[4], v[5], v[6], v[7]));
+#pragma unroll
+      for (int tau = 0; tau < 3; ++tau)
+        reinterpret_cast<uint4*>(seg3 + (rho * 3 + tau) * SW)[x8] = pc.p[tau];
+    }
+    __syncthreads();
+    floatx16 acc[2][QT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < QT; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+    const int rho0 = 2 * wave;
+    const uint4* sa = reinterpret_cast<const uint4*>(seg3) + li + lk * (H / 8);  // + copy (rho, piece) + s
+    const uint4* sb = reinterpret_cast<const uint4*>(taps3) + lk * (H / 8);      // + (piece, t) + s
+    for (int st = 0; st < H / 8; ++st) {
+      uint4 bq[QT][3];
+#pragma unroll
+      for (int b = 0; b < QT; ++b)
+#pragma unroll
+        for (int tau = 0; tau < 3; ++tau) bq[b][tau] = sb[((tau * Q + b * 32 + li) * TW) / 4 + st];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        uint4 aq[3];
+#pragma unroll
+        for (int tau = 0; tau < 3; ++tau) aq[tau] = sa[((rho0 + a) * 3 + tau) * (SW / 4) + st];
+#pragma unroll
+        for (int b = 0; b < QT; ++b) acc[a][b] = mfma_bf16x3(aq, bq[b], acc[a][b]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int n = n_blk + 8 * (8 * (i >> 2) + 4 * lk + (i & 3)) + rho0 + a;
+        if (n < M) {
+#pragma unroll
+          for (int b = 0; b < QT; ++b) c[size_t(n) * Q + b * 32 + li] = acc[a][b][i];
+        }
+      }
+  }
+}
+
+template <int QT>
+__global__ __launch_bounds__(256) void k_corr_x3(const float* __restrict__ rt, const float* __restrict__ hq, int M,
+                                                 int Lh, int rb_per_block, float* __restrict__ fine, long tstride,
+                                                 BinSkip bs) {
+  corr_x3_body<QT>(blockIdx.x, blockIdx.y, rt, hq, M, Lh, rb_per_block, fine, tstride, bs);
+}
+
 template <int QT, int NT>
 __global__ __launch_bounds__(256) void k_corr_mfma(const float* __restrict__ rt,
                                                    const float* __restrict__ hq, int M, int Lh, int rb_per_block,
@@ -1217,7 +1341,19 @@ struct ChunkOrder {
 // 16-byte reads over all banks.  With one accumulation chain the kernel fits
 // 128 registers and 35 KB of LDS at Q = 32, so four blocks share a CU.
 // Epilogue as in k_conv.
-template <int Q, int NTC = 1>
+// X3: the products as three bf16 pieces each (split8_bf16x3) on the bf16
+// matrix cores, v_mfma_f32_32x32x16_bf16, six per 16 contraction indices
+// against eight FP32 ones per 16: lane half lk holds chunk positions
+// 32 lk + 8 s + e (e < 8) in product s of four, the same positions as above.
+// The taps are split once, while staged: a tap row holds the three pieces of
+// its Q taps one after the other, 3 Q / 2 + 4 words (16-byte reads of 8 lanes
+// on distinct banks); a chunk of B is split once for all NTC tiles.
+constexpr int kConvWaves = 4;  // waves of a matrix-core convolution workgroup, sharing its window
+
+template <int Q>
+__host__ __device__ constexpr int conv_x3_row_words() { return 3 * Q / 2 + 4; }
+
+template <int Q, int NTC = 1, bool X3 = false>
 __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
@@ -1232,7 +1368,38 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   const int tr0 = bx * 32;
   const int m0 = by * 32 * NTC;  // NTC output tiles of 32 samples, m0 + 32 j
   const long MQ = long(M) * Q;
-  {
+  constexpr int TS3 = conv_x3_row_words<Q>();
+  if constexpr (X3) {
+    // [Lh + 1][TS3] words: a row's three pieces of Q taps, padding, a zero row
+    unsigned* t3 = reinterpret_cast<unsigned*>(sm);
+    for (int i = threadIdx.x; i < (Lh + 1) * TS3; i += blockDim.x) {
+      const int r = i / TS3, c = i - r * TS3;
+      if (r >= Lh || c >= 3 * Q / 2) t3[i] = 0u;
+    }
+    constexpr int Q4 = Q / 4;
+    const float4* h4 = reinterpret_cast<const float4*>(hq);
+    const int n4 = Lh * Q4;
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < n4; i0 += U * blockDim.x) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = h4[min(i0 + u * int(blockDim.x), n4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * blockDim.x;
+        if (i < n4) {
+          const int k = i / Q4, c = i - k * Q4;  // taps 4 c .. 4 c + 3 of row k
+          uint2 p1, p2, p3;
+          split_pair_bf16x3(v[u].x, v[u].y, p1.x, p2.x, p3.x);
+          split_pair_bf16x3(v[u].z, v[u].w, p1.y, p2.y, p3.y);
+          uint2* row = reinterpret_cast<uint2*>(t3 + k * TS3 + 2 * c);
+          row[0] = p1;
+          row[Q / 4] = p2;
+          row[Q / 2] = p3;
+        }
+      }
+    }
+  } else {
     // zero rows and columns first, then the taps with 16-byte loads, several
     // in flight per thread (hq rows are Q floats, 16-byte aligned)
     constexpr int R4 = TS / 4, Q4 = Q / 4;
@@ -1270,7 +1437,7 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   const bool reach = __syncthreads_or(threadIdx.x < 32 && tr0 + int(threadIdx.x) < PK &&
                                       bin_reaches(bs, tr0 + threadIdx.x, long(m0 - Lh) * Q,
                                                   long(m0 + 31 + EXT) * Q));
-  const int rounds = reach ? (co.P + 3) / 4 : 0;
+  const int rounds = reach ? (co.P + kConvWaves - 1) / kConvWaves : 0;
   floatx16 acc[NTC];
 #pragma unroll
   for (int j = 0; j < NTC; ++j)
@@ -1281,13 +1448,13 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   // row clamped into [0, M); a row outside [0, M), or a step past the window,
   // takes the A row of zeros instead, so B needs no masking.
   const float* src = fine + size_t(min(tr0 + li, PK - 1)) * tstride + t0;
-  // the chunk of step ch = rd 4 + wave advances by 4 per round, modulo P
+  // the chunk of step ch = rd W + wave advances by W = kConvWaves per round, modulo P
   int jf = (wave + co.rot) % co.P, jm = jf;  // fetch and multiply positions
   int sf = wave, sm_ = wave;                  // their steps
   auto next_row = [&](int& j, int& step) {
     const int nc = step < co.P ? co.v_lo + j * CN : -(1 << 30);  // past the window: no row
-    step += 4;
-    j += 4;
+    step += kConvWaves;
+    j += kConvWaves;
     while (j >= co.P) j -= co.P;
     return nc;
   };
@@ -1302,6 +1469,26 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   auto multiply = [&](const float4 (&b)[8]) {
     const int nc = next_row(jm, sm_);
     const int n = nc + ro;
+    if constexpr (X3) {
+      Pieces8 bp[4];  // the chunk's B: positions 8 s .. 8 s + 7 of the lane's 32
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) bp[s4] = split8_bf16x3(b[2 * s4], b[2 * s4 + 1]);
+      __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+      for (int j = 0; j < NTC; ++j) {
+        if (NTC > 1 && (nc > m0 + 32 * j + 30 || nc + CN - 1 < m0 + 32 * j - Lh)) continue;
+        int k = m + 32 * j - 1 - n;
+        if (n < 0 || n >= M || unsigned(k) >= unsigned(Lh)) k = Lh;
+        const uint4* arow = reinterpret_cast<const uint4*>(sm) + k * (TS3 / 4) + t0 / 8;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const uint4 a[3] = {arow[s4], arow[Q / 8 + s4], arow[Q / 4 + s4]};
+          acc[j] = mfma_bf16x3(a, bp[s4].p, acc[j]);
+        }
+      }
+      __builtin_amdgcn_s_setprio(0);
+      return;
+    }
     // a wave issuing its chunk's MFMAs takes precedence over waves issuing
     // loads and address arithmetic (measured: 2-4 % on this kernel; the
     // correlation, whose operands come from LDS, is slower with it)
@@ -1326,13 +1513,14 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
     }
     __builtin_amdgcn_s_setprio(0);
   };
-  // the epilogue's inputs for this thread's 4 NTC outputs, fetched now so
+  // the epilogue's inputs for this thread's EPT NTC outputs, fetched now so
   // that they arrive while the window multiplies
-  float pre_base[4 * NTC], pre_db[4 * NTC], pre_g[4 * NTC];
+  constexpr int EPT = 1024 / (64 * kConvWaves);  // outputs per thread of one 32 x 32 tile
+  float pre_base[EPT * NTC], pre_db[EPT * NTC], pre_g[EPT * NTC];
 #pragma unroll
-  for (int q = 0; q < 4 * NTC; ++q) {
-    const int e = threadIdx.x + (q & 3) * 256;
-    const int mm = min(m0 + 32 * (q >> 2) + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
+  for (int q = 0; q < EPT * NTC; ++q) {
+    const int e = threadIdx.x + (q % EPT) * 64 * kConvWaves;
+    const int mm = min(m0 + 32 * (q / EPT) + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
     const size_t idx = size_t(tr) * M + mm;
     pre_base[q] = base ? base[idx] : 0.0f;
     pre_db[q] = g ? dbasis[idx] : 0.0f;
@@ -1349,26 +1537,27 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
     multiply(b1);
   }
   __syncthreads();  // every wave is done with the taps: reuse them for the reduction
-  // sum the four partial tiles of each output tile: red[j][wave][row][col]
+  // sum the waves' partial tiles of each output tile: red[j][wave][row][col]
   float* red = sm;
 #pragma unroll
   for (int j = 0; j < NTC; ++j)
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
-      red[((j * 4 + wave) * 32 + row) * 33 + li] = acc[j][i];
+      red[((j * kConvWaves + wave) * 32 + row) * 33 + li] = acc[j][i];
     }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4 * NTC; ++q) {
-    const int j = q >> 2;
-    const int e = threadIdx.x + (q & 3) * 256;
+  for (int q = 0; q < EPT * NTC; ++q) {
+    const int j = q / EPT;
+    const int e = threadIdx.x + (q % EPT) * 64 * kConvWaves;
     const int col = e >> 5, row = e & 31;  // consecutive threads: consecutive m of one trace
     const int mm = m0 + 32 * j + row, tr = tr0 + col;
     if (mm < M && tr < PK) {
-      const float* rj = red + j * 4 * 32 * 33;
-      const float v = rj[(0 * 32 + row) * 33 + col] + rj[(1 * 32 + row) * 33 + col] +
-                      rj[(2 * 32 + row) * 33 + col] + rj[(3 * 32 + row) * 33 + col];
+      const float* rj = red + j * kConvWaves * 32 * 33;
+      float v = rj[row * 33 + col];
+#pragma unroll
+      for (int w = 1; w < kConvWaves; ++w) v += rj[(w * 32 + row) * 33 + col];
       float val = sign * v;
       if (base) val += pre_base[q];
       if (g) val -= pre_g[q] * pre_db[q];
@@ -1377,23 +1566,23 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   }
 }
 
-template <int Q, int NTC>
-__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ fine,
+template <int Q, int NTC, bool X3>
+__global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
                                                    const float* __restrict__ dbasis, float* out, long tstride,
                                                    BinSkip bs) {
-  conv_mfma_body<Q, NTC>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+  conv_mfma_body<Q, NTC, X3>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
 }
 
 // The same with the grid's dimensions swapped (sample tiles fastest).
-template <int Q, int NTC>
-__global__ __launch_bounds__(256) void k_conv_mfma_t(const float* __restrict__ fine, const float* __restrict__ hq,
+template <int Q, int NTC, bool X3>
+__global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma_t(const float* __restrict__ fine, const float* __restrict__ hq,
                                                      int M, int Lh, int PK, const float* base, float sign,
                                                      const float* __restrict__ g, const float* __restrict__ dbasis,
                                                      float* out, long tstride, BinSkip bs) {
-  conv_mfma_body<Q, NTC>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+  conv_mfma_body<Q, NTC, X3>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
 }
 
 // C on the matrix cores with 16-bit storage (Q in {32, 64}): as k_conv_mfma,
@@ -1613,20 +1802,30 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
 // LDS of the matrix-core convolution: the padded taps, reused at the end for
 // the four waves' partial tiles of each of the NTC output tiles
 size_t conv_mfma_lds(const umbir_geometry& G) {
-  return std::max<size_t>(size_t(G.Lh + 1) * (G.Q + 4), size_t(G.conv_tiles) * 4 * 32 * 33) * sizeof(float);
+  const size_t row = conv_split(G) ? size_t(3 * G.Q / 2 + 4) : size_t(G.Q + 4);  // words per tap row
+  return std::max<size_t>(size_t(G.Lh + 1) * row, size_t(G.conv_tiles) * kConvWaves * 32 * 33) * sizeof(float);
+}
+
+template <int Q, int NTC, bool X3>
+void launch_conv_mfma_x(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
+                        float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
+  const size_t lds = conv_mfma_lds(G);
+  const unsigned tt = unsigned((G.traces() + 31) / 32), mt = unsigned((G.M + 32 * NTC - 1) / (32 * NTC));
+  if (G.conv_grid == 2)
+    UMBIR_LAUNCH("conv", (k_conv_mfma_t<Q, NTC, X3>), dim3(mt, tt), dim3(64 * kConvWaves), lds, s, fine, hq, G.M, G.Lh,
+                 G.traces(),
+                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+  else
+    UMBIR_LAUNCH("conv", (k_conv_mfma<Q, NTC, X3>), dim3(tt, mt), dim3(64 * kConvWaves), lds, s, fine, hq, G.M, G.Lh,
+                 G.traces(),
+                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
 }
 
 template <int Q, int NTC>
 void launch_conv_mfma_n(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
                         float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
-  const size_t lds = conv_mfma_lds(G);
-  const unsigned tt = unsigned((G.traces() + 31) / 32), mt = unsigned((G.M + 32 * NTC - 1) / (32 * NTC));
-  if (G.conv_grid == 2)
-    UMBIR_LAUNCH("conv", (k_conv_mfma_t<Q, NTC>), dim3(mt, tt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(),
-                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
-  else
-    UMBIR_LAUNCH("conv", (k_conv_mfma<Q, NTC>), dim3(tt, mt), dim3(256), lds, s, fine, hq, G.M, G.Lh, G.traces(),
-                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+  if (conv_split(G)) launch_conv_mfma_x<Q, NTC, true>(G, fine, hq, base, sign, g, out, tstride, gbin, s);
+  else launch_conv_mfma_x<Q, NTC, false>(G, fine, hq, base, sign, g, out, tstride, gbin, s);
 }
 
 template <int Q>
@@ -1692,8 +1891,20 @@ void launch_corr_mfma_nt(const umbir_geometry& G, const float* r, const float* h
 }
 
 template <int QT>
+void launch_corr_x3(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride, int gbin,
+                    hipStream_t s) {
+  const size_t lds = size_t(corr_x3_lds_words(32 * QT, corr_half(G.Lh))) * sizeof(float);
+  const int nrb = (G.M + kCorrX3Rows - 1) / kCorrX3Rows;
+  const int per = std::max(1, int((long(G.traces()) * nrb) / std::max(1, G.corr_blocks)));
+  dim3 grid(G.traces(), (nrb + per - 1) / per);
+  UMBIR_LAUNCH("corr", (k_corr_x3<QT>), grid, dim3(256), lds, s, r, hq, G.M, G.Lh, per, fine, tstride,
+               bin_skip(G, gbin));
+}
+
+template <int QT>
 void launch_corr_mfma(const umbir_geometry& G, const float* r, const float* hq, float* fine, long tstride,
                       int gbin, hipStream_t s) {
+  if (corr_split(G)) return launch_corr_x3<QT>(G, r, hq, fine, tstride, gbin, s);
   if (G.corr_tiles == 1) return launch_corr_mfma_nt<QT, 1>(G, r, hq, fine, tstride, gbin, s);
   if (G.corr_tiles == 4) return launch_corr_mfma_nt<QT, 4>(G, r, hq, fine, tstride, gbin, s);
   return launch_corr_mfma_nt<QT, 2>(G, r, hq, fine, tstride, gbin, s);
@@ -1859,23 +2070,27 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat_list(const BatchProb
 
 // residual e = y - A x - g D of the iteration
 template <int Q>
-__global__ __launch_bounds__(256) void k_conv_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
+__global__ __launch_bounds__(64 * kConvWaves) void k_conv_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
                                                    const int4* __restrict__ items, int n_items) {
   const BinSkip none{nullptr, 0, 0};
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 w = items[it];
     if (!active[w.x]) continue;
     const BatchProb& p = probs[w.x];
-    // the problem's own tile count (uniform over the block)
-    if (p.conv_tiles == 1)
-      conv_mfma_body<Q, 1>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ),
-                           none);
-    else if (p.conv_tiles == 4)
-      conv_mfma_body<Q, 4>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ),
-                           none);
-    else
-      conv_mfma_body<Q, 2>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y, -1.0f, p.g, p.dbasis, p.e, long(p.MQ),
-                           none);
+    // the problem's own tile count and products (uniform over the block)
+    auto body = [&](auto ntc, auto x3) {
+      conv_mfma_body<Q, decltype(ntc)::value, decltype(x3)::value>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y,
+                                                                   -1.0f, p.g, p.dbasis, p.e, long(p.MQ), none);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    if (p.conv_tiles == 1) {
+      if (p.conv_split) body(std::integral_constant<int, 1>(), T()); else body(std::integral_constant<int, 1>(), F());
+    } else if (p.conv_tiles == 4) {
+      if (p.conv_split) body(std::integral_constant<int, 4>(), T()); else body(std::integral_constant<int, 4>(), F());
+    } else {
+      if (p.conv_split) body(std::integral_constant<int, 2>(), T()); else body(std::integral_constant<int, 2>(), F());
+    }
     __syncthreads();
   }
 }
@@ -1888,7 +2103,8 @@ __global__ __launch_bounds__(256) void k_corr_list(const BatchProb* __restrict__
     const int4 w = items[it];
     if (!active[w.x]) continue;
     const BatchProb& p = probs[w.x];
-    corr_mfma_body<QT, 2>(w.y, w.z, p.e, p.h, p.M, p.Lh, p.corr_per, p.fine, long(p.MQ), none);
+    if (p.corr_split) corr_x3_body<QT>(w.y, w.z, p.e, p.h, p.M, p.Lh, p.corr_per, p.fine, long(p.MQ), none);
+    else corr_mfma_body<QT, 2>(w.y, w.z, p.e, p.h, p.M, p.Lh, p.corr_per, p.fine, long(p.MQ), none);
     __syncthreads();
   }
 }
@@ -1958,6 +2174,8 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
   // convolution: as launch_conv_mfma (the problem's tile count and order,
   // so its sums run in the order of its own launch)
   bp.conv_tiles = G.conv_tiles;
+  bp.conv_split = conv_split(G);
+  bp.corr_split = corr_split(G);
   lds[kStConv] = std::max(lds[kStConv], conv_mfma_lds(G));
   const int mts = (G.M + 32 * G.conv_tiles - 1) / (32 * G.conv_tiles);
   if (G.conv_grid == 2) {
@@ -1973,7 +2191,10 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
     constexpr int rows = 4 * 2 * 32;
     const int nrb = (G.M + rows - 1) / rows;
     bp.corr_per = std::max(1, int((long(PK) * nrb) / std::max(1, G.corr_blocks)));
-    lds[kStCorr] = std::max(lds[kStCorr], size_t(corr_lds_words(G.Q, rows, corr_half(G.Lh))) * sizeof(float));
+    static_assert(rows == kCorrX3Rows, "the split correlation's row block");
+    lds[kStCorr] = std::max(lds[kStCorr], size_t(bp.corr_split ? corr_x3_lds_words(G.Q, corr_half(G.Lh))
+                                                         : corr_lds_words(G.Q, rows, corr_half(G.Lh))) *
+                                              sizeof(float));
     for (int rg = 0; rg < (nrb + bp.corr_per - 1) / bp.corr_per; ++rg)
       for (int t = 0; t < PK; ++t) items[kStCorr].push_back(make_int4(pi, t, rg, 0));
   }
@@ -2002,8 +2223,12 @@ int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* acti
       UMBIR_LAUNCH("splat", k_splat_list, grid, dim3(64 * kSplatWaves), L.lds, s, probs, active, L.items, L.n_items);
       break;
     case kStConv:
-      if (Q == 32) UMBIR_LAUNCH("conv", k_conv_list<32>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
-      else UMBIR_LAUNCH("conv", k_conv_list<64>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      if (Q == 32)
+        UMBIR_LAUNCH("conv", k_conv_list<32>, grid, dim3(64 * kConvWaves), L.lds, s, probs, active, L.items,
+                     L.n_items);
+      else
+        UMBIR_LAUNCH("conv", k_conv_list<64>, grid, dim3(64 * kConvWaves), L.lds, s, probs, active, L.items,
+                     L.n_items);
       break;
     case kStCorr:
       if (Q == 32) UMBIR_LAUNCH("corr", k_corr_list<1>, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
@@ -2451,6 +2676,7 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     chosen->corr_tile_rows = 32 * G->corr_tiles;
     chosen->corr_blocks = G->corr_blocks;
     chosen->operator_form = G->form;
+    chosen->products = G->split ? 2 : 1;
   }
   return UMBIR_OK;
 }

@@ -33,8 +33,8 @@ def f32(a, dev):
 def test_tuning_changes_no_result(dev, name, card):
     """Any splat split, convolution tile order, correlation tile shape and
     workgroup count gives bitwise the same forward and adjoint; gather
-    batches and the convolution's output tiles per workgroup change only the
-    order of sums."""
+    batches, the convolution's output tiles per workgroup and the form of the
+    matrix-core products change only the order of sums."""
     geom = umbir.build_geometry(card)
     g = card.grid
     x = f32(random_vector((g.nz, g.nx), seed=3), dev)
@@ -43,9 +43,21 @@ def test_tuning_changes_no_result(dev, name, card):
     t0 = geom.tuning()
     assert t0["splat_blocks"] > 0 and t0["gather_batch_kb"] > 0
     assert t0["conv_grid"] == 1 and t0["corr_tile_rows"] == 128 and t0["corr_blocks"] == 1024
-    # 64-sample tiles when at least 512 workgroups remain, else 32
-    tiles = (geom.n_scans * geom.n_rx + 31) // 32 * ((card.acq.n_samples + 63) // 64)
-    assert t0["conv_tile_rows"] == (64 if tiles >= 512 else 32)
+    # bf16-piece products by default: 128-sample tiles when at least 256
+    # workgroups remain, else 64 likewise, else 64 when 512 remain, else 32
+    assert t0["products"] == 2
+    tt, m = (geom.n_scans * geom.n_rx + 31) // 32, card.acq.n_samples
+    rows = (128 if tt * ((m + 127) // 128) >= 256 else 64 if tt * ((m + 63) // 64) >= 256
+            else 64 if tt * ((m + 63) // 64) >= 512 else 32)
+    assert t0["conv_tile_rows"] == rows
+    # FP32 products: the same operator to rounding
+    geom.set_tuning(products=1)
+    assert geom.tuning()["products"] == 1
+    y1, a1 = umbir.forward(geom, x), umbir.adjoint(geom, r)
+    for u, v in ((y1, y0), (a1, a0)):
+        assert float(torch.linalg.norm((u - v).double()) / torch.linalg.norm(v.double())) <= 1e-6
+    geom.set_tuning(products=2)
+    assert torch.equal(umbir.forward(geom, x), y0)
     for cg, rows, nb in [(2, 32, 1), (1, 64, 100000), (2, 128, 7)]:
         geom.set_tuning(conv_grid=cg, corr_tile_rows=rows, corr_blocks=nb)
         assert torch.equal(umbir.forward(geom, x), y0)
@@ -70,9 +82,12 @@ def test_tuning_changes_no_result(dev, name, card):
         geom.set_tuning(corr_tile_rows=48)
     with pytest.raises(umbir.UmbirError):
         geom.set_tuning(conv_tile_rows=96)
+    with pytest.raises(umbir.UmbirError):
+        geom.set_tuning(products=3)
     chosen = geom.autotune()
     assert chosen == geom.tuning() and chosen["splat_blocks"] > 0 and chosen["gather_batch_kb"] > 0
-    if chosen["operator_form"] == 1 and chosen["conv_tile_rows"] == t0["conv_tile_rows"]:
+    if (chosen["operator_form"] == 1 and chosen["conv_tile_rows"] == t0["conv_tile_rows"]
+            and chosen["products"] == t0["products"]):
         assert torch.equal(umbir.forward(geom, x), y0)
     else:  # the direct form, or other convolution tiles, sum in another order
         yd = umbir.forward(geom, x)
