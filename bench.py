@@ -172,9 +172,14 @@ def copy_rate():
 
 
 PEAK_MFMA = {4: 157.3e12, 2: 2.5e15}  # dense matrix peak by element bytes: FP32, FP16/BF16
+PIECE_PRODUCTS = 6  # bf16 piece products per FP32 product (umbir_tuning.products = 2)
 
 
-def roofline(name, prof, steps, card, n_off, trace_groups, gather_batch_kb=4096, elem=4):
+def roofline(name, prof, steps, card, n_off, trace_groups, gather_batch_kb=4096, elem=4, products=1):
+    """One kernel's achieved rate against its bound.  With products = 2 the
+    FP32 convolution and correlation run on the bf16 matrix cores, six piece
+    products per FP32 product: the record then counts those bf16 flops
+    against the bf16 peak, and gives the FP32 figures beside them."""
     if name not in prof:
         return None
     launches, ms = prof[name]
@@ -182,13 +187,21 @@ def roofline(name, prof, steps, card, n_off, trace_groups, gather_batch_kb=4096,
     amount, bound = kernel_work(name, card, n_off, trace_groups, gather_batch_kb, elem)
     if bound is None:
         return None
-    achieved = amount / avg_s
-    peak = PEAK_HBM if bound == "hbm" else (PEAK_MFMA[elem] if bound == "mfma" else PEAK_FP32)
+    pieces = bound == "mfma" and elem == 4 and products == 2
+    executed = amount * PIECE_PRODUCTS if pieces else amount
+    achieved = executed / avg_s
+    peak = PEAK_HBM if bound == "hbm" else (PEAK_MFMA[2 if pieces else elem] if bound == "mfma" else PEAK_FP32)
     unit, div = ("GB/s", 1e9) if bound == "hbm" else ("TFLOP/s", 1e12)
-    return {"bound": bound, "achieved": achieved / div, "peak": peak / div, "unit": unit,
-            "frac": achieved / peak, "kernel": name, "avg_launch_us": avg_s * 1e6,
-            "launches_per_step": launches / steps, "work_per_launch": amount,
-            "work_unit": "byte" if bound == "hbm" else "flop"}
+    rec = {"bound": bound, "achieved": achieved / div, "peak": peak / div, "unit": unit,
+           "frac": achieved / peak, "kernel": name, "avg_launch_us": avg_s * 1e6,
+           "launches_per_step": launches / steps, "work_per_launch": executed,
+           "work_unit": "byte" if bound == "hbm" else "flop"}
+    if pieces:
+        rec["work_unit"] = "bf16 flop (%d piece products per FP32 product)" % PIECE_PRODUCTS
+        rec["fp32_flop_per_launch"] = amount
+        rec["fp32_equivalent_TFLOPs"] = amount / avg_s / 1e12
+        rec["fp32_equivalent_frac_of_fp32_peak"] = amount / avg_s / PEAK_MFMA[4]
+    return rec
 
 
 def host_cpu():
@@ -278,8 +291,9 @@ def precision_section(umbir, torch, dev, with_parity):
         umbir.profile_enable(False)
         prof = umbir.profile_collect()
         elem = 4 if st == umbir.STORAGE_F32 else 2
-        kb = gm.tuning()["gather_batch_kb"]
-        kern = {k: roofline(k, prof, 3, card, gm.n_off, gm.trace_groups, kb, elem)
+        tn = gm.tuning()
+        kb = tn["gather_batch_kb"]
+        kern = {k: roofline(k, prof, 3, card, gm.n_off, gm.trace_groups, kb, elem, tn["products"])
                 for k in ("splat", "conv", "corr", "gather")}
         dom = max(kern, key=lambda k: kern[k]["avg_launch_us"] * kern[k]["launches_per_step"] if kern[k] else -1)
         res = {"A_evals_per_s": triples / t_a, "AT_evals_per_s": triples / t_at,
@@ -465,8 +479,9 @@ def main():
     # ---- rooflines: the dominant kernel from the timed steps; every sweep
     # kernel from the profiled untimed step
     tg, kb = gm.trace_groups, tuning["gather_batch_kb"]
-    kernels = {k: roofline(k, prof_all, 1, card, gm.n_off, tg, kb) for k in ("splat", "conv", "corr", "gather")}
-    roof = roofline(dname, prof, args.steps, card, gm.n_off, tg, kb)
+    pr = tuning["products"]
+    kernels = {k: roofline(k, prof_all, 1, card, gm.n_off, tg, kb, products=pr) for k in ("splat", "conv", "corr", "gather")}
+    roof = roofline(dname, prof, args.steps, card, gm.n_off, tg, kb, products=pr)
     if roof is not None:  # launches per step from the fully profiled step; the timed ones are a sample
         roof["launches_per_step"] = prof_all[dname][0]
         roof["timed_launches"] = prof[dname][0]

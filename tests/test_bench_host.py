@@ -77,6 +77,14 @@ def test_roofline_record(bench):
     assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
     assert r["launches_per_step"] == 10
     assert bench.roofline("gather", prof, 2, card, 654, 8) is None
+    # bf16 piece products: six bf16 products per FP32 product, against the bf16 peak
+    r2 = bench.roofline("conv", prof, 2, card, 654, 8, products=2)
+    assert r2["peak"] == 2500.0 and r2["work_per_launch"] == 6 * 16106127360.0
+    assert r2["achieved"] == pytest.approx(6 * r["achieved"])
+    assert r2["fp32_equivalent_TFLOPs"] == pytest.approx(r["achieved"])
+    assert r2["fp32_equivalent_frac_of_fp32_peak"] == pytest.approx(r["frac"])
+    # storage in 16 bits keeps its own products
+    assert bench.roofline("conv", prof, 2, card, 654, 8, elem=2, products=2)["work_per_launch"] == 16106127360.0
 
 
 def _counter_csv(path, rows):
