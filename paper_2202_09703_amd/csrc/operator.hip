@@ -1187,6 +1187,7 @@ __device__ __forceinline__ void corr_mfma_body(int bx, int by, const float* __re
 // split and transposed ([piece][t][k], H + 4 words per t: 8 lanes' 16-byte
 // reads on distinct banks).  Writes stay coalesced along t.
 constexpr int kCorrX3Rows = 256;
+constexpr int kCorrX3SegItems = 4;  // segment items (8 positions of one shifted copy) per thread, 256 threads
 
 __host__ __device__ inline int corr_x3_tap_words(int H) { return H + 4; }
 __host__ __device__ inline int corr_x3_seg_words(int H) { return (2 * H + kCorrX3Rows) / 2 + 4; }
@@ -1201,7 +1202,9 @@ inline bool conv_split(const umbir_geometry& G) {
   return G.split && size_t(G.Lh + 1) * (3 * G.Q / 2 + 4) * sizeof(float) <= kMaxWorkgroupLds;
 }
 inline bool corr_split(const umbir_geometry& G) {
-  return G.split && size_t(corr_x3_lds_words(G.Q, corr_half(G.Lh))) * sizeof(float) <= kMaxWorkgroupLds;
+  const int H = corr_half(G.Lh);
+  return G.split && size_t(corr_x3_lds_words(G.Q, H)) * sizeof(float) <= kMaxWorkgroupLds &&
+         2 * H + kCorrX3Rows <= 256 * kCorrX3SegItems;
 }
 
 template <int QT>
@@ -1219,40 +1222,76 @@ __device__ __forceinline__ void corr_x3_body(int bx, int by, const float* __rest
   const int ij = bx;
   const float* r = rt + size_t(ij) * M;
   float* c = fine + size_t(ij) * tstride;
-  // taps: pairs (k, k + 1) of column t, zero from Lh on and in the padding
-  for (int i = threadIdx.x; i < Q * TW; i += blockDim.x) {
-    const int kp = i / Q, t = i - kp * Q;  // consecutive threads: consecutive t of one tap row
-    const int k = 2 * kp;
-    const float h0 = k < Lh && kp < H ? hq[size_t(k) * Q + t] : 0.0f;
-    const float h1 = k + 1 < Lh && kp < H ? hq[size_t(k + 1) * Q + t] : 0.0f;
-    unsigned p1, p2, p3;
-    split_pair_bf16x3(h0, h1, p1, p2, p3);
-    taps3[(0 * Q + t) * TW + kp] = p1;
-    taps3[(1 * Q + t) * TW + kp] = p2;
-    taps3[(2 * Q + t) * TW + kp] = p3;
+  // taps: pairs (k, k + 1) of column t, zero from Lh on and in the padding;
+  // consecutive threads take consecutive t of one tap row, U pairs per thread
+  // in flight
+  {
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < Q * TW; i0 += U * blockDim.x) {
+      float h[U][2];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * blockDim.x;
+        const int kp = i / Q, t = i - kp * Q, k = 2 * kp;
+        h[u][0] = i < Q * TW && k < Lh && kp < H ? hq[size_t(k) * Q + t] : 0.0f;
+        h[u][1] = i < Q * TW && k + 1 < Lh && kp < H ? hq[size_t(k + 1) * Q + t] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * blockDim.x;
+        if (i < Q * TW) {
+          const int kp = i / Q, t = i - kp * Q;
+          unsigned p1, p2, p3;
+          split_pair_bf16x3(h[u][0], h[u][1], p1, p2, p3);
+          taps3[(0 * Q + t) * TW + kp] = p1;
+          taps3[(1 * Q + t) * TW + kp] = p2;
+          taps3[(2 * Q + t) * TW + kp] = p3;
+        }
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 31, lk = lane >> 5;
   const int rb0 = by * rb_per_block;
   const int rb_end = min(rb0 + rb_per_block, (M + ROWS - 1) / ROWS);
-  for (int rb = rb0; rb < rb_end; ++rb) {
+  // copy rho of a row block's segment holds r[n_blk + 1 + rho + x] at
+  // position x < SX, split: item i = (rho, 8 positions), SX items, at most
+  // kCorrX3SegItems per thread (corr_split), loaded into registers one row
+  // block ahead
+  float sv[kCorrX3SegItems][8];
+  auto seg_load = [&](int rb) {
     const int n_blk = rb * ROWS;
-    if (!bin_reaches(bs, ij, long(n_blk) * Q, long(min(n_blk + ROWS, M)) * Q)) continue;  // uniform
-    __syncthreads();  // the previous row block's segment copies are read
-    // copy rho holds r[n_blk + 1 + rho + x] at position x < SX, split; a
-    // thread writes 8 positions of one copy
-    for (int i = threadIdx.x; i < 8 * (SX / 8); i += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kCorrX3SegItems; ++u) {
+      const int i = threadIdx.x + u * blockDim.x;
       const int rho = i / (SX / 8), x8 = i - rho * (SX / 8);
       const int m0 = n_blk + 1 + rho + 8 * x8;
-      float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = m0 + e < M ? r[m0 + e] : 0.0f;
-      const Pieces8 pc = split8_bf16x3(make_float4(v[0], v[1], v[2], v[3]), make_float4(v[4], v[5], v[6], v[7]));
+      for (int e = 0; e < 8; ++e) sv[u][e] = i < SX && m0 + e < M ? r[m0 + e] : 0.0f;
+    }
+  };
+  if (rb0 < rb_end) seg_load(rb0);
+  for (int rb = rb0; rb < rb_end; ++rb) {
+    const int n_blk = rb * ROWS;
+    if (!bin_reaches(bs, ij, long(n_blk) * Q, long(min(n_blk + ROWS, M)) * Q)) {  // uniform
+      if (rb + 1 < rb_end) seg_load(rb + 1);
+      continue;
+    }
+    __syncthreads();  // the previous row block's segment copies are read
 #pragma unroll
-      for (int tau = 0; tau < 3; ++tau)
-        reinterpret_cast<uint4*>(seg3 + (rho * 3 + tau) * SW)[x8] = pc.p[tau];
+    for (int u = 0; u < kCorrX3SegItems; ++u) {
+      const int i = threadIdx.x + u * blockDim.x;
+      if (i < SX) {
+        const int rho = i / (SX / 8), x8 = i - rho * (SX / 8);
+        const Pieces8 pc = split8_bf16x3(make_float4(sv[u][0], sv[u][1], sv[u][2], sv[u][3]),
+                                         make_float4(sv[u][4], sv[u][5], sv[u][6], sv[u][7]));
+#pragma unroll
+        for (int tau = 0; tau < 3; ++tau)
+          reinterpret_cast<uint4*>(seg3 + (rho * 3 + tau) * SW)[x8] = pc.p[tau];
+      }
     }
     __syncthreads();
+    if (rb + 1 < rb_end) seg_load(rb + 1);
     floatx16 acc[2][QT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
