@@ -359,9 +359,11 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   workgroups, else 32.  Changes only the order of the
  *                   sums.
  *  corr_tile_rows   rows (output samples) of one wave's tile in the
- *                   matrix-core correlation: 32, 64 or 128 (default; a
- *                   workgroup of four waves covers four tiles).  Bitwise
- *                   identical results.
+ *                   matrix-core correlation with FP32 products: 32, 64 or
+ *                   128 (default; a workgroup of four waves covers four
+ *                   tiles).  Bitwise identical results.  (With bf16-piece
+ *                   products a workgroup's row block is 256 rows, two
+ *                   8-strided tiles per wave, whatever this field says.)
  *  corr_blocks      target workgroup count of the correlation: each workgroup
  *                   walks ceil(traces x row blocks / corr_blocks) row blocks of
  *                   one trace with the taps staged once.  Bitwise identical.

@@ -2676,11 +2676,14 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     G->conv_grid = best_grid;
     G->conv_tiles = best_tiles;
   }
-  // the matrix-core correlation's tile rows per wave and workgroup count
+  // the matrix-core correlation's tile rows per wave (FP32 products only:
+  // the bf16-piece form has one tile shape) and workgroup count
   if (!st && G->storage == UMBIR_STORAGE_F32 && (G->Q == 32 || G->Q == 64)) {
     int best_t = G->corr_tiles, best_b = G->corr_blocks;
     best = 3.4e38f;
+    const bool one_shape = corr_split(*G);
     for (int t : {1, 2, 4}) {
+      if (one_shape && t != best_t) continue;
       for (int nb : {512, 1024, 2048}) {
         G->corr_tiles = t;
         G->corr_blocks = nb;
