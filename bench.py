@@ -67,11 +67,12 @@ def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
     def per_kernel(path):
         acc = {}
         for row in csv.DictReader(open(path)):
-            m = re.search(r"k_([a-z_]+)", row["Kernel_Name"])
+            m = re.search(r"k_([a-z_0-9]+)", row["Kernel_Name"])
             if not m:
                 continue
-            # the library's launch names: k_conv_mfma / k_conv_mfma16 launch as "conv"
-            name = re.sub(r"_mfma(16)?$", "", m.group(1))
+            # the library's launch names: k_conv_mfma / k_conv_mfma16 launch
+            # as "conv", k_corr_mfma / k_corr_x3 as "corr"
+            name = re.sub(r"_(mfma(16)?|x3)$", "", m.group(1))
             n, v = acc.setdefault(name, [0, 0.0]), float(row["Counter_Value"])
             n[0] += 1
             n[1] += v

@@ -267,6 +267,32 @@ def test_c2_adjoint_sampled(dev, c2geom):
     assert abs(lhs - rhs) <= TOL * np.linalg.norm(ax) * np.linalg.norm(r)
 
 
+def test_c2_products_forms_at_fp32_level(dev, c2geom):
+    """The matrix-core sweeps' two forms of an FP32 product (FP32 products;
+    three bf16 pieces per factor, six piece products) both stay within FP32
+    rounding of the FP64 oracle at full size: sampled traces and voxels to
+    2e-6 relative (about 34 unit roundoffs; either form measures 3e-7 to 7e-7
+    on these random inputs)."""
+    card, geom = c2geom
+    x = random_vector((card.grid.nz, card.grid.nx), seed=53)
+    r = random_vector(geom.trace_shape, seed=54)
+    traces = [(3, 7), (27, 12)]
+    vox = np.random.default_rng(8).choice(card.n_voxels, 24, replace=False)
+    fref, aref = oo.forward(card, x, traces=traces), oo.adjoint_voxels(card, r, vox)
+    t0 = geom.tuning()
+    try:
+        for prod in (1, 2):
+            geom.set_tuning(products=prod)
+            y = umbir.forward(geom, t32(x, dev)).cpu().numpy()
+            xa = umbir.adjoint(geom, t32(r, dev)).cpu().numpy().reshape(-1)
+            fe = max(rel(y[i, j], fref[i, j]) for i, j in traces)
+            ae = rel(xa[vox], aref)
+            print(f"c2 products {prod}: forward {fe:.2e}, adjoint {ae:.2e}")
+            assert fe <= 2e-6 and ae <= 2e-6
+    finally:
+        geom.set_tuning(products=t0["products"])
+
+
 def test_c2_leg_table(dev, c2geom):
     card, geom = c2geom
     dl = geom.table(umbir.TABLE_DELAY).astype(np.float64) / 2.0 ** 32
