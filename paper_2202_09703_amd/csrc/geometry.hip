@@ -178,23 +178,32 @@ __global__ void k_polyphase(int Q, int Lh, int g0, int G, const float* __restric
 
 // Template occupancy: for trace blockIdx.x and voxel v, the template of the
 // pair marks the blocks of its fine positions J and J + 1 (the splat puts its
-// weight on both).
+// weight on both).  A block ORs the marks of its voxels (every gridDim.y-th
+// run of blockDim.x) into its own copy of the trace's mask row in LDS (nb
+// words of dynamic LDS), then ORs the row's nonzero words into memory: one
+// global atomic per word and block instead of one per pair.
 __global__ void k_bin_mask(const Leg* __restrict__ legs, const double* __restrict__ gunit, int n_off,
                            const int* __restrict__ base, int P, int K, int nx, int N, int qs, long MQ, int last, int nb,
                            unsigned long long* __restrict__ mask) {
+  extern __shared__ unsigned long long row_mask[];  // [nb]
   const int t = blockIdx.x;
-  const int v = blockIdx.y * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  const int row = v / nx, col = v - row * nx;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) row_mask[i] = 0ull;
+  __syncthreads();
   const int half = n_off / 2;
-  const size_t ka = size_t(row) * n_off + leg_slot(abs(base[t / K] + 2 * col), half);
-  const size_t kb = size_t(row) * n_off + leg_slot(abs(base[P + t] + 2 * col), half);
-  const uint64_t D = uint64_t(legs[ka].delay + legs[kb].delay);
-  const long J = long(D >> (32 - qs));
-  const unsigned long long bit = 1ull << gamma_bin(gunit[ka] + gunit[kb], last);
-  if (J < MQ) atomicOr(&mask[size_t(t) * nb + (J >> kMaskShift)], bit);
-  if (J + 1 < MQ && ((J + 1) >> kMaskShift) != (J >> kMaskShift))
-    atomicOr(&mask[size_t(t) * nb + ((J + 1) >> kMaskShift)], bit);
+  const int bt = base[t / K], br = base[P + t];
+  for (int v = blockIdx.y * blockDim.x + threadIdx.x; v < N; v += gridDim.y * blockDim.x) {
+    const int row = v / nx, col = v - row * nx;
+    const size_t ka = size_t(row) * n_off + leg_slot(abs(bt + 2 * col), half);
+    const size_t kb = size_t(row) * n_off + leg_slot(abs(br + 2 * col), half);
+    const uint64_t D = uint64_t(legs[ka].delay + legs[kb].delay);
+    const long J = long(D >> (32 - qs));
+    const unsigned long long bit = 1ull << gamma_bin(gunit[ka] + gunit[kb], last);
+    if (J < MQ) atomicOr(&row_mask[J >> kMaskShift], bit);
+    if (J + 1 < MQ && ((J + 1) >> kMaskShift) != (J >> kMaskShift)) atomicOr(&row_mask[(J + 1) >> kMaskShift], bit);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    if (row_mask[i]) atomicOr(&mask[size_t(t) * nb + i], row_mask[i]);
 }
 
 // Column (i, j) of D: the tabulated pulse delayed by td[ij] samples, linearly
@@ -725,9 +734,11 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
       return bail(st);
     int qs = 0;
     while ((1 << qs) < G->Q) ++qs;
-    UMBIR_LAUNCH("bin_mask", k_bin_mask, dim3(unsigned(PK), unsigned((G->voxels() + 255) / 256)), dim3(256), 0, s,
-                 G->legs, G->gunit, G->n_off, G->base, G->P, G->K, G->nx, G->voxels(), qs, MQ, NG - 1,
-                 G->mask_blocks, G->gmask);
+    // eight blocks per trace, each with the trace's mask row in LDS
+    const unsigned vblocks = unsigned(std::min<long>(8, (long(G->voxels()) + 255) / 256));
+    UMBIR_LAUNCH("bin_mask", k_bin_mask, dim3(unsigned(PK), vblocks), dim3(256),
+                 size_t(G->mask_blocks) * sizeof(unsigned long long), s, G->legs, G->gunit, G->n_off, G->base, G->P,
+                 G->K, G->nx, G->voxels(), qs, MQ, NG - 1, G->mask_blocks, G->gmask);
   }
   if (gam_dev) (void)hipFreeAsync(gam_dev, s);
   if (nodes_dev) (void)hipFreeAsync(nodes_dev, s);
