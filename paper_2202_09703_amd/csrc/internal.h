@@ -325,6 +325,7 @@ struct BatchProb {
   int chunk_bins, tile_bins, wide;  // splat
   int conv_tiles;                   // output tiles per convolution block
   int conv_split, corr_split;       // products of the dense sweeps as bf16 pieces (umbir_geometry::split)
+  int conv_waves;                   // waves sharing a convolution block's window
   int corr_per;                     // row blocks per correlation block
   int groups, tpg, gbatch, vpb;     // gather: trace groups, traces per group and launch, voxels per block
   int nblk;                         // prior-update blocks

@@ -1387,7 +1387,11 @@ struct ChunkOrder {
 // The taps are split once, while staged: a tap row holds the three pieces of
 // its Q taps one after the other, 3 Q / 2 + 4 words (16-byte reads of 8 lanes
 // on distinct banks); a chunk of B is split once for all NTC tiles.
-constexpr int kConvWaves = 4;  // waves of a matrix-core convolution workgroup, sharing its window
+// nw waves (4 or 8) share a block's window; a block may have more waves than
+// that (a work-list stage runs every problem with the same block size): the
+// others help stage the taps and write the outputs.  Results do not depend on
+// the block size, only on nw (the order of the waves' partial sums).
+constexpr int kConvMaxWaves = 8;
 
 template <int Q>
 __host__ __device__ constexpr int conv_x3_row_words() { return 3 * Q / 2 + 4; }
@@ -1398,7 +1402,7 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
                                                    const float* __restrict__ dbasis, float* out, long tstride,
-                                                   BinSkip bs) {
+                                                   BinSkip bs, int nw) {
   constexpr int CK = 64;        // (n, t) positions per chunk
   constexpr int CN = CK / Q;    // rows n per chunk
   constexpr int TS = Q + 4;     // tap row stride
@@ -1476,7 +1480,7 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   const bool reach = __syncthreads_or(threadIdx.x < 32 && tr0 + int(threadIdx.x) < PK &&
                                       bin_reaches(bs, tr0 + threadIdx.x, long(m0 - Lh) * Q,
                                                   long(m0 + 31 + EXT) * Q));
-  const int rounds = reach ? (co.P + kConvWaves - 1) / kConvWaves : 0;
+  const int rounds = reach && wave < nw ? (co.P + nw - 1) / nw : 0;
   floatx16 acc[NTC];
 #pragma unroll
   for (int j = 0; j < NTC; ++j)
@@ -1487,13 +1491,13 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   // row clamped into [0, M); a row outside [0, M), or a step past the window,
   // takes the A row of zeros instead, so B needs no masking.
   const float* src = fine + size_t(min(tr0 + li, PK - 1)) * tstride + t0;
-  // the chunk of step ch = rd W + wave advances by W = kConvWaves per round, modulo P
+  // the chunk of step ch = rd nw + wave advances by nw per round, modulo P
   int jf = (wave + co.rot) % co.P, jm = jf;  // fetch and multiply positions
   int sf = wave, sm_ = wave;                  // their steps
   auto next_row = [&](int& j, int& step) {
     const int nc = step < co.P ? co.v_lo + j * CN : -(1 << 30);  // past the window: no row
-    step += kConvWaves;
-    j += kConvWaves;
+    step += nw;
+    j += nw;
     while (j >= co.P) j -= co.P;
     return nc;
   };
@@ -1554,49 +1558,54 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
   };
   // the epilogue's inputs for this thread's EPT NTC outputs, fetched now so
   // that they arrive while the window multiplies
-  constexpr int EPT = 1024 / (64 * kConvWaves);  // outputs per thread of one 32 x 32 tile
-  float pre_base[EPT * NTC], pre_db[EPT * NTC], pre_g[EPT * NTC];
+  // (outputs per thread of one 32 x 32 tile: 1024 / blockDim.x, at most 4)
+  const int ept = 1024 / int(blockDim.x);
+  float pre_base[4 * NTC], pre_db[4 * NTC], pre_g[4 * NTC];
 #pragma unroll
-  for (int q = 0; q < EPT * NTC; ++q) {
-    const int e = threadIdx.x + (q % EPT) * 64 * kConvWaves;
-    const int mm = min(m0 + 32 * (q / EPT) + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
+  for (int q = 0; q < 4 * NTC; ++q) {
+    const int e = threadIdx.x + (q & 3) * blockDim.x;
+    const int mm = min(m0 + 32 * (q >> 2) + (e & 31), M - 1), tr = min(tr0 + (e >> 5), PK - 1);
     const size_t idx = size_t(tr) * M + mm;
-    pre_base[q] = base ? base[idx] : 0.0f;
-    pre_db[q] = g ? dbasis[idx] : 0.0f;
-    pre_g[q] = g ? g[tr] : 0.0f;
+    const bool use = (q & 3) < ept;
+    pre_base[q] = base && use ? base[idx] : 0.0f;
+    pre_db[q] = g && use ? dbasis[idx] : 0.0f;
+    pre_g[q] = g && use ? g[tr] : 0.0f;
   }
   __syncthreads();  // taps staged
   // two register sets in turn: the next chunk is in flight while one multiplies
   float4 b0[8], b1[8];
-  fetch(b0);
-  for (int rd = 0; rd < rounds; rd += 2) {
-    fetch(b1);
-    multiply(b0);
+  if (wave < nw) {  // uniform over the wave
     fetch(b0);
-    multiply(b1);
+    for (int rd = 0; rd < rounds; rd += 2) {
+      fetch(b1);
+      multiply(b0);
+      fetch(b0);
+      multiply(b1);
+    }
   }
   __syncthreads();  // every wave is done with the taps: reuse them for the reduction
   // sum the waves' partial tiles of each output tile: red[j][wave][row][col]
   float* red = sm;
+  if (wave < nw) {
 #pragma unroll
-  for (int j = 0; j < NTC; ++j)
+    for (int j = 0; j < NTC; ++j)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
-      red[((j * kConvWaves + wave) * 32 + row) * 33 + li] = acc[j][i];
-    }
+      for (int i = 0; i < 16; ++i) {
+        const int row = 8 * (i >> 2) + 4 * lk + (i & 3);
+        red[((j * nw + wave) * 32 + row) * 33 + li] = acc[j][i];
+      }
+  }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < EPT * NTC; ++q) {
-    const int j = q / EPT;
-    const int e = threadIdx.x + (q % EPT) * 64 * kConvWaves;
+  for (int q = 0; q < 4 * NTC; ++q) {
+    const int j = q >> 2;
+    const int e = threadIdx.x + (q & 3) * blockDim.x;
     const int col = e >> 5, row = e & 31;  // consecutive threads: consecutive m of one trace
     const int mm = m0 + 32 * j + row, tr = tr0 + col;
-    if (mm < M && tr < PK) {
-      const float* rj = red + j * kConvWaves * 32 * 33;
+    if ((q & 3) < ept && mm < M && tr < PK) {
+      const float* rj = red + j * nw * 32 * 33;
       float v = rj[row * 33 + col];
-#pragma unroll
-      for (int w = 1; w < kConvWaves; ++w) v += rj[(w * 32 + row) * 33 + col];
+      for (int w = 1; w < nw; ++w) v += rj[(w * 32 + row) * 33 + col];
       float val = sign * v;
       if (base) val += pre_base[q];
       if (g) val -= pre_g[q] * pre_db[q];
@@ -1606,22 +1615,22 @@ __device__ __forceinline__ void conv_mfma_body(int bx, int by, const float* __re
 }
 
 template <int Q, int NTC, bool X3>
-__global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(const float* __restrict__ fine,
+__global__ __launch_bounds__(64 * kConvMaxWaves) void k_conv_mfma(const float* __restrict__ fine,
                                                    const float* __restrict__ hq, int M, int Lh,
                                                    int PK, const float* base, float sign,
                                                    const float* __restrict__ g,
                                                    const float* __restrict__ dbasis, float* out, long tstride,
-                                                   BinSkip bs) {
-  conv_mfma_body<Q, NTC, X3>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+                                                   BinSkip bs, int nw) {
+  conv_mfma_body<Q, NTC, X3>(blockIdx.x, blockIdx.y, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs, nw);
 }
 
 // The same with the grid's dimensions swapped (sample tiles fastest).
 template <int Q, int NTC, bool X3>
-__global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma_t(const float* __restrict__ fine, const float* __restrict__ hq,
+__global__ __launch_bounds__(64 * kConvMaxWaves) void k_conv_mfma_t(const float* __restrict__ fine, const float* __restrict__ hq,
                                                      int M, int Lh, int PK, const float* base, float sign,
                                                      const float* __restrict__ g, const float* __restrict__ dbasis,
-                                                     float* out, long tstride, BinSkip bs) {
-  conv_mfma_body<Q, NTC, X3>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs);
+                                                     float* out, long tstride, BinSkip bs, int nw) {
+  conv_mfma_body<Q, NTC, X3>(blockIdx.y, blockIdx.x, fine, hq, M, Lh, PK, base, sign, g, dbasis, out, tstride, bs, nw);
 }
 
 // C on the matrix cores with 16-bit storage (Q in {32, 64}): as k_conv_mfma,
@@ -1840,24 +1849,34 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
 
 // LDS of the matrix-core convolution: the padded taps, reused at the end for
 // the four waves' partial tiles of each of the NTC output tiles
+// Waves sharing a convolution block's window: eight with bf16-piece products
+// when the grid leaves fewer than two blocks per CU (the waves of a block
+// then hide each other's row loads; measured: 256x256, 97 against 111 us),
+// else four.
+int conv_waves(const umbir_geometry& G) {
+  const long tt = (G.traces() + 31) / 32, mt = (G.M + 32 * G.conv_tiles - 1) / (32 * G.conv_tiles);
+  return conv_split(G) && tt * mt < 512 ? 8 : 4;
+}
+
 size_t conv_mfma_lds(const umbir_geometry& G) {
   const size_t row = conv_split(G) ? size_t(3 * G.Q / 2 + 4) : size_t(G.Q + 4);  // words per tap row
-  return std::max<size_t>(size_t(G.Lh + 1) * row, size_t(G.conv_tiles) * kConvWaves * 32 * 33) * sizeof(float);
+  return std::max<size_t>(size_t(G.Lh + 1) * row, size_t(G.conv_tiles) * conv_waves(G) * 32 * 33) * sizeof(float);
 }
 
 template <int Q, int NTC, bool X3>
 void launch_conv_mfma_x(const umbir_geometry& G, const float* fine, const float* hq, const float* base,
                         float sign, const float* g, float* out, long tstride, int gbin, hipStream_t s) {
   const size_t lds = conv_mfma_lds(G);
+  const int nw = conv_waves(G);
   const unsigned tt = unsigned((G.traces() + 31) / 32), mt = unsigned((G.M + 32 * NTC - 1) / (32 * NTC));
   if (G.conv_grid == 2)
-    UMBIR_LAUNCH("conv", (k_conv_mfma_t<Q, NTC, X3>), dim3(mt, tt), dim3(64 * kConvWaves), lds, s, fine, hq, G.M, G.Lh,
+    UMBIR_LAUNCH("conv", (k_conv_mfma_t<Q, NTC, X3>), dim3(mt, tt), dim3(64 * nw), lds, s, fine, hq, G.M, G.Lh,
                  G.traces(),
-                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin), nw);
   else
-    UMBIR_LAUNCH("conv", (k_conv_mfma<Q, NTC, X3>), dim3(tt, mt), dim3(64 * kConvWaves), lds, s, fine, hq, G.M, G.Lh,
+    UMBIR_LAUNCH("conv", (k_conv_mfma<Q, NTC, X3>), dim3(tt, mt), dim3(64 * nw), lds, s, fine, hq, G.M, G.Lh,
                  G.traces(),
-                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin));
+                 base, sign, g, G.dbasis, out, tstride, bin_skip(G, gbin), nw);
 }
 
 template <int Q, int NTC>
@@ -2109,7 +2128,7 @@ __global__ __launch_bounds__(64 * kSplatWaves) void k_splat_list(const BatchProb
 
 // residual e = y - A x - g D of the iteration
 template <int Q>
-__global__ __launch_bounds__(64 * kConvWaves) void k_conv_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
+__global__ __launch_bounds__(64 * kConvMaxWaves) void k_conv_list(const BatchProb* __restrict__ probs, const int* __restrict__ active,
                                                    const int4* __restrict__ items, int n_items) {
   const BinSkip none{nullptr, 0, 0};
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -2119,7 +2138,8 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv_list(const BatchProb* 
     // the problem's own tile count and products (uniform over the block)
     auto body = [&](auto ntc, auto x3) {
       conv_mfma_body<Q, decltype(ntc)::value, decltype(x3)::value>(w.y, w.z, p.fine, p.h, p.M, p.Lh, p.P * p.K, p.y,
-                                                                   -1.0f, p.g, p.dbasis, p.e, long(p.MQ), none);
+                                                                   -1.0f, p.g, p.dbasis, p.e, long(p.MQ), none,
+                                                                   p.conv_waves);
     };
     using T = std::true_type;
     using F = std::false_type;
@@ -2214,6 +2234,7 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
   // so its sums run in the order of its own launch)
   bp.conv_tiles = G.conv_tiles;
   bp.conv_split = conv_split(G);
+  bp.conv_waves = conv_waves(G);
   bp.corr_split = corr_split(G);
   lds[kStConv] = std::max(lds[kStConv], conv_mfma_lds(G));
   const int mts = (G.M + 32 * G.conv_tiles - 1) / (32 * G.conv_tiles);
@@ -2263,10 +2284,10 @@ int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* acti
       break;
     case kStConv:
       if (Q == 32)
-        UMBIR_LAUNCH("conv", k_conv_list<32>, grid, dim3(64 * kConvWaves), L.lds, s, probs, active, L.items,
+        UMBIR_LAUNCH("conv", k_conv_list<32>, grid, dim3(64 * kConvMaxWaves), L.lds, s, probs, active, L.items,
                      L.n_items);
       else
-        UMBIR_LAUNCH("conv", k_conv_list<64>, grid, dim3(64 * kConvWaves), L.lds, s, probs, active, L.items,
+        UMBIR_LAUNCH("conv", k_conv_list<64>, grid, dim3(64 * kConvMaxWaves), L.lds, s, probs, active, L.items,
                      L.n_items);
       break;
     case kStCorr:
