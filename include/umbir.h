@@ -351,9 +351,10 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   workgroup): 1 trace tiles fastest, 2 sample tiles
  *                   fastest.  Bitwise identical results.
  *  conv_tile_rows   output samples per matrix-core convolution workgroup:
- *                   32, 64 or 128; the workgroup's four waves share each
- *                   fetched chunk of fine-grid rows among its 32-sample
- *                   tiles.  Default at build: with bf16-piece products, 128
+ *                   32, 64 or 128; the workgroup's waves (eight with
+ *                   bf16-piece products when the grid leaves fewer than two
+ *                   workgroups per CU, else four) share each fetched chunk of
+ *                   fine-grid rows among its 32-sample tiles.  Default at build: with bf16-piece products, 128
  *                   when that leaves at least 256 workgroups, else 64
  *                   likewise; otherwise 64 when that leaves at least 512
  *                   workgroups, else 32.  Changes only the order of the

@@ -1368,7 +1368,7 @@ struct ChunkOrder {
 //   Y[m][tr] = sum_{(n,t)} H[m-1-n][t] S_tr[n Q + t],
 // A = the banded Toeplitz tile built from the taps (zero where m - 1 - n is
 // outside the window), B = the fine-grid signals of 32 traces.  A block owns a
-// 32 (m) x 32 (trace) output tile; its four waves take the window's 64-wide
+// 32 (m) x 32 (trace) output tile; its nw waves take the window's 64-wide
 // chunks of (n, t) in turn (ChunkOrder) and their partial tiles are summed in
 // LDS at the end.  The contraction index of the 32x32x2 product is labelled
 // so that lane half lk holds chunk positions [32 lk, 32 lk + 32): a lane's A
@@ -1847,8 +1847,6 @@ void launch_corr_q(const umbir_geometry& G, const float* r, const float* hq, flo
                G.Lh, LhP, fine, tstride);
 }
 
-// LDS of the matrix-core convolution: the padded taps, reused at the end for
-// the four waves' partial tiles of each of the NTC output tiles
 // Waves sharing a convolution block's window: eight with bf16-piece products
 // when the grid leaves fewer than two blocks per CU (the waves of a block
 // then hide each other's row loads; measured: 256x256, 97 against 111 us),
@@ -1858,6 +1856,8 @@ int conv_waves(const umbir_geometry& G) {
   return conv_split(G) && tt * mt < 512 ? 8 : 4;
 }
 
+// LDS of the matrix-core convolution: the padded taps, reused at the end for
+// the nw waves' partial tiles of each of the NTC output tiles
 size_t conv_mfma_lds(const umbir_geometry& G) {
   const size_t row = conv_split(G) ? size_t(3 * G.Q / 2 + 4) : size_t(G.Q + 4);  // words per tap row
   return std::max<size_t>(size_t(G.Lh + 1) * row, size_t(G.conv_tiles) * conv_waves(G) * 32 * 33) * sizeof(float);
