@@ -384,7 +384,9 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   and the product taken as the six piece products whose
  *                   orders sum to at most 4 (v_mfma_f32_32x32x16_bf16, FP32
  *                   accumulation; the three left out are below 2^-23 of the
- *                   product).  Results agree to rounding.
+ *                   product).  Results agree to rounding.  Where the
+ *                   pieces' tables would not fit a workgroup's LDS (long
+ *                   templates) the library uses the FP32 products.
  * A field of 0 (or less) in umbir_set_tuning keeps the current value (EINVAL
  * for a conv_grid, conv_tile_rows, corr_tile_rows or products outside the
  * values above).  The tuning of

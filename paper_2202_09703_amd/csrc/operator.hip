@@ -1181,7 +1181,7 @@ __device__ __forceinline__ void corr_mfma_body(int bx, int by, const float* __re
 // column and 8 consecutive segment samples of its row as one 16-byte word.
 // The Hankel rows would put those 8 samples at every alignment, so a tile's
 // 32 rows are n_blk + 8 i + rho (i < 32) for one residue rho: lane i reads
-// segment words 8 (i + s) + ... of the copy of the segment shifted by rho.
+// segment positions 8 (i + s) + lk H + e of the copy shifted by rho.
 // A row block is 256 rows, the 8 residues, two per wave; the block stages
 // eight shifted copies of its segment, split into pieces, and the taps once,
 // split and transposed ([piece][t][k], H + 4 words per t: 8 lanes' 16-byte
