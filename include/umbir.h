@@ -367,7 +367,9 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   8-strided tiles per wave, whatever this field says.)
  *  corr_blocks      target workgroup count of the correlation: each workgroup
  *                   walks ceil(traces x row blocks / corr_blocks) row blocks of
- *                   one trace with the taps staged once.  Bitwise identical.
+ *                   one trace with the taps staged once (default 512 with
+ *                   bf16-piece products, 1024 with FP32 products).  Bitwise
+ *                   identical.
  *  operator_form    1: the factored form (default): A = splat then polyphase
  *                   convolution, A^T = polyphase correlation then gather;
  *                   2: the direct form of Eq. (13): every (trace, voxel) pair

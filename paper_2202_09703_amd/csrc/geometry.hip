@@ -599,6 +599,9 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     if (G->split && tt * ((G->M + 127) / 128) >= 256) G->conv_tiles = 4;
     else if (G->split && tt * ((G->M + 63) / 64) >= 256) G->conv_tiles = 2;
     else G->conv_tiles = tt * ((G->M + 63) / 64) >= 512 ? 2 : 1;
+    // correlation workgroups: the bf16-piece form's 72 KB of LDS leave two
+    // per CU, so 512 make one generation (each stages its taps once)
+    if (G->split) G->corr_blocks = 512;
   }
 
   const size_t legs = size_t(G->nz) * G->n_off;
