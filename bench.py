@@ -513,6 +513,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_note": ("FP32 data and accumulation; the convolution and correlation form each FP32 product "
+                       "from three bf16 pieces per factor on the bf16 matrix cores (six piece products, "
+                       "error below 2^-23 of the product)" if tuning.get("products") == 2 else
+                       "FP32 data, products and accumulation"),
         "data": "synthetic",
         "config": {"workload": "plain FP32 MBIR 256x256, 3 layers, 32 scans x 16 rx, 2048 samples "
                                "@ 20 MHz, 50 iterations", "grid": [256, 256], "scans": P, "receivers": K,
