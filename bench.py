@@ -71,8 +71,9 @@ def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
             if not m:
                 continue
             # the library's launch names: k_conv_mfma / k_conv_mfma16 launch
-            # as "conv", k_corr_mfma / k_corr_x3 as "corr"
-            name = re.sub(r"_(mfma(16)?|x3)$", "", m.group(1))
+            # as "conv", k_corr_mfma / k_corr_x3 as "corr", k_gather_lds as
+            # "gather"
+            name = re.sub(r"_(mfma(16)?|x3|lds)$", "", m.group(1))
             n, v = acc.setdefault(name, [0, 0.0]), float(row["Counter_Value"])
             n[0] += 1
             n[1] += v

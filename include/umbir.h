@@ -345,8 +345,12 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   least 1024 positions.  Results are bitwise identical for
  *                   every value (the splat sums in fixed point).
  *  gather_batch_kb  fine-grid KiB of each trace group per gather launch (at
- *                   least one trace per launch).  Changes only the order of
- *                   the adjoint's sums across launches.
+ *                   least one trace per launch).  Default at build: 4096,
+ *                   or where the FP32 gather stages each voxel tile's
+ *                   window of the fine grid in LDS, 16 traces for every
+ *                   tile one of its workgroups takes when that is more.
+ *                   Changes only the order of the adjoint's sums across
+ *                   launches.
  *  conv_grid        tile order of the matrix-core convolution (32 traces per
  *                   workgroup): 1 trace tiles fastest, 2 sample tiles
  *                   fastest.  Bitwise identical results.

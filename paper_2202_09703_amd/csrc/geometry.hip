@@ -208,6 +208,59 @@ __global__ void k_bin_mask(const Leg* __restrict__ legs, const double* __restric
 
 // Column (i, j) of D: the tabulated pulse delayed by td[ij] samples, linearly
 // interpolated on the fine grid; also its squared norm.
+// The windowed gather's table: for trace blockIdx.x and voxel tile
+// blockIdx.y (kGatherTileRows x kGatherTileCols, row-major over the grid), the
+// fine positions J = floor(delay Q) of the tile's voxels that fall inside the
+// record, as {first, count}: first a multiple of 4 at or below the smallest J,
+// first + count a multiple of 4 above the largest J + 1 (each voxel reads J
+// and J + 1); {0, 0} when no voxel's J lies in the record.  J is the gather's
+// own: the two legs' Q32.32 delays summed and shifted.
+__global__ __launch_bounds__(512) void k_gather_windows(const Leg* __restrict__ legs, const int* __restrict__ base,
+                                                        int P, int K, int nx, int nz, int n_off, int qs, int MQ,
+                                                        int2* __restrict__ gwin) {
+  const int t = blockIdx.x, tile = blockIdx.y;
+  const int tiles_x = (nx + kGatherTileCols - 1) / kGatherTileCols;
+  const int tz = tile / tiles_x, tx = tile - tz * tiles_x;
+  const int half = n_off / 2, sh = 32 - qs;
+  const int bt = base[t / K], br = base[P + t];
+  const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
+  unsigned lo = 0xffffffffu, hi = 0u;
+  for (int row = tz * kGatherTileRows + wave; row < min(nz, (tz + 1) * kGatherTileRows); row += 8) {
+    const int col = tx * kGatherTileCols + lane;
+    if (col < nx) {
+      const int64_t da = legs[size_t(row) * n_off + leg_slot(abs(bt + 2 * col), half)].delay;
+      const int64_t db = legs[size_t(row) * n_off + leg_slot(abs(br + 2 * col), half)].delay;
+      const unsigned J = unsigned(min(uint64_t(da + db) >> sh, uint64_t(MQ)));
+      if (J < unsigned(MQ)) {
+        lo = min(lo, J);
+        hi = max(hi, J);
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, unsigned(__shfl_xor(int(lo), o)));
+    hi = max(hi, unsigned(__shfl_xor(int(hi), o)));
+  }
+  __shared__ unsigned slo[8], shi[8];
+  if (lane == 0) {
+    slo[wave] = lo;
+    shi[wave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) {
+      lo = min(lo, slo[w]);
+      hi = max(hi, shi[w]);
+    }
+    int2 win = make_int2(0, 0);
+    if (lo != 0xffffffffu) {
+      const unsigned first = lo & ~3u;
+      win = make_int2(int(first), int((hi + 2u - first + 3u) & ~3u));
+    }
+    gwin[size_t(tile) * (P * K) + t] = win;
+  }
+}
+
 __global__ void k_dbasis(const float* __restrict__ bank, const double* __restrict__ td, int M,
                          int Q, int Lh, float* __restrict__ d, float* __restrict__ dnorm) {
   const int ij = blockIdx.x;
@@ -512,7 +565,9 @@ size_t umbir_estimate_bytes(const umbir_problem* pb) {
     return 0;
   }
   return table_bytes(pb->grid.nz, dv.n_off, pb->array.n_scans, pb->array.n_rx,
-                     pb->acq.n_samples, pb->acq.oversample, dv.Lh, dv.n_gamma);
+                     pb->acq.n_samples, pb->acq.oversample, dv.Lh, dv.n_gamma) +
+         gather_window_bytes(pb->grid.nx, pb->grid.nz, long(pb->array.n_scans) * pb->array.n_rx,
+                             long(pb->acq.n_samples) * pb->acq.oversample, pb->acq.storage);
 }
 
 void umbir_geometry_free(umbir_geometry* G) {
@@ -521,7 +576,7 @@ void umbir_geometry_free(umbir_geometry* G) {
   (void)hipGetDevice(&cur);
   if (G->device >= 0) (void)hipSetDevice(G->device);
   void* ptrs[] = {G->legs, G->legs_t, G->tau, G->base, G->bank, G->h, G->habs, G->dbasis, G->dnorm, G->gmask,
-                  G->gunit, G->gunit_t};
+                  G->gunit, G->gunit_t, G->gwin};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (cur >= 0) (void)hipSetDevice(cur);
@@ -680,6 +735,21 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   UMBIR_LAUNCH("legs", k_legs, dim3((n_legs + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off, G->z0,
                G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, G->nzp, G->legs_t, log2_int(G->Q), gam_dev);
   if ((st = check_hip(hipGetLastError(), "k_legs"))) return bail(st);
+  // the windowed gather's table (where it applies)
+  if (const size_t wb = gather_window_bytes(G->nx, G->nz, long(PK), G->fine_per_trace(), G->storage)) {
+    if ((st = alloc((void**)&G->gwin, wb))) return bail(st);
+    UMBIR_LAUNCH("gather_windows", k_gather_windows, dim3(unsigned(PK), unsigned(gather_tiles(G->nx, G->nz))),
+                 dim3(512), 0, s, G->legs, G->base, G->P, G->K, G->nx, G->nz, G->n_off, log2_int(G->Q),
+                 int(G->fine_per_trace()), G->gwin);
+    if ((st = check_hip(hipGetLastError(), "k_gather_windows"))) return bail(st);
+    // gather batches of 16 traces per voxel tile a block takes (measured at
+    // 256 x 256: one tile per block, 4 MiB; at 512 x 512: two, 16 MiB against
+    // 5.02 ms per operator pair at 4 MiB and 5.00 at 32 MiB)
+    int tpb;
+    (void)gather_lds_blocks(G->nx, G->nz, G->trace_groups, &tpb);
+    const long kb = 16L * tpb * long(G->fine_per_trace()) * 4 / 1024;
+    G->gather_batch_kb = int(std::min(long(1) << 20, std::max(long(G->gather_batch_kb), kb)));
+  }
   if (dv.n_gamma > 1) {
     // Gamma_max: at a fixed depth a leg's attenuation grows with its lateral
     // offset, so every row's largest is at the largest offset in use

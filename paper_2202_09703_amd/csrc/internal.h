@@ -44,6 +44,34 @@ constexpr int kMaskShift = 10;
 
 __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >> 1) + (o & 1) * half; }
 
+// The windowed gather (FP32 fine grid): voxel tiles of kGatherTileRows x
+// kGatherTileCols, and for every (tile, trace) the window of fine positions
+// its voxels read, staged in LDS when it holds at most kGatherWinFloats.
+constexpr int kGatherTileRows = 32, kGatherTileCols = 64, kGatherWinFloats = 16384;
+inline long gather_tiles(int nx, int nz) {
+  return long((nx + kGatherTileCols - 1) / kGatherTileCols) * ((nz + kGatherTileRows - 1) / kGatherTileRows);
+}
+// Its blocks per trace group: one generation of at most 512 blocks (two per
+// CU, 64 KiB of window each) over the tiles; *tiles_per_block receives each
+// block's share.
+inline int gather_lds_blocks(int nx, int nz, int groups, int* tiles_per_block) {
+  const long tiles = gather_tiles(nx, nz);
+  long nb = tiles < 512 / groups ? tiles : 512 / groups;
+  if (nb < 1) nb = 1;
+  *tiles_per_block = int((tiles + nb - 1) / nb);
+  return int((tiles + *tiles_per_block - 1) / *tiles_per_block);
+}
+// Bytes of the window table ([tiles][traces] of {first position, count}),
+// 0 where the windowed gather does not apply: 16-bit storage, a record of
+// fine positions not a multiple of 4, more tiles than a grid dimension holds
+// or a table over 64 MiB.
+inline size_t gather_window_bytes(int nx, int nz, long traces, long fine_per_trace, int storage) {
+  const long tiles = gather_tiles(nx, nz);
+  const size_t bytes = size_t(tiles) * size_t(traces) * 8;
+  if (storage != UMBIR_STORAGE_F32 || fine_per_trace % 4 != 0 || tiles > 65535 || bytes > (size_t(64) << 20)) return 0;
+  return bytes;
+}
+
 // LDS of one splat workgroup: all 160 KiB of a gfx950 CU, one workgroup of
 // 16 waves per CU (measured against 64 KiB and 80 KiB, two workgroups per CU:
 // the larger tiles need fewer passes over the row pointers and fewer partly
@@ -209,6 +237,7 @@ struct umbir_geometry {
   float* habs = nullptr;     // [n_gamma][Lh][Q] |h|
   float* dbasis = nullptr;   // [P*K][M] direct-arrival columns of D
   float* dnorm = nullptr;    // [P*K] squared norms of the columns of D
+  int2* gwin = nullptr;      // [gather tiles][P*K] windowed gather's {first fine position, count} (or absent)
   size_t bytes = 0;
 
   int traces() const { return P * K; }

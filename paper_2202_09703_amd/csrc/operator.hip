@@ -887,6 +887,183 @@ __global__ __launch_bounds__(256) void k_gather(
   gather_body<ABSW, VPT, ST, ATT, ONE, MULTI>(blockIdx.x, blockIdx.y, fine, nx, nz, n_off, legs, gunit, tau, base, P, K, qs, MQ, tpg, t_off, t_cnt, vox_per_block, gbin, glast, accum, partial);
 }
 
+// S^T with the fine-grid window in LDS (FP32 grid, one template; same pairs,
+// same arithmetic and the same per-voxel order over the traces as k_gather,
+// so the same results).  A trace's delays change by several 128-byte lines of
+// the fine grid from one voxel to the next, so in k_gather nearly every lane's
+// sample is a line of its own, fetched from L2 (0.65 fetches per (voxel,
+// trace) pair at 256 x 256).  Here a block takes voxel tiles of 32 x 64 and
+// for each trace first copies the tile's window of fine positions (from the
+// table k_gather_windows builds: 0.2 lines per pair on average at 256 x 256)
+// into LDS with coalesced 16-byte loads, then every voxel reads its two taps
+// from LDS.  A trace whose window exceeds kGatherWinFloats (about one in ten
+// there: tiles near the array, where the delays spread most) reads its taps
+// from global memory as k_gather does.  The window of trace t + 1 and the
+// legs of trace t + 2 are in flight while trace t accumulates.  Wave w's load
+// u covers row 8 u + w of the tile, one lane per column (neighbouring leg
+// records).  ONE and the arguments as for k_gather.
+template <bool ABSW, bool ONE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_gather_lds(
+    const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ, int tpg, int t_off,
+    int t_cnt, const int2* __restrict__ gwin, int tiles_per_block, float* __restrict__ partial) {
+  extern __shared__ uint4 wlds[];  // the window: kGatherWinFloats floats
+  constexpr int VPT = kGatherTileRows / 8;
+  constexpr int kStage = kGatherWinFloats / 4 / 512;  // 16-byte loads per thread per window
+  const int bx = blockIdx.x;
+  const int N = nx * nz;
+  const int PK = P * K;
+  const int g_end = min((bx + 1) * tpg, PK);
+  const int t0 = bx * tpg + t_off;
+  const int t1 = min(t0 + t_cnt, g_end);
+  if (t0 >= t1 && t_off > 0) return;  // uniform over the block: nothing to add
+  const int tiles_x = (nx + kGatherTileCols - 1) / kGatherTileCols;
+  const int n_tiles = tiles_x * ((nz + kGatherTileRows - 1) / kGatherTileRows);
+  const int tile_end = min(n_tiles, int(blockIdx.y + 1) * tiles_per_block);
+  const int sh = 32 - qs;
+  const int half = n_off / 2;
+  const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
+  const __amdgpu_buffer_rsrc_t leg_rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, nz * n_off * int(sizeof(Leg)), kBufferWord3);
+  const float* wf = reinterpret_cast<const float*>(wlds);
+  struct Legs { int64_t d[VPT]; float p[VPT]; };
+  struct Taps { unsigned J[VPT]; float phi[VPT], w[VPT]; };
+  for (int tile = int(blockIdx.y) * tiles_per_block; tile < tile_end; ++tile) {
+    const int tz = tile / tiles_x;
+    const int tx = tile - tz * tiles_x;
+    int col2[VPT], rowoff[VPT], vox[VPT];
+    bool ok[VPT];
+    float acc[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int row = tz * kGatherTileRows + 8 * u + wave;
+      const int col = tx * kGatherTileCols + lane;
+      ok[u] = row < nz && col < nx;
+      const int r = min(row, nz - 1), c = min(col, nx - 1);  // outside the grid: a voxel of the grid, unused
+      vox[u] = r * nx + c;
+      col2[u] = 2 * c;
+      rowoff[u] = r * n_off;
+      acc[u] = 0.0f;
+    }
+    const int2* wt = gwin + size_t(tile) * PK;
+    auto load_leg = [&](int bt, int64_t (&d)[VPT], float (&p)[VPT]) {
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int o = (rowoff[u] + leg_slot(abs(bt + col2[u]), half)) * int(sizeof(Leg));
+        const auto a = __builtin_amdgcn_raw_buffer_load_b64(leg_rs, o, 0, 0);
+        p[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(leg_rs, o + 8, 0, 0));
+        d[u] = int64_t((uint64_t(a[1]) << 32) | a[0]);
+      }
+    };
+    Legs TX;
+    if constexpr (ONE) load_leg(base[min(t0, t1 - 1) / K], TX.d, TX.p);
+    Legs TXt;  // !ONE: the transmit legs of the trace being loaded
+    auto load_legs = [&](Legs& L, Legs& LT, int t) {
+      t = min(t, t1 - 1);
+      if constexpr (!ONE) load_leg(base[t / K], LT.d, LT.p);
+      load_leg(base[P + t], L.d, L.p);
+    };
+    auto taps_of = [&](const Legs& L, const Legs& LT, Taps& T) {
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int64_t da = ONE ? TX.d[u] : LT.d[u];
+        const uint64_t D = uint64_t(da + L.d[u]);
+        T.J[u] = unsigned(min(D >> sh, uint64_t(MQ)));  // past the record: MQ
+        T.phi[u] = float(uint32_t(D) << qs) * kTwoM32;
+        float w = (ONE ? TX.p[u] : LT.p[u]) * L.p[u];
+        if (ABSW) w = fabsf(w);
+        T.w[u] = w;
+      }
+    };
+    // the window of trace t into registers: 16-byte loads of the trace's fine
+    // data, positions past the record (and loads past the window) read zero
+    auto stage_load = [&](int2 W, int t, uint4 (&R)[kStage]) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(fine + size_t(t) * MQ), 0, MQ * int(sizeof(float)), kBufferWord3);
+      const int nq = W.y >> 2;
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int c = int(threadIdx.x) + 512 * k;
+        const int off = c < nq ? (W.x + 4 * c) * int(sizeof(float)) : 0x7ffffff0;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        R[k] = make_uint4(v[0], v[1], v[2], v[3]);
+      }
+    };
+    auto stage_store = [&](int2 W, const uint4 (&R)[kStage]) {
+      const int nq = W.y >> 2;
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int c = int(threadIdx.x) + 512 * k;
+        if (c < nq) wlds[c] = R[k];
+      }
+    };
+    // trace t's taps from the window in LDS (fits) or from global memory
+    auto add = [&](const Taps& T, int2 W, bool fits, int t) {
+      if (fits) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+          // a voxel whose J lies in the record has J, J + 1 inside the window;
+          // others (past the record, or outside the grid) read a clamped
+          // position and add nothing
+          const int i = int(T.J[u]) - W.x;
+          const bool in = T.J[u] < unsigned(MQ) && i >= 0 && i <= W.y - 2;
+          const int ic = in ? i : 0;
+          const float c0 = in ? wf[ic] : 0.0f;
+          const float c1 = in ? wf[ic + 1] : 0.0f;
+          acc[u] = fmaf(T.w[u], fmaf(T.phi[u], c1 - c0, c0), acc[u]);
+        }
+      } else {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(fine + size_t(t) * MQ), 0, MQ * int(sizeof(float)), kBufferWord3);
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+          const float c0 = fine_at<UMBIR_STORAGE_F32>(rs, T.J[u]);
+          const float c1 = fine_at<UMBIR_STORAGE_F32>(rs, T.J[u] + 1u);
+          acc[u] = fmaf(T.w[u], fmaf(T.phi[u], c1 - c0, c0), acc[u]);
+        }
+      }
+    };
+    if (t0 < t1) {
+      Legs La, Lb, LTa, LTb;
+      Taps T;
+      uint4 R[kStage];
+      int2 W = wt[t0];
+      load_legs(La, LTa, t0);
+      load_legs(Lb, LTb, t0 + 1);
+      if (W.y <= kGatherWinFloats) stage_load(W, t0, R);
+      taps_of(La, LTa, T);
+      // one step: trace t accumulates from (T, W); L holds the legs of t + 1
+      // (in flight), Lf is free for those of t + 2
+      auto step = [&](int t, Legs& L, Legs& LT, Legs& Lf, Legs& LTf) {
+        const bool fits = W.y <= kGatherWinFloats;
+        __syncthreads();  // every wave has read the previous window
+        if (fits) stage_store(W, R);
+        __syncthreads();
+        const int2 Wn = wt[min(t + 1, t1 - 1)];
+        if (t + 1 < t1 && Wn.y <= kGatherWinFloats) stage_load(Wn, t + 1, R);
+        load_legs(Lf, LTf, t + 2);
+        add(T, W, fits, t);
+        taps_of(L, LT, T);
+        W = Wn;
+      };
+      for (int t = t0; t < t1; t += 2) {
+        step(t, Lb, LTb, La, LTa);
+        if (t + 1 < t1) step(t + 1, La, LTa, Lb, LTb);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int v = vox[u];
+      if (ok[u]) {
+        float tr = tau[v / nx];
+        if (ABSW) tr = fabsf(tr);
+        float* pv = partial + size_t(bx) * N + v;
+        *pv = t_off == 0 ? acc[u] * tr : fmaf(acc[u], tr, *pv);
+      }
+    }
+  }
+}
+
 __global__ void k_reduce_groups(const float* __restrict__ partial, int groups, int N, float scale,
                                 float* __restrict__ out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2087,6 +2264,27 @@ bool gather_one_scan(const umbir_geometry& G, int tpg, int t_off, int batch) {
   return true;
 }
 
+// The windowed gather (FP32 grid, one template, window table built).
+void launch_gather_lds(const umbir_geometry& G, bool abs_op, int qs, int MQ, int tpg, int t_off, int batch,
+                       const void* fine, float* partial, hipStream_t s) {
+  int tpb;
+  const dim3 grid(G.trace_groups, gather_lds_blocks(G.nx, G.nz, G.trace_groups, &tpb));
+  const size_t lds = size_t(kGatherWinFloats) * sizeof(float);
+  const float* f = static_cast<const float*>(fine);
+  const bool one = gather_one_scan(G, tpg, t_off, batch);
+#define UMBIR_GATHER_LDS(A, O)                                                                                 \
+  UMBIR_LAUNCH("gather", (k_gather_lds<A, O>), grid, dim3(512), lds, s, f, G.nx, G.nz, G.n_off, G.legs, G.tau, \
+               G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, G.gwin, tpb, partial)
+  if (abs_op) {
+    if (one) UMBIR_GATHER_LDS(true, true);
+    else UMBIR_GATHER_LDS(true, false);
+  } else {
+    if (one) UMBIR_GATHER_LDS(false, true);
+    else UMBIR_GATHER_LDS(false, false);
+  }
+#undef UMBIR_GATHER_LDS
+}
+
 // MULTI: one pass over the resident grids of all templates (see k_gather)
 template <int ST, bool ATT, bool MULTI = false>
 void launch_gather(const umbir_geometry& G, bool abs_op, dim3 grid, int qs, int MQ, int tpg, int t_off,
@@ -2506,6 +2704,8 @@ int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, voi
           if (G.n_gamma > 1)
             launch_gather<UMBIR_STORAGE_F32, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gb, accum,
                                                    fine, partial, s);
+          else if (G.gwin)
+            launch_gather_lds(G, abs_op, qs, MQ, tpg, t_off, batch, fine, partial, s);
           else
             launch_gather<UMBIR_STORAGE_F32, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
                                                     partial, s);

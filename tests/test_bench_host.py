@@ -104,6 +104,7 @@ def test_traffic_file(bench, tmp_path, monkeypatch):
                                       ("void umbir::(anonymous namespace)::k_conv_mfma<32>(float const*)", 300.0),
                                       ("void umbir::(anonymous namespace)::k_splat<false>(int)", 10.0),
                                       ("void umbir::(anonymous namespace)::k_corr_x3<1>(float const*)", 6.0),
+                                      ("void umbir::(anonymous namespace)::k_gather_lds<false, true>(float const*)", 9.0),
                                       ("void at::native::other_kernel", 7.0)])
     _counter_csv(tmp_path / "w.csv", [("void umbir::(anonymous namespace)::k_conv_mfma<32>(float const*)", 4.0),
                                       ("void umbir::(anonymous namespace)::k_splat<false>(int)", 128.0)])
@@ -115,7 +116,8 @@ def test_traffic_file(bench, tmp_path, monkeypatch):
     assert doc["source_sha256"] == bench.source_digest()
     assert doc["calibration"]["fetch_scale"] == pytest.approx(2.0)
     assert doc["calibration"]["write_scale"] == pytest.approx(1.0)
-    assert sorted(doc["kernels"]) == ["conv", "corr", "splat"]  # launch names; other kernels ignored
+    assert sorted(doc["kernels"]) == ["conv", "corr", "gather", "splat"]  # launch names; other kernels ignored
+    assert doc["kernels"]["gather"]["fetch_bytes"] == pytest.approx(9.0 * 2 * 1024)
     assert doc["kernels"]["corr"]["fetch_bytes"] == pytest.approx(6.0 * 2 * 1024)
     assert doc["kernels"]["conv"]["fetch_bytes"] == pytest.approx(200.0 * 2 * 1024)  # mean of 100 and 300 KiB
     assert doc["kernels"]["conv"]["write_bytes"] == pytest.approx(4.0 * 1024)
