@@ -346,9 +346,9 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   every value (the splat sums in fixed point).
  *  gather_batch_kb  fine-grid KiB of each trace group per gather launch (at
  *                   least one trace per launch).  Default at build: 4096,
- *                   or where the FP32 gather stages each voxel tile's
- *                   window of the fine grid in LDS, 16 traces for every
- *                   tile one of its workgroups takes when that is more.
+ *                   or with the windowed gather (gather_form 2 by default)
+ *                   16 traces for every tile one of its workgroups takes
+ *                   when that is more.
  *                   Changes only the order of the adjoint's sums across
  *                   launches.
  *  conv_grid        tile order of the matrix-core convolution (32 traces per
@@ -393,9 +393,20 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   product).  Results agree to rounding.  Where the
  *                   pieces' tables would not fit a workgroup's LDS (long
  *                   templates) the library uses the FP32 products.
+ *  gather_form      the factored adjoint's gather (FP32 storage, one
+ *                   template): 1 row-wise, each voxel's two taps loaded from
+ *                   the fine grid in global memory; 2 windowed, each 32 x 64
+ *                   voxel tile's window of a trace's fine grid staged in LDS
+ *                   first (windows over 64 KiB loaded as in 1).  2 needs the
+ *                   geometry's window table, built where 16-bit storage or a
+ *                   record of fine positions not a multiple of 4 does not
+ *                   rule it out (ENOTSUP from umbir_set_tuning otherwise).
+ *                   Default at build: 2 when its workgroups fill at least
+ *                   three quarters of one generation (two per CU), else 1.
+ *                   Bitwise identical results.
  * A field of 0 (or less) in umbir_set_tuning keeps the current value (EINVAL
- * for a conv_grid, conv_tile_rows, corr_tile_rows or products outside the
- * values above).  The tuning of
+ * for a conv_grid, conv_tile_rows, corr_tile_rows, products or gather_form
+ * outside the values above).  The tuning of
  * a geometry must not change while another call uses it.
  * umbir_autotune times candidates of each field on `stream` (an A + A^T pair
  * for the form, the forward for the splat and the convolution, the adjoint
@@ -412,6 +423,7 @@ typedef struct {
     int corr_blocks;
     int operator_form;
     int products;
+    int gather_form;
 } umbir_tuning;
 int umbir_get_tuning(const umbir_geometry* geom, umbir_tuning* out);
 int umbir_set_tuning(umbir_geometry* geom, const umbir_tuning* tuning);

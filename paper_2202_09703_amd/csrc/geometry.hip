@@ -742,13 +742,16 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
                  dim3(512), 0, s, G->legs, G->base, G->P, G->K, G->nx, G->nz, G->n_off, log2_int(G->Q),
                  int(G->fine_per_trace()), G->gwin);
     if ((st = check_hip(hipGetLastError(), "k_gather_windows"))) return bail(st);
-    // gather batches of 16 traces per voxel tile a block takes (measured at
-    // 256 x 256: one tile per block, 4 MiB; at 512 x 512: two, 16 MiB against
-    // 5.02 ms per operator pair at 4 MiB and 5.00 at 32 MiB)
-    int tpb;
-    (void)gather_lds_blocks(G->nx, G->nz, G->trace_groups, &tpb);
-    const long kb = 16L * tpb * long(G->fine_per_trace()) * 4 / 1024;
-    G->gather_batch_kb = int(std::min(long(1) << 20, std::max(long(G->gather_batch_kb), kb)));
+    if (gather_windowed_default(G->nx, G->nz, G->trace_groups)) {
+      G->gather_form = 2;
+      // gather batches of 16 traces per voxel tile a block takes (measured at
+      // 256 x 256: one tile per block, 4 MiB; at 512 x 512: two, 16 MiB
+      // against 5.02 ms per operator pair at 4 MiB and 5.00 at 32 MiB)
+      int tpb;
+      (void)gather_lds_blocks(G->nx, G->nz, G->trace_groups, &tpb);
+      const long kb = 16L * tpb * long(G->fine_per_trace()) * 4 / 1024;
+      G->gather_batch_kb = int(std::min(long(1) << 20, std::max(long(G->gather_batch_kb), kb)));
+    }
   }
   if (dv.n_gamma > 1) {
     // Gamma_max: at a fixed depth a leg's attenuation grows with its lateral
@@ -839,6 +842,7 @@ int umbir_get_tuning(const umbir_geometry* G, umbir_tuning* out) {
   out->corr_blocks = G->corr_blocks;
   out->operator_form = G->form;
   out->products = G->split ? 2 : 1;
+  out->gather_form = G->gather_form;
   return UMBIR_OK;
 }
 
@@ -847,6 +851,9 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (t->conv_grid > 2) return fail(UMBIR_EINVAL, "conv_grid must be 1 or 2");
   if (t->operator_form > 2) return fail(UMBIR_EINVAL, "operator_form must be 1 or 2");
   if (t->products > 2) return fail(UMBIR_EINVAL, "products must be 1 or 2");
+  if (t->gather_form > 2) return fail(UMBIR_EINVAL, "gather_form must be 1 or 2");
+  if (t->gather_form == 2 && !G->gwin)
+    return fail(UMBIR_ENOTSUP, "the windowed gather needs FP32 storage and M * Q a multiple of 4");
   if (t->operator_form == 2 && !direct_eligible(*G))
     return fail(UMBIR_ENOTSUP, "the direct form needs FP32 storage, one template and 8 M + 4 (Q L_h + 2) <= 65536");
   if (t->corr_tile_rows > 0 && t->corr_tile_rows != 32 && t->corr_tile_rows != 64 && t->corr_tile_rows != 128)
@@ -861,6 +868,7 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (t->corr_blocks > 0) G->corr_blocks = t->corr_blocks;
   if (t->operator_form > 0) G->form = t->operator_form;
   if (t->products > 0) G->split = t->products == 2;
+  if (t->gather_form > 0) G->gather_form = t->gather_form;
   return UMBIR_OK;
 }
 

@@ -71,6 +71,16 @@ inline size_t gather_window_bytes(int nx, int nz, long traces, long fine_per_tra
   if (storage != UMBIR_STORAGE_F32 || fine_per_trace % 4 != 0 || tiles > 65535 || bytes > (size_t(64) << 20)) return 0;
   return bytes;
 }
+// The default gather form where the table exists: windowed when its blocks
+// (groups x tiles, two tiles a block beyond 512) fill at least three quarters
+// of one generation; with fewer, one block per CU leaves the window loads'
+// latency exposed and the row-wise gather is faster (measured at 352 x 352
+// and 384 x 384 with 8 groups, 264 and 288 blocks: 0.43 against 0.33 and
+// 0.42 against 0.37 ms per adjoint).
+inline bool gather_windowed_default(int nx, int nz, int groups) {
+  int tpb;
+  return 4L * groups * gather_lds_blocks(nx, nz, groups, &tpb) >= 3L * 512;
+}
 
 // LDS of one splat workgroup: all 160 KiB of a gfx950 CU, one workgroup of
 // 16 waves per CU (measured against 64 KiB and 80 KiB, two workgroups per CU:
@@ -238,6 +248,7 @@ struct umbir_geometry {
   float* dbasis = nullptr;   // [P*K][M] direct-arrival columns of D
   float* dnorm = nullptr;    // [P*K] squared norms of the columns of D
   int2* gwin = nullptr;      // [gather tiles][P*K] windowed gather's {first fine position, count} (or absent)
+  int gather_form = 1;       // 1 row-wise gather, 2 windowed (needs gwin)
   size_t bytes = 0;
 
   int traces() const { return P * K; }

@@ -2704,7 +2704,7 @@ int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, voi
           if (G.n_gamma > 1)
             launch_gather<UMBIR_STORAGE_F32, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gb, accum,
                                                    fine, partial, s);
-          else if (G.gwin)
+          else if (G.gather_form == 2 && G.gwin)
             launch_gather_lds(G, abs_op, qs, MQ, tpg, t_off, batch, fine, partial, s);
           else
             launch_gather<UMBIR_STORAGE_F32, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
@@ -2917,17 +2917,21 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     G->corr_tiles = best_t;
     G->corr_blocks = best_b;
   }
-  // the gather: fine-grid KiB per trace group and launch
-  int best_kb = G->gather_batch_kb;
+  // the gather: its form (row-wise, or windowed where the table exists) and
+  // fine-grid KiB per trace group and launch
+  int best_kb = G->gather_batch_kb, best_gf = G->gather_form;
   best = 3.4e38f;
-  for (int kb : {2048, 4096, 8192, 16384, 32768}) {
-    if (st) break;
-    G->gather_batch_kb = kb;
-    float ms = 0.0f;
-    if ((st = time_ms(adjoint, &ms))) break;
-    if (ms < best) { best = ms; best_kb = kb; }
-  }
+  for (int gf = 1; gf <= (G->gwin ? 2 : 1); ++gf)
+    for (int kb : {2048, 4096, 8192, 16384, 32768}) {
+      if (st) break;
+      G->gather_form = gf;
+      G->gather_batch_kb = kb;
+      float ms = 0.0f;
+      if ((st = time_ms(adjoint, &ms))) break;
+      if (ms < best) { best = ms; best_kb = kb; best_gf = gf; }
+    }
   G->gather_batch_kb = best_kb;
+  G->gather_form = best_gf;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) return st;
@@ -2940,6 +2944,7 @@ int umbir_autotune(umbir_geometry* G, void* stream, umbir_tuning* chosen) {
     chosen->corr_blocks = G->corr_blocks;
     chosen->operator_form = G->form;
     chosen->products = G->split ? 2 : 1;
+    chosen->gather_form = G->gather_form;
   }
   return UMBIR_OK;
 }

@@ -82,7 +82,7 @@ class _Dims(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("splat_blocks", C.c_int), ("gather_batch_kb", C.c_int), ("conv_grid", C.c_int),
                 ("conv_tile_rows", C.c_int), ("corr_tile_rows", C.c_int), ("corr_blocks", C.c_int),
-                ("operator_form", C.c_int), ("products", C.c_int)]
+                ("operator_form", C.c_int), ("products", C.c_int), ("gather_form", C.c_int)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -233,11 +233,12 @@ class Geometry:
 
     def set_tuning(self, splat_blocks: int = 0, gather_batch_kb: int = 0, conv_grid: int = 0,
                    conv_tile_rows: int = 0, corr_tile_rows: int = 0, corr_blocks: int = 0, operator_form: int = 0,
-                   products: int = 0):
-        """Launch and tile shapes, the operator's form and the matrix-core
-        products (umbir_tuning); 0 keeps a field's value."""
+                   products: int = 0, gather_form: int = 0):
+        """Launch and tile shapes, the operator's form, the matrix-core
+        products and the gather's form (umbir_tuning); 0 keeps a field's
+        value."""
         t = _Tuning(int(splat_blocks), int(gather_batch_kb), int(conv_grid), int(conv_tile_rows), int(corr_tile_rows),
-                    int(corr_blocks), int(operator_form), int(products))
+                    int(corr_blocks), int(operator_form), int(products), int(gather_form))
         _check(_lib.umbir_set_tuning(self.handle, C.byref(t)), "umbir_set_tuning")
 
     def autotune(self, stream=None, cache: Optional[dict] = None) -> dict:

@@ -1,0 +1,121 @@
+"""The adjoint's two gather forms (umbir_tuning.gather_form): the row-wise
+gather and the windowed one (each voxel tile's window of a trace's fine grid
+staged in LDS) sum the same pairs in the same order, so their images agree
+bit for bit; the windowed one is also held against the FP64 oracle (relative
+L2 <= 1e-5) on cards that cover ragged tiles, records shorter than the
+echoes (empty and partial windows), windows too large for LDS (the direct
+fallback) and one sample per fine position (Q = 1); a larger grid whose trace
+groups straddle scan positions (each launch's transmit legs loaded per trace)
+is checked bitwise against the row-wise form."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import card_c1, tiny_card, random_vector
+from oracle import geometry as og, operator as oo
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+umbir = pytest.importorskip("paper_2202_09703_amd.umbir")
+
+TOL = 1e-5
+WIN_FLOATS = 16384  # window capacity of the windowed gather (floats)
+
+CARDS = [
+    ("tiny", tiny_card(n_layers=3)),
+    ("ragged-q16", tiny_card(n_layers=3, nx=17, nz=13, n_scans=3, n_rx=4, n_samples=300, oversample=16)),
+    ("short-record", tiny_card(n_layers=3, nz=70, n_samples=40)),
+    ("q1", tiny_card(n_layers=3, oversample=1, beta=0)),
+    ("wide-q64", tiny_card(n_layers=3, nx=70, nz=40, n_scans=2, n_rx=3, n_samples=600, oversample=64)),
+    ("c1", card_c1()),
+]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def host_windows(card):
+    """Window sizes (floats) of every (32 x 64 tile, trace) from the oracle's
+    FP64 delays, as the geometry's table defines them."""
+    g, acq = card.grid, card.acq
+    mq = acq.n_samples * acq.oversample
+    out = []
+    for i in range(len(card.array.tx_x)):
+        for j in range(len(card.array.rx_offset)):
+            d, _, _ = og.trace_geometry(card, i, j)
+            J = np.minimum(np.floor(d * acq.oversample), mq).astype(np.int64).reshape(g.nz, g.nx)
+            for z0 in range(0, g.nz, 32):
+                for x0 in range(0, g.nx, 64):
+                    b = J[z0:z0 + 32, x0:x0 + 64]
+                    b = b[b < mq]
+                    out.append(0 if b.size == 0 else ((b.max() + 2 - (b.min() & ~3) + 3) & ~3))
+    return np.array(out)
+
+
+def test_cards_cover_the_window_cases():
+    """Host-side check that the cards reach every path of the windowed gather:
+    empty windows, windows that fit and windows over the LDS capacity."""
+    w = {name: host_windows(card) for name, card in CARDS}
+    assert (w["short-record"] == 0).any() and (w["short-record"] > 0).any()
+    assert (w["wide-q64"] > 1.25 * WIN_FLOATS).any() and ((w["wide-q64"] > 0) & (w["wide-q64"] < WIN_FLOATS)).any()
+
+
+@pytest.mark.parametrize("name,card", CARDS)
+def test_windowed_gather_matches_rowwise_and_oracle(dev, name, card):
+    geom = umbir.build_geometry(card)
+    r = torch.tensor(random_vector(geom.trace_shape, seed=41), dtype=torch.float32, device=dev)
+    geom.set_tuning(gather_form=1)
+    assert geom.tuning()["gather_form"] == 1
+    x_row = umbir.adjoint(geom, r).clone()
+    d_row = umbir.sqs_denominator(geom, 1.0).clone()
+    geom.set_tuning(gather_form=2)
+    assert geom.tuning()["gather_form"] == 2
+    x_win = umbir.adjoint(geom, r)
+    d_win = umbir.sqs_denominator(geom, 1.0)
+    assert torch.equal(x_row, x_win)
+    assert torch.equal(d_row, d_win)
+    e = rel(x_win.cpu().numpy(), oo.adjoint(card, r.cpu().numpy().astype(np.float64)))
+    print(f"{name}: windowed adjoint rel L2 {e:.2e}")
+    assert e <= TOL
+    geom.free()
+
+
+def test_windowed_gather_across_scan_positions(dev):
+    """20 traces (5 scans x 4 receivers) over 8 trace groups of 3: groups
+    straddle scan positions, so the gather loads the transmit legs per trace;
+    16 MiB batches put every group's traces in one launch."""
+    card = tiny_card(n_layers=3, nx=448, nz=400, n_scans=5, n_rx=4, n_samples=256, oversample=8)
+    geom = umbir.build_geometry(card)
+    r = torch.tensor(random_vector(geom.trace_shape, seed=43), dtype=torch.float32, device=dev)
+    out = []
+    for form in (1, 2):
+        geom.set_tuning(gather_form=form, gather_batch_kb=16384)
+        out.append((umbir.adjoint(geom, r).clone(), umbir.sqs_denominator(geom, 1.0).clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert float(out[1][0].abs().sum()) > 0.0
+    geom.free()
+
+
+def test_windowed_gather_needs_its_table(dev):
+    """16-bit storage has no window table: gather_form 2 is refused and the
+    tuning keeps the row-wise form."""
+    card = tiny_card(n_layers=3, oversample=32)
+    card = dataclasses.replace(card, acq=dataclasses.replace(card.acq, storage=1))
+    geom = umbir.build_geometry(card)
+    with pytest.raises(umbir.UmbirError):
+        geom.set_tuning(gather_form=2)
+    assert geom.tuning()["gather_form"] == 1
+    with pytest.raises(umbir.UmbirError):
+        geom.set_tuning(gather_form=3)
+    geom.free()
