@@ -368,6 +368,8 @@ struct BatchProb {
   int conv_waves;                   // waves sharing a convolution block's window
   int corr_per;                     // row blocks per correlation block
   int groups, tpg, gbatch, vpb;     // gather: trace groups, traces per group and launch, voxels per block
+                                    // (row-wise) or voxel tiles per block (windowed)
+  const int2* gwin;                 // windowed gather: the geometry's window table
   int nblk;                         // prior-update blocks
   // session state
   const float* y;
@@ -389,7 +391,7 @@ struct BatchProb {
 };
 
 // Stages of one iteration, in launch order.
-enum BatchStage { kStPrescale = 0, kStSplat, kStConv, kStGstep, kStCorr, kStGather, kStPrior, kStCost, kStages };
+enum BatchStage { kStPrescale = 0, kStSplat, kStConv, kStGstep, kStCorr, kStGather, kStGatherW, kStPrior, kStCost, kStages };
 
 // A stage's launch: its items, grid (blocks walk the items with a stride of
 // the grid) and dynamic LDS bytes.

@@ -903,14 +903,13 @@ __global__ __launch_bounds__(256) void k_gather(
 // u covers row 8 u + w of the tile, one lane per column (neighbouring leg
 // records).  ONE and the arguments as for k_gather.
 template <bool ABSW, bool ONE>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_gather_lds(
+__device__ __forceinline__ void gather_lds_body(int bx, int by,
     const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ, int tpg, int t_off,
     int t_cnt, const int2* __restrict__ gwin, int tiles_per_block, float* __restrict__ partial) {
   extern __shared__ uint4 wlds[];  // the window: kGatherWinFloats floats
   constexpr int VPT = kGatherTileRows / 8;
   constexpr int kStage = kGatherWinFloats / 4 / 512;  // 16-byte loads per thread per window
-  const int bx = blockIdx.x;
   const int N = nx * nz;
   const int PK = P * K;
   const int g_end = min((bx + 1) * tpg, PK);
@@ -919,7 +918,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (t0 >= t1 && t_off > 0) return;  // uniform over the block: nothing to add
   const int tiles_x = (nx + kGatherTileCols - 1) / kGatherTileCols;
   const int n_tiles = tiles_x * ((nz + kGatherTileRows - 1) / kGatherTileRows);
-  const int tile_end = min(n_tiles, int(blockIdx.y + 1) * tiles_per_block);
+  const int tile_end = min(n_tiles, (by + 1) * tiles_per_block);
   const int sh = 32 - qs;
   const int half = n_off / 2;
   const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
@@ -928,7 +927,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const float* wf = reinterpret_cast<const float*>(wlds);
   struct Legs { int64_t d[VPT]; float p[VPT]; };
   struct Taps { unsigned J[VPT]; float phi[VPT], w[VPT]; };
-  for (int tile = int(blockIdx.y) * tiles_per_block; tile < tile_end; ++tile) {
+  for (int tile = by * tiles_per_block; tile < tile_end; ++tile) {
     const int tz = tile / tiles_x;
     const int tx = tile - tz * tiles_x;
     int col2[VPT], rowoff[VPT], vox[VPT];
@@ -1062,6 +1061,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
     }
   }
+}
+
+template <bool ABSW, bool ONE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_gather_lds(
+    const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ, int tpg, int t_off,
+    int t_cnt, const int2* __restrict__ gwin, int tiles_per_block, float* __restrict__ partial) {
+  gather_lds_body<ABSW, ONE>(blockIdx.x, blockIdx.y, fine, nx, nz, n_off, legs, tau, base, P, K, qs, MQ, tpg, t_off,
+                             t_cnt, gwin, tiles_per_block, partial);
 }
 
 __global__ void k_reduce_groups(const float* __restrict__ partial, int groups, int N, float scale,
@@ -2394,6 +2402,27 @@ __global__ __launch_bounds__(256) void k_gather_list(const BatchProb* __restrict
   }
 }
 
+// The windowed gather over a work list: items (problem, trace group, block of
+// voxel tiles, batch b) as the problem's own k_gather_lds launch b.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_gather_lds_list(
+    const BatchProb* __restrict__ probs, const int* __restrict__ active, const int4* __restrict__ items, int n_items) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (!active[w.x]) continue;
+    const BatchProb& p = probs[w.x];
+    const int PK = p.P * p.K;
+    const int t_off = w.w * p.gbatch;
+    const int t0 = w.y * p.tpg + t_off;
+    const int t1 = min(t0 + p.gbatch, min((w.y + 1) * p.tpg, PK));
+    if (t0 < t1 && t0 / p.K == (t1 - 1) / p.K)
+      gather_lds_body<false, true>(w.y, w.z, p.fine, p.nx, p.nz, p.n_off, p.legs, p.tau, p.base, p.P, p.K, p.qs,
+                                   p.MQ, p.tpg, t_off, p.gbatch, p.gwin, p.vpb, p.partial);
+    else
+      gather_lds_body<false, false>(w.y, w.z, p.fine, p.nx, p.nz, p.n_off, p.legs, p.tau, p.base, p.P, p.K, p.qs,
+                                    p.MQ, p.tpg, t_off, p.gbatch, p.gwin, p.vpb, p.partial);
+  }
+}
+
 }  // namespace
 
 void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int4>* items, size_t* lds) {
@@ -2456,19 +2485,28 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
     for (int rg = 0; rg < (nrb + bp.corr_per - 1) / bp.corr_per; ++rg)
       for (int t = 0; t < PK; ++t) items[kStCorr].push_back(make_int4(pi, t, rg, 0));
   }
-  // gather: as run_adjoint_partial without attenuation
+  // gather: as run_adjoint_partial without attenuation, in the problem's
+  // gather form
   {
     bp.groups = G.trace_groups;
     bp.tpg = (PK + G.trace_groups - 1) / G.trace_groups;
-    int nb = (N + 1023) / 1024;
-    nb = std::max(1, std::min(nb, 1024 / G.trace_groups));
-    bp.vpb = (N + nb - 1) / nb;
+    bp.gwin = G.gwin;
+    const bool windowed = G.gather_form == 2 && G.gwin;
+    int nb;
+    if (windowed) {
+      nb = gather_lds_blocks(G.nx, G.nz, G.trace_groups, &bp.vpb);
+      lds[kStGatherW] = std::max(lds[kStGatherW], size_t(kGatherWinFloats) * sizeof(float));
+    } else {
+      nb = std::max(1, std::min((N + 1023) / 1024, 1024 / G.trace_groups));
+      bp.vpb = (N + nb - 1) / nb;
+    }
     const size_t trace_bytes = size_t(bp.MQ) * sizeof(float);
     bp.gbatch = int(std::max<size_t>(1, std::min<size_t>(bp.tpg, (size_t(G.gather_batch_kb) << 10) / trace_bytes)));
     const int batches = (bp.tpg + bp.gbatch - 1) / bp.gbatch;
+    const int stage = windowed ? kStGatherW : kStGather;
     for (int b = 0; b < batches; ++b)
       for (int vb = 0; vb < nb; ++vb)
-        for (int gr = 0; gr < G.trace_groups; ++gr) items[kStGather].push_back(make_int4(pi, gr, vb, b));
+        for (int gr = 0; gr < G.trace_groups; ++gr) items[stage].push_back(make_int4(pi, gr, vb, b));
   }
 }
 
@@ -2494,6 +2532,9 @@ int launch_sweep_stage(int stage, int Q, const BatchProb* probs, const int* acti
       break;
     case kStGather:
       UMBIR_LAUNCH("gather", k_gather_list, grid, dim3(256), L.lds, s, probs, active, L.items, L.n_items);
+      break;
+    case kStGatherW:
+      UMBIR_LAUNCH("gather", k_gather_lds_list, grid, dim3(512), L.lds, s, probs, active, L.items, L.n_items);
       break;
     default: return fail(UMBIR_EINVAL, "not a sweep stage");
   }

@@ -1001,8 +1001,8 @@ int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
   // (no prescale launch: the prior update keeps each session's tau x of its
   // current image and the block maxima in place)
   // the gather's items by launch (batch index), in problem order within one
-  std::stable_sort(items[kStGather].begin(), items[kStGather].end(),
-                   [](const int4& a, const int4& b) { return a.w < b.w; });
+  for (int k : {int(kStGather), int(kStGatherW)})
+    std::stable_sort(items[k].begin(), items[k].end(), [](const int4& a, const int4& b) { return a.w < b.w; });
   size_t bytes = aligned(size_t(n) * sizeof(BatchProb)) + aligned(size_t(n) * sizeof(int));
   for (int k = 0; k < kStages; ++k) bytes += aligned(items[k].size() * sizeof(int4));
   int st = check_hip(hipMalloc(&L.plan, bytes), "hipMalloc(batch plan)");
@@ -1036,7 +1036,7 @@ int worklist_lane(umbir_batch* B, umbir_batch::Lane& L) {
     L.kinds.push_back(kind);
   };
   for (int k = 0; k < kStages; ++k) {
-    if (k == kStGather) {  // one launch per batch index
+    if (k == kStGather || k == kStGatherW) {  // one launch per batch index
       size_t a = 0;
       while (a < items[k].size()) {
         size_t b = a;

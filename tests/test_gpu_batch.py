@@ -169,13 +169,17 @@ def test_worklist_batch(dev, q):
     runs with small splat chunks and one-trace gather batches, so its items
     cover several chunks and its gather items several batches; the problems
     take 32-, 64- and 128-sample convolution tiles, so the work list runs each
-    with its own."""
+    with its own; two run the windowed gather (its own work-list stage) and
+    the others the row-wise one."""
     cards = _q_cards(q) + ([dataclasses.replace(card_c1(), n_iter=5)] if q == 64 else [])
     data = [odata.synthesize(c)[1:] for c in cards]
     probs = batch.prepare(umbir, cards, device=dev, log=lambda *a, **k: None, data=data)
     probs[2]["geom"].set_tuning(splat_blocks=probs[2]["geom"].n_scans * probs[2]["geom"].n_rx * 4, gather_batch_kb=1)
     probs[0]["geom"].set_tuning(conv_tile_rows=64)
     probs[1]["geom"].set_tuning(conv_tile_rows=128, conv_grid=2)
+    for i in (1, 2):
+        probs[i]["geom"].set_tuning(gather_form=2)
+    probs[0]["geom"].set_tuning(gather_form=1)
     _, plain = batch.run_plain(umbir, probs)
     _, wl, n_batches = batch.run_batched(umbir, probs, umbir.BATCH_WORKLIST)
     assert n_batches == 1
