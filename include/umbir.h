@@ -398,9 +398,10 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   the fine grid in global memory; 2 windowed, each 32 x 64
  *                   voxel tile's window of a trace's fine grid staged in LDS
  *                   first (windows over 64 KiB loaded as in 1).  2 needs the
- *                   geometry's window table, built where 16-bit storage or a
- *                   record of fine positions not a multiple of 4 does not
- *                   rule it out (ENOTSUP from umbir_set_tuning otherwise).
+ *                   geometry's window table, built where 16-bit storage,
+ *                   attenuation or a record of fine positions not a multiple
+ *                   of 4 does not rule it out (ENOTSUP from umbir_set_tuning
+ *                   otherwise).
  *                   Default at build: 2 when its workgroups fill at least
  *                   three quarters of one generation (two per CU), else 1.
  *                   Bitwise identical results.

@@ -566,8 +566,9 @@ size_t umbir_estimate_bytes(const umbir_problem* pb) {
   }
   return table_bytes(pb->grid.nz, dv.n_off, pb->array.n_scans, pb->array.n_rx,
                      pb->acq.n_samples, pb->acq.oversample, dv.Lh, dv.n_gamma) +
-         gather_window_bytes(pb->grid.nx, pb->grid.nz, long(pb->array.n_scans) * pb->array.n_rx,
-                             long(pb->acq.n_samples) * pb->acq.oversample, pb->acq.storage);
+         (dv.n_gamma > 1 ? 0
+                         : gather_window_bytes(pb->grid.nx, pb->grid.nz, long(pb->array.n_scans) * pb->array.n_rx,
+                                               long(pb->acq.n_samples) * pb->acq.oversample, pb->acq.storage));
 }
 
 void umbir_geometry_free(umbir_geometry* G) {
@@ -735,24 +736,6 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
   UMBIR_LAUNCH("legs", k_legs, dim3((n_legs + 255) / 256), dim3(256), 0, s, G->layers, G->nz, G->n_off, G->z0,
                G->dz, 0.5 * G->dx, G->fs, G->beta, G->legs, G->nzp, G->legs_t, log2_int(G->Q), gam_dev);
   if ((st = check_hip(hipGetLastError(), "k_legs"))) return bail(st);
-  // the windowed gather's table (where it applies)
-  if (const size_t wb = gather_window_bytes(G->nx, G->nz, long(PK), G->fine_per_trace(), G->storage)) {
-    if ((st = alloc((void**)&G->gwin, wb))) return bail(st);
-    UMBIR_LAUNCH("gather_windows", k_gather_windows, dim3(unsigned(PK), unsigned(gather_tiles(G->nx, G->nz))),
-                 dim3(512), 0, s, G->legs, G->base, G->P, G->K, G->nx, G->nz, G->n_off, log2_int(G->Q),
-                 int(G->fine_per_trace()), G->gwin);
-    if ((st = check_hip(hipGetLastError(), "k_gather_windows"))) return bail(st);
-    if (gather_windowed_default(G->nx, G->nz, G->trace_groups)) {
-      G->gather_form = 2;
-      // gather batches of 16 traces per voxel tile a block takes (measured at
-      // 256 x 256: one tile per block, 4 MiB; at 512 x 512: two, 16 MiB
-      // against 5.02 ms per operator pair at 4 MiB and 5.00 at 32 MiB)
-      int tpb;
-      (void)gather_lds_blocks(G->nx, G->nz, G->trace_groups, &tpb);
-      const long kb = 16L * tpb * long(G->fine_per_trace()) * 4 / 1024;
-      G->gather_batch_kb = int(std::min(long(1) << 20, std::max(long(G->gather_batch_kb), kb)));
-    }
-  }
   if (dv.n_gamma > 1) {
     // Gamma_max: at a fixed depth a leg's attenuation grows with its lateral
     // offset, so every row's largest is at the largest offset in use
@@ -773,6 +756,27 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
         return bail(st);
       UMBIR_LAUNCH("leg_units", k_leg_units, dim3((n_legs + 255) / 256), dim3(256), 0, s, n_legs, G->n_off, G->nzp,
                    gam_dev, G->gamma_step, G->gunit, G->gunit_t);
+    }
+  }
+  // the windowed gather's table (where it applies: one template, no
+  // attenuation asked for)
+  const size_t wb =
+      dv.n_gamma > 1 ? 0 : gather_window_bytes(G->nx, G->nz, long(PK), G->fine_per_trace(), G->storage);
+  if (wb) {
+    if ((st = alloc((void**)&G->gwin, wb))) return bail(st);
+    UMBIR_LAUNCH("gather_windows", k_gather_windows, dim3(unsigned(PK), unsigned(gather_tiles(G->nx, G->nz))),
+                 dim3(512), 0, s, G->legs, G->base, G->P, G->K, G->nx, G->nz, G->n_off, log2_int(G->Q),
+                 int(G->fine_per_trace()), G->gwin);
+    if ((st = check_hip(hipGetLastError(), "k_gather_windows"))) return bail(st);
+    if (gather_windowed_default(G->nx, G->nz, G->trace_groups)) {
+      G->gather_form = 2;
+      // gather batches of 16 traces per voxel tile a block takes (measured at
+      // 256 x 256: one tile per block, 4 MiB; at 512 x 512: two, 16 MiB
+      // against 5.02 ms per operator pair at 4 MiB and 5.00 at 32 MiB)
+      int tpb;
+      (void)gather_lds_blocks(G->nx, G->nz, G->trace_groups, &tpb);
+      const long kb = 16L * tpb * long(G->fine_per_trace()) * 4 / 1024;
+      G->gather_batch_kb = int(std::min(long(1) << 20, std::max(long(G->gather_batch_kb), kb)));
     }
   }
   const int NG = G->n_gamma;
@@ -853,7 +857,7 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (t->products > 2) return fail(UMBIR_EINVAL, "products must be 1 or 2");
   if (t->gather_form > 2) return fail(UMBIR_EINVAL, "gather_form must be 1 or 2");
   if (t->gather_form == 2 && !G->gwin)
-    return fail(UMBIR_ENOTSUP, "the windowed gather needs FP32 storage and M * Q a multiple of 4");
+    return fail(UMBIR_ENOTSUP, "the windowed gather needs FP32 storage, no attenuation and M * Q a multiple of 4");
   if (t->operator_form == 2 && !direct_eligible(*G))
     return fail(UMBIR_ENOTSUP, "the direct form needs FP32 storage, one template and 8 M + 4 (Q L_h + 2) <= 65536");
   if (t->corr_tile_rows > 0 && t->corr_tile_rows != 32 && t->corr_tile_rows != 64 && t->corr_tile_rows != 128)

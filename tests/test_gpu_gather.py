@@ -12,7 +12,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from synth import card_c1, tiny_card, random_vector
+from synth import attenuated_card, card_c1, tiny_card, random_vector
 from oracle import geometry as og, operator as oo
 
 pytestmark = pytest.mark.gpu
@@ -107,12 +107,18 @@ def test_windowed_gather_across_scan_positions(dev):
     geom.free()
 
 
-def test_windowed_gather_needs_its_table(dev):
-    """16-bit storage has no window table: gather_form 2 is refused and the
-    tuning keeps the row-wise form."""
-    card = tiny_card(n_layers=3, oversample=32)
-    card = dataclasses.replace(card, acq=dataclasses.replace(card.acq, storage=1))
+@pytest.mark.parametrize("kind", ["fp16", "attenuation"])
+def test_windowed_gather_needs_its_table(dev, kind):
+    """16-bit storage and attenuated problems have no window table (their
+    adjoint runs the row-wise gather): gather_form 2 is refused and the tuning
+    keeps the row-wise form."""
+    if kind == "fp16":
+        card = tiny_card(n_layers=3, oversample=32)
+        card = dataclasses.replace(card, acq=dataclasses.replace(card.acq, storage=1))
+    else:
+        card = attenuated_card(n_gamma=4, oversample=32)
     geom = umbir.build_geometry(card)
+    assert geom.tuning()["gather_form"] == 1
     with pytest.raises(umbir.UmbirError):
         geom.set_tuning(gather_form=2)
     assert geom.tuning()["gather_form"] == 1
