@@ -393,14 +393,14 @@ int umbir_get_dims(const umbir_geometry* geom, umbir_dims* out);
  *                   product).  Results agree to rounding.  Where the
  *                   pieces' tables would not fit a workgroup's LDS (long
  *                   templates) the library uses the FP32 products.
- *  gather_form      the factored adjoint's gather (FP32 storage, one
- *                   template): 1 row-wise, each voxel's two taps loaded from
- *                   the fine grid in global memory; 2 windowed, each 32 x 64
- *                   voxel tile's window of a trace's fine grid staged in LDS
- *                   first (windows over 64 KiB loaded as in 1).  2 needs the
- *                   geometry's window table, built where 16-bit storage,
- *                   attenuation or a record of fine positions not a multiple
- *                   of 4 does not rule it out (ENOTSUP from umbir_set_tuning
+ *  gather_form      the factored adjoint's gather (one template): 1
+ *                   row-wise, each voxel's two taps loaded from the fine
+ *                   grid in global memory; 2 windowed, each 32 x 64 voxel
+ *                   tile's window of a trace's fine grid staged in LDS first
+ *                   (windows over 64 KiB loaded as in 1).  2 needs the
+ *                   geometry's window table, built where attenuation or a
+ *                   record of fine positions not a multiple of 16 bytes
+ *                   does not rule it out (ENOTSUP from umbir_set_tuning
  *                   otherwise).
  *                   Default at build: 2 when its workgroups fill at least
  *                   three quarters of one generation (two per CU), else 1.

@@ -211,13 +211,14 @@ __global__ void k_bin_mask(const Leg* __restrict__ legs, const double* __restric
 // The windowed gather's table: for trace blockIdx.x and voxel tile
 // blockIdx.y (kGatherTileRows x kGatherTileCols, row-major over the grid), the
 // fine positions J = floor(delay Q) of the tile's voxels that fall inside the
-// record, as {first, count}: first a multiple of 4 at or below the smallest J,
-// first + count a multiple of 4 above the largest J + 1 (each voxel reads J
-// and J + 1); {0, 0} when no voxel's J lies in the record.  J is the gather's
+// record, as {first, count}: first a multiple of `align` (16 bytes of the
+// fine grid) at or below the smallest J, first + count a multiple of `align`
+// above the largest J + 1 (each voxel reads J and J + 1); {0, 0} when no
+// voxel's J lies in the record.  J is the gather's
 // own: the two legs' Q32.32 delays summed and shifted.
 __global__ __launch_bounds__(512) void k_gather_windows(const Leg* __restrict__ legs, const int* __restrict__ base,
                                                         int P, int K, int nx, int nz, int n_off, int qs, int MQ,
-                                                        int2* __restrict__ gwin) {
+                                                        int align, int2* __restrict__ gwin) {
   const int t = blockIdx.x, tile = blockIdx.y;
   const int tiles_x = (nx + kGatherTileCols - 1) / kGatherTileCols;
   const int tz = tile / tiles_x, tx = tile - tz * tiles_x;
@@ -254,8 +255,9 @@ __global__ __launch_bounds__(512) void k_gather_windows(const Leg* __restrict__ 
     }
     int2 win = make_int2(0, 0);
     if (lo != 0xffffffffu) {
-      const unsigned first = lo & ~3u;
-      win = make_int2(int(first), int((hi + 2u - first + 3u) & ~3u));
+      const unsigned m = unsigned(align) - 1u;
+      const unsigned first = lo & ~m;
+      win = make_int2(int(first), int((hi + 2u - first + m) & ~m));
     }
     gwin[size_t(tile) * (P * K) + t] = win;
   }
@@ -766,7 +768,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
     if ((st = alloc((void**)&G->gwin, wb))) return bail(st);
     UMBIR_LAUNCH("gather_windows", k_gather_windows, dim3(unsigned(PK), unsigned(gather_tiles(G->nx, G->nz))),
                  dim3(512), 0, s, G->legs, G->base, G->P, G->K, G->nx, G->nz, G->n_off, log2_int(G->Q),
-                 int(G->fine_per_trace()), G->gwin);
+                 int(G->fine_per_trace()), gather_window_align(G->storage), G->gwin);
     if ((st = check_hip(hipGetLastError(), "k_gather_windows"))) return bail(st);
     if (gather_windowed_default(G->nx, G->nz, G->trace_groups)) {
       G->gather_form = 2;
@@ -775,7 +777,7 @@ int umbir_build_geometry(const umbir_problem* pb, void* stream, umbir_geometry**
       // against 5.02 ms per operator pair at 4 MiB and 5.00 at 32 MiB)
       int tpb;
       (void)gather_lds_blocks(G->nx, G->nz, G->trace_groups, &tpb);
-      const long kb = 16L * tpb * long(G->fine_per_trace()) * 4 / 1024;
+      const long kb = 16L * tpb * long(G->fine_per_trace()) * long(G->elem()) / 1024;
       G->gather_batch_kb = int(std::min(long(1) << 20, std::max(long(G->gather_batch_kb), kb)));
     }
   }
@@ -857,7 +859,7 @@ int umbir_set_tuning(umbir_geometry* G, const umbir_tuning* t) {
   if (t->products > 2) return fail(UMBIR_EINVAL, "products must be 1 or 2");
   if (t->gather_form > 2) return fail(UMBIR_EINVAL, "gather_form must be 1 or 2");
   if (t->gather_form == 2 && !G->gwin)
-    return fail(UMBIR_ENOTSUP, "the windowed gather needs FP32 storage, no attenuation and M * Q a multiple of 4");
+    return fail(UMBIR_ENOTSUP, "the windowed gather needs no attenuation and M * Q a multiple of 16 bytes");
   if (t->operator_form == 2 && !direct_eligible(*G))
     return fail(UMBIR_ENOTSUP, "the direct form needs FP32 storage, one template and 8 M + 4 (Q L_h + 2) <= 65536");
   if (t->corr_tile_rows > 0 && t->corr_tile_rows != 32 && t->corr_tile_rows != 64 && t->corr_tile_rows != 128)

@@ -46,8 +46,11 @@ __host__ __device__ __forceinline__ int leg_slot(int o, int half) { return (o >>
 
 // The windowed gather (FP32 fine grid): voxel tiles of kGatherTileRows x
 // kGatherTileCols, and for every (tile, trace) the window of fine positions
-// its voxels read, staged in LDS when it holds at most kGatherWinFloats.
-constexpr int kGatherTileRows = 32, kGatherTileCols = 64, kGatherWinFloats = 16384;
+// its voxels read, staged in LDS when it fits kGatherWinBytes (16384 FP32 or
+// 32768 16-bit positions); windows start and end on 16-byte boundaries
+// (gather_window_align positions).
+constexpr int kGatherTileRows = 32, kGatherTileCols = 64, kGatherWinBytes = 65536;
+inline int gather_window_align(int storage) { return storage == UMBIR_STORAGE_F32 ? 4 : 8; }
 inline long gather_tiles(int nx, int nz) {
   return long((nx + kGatherTileCols - 1) / kGatherTileCols) * ((nz + kGatherTileRows - 1) / kGatherTileRows);
 }
@@ -62,13 +65,13 @@ inline int gather_lds_blocks(int nx, int nz, int groups, int* tiles_per_block) {
   return int((tiles + *tiles_per_block - 1) / *tiles_per_block);
 }
 // Bytes of the window table ([tiles][traces] of {first position, count}),
-// 0 where the windowed gather does not apply: 16-bit storage, a record of
-// fine positions not a multiple of 4, more tiles than a grid dimension holds
-// or a table over 64 MiB.
+// 0 where the windowed gather does not apply: a record of fine positions not
+// a multiple of gather_window_align, more tiles than a grid dimension holds or
+// a table over 64 MiB.
 inline size_t gather_window_bytes(int nx, int nz, long traces, long fine_per_trace, int storage) {
   const long tiles = gather_tiles(nx, nz);
   const size_t bytes = size_t(tiles) * size_t(traces) * 8;
-  if (storage != UMBIR_STORAGE_F32 || fine_per_trace % 4 != 0 || tiles > 65535 || bytes > (size_t(64) << 20)) return 0;
+  if (fine_per_trace % gather_window_align(storage) != 0 || tiles > 65535 || bytes > (size_t(64) << 20)) return 0;
   return bytes;
 }
 // The default gather form where the table exists: windowed when its blocks

@@ -887,7 +887,14 @@ __global__ __launch_bounds__(256) void k_gather(
   gather_body<ABSW, VPT, ST, ATT, ONE, MULTI>(blockIdx.x, blockIdx.y, fine, nx, nz, n_off, legs, gunit, tau, base, P, K, qs, MQ, tpg, t_off, t_cnt, vox_per_block, gbin, glast, accum, partial);
 }
 
-// S^T with the fine-grid window in LDS (FP32 grid, one template; same pairs,
+// One position of the window in LDS, as the storage type's sample reads it
+// (the value fine_at gives).
+template <int ST>
+__device__ __forceinline__ float win_at(const uint4* w, int i) {
+  return Store<ST>::get(reinterpret_cast<const typename Store<ST>::T*>(w)[i]);
+}
+
+// S^T with the fine-grid window in LDS (one template; same pairs,
 // same arithmetic and the same per-voxel order over the traces as k_gather,
 // so the same results).  A trace's delays change by several 128-byte lines of
 // the fine grid from one voxel to the next, so in k_gather nearly every lane's
@@ -896,20 +903,25 @@ __global__ __launch_bounds__(256) void k_gather(
 // for each trace first copies the tile's window of fine positions (from the
 // table k_gather_windows builds: 0.2 lines per pair on average at 256 x 256)
 // into LDS with coalesced 16-byte loads, then every voxel reads its two taps
-// from LDS.  A trace whose window exceeds kGatherWinFloats (about one in ten
-// there: tiles near the array, where the delays spread most) reads its taps
-// from global memory as k_gather does.  The window of trace t + 1 and the
-// legs of trace t + 2 are in flight while trace t accumulates.  Wave w's load
-// u covers row 8 u + w of the tile, one lane per column (neighbouring leg
-// records).  ONE and the arguments as for k_gather.
-template <bool ABSW, bool ONE>
+// from LDS.  A trace whose window exceeds 64 KiB (16384 FP32 or 32768 16-bit
+// positions; about one FP32 window in ten there: tiles near the array, where
+// the delays spread most) reads its taps from global memory as k_gather
+// does.  The window of trace t + 1 and the legs of trace t + 2 are in flight
+// while trace t accumulates.  Wave w's load u covers row 8 u + w of the tile,
+// one lane per column (neighbouring leg records).  ONE and the arguments as
+// for k_gather.
+template <bool ABSW, bool ONE, int ST = UMBIR_STORAGE_F32>
 __device__ __forceinline__ void gather_lds_body(int bx, int by,
-    const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ, int tpg, int t_off,
     int t_cnt, const int2* __restrict__ gwin, int tiles_per_block, float* __restrict__ partial) {
-  extern __shared__ uint4 wlds[];  // the window: kGatherWinFloats floats
+  using T16 = typename Store<ST>::T;
+  extern __shared__ uint4 wlds[];  // the window: kGatherWinBytes
   constexpr int VPT = kGatherTileRows / 8;
-  constexpr int kStage = kGatherWinFloats / 4 / 512;  // 16-byte loads per thread per window
+  constexpr int ES = int(sizeof(T16));                // bytes per position
+  constexpr int EPC = 16 / ES;                        // positions per 16-byte load
+  constexpr int kWin = kGatherWinBytes / ES;          // window capacity in positions
+  constexpr int kStage = kGatherWinBytes / 16 / 512;  // 16-byte loads per thread per window
   const int N = nx * nz;
   const int PK = P * K;
   const int g_end = min((bx + 1) * tpg, PK);
@@ -924,7 +936,6 @@ __device__ __forceinline__ void gather_lds_body(int bx, int by,
   const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
   const __amdgpu_buffer_rsrc_t leg_rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<Leg*>(legs), 0, nz * n_off * int(sizeof(Leg)), kBufferWord3);
-  const float* wf = reinterpret_cast<const float*>(wlds);
   struct Legs { int64_t d[VPT]; float p[VPT]; };
   struct Taps { unsigned J[VPT]; float phi[VPT], w[VPT]; };
   for (int tile = by * tiles_per_block; tile < tile_end; ++tile) {
@@ -978,18 +989,18 @@ __device__ __forceinline__ void gather_lds_body(int bx, int by,
     // data, positions past the record (and loads past the window) read zero
     auto stage_load = [&](int2 W, int t, uint4 (&R)[kStage]) {
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<float*>(fine + size_t(t) * MQ), 0, MQ * int(sizeof(float)), kBufferWord3);
-      const int nq = W.y >> 2;
+          const_cast<T16*>(fine + size_t(t) * MQ), 0, MQ * ES, kBufferWord3);
+      const int nq = W.y / EPC;
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
         const int c = int(threadIdx.x) + 512 * k;
-        const int off = c < nq ? (W.x + 4 * c) * int(sizeof(float)) : 0x7ffffff0;
+        const int off = c < nq ? (W.x + EPC * c) * ES : 0x7ffffff0;
         const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
         R[k] = make_uint4(v[0], v[1], v[2], v[3]);
       }
     };
     auto stage_store = [&](int2 W, const uint4 (&R)[kStage]) {
-      const int nq = W.y >> 2;
+      const int nq = W.y / EPC;
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
         const int c = int(threadIdx.x) + 512 * k;
@@ -1007,17 +1018,17 @@ __device__ __forceinline__ void gather_lds_body(int bx, int by,
           const int i = int(T.J[u]) - W.x;
           const bool in = T.J[u] < unsigned(MQ) && i >= 0 && i <= W.y - 2;
           const int ic = in ? i : 0;
-          const float c0 = in ? wf[ic] : 0.0f;
-          const float c1 = in ? wf[ic + 1] : 0.0f;
+          const float c0 = in ? win_at<ST>(wlds, ic) : 0.0f;
+          const float c1 = in ? win_at<ST>(wlds, ic + 1) : 0.0f;
           acc[u] = fmaf(T.w[u], fmaf(T.phi[u], c1 - c0, c0), acc[u]);
         }
       } else {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float*>(fine + size_t(t) * MQ), 0, MQ * int(sizeof(float)), kBufferWord3);
+            const_cast<T16*>(fine + size_t(t) * MQ), 0, MQ * ES, kBufferWord3);
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
-          const float c0 = fine_at<UMBIR_STORAGE_F32>(rs, T.J[u]);
-          const float c1 = fine_at<UMBIR_STORAGE_F32>(rs, T.J[u] + 1u);
+          const float c0 = fine_at<ST>(rs, T.J[u]);
+          const float c1 = fine_at<ST>(rs, T.J[u] + 1u);
           acc[u] = fmaf(T.w[u], fmaf(T.phi[u], c1 - c0, c0), acc[u]);
         }
       }
@@ -1029,17 +1040,17 @@ __device__ __forceinline__ void gather_lds_body(int bx, int by,
       int2 W = wt[t0];
       load_legs(La, LTa, t0);
       load_legs(Lb, LTb, t0 + 1);
-      if (W.y <= kGatherWinFloats) stage_load(W, t0, R);
+      if (W.y <= kWin) stage_load(W, t0, R);
       taps_of(La, LTa, T);
       // one step: trace t accumulates from (T, W); L holds the legs of t + 1
       // (in flight), Lf is free for those of t + 2
       auto step = [&](int t, Legs& L, Legs& LT, Legs& Lf, Legs& LTf) {
-        const bool fits = W.y <= kGatherWinFloats;
+        const bool fits = W.y <= kWin;
         __syncthreads();  // every wave has read the previous window
         if (fits) stage_store(W, R);
         __syncthreads();
         const int2 Wn = wt[min(t + 1, t1 - 1)];
-        if (t + 1 < t1 && Wn.y <= kGatherWinFloats) stage_load(Wn, t + 1, R);
+        if (t + 1 < t1 && Wn.y <= kWin) stage_load(Wn, t + 1, R);
         load_legs(Lf, LTf, t + 2);
         add(T, W, fits, t);
         taps_of(L, LT, T);
@@ -1063,12 +1074,12 @@ __device__ __forceinline__ void gather_lds_body(int bx, int by,
   }
 }
 
-template <bool ABSW, bool ONE>
+template <bool ABSW, bool ONE, int ST>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_gather_lds(
-    const float* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
+    const typename Store<ST>::T* __restrict__ fine, int nx, int nz, int n_off, const Leg* __restrict__ legs,
     const float* __restrict__ tau, const int* __restrict__ base, int P, int K, int qs, int MQ, int tpg, int t_off,
     int t_cnt, const int2* __restrict__ gwin, int tiles_per_block, float* __restrict__ partial) {
-  gather_lds_body<ABSW, ONE>(blockIdx.x, blockIdx.y, fine, nx, nz, n_off, legs, tau, base, P, K, qs, MQ, tpg, t_off,
+  gather_lds_body<ABSW, ONE, ST>(blockIdx.x, blockIdx.y, fine, nx, nz, n_off, legs, tau, base, P, K, qs, MQ, tpg, t_off,
                              t_cnt, gwin, tiles_per_block, partial);
 }
 
@@ -2272,16 +2283,17 @@ bool gather_one_scan(const umbir_geometry& G, int tpg, int t_off, int batch) {
   return true;
 }
 
-// The windowed gather (FP32 grid, one template, window table built).
+// The windowed gather (one template, window table built).
+template <int ST>
 void launch_gather_lds(const umbir_geometry& G, bool abs_op, int qs, int MQ, int tpg, int t_off, int batch,
                        const void* fine, float* partial, hipStream_t s) {
   int tpb;
   const dim3 grid(G.trace_groups, gather_lds_blocks(G.nx, G.nz, G.trace_groups, &tpb));
-  const size_t lds = size_t(kGatherWinFloats) * sizeof(float);
-  const float* f = static_cast<const float*>(fine);
+  const size_t lds = size_t(kGatherWinBytes);
+  const auto* f = static_cast<const typename Store<ST>::T*>(fine);
   const bool one = gather_one_scan(G, tpg, t_off, batch);
 #define UMBIR_GATHER_LDS(A, O)                                                                                 \
-  UMBIR_LAUNCH("gather", (k_gather_lds<A, O>), grid, dim3(512), lds, s, f, G.nx, G.nz, G.n_off, G.legs, G.tau, \
+  UMBIR_LAUNCH("gather", (k_gather_lds<A, O, ST>), grid, dim3(512), lds, s, f, G.nx, G.nz, G.n_off, G.legs, G.tau, \
                G.base, G.P, G.K, qs, MQ, tpg, t_off, batch, G.gwin, tpb, partial)
   if (abs_op) {
     if (one) UMBIR_GATHER_LDS(true, true);
@@ -2495,7 +2507,7 @@ void plan_sweeps(const umbir_geometry& G, int pi, BatchProb& bp, std::vector<int
     int nb;
     if (windowed) {
       nb = gather_lds_blocks(G.nx, G.nz, G.trace_groups, &bp.vpb);
-      lds[kStGatherW] = std::max(lds[kStGatherW], size_t(kGatherWinFloats) * sizeof(float));
+      lds[kStGatherW] = std::max(lds[kStGatherW], size_t(kGatherWinBytes));
     } else {
       nb = std::max(1, std::min((N + 1023) / 1024, 1024 / G.trace_groups));
       bp.vpb = (N + nb - 1) / nb;
@@ -2734,19 +2746,25 @@ int run_adjoint_partial(const umbir_geometry& G, const void* r, bool abs_op, voi
     for (int t_off = 0; t_off < tpg; t_off += batch) {
       switch (G.storage) {
         case UMBIR_STORAGE_F16:
-          launch_gather<UMBIR_STORAGE_F16, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
-                                                  partial, s);
+          if (G.gather_form == 2 && G.gwin)
+            launch_gather_lds<UMBIR_STORAGE_F16>(G, abs_op, qs, MQ, tpg, t_off, batch, fine, partial, s);
+          else
+            launch_gather<UMBIR_STORAGE_F16, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
+                                                    partial, s);
           break;
         case UMBIR_STORAGE_BF16:
-          launch_gather<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
-                                                   partial, s);
+          if (G.gather_form == 2 && G.gwin)
+            launch_gather_lds<UMBIR_STORAGE_BF16>(G, abs_op, qs, MQ, tpg, t_off, batch, fine, partial, s);
+          else
+            launch_gather<UMBIR_STORAGE_BF16, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
+                                                     partial, s);
           break;
         default:
           if (G.n_gamma > 1)
             launch_gather<UMBIR_STORAGE_F32, true>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, gb, accum,
                                                    fine, partial, s);
           else if (G.gather_form == 2 && G.gwin)
-            launch_gather_lds(G, abs_op, qs, MQ, tpg, t_off, batch, fine, partial, s);
+            launch_gather_lds<UMBIR_STORAGE_F32>(G, abs_op, qs, MQ, tpg, t_off, batch, fine, partial, s);
           else
             launch_gather<UMBIR_STORAGE_F32, false>(G, abs_op, grid, qs, MQ, tpg, t_off, batch, vpb, 0, 0, fine,
                                                     partial, s);

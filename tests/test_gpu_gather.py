@@ -107,16 +107,30 @@ def test_windowed_gather_across_scan_positions(dev):
     geom.free()
 
 
-@pytest.mark.parametrize("kind", ["fp16", "attenuation"])
-def test_windowed_gather_needs_its_table(dev, kind):
-    """16-bit storage and attenuated problems have no window table (their
-    adjoint runs the row-wise gather): gather_form 2 is refused and the tuning
-    keeps the row-wise form."""
-    if kind == "fp16":
-        card = tiny_card(n_layers=3, oversample=32)
-        card = dataclasses.replace(card, acq=dataclasses.replace(card.acq, storage=1))
-    else:
-        card = attenuated_card(n_gamma=4, oversample=32)
+@pytest.mark.parametrize("storage", [1, 2])
+def test_windowed_gather_16bit(dev, storage):
+    """FP16 and BF16 fine grids: the windowed gather (windows of up to 32768
+    positions) holds the row-wise one bit for bit, oversized windows
+    included."""
+    card = tiny_card(n_layers=3, nx=70, nz=40, n_scans=2, n_rx=3, n_samples=1200, oversample=64)
+    card = dataclasses.replace(card, acq=dataclasses.replace(card.acq, storage=storage))
+    assert (host_windows(card) > 2 * WIN_FLOATS).any()
+    geom = umbir.build_geometry(card)
+    r = torch.tensor(random_vector(geom.trace_shape, seed=44), dtype=torch.float32, device=dev).to(geom.trace_dtype)
+    out = []
+    for form in (1, 2):
+        geom.set_tuning(gather_form=form)
+        out.append((umbir.adjoint(geom, r).clone(), umbir.sqs_denominator(geom, 1.0).clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert float(out[1][0].abs().sum()) > 0.0
+    geom.free()
+
+
+def test_windowed_gather_needs_its_table(dev):
+    """Attenuated problems have no window table (their template passes run
+    the row-wise gather): gather_form 2 is refused and the tuning keeps the
+    row-wise form."""
+    card = attenuated_card(n_gamma=4, oversample=32)
     geom = umbir.build_geometry(card)
     assert geom.tuning()["gather_form"] == 1
     with pytest.raises(umbir.UmbirError):
